@@ -1,0 +1,204 @@
+"""ctypes front-end of the FP64 CPU oracle (tdsez_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: imported by tests/, by the smoke check and by the
+CPU-baseline leg of bench.py.  The GPU library never imports this module and
+this module never imports the GPU library.
+
+Band convention (same as the C file): a real symmetric banded matrix is its
+upper half band, diagonal-major, shape (p+1, N): band[d, i] = M[i, i+d].
+Complex vectors are numpy complex128 arrays.
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "tdsez_oracle.c")
+_LIB = os.path.join(_HERE, "libtdsez_oracle.so")
+
+
+def build(force=False):
+    """Compile the oracle with plain gcc (no fast-math, no BLAS, no threads)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(_LIB)
+        dp = ctypes.POINTER(ctypes.c_double)
+        i = ctypes.c_int
+        d = ctypes.c_double
+        L.orc_gauss_legendre.argtypes = [i, dp, dp]
+        L.orc_ndof.argtypes = [i, i]
+        L.orc_quad_points.argtypes = [dp, i, i, dp, dp]
+        L.orc_bspline_values.argtypes = [dp, i, i, dp, i, dp, dp]
+        L.orc_assemble.argtypes = [dp, i, i, i, dp, dp, dp, dp, dp, dp, dp, dp, dp]
+        L.orc_expect.argtypes = [i, i, dp, dp]
+        L.orc_expect.restype = d
+        L.orc_eig_dense.argtypes = [i, i, dp, dp, dp, dp]
+        L.orc_eig_banded.argtypes = [i, i, dp, dp, i, d, d, i, dp, dp]
+        L.orc_propagate.argtypes = [i, i, dp, dp, dp, dp, dp, dp, dp, d, i, dp, dp]
+        L.orc_adjoint.argtypes = [i, i, dp, dp, dp, dp, dp, dp, dp, d, i, dp, dp, dp]
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    if a is None:
+        return None
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _c128(a):
+    return np.ascontiguousarray(a, dtype=np.complex128)
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise OracleError("%s failed with code %d" % (what, rc))
+
+
+def gauss_legendre(n):
+    x = np.zeros(n)
+    w = np.zeros(n)
+    _check(lib().orc_gauss_legendre(n, _p(x), _p(w)), "gauss_legendre")
+    return x, w
+
+
+def ndof(nbr, order):
+    return lib().orc_ndof(nbr, order)
+
+
+def quad_points(breaks, nq):
+    br = _f64(breaks)
+    xq = np.zeros((len(br) - 1) * nq)
+    wq = np.zeros_like(xq)
+    _check(lib().orc_quad_points(_p(br), len(br), nq, _p(xq), _p(wq)), "quad_points")
+    return xq, wq
+
+
+def bspline_values(breaks, order, x):
+    br = _f64(breaks)
+    x = _f64(x)
+    nb = len(br) + order - 2
+    vals = np.zeros((len(x), nb))
+    ders = np.zeros((len(x), nb))
+    _check(lib().orc_bspline_values(_p(br), len(br), order, _p(x), len(x), _p(vals), _p(ders)),
+           "bspline_values")
+    return vals, ders
+
+
+def assemble(breaks, order, nq, minv=None, V=None, dV=None, samples=None):
+    """Half bands of S, T, V, D, G, Mi.
+
+    minv, V, dV are callables of x (numpy arrays) sampled at the oracle's own
+    quadrature points; alternatively `samples` = (minv_q, V_q, dV_q)."""
+    br = _f64(breaks)
+    N = ndof(len(br), order)
+    p = order - 1
+    if samples is None:
+        xq, _ = quad_points(br, nq)
+        minv_q = _f64(minv(xq)) if minv is not None else np.ones_like(xq)
+        V_q = _f64(V(xq)) if V is not None else np.zeros_like(xq)
+        dV_q = _f64(dV(xq)) if dV is not None else np.zeros_like(xq)
+    else:
+        minv_q, V_q, dV_q = (_f64(s) for s in samples)
+    out = {k: np.zeros((p + 1, N)) for k in ("S", "T", "V", "D", "G", "Mi")}
+    _check(lib().orc_assemble(_p(br), len(br), order, nq, _p(minv_q), _p(V_q), _p(dV_q),
+                              _p(out["S"]), _p(out["T"]), _p(out["V"]), _p(out["D"]),
+                              _p(out["G"]), _p(out["Mi"])), "assemble")
+    out["H0"] = out["T"] + out["V"]
+    out["N"] = N
+    out["p"] = p
+    return out
+
+
+def band_to_dense(band):
+    """Dense symmetric matrix from an upper half band (test helper)."""
+    p1, N = band.shape
+    A = np.zeros((N, N))
+    for d in range(p1):
+        idx = np.arange(N - d)
+        A[idx, idx + d] = band[d, :N - d]
+        A[idx + d, idx] = band[d, :N - d]
+    return A
+
+
+def expect(band, c):
+    band = _f64(band)
+    c = _c128(c)
+    p1, N = band.shape
+    return lib().orc_expect(N, p1 - 1, _p(band), _p(c.view(np.float64)))
+
+
+def eig_dense(H, S):
+    H = _f64(H)
+    S = _f64(S)
+    p1, N = S.shape
+    ev = np.zeros(N)
+    vec = np.zeros((N, N))
+    _check(lib().orc_eig_dense(N, p1 - 1, _p(H), _p(S), _p(ev), _p(vec)), "eig_dense")
+    return ev, vec
+
+
+def eig_banded(H, S, nev, sigma, tol=1e-14, maxit=3000):
+    H = _f64(H)
+    S = _f64(S)
+    p1, N = S.shape
+    ev = np.zeros(nev)
+    vec = np.zeros((nev, N))
+    _check(lib().orc_eig_banded(N, p1 - 1, _p(H), _p(S), nev, float(sigma), float(tol), int(maxit),
+                                _p(ev), _p(vec)), "eig_banded")
+    return ev, vec
+
+
+def propagate(m, psi0, E, dt, nsteps, with_accel=True):
+    """CN propagation of one system; m = dict from assemble().  Returns
+    (obs[nsteps+1, 3] = (nu, d, a), psi_final)."""
+    N, p = m["N"], m["p"]
+    psi0 = _c128(psi0)
+    E = _f64(E)
+    assert E.shape[0] >= nsteps + 1
+    obs = np.zeros((nsteps + 1, 3))
+    out = np.zeros(N, dtype=np.complex128)
+    G = _f64(m["G"]) if with_accel else None
+    Mi = _f64(m["Mi"]) if with_accel else None
+    _check(lib().orc_propagate(N, p, _p(_f64(m["S"])), _p(_f64(m["H0"])), _p(_f64(m["D"])), _p(G), _p(Mi),
+                               _p(psi0.view(np.float64)), _p(E), float(dt), int(nsteps), _p(obs),
+                               _p(out.view(np.float64))), "propagate")
+    return obs, out
+
+
+def adjoint(m, psi0, E, dt, nsteps, dJdobs, with_accel=True):
+    """Discrete adjoint: returns (dJ/dE[nsteps+1], dJ/dpsi0)."""
+    N, p = m["N"], m["p"]
+    psi0 = _c128(psi0)
+    E = _f64(E)
+    dJdobs = _f64(dJdobs).reshape(nsteps + 1, 3)
+    dJdE = np.zeros(nsteps + 1)
+    lam0 = np.zeros(N, dtype=np.complex128)
+    G = _f64(m["G"]) if with_accel else None
+    Mi = _f64(m["Mi"]) if with_accel else None
+    _check(lib().orc_adjoint(N, p, _p(_f64(m["S"])), _p(_f64(m["H0"])), _p(_f64(m["D"])), _p(G), _p(Mi),
+                             _p(psi0.view(np.float64)), _p(E), float(dt), int(nsteps), _p(dJdobs),
+                             _p(dJdE), _p(lam0.view(np.float64))), "adjoint")
+    return dJdE, lam0

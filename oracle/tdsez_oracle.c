@@ -1,0 +1,841 @@
+/*
+ * tdsez_oracle.c -- plain, serial, double-precision CPU oracle for the
+ * B-spline Galerkin / Crank-Nicolson TDSE method of Dahbi & Zair,
+ * "Unified Strong-Field Dynamics Simulations from Atoms to Heterostructures"
+ * (arXiv 2608.18472).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the reference that the GPU library
+ * is checked against.  It shares no code, header, table or helper with the
+ * library under paper_2608_18472_amd/ and must never be linked into it.  Only
+ * the test suite, the smoke check and the CPU-baseline leg of the benchmark
+ * load it.
+ *
+ * Everything is written for clarity, not speed: textbook loops, FP64
+ * throughout (complex values as C99 double complex), no blocking, no
+ * reordering beyond what each definition states.
+ *
+ * Conventions shared by every routine here:
+ *   - breakpoints br[0] < br[1] < ... < br[nbr-1]; order k = p + 1 (degree p);
+ *     the open knot vector repeats each end breakpoint k times (section II.C,
+ *     paragraph after eq. tensor3d);
+ *   - the first and last B-spline are dropped (homogeneous Dirichlet, same
+ *     paragraph), so the number of unknowns is N = (nbr - 1) + p - 2;
+ *   - a real symmetric banded matrix M is stored as its upper half band,
+ *     diagonal-major: band[d*N + i] = M[i][i+d] for d = 0..p and
+ *     i = 0..N-1-d (entries with i+d >= N are zero);
+ *   - complex vectors are interleaved (re, im) pairs of doubles.
+ */
+#include <complex.h>
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef double complex zd;
+
+static const double PI = 3.14159265358979323846264338327950288;
+
+#define ORC_OK 0
+#define ORC_EINVAL 1
+#define ORC_ENOMEM 2
+#define ORC_ESING 3
+#define ORC_ENOCONV 4
+
+/* ------------------------------------------------------------------------ */
+/* Gauss-Legendre quadrature on [-1, 1].                                     */
+/* Each span's inner products use Gaussian quadrature (section II.C, the     */
+/* sentence after eq. matrixODE; section V.A).  Nodes are the roots of the   */
+/* Legendre polynomial P_n, found by Newton's method from the Chebyshev-like */
+/* initial guess cos(pi (i + 3/4) / (n + 1/2)); weights 2/((1-x^2) P_n'(x)^2) */
+/* ------------------------------------------------------------------------ */
+int orc_gauss_legendre(int n, double *x, double *w)
+{
+    if (n < 1 || n > 64) return ORC_EINVAL;
+    for (int i = 0; i < n; ++i) {
+        double z = cos(PI * (i + 0.75) / (n + 0.5));
+        double dp = 0.0;
+        for (int it = 0; it < 100; ++it) {
+            /* three-term recurrence: (j+1) P_{j+1} = (2j+1) z P_j - j P_{j-1} */
+            double pm = 1.0, pc = z;
+            for (int j = 1; j < n; ++j) {
+                double pn = ((2.0 * j + 1.0) * z * pc - j * pm) / (j + 1.0);
+                pm = pc;
+                pc = pn;
+            }
+            /* P_n = pc, P_{n-1} = pm; P_n'(z) = n (z P_n - P_{n-1}) / (z^2 - 1) */
+            dp = n * (z * pc - pm) / (z * z - 1.0);
+            double dz = pc / dp;
+            z -= dz;
+            if (fabs(dz) < 1e-16) break;
+        }
+        /* recompute the derivative at the converged root */
+        double pm = 1.0, pc = z;
+        for (int j = 1; j < n; ++j) {
+            double pn = ((2.0 * j + 1.0) * z * pc - j * pm) / (j + 1.0);
+            pm = pc;
+            pc = pn;
+        }
+        dp = n * (z * pc - pm) / (z * z - 1.0);
+        x[i] = -z; /* ascending order */
+        w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+    return ORC_OK;
+}
+
+/* Number of unknowns after dropping the two boundary B-splines. */
+int orc_ndof(int nbr, int order)
+{
+    if (nbr < 2 || order < 2) return -1;
+    return (nbr - 1) + (order - 1) - 2;
+}
+
+static int check_breaks(const double *br, int nbr)
+{
+    if (nbr < 2) return ORC_EINVAL;
+    for (int i = 0; i + 1 < nbr; ++i)
+        if (!(br[i + 1] > br[i])) return ORC_EINVAL;
+    return ORC_OK;
+}
+
+/* Physical quadrature points and weights, span-major: entry e*nq + q is the
+ * q-th Gauss point of span [br[e], br[e+1]] (affine map of [-1,1]; the
+ * Jacobian (br[e+1]-br[e])/2 is folded into the weight). */
+int orc_quad_points(const double *br, int nbr, int nq, double *xq, double *wq)
+{
+    if (check_breaks(br, nbr) != ORC_OK) return ORC_EINVAL;
+    double gx[64], gw[64];
+    int rc = orc_gauss_legendre(nq, gx, gw);
+    if (rc) return rc;
+    for (int e = 0; e + 1 < nbr; ++e) {
+        double a = br[e], b = br[e + 1];
+        double h = 0.5 * (b - a), m = 0.5 * (a + b);
+        for (int q = 0; q < nq; ++q) {
+            xq[e * nq + q] = m + h * gx[q];
+            if (wq) wq[e * nq + q] = h * gw[q];
+        }
+    }
+    return ORC_OK;
+}
+
+/* Open knot vector t (length nbr + 2p) from the breakpoints. */
+static void make_knots(const double *br, int nbr, int order, double *t)
+{
+    int p = order - 1, j = 0;
+    for (int r = 0; r < p; ++r) t[j++] = br[0];
+    for (int i = 0; i < nbr; ++i) t[j++] = br[i];
+    for (int r = 0; r < p; ++r) t[j++] = br[nbr - 1];
+}
+
+/* Cox-de Boor recursion (de Boor, A Practical Guide to Splines): values of
+ * the `order` B-splines of that order that are non-zero on knot span mu
+ * (t[mu] <= x < t[mu+1]), i.e. B_{mu-p}..B_{mu}, and their first derivatives.
+ * vals[a], ders[a] refer to B_{mu-p+a}. */
+static void bspline_span_eval(const double *t, int order, int mu, double x,
+                              double *vals, double *ders)
+{
+    int p = order - 1;
+    /* tab[j][a] holds the order-(j+1) B-splines non-zero on the span,
+     * B_{mu-j+a, j+1} for a = 0..j */
+    double tab[16][16];
+    tab[0][0] = 1.0;
+    for (int j = 1; j <= p; ++j) {
+        /* order j+1 from order j:
+         * B_{i,j+1}(x) = (x - t_i)/(t_{i+j} - t_i) B_{i,j}(x)
+         *              + (t_{i+j+1} - x)/(t_{i+j+1} - t_{i+1}) B_{i+1,j}(x) */
+        for (int a = 0; a <= j; ++a) {
+            int i = mu - j + a;
+            double left = 0.0, right = 0.0;
+            if (a >= 1) { /* B_{i,j} = tab[j-1][a-1] */
+                double den = t[i + j] - t[i];
+                if (den > 0.0) left = (x - t[i]) / den * tab[j - 1][a - 1];
+            }
+            if (a <= j - 1) { /* B_{i+1,j} = tab[j-1][a] */
+                double den = t[i + j + 1] - t[i + 1];
+                if (den > 0.0) right = (t[i + j + 1] - x) / den * tab[j - 1][a];
+            }
+            tab[j][a] = left + right;
+        }
+    }
+    for (int a = 0; a <= p; ++a) vals[a] = tab[p][a];
+    /* derivative: B'_{i,k} = (k-1) [B_{i,k-1}/(t_{i+k-1}-t_i) - B_{i+1,k-1}/(t_{i+k}-t_{i+1})] */
+    for (int a = 0; a <= p; ++a) {
+        int i = mu - p + a;
+        double d = 0.0;
+        if (p == 0) { ders[a] = 0.0; continue; }
+        if (a >= 1) {
+            double den = t[i + p] - t[i];
+            if (den > 0.0) d += tab[p - 1][a - 1] / den;
+        }
+        if (a <= p - 1) {
+            double den = t[i + p + 1] - t[i + 1];
+            if (den > 0.0) d -= tab[p - 1][a] / den;
+        }
+        ders[a] = p * d;
+    }
+}
+
+/* B-spline values at arbitrary points, full (un-reduced) basis: out[j*nb + i]
+ * = B_i(x_j), nb = nbr + p - 1.  Used by the tests to pin the evaluator. */
+int orc_bspline_values(const double *br, int nbr, int order, const double *x,
+                       int nx, double *vals, double *ders)
+{
+    if (check_breaks(br, nbr) != ORC_OK || order < 2 || order > 15) return ORC_EINVAL;
+    int p = order - 1, nb = nbr + p - 1;
+    double *t = malloc(sizeof(double) * (nbr + 2 * p));
+    if (!t) return ORC_ENOMEM;
+    make_knots(br, nbr, order, t);
+    for (int j = 0; j < nx; ++j) {
+        for (int i = 0; i < nb; ++i) {
+            vals[j * nb + i] = 0.0;
+            if (ders) ders[j * nb + i] = 0.0;
+        }
+        if (x[j] < br[0] || x[j] > br[nbr - 1]) continue;
+        int e = 0;
+        while (e + 2 < nbr && x[j] >= br[e + 1]) ++e;
+        int mu = p + e;
+        double v[16], dv[16];
+        bspline_span_eval(t, order, mu, x[j], v, dv);
+        for (int a = 0; a <= p; ++a) {
+            vals[j * nb + e + a] = v[a];
+            if (ders) ders[j * nb + e + a] = dv[a];
+        }
+    }
+    free(t);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Galerkin matrices (section V.A, element formulas for the overlap matrix, */
+/* the BenDaniel-Duke kinetic matrix, the potential and dipole matrices;    */
+/* section II.C eq. matrixODE and the definitions of M and H above it).     */
+/* The acceleration matrices G = <B| m^-1 dV/dx |B> and Mi = <B| m^-1 |B>   */
+/* are the matrix forms of the Ehrenfest expectation in eq.                 */
+/* pdm_acceleration (section IV.A) without its a_Q term.                    */
+/*                                                                          */
+/* Inputs minv_q, V_q, dV_q are the caller's samples of 1/m(x), V(x) and    */
+/* V'(x) at the points orc_quad_points returns (span-major).  Any output    */
+/* pointer may be NULL.                                                     */
+/* ------------------------------------------------------------------------ */
+int orc_assemble(const double *br, int nbr, int order, int nq,
+                 const double *minv_q, const double *V_q, const double *dV_q,
+                 double *S, double *T, double *V, double *D, double *G,
+                 double *Mi)
+{
+    if (check_breaks(br, nbr) != ORC_OK || order < 2 || order > 15 || nq < 1 || nq > 64)
+        return ORC_EINVAL;
+    int p = order - 1;
+    int N = orc_ndof(nbr, order);
+    if (N < 1) return ORC_EINVAL;
+    int nel = nbr - 1;
+    double *out[6] = {S, T, V, D, G, Mi};
+    for (int m = 0; m < 6; ++m)
+        if (out[m]) memset(out[m], 0, sizeof(double) * (size_t)(p + 1) * N);
+
+    double *t = malloc(sizeof(double) * (nbr + 2 * p));
+    double *xq = malloc(sizeof(double) * nel * nq);
+    double *wq = malloc(sizeof(double) * nel * nq);
+    if (!t || !xq || !wq) { free(t); free(xq); free(wq); return ORC_ENOMEM; }
+    make_knots(br, nbr, order, t);
+    orc_quad_points(br, nbr, nq, xq, wq);
+
+    for (int e = 0; e < nel; ++e) {
+        int mu = p + e; /* t[mu] = br[e], t[mu+1] = br[e+1] */
+        for (int q = 0; q < nq; ++q) {
+            int iq = e * nq + q;
+            double x = xq[iq], w = wq[iq];
+            double Nv[16], dN[16];
+            bspline_span_eval(t, order, mu, x, Nv, dN);
+            double minv = minv_q ? minv_q[iq] : 1.0;
+            double Vx = V_q ? V_q[iq] : 0.0;
+            double dVx = dV_q ? dV_q[iq] : 0.0;
+            for (int a = 0; a <= p; ++a) {
+                int gi = e + a; /* global B-spline index */
+                int i = gi - 1; /* unknown index after Dirichlet removal */
+                if (i < 0 || i >= N) continue;
+                for (int b = a; b <= p; ++b) {
+                    int j = e + b - 1;
+                    if (j < 0 || j >= N) continue;
+                    int d = b - a;
+                    size_t at = (size_t)d * N + i;
+                    double nn = w * Nv[a] * Nv[b];
+                    if (S) S[at] += nn;                                   /* overlap  */
+                    if (T) T[at] += 0.5 * w * minv * dN[a] * dN[b];       /* BDD kin. */
+                    if (V) V[at] += nn * Vx;                              /* potential */
+                    if (D) D[at] += nn * x;                               /* dipole   */
+                    if (G) G[at] += nn * minv * dVx;                      /* m^-1 V'  */
+                    if (Mi) Mi[at] += nn * minv;                          /* m^-1     */
+                }
+            }
+        }
+    }
+    free(t); free(xq); free(wq);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Small dense / banded linear algebra (textbook algorithms).                */
+/* ------------------------------------------------------------------------ */
+
+/* y = M x for a real symmetric half-band M and a real vector x. */
+static void symband_mul_real(int N, int p, const double *M, const double *x, double *y)
+{
+    for (int i = 0; i < N; ++i) {
+        double s = M[i] * x[i];
+        for (int d = 1; d <= p; ++d) {
+            if (i + d < N) s += M[(size_t)d * N + i] * x[i + d];
+            if (i - d >= 0) s += M[(size_t)d * N + i - d] * x[i - d];
+        }
+        y[i] = s;
+    }
+}
+
+/* y = M x for a real symmetric half-band M and a complex vector x. */
+static void symband_mul_cplx(int N, int p, const double *M, const zd *x, zd *y)
+{
+    for (int i = 0; i < N; ++i) {
+        zd s = M[i] * x[i];
+        for (int d = 1; d <= p; ++d) {
+            if (i + d < N) s += M[(size_t)d * N + i] * x[i + d];
+            if (i - d >= 0) s += M[(size_t)d * N + i - d] * x[i - d];
+        }
+        y[i] = s;
+    }
+}
+
+/* Expectation value x^H M x (real, M real symmetric), summed in FP64 in row
+ * order.  Exposed for the tests. */
+double orc_expect(int N, int p, const double *M, const double *xin)
+{
+    const zd *x = (const zd *)xin;
+    zd *y = malloc(sizeof(zd) * N);
+    symband_mul_cplx(N, p, M, x, y);
+    double s = 0.0;
+    for (int i = 0; i < N; ++i) s += creal(conj(x[i]) * y[i]);
+    free(y);
+    return s;
+}
+
+/* General banded complex matrix, row-major with 2p+1 entries per row:
+ * A[i][i+d] at a[i*(2p+1) + d + p], d = -p..p.
+ * LU factorisation without pivoting (Doolittle), in place: afterwards the
+ * strictly lower part holds L (unit diagonal implied) and the rest holds U.
+ * No pivoting is needed for the Crank-Nicolson matrix S + i a H: its
+ * Hermitian part S is positive definite, so every leading principal minor is
+ * non-zero. */
+static int zband_lu(int N, int p, zd *a)
+{
+    int w = 2 * p + 1;
+    for (int k = 0; k < N; ++k) {
+        zd piv = a[(size_t)k * w + p];
+        if (piv == 0.0) return ORC_ESING;
+        for (int i = k + 1; i <= k + p && i < N; ++i) {
+            /* A[i][k] lives at offset d = k - i */
+            zd *aik = &a[(size_t)i * w + (k - i) + p];
+            zd l = *aik / piv;
+            *aik = l;
+            for (int j = k + 1; j <= k + p && j < N; ++j)
+                a[(size_t)i * w + (j - i) + p] -= l * a[(size_t)k * w + (j - k) + p];
+        }
+    }
+    return ORC_OK;
+}
+
+static void zband_lu_solve(int N, int p, const zd *a, zd *x)
+{
+    int w = 2 * p + 1;
+    for (int i = 0; i < N; ++i) /* L y = b */
+        for (int k = (i - p > 0 ? i - p : 0); k < i; ++k)
+            x[i] -= a[(size_t)i * w + (k - i) + p] * x[k];
+    for (int i = N - 1; i >= 0; --i) { /* U x = y */
+        for (int j = i + 1; j <= i + p && j < N; ++j)
+            x[i] -= a[(size_t)i * w + (j - i) + p] * x[j];
+        x[i] /= a[(size_t)i * w + p];
+    }
+}
+
+/* Real version of the same banded LU (used for H - sigma S). */
+static int dband_lu(int N, int p, double *a)
+{
+    int w = 2 * p + 1;
+    for (int k = 0; k < N; ++k) {
+        double piv = a[(size_t)k * w + p];
+        if (piv == 0.0) return ORC_ESING;
+        for (int i = k + 1; i <= k + p && i < N; ++i) {
+            double *aik = &a[(size_t)i * w + (k - i) + p];
+            double l = *aik / piv;
+            *aik = l;
+            for (int j = k + 1; j <= k + p && j < N; ++j)
+                a[(size_t)i * w + (j - i) + p] -= l * a[(size_t)k * w + (j - k) + p];
+        }
+    }
+    return ORC_OK;
+}
+
+static void dband_lu_solve(int N, int p, const double *a, double *x)
+{
+    int w = 2 * p + 1;
+    for (int i = 0; i < N; ++i)
+        for (int k = (i - p > 0 ? i - p : 0); k < i; ++k)
+            x[i] -= a[(size_t)i * w + (k - i) + p] * x[k];
+    for (int i = N - 1; i >= 0; --i) {
+        for (int j = i + 1; j <= i + p && j < N; ++j)
+            x[i] -= a[(size_t)i * w + (j - i) + p] * x[j];
+        x[i] /= a[(size_t)i * w + p];
+    }
+}
+
+/* Cyclic Jacobi eigenvalue algorithm for a dense real symmetric n x n matrix
+ * a (row-major, destroyed).  Eigenvalues to ev (ascending), eigenvectors to
+ * the columns of v (row-major v[i*n + j] = component i of vector j). */
+static int jacobi_eig(int n, double *a, double *ev, double *v)
+{
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) v[i * n + j] = (i == j) ? 1.0 : 0.0;
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        double off = 0.0, tot = 0.0;
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                tot += a[i * n + j] * a[i * n + j];
+                if (i != j) off += a[i * n + j] * a[i * n + j];
+            }
+        if (off <= 1e-30 * tot || off == 0.0) break;
+        for (int p = 0; p < n - 1; ++p)
+            for (int q = p + 1; q < n; ++q) {
+                double apq = a[p * n + q];
+                if (apq == 0.0) continue;
+                double app = a[p * n + p], aqq = a[q * n + q];
+                /* rotation angle annihilating a_pq (Golub & Van Loan, sym. Schur 2x2) */
+                double tau = (aqq - app) / (2.0 * apq);
+                double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                double c = 1.0 / sqrt(1.0 + tt * tt), s = tt * c;
+                for (int k = 0; k < n; ++k) { /* A <- A J */
+                    double akp = a[k * n + p], akq = a[k * n + q];
+                    a[k * n + p] = c * akp - s * akq;
+                    a[k * n + q] = s * akp + c * akq;
+                }
+                for (int k = 0; k < n; ++k) { /* A <- J^T A */
+                    double apk = a[p * n + k], aqk = a[q * n + k];
+                    a[p * n + k] = c * apk - s * aqk;
+                    a[q * n + k] = s * apk + c * aqk;
+                }
+                for (int k = 0; k < n; ++k) { /* V <- V J */
+                    double vkp = v[k * n + p], vkq = v[k * n + q];
+                    v[k * n + p] = c * vkp - s * vkq;
+                    v[k * n + q] = s * vkp + c * vkq;
+                }
+            }
+    }
+    for (int i = 0; i < n; ++i) ev[i] = a[i * n + i];
+    /* sort ascending (selection sort, swapping eigenvector columns) */
+    for (int i = 0; i < n; ++i) {
+        int m = i;
+        for (int j = i + 1; j < n; ++j)
+            if (ev[j] < ev[m]) m = j;
+        if (m != i) {
+            double t = ev[i]; ev[i] = ev[m]; ev[m] = t;
+            for (int k = 0; k < n; ++k) {
+                double tv = v[k * n + i]; v[k * n + i] = v[k * n + m]; v[k * n + m] = tv;
+            }
+        }
+    }
+    return ORC_OK;
+}
+
+/* Sign convention for real eigenvectors: the component of largest magnitude
+ * is made positive (lowest index on ties).  Real eigenvectors of the real
+ * symmetric pencil are the result of the phase realignment of section IV.C
+ * (rotation by exp(-i arg(phi^T M phi)/2)); what remains is the sign. */
+static void fix_sign(int N, double *c)
+{
+    int im = 0;
+    for (int i = 1; i < N; ++i)
+        if (fabs(c[i]) > fabs(c[im])) im = i;
+    if (c[im] < 0.0)
+        for (int i = 0; i < N; ++i) c[i] = -c[i];
+}
+
+/* Dense route for the generalised eigenproblem H c = e S c (section II.C eq.
+ * gen_ev): Cholesky S = L L^T, C = L^-1 H L^-T, Jacobi on C, c = L^-T y.
+ * For small N only (O(N^3)).  evecs is N x N column-major-by-vector:
+ * evecs[j*N + i] = component i of eigenvector j, S-normalised. */
+int orc_eig_dense(int N, int p, const double *H, const double *S, double *evals,
+                  double *evecs)
+{
+    if (N < 1) return ORC_EINVAL;
+    double *L = calloc((size_t)N * N, sizeof(double));
+    double *C = calloc((size_t)N * N, sizeof(double));
+    double *Y = malloc(sizeof(double) * (size_t)N * N);
+    if (!L || !C || !Y) { free(L); free(C); free(Y); return ORC_ENOMEM; }
+    /* dense copies */
+    for (int i = 0; i < N; ++i)
+        for (int d = 0; d <= p && i + d < N; ++d) {
+            L[(size_t)i * N + i + d] = L[(size_t)(i + d) * N + i] = S[(size_t)d * N + i];
+            C[(size_t)i * N + i + d] = C[(size_t)(i + d) * N + i] = H[(size_t)d * N + i];
+        }
+    /* Cholesky in place (lower triangle) */
+    for (int j = 0; j < N; ++j) {
+        double s = L[(size_t)j * N + j];
+        for (int k = 0; k < j; ++k) s -= L[(size_t)j * N + k] * L[(size_t)j * N + k];
+        if (s <= 0.0) { free(L); free(C); free(Y); return ORC_ESING; }
+        double ljj = sqrt(s);
+        L[(size_t)j * N + j] = ljj;
+        for (int i = j + 1; i < N; ++i) {
+            double t = L[(size_t)i * N + j];
+            for (int k = 0; k < j; ++k) t -= L[(size_t)i * N + k] * L[(size_t)j * N + k];
+            L[(size_t)i * N + j] = t / ljj;
+        }
+    }
+    /* C <- L^-1 C (forward substitution on each column) */
+    for (int c = 0; c < N; ++c)
+        for (int i = 0; i < N; ++i) {
+            double t = C[(size_t)i * N + c];
+            for (int k = 0; k < i; ++k) t -= L[(size_t)i * N + k] * C[(size_t)k * N + c];
+            C[(size_t)i * N + c] = t / L[(size_t)i * N + i];
+        }
+    /* C <- C L^-T (forward substitution on each row) */
+    for (int r = 0; r < N; ++r)
+        for (int j = 0; j < N; ++j) {
+            double t = C[(size_t)r * N + j];
+            for (int k = 0; k < j; ++k) t -= C[(size_t)r * N + k] * L[(size_t)j * N + k];
+            C[(size_t)r * N + j] = t / L[(size_t)j * N + j];
+        }
+    /* symmetrise against rounding */
+    for (int i = 0; i < N; ++i)
+        for (int j = i + 1; j < N; ++j) {
+            double m = 0.5 * (C[(size_t)i * N + j] + C[(size_t)j * N + i]);
+            C[(size_t)i * N + j] = C[(size_t)j * N + i] = m;
+        }
+    jacobi_eig(N, C, evals, Y);
+    /* back-transform: c_j = L^-T y_j */
+    for (int j = 0; j < N; ++j) {
+        double *c = evecs + (size_t)j * N;
+        for (int i = 0; i < N; ++i) c[i] = Y[(size_t)i * N + j];
+        for (int i = N - 1; i >= 0; --i) {
+            double t = c[i];
+            for (int k = i + 1; k < N; ++k) t -= L[(size_t)k * N + i] * c[k];
+            c[i] = t / L[(size_t)i * N + i];
+        }
+        fix_sign(N, c);
+    }
+    free(L); free(C); free(Y);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Banded route for the lowest eigenpairs of H c = e S c (section II.C eq.  */
+/* gen_ev; section V.C uses shift-and-invert).  Shift-and-invert subspace    */
+/* iteration with Rayleigh-Ritz:                                             */
+/*   K = H - sigma S factorised once (banded LU, no pivoting: sigma must lie */
+/*   below the lowest eigenvalue so that K is positive definite);            */
+/*   repeat: W = K^-1 S V; S-orthonormalise W (modified Gram-Schmidt);       */
+/*   Rayleigh-Ritz on span(W) with the dense Jacobi solver; until every      */
+/*   wanted Ritz pair has relative residual below tol, or the residual has   */
+/*   reached its round-off floor (below 1e-11 and no longer halving over 25  */
+/*   iterations).                                                            */
+/* evecs[j*N + i]: component i of eigenvector j (real, S-normalised).       */
+/* ------------------------------------------------------------------------ */
+int orc_eig_banded(int N, int p, const double *H, const double *S, int nev,
+                   double sigma, double tol, int maxit, double *evals, double *evecs)
+{
+    if (N < 1 || nev < 1 || nev > N) return ORC_EINVAL;
+    int nb = 2 * nev + 4;
+    if (nb > N) nb = N;
+    int w = 2 * p + 1;
+    double *K = calloc((size_t)N * w, sizeof(double));
+    double *V = malloc(sizeof(double) * (size_t)nb * N);
+    double *SV = malloc(sizeof(double) * (size_t)nb * N);
+    double *HV = malloc(sizeof(double) * (size_t)nb * N);
+    double *Hs = malloc(sizeof(double) * (size_t)nb * nb);
+    double *Ys = malloc(sizeof(double) * (size_t)nb * nb);
+    double *ev = malloc(sizeof(double) * nb);
+    double *tmp = malloc(sizeof(double) * (size_t)nb * N);
+    if (!K || !V || !SV || !HV || !Hs || !Ys || !ev || !tmp) {
+        free(K); free(V); free(SV); free(HV); free(Hs); free(Ys); free(ev); free(tmp);
+        return ORC_ENOMEM;
+    }
+    for (int i = 0; i < N; ++i)
+        for (int d = -p; d <= p; ++d) {
+            int j = i + d;
+            if (j < 0 || j >= N) continue;
+            int lo = i < j ? i : j, dd = d < 0 ? -d : d;
+            K[(size_t)i * w + d + p] = H[(size_t)dd * N + lo] - sigma * S[(size_t)dd * N + lo];
+        }
+    int rc = dband_lu(N, p, K);
+    if (rc) goto done;
+    /* deterministic start vectors: smooth, linearly independent */
+    for (int j = 0; j < nb; ++j)
+        for (int i = 0; i < N; ++i)
+            V[(size_t)j * N + i] = sin(PI * (j + 1) * (i + 1.0) / (N + 1.0)) + 1e-3 * cos(0.37 * (i + 1) * (j + 2));
+    rc = ORC_ENOCONV;
+    double best25 = 1e300;
+    for (int it = 0; it < maxit; ++it) {
+        /* W = K^-1 S V */
+        for (int j = 0; j < nb; ++j) {
+            double *vj = V + (size_t)j * N;
+            symband_mul_real(N, p, S, vj, tmp);
+            dband_lu_solve(N, p, K, tmp);
+            memcpy(vj, tmp, sizeof(double) * N);
+        }
+        /* S-orthonormalise (modified Gram-Schmidt, twice for stability) */
+        for (int pass = 0; pass < 2; ++pass)
+            for (int j = 0; j < nb; ++j) {
+                double *vj = V + (size_t)j * N;
+                for (int k = 0; k < j; ++k) {
+                    double *vk = V + (size_t)k * N;
+                    symband_mul_real(N, p, S, vk, tmp);
+                    double dot = 0.0;
+                    for (int i = 0; i < N; ++i) dot += tmp[i] * vj[i];
+                    for (int i = 0; i < N; ++i) vj[i] -= dot * vk[i];
+                }
+                symband_mul_real(N, p, S, vj, tmp);
+                double nrm = 0.0;
+                for (int i = 0; i < N; ++i) nrm += tmp[i] * vj[i];
+                nrm = sqrt(nrm);
+                for (int i = 0; i < N; ++i) vj[i] /= nrm;
+            }
+        /* Rayleigh-Ritz: Hs = V^T H V (V is S-orthonormal) */
+        for (int j = 0; j < nb; ++j) symband_mul_real(N, p, H, V + (size_t)j * N, HV + (size_t)j * N);
+        for (int a = 0; a < nb; ++a)
+            for (int b = 0; b < nb; ++b) {
+                double s = 0.0;
+                for (int i = 0; i < N; ++i) s += V[(size_t)a * N + i] * HV[(size_t)b * N + i];
+                Hs[a * nb + b] = s;
+            }
+        for (int a = 0; a < nb; ++a)
+            for (int b = a + 1; b < nb; ++b) {
+                double m = 0.5 * (Hs[a * nb + b] + Hs[b * nb + a]);
+                Hs[a * nb + b] = Hs[b * nb + a] = m;
+            }
+        jacobi_eig(nb, Hs, ev, Ys);
+        /* rotate the basis to the Ritz vectors */
+        for (int j = 0; j < nb; ++j)
+            for (int i = 0; i < N; ++i) {
+                double s = 0.0;
+                for (int a = 0; a < nb; ++a) s += V[(size_t)a * N + i] * Ys[a * nb + j];
+                SV[(size_t)j * N + i] = s;
+            }
+        memcpy(V, SV, sizeof(double) * (size_t)nb * N);
+        /* convergence: relative residual of every wanted Ritz pair,
+         * |H v - e S v| / (|H v| + |e| |S v|) < tol (vectors, not only
+         * values, must have converged) */
+        double delta = 0.0;
+        for (int j = 0; j < nev; ++j) {
+            double *vj = V + (size_t)j * N;
+            symband_mul_real(N, p, H, vj, HV);
+            symband_mul_real(N, p, S, vj, tmp);
+            double r2 = 0.0, h2 = 0.0, s2 = 0.0;
+            for (int i = 0; i < N; ++i) {
+                double r = HV[i] - ev[j] * tmp[i];
+                r2 += r * r;
+                h2 += HV[i] * HV[i];
+                s2 += tmp[i] * tmp[i];
+            }
+            double r = sqrt(r2) / (sqrt(h2) + fabs(ev[j]) * sqrt(s2));
+            if (r > delta) delta = r;
+        }
+        if (delta < tol) { rc = ORC_OK; break; }
+        /* round-off floor: the residual has stopped decreasing */
+        if (it % 25 == 0) {
+            if (delta > 0.5 * best25 && delta < 1e-11) { rc = ORC_OK; break; }
+            best25 = delta;
+        }
+    }
+    for (int j = 0; j < nev; ++j) {
+        evals[j] = ev[j];
+        memcpy(evecs + (size_t)j * N, V + (size_t)j * N, sizeof(double) * N);
+        fix_sign(N, evecs + (size_t)j * N);
+    }
+done:
+    free(K); free(V); free(SV); free(HV); free(Hs); free(Ys); free(ev); free(tmp);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Crank-Nicolson propagation (section V.B, eq. cn_system):                 */
+/*   (S + i dt/2 H^{n+1/2}) c^{n+1} = (S - i dt/2 H^{n+1/2}) c^n,          */
+/*   H^{n+1/2} = (H^n + H^{n+1})/2 = H0 + Ebar_n D,  Ebar_n = (E_n+E_{n+1})/2 */
+/* (the length-gauge coupling E(t) x of section II.B eq. laser is linear in */
+/* E, so the average of the endpoint Hamiltonians is H0 + Ebar D).          */
+/* The linear system is solved exactly by banded LU (no Krylov solver).     */
+/*                                                                          */
+/* Observables at every n = 0..nsteps, row-major obs[n*3 + k]:              */
+/*   k=0  nu_n = c^H S c              (M-norm, section V.B)                 */
+/*   k=1  d_n  = Re c^H D c           (section IV.A dipole)                 */
+/*   k=2  a_n  = -Re c^H G c - E_n Re c^H Mi c                              */
+/*        (section IV.A eq. pdm_acceleration without a_Q)                   */
+/* No normalisation by nu_n is applied.  G or Mi may be NULL (then the      */
+/* corresponding terms are zero).  psi0/psi_out: interleaved complex, N.     */
+/* ------------------------------------------------------------------------ */
+static void build_cn(int N, int p, const double *S, const double *H0, const double *D,
+                     double Eb, double alpha, double sgn, zd *a)
+{
+    int w = 2 * p + 1;
+    for (int i = 0; i < N; ++i)
+        for (int d = -p; d <= p; ++d) {
+            int j = i + d;
+            zd v = 0.0;
+            if (j >= 0 && j < N) {
+                int lo = i < j ? i : j, dd = d < 0 ? -d : d;
+                size_t at = (size_t)dd * N + lo;
+                double h = H0[at] + Eb * D[at];
+                v = S[at] + sgn * I * alpha * h;
+            }
+            a[(size_t)i * w + d + p] = v;
+        }
+}
+
+/* y = A x for a general complex band (row-major, 2p+1 per row). */
+static void zband_mul(int N, int p, const zd *a, const zd *x, zd *y)
+{
+    int w = 2 * p + 1;
+    for (int i = 0; i < N; ++i) {
+        zd s = 0.0;
+        for (int d = -p; d <= p; ++d) {
+            int j = i + d;
+            if (j >= 0 && j < N) s += a[(size_t)i * w + d + p] * x[j];
+        }
+        y[i] = s;
+    }
+}
+
+static void observe(int N, int p, const double *S, const double *D, const double *G,
+                    const double *Mi, const zd *c, double En, double *o)
+{
+    o[0] = orc_expect(N, p, S, (const double *)c);
+    o[1] = orc_expect(N, p, D, (const double *)c);
+    double a = 0.0;
+    if (G) a -= orc_expect(N, p, G, (const double *)c);
+    if (Mi) a -= En * orc_expect(N, p, Mi, (const double *)c);
+    o[2] = a;
+}
+
+int orc_propagate(int N, int p, const double *S, const double *H0, const double *D,
+                  const double *G, const double *Mi, const double *psi0, const double *E,
+                  double dt, int nsteps, double *obs, double *psi_out)
+{
+    if (N < 1 || p < 0 || nsteps < 0) return ORC_EINVAL;
+    int w = 2 * p + 1;
+    double alpha = 0.5 * dt;
+    zd *c = malloc(sizeof(zd) * N);
+    zd *b = malloc(sizeof(zd) * N);
+    zd *A = malloc(sizeof(zd) * (size_t)N * w);
+    zd *B = malloc(sizeof(zd) * (size_t)N * w);
+    if (!c || !b || !A || !B) { free(c); free(b); free(A); free(B); return ORC_ENOMEM; }
+    memcpy(c, psi0, sizeof(zd) * N);
+    int rc = ORC_OK;
+    for (int n = 0; n < nsteps; ++n) {
+        if (obs) observe(N, p, S, D, G, Mi, c, E[n], obs + (size_t)n * 3);
+        double Eb = 0.5 * (E[n] + E[n + 1]);
+        build_cn(N, p, S, H0, D, Eb, alpha, -1.0, B);
+        build_cn(N, p, S, H0, D, Eb, alpha, +1.0, A);
+        zband_mul(N, p, B, c, b);
+        rc = zband_lu(N, p, A);
+        if (rc) break;
+        zband_lu_solve(N, p, A, b);
+        memcpy(c, b, sizeof(zd) * N);
+    }
+    if (!rc && obs) observe(N, p, S, D, G, Mi, c, E[nsteps], obs + (size_t)nsteps * 3);
+    if (!rc && psi_out) memcpy(psi_out, c, sizeof(zd) * N);
+    free(c); free(b); free(A); free(B);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Discrete adjoint of orc_propagate (no counterpart in the paper; derived  */
+/* from eq. cn_system).  With A_n = S + i a H_n, B_n = S - i a H_n,          */
+/* H_n = H0 + Ebar_n D all real symmetric, A_n^H = B_n, so the transposed    */
+/* one-step map (A_n^-1 B_n)^H = A_n B_n^-1.  For a real objective          */
+/* J(nu, d, acc) with given partials dJ/dobs[n][k], and the convention       */
+/* dJ = Re(g^H dc) for complex states:                                      */
+/*   g_n   = 2 (dJ/dnu_n S c_n + dJ/dd_n D c_n - dJ/da_n (G c_n + E_n Mi c_n)) */
+/*   lam_N = g_N;  z_n = B_n^-1 lam_{n+1};  lam_n = g_n + A_n z_n            */
+/*   dJ/dEbar_n = a Im( z_n^H D (c_n + c_{n+1}) )                           */
+/*   dJ/dE_n = (dJ/dEbar_{n-1} + dJ/dEbar_n)/2 - dJ/da_n Re(c_n^H Mi c_n)    */
+/* All forward states are stored (one system at a time).                   */
+/* dJdE: nsteps+1 outputs.  dJdpsi0 (may be NULL) receives lam_0.           */
+/* ------------------------------------------------------------------------ */
+int orc_adjoint(int N, int p, const double *S, const double *H0, const double *D,
+                const double *G, const double *Mi, const double *psi0, const double *E,
+                double dt, int nsteps, const double *dJdobs, double *dJdE, double *dJdpsi0)
+{
+    if (N < 1 || nsteps < 0) return ORC_EINVAL;
+    int w = 2 * p + 1;
+    double alpha = 0.5 * dt;
+    zd *C = malloc(sizeof(zd) * (size_t)N * (nsteps + 1));
+    zd *A = malloc(sizeof(zd) * (size_t)N * w);
+    zd *B = malloc(sizeof(zd) * (size_t)N * w);
+    zd *lam = malloc(sizeof(zd) * N), *z = malloc(sizeof(zd) * N);
+    zd *t1 = malloc(sizeof(zd) * N), *t2 = malloc(sizeof(zd) * N);
+    double *dEb = malloc(sizeof(double) * (nsteps > 0 ? nsteps : 1));
+    if (!C || !A || !B || !lam || !z || !t1 || !t2 || !dEb) {
+        free(C); free(A); free(B); free(lam); free(z); free(t1); free(t2); free(dEb);
+        return ORC_ENOMEM;
+    }
+    int rc = ORC_OK;
+    memcpy(C, psi0, sizeof(zd) * N);
+    for (int n = 0; n < nsteps && !rc; ++n) { /* forward, storing every state */
+        double Eb = 0.5 * (E[n] + E[n + 1]);
+        build_cn(N, p, S, H0, D, Eb, alpha, -1.0, B);
+        build_cn(N, p, S, H0, D, Eb, alpha, +1.0, A);
+        zd *cn = C + (size_t)n * N, *cn1 = C + (size_t)(n + 1) * N;
+        zband_mul(N, p, B, cn, cn1);
+        rc = zband_lu(N, p, A);
+        if (!rc) zband_lu_solve(N, p, A, cn1);
+    }
+    /* g_n into lam (for n = nsteps) */
+#define GRAD_OBS(n, out)                                                           \
+    do {                                                                           \
+        const zd *cc = C + (size_t)(n) * N;                                        \
+        double jn = dJdobs[(size_t)(n) * 3 + 0], jd = dJdobs[(size_t)(n) * 3 + 1]; \
+        double ja = dJdobs[(size_t)(n) * 3 + 2];                                   \
+        for (int i = 0; i < N; ++i) out[i] = 0.0;                                  \
+        symband_mul_cplx(N, p, S, cc, t2);                                         \
+        for (int i = 0; i < N; ++i) out[i] += 2.0 * jn * t2[i];                    \
+        symband_mul_cplx(N, p, D, cc, t2);                                         \
+        for (int i = 0; i < N; ++i) out[i] += 2.0 * jd * t2[i];                    \
+        if (G) {                                                                   \
+            symband_mul_cplx(N, p, G, cc, t2);                                     \
+            for (int i = 0; i < N; ++i) out[i] -= 2.0 * ja * t2[i];                \
+        }                                                                          \
+        if (Mi) {                                                                  \
+            symband_mul_cplx(N, p, Mi, cc, t2);                                    \
+            for (int i = 0; i < N; ++i) out[i] -= 2.0 * ja * E[n] * t2[i];         \
+        }                                                                          \
+    } while (0)
+    if (!rc) {
+        GRAD_OBS(nsteps, lam);
+        for (int n = nsteps - 1; n >= 0 && !rc; --n) {
+            double Eb = 0.5 * (E[n] + E[n + 1]);
+            build_cn(N, p, S, H0, D, Eb, alpha, -1.0, B);
+            build_cn(N, p, S, H0, D, Eb, alpha, +1.0, A);
+            /* z = B^-1 lam_{n+1} */
+            memcpy(z, lam, sizeof(zd) * N);
+            rc = zband_lu(N, p, B);
+            if (rc) break;
+            zband_lu_solve(N, p, B, z);
+            /* dJ/dEbar_n = a Im(z^H D (c_n + c_{n+1})) */
+            const zd *cn = C + (size_t)n * N, *cn1 = C + (size_t)(n + 1) * N;
+            for (int i = 0; i < N; ++i) t1[i] = cn[i] + cn1[i];
+            symband_mul_cplx(N, p, D, t1, t2);
+            zd s = 0.0;
+            for (int i = 0; i < N; ++i) s += conj(z[i]) * t2[i];
+            dEb[n] = alpha * cimag(s);
+            /* lam_n = g_n + A_n z */
+            zband_mul(N, p, A, z, t1);
+            GRAD_OBS(n, lam);
+            for (int i = 0; i < N; ++i) lam[i] += t1[i];
+        }
+    }
+#undef GRAD_OBS
+    if (!rc) {
+        for (int n = 0; n <= nsteps; ++n) {
+            double g = 0.0;
+            if (n >= 1) g += 0.5 * dEb[n - 1];
+            if (n < nsteps) g += 0.5 * dEb[n];
+            if (Mi) g -= dJdobs[(size_t)n * 3 + 2] * orc_expect(N, p, Mi, (const double *)(C + (size_t)n * N));
+            dJdE[n] = g;
+        }
+        if (dJdpsi0) memcpy(dJdpsi0, lam, sizeof(zd) * N);
+    }
+    free(C); free(A); free(B); free(lam); free(z); free(t1); free(t2); free(dEb);
+    return rc;
+}

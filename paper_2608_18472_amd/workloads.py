@@ -1,0 +1,259 @@
+"""Seeded synthetic inputs: geometries, material profiles, potentials, pulses.
+
+This module defines *problems*, not the method: breakpoint sequences, the
+functions m^-1(x), V(x), V'(x) that a caller samples at quadrature points, and
+laser-field samples E_n = E(n dt).  It contains none of the discretisation
+arithmetic (no quadrature, no B-splines, no matrices, no propagation), so the
+GPU library and the CPU oracle can both be fed from it without sharing code.
+
+Units are Hartree atomic units.  The knot gradings are the coordinate maps of
+the paper's Table I (section III); the workloads reproduce the shapes of the
+paper's examples (soft-Coulomb atoms, the GaAs/AlGaAs double quantum well of
+section VII.B, the Quesne position-dependent-mass oscillator of section VII.A,
+the driven harmonic oscillator of Appendix A).  Everything is generated from
+parameters and seeds; no dataset is read.
+"""
+import math
+from dataclasses import dataclass, field
+from typing import Callable, Optional
+
+import numpy as np
+
+BOHR_PER_NM = 18.897261246257703  # 1 nm in bohr
+EV_PER_HA = 27.211386245988  # 1 Hartree in eV
+MEV_PER_HA = 1000.0 * EV_PER_HA
+
+
+# --------------------------------------------------------------------------
+# Knot gradings (Table I, section III).  t_i runs uniformly over [-1, 1].
+# --------------------------------------------------------------------------
+def _t(nel):
+    return -1.0 + 2.0 * np.arange(nel + 1) / nel
+
+
+def breaks_uniform(L, nel):
+    """x_i = -L + 2 i L / N_elem."""
+    return -L + 2.0 * L * np.arange(nel + 1) / nel
+
+
+def breaks_symexp(L, nel, alpha):
+    t = _t(nel)
+    return np.sign(t) * L * (np.exp(alpha * np.abs(t)) - 1.0) / (np.exp(alpha) - 1.0)
+
+
+def breaks_symtan(L, nel, alpha):
+    a_s = 0.5 * math.pi * alpha / (alpha + 1.0)
+    return L * np.tan(a_s * _t(nel)) / math.tan(a_s)
+
+
+def breaks_symtann(Lmin, Lmax, nel, beta):
+    """Clusters knots toward both ends of [Lmin, Lmax]."""
+    return Lmin + 0.5 * (Lmax - Lmin) * (1.0 + np.tanh(beta * _t(nel)) / math.tanh(beta))
+
+
+def breaks_symtanu(Lmin, Lmax, nel, beta):
+    """Clusters knots toward the middle of [Lmin, Lmax]."""
+    return Lmin + 0.5 * (Lmax - Lmin) * (1.0 + np.arctanh(_t(nel) * math.tanh(beta)) / beta)
+
+
+def breaks_hydrogenic(r1, nlin, nexp, Lmax):
+    """Radial: linear steps r1 up to r_cross = nlin*r1, then exponential to Lmax."""
+    rc = nlin * r1
+    lin = r1 * np.arange(nlin + 1)
+    k = np.arange(1, nexp + 1)
+    ex = rc * np.exp(k * math.log(Lmax / rc) / nexp)
+    return np.concatenate([lin, ex])
+
+
+def breaks_hydrogenic_symmetric(r1, nlin, nexp, Lmax):
+    """The radial hydrogenic map mirrored about 0 for a symmetric box."""
+    r = breaks_hydrogenic(r1, nlin, nexp, Lmax)
+    return np.concatenate([-r[::-1], r[1:]])
+
+
+def breaks_layered(interfaces, nel_total, beta=2.0):
+    """Breakpoints with every material interface on a breakpoint.
+
+    `interfaces` = sorted region boundaries x_0 < ... < x_R (box ends
+    included).  Spans are shared among regions in proportion to region length
+    (the rounding remainder goes to the widest region); inside each region the
+    `symtann` map clusters knots toward the region's two ends, i.e. toward the
+    interfaces.  No span straddles a jump of m or V."""
+    x = np.asarray(interfaces, dtype=float)
+    lens = np.diff(x)
+    share = lens / lens.sum() * nel_total
+    n = np.maximum(np.floor(share).astype(int), 1)
+    n[np.argmax(lens)] += nel_total - n.sum()
+    out = [np.array([x[0]])]
+    for r in range(len(lens)):
+        b = breaks_symtann(x[r], x[r + 1], int(n[r]), beta)
+        b[0], b[-1] = x[r], x[r + 1]
+        out.append(b[1:])
+    return np.concatenate(out)
+
+
+# --------------------------------------------------------------------------
+# Pulses.  E(t) is supplied to the propagator as samples E_n = E(n dt).
+# --------------------------------------------------------------------------
+def sin2_pulse(E0, omega, ncycles, dt, nsteps=None):
+    """E(t) = E0 sin^2(pi t / Tp) sin(omega t) on [0, Tp], 0 afterwards,
+    Tp = ncycles 2 pi / omega; nsteps defaults to ceil(Tp/dt)."""
+    Tp = ncycles * 2.0 * math.pi / omega
+    if nsteps is None:
+        nsteps = int(math.ceil(Tp / dt - 1e-9))
+    t = dt * np.arange(nsteps + 1)
+    E = np.where(t <= Tp, E0 * np.sin(math.pi * t / Tp) ** 2 * np.sin(omega * t), 0.0)
+    return E, nsteps, Tp
+
+
+def fourier_pulse(theta, Tp, dt, nsteps):
+    """E(t; theta) = sum_j theta_j sin(j pi t / Tp) on [0, Tp] (j = 1..len(theta))."""
+    t = dt * np.arange(nsteps + 1)
+    j = np.arange(1, len(theta) + 1)
+    basis = np.sin(np.outer(t, j) * math.pi / Tp) * (t <= Tp)[:, None]
+    return basis @ np.asarray(theta, dtype=float), basis
+
+
+# --------------------------------------------------------------------------
+# Problem description.
+# --------------------------------------------------------------------------
+@dataclass
+class System:
+    name: str
+    breaks: np.ndarray
+    order: int
+    minv: Callable
+    V: Callable
+    dV: Callable
+    nq: int = 10
+    E: Optional[np.ndarray] = None
+    dt: float = 0.0
+    nsteps: int = 0
+    const_mass: bool = True
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def p(self):
+        return self.order - 1
+
+    @property
+    def ndof(self):
+        return (len(self.breaks) - 1) + self.order - 3
+
+    def sample(self, xq):
+        xq = np.asarray(xq, dtype=float)
+        return (np.asarray(self.minv(xq), float), np.asarray(self.V(xq), float),
+                np.asarray(self.dV(xq), float))
+
+
+def _ones(x):
+    return np.ones_like(x)
+
+
+def _zeros(x):
+    return np.zeros_like(x)
+
+
+def soft_coulomb(a):
+    return (lambda x: -1.0 / np.sqrt(x * x + a)), (lambda x: x / (x * x + a) ** 1.5)
+
+
+def harmonic(omega=1.0):
+    return (lambda x: 0.5 * omega * omega * x * x), (lambda x: omega * omega * x)
+
+
+# --------------------------------------------------------------------------
+# Workloads.
+# --------------------------------------------------------------------------
+def config1(nsteps=None):
+    """1D soft-Coulomb atom V = -1/sqrt(x^2+2), order 8, 1000 uniform
+    breakpoints on [-200, 200] (N = 1004), sin^2 pulse w = 0.057, E0 = 0.0534,
+    4 cycles, dt = 0.05 (8819 steps)."""
+    V, dV = soft_coulomb(2.0)
+    E, ns, Tp = sin2_pulse(0.0534, 0.057, 4, 0.05, nsteps)
+    return System("soft-coulomb-1d", breaks_uniform(200.0, 999), 8, _ones, V, dV, 10, E, 0.05, ns,
+                  True, {"E0": 0.0534, "omega": 0.057, "Tp": Tp})
+
+
+def dqw_profile(wb_nm, lw_nm, mw, mb, V0_ha):
+    """Piecewise-constant conduction band and mass of a symmetric double
+    quantum well (section VII.B): barrier |x| < wb/2, wells, outer barriers."""
+    xb = 0.5 * wb_nm * BOHR_PER_NM
+    xw = xb + lw_nm * BOHR_PER_NM
+
+    def well(x):
+        ax = np.abs(x)
+        return (ax > xb) & (ax < xw)
+
+    minv = lambda x: np.where(well(x), 1.0 / mw, 1.0 / mb)
+    V = lambda x: np.where(well(x), 0.0, V0_ha)
+    return minv, V, xb, xw
+
+
+def config2(wb_nm=4.0, N=1500, nsteps=20000, E0=2e-5, outer_nm=30.0, beta=2.0):
+    """1D BenDaniel-Duke GaAs/Al0.3Ga0.7As double quantum well: 10 nm wells,
+    barrier wb, m* = 0.067 (well) / 0.0919 (barrier), offset 0.23 eV, box
+    +-(wb/2 + 10 + outer) nm, order 8, N unknowns with breakpoints on the four
+    interfaces; mid-IR sin^2 pulse (0.3 eV photon, 8 cycles)."""
+    order = 8
+    p = order - 1
+    minv, V, xb, xw = dqw_profile(wb_nm, 10.0, 0.067, 0.0919, 0.23 / EV_PER_HA)
+    L = xw + outer_nm * BOHR_PER_NM
+    nel = N - p + 2
+    br = breaks_layered([-L, -xw, -xb, xb, xw, L], nel, beta)
+    omega = 0.3 / EV_PER_HA
+    Tp = 8 * 2.0 * math.pi / omega
+    dt = Tp / nsteps
+    E, ns, _ = sin2_pulse(E0, omega, 8, dt, nsteps)
+    return System("dqw-bdd-1d", br, order, minv, V, _zeros, 10, E, dt, ns, False,
+                  {"wb_nm": wb_nm, "E0": E0, "omega": omega, "Tp": Tp})
+
+
+def dqw_static_paper(wb_nm=4.0, N=3000, box_nm=40.0, beta=2.0, order=8):
+    """The paper's static DQW (section VII.B): 8 nm wells, m_b = 0.092,
+    m_w = 0.067, V0 = 233.7 meV, box +-box_nm."""
+    p = order - 1
+    minv, V, xb, xw = dqw_profile(wb_nm, 8.0, 0.067, 0.092, 0.2337 / EV_PER_HA)
+    L = box_nm * BOHR_PER_NM
+    nel = N - p + 2
+    br = breaks_layered([-L, -xw, -xb, xb, xw, L], nel, beta)
+    return System("dqw-static", br, order, minv, V, _zeros, 10, const_mass=False,
+                  meta={"wb_nm": wb_nm})
+
+
+def config3(nsys=1024, seed=0):
+    """Batch of soft-Coulomb systems with seeded uneven sizes and pulses:
+    per system, in this order, N ~ U{500..4000}, order ~ U{6,7,8},
+    E0 = exp(U(ln 0.02, ln 0.1)), omega ~ U(0.03, 0.08); uniform breakpoints
+    on [-200, 200] with N - p + 2 spans, 4-cycle sin^2, dt = 0.05."""
+    rng = np.random.default_rng(seed)
+    V, dV = soft_coulomb(2.0)
+    out = []
+    for s in range(nsys):
+        N = int(rng.integers(500, 4001))
+        order = int(rng.integers(6, 9))
+        E0 = float(math.exp(rng.uniform(math.log(0.02), math.log(0.1))))
+        omega = float(rng.uniform(0.03, 0.08))
+        p = order - 1
+        E, ns, Tp = sin2_pulse(E0, omega, 4, 0.05)
+        out.append(System("batch-%d" % s, breaks_uniform(200.0, N - p + 2), order, _ones, V, dV, 10, E,
+                          0.05, ns, True, {"E0": E0, "omega": omega, "Tp": Tp}))
+    return out
+
+
+def driven_ho(E0=0.1, dt=0.01, tmax=10.0, L=12.0, nel=200, order=8):
+    """1D reduction of Appendix A: m = w = 1, E(t) = E0 sin t, from t = 0."""
+    V, dV = harmonic(1.0)
+    nsteps = int(round(tmax / dt))
+    t = dt * np.arange(nsteps + 1)
+    return System("driven-ho", breaks_uniform(L, nel), order, _ones, V, dV, 10, E0 * np.sin(t), dt, nsteps,
+                  True, {"E0": E0})
+
+
+def quesne(nel=8000, order=8, a=2.0, omega=1.0, xmax=50.0):
+    """Quesne PDM oscillator (section VII.A): M(x) = (1 + x/a)^-1 on
+    [-a, xmax], V_code = V_paper/2 with V_paper = a w^2 x^2 / (4 (x + a))
+    (the alpha = a^2 w case); exact levels w (n + 1/2) / 2."""
+    minv = lambda x: 1.0 + x / a
+    V = lambda x: 0.5 * a * omega * omega * x * x / (4.0 * (x + a))
+    return System("quesne", np.linspace(-a, xmax, nel + 1), order, minv, V, _zeros, 10, const_mass=False)
