@@ -1,0 +1,202 @@
+"""Throughput benchmark: batched Crank-Nicolson propagation on one MI355X.
+
+Workload: 1024 seeded soft-Coulomb systems of uneven size (N ~ U{500..4000},
+B-spline order 6-8, 4-cycle sin^2 pulses with seeded amplitude and carrier,
+dt = 0.05), all propagated over their whole pulse in one persistent launch.
+One benchmark step = one full propagation of the whole batch (every system,
+every time step, with the norm/dipole/acceleration series).
+
+Prints one JSON line.  Metric: complex DOF-steps/s = sum_i N_i nsteps_i /
+wall time of the propagate call (HIP events on the launch stream), for the
+FP32-refined path; the FP64 path is timed beside it and the dipole error of
+the FP32 path against the FP64 path is reported.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "complex DOF-steps/s per GPU, FP32-refined vs FP64 at dipole error ≤1e-5"
+HBM_PEAK_GBS = 8000.0
+
+
+def greville_gaussian(sd, width=1.0):
+    """Initial state: B-spline coefficients of exp(-x^2/(2 w^2)) by quasi-
+    interpolation at the Greville abscissae (unknown i is B-spline i+1)."""
+    p = sd.order - 1
+    br = sd.breaks
+    t = np.r_[[br[0]] * p, br, [br[-1]] * p]
+    N = sd.ndof
+    g = np.arange(1, N + 1)
+    xi = np.array([t[j + 1: j + 1 + p].mean() for j in g])
+    return np.exp(-0.5 * (xi / width) ** 2).astype(np.complex128)
+
+
+def _oracle_worker(args):
+    idx, nsteps = args
+    from oracle import oracle as O
+    from paper_2608_18472_amd import workloads as W
+    sd = W.config3(nsys=idx + 1, seed=0)[idx]
+    m = O.assemble(sd.breaks, sd.order, sd.nq, None, sd.V, sd.dV)
+    psi0 = greville_gaussian(sd)
+    t0 = time.perf_counter()
+    O.propagate(m, psi0, sd.E, sd.dt, nsteps)
+    return sd.ndof * nsteps, time.perf_counter() - t0
+
+
+def cpu_baseline(nsys_sample, nsteps):
+    """The oracle (serial FP64 C) on a bounded sample of the batch: one
+    system per worker process, one worker per host core (at most 16)."""
+    import multiprocessing as mp
+    from oracle import oracle as O
+    O.build()
+    cores = min(16, os.cpu_count() or 1)
+    jobs = [(i, nsteps) for i in range(nsys_sample)]
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(cores) as pool:
+        res = pool.map(_oracle_worker, jobs)
+    wall = time.perf_counter() - t0
+    dofsteps = sum(r[0] for r in res)
+    return {"value": dofsteps / wall, "unit": "DOF-steps/s", "cores": cores, "kind": "oracle",
+            "sample": "first %d systems of the batch, %d steps each (%.3g DOF-steps), serial FP64 C, "
+                      "one system per process, wall %.1f s" % (nsys_sample, nsteps, dofsteps, wall)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--nsys", type=int, default=1024)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-systems", type=int, default=48)
+    ap.add_argument("--cpu-steps", type=int, default=3000)
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the batched propagation has no multi-GPU path in this "
+              "build (run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2608_18472_amd import tdsez as T
+    from paper_2608_18472_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    dev = "cuda"
+    t_setup = time.perf_counter()
+    defs = W.config3(nsys=args.nsys, seed=0)
+    systems = [T.assemble_workload(s) for s in defs]
+    psi0s = []
+    for s, g in zip(defs, systems):
+        c = greville_gaussian(s)
+        S = T.get_band(g, "S")
+        nrm = float(np.real(np.vdot(c, _symband_mul(S, c))))
+        psi0s.append(c / math.sqrt(nrm))
+    psi_init, po, E, eo, obs, oo = T.pack_batch_inputs(defs, psi0s, dev)
+    dts = [s.dt for s in defs]
+    nsteps = [s.nsteps for s in defs]
+    dofsteps = float(sum(s.ndof * s.nsteps for s in defs))
+    batch = T.batch_create(systems)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t_setup
+
+    stream = torch.cuda.current_stream()
+
+    def run(prec, k, obs_buf):
+        psi = psi_init.clone()
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        for _ in range(k):
+            psi.copy_(psi_init)
+            T.propagate_batched(batch, psi, po, E, eo, dts, nsteps, prec, T.OBS_ALL, obs_buf, oo, stream)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        T.batch_status(batch, stream)
+        return ev0.elapsed_time(ev1) / 1000.0, psi
+
+    results = {}
+    precs = [("fp32-refined", T.FP32_REFINED)] + ([] if args.no_fp64 else [("fp64", T.FP64)])
+    obs_by = {}
+    for name, prec in precs:
+        ob = torch.zeros_like(obs)
+        if args.warmup > 0:
+            run(prec, args.warmup, ob)
+        sec, psi = run(prec, args.steps, ob)
+        results[name] = sec / args.steps
+        obs_by[name] = ob.cpu().numpy()
+
+    ms32 = results["fp32-refined"] * 1000.0
+    value = dofsteps / results["fp32-refined"]
+    eps_d = None
+    if "fp64" in obs_by:
+        e = []
+        for i in range(len(defs)):
+            a = obs_by["fp32-refined"][3 * eo[i]: 3 * eo[i] + 3 * (nsteps[i] + 1)].reshape(-1, 3)[:, 1]
+            b = obs_by["fp64"][3 * eo[i]: 3 * eo[i] + 3 * (nsteps[i] + 1)].reshape(-1, 3)[:, 1]
+            e.append(np.linalg.norm(a - b) / np.linalg.norm(b))
+        eps_d = float(max(e))
+    # algorithmic bytes per DOF-step: S, H0, D, G half bands (p+1 each) in the
+    # band precision, complex128 state read and written
+    def bytes_per(prec_bytes):
+        return sum(s.ndof * s.nsteps * (4 * s.order * prec_bytes + 2 * 16) for s in defs)
+    achieved = bytes_per(4) / results["fp32-refined"] / 1e9
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "DOF-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms32,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "batched 1D soft-Coulomb propagation: %d systems, N~U{500..4000}, B-spline order "
+                        "6-8, 4-cycle sin^2 pulses (E0 log-U[0.02,0.1], w U[0.03,0.08]), dt 0.05, seed 0"
+                        % len(defs),
+            "systems": len(defs),
+            "dof_steps": dofsteps,
+            "precision": "FP32 bands/factorisation/solve, FP64 residual/state/reductions",
+            "fp64_value": dofsteps / results["fp64"] if "fp64" in results else None,
+            "fp64_ms_per_step": results["fp64"] * 1000.0 if "fp64" in results else None,
+            "dipole_rel_err_fp32_vs_fp64": eps_d,
+            "setup_s": t_setup,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+        },
+    }
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(args.cpu_systems, args.cpu_steps)
+    print(json.dumps(line), flush=True)
+
+
+def _symband_mul(band, c):
+    p1, N = band.shape
+    y = band[0] * c
+    for d in range(1, p1):
+        y[:-d] += band[d, :N - d] * c[d:]
+        y[d:] += band[d, :N - d] * c[:-d]
+    return y
+
+
+if __name__ == "__main__":
+    main()

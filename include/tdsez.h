@@ -1,0 +1,192 @@
+/*
+ * tdsez.h -- C ABI of the MI355X (gfx950) Crank-Nicolson propagation library
+ * for the single-active-electron time-dependent Schroedinger equation on
+ * B-spline Galerkin matrices, after Dahbi & Zair, "Unified Strong-Field
+ * Dynamics Simulations from Atoms to Heterostructures" (arXiv 2608.18472).
+ *
+ * Problem statement (the paper's section II and section V):
+ *   i M dc/dt = H(t) c                                 (section II.C, eq. matrixODE)
+ *   H(t) = T_BDD + V + E(t) D,  T_BDD = 1/2 <grad B_J, m^-1 grad B_I>
+ *                                                      (section II.A-II.C, eq. laser)
+ *   (M + i dt/2 H^{n+1/2}) c^{n+1} = (M - i dt/2 H^{n+1/2}) c^n,
+ *   H^{n+1/2} = (H^n + H^{n+1})/2                      (section V.B, eq. cn_system)
+ * with the per-step observables of section IV.A: the M-norm, the dipole
+ * d = c^H D c and the Ehrenfest acceleration a = -<m^-1 (dV/dx + E)>
+ * (eq. pdm_acceleration without its a_Q term).  The mass matrix is called S
+ * here (the paper's M).
+ *
+ * Conventions for every entry point
+ *   - Return value: TDSEZ_OK (0) or an error code; tdsez_last_error() gives a
+ *     thread-local message for the last non-OK status of the calling thread.
+ *     No C++ exception ever crosses this boundary.
+ *   - Host inputs are copied before the call returns; the caller keeps
+ *     ownership.  Device pointers (marked "device") are caller-owned memory
+ *     on the current HIP device; the library never frees them.  Handles own
+ *     their device storage and release it in the matching destroy call.
+ *   - Work on device pointers is enqueued on the HIP stream `stream` (NULL =
+ *     the null stream) and is asynchronous unless stated otherwise.  Errors
+ *     that can only be seen on the device (a non-finite state, norm drift)
+ *     are latched in the handle and returned by tdsez_batch_status().
+ *   - Units: Hartree atomic units.  Complex vectors are interleaved
+ *     (re, im) doubles (complex128).
+ *   - Unknowns: B-splines of order k = p + 1 on the open knot vector built
+ *     from strictly increasing breakpoints (end breakpoints repeated k times);
+ *     the first and last B-spline are dropped (homogeneous Dirichlet,
+ *     section II.C), so N = (nbreaks - 1) + p - 2.
+ *   - Band convention for host copies: a real symmetric banded matrix M is
+ *     its upper half band, diagonal-major: band[d*N + i] = M[i][i+d] for
+ *     d = 0..p, i = 0..N-1-d (entries with i+d >= N are zero).
+ */
+#ifndef TDSEZ_H
+#define TDSEZ_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum tdsez_status {
+    TDSEZ_OK = 0,
+    TDSEZ_EINVAL = 1,       /* invalid argument (sizes, knots, order, pointers) */
+    TDSEZ_ENOMEM = 2,       /* device or host allocation failed */
+    TDSEZ_EHIP = 3,         /* a HIP runtime call failed (message has the HIP error) */
+    TDSEZ_ENOCONV = 4,      /* an iterative procedure did not converge */
+    TDSEZ_ENONFINITE = 5,   /* a NaN/Inf appeared in a state (latched on device) */
+    TDSEZ_ENORMDRIFT = 6,   /* |nu_n / nu_0 - 1| exceeded the batch tolerance */
+    TDSEZ_EUNSUPPORTED = 7  /* valid but unsupported request (e.g. order > 8) */
+} tdsez_status;
+
+/* Arithmetic of the propagation.
+ *   TDSEZ_FP64: bands, factorisations, solves, state and reductions in FP64.
+ *   TDSEZ_FP32_REFINED: bands stored and the banded factorisation/solve done
+ *     in FP32; each step's solve is refined from the previous state (the
+ *     residual (B_n - A_n) c_n = -i dt H^{n+1/2} c_n is formed in FP64, the
+ *     FP32 solve gives the increment, the state is accumulated in FP64),
+ *     plus `refine` further FP64-residual sweeps (see tdsez_batch_set).
+ *     State, observables and time series stay FP64. */
+typedef enum tdsez_precision { TDSEZ_FP64 = 0, TDSEZ_FP32_REFINED = 1 } tdsez_precision;
+
+/* Observable selection bits.  The output series always has 3 columns per
+ * step, obs[n*3 + 0..2] = (nu_n, d_n, a_n) for n = 0..nsteps; unselected
+ * columns are written as 0.
+ *   nu_n = c_n^H S c_n                         (M-norm, section V.B)
+ *   d_n  = Re c_n^H D c_n                      (dipole, section IV.A)
+ *   a_n  = -Re c_n^H G c_n - E_n Re c_n^H Mi c_n,
+ *          G = <B| m^-1 dV/dx |B>, Mi = <B| m^-1 |B>
+ *                                              (eq. pdm_acceleration, no a_Q)
+ * None of them is divided by nu_n. */
+enum { TDSEZ_OBS_NORM = 1, TDSEZ_OBS_DIPOLE = 2, TDSEZ_OBS_ACCEL = 4 };
+
+/* Band selectors for tdsez_get_band. */
+enum { TDSEZ_BAND_S = 0, TDSEZ_BAND_T = 1, TDSEZ_BAND_V = 2, TDSEZ_BAND_D = 3,
+       TDSEZ_BAND_G = 4, TDSEZ_BAND_MI = 5, TDSEZ_BAND_H0 = 6 };
+
+typedef struct tdsez_system_s* tdsez_system; /* one assembled 1D problem */
+typedef struct tdsez_batch_s* tdsez_batch;   /* propagation plan for several systems */
+
+/* Message for the last non-OK status returned to this thread ("" if none). */
+const char* tdsez_last_error(void);
+
+/* Library ABI version (major*100 + minor). */
+int tdsez_version(void);
+
+/* Gauss-Legendre nodes and weights on [-1, 1] (nq in 1..32), ascending.
+ * The inner products of section II.C are Gauss quadratures per knot span. */
+tdsez_status tdsez_gauss_legendre(int nq, double* x_out, double* w_out);
+
+/* Physical quadrature points at which the caller must sample m^-1(x), V(x)
+ * and V'(x) for tdsez_assemble: x_out[e*nq + q] is the q-th Gauss point of
+ * span [breaks[e], breaks[e+1]], e = 0..nbreaks-2 (host arrays).
+ * EINVAL if nbreaks < 2, nq outside 1..32 or breaks not strictly increasing. */
+tdsez_status tdsez_quad_points(const double* breaks, int nbreaks, int nq, double* x_out);
+
+/* Galerkin assembly on the GPU (section V.A element formulas for the overlap
+ * matrix, the BenDaniel-Duke kinetic matrix, the potential and dipole
+ * matrices; G and Mi for the acceleration).  Inputs are host arrays:
+ * breakpoints (nbreaks, strictly increasing), order k = p + 1 in 2..8,
+ * nq Gauss points per span, and the caller's samples of m^-1, V, V' at the
+ * points of tdsez_quad_points (each (nbreaks-1)*nq doubles; dV_q may be NULL
+ * when the acceleration is not needed, minv_q may be NULL for m = 1).
+ * Creates a system handle that owns FP64 device bands of S, T, V, D, G, Mi.
+ * Runs on the null stream and returns when assembly is complete.
+ * EINVAL on bad sizes/knots/order, EUNSUPPORTED for order > 8, EHIP/ENOMEM
+ * on device failures. */
+tdsez_status tdsez_assemble(const double* breaks, int nbreaks, int order, int nq,
+                            const double* minv_q, const double* V_q, const double* dV_q,
+                            tdsez_system* out);
+
+/* N (unknowns after Dirichlet removal) and half-bandwidth p. */
+tdsez_status tdsez_system_size(tdsez_system sys, int* ndof, int* halfbw);
+
+/* Copy one assembled band to host memory, (p+1)*N doubles in the header's
+ * band convention; `which` is a TDSEZ_BAND_* selector.  Synchronous. */
+tdsez_status tdsez_get_band(tdsez_system sys, int which, double* host_out);
+
+/* Lowest `nev` eigenpairs of the generalised problem H0 c = e S c
+ * (section II.C eq. gen_ev), computed on the GPU in FP64 by shift-and-invert
+ * subspace iteration with Rayleigh-Ritz (section V.C uses shift-and-invert).
+ * sigma must lie below the lowest wanted eigenvalue (H0 - sigma S positive
+ * definite); passing sigma >= 1e300 picks min_q V(x_q) - 1e-3 (|min V| + 1),
+ * which is a valid lower bound for the assembled pencil.  tol: relative
+ * residual |H0 v - e S v| / (|H0 v| + |e| |S v|) of every wanted pair.
+ * Outputs (host): eps_out[nev] ascending; c_out[nev*N], vector j at
+ * c_out + j*N, real, S-normalised, largest-magnitude component positive
+ * (the real, phase-realigned form of section IV.C).
+ * ENOCONV if maxit iterations do not reach tol.  Synchronous. */
+tdsez_status tdsez_ground_state(tdsez_system sys, int nev, double sigma, double tol, int maxit,
+                                double* eps_out, double* c_out);
+
+/* Create a propagation plan for nsys systems (copied handles are borrowed:
+ * the systems must outlive the batch).  Packs every system's bands into the
+ * propagation layout in FP64 and FP32 and sizes the device workspaces.
+ * Synchronous. */
+tdsez_status tdsez_batch_create(const tdsez_system* sys, int nsys, tdsez_batch* out);
+
+/* Tuning knobs of a batch.  key: "refine" (extra FP64-residual refinement
+ * sweeps of the FP32 path, 0..4, default 0), "norm_tol" (latch ENORMDRIFT
+ * when |nu_n/nu_0 - 1| > value; 0 disables, default 0), "chunks" (force the
+ * partition count of every system, 0 = plan, default 0). */
+tdsez_status tdsez_batch_set(tdsez_batch b, const char* key, double value);
+
+/* Crank-Nicolson propagation of every system of the batch in one persistent
+ * kernel launch (one workgroup per system), section V.B eq. cn_system with
+ * H^{n+1/2} = H0 + (E_n + E_{n+1})/2 D.
+ *   psi_packed (device, in/out): complex128 states; system s starts at
+ *       element psi_off[s] (host array of nsys offsets, in complex elements)
+ *       and has N_s elements; on return it holds c_{nsteps_s}.
+ *   E_packed (device): FP64 samples E_0..E_{nsteps_s} of system s at
+ *       E_packed + E_off[s] (host offsets, in doubles).
+ *   dt, nsteps (host arrays, nsys each): time step (> 0) and step count (>= 0).
+ *   obs_packed (device, out): FP64 series, system s at obs_packed + obs_off[s]
+ *       (host offsets, in doubles), (nsteps_s + 1) x 3 as described at
+ *       TDSEZ_OBS_*; may be NULL when obs == 0.
+ * Asynchronous on `stream`.  EINVAL on bad arguments (detected on the host);
+ * device-side failures are latched (tdsez_batch_status). */
+tdsez_status tdsez_propagate_batched(tdsez_batch b, double* psi_packed, const long* psi_off,
+                                     const double* E_packed, const long* E_off,
+                                     const double* dt, const int* nsteps, tdsez_precision prec,
+                                     unsigned obs, double* obs_packed, const long* obs_off,
+                                     void* stream);
+
+/* Single-system convenience form of tdsez_propagate_batched (the library
+ * keeps a one-system plan inside the system handle).  psi: device complex128
+ * [N] in/out; E: device FP64 [nsteps+1]; obs_out: device FP64 [(nsteps+1)*3]
+ * or NULL.  Asynchronous on `stream`. */
+tdsez_status tdsez_propagate(tdsez_system sys, double* psi, const double* E, double dt, int nsteps,
+                             tdsez_precision prec, unsigned obs, double* obs_out, void* stream);
+
+/* Synchronise `stream`, then return and clear the first device-side failure
+ * latched by the batch (TDSEZ_OK if none); sys_out/step_out (may be NULL)
+ * receive the system index and step. */
+tdsez_status tdsez_batch_status(tdsez_batch b, void* stream, int* sys_out, int* step_out);
+
+/* Same for the one-system plan of tdsez_propagate. */
+tdsez_status tdsez_system_status(tdsez_system sys, void* stream, int* step_out);
+
+void tdsez_batch_destroy(tdsez_batch b);
+void tdsez_system_destroy(tdsez_system sys);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TDSEZ_H */

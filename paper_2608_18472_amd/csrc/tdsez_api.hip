@@ -1,0 +1,278 @@
+// C ABI of libtdsez (declared in include/tdsez.h): argument checking, handle
+// management and error reporting around the device code of tdsez_*.hip.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "tdsez_internal.hpp"
+
+namespace tdsez {
+
+static thread_local std::string g_last_error;
+
+void set_error(const char* fmt, ...) {
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+}
+
+tdsez_status fail(tdsez_status st, const char* fmt, ...) {
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+static tdsez_status check_breaks(const double* breaks, int nbreaks) {
+    if (!breaks) return fail(TDSEZ_EINVAL, "breaks is NULL");
+    if (nbreaks < 2) return fail(TDSEZ_EINVAL, "nbreaks=%d < 2", nbreaks);
+    for (int i = 0; i + 1 < nbreaks; ++i)
+        if (!(breaks[i + 1] > breaks[i]) || !std::isfinite(breaks[i]) || !std::isfinite(breaks[i + 1]))
+            return fail(TDSEZ_EINVAL, "breaks must be finite and strictly increasing (index %d)", i);
+    return TDSEZ_OK;
+}
+
+static void free_batch_device(BatchData* b) {
+    (void)hipFree(b->d_band64);
+    (void)hipFree(b->d_band32);
+    (void)hipFree(b->d_state);
+    (void)hipFree(b->d_fac);
+    (void)hipFree(b->d_red);
+    (void)hipFree(b->d_desc);
+    (void)hipFree(b->d_status);
+    b->d_band64 = nullptr;
+    b->d_band32 = nullptr;
+    b->d_state = nullptr;
+    b->d_fac = nullptr;
+    b->d_red = nullptr;
+    b->d_desc = nullptr;
+    b->d_status = nullptr;
+}
+
+}  // namespace tdsez
+
+using namespace tdsez;
+
+struct tdsez_system_s {
+    SystemData d;
+};
+struct tdsez_batch_s {
+    BatchData d;
+};
+
+extern "C" {
+
+const char* tdsez_last_error(void) { return g_last_error.c_str(); }
+
+int tdsez_version(void) { return 100; }
+
+tdsez_status tdsez_gauss_legendre(int nq, double* x_out, double* w_out) {
+    if (!x_out || !w_out) return fail(TDSEZ_EINVAL, "NULL output");
+    if (nq < 1 || nq > 32) return fail(TDSEZ_EINVAL, "nq=%d outside 1..32", nq);
+    gauss_legendre_host(nq, x_out, w_out);
+    return TDSEZ_OK;
+}
+
+tdsez_status tdsez_quad_points(const double* breaks, int nbreaks, int nq, double* x_out) {
+    tdsez_status st = check_breaks(breaks, nbreaks);
+    if (st) return st;
+    if (!x_out) return fail(TDSEZ_EINVAL, "x_out is NULL");
+    if (nq < 1 || nq > 32) return fail(TDSEZ_EINVAL, "nq=%d outside 1..32", nq);
+    double gx[32], gw[32];
+    gauss_legendre_host(nq, gx, gw);
+    for (int e = 0; e + 1 < nbreaks; ++e) {
+        double h = 0.5 * (breaks[e + 1] - breaks[e]), c = 0.5 * (breaks[e + 1] + breaks[e]);
+        for (int q = 0; q < nq; ++q) x_out[(size_t)e * nq + q] = c + h * gx[q];
+    }
+    return TDSEZ_OK;
+}
+
+tdsez_status tdsez_assemble(const double* breaks, int nbreaks, int order, int nq,
+                            const double* minv_q, const double* V_q, const double* dV_q,
+                            tdsez_system* out) {
+    if (!out) return fail(TDSEZ_EINVAL, "out is NULL");
+    *out = nullptr;
+    tdsez_status st = check_breaks(breaks, nbreaks);
+    if (st) return st;
+    if (order < 2) return fail(TDSEZ_EINVAL, "order=%d < 2", order);
+    if (order > kMaxP + 1) return fail(TDSEZ_EUNSUPPORTED, "order=%d > %d", order, kMaxP + 1);
+    if (nq < 1 || nq > 32) return fail(TDSEZ_EINVAL, "nq=%d outside 1..32", nq);
+    int N = (nbreaks - 1) + (order - 1) - 2;
+    if (N < 1) return fail(TDSEZ_EINVAL, "no unknowns left after Dirichlet removal (N=%d)", N);
+    size_t nqt = (size_t)(nbreaks - 1) * nq;
+    const double* arrs[3] = {minv_q, V_q, dV_q};
+    for (int a = 0; a < 3; ++a)
+        if (arrs[a])
+            for (size_t i = 0; i < nqt; ++i)
+                if (!std::isfinite(arrs[a][i]))
+                    return fail(TDSEZ_EINVAL, "non-finite sample %zu in input array %d", i, a);
+    if (minv_q)
+        for (size_t i = 0; i < nqt; ++i)
+            if (!(minv_q[i] > 0.0)) return fail(TDSEZ_EINVAL, "m^-1 must be positive (sample %zu)", i);
+    tdsez_system_s* s = new (std::nothrow) tdsez_system_s();
+    if (!s) return fail(TDSEZ_ENOMEM, "host allocation failed");
+    st = assemble_device(breaks, nbreaks, order, nq, minv_q, V_q, dV_q, &s->d);
+    if (st) {
+        tdsez_system_destroy(s);
+        return st;
+    }
+    *out = s;
+    return TDSEZ_OK;
+}
+
+tdsez_status tdsez_system_size(tdsez_system sys, int* ndof, int* halfbw) {
+    if (!sys) return fail(TDSEZ_EINVAL, "sys is NULL");
+    if (ndof) *ndof = sys->d.N;
+    if (halfbw) *halfbw = sys->d.p;
+    return TDSEZ_OK;
+}
+
+tdsez_status tdsez_get_band(tdsez_system sys, int which, double* host_out) {
+    if (!sys || !host_out) return fail(TDSEZ_EINVAL, "NULL argument");
+    const int N = sys->d.N, p = sys->d.p;
+    const double* src = nullptr;
+    if (which >= TDSEZ_BAND_S && which <= TDSEZ_BAND_MI) src = sys->d.d_band[which];
+    else if (which == TDSEZ_BAND_H0) src = sys->d.d_H0;
+    else return fail(TDSEZ_EINVAL, "unknown band selector %d", which);
+    std::vector<double> rows((size_t)N * (p + 1));
+    TDSEZ_HIP_TRY(hipMemcpy(rows.data(), src, sizeof(double) * rows.size(), hipMemcpyDeviceToHost));
+    // rows[j*(p+1)+d] = M[j][j-d]  ->  band[d*N + i] = M[i][i+d] = M[i+d][i]
+    for (int d = 0; d <= p; ++d)
+        for (int i = 0; i < N; ++i)
+            host_out[(size_t)d * N + i] = (i + d < N) ? rows[(size_t)(i + d) * (p + 1) + d] : 0.0;
+    return TDSEZ_OK;
+}
+
+tdsez_status tdsez_ground_state(tdsez_system sys, int nev, double sigma, double tol, int maxit,
+                                double* eps_out, double* c_out) {
+    if (!sys || !eps_out || !c_out) return fail(TDSEZ_EINVAL, "NULL argument");
+    if (!(tol > 0.0)) return fail(TDSEZ_EINVAL, "tol must be > 0");
+    if (maxit < 1) return fail(TDSEZ_EINVAL, "maxit must be >= 1");
+    return ground_state_device(&sys->d, nev, sigma, tol, maxit, eps_out, c_out);
+}
+
+tdsez_status tdsez_batch_create(const tdsez_system* sys, int nsys, tdsez_batch* out) {
+    if (!out) return fail(TDSEZ_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!sys || nsys < 1) return fail(TDSEZ_EINVAL, "need at least one system");
+    for (int s = 0; s < nsys; ++s)
+        if (!sys[s]) return fail(TDSEZ_EINVAL, "system %d is NULL", s);
+    tdsez_batch_s* b = new (std::nothrow) tdsez_batch_s();
+    if (!b) return fail(TDSEZ_ENOMEM, "host allocation failed");
+    for (int s = 0; s < nsys; ++s) b->d.sys.push_back(&sys[s]->d);
+    tdsez_status st = pack_bands(&b->d);
+    if (st) {
+        tdsez_batch_destroy(b);
+        return st;
+    }
+    *out = b;
+    return TDSEZ_OK;
+}
+
+tdsez_status tdsez_batch_set(tdsez_batch b, const char* key, double value) {
+    if (!b || !key) return fail(TDSEZ_EINVAL, "NULL argument");
+    if (!std::strcmp(key, "refine")) {
+        if (value < 0 || value > 4) return fail(TDSEZ_EINVAL, "refine must be in 0..4");
+        if (value != 0) return fail(TDSEZ_EUNSUPPORTED, "extra refinement sweeps are not built yet");
+        b->d.refine = (int)value;
+        return TDSEZ_OK;
+    }
+    if (!std::strcmp(key, "norm_tol")) {
+        if (!(value >= 0.0)) return fail(TDSEZ_EINVAL, "norm_tol must be >= 0");
+        b->d.norm_tol = value;
+        return TDSEZ_OK;
+    }
+    if (!std::strcmp(key, "chunks")) {
+        if (value < 0 || value > kMaxChunks) return fail(TDSEZ_EINVAL, "chunks must be in 0..%d", kMaxChunks);
+        b->d.force_chunks = (int)value;
+        free_batch_device(&b->d);
+        return pack_bands(&b->d);
+    }
+    return fail(TDSEZ_EINVAL, "unknown key '%s'", key);
+}
+
+tdsez_status tdsez_propagate_batched(tdsez_batch b, double* psi_packed, const long* psi_off,
+                                     const double* E_packed, const long* E_off, const double* dt,
+                                     const int* nsteps, tdsez_precision prec, unsigned obs,
+                                     double* obs_packed, const long* obs_off, void* stream) {
+    if (!b || !psi_packed || !psi_off || !E_packed || !E_off || !dt || !nsteps)
+        return fail(TDSEZ_EINVAL, "NULL argument");
+    if (prec != TDSEZ_FP64 && prec != TDSEZ_FP32_REFINED)
+        return fail(TDSEZ_EINVAL, "unknown precision %d", (int)prec);
+    if (obs & ~7u) return fail(TDSEZ_EINVAL, "unknown observable bits 0x%x", obs);
+    if (obs && (!obs_packed || !obs_off)) return fail(TDSEZ_EINVAL, "obs requested but obs buffer is NULL");
+    BatchData* d = &b->d;
+    const int nsys = (int)d->sys.size();
+    for (int s = 0; s < nsys; ++s) {
+        if (!(dt[s] > 0.0) || !std::isfinite(dt[s])) return fail(TDSEZ_EINVAL, "dt[%d] must be > 0", s);
+        if (nsteps[s] < 0) return fail(TDSEZ_EINVAL, "nsteps[%d] < 0", s);
+        if (psi_off[s] < 0 || E_off[s] < 0 || (obs && obs_off[s] < 0))
+            return fail(TDSEZ_EINVAL, "negative offset for system %d", s);
+        SysDesc& sd = d->desc[s];
+        sd.nsteps = nsteps[s];
+        sd.dt = dt[s];
+        sd.psi_off = psi_off[s];
+        sd.E_off = E_off[s];
+        sd.obs_off = obs ? obs_off[s] : 0;
+    }
+    return launch_propagate(d, psi_packed, E_packed, obs ? obs_packed : nullptr, prec, obs,
+                            (hipStream_t)stream);
+}
+
+tdsez_status tdsez_propagate(tdsez_system sys, double* psi, const double* E, double dt, int nsteps,
+                             tdsez_precision prec, unsigned obs, double* obs_out, void* stream) {
+    if (!sys) return fail(TDSEZ_EINVAL, "sys is NULL");
+    if (!sys->d.solo) {
+        tdsez_system one = sys;
+        tdsez_status st = tdsez_batch_create(&one, 1, &sys->d.solo);
+        if (st) return st;
+    }
+    long zero = 0;
+    return tdsez_propagate_batched(sys->d.solo, psi, &zero, E, &zero, &dt, &nsteps, prec, obs, obs_out,
+                                   &zero, stream);
+}
+
+tdsez_status tdsez_batch_status(tdsez_batch b, void* stream, int* sys_out, int* step_out) {
+    if (!b) return fail(TDSEZ_EINVAL, "b is NULL");
+    TDSEZ_HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+    int h[4] = {0, 0, 0, 0};
+    TDSEZ_HIP_TRY(hipMemcpy(h, b->d.d_status, sizeof(int) * 4, hipMemcpyDeviceToHost));
+    TDSEZ_HIP_TRY(hipMemset(b->d.d_status, 0, sizeof(int) * 4));
+    if (sys_out) *sys_out = h[1];
+    if (step_out) *step_out = h[2];
+    if (h[0] == TDSEZ_ENONFINITE) return fail(TDSEZ_ENONFINITE, "non-finite state in system %d at step %d", h[1], h[2]);
+    if (h[0] == TDSEZ_ENORMDRIFT) return fail(TDSEZ_ENORMDRIFT, "norm drift beyond tolerance in system %d at step %d", h[1], h[2]);
+    if (h[0] != 0) return fail((tdsez_status)h[0], "device error %d in system %d at step %d", h[0], h[1], h[2]);
+    return TDSEZ_OK;
+}
+
+tdsez_status tdsez_system_status(tdsez_system sys, void* stream, int* step_out) {
+    if (!sys) return fail(TDSEZ_EINVAL, "sys is NULL");
+    if (!sys->d.solo) return TDSEZ_OK;
+    return tdsez_batch_status(sys->d.solo, stream, nullptr, step_out);
+}
+
+void tdsez_batch_destroy(tdsez_batch b) {
+    if (!b) return;
+    free_batch_device(&b->d);
+    delete b;
+}
+
+void tdsez_system_destroy(tdsez_system sys) {
+    if (!sys) return;
+    if (sys->d.solo) tdsez_batch_destroy(sys->d.solo);
+    for (int m = 0; m < 6; ++m) (void)hipFree(sys->d.d_band[m]);
+    (void)hipFree(sys->d.d_H0);
+    delete sys;
+}
+
+}  // extern "C"

@@ -1,0 +1,142 @@
+// Internal declarations shared by the HIP translation units of libtdsez.
+// Not part of the public ABI (see include/tdsez.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "tdsez.h"
+
+namespace tdsez {
+
+// Largest supported half-bandwidth (order 8 B-splines).
+constexpr int kMaxP = 7;
+// Lanes of one propagation workgroup (one wave64 per system).
+constexpr int kWave = 64;
+// Largest partition count of one system (one chunk per lane).
+constexpr int kMaxChunks = 64;
+// Matrices stored per band row in the propagation layout: S, H0, D, G, Mi.
+constexpr int kNumMats = 5;
+
+// ---------------------------------------------------------------- errors
+void set_error(const char* fmt, ...);
+tdsez_status fail(tdsez_status st, const char* fmt, ...);
+
+#define TDSEZ_HIP_TRY(expr)                                                                 \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return ::tdsez::fail(TDSEZ_EHIP, "%s failed: %s (%s:%d)", #expr,                \
+                                 hipGetErrorString(e_), __FILE__, __LINE__);                \
+    } while (0)
+
+// ---------------------------------------------------------------- complex
+template <typename T>
+struct cplx {
+    T re, im;
+};
+
+template <typename T>
+__host__ __device__ inline cplx<T> cmk(T r, T i) { return cplx<T>{r, i}; }
+template <typename T>
+__host__ __device__ inline cplx<T> cadd(cplx<T> a, cplx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename T>
+__host__ __device__ inline cplx<T> csub(cplx<T> a, cplx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename T>
+__host__ __device__ inline cplx<T> cmul(cplx<T> a, cplx<T> b) {
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+// a - b*c
+template <typename T>
+__host__ __device__ inline cplx<T> cfms(cplx<T> a, cplx<T> b, cplx<T> c) {
+    return {a.re - b.re * c.re + b.im * c.im, a.im - b.re * c.im - b.im * c.re};
+}
+// a + b*c
+template <typename T>
+__host__ __device__ inline cplx<T> cfma(cplx<T> a, cplx<T> b, cplx<T> c) {
+    return {a.re + b.re * c.re - b.im * c.im, a.im + b.re * c.im + b.im * c.re};
+}
+template <typename T>
+__host__ __device__ inline cplx<T> cinv(cplx<T> a) {
+    T s = T(1) / (a.re * a.re + a.im * a.im);
+    return {a.re * s, -a.im * s};
+}
+template <typename T>
+__host__ __device__ inline cplx<T> cscale(cplx<T> a, T s) { return {a.re * s, a.im * s}; }
+
+// ---------------------------------------------------------------- handles
+// Assembled 1D system.  Device bands are FP64, lower half band by rows:
+// band[m][j*(p+1) + d] = M[j][j-d] (0 when j-d < 0).
+struct SystemData {
+    int N = 0, p = 0, order = 0, nq = 0, nbreaks = 0;
+    bool const_mass = true;
+    std::vector<double> breaks;
+    double minV = 0.0;               // min_q V(x_q), for the default eigen shift
+    double* d_band[6] = {nullptr};   // S, T, V, D, G, Mi
+    double* d_H0 = nullptr;          // T + V
+    tdsez_batch solo = nullptr;      // one-system plan for tdsez_propagate
+};
+
+// Per-system plan of the partitioned solve.
+struct Plan {
+    int N, p, P, L, m;   // rows, half-bandwidth, chunks, rows per chunk, interior rows
+    int LS;              // interleave stride (P + 2: chunk k lives in column k + 1)
+};
+
+// Device descriptor of one system of a batch (read by the propagation kernel).
+struct SysDesc {
+    int N, p, P, L, m, LS;
+    int nsteps;
+    int pad_;
+    double dt;
+    long long band_off;   // elements into the FP64/FP32 packed band buffers
+    long long state_off;  // complex elements into the interleaved state buffer
+    long long fac_off;    // complex elements into the factor workspace
+    long long red_off;    // complex elements into the reduced-system workspace
+    long long psi_off;    // complex elements into the caller's psi buffer
+    long long E_off;      // doubles into the caller's E buffer
+    long long obs_off;    // doubles into the caller's obs buffer
+};
+
+struct BatchData {
+    std::vector<SystemData*> sys;
+    std::vector<Plan> plan;
+    std::vector<SysDesc> desc;       // host copy, offsets of the internal buffers
+    int maxp = 0;
+    int refine = 0;
+    double norm_tol = 0.0;
+    int force_chunks = 0;
+    long long band_elems = 0, state_elems = 0, fac_elems64 = 0, red_elems64 = 0;
+    double* d_band64 = nullptr;
+    float* d_band32 = nullptr;
+    double* d_state = nullptr;       // interleaved complex128 states
+    void* d_fac = nullptr;           // factor workspace (sized for FP64)
+    void* d_red = nullptr;           // reduced-system workspace (sized for FP64)
+    SysDesc* d_desc = nullptr;
+    int* d_status = nullptr;         // [0] code, [1] system, [2] step
+    int nsys_alloc_desc = 0;
+};
+
+// ---------------------------------------------------------------- kernels
+// Assembly (tdsez_assemble.hip)
+tdsez_status assemble_device(const double* breaks, int nbreaks, int order, int nq,
+                             const double* minv_q, const double* V_q, const double* dV_q,
+                             SystemData* sys);
+// Host Gauss-Legendre (tdsez_assemble.hip)
+int gauss_legendre_host(int nq, double* x, double* w);
+
+// Propagation (tdsez_propagate.hip)
+Plan make_plan(int N, int p, int force_chunks);
+tdsez_status pack_bands(BatchData* b);
+tdsez_status launch_propagate(BatchData* b, double* psi, const double* E, double* obs,
+                              tdsez_precision prec, unsigned obs_mask, hipStream_t stream);
+
+// Eigen (tdsez_eigen.hip)
+tdsez_status ground_state_device(SystemData* sys, int nev, double sigma, double tol, int maxit,
+                                 double* eps_out, double* c_out);
+
+}  // namespace tdsez

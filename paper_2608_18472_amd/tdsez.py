@@ -1,0 +1,257 @@
+"""Python binding of libtdsez (include/tdsez.h): argument marshalling only.
+
+Every numerical step runs in the HIP library; PyTorch provides device memory
+and streams.  The binding raises TdsezError when the library is missing or a
+call fails -- there is no CPU fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtdsez.so")
+
+TDSEZ_OK = 0
+STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EHIP", 4: "ENOCONV", 5: "ENONFINITE",
+                6: "ENORMDRIFT", 7: "EUNSUPPORTED"}
+FP64 = 0
+FP32_REFINED = 1
+OBS_NORM, OBS_DIPOLE, OBS_ACCEL = 1, 2, 4
+OBS_ALL = 7
+BAND = {"S": 0, "T": 1, "V": 2, "D": 3, "G": 4, "Mi": 5, "H0": 6}
+
+
+class TdsezError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__("tdsez %s: %s" % (STATUS_NAMES.get(status, status), message))
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """Load libtdsez.so (built in-tree by __graft_entry__.build())."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise TdsezError(-1, "libtdsez.so not found at %s; build it with __graft_entry__.build()" % LIB_PATH)
+    L = ctypes.CDLL(LIB_PATH)
+    vp, dp, ip, lp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int), \
+        ctypes.POINTER(ctypes.c_long)
+    i, d, u = ctypes.c_int, ctypes.c_double, ctypes.c_uint
+    L.tdsez_last_error.restype = ctypes.c_char_p
+    L.tdsez_version.restype = i
+    sigs = {
+        "tdsez_gauss_legendre": [i, dp, dp],
+        "tdsez_quad_points": [dp, i, i, dp],
+        "tdsez_assemble": [dp, i, i, i, dp, dp, dp, ctypes.POINTER(vp)],
+        "tdsez_system_size": [vp, ip, ip],
+        "tdsez_get_band": [vp, i, dp],
+        "tdsez_ground_state": [vp, i, d, d, i, dp, dp],
+        "tdsez_batch_create": [ctypes.POINTER(vp), i, ctypes.POINTER(vp)],
+        "tdsez_batch_set": [vp, ctypes.c_char_p, d],
+        "tdsez_propagate_batched": [vp, vp, lp, vp, lp, dp, ip, i, u, vp, lp, vp],
+        "tdsez_propagate": [vp, vp, vp, d, i, i, u, vp, vp],
+        "tdsez_batch_status": [vp, vp, ip, ip],
+        "tdsez_system_status": [vp, vp, ip],
+    }
+    for name, args in sigs.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = i
+    L.tdsez_batch_destroy.argtypes = [vp]
+    L.tdsez_batch_destroy.restype = None
+    L.tdsez_system_destroy.argtypes = [vp]
+    L.tdsez_system_destroy.restype = None
+    _lib = L
+    return L
+
+
+def _check(st):
+    if st != TDSEZ_OK:
+        raise TdsezError(st, lib().tdsez_last_error().decode())
+
+
+def _dptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _stream_handle(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    if hasattr(stream, "cuda_stream"):
+        return ctypes.c_void_p(stream.cuda_stream)
+    return ctypes.c_void_p(stream)
+
+
+def version():
+    return lib().tdsez_version()
+
+
+def gauss_legendre(nq):
+    x = np.zeros(nq)
+    w = np.zeros(nq)
+    _check(lib().tdsez_gauss_legendre(nq, _dptr(x), _dptr(w)))
+    return x, w
+
+
+def quad_points(breaks, nq):
+    br = _f64(breaks)
+    x = np.zeros((len(br) - 1) * nq)
+    _check(lib().tdsez_quad_points(_dptr(br), len(br), nq, _dptr(x)))
+    return x
+
+
+class System:
+    """An assembled 1D problem (owns FP64 device bands)."""
+
+    def __init__(self, handle):
+        self.handle = handle
+        N = ctypes.c_int()
+        p = ctypes.c_int()
+        _check(lib().tdsez_system_size(handle, ctypes.byref(N), ctypes.byref(p)))
+        self.N, self.p = N.value, p.value
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.tdsez_system_destroy(self.handle)
+            self.handle = None
+
+
+def assemble(breaks, order, nq, minv_q=None, V_q=None, dV_q=None):
+    br = _f64(breaks)
+    arrs = [None if a is None else _f64(a) for a in (minv_q, V_q, dV_q)]
+    h = ctypes.c_void_p()
+    _check(lib().tdsez_assemble(_dptr(br), len(br), order, nq,
+                                *[None if a is None else _dptr(a) for a in arrs], ctypes.byref(h)))
+    return System(h)
+
+
+def assemble_workload(sysdef):
+    """Assemble a workloads.System: sample its m^-1, V, V' at the library's
+    own quadrature points."""
+    xq = quad_points(sysdef.breaks, sysdef.nq)
+    minv, V, dV = sysdef.sample(xq)
+    return assemble(sysdef.breaks, sysdef.order, sysdef.nq, None if sysdef.const_mass else minv, V, dV)
+
+
+def system_size(sys):
+    return sys.N, sys.p
+
+
+def get_band(sys, which):
+    out = np.zeros((sys.p + 1) * sys.N)
+    _check(lib().tdsez_get_band(sys.handle, BAND[which] if isinstance(which, str) else which, _dptr(out)))
+    return out.reshape(sys.p + 1, sys.N)
+
+
+def ground_state(sys, nev=1, sigma=None, tol=1e-13, maxit=5000):
+    eps = np.zeros(nev)
+    vec = np.zeros(nev * sys.N)
+    _check(lib().tdsez_ground_state(sys.handle, nev, 1e301 if sigma is None else float(sigma), tol, maxit,
+                                    _dptr(eps), _dptr(vec)))
+    return eps, vec.reshape(nev, sys.N)
+
+
+class Batch:
+    def __init__(self, handle, systems):
+        self.handle = handle
+        self.systems = list(systems)  # keep the systems alive
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.tdsez_batch_destroy(self.handle)
+            self.handle = None
+
+
+def batch_create(systems):
+    arr = (ctypes.c_void_p * len(systems))(*[s.handle for s in systems])
+    h = ctypes.c_void_p()
+    _check(lib().tdsez_batch_create(arr, len(systems), ctypes.byref(h)))
+    return Batch(h, systems)
+
+
+def batch_set(batch, key, value):
+    _check(lib().tdsez_batch_set(batch.handle, key.encode(), float(value)))
+
+
+def _longs(a):
+    a = np.ascontiguousarray(a, dtype=np.int64)
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_long))
+
+
+def _check_dev(t, dtype):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dtype and t.is_contiguous()):
+        raise TdsezError(1, "expected a contiguous CUDA tensor of dtype %s" % dtype)
+
+
+def propagate_batched(batch, psi_packed, psi_off, E_packed, E_off, dt, nsteps, prec=FP64, obs=OBS_ALL,
+                      obs_packed=None, obs_off=None, stream=None):
+    """psi_packed: torch complex128 (device, in/out); E_packed: torch float64
+    (device); obs_packed: torch float64 (device) or None.  Offsets, dt and
+    nsteps are host sequences."""
+    import torch
+    _check_dev(psi_packed, torch.complex128)
+    _check_dev(E_packed, torch.float64)
+    n = len(batch.systems)
+    po, pp = _longs(psi_off)
+    eo, ep = _longs(E_off)
+    dtv = _f64(dt)
+    ns = np.ascontiguousarray(nsteps, dtype=np.int32)
+    if len(po) != n or len(eo) != n or len(dtv) != n or len(ns) != n:
+        raise TdsezError(1, "per-system arrays must have one entry per system")
+    if obs:
+        _check_dev(obs_packed, torch.float64)
+        oo, op_ = _longs(obs_off)
+        optr = ctypes.c_void_p(obs_packed.data_ptr())
+    else:
+        oo, op_ = _longs(np.zeros(n))
+        optr = None
+    _check(lib().tdsez_propagate_batched(batch.handle, ctypes.c_void_p(psi_packed.data_ptr()), pp,
+                                         ctypes.c_void_p(E_packed.data_ptr()), ep, _dptr(dtv),
+                                         ns.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), int(prec), int(obs),
+                                         optr, op_, _stream_handle(stream)))
+
+
+def propagate(sys, psi, E, dt, nsteps, prec=FP64, obs=OBS_ALL, obs_out=None, stream=None):
+    import torch
+    _check_dev(psi, torch.complex128)
+    _check_dev(E, torch.float64)
+    if obs:
+        _check_dev(obs_out, torch.float64)
+    _check(lib().tdsez_propagate(sys.handle, ctypes.c_void_p(psi.data_ptr()), ctypes.c_void_p(E.data_ptr()),
+                                 float(dt), int(nsteps), int(prec), int(obs),
+                                 ctypes.c_void_p(obs_out.data_ptr()) if obs else None, _stream_handle(stream)))
+
+
+def batch_status(batch, stream=None):
+    s = ctypes.c_int()
+    n = ctypes.c_int()
+    _check(lib().tdsez_batch_status(batch.handle, _stream_handle(stream), ctypes.byref(s), ctypes.byref(n)))
+
+
+def system_status(sys, stream=None):
+    n = ctypes.c_int()
+    _check(lib().tdsez_system_status(sys.handle, _stream_handle(stream), ctypes.byref(n)))
+
+
+def pack_batch_inputs(systems_defs, psi0_list, device="cuda"):
+    """Pack per-system initial states and pulse samples into the flat device
+    buffers of propagate_batched; returns (psi, psi_off, E, E_off, obs, obs_off)."""
+    import torch
+    psi_off = np.cumsum([0] + [len(p) for p in psi0_list[:-1]]).astype(np.int64)
+    E_off = np.cumsum([0] + [s.nsteps + 1 for s in systems_defs[:-1]]).astype(np.int64)
+    obs_off = 3 * E_off
+    psi = torch.from_numpy(np.concatenate(psi0_list).astype(np.complex128)).to(device)
+    E = torch.from_numpy(np.concatenate([s.E[: s.nsteps + 1] for s in systems_defs]).astype(np.float64)).to(device)
+    obs = torch.zeros(3 * int(E.numel()), dtype=torch.float64, device=device)
+    return psi, psi_off, E, E_off, obs, obs_off
