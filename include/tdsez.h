@@ -135,6 +135,20 @@ tdsez_status tdsez_get_band(tdsez_system sys, int which, double* host_out);
 tdsez_status tdsez_ground_state(tdsez_system sys, int nev, double sigma, double tol, int maxit,
                                 double* eps_out, double* c_out);
 
+/* Ground states of every system of a batch in one launch (one workgroup per
+ * system, FP64): the lowest eigenpair of H0 c = e S c (section II.C eq.
+ * gen_ev) by shift-and-invert power iteration with K = H0 - sigma S
+ * factorised once per system.  sigma as in tdsez_ground_state (>= 1e300
+ * picks each system's own min_q V(x_q) - 1e-3 (|min V| + 1)).  Writes
+ * eps_out[s] (host) and the real, S-normalised ground state of system s
+ * (largest-magnitude component positive, imaginary parts 0) into the
+ * device complex128 buffer psi_packed at element psi_off[s] (host offsets).
+ * EINVAL if K is not positive definite, ENOCONV if some system misses tol
+ * (relative residual as in tdsez_ground_state) after maxit iterations.
+ * Synchronous. */
+tdsez_status tdsez_ground_state_batched(tdsez_batch b, double sigma, double tol, int maxit,
+                                        double* eps_out, double* psi_packed, const long* psi_off);
+
 /* Create a propagation plan for nsys systems (copied handles are borrowed:
  * the systems must outlive the batch).  Packs every system's bands into the
  * propagation layout in FP64 and FP32 and sizes the device workspaces.
@@ -144,7 +158,8 @@ tdsez_status tdsez_batch_create(const tdsez_system* sys, int nsys, tdsez_batch* 
 /* Tuning knobs of a batch.  key: "refine" (extra FP64-residual refinement
  * sweeps of the FP32 path, 0..4, default 0), "norm_tol" (latch ENORMDRIFT
  * when |nu_n/nu_0 - 1| > value; 0 disables, default 0), "chunks" (force the
- * partition count of every system, 0 = plan, default 0). */
+ * partition count of every system, 0 = plan, default 0), "profile" (1 turns
+ * on per-phase cycle counters read by tdsez_batch_profile, 0 off). */
 tdsez_status tdsez_batch_set(tdsez_batch b, const char* key, double value);
 
 /* Crank-Nicolson propagation of every system of the batch in one persistent
@@ -173,6 +188,14 @@ tdsez_status tdsez_propagate_batched(tdsez_batch b, double* psi_packed, const lo
  * or NULL.  Asynchronous on `stream`. */
 tdsez_status tdsez_propagate(tdsez_system sys, double* psi, const double* E, double dt, int nsteps,
                              tdsez_precision prec, unsigned obs, double* obs_out, void* stream);
+
+/* Phase profile of the last propagation of a profiled batch (see
+ * tdsez_batch_set "profile").  Synchronises `stream`; out[4*s + 0..3] =
+ * average shader-clock cycles per time step spent by system s in the
+ * factorisation sweep, the separator (reduced) solve and the back-
+ * substitution sweeps, and the partition count used for it.  EINVAL when
+ * profiling is off. */
+tdsez_status tdsez_batch_profile(tdsez_batch b, void* stream, double* out);
 
 /* Synchronise `stream`, then return and clear the first device-side failure
  * latched by the batch (TDSEZ_OK if none); sys_out/step_out (may be NULL)

@@ -49,6 +49,8 @@ static void free_batch_device(BatchData* b) {
     (void)hipFree(b->d_red);
     (void)hipFree(b->d_desc);
     (void)hipFree(b->d_status);
+    (void)hipFree(b->d_prof);
+    b->d_prof = nullptr;
     b->d_band64 = nullptr;
     b->d_band32 = nullptr;
     b->d_state = nullptr;
@@ -160,6 +162,16 @@ tdsez_status tdsez_ground_state(tdsez_system sys, int nev, double sigma, double 
     return ground_state_device(&sys->d, nev, sigma, tol, maxit, eps_out, c_out);
 }
 
+tdsez_status tdsez_ground_state_batched(tdsez_batch b, double sigma, double tol, int maxit, double* eps_out,
+                                       double* psi_packed, const long* psi_off) {
+    if (!b || !eps_out || !psi_packed || !psi_off) return fail(TDSEZ_EINVAL, "NULL argument");
+    if (!(tol > 0.0)) return fail(TDSEZ_EINVAL, "tol must be > 0");
+    if (maxit < 1) return fail(TDSEZ_EINVAL, "maxit must be >= 1");
+    for (size_t s = 0; s < b->d.sys.size(); ++s)
+        if (psi_off[s] < 0) return fail(TDSEZ_EINVAL, "negative psi offset for system %zu", s);
+    return ground_state_batched_device(&b->d, sigma, tol, maxit, eps_out, psi_packed, psi_off);
+}
+
 tdsez_status tdsez_batch_create(const tdsez_system* sys, int nsys, tdsez_batch* out) {
     if (!out) return fail(TDSEZ_EINVAL, "out is NULL");
     *out = nullptr;
@@ -191,11 +203,25 @@ tdsez_status tdsez_batch_set(tdsez_batch b, const char* key, double value) {
         b->d.norm_tol = value;
         return TDSEZ_OK;
     }
+    if (!std::strcmp(key, "profile")) {
+        if (value != 0.0 && !b->d.d_prof) {
+            size_t bytes = sizeof(unsigned long long) * 4 * b->d.sys.size();
+            TDSEZ_HIP_TRY(hipMalloc(&b->d.d_prof, bytes));
+            TDSEZ_HIP_TRY(hipMemset(b->d.d_prof, 0, bytes));
+        } else if (value == 0.0 && b->d.d_prof) {
+            (void)hipFree(b->d.d_prof);
+            b->d.d_prof = nullptr;
+        }
+        return TDSEZ_OK;
+    }
     if (!std::strcmp(key, "chunks")) {
+        bool prof = b->d.d_prof != nullptr;
         if (value < 0 || value > kMaxChunks) return fail(TDSEZ_EINVAL, "chunks must be in 0..%d", kMaxChunks);
         b->d.force_chunks = (int)value;
         free_batch_device(&b->d);
-        return pack_bands(&b->d);
+        tdsez_status st = pack_bands(&b->d);
+        if (st == TDSEZ_OK && prof) return tdsez_batch_set(b, "profile", 1.0);
+        return st;
     }
     return fail(TDSEZ_EINVAL, "unknown key '%s'", key);
 }
@@ -239,6 +265,21 @@ tdsez_status tdsez_propagate(tdsez_system sys, double* psi, const double* E, dou
     long zero = 0;
     return tdsez_propagate_batched(sys->d.solo, psi, &zero, E, &zero, &dt, &nsteps, prec, obs, obs_out,
                                    &zero, stream);
+}
+
+tdsez_status tdsez_batch_profile(tdsez_batch b, void* stream, double* out) {
+    if (!b || !out) return fail(TDSEZ_EINVAL, "NULL argument");
+    if (!b->d.d_prof) return fail(TDSEZ_EINVAL, "profiling is off (tdsez_batch_set(b, \"profile\", 1))");
+    TDSEZ_HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+    const size_t n = b->d.sys.size();
+    std::vector<unsigned long long> h(4 * n);
+    TDSEZ_HIP_TRY(hipMemcpy(h.data(), b->d.d_prof, sizeof(unsigned long long) * 4 * n, hipMemcpyDeviceToHost));
+    for (size_t s = 0; s < n; ++s) {
+        double ns = h[4 * s + 3] > 0 ? (double)h[4 * s + 3] : 1.0;
+        for (int k = 0; k < 3; ++k) out[4 * s + k] = (double)h[4 * s + k] / ns;
+        out[4 * s + 3] = (double)b->d.plan[s].P;
+    }
+    return TDSEZ_OK;
 }
 
 tdsez_status tdsez_batch_status(tdsez_batch b, void* stream, int* sys_out, int* step_out) {

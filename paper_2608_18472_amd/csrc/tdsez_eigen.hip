@@ -339,3 +339,201 @@ tdsez_status ground_state_device(SystemData* sys, int nev, double sigma, double 
 }
 
 }  // namespace tdsez
+
+// ----------------------------------------------------------------------------
+// Batched ground states: one workgroup per system, all systems in one launch.
+// Shift-and-invert power iteration on the lowest eigenpair of H0 c = e S c:
+//   K = H0 - sigma S = L D L^T (banded, factorised by one lane, FP64);
+//   repeat  z = K^-1 S x;  x = z / sqrt(z^T S z);  e = x^T H0 x
+//   until |H0 x - e S x| / (|H0 x| + |e| |S x|) < tol (checked every 4 steps).
+// The matrix-vector products and reductions use the whole workgroup; the
+// banded triangular solves are serial in one lane (the systems run in
+// parallel across workgroups).
+namespace tdsez {
+namespace {
+
+struct GsDesc {
+    const double* S;
+    const double* H0;
+    double* work;      // (p+1)*N factor + 3*N vectors
+    long long psi_off; // complex elements into the packed state buffer
+    int N, p;
+    double sigma;
+};
+
+__device__ double block_sum(double v, double* red) {
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    __syncthreads();
+    if (l == 0) red[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += red[i];
+    return s;
+}
+
+__device__ void band_mv(const double* __restrict__ M, int N, int p, const double* __restrict__ x,
+                        double* __restrict__ y) {
+    for (int i = threadIdx.x; i < N; i += blockDim.x) {
+        double s = M[(long long)i * (p + 1)] * x[i];
+        for (int d = 1; d <= p; ++d) {
+            if (i - d >= 0) s += M[(long long)i * (p + 1) + d] * x[i - d];
+            if (i + d < N) s += M[(long long)(i + d) * (p + 1) + d] * x[i + d];
+        }
+        y[i] = s;
+    }
+}
+
+__global__ __launch_bounds__(256) void ground_batched_kernel(const GsDesc* __restrict__ descs, double tol,
+                                                             int maxit, double* __restrict__ psi,
+                                                             double* __restrict__ eps_out,
+                                                             int* __restrict__ status) {
+    const GsDesc g = descs[blockIdx.x];
+    const int N = g.N, p = g.p;
+    double* Kf = g.work;
+    double* x = Kf + (long long)N * (p + 1);
+    double* y = x + N;
+    double* z = y + N;
+    __shared__ double red[4];
+    __shared__ int bad;
+    if (threadIdx.x == 0) bad = 0;
+    for (long long e = threadIdx.x; e < (long long)N * (p + 1); e += blockDim.x)
+        Kf[e] = g.H0[e] - g.sigma * g.S[e];
+    for (int i = threadIdx.x; i < N; i += blockDim.x) {
+        double t = (i + 1.0) / (N + 1.0);
+        x[i] = t * (1.0 - t);  // positive, smooth start (not orthogonal to the ground state)
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int j = 0; j < N && !bad; ++j) {
+            double dj = Kf[(long long)j * (p + 1)];
+            if (!(dj > 0.0)) { bad = 1; break; }
+            for (int i = j + 1; i <= j + p && i < N; ++i) {
+                double lij = Kf[(long long)i * (p + 1) + (i - j)] / dj;
+                for (int i2 = j + 1; i2 <= i; ++i2)
+                    Kf[(long long)i * (p + 1) + (i - i2)] -= lij * Kf[(long long)i2 * (p + 1) + (i2 - j)];
+            }
+            for (int i = j + 1; i <= j + p && i < N; ++i) Kf[(long long)i * (p + 1) + (i - j)] /= dj;
+        }
+    }
+    __syncthreads();
+    if (bad) {
+        if (threadIdx.x == 0) status[blockIdx.x] = 1;
+        return;
+    }
+    double e = 0.0;
+    int it = 0, converged = 0;
+    for (; it < maxit && !converged; ++it) {
+        band_mv(g.S, N, p, x, y);
+        __syncthreads();
+        if (threadIdx.x == 0) {  // z = K^-1 y
+            for (int i = 0; i < N; ++i) {
+                double s = y[i];
+                for (int d = 1; d <= p && i - d >= 0; ++d) s -= Kf[(long long)i * (p + 1) + d] * z[i - d];
+                z[i] = s;
+            }
+            for (int i = 0; i < N; ++i) z[i] /= Kf[(long long)i * (p + 1)];
+            for (int i = N - 1; i >= 0; --i) {
+                double s = z[i];
+                for (int d = 1; d <= p && i + d < N; ++d) s -= Kf[(long long)(i + d) * (p + 1) + d] * z[i + d];
+                z[i] = s;
+            }
+        }
+        __syncthreads();
+        band_mv(g.S, N, p, z, y);
+        __syncthreads();
+        double nz = 0.0;
+        for (int i = threadIdx.x; i < N; i += blockDim.x) nz += z[i] * y[i];
+        nz = block_sum(nz, red);
+        const double sc = 1.0 / sqrt(nz);
+        for (int i = threadIdx.x; i < N; i += blockDim.x) x[i] = z[i] * sc;
+        __syncthreads();
+        if ((it & 3) == 3 || it == maxit - 1) {
+            band_mv(g.H0, N, p, x, y);  // y = H0 x
+            band_mv(g.S, N, p, x, z);   // z = S x
+            __syncthreads();
+            double ev = 0.0;
+            for (int i = threadIdx.x; i < N; i += blockDim.x) ev += x[i] * y[i];
+            ev = block_sum(ev, red);
+            double r2 = 0.0, h2 = 0.0, s2 = 0.0;
+            for (int i = threadIdx.x; i < N; i += blockDim.x) {
+                double r = y[i] - ev * z[i];
+                r2 += r * r;
+                h2 += y[i] * y[i];
+                s2 += z[i] * z[i];
+            }
+            r2 = block_sum(r2, red);
+            h2 = block_sum(h2, red);
+            s2 = block_sum(s2, red);
+            e = ev;
+            if (sqrt(r2) < tol * (sqrt(h2) + fabs(ev) * sqrt(s2))) converged = 1;
+            __syncthreads();
+        }
+    }
+    // sign convention: largest-magnitude component positive (lowest index on ties)
+    double best = 0.0;
+    int bi = 0;
+    if (threadIdx.x == 0) {
+        for (int i = 0; i < N; ++i)
+            if (fabs(x[i]) > best) { best = fabs(x[i]); bi = i; }
+        red[0] = x[bi] < 0.0 ? -1.0 : 1.0;
+        eps_out[blockIdx.x] = e;
+        status[blockIdx.x] = converged ? 0 : 2;
+    }
+    __syncthreads();
+    const double sg = red[0];
+    for (int i = threadIdx.x; i < N; i += blockDim.x) {
+        psi[2 * (g.psi_off + i)] = sg * x[i];
+        psi[2 * (g.psi_off + i) + 1] = 0.0;
+    }
+}
+
+}  // namespace
+
+tdsez_status ground_state_batched_device(BatchData* b, double sigma, double tol, int maxit, double* eps_out,
+                                         double* psi, const long* psi_off) {
+    const int nsys = (int)b->sys.size();
+    std::vector<GsDesc> hd(nsys);
+    long long wtot = 0;
+    for (int s = 0; s < nsys; ++s) wtot += (long long)b->sys[s]->N * (b->sys[s]->p + 4);
+    double* work = nullptr;
+    GsDesc* dd = nullptr;
+    double* dev_eps = nullptr;
+    int* dstat = nullptr;
+    auto cleanup = [&]() { (void)hipFree(work); (void)hipFree(dd); (void)hipFree(dev_eps); (void)hipFree(dstat); };
+#define GB_TRY(expr)                                                                    \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess) {                                                         \
+            cleanup();                                                                  \
+            return fail(TDSEZ_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_));    \
+        }                                                                               \
+    } while (0)
+    GB_TRY(hipMalloc(&work, sizeof(double) * (size_t)wtot));
+    long long woff = 0;
+    for (int s = 0; s < nsys; ++s) {
+        SystemData* sy = b->sys[s];
+        double sg = sigma >= 1e300 ? sy->minV - 1e-3 * (std::fabs(sy->minV) + 1.0) : sigma;
+        hd[s] = GsDesc{sy->d_band[0], sy->d_H0, work + woff, (long long)psi_off[s], sy->N, sy->p, sg};
+        woff += (long long)sy->N * (sy->p + 4);
+    }
+    GB_TRY(hipMalloc(&dd, sizeof(GsDesc) * nsys));
+    GB_TRY(hipMalloc(&dev_eps, sizeof(double) * nsys));
+    GB_TRY(hipMalloc(&dstat, sizeof(int) * nsys));
+    GB_TRY(hipMemcpy(dd, hd.data(), sizeof(GsDesc) * nsys, hipMemcpyHostToDevice));
+    ground_batched_kernel<<<nsys, 256>>>(dd, tol, maxit, psi, dev_eps, dstat);
+    GB_TRY(hipGetLastError());
+    std::vector<int> hs(nsys);
+    GB_TRY(hipMemcpy(eps_out, dev_eps, sizeof(double) * nsys, hipMemcpyDeviceToHost));
+    GB_TRY(hipMemcpy(hs.data(), dstat, sizeof(int) * nsys, hipMemcpyDeviceToHost));
+#undef GB_TRY
+    cleanup();
+    for (int s = 0; s < nsys; ++s) {
+        if (hs[s] == 1)
+            return fail(TDSEZ_EINVAL, "system %d: H0 - sigma S not positive definite (choose sigma below the spectrum)", s);
+        if (hs[s] == 2) return fail(TDSEZ_ENOCONV, "system %d: no convergence to tol=%g in %d iterations", s, tol, maxit);
+    }
+    return TDSEZ_OK;
+}
+
+}  // namespace tdsez

@@ -118,6 +118,7 @@ struct BatchData {
     void* d_red = nullptr;           // reduced-system workspace (sized for FP64)
     SysDesc* d_desc = nullptr;
     int* d_status = nullptr;         // [0] code, [1] system, [2] step
+    unsigned long long* d_prof = nullptr;  // optional phase cycle counters, 4 per system
     int nsys_alloc_desc = 0;
 };
 
@@ -138,5 +139,7 @@ tdsez_status launch_propagate(BatchData* b, double* psi, const double* E, double
 // Eigen (tdsez_eigen.hip)
 tdsez_status ground_state_device(SystemData* sys, int nev, double sigma, double tol, int maxit,
                                  double* eps_out, double* c_out);
+tdsez_status ground_state_batched_device(BatchData* b, double sigma, double tol, int maxit, double* eps_out,
+                                         double* psi, const long* psi_off);
 
 }  // namespace tdsez

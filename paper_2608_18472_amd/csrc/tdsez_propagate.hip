@@ -511,7 +511,10 @@ template <int PP, typename FT>
 __device__ void run_system(const SysDesc& sd, int sidx, const FT* __restrict__ band,
                            double* __restrict__ st, FT* __restrict__ fac, FT* __restrict__ red,
                            const double* __restrict__ E, double* __restrict__ obs, unsigned mask,
-                           double norm_tol, int* status) {
+                           double norm_tol, int* status, unsigned long long* __restrict__ prof) {
+    // optional phase profile: shader-clock cycles spent in the factor sweep,
+    // the reduced solve and the back-substitution sweeps, summed over steps
+    unsigned long long t_fac = 0, t_red = 0, t_back = 0, t0 = 0;
     const int lane = threadIdx.x;
     const bool active = lane < sd.P;
     const double alpha = 0.5 * sd.dt;
@@ -524,6 +527,7 @@ __device__ void run_system(const SysDesc& sd, int sidx, const FT* __restrict__ b
         const double En = Es[n];
         const double Ebar = last ? En : 0.5 * (En + Es[n + 1]);
         double part[3] = {0.0, 0.0, 0.0};
+        if (prof) t0 = clock64();
         if (active)
             pass_factor<PP, FT>(sd, lane, band, st, fac, red, alpha, Ebar, En, want_acc, !last, part);
         double nu = wave_sum(part[0]);
@@ -545,10 +549,19 @@ __device__ void run_system(const SysDesc& sd, int sidx, const FT* __restrict__ b
         }
         if (last) break;
         __syncthreads();
+        if (prof) { unsigned long long t = clock64(); t_fac += t - t0; t0 = t; }
         pass_reduced<FT>(sd, lane, red);
         __syncthreads();
+        if (prof) { unsigned long long t = clock64(); t_red += t - t0; t0 = t; }
         if (active) pass_backsub<PP, FT>(sd, lane, band, st, fac, red, alpha, Ebar);
         __syncthreads();
+        if (prof) { unsigned long long t = clock64(); t_back += t - t0; }
+    }
+    if (prof && lane == 0) {
+        prof[4 * sidx + 0] = t_fac;
+        prof[4 * sidx + 1] = t_red;
+        prof[4 * sidx + 2] = t_back;
+        prof[4 * sidx + 3] = (unsigned long long)sd.nsteps;
     }
 }
 
@@ -560,17 +573,18 @@ __global__ __launch_bounds__(kWave) void propagate_kernel(const SysDesc* __restr
                                                           FT* __restrict__ red,
                                                           const double* __restrict__ E,
                                                           double* __restrict__ obs, unsigned mask,
-                                                          double norm_tol, int* status) {
+                                                          double norm_tol, int* status,
+                                                          unsigned long long* __restrict__ prof) {
     const int sidx = blockIdx.x;
     const SysDesc sd = descs[sidx];
     switch (sd.p) {
-        case 1: run_system<1, FT>(sd, sidx, band, st, fac, red, E, obs, mask, norm_tol, status); break;
-        case 2: run_system<2, FT>(sd, sidx, band, st, fac, red, E, obs, mask, norm_tol, status); break;
-        case 3: run_system<3, FT>(sd, sidx, band, st, fac, red, E, obs, mask, norm_tol, status); break;
-        case 4: run_system<4, FT>(sd, sidx, band, st, fac, red, E, obs, mask, norm_tol, status); break;
-        case 5: run_system<5, FT>(sd, sidx, band, st, fac, red, E, obs, mask, norm_tol, status); break;
-        case 6: run_system<6, FT>(sd, sidx, band, st, fac, red, E, obs, mask, norm_tol, status); break;
-        case 7: run_system<7, FT>(sd, sidx, band, st, fac, red, E, obs, mask, norm_tol, status); break;
+        case 1: run_system<1, FT>(sd, sidx, band, st, fac, red, E, obs, mask, norm_tol, status, prof); break;
+        case 2: run_system<2, FT>(sd, sidx, band, st, fac, red, E, obs, mask, norm_tol, status, prof); break;
+        case 3: run_system<3, FT>(sd, sidx, band, st, fac, red, E, obs, mask, norm_tol, status, prof); break;
+        case 4: run_system<4, FT>(sd, sidx, band, st, fac, red, E, obs, mask, norm_tol, status, prof); break;
+        case 5: run_system<5, FT>(sd, sidx, band, st, fac, red, E, obs, mask, norm_tol, status, prof); break;
+        case 6: run_system<6, FT>(sd, sidx, band, st, fac, red, E, obs, mask, norm_tol, status, prof); break;
+        case 7: run_system<7, FT>(sd, sidx, band, st, fac, red, E, obs, mask, norm_tol, status, prof); break;
         default: break;
     }
 }
@@ -743,11 +757,11 @@ tdsez_status launch_propagate(BatchData* b, double* psi, const double* E, double
     if (prec == TDSEZ_FP64) {
         propagate_kernel<double><<<nsys, kWave, 0, stream>>>(
             b->d_desc, b->d_band64, b->d_state, (double*)b->d_fac, (double*)b->d_red, E, obs,
-            obs_mask, b->norm_tol, b->d_status);
+            obs_mask, b->norm_tol, b->d_status, b->d_prof);
     } else {
         propagate_kernel<float><<<nsys, kWave, 0, stream>>>(
             b->d_desc, b->d_band32, b->d_state, (float*)b->d_fac, (float*)b->d_red, E, obs,
-            obs_mask, b->norm_tol, b->d_status);
+            obs_mask, b->norm_tol, b->d_status, b->d_prof);
     }
     TDSEZ_HIP_TRY(hipGetLastError());
     {

@@ -52,10 +52,12 @@ def lib():
         "tdsez_get_band": [vp, i, dp],
         "tdsez_ground_state": [vp, i, d, d, i, dp, dp],
         "tdsez_batch_create": [ctypes.POINTER(vp), i, ctypes.POINTER(vp)],
+        "tdsez_ground_state_batched": [vp, d, d, i, dp, vp, lp],
         "tdsez_batch_set": [vp, ctypes.c_char_p, d],
         "tdsez_propagate_batched": [vp, vp, lp, vp, lp, dp, ip, i, u, vp, lp, vp],
         "tdsez_propagate": [vp, vp, vp, d, i, i, u, vp, vp],
         "tdsez_batch_status": [vp, vp, ip, ip],
+        "tdsez_batch_profile": [vp, vp, dp],
         "tdsez_system_status": [vp, vp, ip],
     }
     for name, args in sigs.items():
@@ -179,6 +181,18 @@ def batch_create(systems):
     return Batch(h, systems)
 
 
+def ground_state_batched(batch, psi_packed, psi_off, sigma=None, tol=1e-13, maxit=20000):
+    """Ground states of every system, written into the device complex128
+    buffer psi_packed at the host offsets psi_off; returns the energies."""
+    import torch
+    _check_dev(psi_packed, torch.complex128)
+    eps = np.zeros(len(batch.systems))
+    po, pp = _longs(psi_off)
+    _check(lib().tdsez_ground_state_batched(batch.handle, 1e301 if sigma is None else float(sigma), tol, maxit,
+                                            _dptr(eps), ctypes.c_void_p(psi_packed.data_ptr()), pp))
+    return eps
+
+
 def batch_set(batch, key, value):
     _check(lib().tdsez_batch_set(batch.handle, key.encode(), float(value)))
 
@@ -237,6 +251,14 @@ def batch_status(batch, stream=None):
     s = ctypes.c_int()
     n = ctypes.c_int()
     _check(lib().tdsez_batch_status(batch.handle, _stream_handle(stream), ctypes.byref(s), ctypes.byref(n)))
+
+
+def batch_profile(batch, stream=None):
+    """Average cycles per step in (factor sweep, separator solve, back
+    substitution) and the partition count, one row per system."""
+    out = np.zeros(4 * len(batch.systems))
+    _check(lib().tdsez_batch_profile(batch.handle, _stream_handle(stream), _dptr(out)))
+    return out.reshape(-1, 4)
 
 
 def system_status(sys, stream=None):

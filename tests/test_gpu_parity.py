@@ -89,6 +89,24 @@ def test_ground_state_matches_oracle(name, nev):
         assert np.abs(vec_g[j] - vec_o[j]).max() < 1e-6
 
 
+def test_batched_ground_states_match_oracle():
+    defs = W.config3(nsys=10, seed=0)
+    say("batched ground states", [s.ndof for s in defs])
+    gs = [T.assemble_workload(s) for s in defs]
+    b = T.batch_create(gs)
+    off = np.cumsum([0] + [s.ndof for s in defs[:-1]])
+    psi = torch.zeros(sum(s.ndof for s in defs), dtype=torch.complex128, device="cuda")
+    eps = T.ground_state_batched(b, psi, off)
+    c = psi.cpu().numpy()
+    for i, s in enumerate(defs):
+        m = oracle_of(s)
+        ev, vec = O.eig_banded(m["H0"], m["S"], 1, m["shift"])
+        assert abs(eps[i] - ev[0]) < 1e-12 * abs(ev[0])
+        ci = c[off[i]: off[i] + s.ndof]
+        assert np.abs(ci.imag).max() == 0.0
+        assert np.abs(ci.real - vec[0]).max() < 1e-7
+
+
 def _ground_oracle(m, shift=None):
     ev, vec = O.eig_banded(m["H0"], m["S"], 1, m["shift"] if shift is None else shift)
     return vec[0].astype(np.complex128)
