@@ -58,11 +58,16 @@ typedef enum tdsez_status {
 /* Arithmetic of the propagation.
  *   TDSEZ_FP64: bands, factorisations, solves, state and reductions in FP64.
  *   TDSEZ_FP32_REFINED: bands stored and the banded factorisation/solve done
- *     in FP32; each step's solve is refined from the previous state (the
- *     residual (B_n - A_n) c_n = -i dt H^{n+1/2} c_n is formed in FP64, the
- *     FP32 solve gives the increment, the state is accumulated in FP64),
- *     plus `refine` further FP64-residual sweeps (see tdsez_batch_set).
- *     State, observables and time series stay FP64. */
+ *     in FP32.  Each step solves for the increment from the previous state
+ *     (right-hand side (B_n - A_n) c_n = -i dt H^{n+1/2} c_n formed in FP64,
+ *     state accumulated in FP64), then runs `refine` iterative-refinement
+ *     sweeps (default 1, see tdsez_batch_set): the residual
+ *     B_n c_n - A_n c of the current iterate is formed in FP64 from the FP64
+ *     bands and solved with the same FP32 factorisation, so the sweeps
+ *     converge to the FP64 Crank-Nicolson step.  Without a sweep the FP32
+ *     rounding of the factorisation acts like a perturbed mass matrix and
+ *     the phase error grows linearly in time.  State, observables and time
+ *     series stay FP64. */
 typedef enum tdsez_precision { TDSEZ_FP64 = 0, TDSEZ_FP32_REFINED = 1 } tdsez_precision;
 
 /* Observable selection bits.  The output series always has 3 columns per
@@ -155,8 +160,9 @@ tdsez_status tdsez_ground_state_batched(tdsez_batch b, double sigma, double tol,
  * Synchronous. */
 tdsez_status tdsez_batch_create(const tdsez_system* sys, int nsys, tdsez_batch* out);
 
-/* Tuning knobs of a batch.  key: "refine" (extra FP64-residual refinement
- * sweeps of the FP32 path, 0..4, default 0), "norm_tol" (latch ENORMDRIFT
+/* Tuning knobs of a batch.  key: "refine" (FP64-residual refinement sweeps
+ * per step of TDSEZ_FP32_REFINED calls, integer 0..4, default 1; TDSEZ_FP64
+ * calls run none), "norm_tol" (latch ENORMDRIFT
  * when |nu_n/nu_0 - 1| > value; 0 disables, default 0), "chunks" (force the
  * partition count of every system, 0 = plan, default 0), "profile" (1 turns
  * on per-phase cycle counters read by tdsez_batch_profile, 0 off). */
@@ -190,11 +196,11 @@ tdsez_status tdsez_propagate(tdsez_system sys, double* psi, const double* E, dou
                              tdsez_precision prec, unsigned obs, double* obs_out, void* stream);
 
 /* Phase profile of the last propagation of a profiled batch (see
- * tdsez_batch_set "profile").  Synchronises `stream`; out[4*s + 0..3] =
+ * tdsez_batch_set "profile").  Synchronises `stream`; out[5*s + 0..4] =
  * average shader-clock cycles per time step spent by system s in the
- * factorisation sweep, the separator (reduced) solve and the back-
- * substitution sweeps, and the partition count used for it.  EINVAL when
- * profiling is off. */
+ * factorisation sweep, the separator (reduced) solve, the back-
+ * substitution sweep and the refinement sweeps, and the partition count
+ * used for it.  EINVAL when profiling is off. */
 tdsez_status tdsez_batch_profile(tdsez_batch b, void* stream, double* out);
 
 /* Synchronise `stream`, then return and clear the first device-side failure

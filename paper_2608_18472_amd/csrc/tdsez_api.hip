@@ -45,6 +45,8 @@ static void free_batch_device(BatchData* b) {
     (void)hipFree(b->d_band64);
     (void)hipFree(b->d_band32);
     (void)hipFree(b->d_state);
+    (void)hipFree(b->d_dtot);
+    (void)hipFree(b->d_rhs);
     (void)hipFree(b->d_fac);
     (void)hipFree(b->d_red);
     (void)hipFree(b->d_desc);
@@ -54,6 +56,8 @@ static void free_batch_device(BatchData* b) {
     b->d_band64 = nullptr;
     b->d_band32 = nullptr;
     b->d_state = nullptr;
+    b->d_dtot = nullptr;
+    b->d_rhs = nullptr;
     b->d_fac = nullptr;
     b->d_red = nullptr;
     b->d_desc = nullptr;
@@ -193,8 +197,8 @@ tdsez_status tdsez_batch_create(const tdsez_system* sys, int nsys, tdsez_batch* 
 tdsez_status tdsez_batch_set(tdsez_batch b, const char* key, double value) {
     if (!b || !key) return fail(TDSEZ_EINVAL, "NULL argument");
     if (!std::strcmp(key, "refine")) {
-        if (value < 0 || value > 4) return fail(TDSEZ_EINVAL, "refine must be in 0..4");
-        if (value != 0) return fail(TDSEZ_EUNSUPPORTED, "extra refinement sweeps are not built yet");
+        if (!(value >= 0 && value <= 4) || value != (double)(int)value)
+            return fail(TDSEZ_EINVAL, "refine must be an integer in 0..4");
         b->d.refine = (int)value;
         return TDSEZ_OK;
     }
@@ -205,7 +209,7 @@ tdsez_status tdsez_batch_set(tdsez_batch b, const char* key, double value) {
     }
     if (!std::strcmp(key, "profile")) {
         if (value != 0.0 && !b->d.d_prof) {
-            size_t bytes = sizeof(unsigned long long) * 4 * b->d.sys.size();
+            size_t bytes = sizeof(unsigned long long) * 5 * b->d.sys.size();
             TDSEZ_HIP_TRY(hipMalloc(&b->d.d_prof, bytes));
             TDSEZ_HIP_TRY(hipMemset(b->d.d_prof, 0, bytes));
         } else if (value == 0.0 && b->d.d_prof) {
@@ -272,12 +276,12 @@ tdsez_status tdsez_batch_profile(tdsez_batch b, void* stream, double* out) {
     if (!b->d.d_prof) return fail(TDSEZ_EINVAL, "profiling is off (tdsez_batch_set(b, \"profile\", 1))");
     TDSEZ_HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
     const size_t n = b->d.sys.size();
-    std::vector<unsigned long long> h(4 * n);
-    TDSEZ_HIP_TRY(hipMemcpy(h.data(), b->d.d_prof, sizeof(unsigned long long) * 4 * n, hipMemcpyDeviceToHost));
+    std::vector<unsigned long long> h(5 * n);
+    TDSEZ_HIP_TRY(hipMemcpy(h.data(), b->d.d_prof, sizeof(unsigned long long) * 5 * n, hipMemcpyDeviceToHost));
     for (size_t s = 0; s < n; ++s) {
-        double ns = h[4 * s + 3] > 0 ? (double)h[4 * s + 3] : 1.0;
-        for (int k = 0; k < 3; ++k) out[4 * s + k] = (double)h[4 * s + k] / ns;
-        out[4 * s + 3] = (double)b->d.plan[s].P;
+        double ns = h[5 * s + 4] > 0 ? (double)h[5 * s + 4] : 1.0;
+        for (int k = 0; k < 4; ++k) out[5 * s + k] = (double)h[5 * s + k] / ns;
+        out[5 * s + 4] = (double)b->d.plan[s].P;
     }
     return TDSEZ_OK;
 }

@@ -107,18 +107,20 @@ struct BatchData {
     std::vector<Plan> plan;
     std::vector<SysDesc> desc;       // host copy, offsets of the internal buffers
     int maxp = 0;
-    int refine = 0;
+    int refine = 1;                  // refinement sweeps of TDSEZ_FP32_REFINED calls
     double norm_tol = 0.0;
     int force_chunks = 0;
     long long band_elems = 0, state_elems = 0, fac_elems64 = 0, red_elems64 = 0;
     double* d_band64 = nullptr;
     float* d_band32 = nullptr;
     double* d_state = nullptr;       // interleaved complex128 states
+    double* d_dtot = nullptr;        // increment of the current step (refinement sweeps)
+    void* d_rhs = nullptr;           // right-hand side of the current step (FP64 or FP32)
     void* d_fac = nullptr;           // factor workspace (sized for FP64)
     void* d_red = nullptr;           // reduced-system workspace (sized for FP64)
     SysDesc* d_desc = nullptr;
     int* d_status = nullptr;         // [0] code, [1] system, [2] step
-    unsigned long long* d_prof = nullptr;  // optional phase cycle counters, 4 per system
+    unsigned long long* d_prof = nullptr;  // optional phase cycle counters, 5 per system
     int nsys_alloc_desc = 0;
 };
 

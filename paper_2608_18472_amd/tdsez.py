@@ -255,10 +255,11 @@ def batch_status(batch, stream=None):
 
 def batch_profile(batch, stream=None):
     """Average cycles per step in (factor sweep, separator solve, back
-    substitution) and the partition count, one row per system."""
-    out = np.zeros(4 * len(batch.systems))
+    substitution, refinement sweeps) and the partition count, one row per
+    system."""
+    out = np.zeros(5 * len(batch.systems))
     _check(lib().tdsez_batch_profile(batch.handle, _stream_handle(stream), _dptr(out)))
-    return out.reshape(-1, 4)
+    return out.reshape(-1, 5)
 
 
 def system_status(sys, stream=None):

@@ -286,3 +286,46 @@ def test_invalid_arguments():
         assert e.value.status == 1
     with pytest.raises(T.TdsezError):
         T.propagate(g, psi, E, 0.05, 5, 3, T.OBS_ALL, o)
+    b = T.batch_create([g])
+    for bad in (-1, 5, 0.5, math.nan):
+        with pytest.raises(T.TdsezError) as e:
+            T.batch_set(b, "refine", bad)
+        assert e.value.status == 1
+    with pytest.raises(T.TdsezError) as e:
+        T.batch_set(b, "no-such-key", 1)
+    assert e.value.status == 1
+
+
+def _strong_field_systems(count, nmax=1100):
+    """Systems of the 1024-system batch with the largest quiver amplitude
+    E0/w^2 (the longest, strongest pulses), restricted to N <= nmax."""
+    defs = [s for s in W.config3(nsys=1024, seed=0) if s.ndof <= nmax]
+    return sorted(defs, key=lambda s: -s.meta["E0"] / s.meta["omega"] ** 2)[:count]
+
+
+@pytest.mark.parametrize("which", [0, 1])
+def test_refinement_sweep_meets_dipole_bar_on_strong_fields(which):
+    """Whole pulses of the strongest-field systems of the uneven batch.  The
+    FP32 factorisation without a sweep drifts in phase (its rounding acts like
+    a perturbed mass matrix); one FP64-residual sweep restores the 1e-5 bar."""
+    sd = _strong_field_systems(2)[which]
+    say("strong field", sd.ndof, sd.order, sd.meta["E0"], sd.meta["omega"], sd.nsteps)
+    g = T.assemble_workload(sd)
+    m = oracle_of(sd)
+    psi0 = _ground_oracle(m)
+    ref, _ = O.propagate(m, psi0, sd.E, sd.dt, sd.nsteps)
+    errs = {}
+    b = T.batch_create([g])
+    for refine in (0, 1, 2):
+        T.batch_set(b, "refine", refine)
+        psi = torch.from_numpy(psi0.copy()).cuda()
+        E = torch.from_numpy(sd.E[: sd.nsteps + 1].copy()).cuda()
+        o = torch.zeros(3 * (sd.nsteps + 1), dtype=torch.float64, device="cuda")
+        T.propagate_batched(b, psi, [0], E, [0], [sd.dt], [sd.nsteps], T.FP32_REFINED, T.OBS_ALL, o, [0])
+        T.batch_status(b)
+        got = o.cpu().numpy().reshape(-1, 3)
+        errs[refine] = rel(got[:, 1], ref[:, 1])
+    say("dipole errors by sweeps", errs)
+    assert errs[1] < 1e-5
+    assert errs[2] < 1e-5
+    assert errs[1] < errs[0]
