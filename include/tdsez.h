@@ -195,6 +195,35 @@ tdsez_status tdsez_propagate_batched(tdsez_batch b, double* psi_packed, const lo
 tdsez_status tdsez_propagate(tdsez_system sys, double* psi, const double* E, double dt, int nsteps,
                              tdsez_precision prec, unsigned obs, double* obs_out, void* stream);
 
+/* Gradient of a real function J of the observable series by the discrete
+ * adjoint of the Crank-Nicolson recursion of section V.B (the paper gives no
+ * adjoint; this is the exact gradient of the discrete recursion).  With
+ * lambda_N = g_N and, for n = N-1..0,
+ *   z_n = B_n^-1 lambda_{n+1},   lambda_n = g_n + A_n z_n,
+ *   g_n = 2 J_nu,n S c_n + 2 J_d,n D c_n - 2 J_a,n (G c_n + E_n Mi c_n),
+ * the outputs are
+ *   dJdE[n] = (a Im(z_{n-1}^H D (c_{n-1} + c_n)) + a Im(z_n^H D (c_n + c_{n+1})))/2
+ *             - J_a,n c_n^H Mi c_n        (a = dt/2; missing terms at n = 0, N)
+ *   dJdpsi0 = lambda_0.
+ * J_nu,n, J_d,n, J_a,n = dJdobs[n*3 + 0..2] (columns whose bit is not in
+ * `obs` are ignored).  psi0_packed: device complex128 initial states at
+ * psi_off (natural order); E_packed/E_off, dt, nsteps as for
+ * tdsez_propagate_batched; dJdobs_packed: device FP64 at obs_off;
+ * dJdE_packed: device FP64 [nsteps+1] per system at E_off (overwritten);
+ * dJdpsi0_packed: device complex128 at psi_off, or NULL.  The forward
+ * states are recomputed from psi0 with a checkpoint every ckpt_stride steps
+ * (0: ceil(sqrt(nsteps))), so the cost is about three propagations and the
+ * memory (nsteps/ckpt_stride + ckpt_stride + 1) states per system (device
+ * workspace owned by the batch, grown on demand).  FP64 only
+ * (TDSEZ_FP32_REFINED: EUNSUPPORTED).  Asynchronous on `stream`; device
+ * failures are latched as for propagation.  Uses the batch's working state,
+ * so it must not overlap a propagation of the same batch. */
+tdsez_status tdsez_adjoint_batched(tdsez_batch b, const double* psi0_packed, const long* psi_off,
+                                   const double* E_packed, const long* E_off, const double* dt,
+                                   const int* nsteps, tdsez_precision prec, unsigned obs,
+                                   const double* dJdobs_packed, const long* obs_off, double* dJdE_packed,
+                                   double* dJdpsi0_packed, int ckpt_stride, void* stream);
+
 /* Phase profile of the last propagation of a profiled batch (see
  * tdsez_batch_set "profile").  Synchronises `stream`; out[5*s + 0..4] =
  * average shader-clock cycles per time step spent by system s in the

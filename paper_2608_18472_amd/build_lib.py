@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["tdsez_api.hip", "tdsez_assemble.hip", "tdsez_eigen.hip", "tdsez_propagate.hip"]
+SOURCES = ["tdsez_api.hip", "tdsez_assemble.hip", "tdsez_eigen.hip", "tdsez_propagate.hip", "tdsez_adjoint.hip"]
 LIB = os.path.join(HERE, "libtdsez.so")
 
 HIPCC_FLAGS = [

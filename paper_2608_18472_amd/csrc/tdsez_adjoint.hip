@@ -1,0 +1,422 @@
+// Discrete adjoint of the batched Crank-Nicolson propagation (gradients of a
+// function J of the observable series with respect to the field samples and
+// the initial state).
+//
+// The forward recursion is A_n c_{n+1} = B_n c_n with A_n = S + i a H_n,
+// B_n = S - i a H_n = conj(A_n), H_n = H0 + Ebar_n D, a = dt/2,
+// Ebar_n = (E_n + E_{n+1})/2 (section V.B).  For J(nu, d, a-series) the
+// adjoint recursion, run backwards from lambda_N = g_N, is
+//   z_n = B_n^-1 lambda_{n+1} = conj(A_n^-1 conj(lambda_{n+1}))
+//   lambda_n = g_n + A_n z_n
+//   dJ/dEbar_n = a Im(z_n^H D (c_n + c_{n+1}))
+//   g_n = 2 dJ/dnu_n S c_n + 2 dJ/dd_n D c_n - 2 dJ/da_n (G c_n + E_n Mi c_n)
+//   dJ/dE_n = (dJ/dEbar_{n-1} + dJ/dEbar_n)/2 - dJ/da_n c_n^H Mi c_n
+// and dJ/dpsi0 = lambda_0.  The solve with B_n reuses the partitioned
+// factorisation of A_n on the conjugated right-hand side.
+//
+// States are not stored for every step: a first forward sweep keeps every
+// ck-th state (ck ~ sqrt(nsteps)); each segment between two checkpoints is
+// recomputed into a segment buffer before its adjoint steps run, so the
+// cost is about three forward propagations and the memory
+// (nsteps/ck + ck + 1) states per system.  Everything runs in FP64, one
+// wave per system, all systems of the batch in one launch.
+#include <algorithm>
+#include <cmath>
+
+#include "tdsez_passes.hpp"
+
+namespace tdsez {
+
+namespace {
+
+struct AdjArgs {
+    const SysDesc* descs;
+    const double* band;   // FP64 bands
+    double* st;           // working state (interleaved)
+    double* rhs;          // right-hand side of the forward steps
+    double* fac;
+    double* red;
+    double* lam;          // lambda_{n+1} / lambda_n (interleaved)
+    double* wsol;         // A_n^-1 conj(lambda_{n+1}) (interleaved, zero halos)
+    double* ckpt;
+    double* seg;
+    const double* psi0;   // caller's initial states (natural order)
+    const double* E;
+    const double* dJdobs; // [n*3 + 0..2] per system, at obs_off
+    unsigned mask;
+    double* dJdE;         // per system at E_off
+    double* dJdpsi0;      // per system at psi_off, or nullptr
+    int* status;
+    long long state_total;  // complex elements of one whole-batch state
+};
+
+// copy the system's interleaved state (L x LS complex, at state_off of a
+// batch-layout buffer) with lane k owning column k+1 and the first/last lane
+// also copying the zero halo columns
+__device__ void copy_state(const SysDesc& sd, int lane, const double* __restrict__ src,
+                           double* __restrict__ dst) {
+    if (lane >= sd.P) return;
+    const int LS = sd.LS;
+    for (int l = 0; l < sd.L; ++l) {
+        const long long base = sd.state_off + (long long)l * LS;
+        long long at = base + lane + 1;
+        dst[2 * at] = src[2 * at];
+        dst[2 * at + 1] = src[2 * at + 1];
+        if (lane == 0) {
+            dst[2 * base] = src[2 * base];
+            dst[2 * base + 1] = src[2 * base + 1];
+        }
+        if (lane == sd.P - 1) {
+            at = base + sd.P + 1;
+            dst[2 * at] = src[2 * at];
+            dst[2 * at + 1] = src[2 * at + 1];
+        }
+    }
+}
+
+// Update pass of adjoint step n (lane-serial over chunk k, rows 0..L-1 and a
+// halo of p rows of the next chunk):
+//   lambda_n = A_n z + g_n         (z = conj(wsol); z = 0 when !has_z)
+//   part[0] = sum Im(conj(z_r) (D v)_r), v = c_n + c_{n+1}
+//   part[1] = c_n^H Mi c_n
+// Band products use the scatter/gather split of the right-hand-side pass;
+// pairs (r, r-d) of the two reductions are counted by the owner of row r.
+template <int PP>
+__device__ void pass_adjoint_update(const SysDesc& sd, int k, const double* __restrict__ band,
+                                    const double* __restrict__ wsol, const double* __restrict__ cn,
+                                    const double* __restrict__ cn1, double* __restrict__ lam,
+                                    bool has_z, double alpha, double Ebar, double En, double jn,
+                                    double jd, double ja, double part[2]) {
+    constexpr int NM = kNumMats;
+    const int L = sd.L, LS = sd.LS;
+    int col = k + 1;
+    asm volatile("" : "+v"(col));
+    const double* __restrict__ bnd = band + sd.band_off;
+    const unsigned rowstride = (unsigned)(NM * (PP + 1) * LS);
+    const double* __restrict__ ws = wsol + 2 * sd.state_off;
+    const double* __restrict__ c0 = cn + 2 * sd.state_off;
+    const double* __restrict__ c1 = has_z ? cn1 + 2 * sd.state_off : nullptr;
+    double* __restrict__ lm = lam + 2 * sd.state_off;
+
+    cplx<double> zw[PP + 1], cw[PP + 1], vw[PP + 1];  // rows r-p..r, slot PP newest
+    cplx<double> az[PP + 1], kc[PP + 1];               // pending (A z), (K c) of rows r-p..r
+    auto load3 = [&](unsigned at, cplx<double>& z, cplx<double>& c, cplx<double>& v) {
+        c = cmk<double>(c0[2 * at], c0[2 * at + 1]);
+        z = cmk<double>(0, 0);
+        v = c;
+        if (has_z) {
+            z = cmk<double>(ws[2 * at], -ws[2 * at + 1]);
+            v = cmk<double>(c.re + c1[2 * at], c.im + c1[2 * at + 1]);
+        }
+    };
+#pragma unroll
+    for (int i = 0; i <= PP; ++i) {
+        az[i] = cmk<double>(0, 0);
+        kc[i] = cmk<double>(0, 0);
+    }
+    zw[0] = cw[0] = vw[0] = cmk<double>(0, 0);
+#pragma unroll
+    for (int d = 0; d < PP; ++d) {
+        const unsigned at = (unsigned)(L - PP + d) * (unsigned)LS + (unsigned)(col - 1);
+        load3(at, zw[d + 1], cw[d + 1], vw[d + 1]);
+    }
+    double dimag = 0.0, mexp = 0.0;
+    auto stream_row = [&](int r, bool own) {
+        const int lr = own ? r : r - L;
+        const unsigned cc = (unsigned)(own ? col : col + 1);
+        const unsigned rb = (unsigned)lr * rowstride + cc;
+        cplx<double> a[PP + 1];
+        double kk[PP + 1], dd[PP + 1], mi[PP + 1];
+#pragma unroll
+        for (int d = 0; d <= PP; ++d) {
+            const double s = bnd[rb + (unsigned)((0 * (PP + 1) + d) * LS)];
+            const double h = bnd[rb + (unsigned)((1 * (PP + 1) + d) * LS)];
+            dd[d] = bnd[rb + (unsigned)((2 * (PP + 1) + d) * LS)];
+            const double g = bnd[rb + (unsigned)((3 * (PP + 1) + d) * LS)];
+            mi[d] = bnd[rb + (unsigned)((4 * (PP + 1) + d) * LS)];
+            a[d] = cmk<double>(s, alpha * (h + Ebar * dd[d]));
+            kk[d] = 2.0 * jn * s + 2.0 * jd * dd[d] - 2.0 * ja * (g + En * mi[d]);
+        }
+        const unsigned at = (unsigned)lr * (unsigned)LS + cc;
+        cplx<double> zr, cr, vr;
+        load3(at, zr, cr, vr);
+#pragma unroll
+        for (int d = 0; d < PP; ++d) {
+            zw[d] = zw[d + 1];
+            cw[d] = cw[d + 1];
+            vw[d] = vw[d + 1];
+            az[d] = az[d + 1];
+            kc[d] = kc[d + 1];
+        }
+        zw[PP] = zr;
+        cw[PP] = cr;
+        vw[PP] = vr;
+        cplx<double> sa = cmk<double>(0, 0), sk = cmk<double>(0, 0);
+        if (own) {
+#pragma unroll
+            for (int d = 0; d <= PP; ++d) {
+                sa = cfma(sa, a[d], zw[PP - d]);
+                sk.re += kk[d] * cw[PP - d].re;
+                sk.im += kk[d] * cw[PP - d].im;
+            }
+            // reductions over the pairs (r, r - d)
+            double di = dd[0] * (zr.re * vr.im - zr.im * vr.re);
+            double me = mi[0] * (cr.re * cr.re + cr.im * cr.im);
+#pragma unroll
+            for (int d = 1; d <= PP; ++d) {
+                // Im(conj(z_r) v_{r-d} + conj(z_{r-d}) v_r)
+                di += dd[d] * (zr.re * vw[PP - d].im - zr.im * vw[PP - d].re + zw[PP - d].re * vr.im -
+                               zw[PP - d].im * vr.re);
+                me += 2.0 * mi[d] * (cr.re * cw[PP - d].re + cr.im * cw[PP - d].im);
+            }
+            dimag += di;
+            mexp += me;
+        }
+        az[PP] = sa;
+        kc[PP] = sk;
+#pragma unroll
+        for (int d = 1; d <= PP; ++d) {
+            az[PP - d] = cfma(az[PP - d], a[d], zr);
+            kc[PP - d].re += kk[d] * cr.re;
+            kc[PP - d].im += kk[d] * cr.im;
+        }
+        if (r >= PP) {
+            const unsigned o = (unsigned)(r - PP) * (unsigned)LS + (unsigned)col;
+            lm[2 * o] = az[0].re + kc[0].re;
+            lm[2 * o + 1] = az[0].im + kc[0].im;
+        }
+    };
+    for (int r = 0; r < L; ++r) stream_row(r, true);
+#pragma unroll
+    for (int t = 0; t < PP; ++t) stream_row(L + t, false);
+    part[0] = dimag;
+    part[1] = mexp;
+}
+
+// one forward step n -> n+1 in place on st (FP64, no refinement)
+template <int PP>
+__device__ void forward_step(const AdjArgs& ka, const SysDesc& sd, int lane, double alpha, double Ebar) {
+    const bool active = lane < sd.P;
+    double part[3];
+    if (active) {
+        pass_rhs<PP, double>(sd, lane, ka.band, ka.st, ka.rhs, alpha, Ebar, Ebar, false, true, part);
+        pass_elim<PP, double>(sd, lane, ka.band, ka.rhs, ka.fac, ka.red, alpha, Ebar);
+        pass_fill<PP, double, false>(sd, lane, ka.band, ka.fac, ka.red, alpha, Ebar);
+        pass_schur<PP, double>(sd, lane, ka.fac, ka.red);
+    }
+    __syncthreads();
+    pass_reduced<PP, double>(sd, lane, ka.red, true);
+    __syncthreads();
+    if (active) pass_backsub<PP, double>(sd, lane, ka.band, ka.st, nullptr, true, ka.fac, ka.red, alpha, Ebar);
+    __syncthreads();
+}
+
+template <int PP>
+__device__ void run_adjoint(const AdjArgs& ka, const SysDesc& sd, int sidx) {
+    const int lane = threadIdx.x;
+    const bool active = lane < sd.P;
+    const int N = sd.N, L = sd.L, LS = sd.LS, ns = sd.nsteps, ck = sd.ck;
+    const double alpha = 0.5 * sd.dt;
+    const double* Es = ka.E + sd.E_off;
+    const double* jo = ka.dJdobs + sd.obs_off;
+    double* gE = ka.dJdE + sd.E_off;
+    double* ckpt = ka.ckpt;
+    double* seg = ka.seg;
+    const bool use_n = (ka.mask & TDSEZ_OBS_NORM) != 0;
+    const bool use_d = (ka.mask & TDSEZ_OBS_DIPOLE) != 0;
+    const bool use_a = (ka.mask & TDSEZ_OBS_ACCEL) != 0;
+    auto jn = [&](int n) { return use_n ? jo[3 * n + 0] : 0.0; };
+    auto jd = [&](int n) { return use_d ? jo[3 * n + 1] : 0.0; };
+    auto ja = [&](int n) { return use_a ? jo[3 * n + 2] : 0.0; };
+    auto ebar = [&](int n) { return 0.5 * (Es[n] + Es[n + 1]); };
+    // checkpoint and segment buffers hold whole-batch states (the system's
+    // part at state_off, like the working state)
+    auto state_at = [&](double* base, long long idx) { return base + 2 * (idx * ka.state_total); };
+
+    // initial state: natural order -> interleaved, zero halos and padding
+    if (active) {
+        for (int l = 0; l < L; ++l) {
+            const long long row = (long long)lane * L + l;
+            const long long at = sd.state_off + (long long)l * LS + lane + 1;
+            double re = 0.0, im = 0.0;
+            if (row < N) {
+                re = ka.psi0[2 * (sd.psi_off + row)];
+                im = ka.psi0[2 * (sd.psi_off + row) + 1];
+            }
+            ka.st[2 * at] = re;
+            ka.st[2 * at + 1] = im;
+            if (lane == 0) {
+                const long long h = sd.state_off + (long long)l * LS;
+                ka.st[2 * h] = ka.st[2 * h + 1] = 0.0;
+            }
+            if (lane == sd.P - 1) {
+                const long long h = sd.state_off + (long long)l * LS + sd.P + 1;
+                ka.st[2 * h] = ka.st[2 * h + 1] = 0.0;
+            }
+        }
+    }
+    for (int n = lane; n <= ns; n += kWave) gE[n] = 0.0;
+    __syncthreads();
+    // forward sweep keeping checkpoints 0, ck, 2 ck, ...
+    copy_state(sd, lane, ka.st, state_at(ckpt, 0));
+    __syncthreads();
+    for (int n = 0; n < ns; ++n) {
+        forward_step<PP>(ka, sd, lane, alpha, ebar(n));
+        if ((n + 1) % ck == 0 && n + 1 < ns) {
+            copy_state(sd, lane, ka.st, state_at(ckpt, (n + 1) / ck));
+            __syncthreads();
+        }
+    }
+    // lambda_N = g_N and the direct field term of step N
+    {
+        double part[2] = {0.0, 0.0};
+        if (active)
+            pass_adjoint_update<PP>(sd, lane, ka.band, ka.wsol, ka.st, nullptr, ka.lam, false, alpha, Es[ns],
+                                    Es[ns], jn(ns), jd(ns), ja(ns), part);
+        const double me = wave_sum(part[1]);
+        if (lane == 0) gE[ns] -= ja(ns) * me;
+        __syncthreads();
+    }
+    for (int sgi = sd.nseg - 1; sgi >= 0; --sgi) {
+        const int n0 = sgi * ck;
+        const int n1 = n0 + ck < ns ? n0 + ck : ns;
+        // recompute c_{n0} .. c_{n1} into the segment buffer
+        copy_state(sd, lane, state_at(ckpt, sgi), ka.st);
+        copy_state(sd, lane, state_at(ckpt, sgi), state_at(seg, 0));
+        __syncthreads();
+        for (int n = n0; n < n1; ++n) {
+            forward_step<PP>(ka, sd, lane, alpha, ebar(n));
+            copy_state(sd, lane, ka.st, state_at(seg, n - n0 + 1));
+            __syncthreads();
+        }
+        for (int n = n1 - 1; n >= n0; --n) {
+            const double Eb = ebar(n);
+            // w = A_n^-1 conj(lambda_{n+1})
+            if (active) {
+                pass_elim<PP, double, true>(sd, lane, ka.band, ka.lam, ka.fac, ka.red, alpha, Eb);
+                pass_fill<PP, double, false>(sd, lane, ka.band, ka.fac, ka.red, alpha, Eb);
+                pass_schur<PP, double>(sd, lane, ka.fac, ka.red);
+            }
+            __syncthreads();
+            pass_reduced<PP, double>(sd, lane, ka.red, true);
+            __syncthreads();
+            if (active)
+                pass_backsub<PP, double>(sd, lane, ka.band, ka.wsol, nullptr, true, ka.fac, ka.red, alpha, Eb,
+                                         true);
+            __syncthreads();
+            // lambda_n = g_n + A_n z, z = conj(w)
+            double part[2] = {0.0, 0.0};
+            if (active)
+                pass_adjoint_update<PP>(sd, lane, ka.band, ka.wsol, state_at(seg, n - n0),
+                                        state_at(seg, n - n0 + 1), ka.lam, true, alpha, Eb, Es[n], jn(n),
+                                        jd(n), ja(n), part);
+            const double di = wave_sum(part[0]);
+            const double me = wave_sum(part[1]);
+            if (!isfinite(di) || !isfinite(me)) {
+                if (lane == 0) latch(ka.status, TDSEZ_ENONFINITE, sidx, n);
+                return;
+            }
+            if (lane == 0) {
+                const double dEb = alpha * di;
+                gE[n] += 0.5 * dEb - ja(n) * me;
+                gE[n + 1] += 0.5 * dEb;
+            }
+            __syncthreads();
+        }
+    }
+    // dJ/dpsi0 = lambda_0
+    if (ka.dJdpsi0 && active) {
+        const double* lm = ka.lam + 2 * sd.state_off;
+        for (int l = 0; l < L; ++l) {
+            const long long row = (long long)lane * L + l;
+            if (row >= N) break;
+            const long long at = (long long)l * LS + lane + 1;
+            ka.dJdpsi0[2 * (sd.psi_off + row)] = lm[2 * at];
+            ka.dJdpsi0[2 * (sd.psi_off + row) + 1] = lm[2 * at + 1];
+        }
+    }
+}
+
+__global__ __launch_bounds__(kWave) void adjoint_kernel(AdjArgs ka) {
+    const int sidx = blockIdx.x;
+    const SysDesc sd = ka.descs[sidx];
+    switch (sd.p) {
+        case 1: run_adjoint<1>(ka, sd, sidx); break;
+        case 2: run_adjoint<2>(ka, sd, sidx); break;
+        case 3: run_adjoint<3>(ka, sd, sidx); break;
+        case 4: run_adjoint<4>(ka, sd, sidx); break;
+        case 5: run_adjoint<5>(ka, sd, sidx); break;
+        case 6: run_adjoint<6>(ka, sd, sidx); break;
+        case 7: run_adjoint<7>(ka, sd, sidx); break;
+        default: break;
+    }
+}
+
+}  // namespace
+
+tdsez_status launch_adjoint(BatchData* b, const double* psi0, const double* E, const double* dJdobs,
+                            unsigned obs_mask, double* dJdE, double* dJdpsi0, int ckpt_stride,
+                            hipStream_t stream) {
+    const int nsys = (int)b->sys.size();
+    const long long state_total = b->state_elems;
+    int max_nseg = 1, max_ck = 1;
+    for (int s = 0; s < nsys; ++s) {
+        SysDesc& d = b->desc[s];
+        const int ns = d.nsteps;
+        int ck = ckpt_stride > 0 ? ckpt_stride : (int)std::ceil(std::sqrt((double)(ns > 0 ? ns : 1)));
+        if (ck > ns) ck = ns > 0 ? ns : 1;
+        if (ck < 1) ck = 1;
+        d.ck = ck;
+        d.nseg = ns > 0 ? (ns + ck - 1) / ck : 0;
+        max_nseg = std::max(max_nseg, d.nseg);
+        max_ck = std::max(max_ck, ck);
+    }
+    const long long ck_total = (long long)max_nseg * state_total;
+    const long long seg_total = (long long)(max_ck + 1) * state_total;
+    if (!b->d_lam) {
+        TDSEZ_HIP_TRY(hipMalloc(&b->d_lam, 2 * sizeof(double) * (size_t)state_total));
+        TDSEZ_HIP_TRY(hipMalloc(&b->d_wsol, 2 * sizeof(double) * (size_t)state_total));
+        // halo columns of the solution buffer are read and never written
+        TDSEZ_HIP_TRY(hipMemset(b->d_wsol, 0, 2 * sizeof(double) * (size_t)state_total));
+    }
+    if (ck_total > b->ckpt_elems) {
+        (void)hipFree(b->d_ckpt);
+        b->d_ckpt = nullptr;
+        b->ckpt_elems = 0;
+        TDSEZ_HIP_TRY(hipMalloc(&b->d_ckpt, 2 * sizeof(double) * (size_t)ck_total));
+        b->ckpt_elems = ck_total;
+    }
+    if (seg_total > b->seg_elems) {
+        (void)hipFree(b->d_seg);
+        b->d_seg = nullptr;
+        b->seg_elems = 0;
+        TDSEZ_HIP_TRY(hipMalloc(&b->d_seg, 2 * sizeof(double) * (size_t)seg_total));
+        b->seg_elems = seg_total;
+    }
+    TDSEZ_HIP_TRY(hipMemcpyAsync(b->d_desc, b->desc.data(), sizeof(SysDesc) * nsys, hipMemcpyHostToDevice,
+                                 stream));
+    AdjArgs ka;
+    ka.descs = b->d_desc;
+    ka.band = b->d_band64;
+    ka.st = b->d_state;
+    ka.rhs = (double*)b->d_rhs;
+    ka.fac = (double*)b->d_fac;
+    ka.red = (double*)b->d_red;
+    ka.lam = b->d_lam;
+    ka.wsol = b->d_wsol;
+    ka.ckpt = b->d_ckpt;
+    ka.seg = b->d_seg;
+    ka.psi0 = psi0;
+    ka.E = E;
+    ka.dJdobs = dJdobs;
+    ka.mask = obs_mask;
+    ka.dJdE = dJdE;
+    ka.dJdpsi0 = dJdpsi0;
+    ka.status = b->d_status;
+    ka.state_total = state_total;
+    adjoint_kernel<<<nsys, kWave, 0, stream>>>(ka);
+    TDSEZ_HIP_TRY(hipGetLastError());
+    return TDSEZ_OK;
+}
+
+}  // namespace tdsez

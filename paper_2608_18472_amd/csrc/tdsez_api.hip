@@ -47,6 +47,12 @@ static void free_batch_device(BatchData* b) {
     (void)hipFree(b->d_state);
     (void)hipFree(b->d_dtot);
     (void)hipFree(b->d_rhs);
+    (void)hipFree(b->d_lam);
+    (void)hipFree(b->d_wsol);
+    (void)hipFree(b->d_ckpt);
+    (void)hipFree(b->d_seg);
+    b->d_lam = b->d_wsol = b->d_ckpt = b->d_seg = nullptr;
+    b->ckpt_elems = b->seg_elems = 0;
     (void)hipFree(b->d_fac);
     (void)hipFree(b->d_red);
     (void)hipFree(b->d_desc);
@@ -256,6 +262,37 @@ tdsez_status tdsez_propagate_batched(tdsez_batch b, double* psi_packed, const lo
     }
     return launch_propagate(d, psi_packed, E_packed, obs ? obs_packed : nullptr, prec, obs,
                             (hipStream_t)stream);
+}
+
+tdsez_status tdsez_adjoint_batched(tdsez_batch b, const double* psi0_packed, const long* psi_off,
+                                   const double* E_packed, const long* E_off, const double* dt,
+                                   const int* nsteps, tdsez_precision prec, unsigned obs,
+                                   const double* dJdobs_packed, const long* obs_off, double* dJdE_packed,
+                                   double* dJdpsi0_packed, int ckpt_stride, void* stream) {
+    if (!b || !psi0_packed || !psi_off || !E_packed || !E_off || !dt || !nsteps || !dJdobs_packed ||
+        !obs_off || !dJdE_packed)
+        return fail(TDSEZ_EINVAL, "NULL argument");
+    if (prec == TDSEZ_FP32_REFINED)
+        return fail(TDSEZ_EUNSUPPORTED, "the adjoint runs in FP64 only (use TDSEZ_FP64)");
+    if (prec != TDSEZ_FP64) return fail(TDSEZ_EINVAL, "unknown precision %d", (int)prec);
+    if (obs & ~7u) return fail(TDSEZ_EINVAL, "unknown observable bits 0x%x", obs);
+    if (ckpt_stride < 0) return fail(TDSEZ_EINVAL, "ckpt_stride must be >= 0");
+    BatchData* d = &b->d;
+    const int nsys = (int)d->sys.size();
+    for (int s = 0; s < nsys; ++s) {
+        if (!(dt[s] > 0.0) || !std::isfinite(dt[s])) return fail(TDSEZ_EINVAL, "dt[%d] must be > 0", s);
+        if (nsteps[s] < 0) return fail(TDSEZ_EINVAL, "nsteps[%d] < 0", s);
+        if (psi_off[s] < 0 || E_off[s] < 0 || obs_off[s] < 0)
+            return fail(TDSEZ_EINVAL, "negative offset for system %d", s);
+        SysDesc& sd = d->desc[s];
+        sd.nsteps = nsteps[s];
+        sd.dt = dt[s];
+        sd.psi_off = psi_off[s];
+        sd.E_off = E_off[s];
+        sd.obs_off = obs_off[s];
+    }
+    return launch_adjoint(d, psi0_packed, E_packed, dJdobs_packed, obs, dJdE_packed, dJdpsi0_packed, ckpt_stride,
+                          (hipStream_t)stream);
 }
 
 tdsez_status tdsez_propagate(tdsez_system sys, double* psi, const double* E, double dt, int nsteps,

@@ -100,6 +100,8 @@ struct SysDesc {
     long long psi_off;    // complex elements into the caller's psi buffer
     long long E_off;      // doubles into the caller's E buffer
     long long obs_off;    // doubles into the caller's obs buffer
+    // adjoint only: checkpoint stride and number of segments
+    int ck, nseg;
 };
 
 struct BatchData {
@@ -116,6 +118,12 @@ struct BatchData {
     double* d_state = nullptr;       // interleaved complex128 states
     double* d_dtot = nullptr;        // increment of the current step (refinement sweeps)
     void* d_rhs = nullptr;           // right-hand side of the current step (FP64 or FP32)
+    // adjoint workspaces (allocated by the first adjoint call, grown on demand)
+    double* d_lam = nullptr;         // adjoint variable, state layout
+    double* d_wsol = nullptr;        // solution of the conjugated solve, state layout
+    double* d_ckpt = nullptr;        // checkpoint states
+    double* d_seg = nullptr;         // states of the segment being reversed
+    long long ckpt_elems = 0, seg_elems = 0;
     void* d_fac = nullptr;           // factor workspace (sized for FP64)
     void* d_red = nullptr;           // reduced-system workspace (sized for FP64)
     SysDesc* d_desc = nullptr;
@@ -137,6 +145,10 @@ Plan make_plan(int N, int p, int force_chunks);
 tdsez_status pack_bands(BatchData* b);
 tdsez_status launch_propagate(BatchData* b, double* psi, const double* E, double* obs,
                               tdsez_precision prec, unsigned obs_mask, hipStream_t stream);
+// Adjoint (tdsez_adjoint.hip): descriptors already hold nsteps, dt and offsets
+tdsez_status launch_adjoint(BatchData* b, const double* psi0, const double* E, const double* dJdobs,
+                            unsigned obs_mask, double* dJdE, double* dJdpsi0, int ckpt_stride,
+                            hipStream_t stream);
 
 // Eigen (tdsez_eigen.hip)
 tdsez_status ground_state_device(SystemData* sys, int nev, double sigma, double tol, int maxit,

@@ -35,966 +35,11 @@
 //   factor [j][item][k]      2p+2 items per interior pivot j (fac_items)
 #include <cmath>
 
-#include "tdsez_internal.hpp"
+#include "tdsez_passes.hpp"
 
 namespace tdsez {
 
 namespace {
-
-// Reduced-system workspace of one system (complex elements of FT).
-template <typename FT>
-struct RedLayout {
-    // per separator block: W (p*p), F (p*p), TL (p*p), yR (p), gT (p)
-    __host__ __device__ static long long chunk_block(int p) { return 3LL * p * p + 2LL * p; }
-    __host__ __device__ static long long dinv(int p, int P) { return (long long)P * chunk_block(p); }
-    __host__ __device__ static long long mblk(int p, int P) { return dinv(p, P) + (long long)P * p * p; }
-    __host__ __device__ static long long zvec(int p, int P) { return mblk(p, P) + (long long)P * p * p; }
-    __host__ __device__ static long long xvec(int p, int P) { return zvec(p, P) + (long long)P * p; }
-    __host__ __device__ static long long total(int p, int P) { return xvec(p, P) + (long long)P * p; }
-};
-
-// Factor rows: pivot j of chunk k stores, at fb = j * IT * P + item * P + k
-// (IT = 2p + 2 complex items): items 0..p-1 the multipliers L[j+1+i][j],
-// item p 1/D_j, item p+1 yhat_j = (L^-1 b)_j, items p+2..2p+1 the fill row
-// f_j = (L^-1 A_{I,left})_j (coupling of pivot j to the left separator).
-__host__ __device__ inline int fac_items(int p) { return 2 * p + 2; }
-
-
-
-// 1/z with the hardware reciprocal: one v_rcp_f32 (about 1 ulp) for FP32,
-// v_rcp_f64 refined by two Newton steps for FP64.  Used for pivots, which
-// are never zero (the Hermitian part of A_n is positive definite).
-__device__ inline float rcp_dev(float d) { return __builtin_amdgcn_rcpf(d); }
-__device__ inline double rcp_dev(double d) {
-    double r = __builtin_amdgcn_rcp(d);
-    double e = fma(-d, r, 1.0);
-    r = fma(r, e, r);
-    e = fma(-d, r, 1.0);
-    return fma(r, e, r);
-}
-template <typename FT>
-__device__ inline cplx<FT> cinv_dev(cplx<FT> a) {
-    FT s = rcp_dev(a.re * a.re + a.im * a.im);
-    return {a.re * s, -a.im * s};
-}
-template <typename FT>
-__device__ inline cplx<FT> csel(bool c, cplx<FT> x, cplx<FT> y) {
-    return {c ? x.re : y.re, c ? x.im : y.im};
-}
-// value of lane `src` (wave-uniform) in every lane, without LDS
-__device__ inline float bcast_lane(float v, int src) {
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
-}
-__device__ inline double bcast_lane(double v, int src) {
-    int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
-    int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
-    return __hiloint2double(hi, lo);
-}
-template <typename FT>
-__device__ inline cplx<FT> bcast_c(cplx<FT> v, int src) {
-    return {bcast_lane(v.re, src), bcast_lane(v.im, src)};
-}
-
-__device__ inline double wave_sum(double v) {
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
-// complex element idx of an interleaved (re, im) array; per-system indices
-// fit in 32 bits, which lets the compiler use SGPR-base + 32-bit offsets
-template <typename FT>
-__device__ inline cplx<FT> ld_c(const FT* base, unsigned idx) {
-    return cplx<FT>{base[2u * idx], base[2u * idx + 1u]};
-}
-template <typename FT>
-__device__ inline void st_c(FT* base, unsigned idx, cplx<FT> v) {
-    base[2u * idx] = v.re;
-    base[2u * idx + 1u] = v.im;
-}
-
-// Pass H: FP64 observables of c_n and the right-hand side of (1),
-//   rhs_r = -i dt (H0 + Ebar D) c_n,   r = 0..L-1 of chunk k,
-// stored (in FT) for the elimination.  Lane-serial over the chunk's rows
-// plus a halo of p rows of the next chunk; each pair of rows (r, r-d) of an
-// observable is counted by the owner of the larger row.
-template <int PP, typename FT>
-__device__ void pass_rhs(const SysDesc& sd, int k, const FT* __restrict__ band,
-                         const double* __restrict__ st, FT* __restrict__ rhs, double alpha,
-                         double Ebar, double En, bool want_acc, bool want_rhs, double obs_part[3]) {
-    constexpr int NM = kNumMats;
-    const int L = sd.L, LS = sd.LS;
-    int col = k + 1;
-    // Per-lane addresses are rebuilt every step instead of being hoisted out
-    // of the time loop (that would keep hundreds of them live in registers).
-    asm volatile("" : "+v"(col));
-    const FT* __restrict__ bnd = band + sd.band_off;
-    const double* __restrict__ cst = st + 2 * sd.state_off;
-    FT* __restrict__ rs = rhs + 2 * sd.state_off;
-    const unsigned rowstride = (unsigned)(NM * (PP + 1) * LS);
-
-    cplx<double> cw[PP + 1];    // c rows r-p..r (slot PP newest)
-    cplx<double> hacc[PP + 1];  // pending (H c) of rows r-p..r
-#pragma unroll
-    for (int i = 0; i <= PP; ++i) hacc[i] = cmk<double>(0, 0);
-    // c rows -p..-1 come from the previous chunk (column k; zero for k = 0)
-    cw[0] = cmk<double>(0, 0);
-#pragma unroll
-    for (int d = 0; d < PP; ++d) {
-        unsigned at = (unsigned)(L - PP + d) * (unsigned)LS + (unsigned)(col - 1);
-        cw[d + 1] = cmk<double>(cst[2 * at], cst[2 * at + 1]);
-    }
-    double nu = 0.0, dip = 0.0, acc = 0.0;
-
-    struct RowIn {
-        FT bS[PP + 1], bH[PP + 1], bD[PP + 1], bG[PP + 1], bM[PP + 1];
-        cplx<double> cr;
-    };
-    auto load_row = [&](int r) {
-        if (r >= L + PP) r = L + PP - 1;  // past the end: reload the last row (unused)
-        const bool own = r < L;
-        const int lr = own ? r : r - L;
-        const unsigned cc = (unsigned)(own ? col : col + 1);
-        const unsigned rb = (unsigned)lr * rowstride + cc;
-        RowIn in;
-#pragma unroll
-        for (int d = 0; d <= PP; ++d) {
-            in.bS[d] = bnd[rb + (unsigned)((0 * (PP + 1) + d) * LS)];
-            in.bH[d] = bnd[rb + (unsigned)((1 * (PP + 1) + d) * LS)];
-            in.bD[d] = bnd[rb + (unsigned)((2 * (PP + 1) + d) * LS)];
-            in.bG[d] = (FT)0;
-            in.bM[d] = (FT)0;
-        }
-        if (want_acc && own) {
-#pragma unroll
-            for (int d = 0; d <= PP; ++d) {
-                in.bG[d] = bnd[rb + (unsigned)((3 * (PP + 1) + d) * LS)];
-                in.bM[d] = bnd[rb + (unsigned)((4 * (PP + 1) + d) * LS)];
-            }
-        }
-        const unsigned sat = (unsigned)lr * (unsigned)LS + cc;
-        in.cr = cmk<double>(cst[2 * sat], cst[2 * sat + 1]);
-        return in;
-    };
-    auto stream_row = [&](const RowIn& in, int r, bool own) {
-        const cplx<double> cr = in.cr;
-#pragma unroll
-        for (int d = 0; d < PP; ++d) cw[d] = cw[d + 1];
-        cw[PP] = cr;
-        double h[PP + 1];
-#pragma unroll
-        for (int d = 0; d <= PP; ++d) h[d] = (double)in.bH[d] + Ebar * (double)in.bD[d];
-#pragma unroll
-        for (int d = 0; d < PP; ++d) hacc[d] = hacc[d + 1];
-        {
-            cplx<double> sum = cmk<double>(0, 0);
-            if (own) {
-#pragma unroll
-                for (int d = 0; d <= PP; ++d) {
-                    sum.re += h[d] * cw[PP - d].re;
-                    sum.im += h[d] * cw[PP - d].im;
-                }
-            }
-            hacc[PP] = sum;
-        }
-#pragma unroll
-        for (int d = 1; d <= PP; ++d) {
-            hacc[PP - d].re += h[d] * cr.re;
-            hacc[PP - d].im += h[d] * cr.im;
-        }
-        if (own) {
-            double o[PP + 1];
-#pragma unroll
-            for (int d = 0; d <= PP; ++d) o[d] = cr.re * cw[PP - d].re + cr.im * cw[PP - d].im;
-            double sn = (double)in.bS[0] * o[0], sdp = (double)in.bD[0] * o[0];
-#pragma unroll
-            for (int d = 1; d <= PP; ++d) {
-                sn += 2.0 * (double)in.bS[d] * o[d];
-                sdp += 2.0 * (double)in.bD[d] * o[d];
-            }
-            nu += sn;
-            dip += sdp;
-            if (want_acc) {
-                double sg = 0.0, sm = 0.0;
-#pragma unroll
-                for (int d = 0; d <= PP; ++d) {
-                    double w = d == 0 ? 1.0 : 2.0;
-                    sg += w * (double)in.bG[d] * o[d];
-                    sm += w * (double)in.bM[d] * o[d];
-                }
-                acc -= sg + En * sm;
-            }
-        }
-        // row r - p is complete: -i dt H c = (2a Im, -2a Re)
-        if (want_rhs && r >= PP) {
-            const unsigned at = (unsigned)(r - PP) * (unsigned)LS + (unsigned)col;
-            st_c(rs, at, cmk<FT>((FT)(2.0 * alpha * hacc[0].im), (FT)(-2.0 * alpha * hacc[0].re)));
-        }
-    };
-    RowIn cur = load_row(0);
-    for (int r = 0; r < L; ++r) {
-        RowIn nxt = load_row(r + 1);
-        stream_row(cur, r, true);
-        cur = nxt;
-    }
-    if (want_rhs) {
-#pragma unroll
-        for (int t = 0; t < PP; ++t) {
-            RowIn nxt = load_row(L + t + 1);
-            stream_row(cur, L + t, false);
-            cur = nxt;
-        }
-    }
-    obs_part[0] = nu;
-    obs_part[1] = dip;
-    obs_part[2] = acc;
-}
-
-// Pass A1: complex symmetric LDL^T of the chunk's rows in order (no
-// pivoting: the Hermitian part S of A_n is positive definite) with forward
-// substitution of the right-hand side.  Row r of A_n = S + i a (H0 + Ebar D)
-// enters a (p+1)-row window; pivot j = r - p leaves it.  Entries coupling
-// rows 0..p-1 to the left separator are the fill of pass A2.  Stores the
-// multipliers, 1/D_j and yhat_j of every interior pivot, and the Schur block
-// W and right-hand side yR of the chunk's separator rows.
-template <int PP, typename FT>
-__device__ void pass_elim(const SysDesc& sd, int k, const FT* __restrict__ band,
-                          const FT* __restrict__ rhs, FT* __restrict__ fac, FT* __restrict__ red,
-                          double alpha, double Ebar) {
-    constexpr int NM = kNumMats;
-    constexpr int IT = 2 * PP + 2;
-    const int L = sd.L, LS = sd.LS, P = sd.P;
-    int col = k + 1;
-    asm volatile("" : "+v"(col));
-    const int kk = col - 1;
-    const FT* __restrict__ bnd = band + sd.band_off;
-    const FT* __restrict__ rs = rhs + 2 * sd.state_off;
-    FT* __restrict__ fc = fac + 2 * sd.fac_off;
-    const unsigned rowstride = (unsigned)(NM * (PP + 1) * LS);
-    const unsigned fstride = (unsigned)(IT * P);
-    const FT a_f = (FT)alpha;
-    const FT eb_f = (FT)Ebar;
-
-    cplx<FT> W[PP + 1][PP + 1];  // lower triangle used: W[i][i2], i2 <= i
-    cplx<FT> y[PP + 1];
-#pragma unroll
-    for (int i = 0; i <= PP; ++i) {
-#pragma unroll
-        for (int i2 = 0; i2 <= PP; ++i2) W[i][i2] = cmk<FT>(0, 0);
-        y[i] = cmk<FT>(0, 0);
-    }
-    struct RowIn {
-        FT bS[PP + 1], bH[PP + 1], bD[PP + 1];
-        cplx<FT> b;
-    };
-    auto load_row = [&](int r) {
-        if (r >= L) r = L - 1;
-        const unsigned rb = (unsigned)r * rowstride + (unsigned)col;
-        RowIn in;
-#pragma unroll
-        for (int d = 0; d <= PP; ++d) {
-            in.bS[d] = bnd[rb + (unsigned)((0 * (PP + 1) + d) * LS)];
-            in.bH[d] = bnd[rb + (unsigned)((1 * (PP + 1) + d) * LS)];
-            in.bD[d] = bnd[rb + (unsigned)((2 * (PP + 1) + d) * LS)];
-        }
-        in.b = ld_c(rs, (unsigned)r * (unsigned)LS + (unsigned)col);
-        return in;
-    };
-    auto row = [&](const RowIn& in, int r, bool first_rows, bool elim) {
-        // insert row r as window slot PP: A[r][r-d] = S + i a (H0 + Ebar D)
-#pragma unroll
-        for (int d = 0; d <= PP; ++d) {
-            const cplx<FT> a = cmk<FT>(in.bS[d], a_f * (in.bH[d] + eb_f * in.bD[d]));
-            if (!first_rows || r - d >= 0) W[PP][PP - d] = a;
-        }
-        y[PP] = in.b;
-        if (elim) {
-            const int j = r - PP;
-            const cplx<FT> dinv = cinv_dev(W[0][0]);
-            cplx<FT> l[PP + 1];
-#pragma unroll
-            for (int i = 1; i <= PP; ++i) l[i] = cmul(W[i][0], dinv);
-#pragma unroll
-            for (int i = 1; i <= PP; ++i)
-#pragma unroll
-                for (int i2 = 1; i2 <= i; ++i2) W[i][i2] = cfms(W[i][i2], l[i], W[i2][0]);
-            const cplx<FT> yj = y[0];
-#pragma unroll
-            for (int i = 1; i <= PP; ++i) y[i] = cfms(y[i], l[i], yj);
-            const unsigned fb = (unsigned)j * fstride + (unsigned)kk;
-#pragma unroll
-            for (int i = 1; i <= PP; ++i) st_c(fc, fb + (unsigned)((i - 1) * P), l[i]);
-            st_c(fc, fb + (unsigned)(PP * P), dinv);
-            st_c(fc, fb + (unsigned)((PP + 1) * P), yj);
-        }
-        // shift the window by one row
-#pragma unroll
-        for (int i = 1; i <= PP; ++i) {
-#pragma unroll
-            for (int i2 = 1; i2 <= i; ++i2) W[i - 1][i2 - 1] = W[i][i2];
-            y[i - 1] = y[i];
-        }
-#pragma unroll
-        for (int i2 = 0; i2 <= PP; ++i2) W[PP][i2] = cmk<FT>(0, 0);
-        y[PP] = cmk<FT>(0, 0);
-    };
-    RowIn cur = load_row(0);
-#pragma unroll
-    for (int r = 0; r < PP; ++r) {
-        RowIn nxt = load_row(r + 1);
-        row(cur, r, true, false);
-        cur = nxt;
-    }
-    for (int r = PP; r < L; ++r) {
-        RowIn nxt = load_row(r + 1);
-        row(cur, r, false, true);
-        cur = nxt;
-    }
-    // the window now holds the chunk's separator rows m..L-1
-    FT* rb = red + 2 * (sd.red_off + (long long)k * RedLayout<FT>::chunk_block(PP));
-    const int pp = PP * PP;
-#pragma unroll
-    for (int i = 0; i < PP; ++i) {
-#pragma unroll
-        for (int i2 = 0; i2 <= i; ++i2) {
-            st_c(rb, (unsigned)(i * PP + i2), W[i][i2]);
-            st_c(rb, (unsigned)(i2 * PP + i), W[i][i2]);
-        }
-        st_c(rb, (unsigned)(3 * pp + i), y[i]);
-    }
-}
-
-// Pass A2: the fill of the chunk's rows towards the left separator,
-//   F = L^-1 A_{I,left}  (row j of F is stored with pivot j as f_j),
-// the separator rows' part of it (block F of the reduced system) and the
-// Schur update of the left separator,
-//   TL = -sum_j f_j^T (1/D_j) f_j,   gT = -sum_j f_j^T (1/D_j) yhat_j.
-// Only rows 0..p-1 couple to the left separator directly; the multipliers of
-// pass A1 carry the fill down the chunk.  With kTL == false the Schur update
-// is left to pass_schur (fewer live registers for FP64).
-template <int PP, typename FT, bool kTL>
-__device__ void pass_fill(const SysDesc& sd, int k, const FT* __restrict__ band, FT* __restrict__ fac,
-                          FT* __restrict__ red, double alpha, double Ebar) {
-    constexpr int NM = kNumMats;
-    constexpr int IT = 2 * PP + 2;
-    const int L = sd.L, LS = sd.LS, P = sd.P, m = sd.m;
-    int col = k + 1;
-    asm volatile("" : "+v"(col));
-    const int kk = col - 1;
-    const FT* __restrict__ bnd = band + sd.band_off;
-    FT* __restrict__ fc = fac + 2 * sd.fac_off;
-    const unsigned rowstride = (unsigned)(NM * (PP + 1) * LS);
-    const unsigned fstride = (unsigned)(IT * P);
-    const FT a_f = (FT)alpha;
-    const FT eb_f = (FT)Ebar;
-    auto fitem = [&](int j, int item) {
-        return ld_c(fc, (unsigned)j * fstride + (unsigned)(item * P) + (unsigned)kk);
-    };
-    cplx<FT> F[PP + 1][PP];
-    cplx<FT> TL[PP][PP];  // upper triangle used
-    cplx<FT> gT[PP];
-#pragma unroll
-    for (int i = 0; i <= PP; ++i)
-#pragma unroll
-        for (int t = 0; t < PP; ++t) F[i][t] = cmk<FT>(0, 0);
-#pragma unroll
-    for (int t = 0; t < PP; ++t) {
-        gT[t] = cmk<FT>(0, 0);
-#pragma unroll
-        for (int u = 0; u < PP; ++u) TL[t][u] = cmk<FT>(0, 0);
-    }
-    // rows 0..p-1: A[r][r-d] for r - d < 0 couples to left separator row
-    // t = r - d + p; after the r-th shift, row r sits in window slot r
-#pragma unroll
-    for (int r = 0; r < PP; ++r) {
-        const unsigned rb = (unsigned)r * rowstride + (unsigned)col;
-#pragma unroll
-        for (int d = r + 1; d <= PP; ++d) {
-            FT sv = bnd[rb + (unsigned)((0 * (PP + 1) + d) * LS)];
-            FT hv = bnd[rb + (unsigned)((1 * (PP + 1) + d) * LS)];
-            FT dv = bnd[rb + (unsigned)((2 * (PP + 1) + d) * LS)];
-            F[r][r - d + PP] = cmk<FT>(sv, a_f * (hv + eb_f * dv));
-        }
-    }
-    // pivots j = 0..m-1 leave the window from slot 0 (slot i is row j + i)
-    struct FRow {
-        cplx<FT> l[PP], dinv, yh;
-    };
-    auto load_frow = [&](int j) {
-        if (j > m - 1) j = m - 1;
-        FRow fr;
-#pragma unroll
-        for (int i = 0; i < PP; ++i) fr.l[i] = fitem(j, i);
-        if (kTL) {
-            fr.dinv = fitem(j, PP);
-            fr.yh = fitem(j, PP + 1);
-        }
-        return fr;
-    };
-    FRow cur = load_frow(0);
-    for (int j = 0; j < m; ++j) {
-        FRow nxt = load_frow(j + 1);
-        cplx<FT> f[PP];
-#pragma unroll
-        for (int t = 0; t < PP; ++t) f[t] = F[0][t];
-        const unsigned fb = (unsigned)j * fstride + (unsigned)kk;
-#pragma unroll
-        for (int t = 0; t < PP; ++t) st_c(fc, fb + (unsigned)((PP + 2 + t) * P), f[t]);
-#pragma unroll
-        for (int i = 1; i <= PP; ++i)
-#pragma unroll
-            for (int t = 0; t < PP; ++t) F[i][t] = cfms(F[i][t], cur.l[i - 1], f[t]);
-        if (kTL) {
-            cplx<FT> g[PP];
-#pragma unroll
-            for (int t = 0; t < PP; ++t) g[t] = cmul(f[t], cur.dinv);
-#pragma unroll
-            for (int t = 0; t < PP; ++t)
-#pragma unroll
-                for (int u = t; u < PP; ++u) TL[t][u] = cfms(TL[t][u], f[t], g[u]);
-#pragma unroll
-            for (int t = 0; t < PP; ++t) gT[t] = cfms(gT[t], g[t], cur.yh);
-        }
-        // shift the window by one row
-#pragma unroll
-        for (int i = 1; i <= PP; ++i)
-#pragma unroll
-            for (int t = 0; t < PP; ++t) F[i - 1][t] = F[i][t];
-#pragma unroll
-        for (int t = 0; t < PP; ++t) F[PP][t] = cmk<FT>(0, 0);
-        cur = nxt;
-    }
-    FT* rb = red + 2 * (sd.red_off + (long long)k * RedLayout<FT>::chunk_block(PP));
-    const int pp = PP * PP;
-#pragma unroll
-    for (int i = 0; i < PP; ++i) {
-#pragma unroll
-        for (int t = 0; t < PP; ++t) st_c(rb, (unsigned)(pp + i * PP + t), F[i][t]);
-        if (kTL) {
-#pragma unroll
-            for (int u = i; u < PP; ++u) {
-                st_c(rb, (unsigned)(2 * pp + i * PP + u), TL[i][u]);
-                st_c(rb, (unsigned)(2 * pp + u * PP + i), TL[i][u]);
-            }
-            st_c(rb, (unsigned)(3 * pp + PP + i), gT[i]);
-        }
-    }
-}
-
-// Pass A3 (used when pass_fill runs without the Schur update): TL and gT of
-// the left separator from the stored fill rows.
-template <int PP, typename FT>
-__device__ void pass_schur(const SysDesc& sd, int k, const FT* __restrict__ fac, FT* __restrict__ red) {
-    constexpr int IT = 2 * PP + 2;
-    const int P = sd.P, m = sd.m;
-    int col = k + 1;
-    asm volatile("" : "+v"(col));
-    const int kk = col - 1;
-    const FT* __restrict__ fc = fac + 2 * sd.fac_off;
-    const unsigned fstride = (unsigned)(IT * P);
-    auto fitem = [&](int j, int item) {
-        return ld_c(fc, (unsigned)j * fstride + (unsigned)(item * P) + (unsigned)kk);
-    };
-    cplx<FT> TL[PP][PP];
-    cplx<FT> gT[PP];
-#pragma unroll
-    for (int t = 0; t < PP; ++t) {
-        gT[t] = cmk<FT>(0, 0);
-#pragma unroll
-        for (int u = 0; u < PP; ++u) TL[t][u] = cmk<FT>(0, 0);
-    }
-    struct FRow {
-        cplx<FT> f[PP], dinv, yh;
-    };
-    auto load_frow = [&](int j) {
-        if (j > m - 1) j = m - 1;
-        FRow fr;
-#pragma unroll
-        for (int t = 0; t < PP; ++t) fr.f[t] = fitem(j, PP + 2 + t);
-        fr.dinv = fitem(j, PP);
-        fr.yh = fitem(j, PP + 1);
-        return fr;
-    };
-    FRow cur = load_frow(0);
-    for (int j = 0; j < m; ++j) {
-        FRow nxt = load_frow(j + 1);
-        cplx<FT> g[PP];
-#pragma unroll
-        for (int t = 0; t < PP; ++t) g[t] = cmul(cur.f[t], cur.dinv);
-#pragma unroll
-        for (int t = 0; t < PP; ++t)
-#pragma unroll
-            for (int u = t; u < PP; ++u) TL[t][u] = cfms(TL[t][u], cur.f[t], g[u]);
-#pragma unroll
-        for (int t = 0; t < PP; ++t) gT[t] = cfms(gT[t], g[t], cur.yh);
-        cur = nxt;
-    }
-    FT* rb = red + 2 * (sd.red_off + (long long)k * RedLayout<FT>::chunk_block(PP));
-    const int pp = PP * PP;
-#pragma unroll
-    for (int i = 0; i < PP; ++i) {
-#pragma unroll
-        for (int u = i; u < PP; ++u) {
-            st_c(rb, (unsigned)(2 * pp + i * PP + u), TL[i][u]);
-            st_c(rb, (unsigned)(2 * pp + u * PP + i), TL[i][u]);
-        }
-        st_c(rb, (unsigned)(3 * pp + PP + i), gT[i]);
-    }
-}
-
-// Pass R: block tridiagonal solve over the P separators (block size p).
-//   Sigma_s = W_s + TL_{s+1},  coupling T[s][s-1] = F_s,  g_s = yR_s + gT_{s+1}
-//   Delta_0 = Sigma_0,  M_s = F_s Delta_{s-1}^-1,  Delta_s = Sigma_s - M_s F_s^T
-//   z_0 = g_0,  z_s = g_s - M_s z_{s-1}
-//   x_{P-1} = Delta_{P-1}^-1 z_{P-1},  x_s = Delta_s^-1 (z_s - F_{s+1}^T x_{s+1})
-// Entry-parallel over one wave: lane 8i + j holds entry (i, j) of an 8 x 8
-// block (p <= 7; padding rows and columns are identity / zero).  Products
-// and the Gauss-Jordan inverse exchange entries with wave shuffles, so the
-// chain has no LDS round trips or barriers.  Vectors are held either in row
-// layout (lane (i, j) holds v[i]) or in column layout (lane (i, j) holds
-// v[j]).  With factor == false the block factors Delta_s^-1 and M_s stored by
-// an earlier call are reused (a further solve with the same matrix).
-
-template <typename FT>
-__device__ inline cplx<FT> shfl_c(cplx<FT> v, int src) {
-    return cplx<FT>{__shfl(v.re, src, 64), __shfl(v.im, src, 64)};
-}
-template <typename FT>
-__device__ inline cplx<FT> shfl_xor_c(cplx<FT> v, int m) {
-    return cplx<FT>{__shfl_xor(v.re, m, 64), __shfl_xor(v.im, m, 64)};
-}
-// sums over the 8 lanes of a row group (j) / of a column group (i)
-template <typename FT>
-__device__ inline cplx<FT> row_sum(cplx<FT> v) {
-    v = cadd(v, shfl_xor_c(v, 1));
-    v = cadd(v, shfl_xor_c(v, 2));
-    return cadd(v, shfl_xor_c(v, 4));
-}
-template <typename FT>
-__device__ inline cplx<FT> col_sum(cplx<FT> v) {
-    v = cadd(v, shfl_xor_c(v, 8));
-    v = cadd(v, shfl_xor_c(v, 16));
-    return cadd(v, shfl_xor_c(v, 32));
-}
-
-template <int PP, typename FT>
-__device__ void pass_reduced(const SysDesc& sd, int lane, FT* __restrict__ red, bool factor) {
-    constexpr int p = PP;
-    const int P = sd.P;
-    const long long cb = RedLayout<FT>::chunk_block(p);
-    FT* rbase = red + 2 * sd.red_off;
-    FT* dinv_base = rbase + 2 * RedLayout<FT>::dinv(p, P);
-    FT* m_base = rbase + 2 * RedLayout<FT>::mblk(p, P);
-    FT* z_base = rbase + 2 * RedLayout<FT>::zvec(p, P);
-    FT* x_base = rbase + 2 * RedLayout<FT>::xvec(p, P);
-    const int i = lane >> 3, j = lane & 7;
-    const bool valid = (i < p) && (j < p);
-    constexpr unsigned pp = (unsigned)(p * p);
-    const unsigned eij = (unsigned)(i * p + j);
-    const cplx<FT> zero = cmk<FT>(0, 0);
-    const cplx<FT> ident = cmk<FT>(i == j ? (FT)1 : (FT)0, 0);
-    auto blk = [&](int s) { return rbase + 2 * ((long long)s * cb); };
-
-    // the inputs of block s, loaded one block ahead of their use
-    struct Fwd {
-        cplx<FT> g, a, f;
-    };
-    auto load_fwd = [&](int s) {
-        Fwd r{zero, ident, zero};
-        if (s >= P) return r;
-        const FT* bs = blk(s);
-        if (i < p) {
-            r.g = ld_c(bs, 3 * pp + (unsigned)i);
-            if (s + 1 < P) r.g = cadd(r.g, ld_c(blk(s + 1), 3 * pp + (unsigned)p + (unsigned)i));
-        }
-        if (valid) {
-            if (factor) {
-                r.a = ld_c(bs, eij);
-                if (s + 1 < P) r.a = cadd(r.a, ld_c(blk(s + 1), 2 * pp + eij));
-                r.f = ld_c(bs, pp + eij);
-            } else if (s >= 1) {
-                r.f = ld_c(m_base, (unsigned)s * pp + eij);  // stored M_s
-            }
-        }
-        return r;
-    };
-
-    // forward sweep
-    cplx<FT> dprev = zero;  // Delta_{s-1}^-1 entry
-    cplx<FT> zc = zero;     // z_{s-1} in column layout
-    Fwd cur = load_fwd(0);
-    for (int s = 0; s < P; ++s) {
-        Fwd nxt = load_fwd(s + 1);
-        cplx<FT> mm = zero;
-        if (factor) {
-            cplx<FT> a = cur.a;
-            if (s >= 1) {
-                cplx<FT> fr[p], dc[p];
-#pragma unroll
-                for (int l = 0; l < p; ++l) {
-                    fr[l] = shfl_c(cur.f, 8 * i + l);
-                    dc[l] = shfl_c(dprev, 8 * l + j);
-                }
-#pragma unroll
-                for (int l = 0; l < p; ++l) mm = cfma(mm, fr[l], dc[l]);
-                cplx<FT> mr[p], fc2[p];
-#pragma unroll
-                for (int l = 0; l < p; ++l) {
-                    mr[l] = shfl_c(mm, 8 * i + l);
-                    fc2[l] = shfl_c(cur.f, 8 * j + l);
-                }
-#pragma unroll
-                for (int l = 0; l < p; ++l) a = cfms(a, mr[l], fc2[l]);
-                if (valid) st_c(m_base, (unsigned)s * pp + eij, mm);
-            }
-            // Gauss-Jordan inverse of the (identity padded) block, no pivoting
-#pragma unroll
-            for (int q = 0; q < p; ++q) {
-                const cplx<FT> aiq = shfl_c(a, 8 * i + q);
-                const cplx<FT> aqj = shfl_c(a, 8 * q + j);
-                const cplx<FT> piv = cinv_dev(bcast_c(a, 9 * q));
-                const cplx<FT> t = cmul(aiq, piv);
-                const cplx<FT> rowq = csel(j == q, piv, cmul(aqj, piv));
-                const cplx<FT> other = csel(j == q, cmk<FT>(-t.re, -t.im), cfms(a, t, aqj));
-                a = csel(i == q, rowq, other);
-            }
-            if (valid) st_c(dinv_base, (unsigned)s * pp + eij, a);
-            dprev = a;
-        } else {
-            mm = cur.f;
-        }
-        cplx<FT> zr = csub(cur.g, row_sum(cmul(mm, zc)));
-        if (j == 0 && i < p) st_c(z_base, (unsigned)(s * p + i), zr);
-        zc = shfl_c(zr, 8 * j);
-        cur = nxt;
-    }
-    __syncthreads();  // z_s written by other lanes
-    // backward sweep
-    struct Bwd {
-        cplx<FT> dv, fn, zs;
-    };
-    auto load_bwd = [&](int s) {
-        Bwd r{ident, zero, zero};
-        if (s < 0) return r;
-        if (valid) {
-            r.dv = ld_c(dinv_base, (unsigned)s * pp + eij);
-            if (s + 1 < P) r.fn = ld_c(blk(s + 1), pp + eij);
-        }
-        if (j < p) r.zs = ld_c(z_base, (unsigned)(s * p + j));
-        return r;
-    };
-    cplx<FT> xr = zero;  // x_{s+1} in row layout
-    Bwd bc = load_bwd(P - 1);
-    for (int s = P - 1; s >= 0; --s) {
-        Bwd bn = load_bwd(s - 1);
-        cplx<FT> w = csub(bc.zs, col_sum(cmul(bc.fn, xr)));
-        xr = row_sum(cmul(bc.dv, w));
-        if (j == 0 && i < p) st_c(x_base, (unsigned)(s * p + i), xr);
-        bc = bn;
-    }
-}
-
-// Pass B: interior values of the chunk from its separator values.
-//   x_I = L^-T D^-1 (yhat - F x_left - L^-1 A_{I,right} x_right)
-// The fill rows make the left-separator term a dot product per row; the
-// right-separator term reaches only the last p pivots (a p-row forward
-// substitution).  The state gets the increment; with dtot != nullptr the
-// increment is also written (first == true) or added to dtot.
-template <int PP, typename FT>
-__device__ void pass_backsub(const SysDesc& sd, int k, const FT* __restrict__ band,
-                             double* __restrict__ st, double* __restrict__ dtot, bool first,
-                             const FT* __restrict__ fac, const FT* __restrict__ red, double alpha,
-                             double Ebar) {
-    constexpr int NM = kNumMats;
-    constexpr int IT = 2 * PP + 2;
-    const int LS = sd.LS, P = sd.P, m = sd.m;
-    int col = k + 1;
-    asm volatile("" : "+v"(col));
-    const int kk = col - 1;
-    const FT* __restrict__ bnd = band + sd.band_off;
-    double* __restrict__ cst = st + 2 * sd.state_off;
-    double* __restrict__ dst = dtot ? dtot + 2 * sd.state_off : nullptr;
-    const FT* __restrict__ fc = fac + 2 * sd.fac_off;
-    const unsigned rowstride = (unsigned)(NM * (PP + 1) * LS);
-    const unsigned fstride = (unsigned)(IT * P);
-    const FT* x_base = red + 2 * (sd.red_off + RedLayout<FT>::xvec(PP, P));
-    const FT a_f = (FT)alpha;
-    const FT eb_f = (FT)Ebar;
-    cplx<FT> xl[PP], xr[PP];
-#pragma unroll
-    for (int t = 0; t < PP; ++t) {
-        xl[t] = kk >= 1 ? ld_c(x_base, (unsigned)((kk - 1) * PP + t)) : cmk<FT>(0, 0);
-        xr[t] = ld_c(x_base, (unsigned)(kk * PP + t));
-    }
-    auto Aentry = [&](int lrow, int d) {
-        const unsigned rb = (unsigned)lrow * rowstride + (unsigned)col;
-        FT s = bnd[rb + (unsigned)((0 * (PP + 1) + d) * LS)];
-        FT h = bnd[rb + (unsigned)((1 * (PP + 1) + d) * LS)];
-        FT dd = bnd[rb + (unsigned)((2 * (PP + 1) + d) * LS)];
-        return cmk<FT>(s, a_f * (h + eb_f * dd));
-    };
-    auto fitem = [&](int j, int item) {
-        return ld_c(fc, (unsigned)j * fstride + (unsigned)(item * P) + (unsigned)kk);
-    };
-    auto update = [&](int lrow, cplx<FT> x) {
-        const unsigned at = (unsigned)lrow * (unsigned)LS + (unsigned)col;
-        cst[2 * at] += (double)x.re;
-        cst[2 * at + 1] += (double)x.im;
-        if (dst) {
-            if (first) {
-                dst[2 * at] = (double)x.re;
-                dst[2 * at + 1] = (double)x.im;
-            } else {
-                dst[2 * at] += (double)x.re;
-                dst[2 * at + 1] += (double)x.im;
-            }
-        }
-    };
-    // u = L^-1 A_{I,right} x_right on pivots m-p+q, q = 0..p-1
-    cplx<FT> ur[PP];
-#pragma unroll
-    for (int q = 0; q < PP; ++q) {
-        const int j = m - PP + q;
-        cplx<FT> u = cmk<FT>(0, 0);
-        // A[j][m+t] is band row m+t, diagonal p+t-q (<= p for t <= q)
-#pragma unroll
-        for (int t = 0; t <= q; ++t) u = cfma(u, Aentry(m + t, PP + t - q), xr[t]);
-        // L[j][i] for pivots i = m-p..j-1 is item j-i-1 of pivot i
-#pragma unroll
-        for (int q2 = 0; q2 < q; ++q2) u = cfms(u, fitem(m - PP + q2, q - q2 - 1), ur[q2]);
-        ur[q] = u;
-    }
-    // back substitution over the interior pivots, window of the next p
-    // values; each pivot's factor row is loaded one pivot ahead
-    struct FRow {
-        cplx<FT> it[IT];  // items 0..p-1 l, p dinv, p+1 yhat, p+2..2p+1 f
-    };
-    auto load_frow = [&](int j) {
-        // j = -1 (after the last pivot) reloads pivot 0; the row is not used
-        const int jj = j < 0 ? 0 : j;
-        FRow r;
-#pragma unroll
-        for (int it = 0; it < IT; ++it) r.it[it] = fitem(jj, it);
-        return r;
-    };
-    cplx<FT> xw[PP + 1];
-#pragma unroll
-    for (int t = 0; t <= PP; ++t) xw[t] = cmk<FT>(0, 0);
-    auto back_row = [&](int j, const FRow& fr, cplx<FT> ucorr) {
-        cplx<FT> yh = csub(fr.it[PP + 1], ucorr);
-#pragma unroll
-        for (int t = 0; t < PP; ++t) yh = cfms(yh, fr.it[PP + 2 + t], xl[t]);
-        cplx<FT> xj = cmul(fr.it[PP], yh);
-#pragma unroll
-        for (int i = 1; i <= PP; ++i) xj = cfms(xj, fr.it[i - 1], xw[i]);
-#pragma unroll
-        for (int i = PP; i >= 2; --i) xw[i] = xw[i - 1];
-        xw[1] = xj;
-        update(j, xj);
-    };
-    FRow cur = load_frow(m - 1);
-#pragma unroll
-    for (int q = PP - 1; q >= 0; --q) {
-        FRow nxt = load_frow(m - PP + q - 1);
-        back_row(m - PP + q, cur, ur[q]);
-        cur = nxt;
-    }
-    for (int j = m - PP - 1; j >= 0; --j) {
-        FRow nxt = load_frow(j - 1);
-        back_row(j, cur, cmk<FT>(0, 0));
-        cur = nxt;
-    }
-#pragma unroll
-    for (int t = 0; t < PP; ++t) update(m + t, xr[t]);
-}
-
-// Pass C (refinement sweep): residual of the current iterate in FP64,
-//   r = B c_n - A c = -S dtot - i a H (2 c - dtot),   dtot = c - c_n,
-// from the FP64 bands S, H0, D (so the sweeps converge to the FP64
-// Crank-Nicolson step), then forward substitution with the stored factor
-// rows (yhat, and the chunk's separator right-hand sides yR, gT).
-template <int PP, typename FT>
-__device__ void pass_residual(const SysDesc& sd, int k, const FT* __restrict__ band,
-                              const double* __restrict__ band64, const double* __restrict__ st,
-                              const double* __restrict__ dtot, FT* __restrict__ fac,
-                              FT* __restrict__ red, double alpha, double Ebar) {
-    constexpr int NM = kNumMats;
-    constexpr int IT = 2 * PP + 2;
-    const int L = sd.L, LS = sd.LS, P = sd.P;
-    int col = k + 1;
-    asm volatile("" : "+v"(col));
-    const int kk = col - 1;
-    const FT* __restrict__ bnd = band + sd.band_off;
-    const double* __restrict__ bnd64 = band64 + sd.band_off;
-    const double* __restrict__ cst = st + 2 * sd.state_off;
-    const double* __restrict__ dst = dtot + 2 * sd.state_off;
-    FT* __restrict__ fc = fac + 2 * sd.fac_off;
-    const unsigned rowstride = (unsigned)(NM * (PP + 1) * LS);
-    const unsigned fstride = (unsigned)(IT * P);
-    auto fitem = [&](int j, int item) {
-        return ld_c(fc, (unsigned)j * fstride + (unsigned)(item * P) + (unsigned)kk);
-    };
-    // windows of v = 2c - dtot and of dtot: slot PP is the newest row
-    cplx<double> vw[PP + 1], dw[PP + 1], hacc[PP + 1], sacc[PP + 1];
-    cplx<FT> y[PP + 1];
-    cplx<FT> gT[PP];
-#pragma unroll
-    for (int i = 0; i <= PP; ++i) {
-        hacc[i] = cmk<double>(0, 0);
-        sacc[i] = cmk<double>(0, 0);
-        y[i] = cmk<FT>(0, 0);
-    }
-#pragma unroll
-    for (int t = 0; t < PP; ++t) gT[t] = cmk<FT>(0, 0);
-    vw[0] = dw[0] = cmk<double>(0, 0);
-#pragma unroll
-    for (int d = 0; d < PP; ++d) {
-        unsigned at = (unsigned)(L - PP + d) * (unsigned)LS + (unsigned)(col - 1);
-        cplx<double> c = cmk<double>(cst[2 * at], cst[2 * at + 1]);
-        cplx<double> dd = cmk<double>(dst[2 * at], dst[2 * at + 1]);
-        dw[d + 1] = dd;
-        vw[d + 1] = cmk<double>(2.0 * c.re - dd.re, 2.0 * c.im - dd.im);
-    }
-    // streamed row r (0 <= r < L + p; rows >= L are the next chunk's halo),
-    // loaded one row ahead of its use
-    struct RowIn {
-        double bS[PP + 1], bH[PP + 1], bD[PP + 1];
-        cplx<double> c, dd;
-    };
-    auto load_row = [&](int r) {
-        if (r >= L + PP) r = L + PP - 1;  // past the end: reload the last row (unused)
-        const bool own = r < L;
-        const int lr = own ? r : r - L;
-        const unsigned cc = (unsigned)(own ? col : col + 1);
-        const unsigned rb = (unsigned)lr * rowstride + cc;
-        RowIn in;
-#pragma unroll
-        for (int d = 0; d <= PP; ++d) {
-            in.bS[d] = bnd64[rb + (unsigned)((0 * (PP + 1) + d) * LS)];
-            in.bH[d] = bnd64[rb + (unsigned)((1 * (PP + 1) + d) * LS)];
-            in.bD[d] = bnd64[rb + (unsigned)((2 * (PP + 1) + d) * LS)];
-        }
-        const unsigned sat = (unsigned)lr * (unsigned)LS + cc;
-        in.c = cmk<double>(cst[2 * sat], cst[2 * sat + 1]);
-        in.dd = cmk<double>(dst[2 * sat], dst[2 * sat + 1]);
-        return in;
-    };
-    auto stream_row = [&](const RowIn& in, bool own) {
-        double h[PP + 1];
-#pragma unroll
-        for (int d = 0; d <= PP; ++d) h[d] = in.bH[d] + Ebar * in.bD[d];
-#pragma unroll
-        for (int d = 0; d < PP; ++d) {
-            vw[d] = vw[d + 1];
-            dw[d] = dw[d + 1];
-            hacc[d] = hacc[d + 1];
-            sacc[d] = sacc[d + 1];
-        }
-        dw[PP] = in.dd;
-        vw[PP] = cmk<double>(2.0 * in.c.re - in.dd.re, 2.0 * in.c.im - in.dd.im);
-        cplx<double> hs = cmk<double>(0, 0), ss = cmk<double>(0, 0);
-        if (own) {
-#pragma unroll
-            for (int d = 0; d <= PP; ++d) {
-                hs.re += h[d] * vw[PP - d].re;
-                hs.im += h[d] * vw[PP - d].im;
-                ss.re += in.bS[d] * dw[PP - d].re;
-                ss.im += in.bS[d] * dw[PP - d].im;
-            }
-        }
-        hacc[PP] = hs;
-        sacc[PP] = ss;
-#pragma unroll
-        for (int d = 1; d <= PP; ++d) {
-            hacc[PP - d].re += h[d] * vw[PP].re;
-            hacc[PP - d].im += h[d] * vw[PP].im;
-            sacc[PP - d].re += in.bS[d] * dw[PP].re;
-            sacc[PP - d].im += in.bS[d] * dw[PP].im;
-        }
-        // completed residual of row r - p: -S dtot - i a H v
-        return cmk<FT>((FT)(-sacc[0].re + alpha * hacc[0].im), (FT)(-sacc[0].im - alpha * hacc[0].re));
-    };
-    auto shift_y = [&]() {
-#pragma unroll
-        for (int i = 1; i <= PP; ++i) y[i - 1] = y[i];
-        y[PP] = cmk<FT>(0, 0);
-    };
-    // factor row of pivot j (l, dinv, f), loaded one pivot ahead
-    struct FRow {
-        cplx<FT> l[PP], dinv, f[PP];
-    };
-    auto load_frow = [&](int j) {
-        if (j > sd.m - 1) j = sd.m - 1;
-        FRow fr;
-#pragma unroll
-        for (int i = 0; i < PP; ++i) fr.l[i] = fitem(j, i);
-        fr.dinv = fitem(j, PP);
-#pragma unroll
-        for (int t = 0; t < PP; ++t) fr.f[t] = fitem(j, PP + 2 + t);
-        return fr;
-    };
-    RowIn cur = load_row(0);
-#pragma unroll
-    for (int r = 0; r < PP; ++r) {
-        RowIn nxt = load_row(r + 1);
-        (void)stream_row(cur, true);
-        shift_y();
-        cur = nxt;
-    }
-    FRow fcur = load_frow(0);
-    for (int r = PP; r < L; ++r) {
-        RowIn nxt = load_row(r + 1);
-        FRow fnxt = load_frow(r - PP + 1);
-        const int j = r - PP;
-        cplx<FT> yj = cadd(y[0], stream_row(cur, true));
-        const unsigned fb = (unsigned)j * fstride + (unsigned)kk;
-        st_c(fc, fb + (unsigned)((PP + 1) * P), yj);
-#pragma unroll
-        for (int i = 1; i <= PP; ++i) y[i] = cfms(y[i], fcur.l[i - 1], yj);
-#pragma unroll
-        for (int t = 0; t < PP; ++t) gT[t] = cfms(gT[t], cmul(fcur.f[t], fcur.dinv), yj);
-        shift_y();
-        cur = nxt;
-        fcur = fnxt;
-    }
-#pragma unroll
-    for (int t = 0; t < PP; ++t) {
-        RowIn nxt = load_row(L + t + 1);
-        y[t] = cadd(y[t], stream_row(cur, false));
-        cur = nxt;
-    }
-    FT* rb = red + 2 * (sd.red_off + (long long)k * RedLayout<FT>::chunk_block(PP));
-    const int pp = PP * PP;
-#pragma unroll
-    for (int i = 0; i < PP; ++i) {
-        st_c(rb, (unsigned)(3 * pp + i), y[i]);
-        st_c(rb, (unsigned)(3 * pp + PP + i), gT[i]);
-    }
-}
-
-__device__ inline void latch(int* status, int code, int sys, int step) {
-    if (atomicCAS(&status[0], 0, code) == 0) {
-        status[1] = sys;
-        status[2] = step;
-    }
-}
-
-struct KernelArgs {
-    const SysDesc* descs;
-    const void* band;          // FT bands (factorisation, solve, right-hand side)
-    const double* band64;      // FP64 bands (S of the refinement residual)
-    double* st;
-    double* dtot;              // increment of the current step (refinement only)
-    void* rhs;                 // right-hand side of the step (FT, state layout)
-    void* fac;
-    void* red;
-    const double* E;
-    double* obs;
-    unsigned mask;
-    int refine;
-    double norm_tol;
-    int* status;
-    unsigned long long* prof;
-};
 
 template <int PP, typename FT>
 __device__ void run_system(const KernelArgs& ka, const SysDesc& sd, int sidx) {

@@ -56,6 +56,7 @@ def lib():
         "tdsez_batch_set": [vp, ctypes.c_char_p, d],
         "tdsez_propagate_batched": [vp, vp, lp, vp, lp, dp, ip, i, u, vp, lp, vp],
         "tdsez_propagate": [vp, vp, vp, d, i, i, u, vp, vp],
+        "tdsez_adjoint_batched": [vp, vp, lp, vp, lp, dp, ip, i, u, vp, lp, vp, vp, i, vp],
         "tdsez_batch_status": [vp, vp, ip, ip],
         "tdsez_batch_profile": [vp, vp, dp],
         "tdsez_system_status": [vp, vp, ip],
@@ -234,6 +235,82 @@ def propagate_batched(batch, psi_packed, psi_off, E_packed, E_off, dt, nsteps, p
                                          ctypes.c_void_p(E_packed.data_ptr()), ep, _dptr(dtv),
                                          ns.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), int(prec), int(obs),
                                          optr, op_, _stream_handle(stream)))
+
+
+def adjoint_batched(batch, psi0_packed, psi_off, E_packed, E_off, dt, nsteps, obs, dJdobs_packed, obs_off,
+                    dJdE_packed, dJdpsi0_packed=None, ckpt_stride=0, prec=FP64, stream=None):
+    """Discrete-adjoint gradient of J(observable series): fills dJdE_packed
+    (device float64, E layout) and optionally dJdpsi0_packed (device
+    complex128, psi layout) from dJdobs_packed (device float64, obs layout)."""
+    import torch
+    _check_dev(psi0_packed, torch.complex128)
+    _check_dev(E_packed, torch.float64)
+    _check_dev(dJdobs_packed, torch.float64)
+    _check_dev(dJdE_packed, torch.float64)
+    if dJdpsi0_packed is not None:
+        _check_dev(dJdpsi0_packed, torch.complex128)
+    n = len(batch.systems)
+    po, pp = _longs(psi_off)
+    eo, ep = _longs(E_off)
+    oo, op_ = _longs(obs_off)
+    dtv = _f64(dt)
+    ns = np.ascontiguousarray(nsteps, dtype=np.int32)
+    if len(po) != n or len(eo) != n or len(oo) != n or len(dtv) != n or len(ns) != n:
+        raise TdsezError(1, "per-system arrays must have one entry per system")
+    _check(lib().tdsez_adjoint_batched(batch.handle, ctypes.c_void_p(psi0_packed.data_ptr()), pp,
+                                       ctypes.c_void_p(E_packed.data_ptr()), ep, _dptr(dtv),
+                                       ns.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), int(prec), int(obs),
+                                       ctypes.c_void_p(dJdobs_packed.data_ptr()), op_,
+                                       ctypes.c_void_p(dJdE_packed.data_ptr()),
+                                       None if dJdpsi0_packed is None else ctypes.c_void_p(dJdpsi0_packed.data_ptr()),
+                                       int(ckpt_stride), _stream_handle(stream)))
+
+
+def _series_function():
+    import torch
+
+    class ObservableSeries(torch.autograd.Function):
+        """E samples (device float64, packed) -> observable series (device
+        float64, packed [n*3 + (nu, d, a)]) of a batch propagated from fixed
+        initial states; backward runs tdsez_adjoint_batched (FP64)."""
+
+        @staticmethod
+        def forward(ctx, E_packed, batch, psi0_packed, psi_off, E_off, dt, nsteps, obs_off, obs, prec, ckpt_stride):
+            psi = psi0_packed.clone()
+            total = max(int(o) + 3 * (int(k) + 1) for o, k in zip(obs_off, nsteps))
+            series = torch.zeros(total, dtype=torch.float64, device=E_packed.device)
+            propagate_batched(batch, psi, psi_off, E_packed.detach().contiguous(), E_off, dt, nsteps, prec, obs,
+                              series, obs_off)
+            batch_status(batch)
+            ctx.save_for_backward(E_packed.detach(), psi0_packed)
+            ctx.args = (batch, psi_off, E_off, dt, nsteps, obs_off, obs, ckpt_stride)
+            return series
+
+        @staticmethod
+        def backward(ctx, grad_series):
+            E_packed, psi0_packed = ctx.saved_tensors
+            batch, psi_off, E_off, dt, nsteps, obs_off, obs, ckpt_stride = ctx.args
+            dJdE = torch.zeros_like(E_packed)
+            adjoint_batched(batch, psi0_packed, psi_off, E_packed.contiguous(), E_off, dt, nsteps, obs,
+                            grad_series.contiguous(), obs_off, dJdE, None, ckpt_stride, FP64)
+            batch_status(batch)
+            return dJdE, None, None, None, None, None, None, None, None, None, None
+
+    return ObservableSeries
+
+
+_OBS_FN = None
+
+
+def observable_series(E_packed, batch, psi0_packed, psi_off, E_off, dt, nsteps, obs_off, obs=OBS_ALL, prec=FP64,
+                      ckpt_stride=0):
+    """Differentiable propagation: returns the packed observable series as a
+    torch tensor whose gradient with respect to E_packed comes from the
+    discrete adjoint (tdsez_adjoint_batched)."""
+    global _OBS_FN
+    if _OBS_FN is None:
+        _OBS_FN = _series_function()
+    return _OBS_FN.apply(E_packed, batch, psi0_packed, psi_off, E_off, dt, nsteps, obs_off, obs, prec, ckpt_stride)
 
 
 def propagate(sys, psi, E, dt, nsteps, prec=FP64, obs=OBS_ALL, obs_out=None, stream=None):

@@ -241,6 +241,43 @@ def config3(nsys=1024, seed=0):
     return out
 
 
+def config5(nsys=64, N=1500, nsteps=20000, ntheta=64, seed=1, wb_nm=4.0):
+    """Batch for the pulse-gradient workload: config2 double quantum wells
+    (all systems share the geometry) driven by Fourier pulses
+    E(t) = sum_j theta_j sin(j pi t / Tp), j = 1..ntheta.  theta is the least
+    squares fit of the config2 sin^2 pulse, times (1 + 0.1 g) with g standard
+    normal from default_rng(seed), drawn per system in order.  Returns
+    (systems, thetas, basis); each system's E is its own pulse."""
+    base = config2(wb_nm=wb_nm, N=N, nsteps=nsteps)
+    Tp = base.meta["Tp"]
+    _, basis = fourier_pulse(np.zeros(ntheta), Tp, base.dt, base.nsteps)
+    theta0 = np.linalg.lstsq(basis, base.E[: base.nsteps + 1], rcond=None)[0]
+    rng = np.random.default_rng(seed)
+    systems, thetas = [], []
+    for s in range(nsys):
+        th = theta0 * (1.0 + 0.1 * rng.standard_normal(ntheta))
+        E = basis @ th
+        systems.append(System("dqw-grad-%d" % s, base.breaks, base.order, base.minv, base.V, base.dV, base.nq, E,
+                              base.dt, base.nsteps, False, dict(base.meta)))
+        thetas.append(th)
+    return systems, np.array(thetas), basis
+
+
+def harmonic_yield(d, dt, omega, qmin=15, qmax=35):
+    """J = sum over DFT frequencies w_q in [qmin w, qmax w] of w_q^4 |X(w_q)|^2,
+    X(w) = sum_n W_n d_n exp(i w t_n) dt with a Hann window W over the series
+    and the DFT grid zero-padded to 2^ceil(log2(4 (n+1))) points.  d: torch
+    tensor (any device, float64); differentiable."""
+    import torch
+    n1 = d.shape[-1]
+    nfft = 1 << int(math.ceil(math.log2(4 * n1)))
+    win = torch.hann_window(n1, periodic=False, dtype=d.dtype, device=d.device)
+    X = torch.fft.fft(win * d, n=nfft) * dt
+    w = 2.0 * math.pi * torch.fft.fftfreq(nfft, d=dt, device=d.device).to(d.dtype)
+    sel = (w >= qmin * omega) & (w <= qmax * omega)
+    return torch.sum(w[sel] ** 4 * (X[..., sel].abs() ** 2), dim=-1)
+
+
 def driven_ho(E0=0.1, dt=0.01, tmax=10.0, L=12.0, nel=200, order=8):
     """1D reduction of Appendix A: m = w = 1, E(t) = E0 sin t, from t = 0."""
     V, dV = harmonic(1.0)
