@@ -225,11 +225,13 @@ tdsez_status tdsez_adjoint_batched(tdsez_batch b, const double* psi0_packed, con
                                    double* dJdpsi0_packed, int ckpt_stride, void* stream);
 
 /* Phase profile of the last propagation of a profiled batch (see
- * tdsez_batch_set "profile").  Synchronises `stream`; out[5*s + 0..4] =
- * average shader-clock cycles per time step spent by system s in the
- * factorisation sweep, the separator (reduced) solve, the back-
- * substitution sweep and the refinement sweeps, and the partition count
- * used for it.  EINVAL when profiling is off. */
+ * tdsez_batch_set "profile").  Synchronises `stream`; out[9*s + 0..8] =
+ * average shader-clock cycles per time step spent by system s in: the
+ * right-hand-side/observables pass, the elimination pass, the fill pass, the
+ * separator (reduced) solve, the back substitution, and summed over the
+ * refinement sweeps their residual pass, separator solve and back
+ * substitution; then the partition count.  Profiling adds a barrier per
+ * phase.  EINVAL when profiling is off. */
 tdsez_status tdsez_batch_profile(tdsez_batch b, void* stream, double* out);
 
 /* Synchronise `stream`, then return and clear the first device-side failure

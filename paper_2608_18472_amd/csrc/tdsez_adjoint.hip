@@ -53,8 +53,7 @@ struct AdjArgs {
 // copy the system's interleaved state (L x LS complex, at state_off of a
 // batch-layout buffer) with lane k owning column k+1 and the first/last lane
 // also copying the zero halo columns
-__device__ void copy_state(const SysDesc& sd, int lane, const double* __restrict__ src,
-                           double* __restrict__ dst) {
+__device__ __forceinline__ void copy_state(const SysDesc& sd, int lane, const double* src, double* dst) {
     if (lane >= sd.P) return;
     const int LS = sd.LS;
     for (int l = 0; l < sd.L; ++l) {
@@ -82,7 +81,7 @@ __device__ void copy_state(const SysDesc& sd, int lane, const double* __restrict
 // Band products use the scatter/gather split of the right-hand-side pass;
 // pairs (r, r-d) of the two reductions are counted by the owner of row r.
 template <int PP>
-__device__ void pass_adjoint_update(const SysDesc& sd, int k, const double* __restrict__ band,
+__device__ __forceinline__ void pass_adjoint_update(const SysDesc& sd, int k, const double* __restrict__ band,
                                     const double* __restrict__ wsol, const double* __restrict__ cn,
                                     const double* __restrict__ cn1, double* __restrict__ lam,
                                     bool has_z, double alpha, double Ebar, double En, double jn,
@@ -195,7 +194,7 @@ __device__ void pass_adjoint_update(const SysDesc& sd, int k, const double* __re
 
 // one forward step n -> n+1 in place on st (FP64, no refinement)
 template <int PP>
-__device__ void forward_step(const AdjArgs& ka, const SysDesc& sd, int lane, double alpha, double Ebar) {
+__device__ __forceinline__ void forward_step(const AdjArgs& ka, const SysDesc& sd, int lane, double alpha, double Ebar) {
     const bool active = lane < sd.P;
     double part[3];
     if (active) {
@@ -212,7 +211,7 @@ __device__ void forward_step(const AdjArgs& ka, const SysDesc& sd, int lane, dou
 }
 
 template <int PP>
-__device__ void run_adjoint(const AdjArgs& ka, const SysDesc& sd, int sidx) {
+__device__ __forceinline__ void run_adjoint(const AdjArgs& ka, const SysDesc& sd, int sidx) {
     const int lane = threadIdx.x;
     const bool active = lane < sd.P;
     const int N = sd.N, L = sd.L, LS = sd.LS, ns = sd.nsteps, ck = sd.ck;

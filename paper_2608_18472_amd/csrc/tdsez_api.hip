@@ -215,7 +215,7 @@ tdsez_status tdsez_batch_set(tdsez_batch b, const char* key, double value) {
     }
     if (!std::strcmp(key, "profile")) {
         if (value != 0.0 && !b->d.d_prof) {
-            size_t bytes = sizeof(unsigned long long) * 5 * b->d.sys.size();
+            size_t bytes = sizeof(unsigned long long) * 9 * b->d.sys.size();
             TDSEZ_HIP_TRY(hipMalloc(&b->d.d_prof, bytes));
             TDSEZ_HIP_TRY(hipMemset(b->d.d_prof, 0, bytes));
         } else if (value == 0.0 && b->d.d_prof) {
@@ -313,12 +313,12 @@ tdsez_status tdsez_batch_profile(tdsez_batch b, void* stream, double* out) {
     if (!b->d.d_prof) return fail(TDSEZ_EINVAL, "profiling is off (tdsez_batch_set(b, \"profile\", 1))");
     TDSEZ_HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
     const size_t n = b->d.sys.size();
-    std::vector<unsigned long long> h(5 * n);
-    TDSEZ_HIP_TRY(hipMemcpy(h.data(), b->d.d_prof, sizeof(unsigned long long) * 5 * n, hipMemcpyDeviceToHost));
+    std::vector<unsigned long long> h(9 * n);
+    TDSEZ_HIP_TRY(hipMemcpy(h.data(), b->d.d_prof, sizeof(unsigned long long) * 9 * n, hipMemcpyDeviceToHost));
     for (size_t s = 0; s < n; ++s) {
-        double ns = h[5 * s + 4] > 0 ? (double)h[5 * s + 4] : 1.0;
-        for (int k = 0; k < 4; ++k) out[5 * s + k] = (double)h[5 * s + k] / ns;
-        out[5 * s + 4] = (double)b->d.plan[s].P;
+        double ns = h[9 * s + 8] > 0 ? (double)h[9 * s + 8] : 1.0;
+        for (int k = 0; k < 8; ++k) out[9 * s + k] = (double)h[9 * s + k] / ns;
+        out[9 * s + 8] = (double)b->d.plan[s].P;
     }
     return TDSEZ_OK;
 }

@@ -88,7 +88,7 @@ __device__ inline void st_c(FT* base, unsigned idx, cplx<FT> v) {
 // plus a halo of p rows of the next chunk; each pair of rows (r, r-d) of an
 // observable is counted by the owner of the larger row.
 template <int PP, typename FT>
-__device__ void pass_rhs(const SysDesc& sd, int k, const FT* __restrict__ band,
+__device__ __forceinline__ void pass_rhs(const SysDesc& sd, int k, const FT* __restrict__ band,
                          const double* __restrict__ st, FT* __restrict__ rhs, double alpha,
                          double Ebar, double En, bool want_acc, bool want_rhs, double obs_part[3]) {
     constexpr int NM = kNumMats;
@@ -228,7 +228,7 @@ __device__ void pass_rhs(const SysDesc& sd, int k, const FT* __restrict__ band,
 // W and right-hand side yR of the chunk's separator rows.  With kConj the
 // right-hand side is the complex conjugate of `rhs` (adjoint solves).
 template <int PP, typename FT, bool kConj = false>
-__device__ void pass_elim(const SysDesc& sd, int k, const FT* __restrict__ band,
+__device__ __forceinline__ void pass_elim(const SysDesc& sd, int k, const FT* __restrict__ band,
                           const FT* __restrict__ rhs, FT* __restrict__ fac, FT* __restrict__ red,
                           double alpha, double Ebar) {
     constexpr int NM = kNumMats;
@@ -268,7 +268,6 @@ __device__ void pass_elim(const SysDesc& sd, int k, const FT* __restrict__ band,
             in.bD[d] = bnd[rb + (unsigned)((2 * (PP + 1) + d) * LS)];
         }
         in.b = ld_c(rs, (unsigned)r * (unsigned)LS + (unsigned)col);
-        if (kConj) in.b.im = -in.b.im;
         return in;
     };
     auto row = [&](const RowIn& in, int r, bool first_rows, bool elim) {
@@ -278,7 +277,7 @@ __device__ void pass_elim(const SysDesc& sd, int k, const FT* __restrict__ band,
             const cplx<FT> a = cmk<FT>(in.bS[d], a_f * (in.bH[d] + eb_f * in.bD[d]));
             if (!first_rows || r - d >= 0) W[PP][PP - d] = a;
         }
-        y[PP] = in.b;
+        y[PP] = kConj ? cmk<FT>(in.b.re, -in.b.im) : in.b;
         if (elim) {
             const int j = r - PP;
             const cplx<FT> dinv = cinv_dev(W[0][0]);
@@ -344,7 +343,7 @@ __device__ void pass_elim(const SysDesc& sd, int k, const FT* __restrict__ band,
 // pass A1 carry the fill down the chunk.  With kTL == false the Schur update
 // is left to pass_schur (fewer live registers for FP64).
 template <int PP, typename FT, bool kTL>
-__device__ void pass_fill(const SysDesc& sd, int k, const FT* __restrict__ band, FT* __restrict__ fac,
+__device__ __forceinline__ void pass_fill(const SysDesc& sd, int k, const FT* __restrict__ band, FT* __restrict__ fac,
                           FT* __restrict__ red, double alpha, double Ebar) {
     constexpr int NM = kNumMats;
     constexpr int IT = 2 * PP + 2;
@@ -455,7 +454,7 @@ __device__ void pass_fill(const SysDesc& sd, int k, const FT* __restrict__ band,
 // Pass A3 (used when pass_fill runs without the Schur update): TL and gT of
 // the left separator from the stored fill rows.
 template <int PP, typename FT>
-__device__ void pass_schur(const SysDesc& sd, int k, const FT* __restrict__ fac, FT* __restrict__ red) {
+__device__ __forceinline__ void pass_schur(const SysDesc& sd, int k, const FT* __restrict__ fac, FT* __restrict__ red) {
     constexpr int IT = 2 * PP + 2;
     const int P = sd.P, m = sd.m;
     int col = k + 1;
@@ -530,26 +529,37 @@ template <typename FT>
 __device__ inline cplx<FT> shfl_c(cplx<FT> v, int src) {
     return cplx<FT>{__shfl(v.re, src, 64), __shfl(v.im, src, 64)};
 }
-template <typename FT>
-__device__ inline cplx<FT> shfl_xor_c(cplx<FT> v, int m) {
-    return cplx<FT>{__shfl_xor(v.re, m, 64), __shfl_xor(v.im, m, 64)};
+// Data-parallel-primitive lane permutes (VALU latency, no LDS round trip):
+// quad_perm [1,0,3,2] and [2,3,0,1] pair lanes within a quad, row_half_mirror
+// reverses each group of 8 lanes (pairing its two quads).
+template <int CTRL>
+__device__ inline float dpp(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
 }
-// sums over the 8 lanes of a row group (j) / of a column group (i)
+template <int CTRL>
+__device__ inline double dpp(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+constexpr int kDppQuadXor1 = 0xB1;      // quad_perm [1,0,3,2]
+constexpr int kDppQuadXor2 = 0x4E;      // quad_perm [2,3,0,1]
+constexpr int kDppRowHalfMirror = 0x141;
+template <int CTRL, typename FT>
+__device__ inline cplx<FT> dpp_c(cplx<FT> v) {
+    return {dpp<CTRL>(v.re), dpp<CTRL>(v.im)};
+}
+// sum over the 8 lanes of a row group (lane = 8i + j, summed over j); every
+// lane of the group receives the sum.  Needs all 64 lanes active.
 template <typename FT>
 __device__ inline cplx<FT> row_sum(cplx<FT> v) {
-    v = cadd(v, shfl_xor_c(v, 1));
-    v = cadd(v, shfl_xor_c(v, 2));
-    return cadd(v, shfl_xor_c(v, 4));
-}
-template <typename FT>
-__device__ inline cplx<FT> col_sum(cplx<FT> v) {
-    v = cadd(v, shfl_xor_c(v, 8));
-    v = cadd(v, shfl_xor_c(v, 16));
-    return cadd(v, shfl_xor_c(v, 32));
+    v = cadd(v, dpp_c<kDppQuadXor1>(v));
+    v = cadd(v, dpp_c<kDppQuadXor2>(v));
+    return cadd(v, dpp_c<kDppRowHalfMirror>(v));
 }
 
 template <int PP, typename FT>
-__device__ void pass_reduced(const SysDesc& sd, int lane, FT* __restrict__ red, bool factor) {
+__device__ __forceinline__ void pass_reduced(const SysDesc& sd, int lane, FT* __restrict__ red, bool factor) {
     constexpr int p = PP;
     const int P = sd.P;
     const long long cb = RedLayout<FT>::chunk_block(p);
@@ -566,26 +576,30 @@ __device__ void pass_reduced(const SysDesc& sd, int lane, FT* __restrict__ red, 
     const cplx<FT> ident = cmk<FT>(i == j ? (FT)1 : (FT)0, 0);
     auto blk = [&](int s) { return rbase + 2 * ((long long)s * cb); };
 
-    // the inputs of block s, loaded one block ahead of their use
+    // the raw inputs of block s, loaded one block ahead of their use; loads
+    // are unconditional (indices clamped into the workspace) and the
+    // padding/boundary masks are applied when the values are used, so that no
+    // load sits in a branch that would force an early wait
+    const unsigned ii = (unsigned)(i < p ? i : 0);
+    const unsigned ee = valid ? eij : 0u;
     struct Fwd {
-        cplx<FT> g, a, f;
+        cplx<FT> y, gt, w, tl, f;
     };
     auto load_fwd = [&](int s) {
-        Fwd r{zero, ident, zero};
-        if (s >= P) return r;
-        const FT* bs = blk(s);
-        if (i < p) {
-            r.g = ld_c(bs, 3 * pp + (unsigned)i);
-            if (s + 1 < P) r.g = cadd(r.g, ld_c(blk(s + 1), 3 * pp + (unsigned)p + (unsigned)i));
-        }
-        if (valid) {
-            if (factor) {
-                r.a = ld_c(bs, eij);
-                if (s + 1 < P) r.a = cadd(r.a, ld_c(blk(s + 1), 2 * pp + eij));
-                r.f = ld_c(bs, pp + eij);
-            } else if (s >= 1) {
-                r.f = ld_c(m_base, (unsigned)s * pp + eij);  // stored M_s
-            }
+        const int sc = s < P ? s : P - 1;
+        const int s1 = s + 1 < P ? s + 1 : P - 1;
+        const FT* bs = blk(sc);
+        const FT* b1 = blk(s1);
+        Fwd r;
+        r.y = ld_c(bs, 3 * pp + ii);
+        r.gt = ld_c(b1, 3 * pp + (unsigned)p + ii);
+        if (factor) {
+            r.w = ld_c(bs, ee);
+            r.tl = ld_c(b1, 2 * pp + ee);
+            r.f = ld_c(bs, pp + ee);
+        } else {
+            r.w = r.tl = zero;
+            r.f = ld_c(m_base, (unsigned)sc * pp + ee);  // stored M_s
         }
         return r;
     };
@@ -596,14 +610,17 @@ __device__ void pass_reduced(const SysDesc& sd, int lane, FT* __restrict__ red, 
     Fwd cur = load_fwd(0);
     for (int s = 0; s < P; ++s) {
         Fwd nxt = load_fwd(s + 1);
+        const bool more = s + 1 < P;
+        const cplx<FT> g = csel(i < p, cadd(cur.y, csel(more, cur.gt, zero)), zero);
+        const cplx<FT> fv = csel(valid, cur.f, zero);
         cplx<FT> mm = zero;
         if (factor) {
-            cplx<FT> a = cur.a;
+            cplx<FT> a = csel(valid, cadd(cur.w, csel(more, cur.tl, zero)), ident);
             if (s >= 1) {
                 cplx<FT> fr[p], dc[p];
 #pragma unroll
                 for (int l = 0; l < p; ++l) {
-                    fr[l] = shfl_c(cur.f, 8 * i + l);
+                    fr[l] = shfl_c(fv, 8 * i + l);
                     dc[l] = shfl_c(dprev, 8 * l + j);
                 }
 #pragma unroll
@@ -612,7 +629,7 @@ __device__ void pass_reduced(const SysDesc& sd, int lane, FT* __restrict__ red, 
 #pragma unroll
                 for (int l = 0; l < p; ++l) {
                     mr[l] = shfl_c(mm, 8 * i + l);
-                    fc2[l] = shfl_c(cur.f, 8 * j + l);
+                    fc2[l] = shfl_c(fv, 8 * j + l);
                 }
 #pragma unroll
                 for (int l = 0; l < p; ++l) a = cfms(a, mr[l], fc2[l]);
@@ -632,35 +649,43 @@ __device__ void pass_reduced(const SysDesc& sd, int lane, FT* __restrict__ red, 
             if (valid) st_c(dinv_base, (unsigned)s * pp + eij, a);
             dprev = a;
         } else {
-            mm = cur.f;
+            mm = csel(s >= 1, fv, zero);
         }
-        cplx<FT> zr = csub(cur.g, row_sum(cmul(mm, zc)));
+        cplx<FT> zr = csub(g, row_sum(cmul(mm, zc)));
         if (j == 0 && i < p) st_c(z_base, (unsigned)(s * p + i), zr);
         zc = shfl_c(zr, 8 * j);
         cur = nxt;
     }
     __syncthreads();  // z_s written by other lanes
-    // backward sweep
+    // backward sweep: lane (i, j) loads F_{s+1}[j][i] (transposed) so that
+    // both products are row sums; x and w change layout with one shuffle each
+    const unsigned eji = valid ? (unsigned)(j * p + i) : 0u;
     struct Bwd {
-        cplx<FT> dv, fn, zs;
+        cplx<FT> dv, fnt, zs;
     };
     auto load_bwd = [&](int s) {
-        Bwd r{ident, zero, zero};
-        if (s < 0) return r;
-        if (valid) {
-            r.dv = ld_c(dinv_base, (unsigned)s * pp + eij);
-            if (s + 1 < P) r.fn = ld_c(blk(s + 1), pp + eij);
-        }
-        if (j < p) r.zs = ld_c(z_base, (unsigned)(s * p + j));
+        const int sc = s < 0 ? 0 : s;
+        const int s1 = sc + 1 < P ? sc + 1 : P - 1;
+        Bwd r;
+        r.dv = ld_c(dinv_base, (unsigned)sc * pp + ee);
+        r.fnt = ld_c(blk(s1), pp + eji);
+        r.zs = ld_c(z_base, (unsigned)(sc * p) + ii);
         return r;
     };
-    cplx<FT> xr = zero;  // x_{s+1} in row layout
+    cplx<FT> xc = zero;  // x_{s+1} in column layout
     Bwd bc = load_bwd(P - 1);
     for (int s = P - 1; s >= 0; --s) {
         Bwd bn = load_bwd(s - 1);
-        cplx<FT> w = csub(bc.zs, col_sum(cmul(bc.fn, xr)));
-        xr = row_sum(cmul(bc.dv, w));
+        const cplx<FT> dv = csel(valid, bc.dv, ident);
+        const cplx<FT> fnt = csel(valid && s + 1 < P, bc.fnt, zero);
+        const cplx<FT> zs = csel(i < p, bc.zs, zero);
+        // w_s = z_s - F_{s+1}^T x_{s+1}  (row layout), then column layout
+        const cplx<FT> wr = csub(zs, row_sum(cmul(fnt, xc)));
+        const cplx<FT> wc = shfl_c(wr, 8 * j);
+        // x_s = Delta_s^-1 w_s  (row layout), then column layout
+        const cplx<FT> xr = row_sum(cmul(dv, wc));
         if (j == 0 && i < p) st_c(x_base, (unsigned)(s * p + i), xr);
+        xc = shfl_c(xr, 8 * j);
         bc = bn;
     }
 }
@@ -673,7 +698,7 @@ __device__ void pass_reduced(const SysDesc& sd, int lane, FT* __restrict__ red, 
 // overwritten by the solution); with dtot != nullptr the increment is also
 // written (first == true) or added to dtot.
 template <int PP, typename FT>
-__device__ void pass_backsub(const SysDesc& sd, int k, const FT* __restrict__ band,
+__device__ __forceinline__ void pass_backsub(const SysDesc& sd, int k, const FT* __restrict__ band,
                              double* __restrict__ st, double* __restrict__ dtot, bool first,
                              const FT* __restrict__ fac, const FT* __restrict__ red, double alpha,
                              double Ebar, bool assign = false) {
@@ -791,7 +816,7 @@ __device__ void pass_backsub(const SysDesc& sd, int k, const FT* __restrict__ ba
 // Crank-Nicolson step), then forward substitution with the stored factor
 // rows (yhat, and the chunk's separator right-hand sides yR, gT).
 template <int PP, typename FT>
-__device__ void pass_residual(const SysDesc& sd, int k, const FT* __restrict__ band,
+__device__ __forceinline__ void pass_residual(const SysDesc& sd, int k, const FT* __restrict__ band,
                               const double* __restrict__ band64, const double* __restrict__ st,
                               const double* __restrict__ dtot, FT* __restrict__ fac,
                               FT* __restrict__ red, double alpha, double Ebar) {

@@ -41,11 +41,15 @@ namespace tdsez {
 
 namespace {
 
+// number of per-system counters of the optional phase profile
+constexpr int kProfSlots = 9;
+
 template <int PP, typename FT>
-__device__ void run_system(const KernelArgs& ka, const SysDesc& sd, int sidx) {
-    // optional phase profile: shader-clock cycles of the factor sweep, the
-    // reduced solve, the back substitution and the refinement sweeps
-    unsigned long long t_fac = 0, t_red = 0, t_back = 0, t_ref = 0, t0 = 0;
+__device__ __forceinline__ void run_system(const KernelArgs& ka, const SysDesc& sd, int sidx) {
+    // optional phase profile: shader-clock cycles summed over the steps for
+    // the passes H, A1, A2, R, B and, per refinement sweep, C, R, B
+    unsigned long long tp[kProfSlots - 1] = {0, 0, 0, 0, 0, 0, 0, 0};
+    unsigned long long t0 = 0;
     const FT* band = (const FT*)ka.band;
     FT* fac = (FT*)ka.fac;
     FT* red = (FT*)ka.red;
@@ -61,6 +65,16 @@ __device__ void run_system(const KernelArgs& ka, const SysDesc& sd, int sidx) {
     const int refine = ka.refine;
     double* dtot = refine > 0 ? ka.dtot : nullptr;
     const bool prof = ka.prof != nullptr;
+    // phase boundary: a barrier (so the clock covers the whole wave) when
+    // profiling, then the cycles since the last boundary go to slot k
+    auto mark = [&](int k) {
+        if (prof) {
+            __syncthreads();
+            const unsigned long long t = clock64();
+            tp[k] += t - t0;
+            t0 = t;
+        }
+    };
     double nu0 = 0.0;
     for (int n = 0; n <= sd.nsteps; ++n) {
         const bool last = (n == sd.nsteps);
@@ -68,14 +82,14 @@ __device__ void run_system(const KernelArgs& ka, const SysDesc& sd, int sidx) {
         const double Ebar = last ? En : 0.5 * (En + Es[n + 1]);
         double part[3] = {0.0, 0.0, 0.0};
         if (prof) t0 = clock64();
-        if (active) {
-            pass_rhs<PP, FT>(sd, lane, band, st, rhs, alpha, Ebar, En, want_acc, !last, part);
-            if (!last) {
-                pass_elim<PP, FT>(sd, lane, band, rhs, fac, red, alpha, Ebar);
-                constexpr bool kFused = sizeof(FT) == 4;
-                pass_fill<PP, FT, kFused>(sd, lane, band, fac, red, alpha, Ebar);
-                if (!kFused) pass_schur<PP, FT>(sd, lane, fac, red);
-            }
+        if (active) pass_rhs<PP, FT>(sd, lane, band, st, rhs, alpha, Ebar, En, want_acc, !last, part);
+        mark(0);
+        if (active && !last) pass_elim<PP, FT>(sd, lane, band, rhs, fac, red, alpha, Ebar);
+        mark(1);
+        if (active && !last) {
+            constexpr bool kFused = sizeof(FT) == 4;
+            pass_fill<PP, FT, kFused>(sd, lane, band, fac, red, alpha, Ebar);
+            if (!kFused) pass_schur<PP, FT>(sd, lane, fac, red);
         }
         double nu = wave_sum(part[0]);
         double dip = wave_sum(part[1]);
@@ -96,33 +110,32 @@ __device__ void run_system(const KernelArgs& ka, const SysDesc& sd, int sidx) {
         }
         if (last) break;
         __syncthreads();
-        if (prof) { unsigned long long t = clock64(); t_fac += t - t0; t0 = t; }
+        mark(2);
         pass_reduced<PP, FT>(sd, lane, red, true);
         __syncthreads();
-        if (prof) { unsigned long long t = clock64(); t_red += t - t0; t0 = t; }
+        mark(3);
         if (active) pass_backsub<PP, FT>(sd, lane, band, st, dtot, true, fac, red, alpha, Ebar);
         __syncthreads();
-        if (prof) { unsigned long long t = clock64(); t_back += t - t0; t0 = t; }
+        mark(4);
         for (int sweep = 0; sweep < refine; ++sweep) {
             if (active)
                 pass_residual<PP, FT>(sd, lane, band, ka.band64, st, dtot, fac, red, alpha, Ebar);
             __syncthreads();
+            mark(5);
             pass_reduced<PP, FT>(sd, lane, red, false);
             __syncthreads();
+            mark(6);
             if (active)
                 pass_backsub<PP, FT>(sd, lane, band, st, sweep + 1 < refine ? dtot : nullptr, false, fac,
                                      red, alpha, Ebar);
             __syncthreads();
+            mark(7);
         }
-        if (prof) { unsigned long long t = clock64(); t_ref += t - t0; }
     }
     if (prof && lane == 0) {
-        unsigned long long* pr = ka.prof + 5 * sidx;
-        pr[0] = t_fac;
-        pr[1] = t_red;
-        pr[2] = t_back;
-        pr[3] = t_ref;
-        pr[4] = (unsigned long long)sd.nsteps;
+        unsigned long long* pr = ka.prof + kProfSlots * sidx;
+        for (int k = 0; k < kProfSlots - 1; ++k) pr[k] = tp[k];
+        pr[kProfSlots - 1] = (unsigned long long)sd.nsteps;
     }
 }
 

@@ -331,12 +331,12 @@ def batch_status(batch, stream=None):
 
 
 def batch_profile(batch, stream=None):
-    """Average cycles per step in (factor sweep, separator solve, back
-    substitution, refinement sweeps) and the partition count, one row per
-    system."""
-    out = np.zeros(5 * len(batch.systems))
+    """Average cycles per step per phase, one row per system: (rhs, elim,
+    fill, reduced, backsub, refine residual, refine reduced, refine backsub,
+    partition count)."""
+    out = np.zeros(9 * len(batch.systems))
     _check(lib().tdsez_batch_profile(batch.handle, _stream_handle(stream), _dptr(out)))
-    return out.reshape(-1, 5)
+    return out.reshape(-1, 9)
 
 
 def system_status(sys, stream=None):
