@@ -8,8 +8,10 @@ every time step, with the norm/dipole/acceleration series).
 
 Prints one JSON line.  Metric: complex DOF-steps/s = sum_i N_i nsteps_i /
 wall time of the propagate call (HIP events on the launch stream), for the
-FP32-refined path; the FP64 path is timed beside it and the dipole error of
-the FP32 path against the FP64 path is reported.
+FP32-refined path (one refinement sweep per step); the FP64 path is timed
+beside it and the dipole error of the FP32 path against the FP64 path is
+reported.  roofline.achieved = algorithmic bytes of the launch / its time;
+roofline.traffic = HBM bytes of the launch measured with hardware counters.
 """
 import argparse
 import json
@@ -25,6 +27,32 @@ sys.path.insert(0, ROOT)
 
 METRIC = "complex DOF-steps/s per GPU, FP32-refined vs FP64 at dipole error ≤1e-5"
 HBM_PEAK_GBS = 8000.0
+# device copy launched before the timed region: the calibration kernel of the
+# HBM byte counters (FETCH_SIZE / WRITE_SIZE read this many bytes each way)
+CALIB_COPY_BYTES = 512 * 2 ** 20
+# HBM bytes per launch of the FP32 propagation kernel on this workload, from
+# two rocprofv3 --pmc runs of this script (FETCH_SIZE, then WRITE_SIZE) scaled
+# by the copy calibration; valid only for the kernel sources they were taken
+# on (sha256 of the listed files).  See profiles/propagate_kernel_fp32_batch1024_pmc.md.
+TRAFFIC = {"sources_sha256": "7b2274036231c04085cb4bee5f28fc2a89d7347b518bf08da375e32ac626fe3e",
+           "bytes_per_launch": 2.7145e13}
+KERNEL_SOURCES = ["paper_2608_18472_amd/csrc/tdsez_passes.hpp", "paper_2608_18472_amd/csrc/tdsez_propagate.hip",
+                  "paper_2608_18472_amd/csrc/tdsez_internal.hpp"]
+
+
+def kernel_sources_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def algorithmic_bytes(order, real_bytes, cplx_bytes):
+    """Per DOF-step: the S, H0, D, G half bands (p+1 diagonals each) read
+    once, the state read once and written once."""
+    return 4 * order * real_bytes + 2 * cplx_bytes
 
 
 def greville_gaussian(sd, width=1.0):
@@ -95,6 +123,7 @@ def main():
     defs = W.config3(nsys=args.nsys, seed=0)
     systems = [T.assemble_workload(s) for s in defs]
     batch = T.batch_create(systems)
+    T.batch_set(batch, "refine", 1)
     psi_init, po, E, eo, obs, oo = T.pack_batch_inputs(defs, [np.zeros(s.ndof) for s in defs], dev)
     # initial states: every system's ground state (batched FP64 shift-and-invert on the GPU)
     t_gs = time.perf_counter()
@@ -108,6 +137,13 @@ def main():
     t_setup = time.perf_counter() - t_setup
 
     stream = torch.cuda.current_stream()
+    # calibration copy for the HBM byte counters (outside every timed region)
+    src = torch.empty(CALIB_COPY_BYTES // 8, dtype=torch.float64, device=dev)
+    src.fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
 
     def run(prec, k, obs_buf):
         psi = psi_init.clone()
@@ -144,11 +180,12 @@ def main():
             b = obs_by["fp64"][3 * eo[i]: 3 * eo[i] + 3 * (nsteps[i] + 1)].reshape(-1, 3)[:, 1]
             e.append(np.linalg.norm(a - b) / np.linalg.norm(b))
         eps_d = float(max(e))
-    # algorithmic bytes per DOF-step: S, H0, D, G half bands (p+1 each) in the
-    # band precision, complex128 state read and written
-    def bytes_per(prec_bytes):
-        return sum(s.ndof * s.nsteps * (4 * s.order * prec_bytes + 2 * 16) for s in defs)
-    achieved = bytes_per(4) / results["fp32-refined"] / 1e9
+    # algorithmic bytes of one launch (FP32: 4-byte reals, 8-byte complex)
+    alg_bytes = sum(s.ndof * s.nsteps * algorithmic_bytes(s.order, 4, 8) for s in defs)
+    achieved = alg_bytes / results["fp32-refined"] / 1e9
+    traffic = None
+    if TRAFFIC["bytes_per_launch"] is not None and TRAFFIC["sources_sha256"] == kernel_sources_sha():
+        traffic = TRAFFIC["bytes_per_launch"]
     line = {
         "metric": METRIC,
         "value": value,
@@ -172,6 +209,8 @@ def main():
             "fp64_value": dofsteps / results["fp64"] if "fp64" in results else None,
             "fp64_ms_per_step": results["fp64"] * 1000.0 if "fp64" in results else None,
             "dipole_rel_err_fp32_vs_fp64": eps_d,
+            "refine_sweeps": 1,
+            "algorithmic_bytes_per_launch": alg_bytes,
             "setup_s": t_setup,
             "ground_state_s": t_gs,
         },
@@ -181,7 +220,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": traffic,
         },
     }
     if not args.no_cpu:
