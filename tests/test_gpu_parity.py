@@ -329,3 +329,77 @@ def test_refinement_sweep_meets_dipole_bar_on_strong_fields(which):
     assert errs[1] < 1e-5
     assert errs[2] < 1e-5
     assert errs[1] < errs[0]
+
+
+def test_full_config2_dqw_dipole_series():
+    """The double-quantum-well workload (position-dependent mass, N = 1500,
+    20 000 steps of the 8-cycle mid-IR pulse) over its whole pulse, FP64 and
+    FP32-refined against the oracle (norm and dipole)."""
+    sd = W.config2()
+    say("full config2", sd.ndof, sd.nsteps)
+    g = T.assemble_workload(sd)
+    m = oracle_of(sd)
+    ev, vec = O.eig_banded(m["H0"], m["S"], 1, m["shift"])
+    psi0 = vec[0].astype(np.complex128)
+    ref, _ = O.propagate(m, psi0, sd.E, sd.dt, sd.nsteps, with_accel=False)
+    for prec, tol in ((T.FP64, 1e-10), (T.FP32_REFINED, 1e-5)):
+        got, _ = run_gpu(g, psi0, sd.E, sd.dt, sd.nsteps, prec, T.OBS_NORM | T.OBS_DIPOLE)
+        errs = [rel(got[:, k], ref[:, k]) for k in range(2)]
+        say("config2", prec, errs)
+        assert errs[1] < tol
+        if prec == T.FP64:
+            assert errs[0] < tol
+
+
+def _oracle_series(args):
+    idx, nsteps = args
+    from oracle import oracle as Oc
+    sd = W.config3(nsys=1024, seed=0)[idx]
+    m = Oc.assemble(sd.breaks, sd.order, sd.nq, None, sd.V, sd.dV)
+    xq, _ = Oc.quad_points(sd.breaks, sd.nq)
+    vmin = float(np.min(sd.V(xq)))
+    ev, vec = Oc.eig_banded(m["H0"], m["S"], 1, vmin - 1e-3 * (abs(vmin) + 1.0))
+    psi0 = vec[0].astype(np.complex128)
+    ref, _ = Oc.propagate(m, psi0, sd.E, sd.dt, nsteps)
+    return idx, psi0, ref
+
+
+def test_batch_subset_fp64_matches_oracle():
+    """FP64 GPU path vs the oracle on 32 systems of the 1024-system batch
+    (seeded subset with the smallest and largest N and every order), one
+    persistent launch, the first 2000 steps of each pulse (the field is on
+    over this window).  The oracle runs serially in this process (no fork
+    of a process that has initialised the GPU)."""
+    defs_all = W.config3(nsys=1024, seed=0)
+    order = np.argsort([s.ndof for s in defs_all])
+    rng = np.random.default_rng(5)
+    pick = {int(order[0]), int(order[-1])}
+    for k in (6, 7, 8):
+        pick.add(int(next(i for i in order if defs_all[i].order == k)))
+    while len(pick) < 32:
+        pick.add(int(rng.integers(0, 1024)))
+    pick = sorted(pick)
+    ns = 2000
+    say("subset", [(defs_all[i].ndof, defs_all[i].order) for i in pick])
+    res = {}
+    for i in pick:
+        _, p0, r = _oracle_series((i, ns))
+        res[i] = (p0, r)
+    defs = [defs_all[i] for i in pick]
+    for s in defs:
+        s.nsteps = ns
+    gs = [T.assemble_workload(s) for s in defs]
+    b = T.batch_create(gs)
+    psi, po, E, eo, obs, oo = T.pack_batch_inputs(defs, [res[i][0] for i in pick])
+    T.propagate_batched(b, psi, po, E, eo, [s.dt for s in defs], [ns] * len(defs), T.FP64, T.OBS_ALL, obs, oo)
+    T.batch_status(b)
+    o = obs.cpu().numpy()
+    worst = 0.0
+    for j, i in enumerate(pick):
+        got = o[3 * eo[j]: 3 * eo[j] + 3 * (ns + 1)].reshape(-1, 3)
+        ref = res[i][1]
+        for k in range(3):
+            e = rel(got[:, k], ref[:, k])
+            worst = max(worst, e)
+            assert e < 1e-10, (i, k, e)
+    say("subset worst", worst)
