@@ -50,6 +50,8 @@ def lib():
         L.orc_eig_banded.argtypes = [i, i, dp, dp, i, d, d, i, dp, dp]
         L.orc_propagate.argtypes = [i, i, dp, dp, dp, dp, dp, dp, dp, d, i, dp, dp]
         L.orc_adjoint.argtypes = [i, i, dp, dp, dp, dp, dp, dp, dp, d, i, dp, dp, dp]
+        L.orc_assemble_v2.argtypes = [dp, i, dp, i, i, i, dp, dp]
+        L.orc_apply_2d.argtypes = [i, i, i, dp, dp, dp, dp, dp, dp, d, d, d, d, d, dp, dp]
         _lib = L
     return _lib
 
@@ -202,3 +204,115 @@ def adjoint(m, psi0, E, dt, nsteps, dJdobs, with_accel=True):
                              _p(psi0.view(np.float64)), _p(E), float(dt), int(nsteps), _p(dJdobs),
                              _p(dJdE), _p(lam0.view(np.float64))), "adjoint")
     return dJdE, lam0
+
+
+# --------------------------------------------------------------------------
+# Two dimensions (tensor-product basis, constant mass, x-polarised field)
+# --------------------------------------------------------------------------
+def quad_grid_2d(breaks_x, breaks_y, nq):
+    """Tensor grid of the per-axis quadrature points: (X, Y) with shape
+    (nqy, nqx) (y slow), matching the V_q layout of orc_assemble_v2."""
+    xq, _ = quad_points(breaks_x, nq)
+    yq, _ = quad_points(breaks_y, nq)
+    return np.meshgrid(xq, yq)
+
+
+def assemble_2d(breaks_x, breaks_y, order, nq, V):
+    """Matrices of the 2D problem: per-axis S, T, D half bands (1D assembly
+    with V = 0) and the potential stencil V2 (orc_assemble_v2) for the
+    callable V(x, y)."""
+    bx, by = _f64(breaks_x), _f64(breaks_y)
+    mx = assemble(bx, order, nq)
+    my = assemble(by, order, nq)
+    X, Y = quad_grid_2d(bx, by, nq)
+    Vq = _f64(V(X, Y))
+    Nx, Ny, p = mx["N"], my["N"], mx["p"]
+    w2 = 2 * p + 1
+    V2 = np.zeros((Ny * Nx, w2, w2))
+    _check(lib().orc_assemble_v2(_p(bx), len(bx), _p(by), len(by), order, nq, _p(Vq), _p(V2)), "assemble_v2")
+    return {"Nx": Nx, "Ny": Ny, "p": p, "Sx": mx["S"], "Tx": mx["T"], "Dx": mx["D"], "Sy": my["S"],
+            "Ty": my["T"], "V2": V2}
+
+
+def apply_2d(m2, c, a, b, Ebar, with_V=True):
+    """a S2 c + b (T2 + V2 + Ebar D2) c for complex scalars a, b; c complex
+    of shape (Ny, Nx) or flat."""
+    c = _c128(np.asarray(c).reshape(-1))
+    y = np.zeros_like(c)
+    _check(lib().orc_apply_2d(m2["Nx"], m2["Ny"], m2["p"], _p(_f64(m2["Sx"])), _p(_f64(m2["Tx"])),
+                              _p(_f64(m2["Dx"])), _p(_f64(m2["Sy"])), _p(_f64(m2["Ty"])),
+                              _p(_f64(m2["V2"])) if with_V else None, float(np.real(a)), float(np.imag(a)),
+                              float(np.real(b)), float(np.imag(b)), float(Ebar), _p(c.view(np.float64)),
+                              _p(y.view(np.float64))), "apply_2d")
+    return y
+
+
+def _fdm_factors(m2):
+    """Per-axis generalised eigenpairs T Q = S Q Lambda, Q^T S Q = I (LAPACK
+    via scipy): the separable part S2 + i a T2 is diagonal in Q_y (x) Q_x."""
+    import scipy.linalg as sl
+    lx, Qx = sl.eigh(band_to_dense(m2["Tx"]), band_to_dense(m2["Sx"]))
+    ly, Qy = sl.eigh(band_to_dense(m2["Ty"]), band_to_dense(m2["Sy"]))
+    return lx, Qx, ly, Qy
+
+
+def cn_solve_2d(m2, rhs, alpha, Ebar, x0=None, fdm=None, tol=1e-14, maxit=500):
+    """Solve (S2 + i a H2(Ebar)) x = rhs (section V.B, eq. cn_system in 2D)
+    by conjugate-orthogonal CG (A is complex symmetric), preconditioned by
+    the exact inverse of the separable part S2 + i a T2 (per-axis
+    eigendecompositions); stops at relative residual tol."""
+    Nx, Ny = m2["Nx"], m2["Ny"]
+    lx, Qx, ly, Qy = fdm if fdm is not None else _fdm_factors(m2)
+    den = 1.0 + 1j * alpha * (ly[:, None] + lx[None, :])
+
+    def A(v):
+        return apply_2d(m2, v, 1.0, 1j * alpha, Ebar)
+
+    def M(r):
+        R = r.reshape(Ny, Nx)
+        Z = (Qy.T @ R @ Qx) / den
+        return (Qy @ Z @ Qx.T).reshape(-1)
+
+    b = _c128(np.asarray(rhs).reshape(-1))
+    x = np.zeros_like(b) if x0 is None else _c128(np.asarray(x0).reshape(-1)).copy()
+    r = b - A(x)
+    nb = np.linalg.norm(b)
+    if nb == 0.0:
+        return x, 0
+    z = M(r)
+    pv = z.copy()
+    rho = np.sum(r * z)
+    for it in range(1, maxit + 1):
+        q = A(pv)
+        a = rho / np.sum(pv * q)
+        x += a * pv
+        r -= a * q
+        if np.linalg.norm(r) <= tol * nb:
+            return x, it
+        z = M(r)
+        rho_new = np.sum(r * z)
+        pv = z + (rho_new / rho) * pv
+        rho = rho_new
+    raise OracleError("cn_solve_2d: no convergence to %g in %d iterations" % (tol, maxit))
+
+
+def propagate_2d(m2, psi0, E, dt, nsteps, tol=1e-14):
+    """Crank-Nicolson propagation in 2D (section V.B with Ebar_n =
+    (E_n + E_{n+1})/2): returns obs[n] = (nu_n, d_n) = (c^H S2 c, Re c^H D2 c)
+    for n = 0..nsteps and the final state (shape (Ny, Nx))."""
+    alpha = 0.5 * dt
+    c = _c128(np.asarray(psi0).reshape(-1)).copy()
+    fdm = _fdm_factors(m2)
+    obs = np.zeros((nsteps + 1, 2))
+    for n in range(nsteps + 1):
+        Sc = apply_2d(m2, c, 1.0, 0.0, 0.0, with_V=False)
+        # D2 c = (T2 + V2 + 1 * D2) c - (T2 + V2) c
+        Dc = apply_2d(m2, c, 0.0, 1.0, 1.0) - apply_2d(m2, c, 0.0, 1.0, 0.0)
+        obs[n, 0] = np.real(np.vdot(c, Sc))
+        obs[n, 1] = np.real(np.vdot(c, Dc))
+        if n == nsteps:
+            break
+        Eb = 0.5 * (E[n] + E[n + 1])
+        rhs = apply_2d(m2, c, 1.0, -1j * alpha, Eb)
+        c, _ = cn_solve_2d(m2, rhs, alpha, Eb, x0=c, fdm=fdm, tol=tol)
+    return obs, c.reshape(m2["Ny"], m2["Nx"])

@@ -23,7 +23,9 @@
  *   - a real symmetric banded matrix M is stored as its upper half band,
  *     diagonal-major: band[d*N + i] = M[i][i+d] for d = 0..p and
  *     i = 0..N-1-d (entries with i+d >= N are zero);
- *   - complex vectors are interleaved (re, im) pairs of doubles.
+ *   - complex vectors are interleaved (re, im) pairs of doubles;
+ *   - two-dimensional problems use the tensor product of the reduced 1D
+ *     bases, unknown (iy, ix) at row-major index iy*Nx + ix.
  */
 #include <complex.h>
 #include <math.h>
@@ -838,4 +840,140 @@ int orc_adjoint(int N, int p, const double *S, const double *H0, const double *D
     }
     free(C); free(A); free(B); free(lam); free(z); free(t1); free(t2); free(dEb);
     return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Two dimensions: tensor-product basis N_ix(x) N_iy(y) of the reduced 1D   */
+/* bases on each axis (section II.C, eq. tensor3d with two factors),         */
+/* constant mass.  Unknown (iy, ix) has the row-major index iy*Nx + ix.      */
+/* With the 1D half bands of each axis (orc_assemble with V = 0):            */
+/*   S2 = Sx (x) Sy,  T2 = Tx (x) Sy + Sx (x) Ty,  D2 = Dx (x) Sy,           */
+/* and the potential matrix, which does not factor, is computed here by the */
+/* tensor Gauss rule on every pair of spans:                                 */
+/*   V2[(iy,ix),(jy,jx)] = sum_q wx wy V(xq, yq) N_ix N_jx (xq) N_iy N_jy (yq) */
+/* stored as a (2p+1)^2 stencil per row:                                     */
+/*   V2[row*(2p+1)^2 + (dy+p)*(2p+1) + (dx+p)],  jy = iy+dy, jx = ix+dx.    */
+/* V_q holds the caller's samples of V on the tensor grid of the per-axis    */
+/* quadrature points, V_q[qy * nqx + qx] with nqx = (nbrx-1)*nq.  Within a   */
+/* pair of spans the x quadrature sum is taken first (a reassociation of the */
+/* same tensor sum).                                                         */
+/* ------------------------------------------------------------------------ */
+int orc_assemble_v2(const double *brx, int nbrx, const double *bry, int nbry, int order, int nq,
+                    const double *V_q, double *V2)
+{
+    if (check_breaks(brx, nbrx) != ORC_OK || check_breaks(bry, nbry) != ORC_OK || order < 2 ||
+        order > 15 || nq < 1 || nq > 64)
+        return ORC_EINVAL;
+    int p = order - 1, w2 = 2 * p + 1;
+    int Nx = orc_ndof(nbrx, order), Ny = orc_ndof(nbry, order);
+    if (Nx < 1 || Ny < 1) return ORC_EINVAL;
+    int nelx = nbrx - 1, nely = nbry - 1, nqx = nelx * nq;
+    memset(V2, 0, sizeof(double) * (size_t)Nx * Ny * w2 * w2);
+    double *tx = malloc(sizeof(double) * (nbrx + 2 * p)), *ty = malloc(sizeof(double) * (nbry + 2 * p));
+    double *xq = malloc(sizeof(double) * nqx), *wxq = malloc(sizeof(double) * nqx);
+    double *yq = malloc(sizeof(double) * nely * nq), *wyq = malloc(sizeof(double) * nely * nq);
+    double *Bx = malloc(sizeof(double) * (size_t)nqx * (p + 1));      /* Bx[qx*(p+1)+a] */
+    double *By = malloc(sizeof(double) * (size_t)nely * nq * (p + 1));
+    double *W = malloc(sizeof(double) * (size_t)(p + 1) * (p + 1) * nq);
+    if (!tx || !ty || !xq || !wxq || !yq || !wyq || !Bx || !By || !W) {
+        free(tx); free(ty); free(xq); free(wxq); free(yq); free(wyq); free(Bx); free(By); free(W);
+        return ORC_ENOMEM;
+    }
+    make_knots(brx, nbrx, order, tx);
+    make_knots(bry, nbry, order, ty);
+    orc_quad_points(brx, nbrx, nq, xq, wxq);
+    orc_quad_points(bry, nbry, nq, yq, wyq);
+    double dv[16];
+    for (int e = 0; e < nelx; ++e)
+        for (int q = 0; q < nq; ++q)
+            bspline_span_eval(tx, order, p + e, xq[e * nq + q], Bx + (size_t)(e * nq + q) * (p + 1), dv);
+    for (int e = 0; e < nely; ++e)
+        for (int q = 0; q < nq; ++q)
+            bspline_span_eval(ty, order, p + e, yq[e * nq + q], By + (size_t)(e * nq + q) * (p + 1), dv);
+    for (int ey = 0; ey < nely; ++ey) {
+        for (int ex = 0; ex < nelx; ++ex) {
+            /* W[a][b][qy] = sum_qx wx V N_a N_b (x part of the span pair) */
+            for (int a = 0; a <= p; ++a)
+                for (int b = 0; b <= p; ++b)
+                    for (int qy = 0; qy < nq; ++qy) {
+                        double s = 0.0;
+                        int iy = ey * nq + qy;
+                        for (int qx = 0; qx < nq; ++qx) {
+                            int ix = ex * nq + qx;
+                            s += wxq[ix] * V_q[(size_t)iy * nqx + ix] * Bx[(size_t)ix * (p + 1) + a] *
+                                 Bx[(size_t)ix * (p + 1) + b];
+                        }
+                        W[((size_t)a * (p + 1) + b) * nq + qy] = s;
+                    }
+            for (int c = 0; c <= p; ++c) {
+                int iy = ey + c - 1;
+                if (iy < 0 || iy >= Ny) continue;
+                for (int d = 0; d <= p; ++d) {
+                    int jy = ey + d - 1;
+                    if (jy < 0 || jy >= Ny) continue;
+                    for (int a = 0; a <= p; ++a) {
+                        int ix = ex + a - 1;
+                        if (ix < 0 || ix >= Nx) continue;
+                        for (int b = 0; b <= p; ++b) {
+                            int jx = ex + b - 1;
+                            if (jx < 0 || jx >= Nx) continue;
+                            double s = 0.0;
+                            for (int qy = 0; qy < nq; ++qy) {
+                                int q = ey * nq + qy;
+                                s += wyq[q] * By[(size_t)q * (p + 1) + c] * By[(size_t)q * (p + 1) + d] *
+                                     W[((size_t)a * (p + 1) + b) * nq + qy];
+                            }
+                            size_t row = (size_t)iy * Nx + ix;
+                            V2[row * w2 * w2 + (size_t)(jy - iy + p) * w2 + (jx - ix + p)] += s;
+                        }
+                    }
+                }
+            }
+        }
+    }
+    free(tx); free(ty); free(xq); free(wxq); free(yq); free(wyq); free(Bx); free(By); free(W);
+    return ORC_OK;
+}
+
+/* entry M[i][j] of a real symmetric half band (zero outside the band) */
+static double band_at(int N, int p, const double *M, int i, int j)
+{
+    int d = j > i ? j - i : i - j, lo = j > i ? i : j;
+    if (d > p || lo < 0 || lo + d >= N) return 0.0;
+    return M[(size_t)d * N + lo];
+}
+
+/* y = a S2 c + b (T2 + V2 + Ebar D2) c for complex a, b (section V.B: with
+ * a = 1, b = -+i dt/2 these are the two sides of eq. cn_system in 2D).  c, y:
+ * interleaved complex, row-major (iy, ix).  V2 may be NULL (no potential). */
+int orc_apply_2d(int Nx, int Ny, int p, const double *Sx, const double *Tx, const double *Dx,
+                 const double *Sy, const double *Ty, const double *V2, double are, double aim, double bre,
+                 double bim, double Ebar, const double *cin, double *yout)
+{
+    if (Nx < 1 || Ny < 1 || p < 1) return ORC_EINVAL;
+    int w2 = 2 * p + 1;
+    const zd *c = (const zd *)cin;
+    zd *y = (zd *)yout;
+    zd a = are + I * aim, b = bre + I * bim;
+    for (int iy = 0; iy < Ny; ++iy)
+        for (int ix = 0; ix < Nx; ++ix) {
+            zd s = 0.0;
+            size_t row = (size_t)iy * Nx + ix;
+            for (int dy = -p; dy <= p; ++dy) {
+                int jy = iy + dy;
+                if (jy < 0 || jy >= Ny) continue;
+                double sy = band_at(Ny, p, Sy, iy, jy), ty = band_at(Ny, p, Ty, iy, jy);
+                for (int dx = -p; dx <= p; ++dx) {
+                    int jx = ix + dx;
+                    if (jx < 0 || jx >= Nx) continue;
+                    double sx = band_at(Nx, p, Sx, ix, jx), tx = band_at(Nx, p, Tx, ix, jx);
+                    double ddx = band_at(Nx, p, Dx, ix, jx);
+                    double h = tx * sy + sx * ty + Ebar * ddx * sy;
+                    if (V2) h += V2[row * w2 * w2 + (size_t)(dy + p) * w2 + (dx + p)];
+                    s += (a * sx * sy + b * h) * c[(size_t)jy * Nx + jx];
+                }
+            }
+            y[row] = s;
+        }
+    return ORC_OK;
 }

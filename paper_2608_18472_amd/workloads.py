@@ -241,6 +241,44 @@ def config3(nsys=1024, seed=0):
     return out
 
 
+@dataclass
+class System2D:
+    """Tensor-product 2D problem with constant mass and an x-polarised field."""
+    name: str
+    breaks_x: np.ndarray
+    breaks_y: np.ndarray
+    order: int
+    V: Callable  # V(x, y), vectorised
+    nq: int = 10
+    E: Optional[np.ndarray] = None
+    dt: float = 0.0
+    nsteps: int = 0
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def p(self):
+        return self.order - 1
+
+    @property
+    def nx(self):
+        return len(self.breaks_x) - 1 + self.p - 2
+
+    @property
+    def ny(self):
+        return len(self.breaks_y) - 1 + self.p - 2
+
+
+def config4(n=512, nsteps=None, L=120.0, order=6):
+    """2D soft-Coulomb atom V = -1/sqrt(x^2 + y^2 + 1): order 6, n unknowns per
+    axis on [-L, L]^2 (n - p + 2 uniform spans), x-polarised 4-cycle sin^2
+    pulse E0 = 0.05, w = 0.057, dt = 0.05 (8819 steps for the whole pulse)."""
+    p = order - 1
+    br = breaks_uniform(L, n - p + 2)
+    E, ns, Tp = sin2_pulse(0.05, 0.057, 4, 0.05, nsteps)
+    return System2D("soft-coulomb-2d", br, br.copy(), order, lambda x, y: -1.0 / np.sqrt(x * x + y * y + 1.0),
+                    10, E, 0.05, ns, {"E0": 0.05, "omega": 0.057, "Tp": Tp})
+
+
 def config5(nsys=64, N=1500, nsteps=20000, ntheta=64, seed=1, wb_nm=4.0):
     """Batch for the pulse-gradient workload: config2 double quantum wells
     (all systems share the geometry) driven by Fourier pulses
