@@ -224,6 +224,45 @@ tdsez_status tdsez_adjoint_batched(tdsez_batch b, const double* psi0_packed, con
                                    const double* dJdobs_packed, const long* obs_off, double* dJdE_packed,
                                    double* dJdpsi0_packed, int ckpt_stride, void* stream);
 
+/* ------------------------------------------------------------------ 2D
+ * Tensor-product problem on [x breakpoints] x [y breakpoints] with the same
+ * order on both axes, constant mass, x-polarised field (section II.C eq.
+ * tensor3d with two factors; section V.B for the step).  Unknown (iy, ix)
+ * is N_ix(x) N_iy(y) of the reduced 1D bases, row-major index iy*Nx + ix.
+ * S2 = Sx(x)Sy, T2 = Tx(x)Sy + Sx(x)Ty, D2 = Dx(x)Sy, and the potential
+ * matrix V2[(iy,ix),(jy,jx)] = sum_q wx wy V N_ix N_jx N_iy N_jy by the
+ * tensor Gauss rule. */
+typedef struct tdsez_system2d_s* tdsez_system2d;
+
+/* Assemble a 2D problem on the device.  V_q: host FP64 samples of V at the
+ * tensor grid of the per-axis quadrature points (tdsez_quad_points of each
+ * axis), V_q[qy * nqx + qx], nqx = (nbx-1)*nq, nqy = (nby-1)*nq (copied).
+ * Also computes, once, the per-axis generalised eigendecompositions
+ * T Q = S Q Lambda used by the preconditioner.  Needs at least 2p+1
+ * unknowns per axis; order <= 8.  Synchronous. */
+tdsez_status tdsez_assemble_2d(const double* breaks_x, int nbx, const double* breaks_y, int nby, int order, int nq,
+                               const double* V_q, tdsez_system2d* out);
+tdsez_status tdsez_system2d_size(tdsez_system2d s, int* nx, int* ny, int* halfbw);
+/* Potential matrix as a (2p+1)^2 stencil per row (host FP64, caller-owned):
+ * out[row*(2p+1)^2 + (dy+p)*(2p+1) + (dx+p)] = V2[row][(iy+dy)*Nx + ix+dx]. */
+tdsez_status tdsez_get_v2(tdsez_system2d s, double* host_out);
+/* Crank-Nicolson propagation of psi (device complex128 [Ny][Nx], in/out)
+ * over nsteps steps of dt with E (device FP64 [nsteps+1]).  Each step solves
+ * A_n (c_{n+1} - c_n) = -i dt H_n c_n by COCG preconditioned with the exact
+ * inverse of S2 + i dt/2 T2 (per-axis eigenvectors, GEMMs on the matrix
+ * cores), to relative residual tol (at most maxit iterations, else
+ * ENOCONV).  obs: TDSEZ_OBS_NORM | TDSEZ_OBS_DIPOLE (x dipole);
+ * obs_out[n*3 + 0..2] = (nu_n, d_n, 0) on the device.  FP64 only
+ * (TDSEZ_FP32_REFINED: EUNSUPPORTED).  Enqueued on `stream`, but the host
+ * waits for the iteration scalars, so the call returns when done. */
+tdsez_status tdsez_propagate_2d(tdsez_system2d s, double* psi, const double* E, double dt, int nsteps,
+                                tdsez_precision prec, unsigned obs, double* obs_out, double tol, int maxit,
+                                void* stream);
+/* Steps and COCG iterations of the 2D propagations since the last call, and
+ * the largest iteration count of one step; resets the counters. */
+tdsez_status tdsez_system2d_stats(tdsez_system2d s, long* steps, long* iterations, int* max_iterations);
+void tdsez_system2d_destroy(tdsez_system2d s);
+
 /* Phase profile of the last propagation of a profiled batch (see
  * tdsez_batch_set "profile").  Synchronises `stream`; out[9*s + 0..8] =
  * average shader-clock cycles per time step spent by system s in: the

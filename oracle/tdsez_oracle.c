@@ -950,15 +950,21 @@ int orc_apply_2d(int Nx, int Ny, int p, const double *Sx, const double *Tx, cons
                  const double *Sy, const double *Ty, const double *V2, double are, double aim, double bre,
                  double bim, double Ebar, const double *cin, double *yout)
 {
-    if (Nx < 1 || Ny < 1 || p < 1) return ORC_EINVAL;
+    if (Nx < 1 || Ny < 1 || p < 1 || p > 15) return ORC_EINVAL;
     int w2 = 2 * p + 1;
     const zd *c = (const zd *)cin;
     zd *y = (zd *)yout;
     zd a = are + I * aim, b = bre + I * bim;
+    double sxv[31], txv[31], dxv[31];
     for (int iy = 0; iy < Ny; ++iy)
         for (int ix = 0; ix < Nx; ++ix) {
             zd s = 0.0;
             size_t row = (size_t)iy * Nx + ix;
+            for (int dx = -p; dx <= p; ++dx) { /* row ix of the x factors */
+                sxv[dx + p] = band_at(Nx, p, Sx, ix, ix + dx);
+                txv[dx + p] = band_at(Nx, p, Tx, ix, ix + dx);
+                dxv[dx + p] = band_at(Nx, p, Dx, ix, ix + dx);
+            }
             for (int dy = -p; dy <= p; ++dy) {
                 int jy = iy + dy;
                 if (jy < 0 || jy >= Ny) continue;
@@ -966,8 +972,7 @@ int orc_apply_2d(int Nx, int Ny, int p, const double *Sx, const double *Tx, cons
                 for (int dx = -p; dx <= p; ++dx) {
                     int jx = ix + dx;
                     if (jx < 0 || jx >= Nx) continue;
-                    double sx = band_at(Nx, p, Sx, ix, jx), tx = band_at(Nx, p, Tx, ix, jx);
-                    double ddx = band_at(Nx, p, Dx, ix, jx);
+                    double sx = sxv[dx + p], tx = txv[dx + p], ddx = dxv[dx + p];
                     double h = tx * sy + sx * ty + Ebar * ddx * sy;
                     if (V2) h += V2[row * w2 * w2 + (size_t)(dy + p) * w2 + (dx + p)];
                     s += (a * sx * sy + b * h) * c[(size_t)jy * Nx + jx];

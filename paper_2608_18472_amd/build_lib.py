@@ -6,7 +6,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["tdsez_api.hip", "tdsez_assemble.hip", "tdsez_eigen.hip", "tdsez_propagate.hip", "tdsez_adjoint.hip"]
+SOURCES = ["tdsez_api.hip", "tdsez_assemble.hip", "tdsez_eigen.hip", "tdsez_propagate.hip", "tdsez_adjoint.hip",
+           "tdsez_2d.hip"]
 LIB = os.path.join(HERE, "libtdsez.so")
 
 HIPCC_FLAGS = [
@@ -40,7 +41,10 @@ def build(verbose=False, jobs=4):
         if p.wait() != 0:
             raise RuntimeError("hipcc failed on %s" % s)
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
+    # rocBLAS (per-axis GEMMs of the 2D preconditioner) and rocSOLVER (its
+    # one-off generalised eigendecompositions)
+    cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs + [
+        "-L/opt/rocm/lib", "-lrocblas", "-lrocsolver", "-Wl,-rpath,/opt/rocm/lib"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

@@ -1,0 +1,738 @@
+// Two-dimensional tensor-product propagation (constant mass, x-polarised
+// field): Crank-Nicolson steps of section V.B on the basis N_ix(x) N_iy(y).
+//
+// Matrices, with the 1D half bands of each axis (tdsez_assemble.hip) and the
+// non-separable potential stencil assembled here:
+//   S2 = Sx (x) Sy,  T2 = Tx (x) Sy + Sx (x) Ty,  D2 = Dx (x) Sy,
+//   V2[(iy,ix),(jy,jx)] = sum_q wx wy V(x_q, y_q) N_ix N_jx N_iy N_jy.
+// Unknown (iy, ix) has the row-major index iy*Nx + ix.  Complex vectors are
+// held planar on the device (real plane, then imaginary plane, each Ny x Nx
+// row-major) so that the per-axis transforms are plain real GEMMs.
+//
+// Each step solves the increment form A_n Delta = -i dt H_n c_n with
+// A_n = S2 + i a H_n, H_n = T2 + V2 + Ebar_n D2, a = dt/2, by conjugate-
+// orthogonal CG (A_n is complex symmetric) preconditioned with the exact
+// inverse of the separable part P = S2 + i a T2: with T Q = S Q Lambda and
+// Q^T S Q = I on each axis (generalised eigendecomposition, once per system),
+//   P^-1 R = Q_y [ (Q_y^T R Q_x) / (1 + i a (mu_iy + lambda_ix)) ] Q_x^T,
+// i.e. four real GEMMs per plane on the matrix cores and a diagonal scaling.
+// The field and the potential are the only parts left to the iteration.  The
+// operator itself is one stencil kernel over the (2p+1)^2 neighbours of every
+// unknown: the separable parts from the per-axis bands, V2 from a half
+// stencil (symmetric: the other half is read from the neighbour's row).
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "tdsez_internal.hpp"
+
+struct tdsez_system2d_s;
+
+namespace tdsez {
+
+__global__ void basis_kernel(const double* __restrict__ br, int nbr, int p, int nq,
+                             const double* __restrict__ xq, double* __restrict__ Bv,
+                             double* __restrict__ dB);
+
+namespace {
+
+// number of stored stencil offsets: (dy, dx) with dy > 0, or dy == 0 and dx >= 0
+__host__ __device__ inline int half_count(int p) { return (p + 1) + p * (2 * p + 1); }
+// index of a stored offset
+__host__ __device__ inline int half_index(int p, int dy, int dx) {
+    return dy == 0 ? dx : (p + 1) + (dy - 1) * (2 * p + 1) + (dx + p);
+}
+
+// M[i][j] of a 1D lower half band by rows (band[j*(p+1) + d] = M[j][j-d])
+__device__ inline double band_ij(const double* __restrict__ band, int p, int i, int j) {
+    const int hi = i > j ? i : j;
+    const int d = i > j ? i - j : j - i;
+    return band[hi * (p + 1) + d];
+}
+
+// V2 half stencil, one thread per (row, stored offset).  Sums over the spans
+// shared by the two x B-splines and by the two y B-splines, x innermost.
+__global__ void v2_kernel(int Nx, int Ny, int p, int nq, int nelx, int nely, const double* __restrict__ brx,
+                          const double* __restrict__ bry, const double* __restrict__ gw,
+                          const double* __restrict__ Bx, const double* __restrict__ By,
+                          const double* __restrict__ Vq, double* __restrict__ V2h) {
+    const int nh = half_count(p);
+    const long long total = (long long)Nx * Ny * nh;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+         e += (long long)gridDim.x * blockDim.x) {
+        const int h = (int)(e / ((long long)Nx * Ny));
+        const long long row = e % ((long long)Nx * Ny);
+        const int iy = (int)(row / Nx), ix = (int)(row % Nx);
+        int dy, dx;
+        if (h <= p) {
+            dy = 0;
+            dx = h;
+        } else {
+            dy = 1 + (h - p - 1) / (2 * p + 1);
+            dx = (h - p - 1) % (2 * p + 1) - p;
+        }
+        const int jy = iy + dy, jx = ix + dx;
+        double sum = 0.0;
+        if (jy < Ny && jx >= 0 && jx < Nx) {
+            // global B-spline indices are unknown + 1
+            const int gxa = ix + 1, gxb = jx + 1, gya = iy + 1, gyb = jy + 1;
+            const int gxh = gxa > gxb ? gxa : gxb, gxl = gxa > gxb ? gxb : gxa;
+            const int gyh = gya > gyb ? gya : gyb, gyl = gya > gyb ? gyb : gya;
+            const int ex0 = gxh - p > 0 ? gxh - p : 0, ex1 = gxl < nelx - 1 ? gxl : nelx - 1;
+            const int ey0 = gyh - p > 0 ? gyh - p : 0, ey1 = gyl < nely - 1 ? gyl : nely - 1;
+            const int nqx = nelx * nq;
+            for (int ey = ey0; ey <= ey1; ++ey) {
+                const double hy = 0.5 * (bry[ey + 1] - bry[ey]);
+                for (int qy = 0; qy < nq; ++qy) {
+                    const long long iqy = (long long)ey * nq + qy;
+                    const double wy = gw[qy] * hy * By[iqy * (p + 1) + (gya - ey)] * By[iqy * (p + 1) + (gyb - ey)];
+                    double sx = 0.0;
+                    for (int ex = ex0; ex <= ex1; ++ex) {
+                        const double hx = 0.5 * (brx[ex + 1] - brx[ex]);
+                        for (int qx = 0; qx < nq; ++qx) {
+                            const long long iqx = (long long)ex * nq + qx;
+                            sx += gw[qx] * hx * Bx[iqx * (p + 1) + (gxa - ex)] * Bx[iqx * (p + 1) + (gxb - ex)] *
+                                  Vq[iqy * nqx + iqx];
+                        }
+                    }
+                    sum += wy * sx;
+                }
+            }
+        }
+        V2h[e] = sum;
+    }
+}
+
+// lower half band by rows -> dense symmetric (column-major = row-major)
+__global__ void band_to_dense_kernel(const double* __restrict__ band, int N, int p, double* __restrict__ out) {
+    const long long total = (long long)N * N;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+         e += (long long)gridDim.x * blockDim.x) {
+        const int i = (int)(e / N), j = (int)(e % N);
+        const int d = i > j ? i - j : j - i;
+        out[e] = d <= p ? band_ij(band, p, i, j) : 0.0;
+    }
+}
+
+// natural interleaved complex <-> planar
+__global__ void to_planar_kernel(const double* __restrict__ z, long long n, double* __restrict__ re,
+                                 double* __restrict__ im) {
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x) {
+        re[e] = z[2 * e];
+        im[e] = z[2 * e + 1];
+    }
+}
+__global__ void from_planar_kernel(const double* __restrict__ re, const double* __restrict__ im, long long n,
+                                   double* __restrict__ z) {
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x) {
+        z[2 * e] = re[e];
+        z[2 * e + 1] = im[e];
+    }
+}
+
+constexpr int kTile = 16;          // output tile edge of the stencil kernel
+constexpr int kStencilThreads = kTile * kTile;
+
+struct Cd {
+    double re, im;
+};
+__device__ inline Cd cd_mul(Cd a, Cd b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+
+// out = w * y + a S2 c + b (T2 + V2 + Ebar D2) c   (all planar complex; y may
+// be null).  With obs != null each block also writes partial sums of
+// Re c^H S2 c and Re c^H D2 c (the observables of c).
+template <int PP>
+__global__ __launch_bounds__(kStencilThreads) void apply_kernel(
+    int Nx, int Ny, const double* __restrict__ Sxb, const double* __restrict__ Txb,
+    const double* __restrict__ Dxb, const double* __restrict__ Syb, const double* __restrict__ Tyb,
+    const double* __restrict__ V2h, const double* __restrict__ cre, const double* __restrict__ cim,
+    const double* __restrict__ yre, const double* __restrict__ yim, double wre, double wim, double are,
+    double aim, double bre, double bim, double Ebar, double* __restrict__ ore, double* __restrict__ oim,
+    double* __restrict__ obs) {
+    constexpr int W = kTile + 2 * PP;
+    constexpr int NH = (PP + 1) + PP * (2 * PP + 1);
+    __shared__ double tre[W][W], tim[W][W];
+    __shared__ double red[2][kStencilThreads];
+    const int tx = threadIdx.x % kTile, ty = threadIdx.x / kTile;
+    const int x0 = blockIdx.x * kTile, y0 = blockIdx.y * kTile;
+    const long long plane = (long long)Nx * Ny;
+    for (int t = threadIdx.x; t < W * W; t += kStencilThreads) {
+        const int ly = t / W, lx = t % W;
+        const int gy = y0 + ly - PP, gx = x0 + lx - PP;
+        double vr = 0.0, vi = 0.0;
+        if (gy >= 0 && gy < Ny && gx >= 0 && gx < Nx) {
+            vr = cre[(long long)gy * Nx + gx];
+            vi = cim[(long long)gy * Nx + gx];
+        }
+        tre[ly][lx] = vr;
+        tim[ly][lx] = vi;
+    }
+    __syncthreads();
+    const int ix = x0 + tx, iy = y0 + ty;
+    const bool inside = ix < Nx && iy < Ny;
+    double nu = 0.0, dip = 0.0;
+    if (inside) {
+        const Cd a = {are, aim}, b = {bre, bim};
+        // x factors: X1 = a Sx + b (Tx + Ebar Dx), X2 = b Sx; observables use Sx, Dx
+        Cd X1[2 * PP + 1], X2[2 * PP + 1];
+        double sxv[2 * PP + 1], dxv[2 * PP + 1];
+#pragma unroll
+        for (int k = 0; k <= 2 * PP; ++k) {
+            const int jx = ix + k - PP;
+            double s = 0.0, t = 0.0, d = 0.0;
+            if (jx >= 0 && jx < Nx) {
+                s = band_ij(Sxb, PP, ix, jx);
+                t = band_ij(Txb, PP, ix, jx);
+                d = band_ij(Dxb, PP, ix, jx);
+            }
+            sxv[k] = s;
+            dxv[k] = d;
+            const double h = t + Ebar * d;
+            X1[k] = {a.re * s + b.re * h, a.im * s + b.im * h};
+            X2[k] = {b.re * s, b.im * s};
+        }
+        const long long row = (long long)iy * Nx + ix;
+        double accr = 0.0, acci = 0.0, sr = 0.0, si = 0.0, dr = 0.0, di = 0.0;
+#pragma unroll
+        for (int ky = 0; ky <= 2 * PP; ++ky) {
+            const int dy = ky - PP, jy = iy + dy;
+            if (jy < 0 || jy >= Ny) continue;
+            const double sy = band_ij(Syb, PP, iy, jy), tyv = band_ij(Tyb, PP, iy, jy);
+#pragma unroll
+            for (int kx = 0; kx <= 2 * PP; ++kx) {
+                const int dx = kx - PP, jx = ix + dx;
+                if (jx < 0 || jx >= Nx) continue;
+                // V2 entry: stored at this row or, mirrored, at the neighbour's
+                double v;
+                if (dy > 0 || (dy == 0 && dx >= 0))
+                    v = V2h[(long long)half_index(PP, dy, dx) * plane + row];
+                else
+                    v = V2h[(long long)half_index(PP, -dy, -dx) * plane + (long long)jy * Nx + jx];
+                const double cr = sy * X1[kx].re + tyv * X2[kx].re + b.re * v;
+                const double ci = sy * X1[kx].im + tyv * X2[kx].im + b.im * v;
+                const double zr = tre[ty + ky][tx + kx], zi = tim[ty + ky][tx + kx];
+                accr += cr * zr - ci * zi;
+                acci += cr * zi + ci * zr;
+                if (obs) {
+                    const double s2 = sy * sxv[kx], d2 = sy * dxv[kx];
+                    sr += s2 * zr;
+                    si += s2 * zi;
+                    dr += d2 * zr;
+                    di += d2 * zi;
+                }
+            }
+        }
+        (void)NH;
+        if (yre) {
+            const double vr = yre[row], vi = yim[row];
+            accr += wre * vr - wim * vi;
+            acci += wre * vi + wim * vr;
+        }
+        ore[row] = accr;
+        oim[row] = acci;
+        if (obs) {
+            const double c0r = tre[ty + PP][tx + PP], c0i = tim[ty + PP][tx + PP];
+            nu = c0r * sr + c0i * si;
+            dip = c0r * dr + c0i * di;
+        }
+    }
+    if (obs) {
+        red[0][threadIdx.x] = nu;
+        red[1][threadIdx.x] = dip;
+        __syncthreads();
+        for (int s = kStencilThreads / 2; s > 0; s >>= 1) {
+            if (threadIdx.x < s) {
+                red[0][threadIdx.x] += red[0][threadIdx.x + s];
+                red[1][threadIdx.x] += red[1][threadIdx.x + s];
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            const long long blk = (long long)blockIdx.y * gridDim.x + blockIdx.x;
+            obs[2 * blk] = red[0][0];
+            obs[2 * blk + 1] = red[1][0];
+        }
+    }
+}
+
+constexpr int kRedThreads = 256;
+constexpr int kRedBlocks = 512;
+
+// partial sums over blocks: sum u v (complex, unconjugated) or sum |u|^2
+__global__ __launch_bounds__(kRedThreads) void dot_kernel(long long n, const double* __restrict__ ur,
+                                                          const double* __restrict__ ui,
+                                                          const double* __restrict__ vr,
+                                                          const double* __restrict__ vi, bool abs2,
+                                                          double* __restrict__ part) {
+    __shared__ double sr[kRedThreads], si[kRedThreads];
+    double ar = 0.0, ai = 0.0;
+    for (long long e = blockIdx.x * (long long)kRedThreads + threadIdx.x; e < n; e += (long long)gridDim.x * kRedThreads) {
+        if (abs2) {
+            ar += ur[e] * ur[e] + ui[e] * ui[e];
+        } else {
+            ar += ur[e] * vr[e] - ui[e] * vi[e];
+            ai += ur[e] * vi[e] + ui[e] * vr[e];
+        }
+    }
+    sr[threadIdx.x] = ar;
+    si[threadIdx.x] = ai;
+    __syncthreads();
+    for (int s = kRedThreads / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            sr[threadIdx.x] += sr[threadIdx.x + s];
+            si[threadIdx.x] += si[threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = sr[0];
+        part[2 * blockIdx.x + 1] = si[0];
+    }
+}
+
+// x += al p, r -= al q   (planar complex, al complex)
+__global__ void cocg_xr_kernel(long long n, double alr, double ali, const double* __restrict__ pr,
+                               const double* __restrict__ pi, const double* __restrict__ qr,
+                               const double* __restrict__ qi, double* __restrict__ xr, double* __restrict__ xi,
+                               double* __restrict__ rr, double* __restrict__ ri) {
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x) {
+        xr[e] += alr * pr[e] - ali * pi[e];
+        xi[e] += alr * pi[e] + ali * pr[e];
+        rr[e] -= alr * qr[e] - ali * qi[e];
+        ri[e] -= alr * qi[e] + ali * qr[e];
+    }
+}
+
+// p = z + be p
+__global__ void cocg_p_kernel(long long n, double ber, double bei, const double* __restrict__ zr,
+                              const double* __restrict__ zi, double* __restrict__ pr, double* __restrict__ pi) {
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x) {
+        const double a = pr[e], b = pi[e];
+        pr[e] = zr[e] + ber * a - bei * b;
+        pi[e] = zi[e] + ber * b + bei * a;
+    }
+}
+
+// c += x
+__global__ void add_kernel(long long n, const double* __restrict__ xr, const double* __restrict__ xi,
+                           double* __restrict__ cr, double* __restrict__ ci) {
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x) {
+        cr[e] += xr[e];
+        ci[e] += xi[e];
+    }
+}
+
+// Z (column-major Nx x Ny, both planes) /= 1 + i a (lambda_ix + mu_iy)
+__global__ void fdm_scale_kernel(int Nx, int Ny, double alpha, const double* __restrict__ lx,
+                                 const double* __restrict__ my, double* __restrict__ zr, double* __restrict__ zi) {
+    const long long n = (long long)Nx * Ny;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x) {
+        const int ix = (int)(e % Nx), iy = (int)(e / Nx);
+        const double t = alpha * (lx[ix] + my[iy]);
+        const double s = 1.0 / (1.0 + t * t);
+        const double a = zr[e], b = zi[e];
+        zr[e] = (a + t * b) * s;
+        zi[e] = (b - t * a) * s;
+    }
+}
+
+// observables: sum the per-block partials of apply_kernel in a fixed order
+__global__ void obs_finish_kernel(const double* __restrict__ part, int nblk, double* __restrict__ out, unsigned mask) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double nu = 0.0, d = 0.0;
+    for (int b = 0; b < nblk; ++b) {
+        nu += part[2 * b];
+        d += part[2 * b + 1];
+    }
+    out[0] = (mask & TDSEZ_OBS_NORM) ? nu : 0.0;
+    out[1] = (mask & TDSEZ_OBS_DIPOLE) ? d : 0.0;
+    out[2] = 0.0;
+}
+
+}  // namespace
+}  // namespace tdsez
+
+using namespace tdsez;
+
+struct tdsez_system2d_s {
+    SystemData ax, ay;         // per-axis 1D matrices (V = 0, m = 1)
+    int Nx = 0, Ny = 0, p = 0, order = 0, nq = 0;
+    double* d_V2h = nullptr;   // half stencil, [offset][row]
+    double* d_Qx = nullptr;    // generalised eigenvectors (column-major), T Q = S Q Lambda
+    double* d_Qy = nullptr;
+    double* d_lx = nullptr;
+    double* d_my = nullptr;
+    double* d_work = nullptr;  // planar vectors: c, x, r, z, p, q, b, t1, t2 (2 planes each)
+    double* d_part = nullptr;  // reduction partials
+    double* d_obs_part = nullptr;
+    rocblas_handle blas = nullptr;
+    long long iters_total = 0;
+    int iters_max = 0;
+    long long steps_total = 0;
+};
+
+namespace {
+
+tdsez_status blas_fail(rocblas_status s, const char* what) {
+    return fail(TDSEZ_EHIP, "%s failed: rocblas status %d", what, (int)s);
+}
+
+#define TD2_BLAS(expr)                                  \
+    do {                                                \
+        rocblas_status s_ = (expr);                     \
+        if (s_ != rocblas_status_success) return blas_fail(s_, #expr); \
+    } while (0)
+
+void free2d(tdsez_system2d_s* s) {
+    for (int m = 0; m < 6; ++m) {
+        (void)hipFree(s->ax.d_band[m]);
+        (void)hipFree(s->ay.d_band[m]);
+    }
+    (void)hipFree(s->ax.d_H0);
+    (void)hipFree(s->ay.d_H0);
+    (void)hipFree(s->d_V2h);
+    (void)hipFree(s->d_Qx);
+    (void)hipFree(s->d_Qy);
+    (void)hipFree(s->d_lx);
+    (void)hipFree(s->d_my);
+    (void)hipFree(s->d_work);
+    (void)hipFree(s->d_part);
+    (void)hipFree(s->d_obs_part);
+    if (s->blas) rocblas_destroy_handle(s->blas);
+}
+
+int grid_for(long long n) {
+    long long b = (n + 255) / 256;
+    return (int)(b < 2048 ? (b > 0 ? b : 1) : 2048);
+}
+
+// generalised eigendecomposition T Q = S Q Lambda of one axis (FP64, on the GPU)
+tdsez_status axis_eigen(tdsez_system2d_s* s, const SystemData& ax, double** d_Q, double** d_l) {
+    const int N = ax.N, p = ax.p;
+    double *dS = nullptr, *dE = nullptr;
+    rocblas_int* dinfo = nullptr;
+    TDSEZ_HIP_TRY(hipMalloc(d_Q, sizeof(double) * (size_t)N * N));
+    TDSEZ_HIP_TRY(hipMalloc(d_l, sizeof(double) * N));
+    TDSEZ_HIP_TRY(hipMalloc(&dS, sizeof(double) * (size_t)N * N));
+    TDSEZ_HIP_TRY(hipMalloc(&dE, sizeof(double) * N));
+    TDSEZ_HIP_TRY(hipMalloc(&dinfo, sizeof(rocblas_int)));
+    band_to_dense_kernel<<<grid_for((long long)N * N), 256>>>(ax.d_band[1], N, p, *d_Q);  // T
+    band_to_dense_kernel<<<grid_for((long long)N * N), 256>>>(ax.d_band[0], N, p, dS);    // S
+    TDSEZ_HIP_TRY(hipGetLastError());
+    rocblas_set_stream(s->blas, nullptr);
+    rocblas_status bs = rocsolver_dsygvd(s->blas, rocblas_eform_ax, rocblas_evect_original, rocblas_fill_upper, N,
+                                         *d_Q, N, dS, N, *d_l, dE, dinfo);
+    rocblas_int info = 0;
+    hipError_t he = hipMemcpy(&info, dinfo, sizeof(info), hipMemcpyDeviceToHost);
+    (void)hipFree(dS);
+    (void)hipFree(dE);
+    (void)hipFree(dinfo);
+    if (bs != rocblas_status_success) return blas_fail(bs, "rocsolver_dsygvd");
+    if (he != hipSuccess) return fail(TDSEZ_EHIP, "hipMemcpy failed: %s", hipGetErrorString(he));
+    if (info != 0) return fail(TDSEZ_ENOCONV, "per-axis generalised eigensolve failed (info %d)", (int)info);
+    return TDSEZ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+tdsez_status tdsez_assemble_2d(const double* breaks_x, int nbx, const double* breaks_y, int nby, int order, int nq,
+                               const double* V_q, tdsez_system2d* out) {
+    if (!out) return fail(TDSEZ_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!breaks_x || !breaks_y || !V_q) return fail(TDSEZ_EINVAL, "NULL argument");
+    if (order < 2) return fail(TDSEZ_EINVAL, "order must be >= 2");
+    if (order - 1 > kMaxP) return fail(TDSEZ_EUNSUPPORTED, "order %d > %d", order, kMaxP + 1);
+    if (nq < 1 || nq > 32) return fail(TDSEZ_EINVAL, "nq must be in 1..32");
+    for (int a = 0; a < 2; ++a) {
+        const double* br = a ? breaks_y : breaks_x;
+        const int nb = a ? nby : nbx;
+        if (nb < 2) return fail(TDSEZ_EINVAL, "need at least 2 breakpoints per axis");
+        for (int i = 0; i + 1 < nb; ++i)
+            if (!(br[i + 1] > br[i]) || !std::isfinite(br[i]) || !std::isfinite(br[i + 1]))
+                return fail(TDSEZ_EINVAL, "breakpoints must be finite and strictly increasing");
+    }
+    const int p = order - 1;
+    const int Nx = nbx - 1 + p - 2, Ny = nby - 1 + p - 2;
+    if (Nx < 2 * p + 1 || Ny < 2 * p + 1) return fail(TDSEZ_EINVAL, "need at least 2p+1 unknowns per axis");
+    const long long nqx = (long long)(nbx - 1) * nq, nqy = (long long)(nby - 1) * nq;
+    for (long long i = 0; i < nqx * nqy; ++i)
+        if (!std::isfinite(V_q[i])) return fail(TDSEZ_EINVAL, "V_q[%lld] is not finite", i);
+    auto* s = new tdsez_system2d_s();
+    s->Nx = Nx;
+    s->Ny = Ny;
+    s->p = p;
+    s->order = order;
+    s->nq = nq;
+    auto bail = [&](tdsez_status st) {
+        free2d(s);
+        delete s;
+        return st;
+    };
+    tdsez_status st = assemble_device(breaks_x, nbx, order, nq, nullptr, nullptr, nullptr, &s->ax);
+    if (st) return bail(st);
+    st = assemble_device(breaks_y, nby, order, nq, nullptr, nullptr, nullptr, &s->ay);
+    if (st) return bail(st);
+    if (rocblas_create_handle(&s->blas) != rocblas_status_success)
+        return bail(fail(TDSEZ_EHIP, "rocblas_create_handle failed"));
+    // V2: basis values at the quadrature points of each axis, then the stencil
+    {
+        double gx[32], gw[32];
+        gauss_legendre_host(nq, gx, gw);
+        std::vector<double> xq(nqx), yq(nqy);
+        for (int e = 0; e + 1 < nbx; ++e)
+            for (int q = 0; q < nq; ++q)
+                xq[(size_t)e * nq + q] = 0.5 * (breaks_x[e + 1] + breaks_x[e]) + 0.5 * (breaks_x[e + 1] - breaks_x[e]) * gx[q];
+        for (int e = 0; e + 1 < nby; ++e)
+            for (int q = 0; q < nq; ++q)
+                yq[(size_t)e * nq + q] = 0.5 * (breaks_y[e + 1] + breaks_y[e]) + 0.5 * (breaks_y[e + 1] - breaks_y[e]) * gx[q];
+        double *dbx = nullptr, *dby = nullptr, *dgw = nullptr, *dxq = nullptr, *dyq = nullptr, *dBx = nullptr,
+               *dBy = nullptr, *ddB = nullptr, *dVq = nullptr;
+        auto clean = [&]() {
+            (void)hipFree(dbx); (void)hipFree(dby); (void)hipFree(dgw); (void)hipFree(dxq); (void)hipFree(dyq);
+            (void)hipFree(dBx); (void)hipFree(dBy); (void)hipFree(ddB); (void)hipFree(dVq);
+        };
+        hipError_t he = hipSuccess;
+        auto H = [&](hipError_t e) { if (he == hipSuccess) he = e; };
+        H(hipMalloc(&dbx, sizeof(double) * nbx));
+        H(hipMalloc(&dby, sizeof(double) * nby));
+        H(hipMalloc(&dgw, sizeof(double) * nq));
+        H(hipMalloc(&dxq, sizeof(double) * nqx));
+        H(hipMalloc(&dyq, sizeof(double) * nqy));
+        H(hipMalloc(&dBx, sizeof(double) * nqx * (p + 1)));
+        H(hipMalloc(&dBy, sizeof(double) * nqy * (p + 1)));
+        H(hipMalloc(&ddB, sizeof(double) * (nqx > nqy ? nqx : nqy) * (p + 1)));
+        H(hipMalloc(&dVq, sizeof(double) * nqx * nqy));
+        H(hipMalloc(&s->d_V2h, sizeof(double) * (size_t)half_count(p) * Nx * Ny));
+        if (he == hipSuccess) {
+            H(hipMemcpy(dbx, breaks_x, sizeof(double) * nbx, hipMemcpyHostToDevice));
+            H(hipMemcpy(dby, breaks_y, sizeof(double) * nby, hipMemcpyHostToDevice));
+            H(hipMemcpy(dgw, gw, sizeof(double) * nq, hipMemcpyHostToDevice));
+            H(hipMemcpy(dxq, xq.data(), sizeof(double) * nqx, hipMemcpyHostToDevice));
+            H(hipMemcpy(dyq, yq.data(), sizeof(double) * nqy, hipMemcpyHostToDevice));
+            H(hipMemcpy(dVq, V_q, sizeof(double) * nqx * nqy, hipMemcpyHostToDevice));
+        }
+        if (he == hipSuccess) {
+            basis_kernel<<<grid_for(nqx), 256>>>(dbx, nbx, p, nq, dxq, dBx, ddB);
+            basis_kernel<<<grid_for(nqy), 256>>>(dby, nby, p, nq, dyq, dBy, ddB);
+            v2_kernel<<<4096, 256>>>(Nx, Ny, p, nq, nbx - 1, nby - 1, dbx, dby, dgw, dBx, dBy, dVq, s->d_V2h);
+            H(hipGetLastError());
+            H(hipDeviceSynchronize());
+        }
+        clean();
+        if (he != hipSuccess) return bail(fail(TDSEZ_EHIP, "2D assembly: %s", hipGetErrorString(he)));
+    }
+    st = axis_eigen(s, s->ax, &s->d_Qx, &s->d_lx);
+    if (st) return bail(st);
+    st = axis_eigen(s, s->ay, &s->d_Qy, &s->d_my);
+    if (st) return bail(st);
+    const long long plane = (long long)Nx * Ny;
+    if (hipMalloc(&s->d_work, sizeof(double) * (size_t)plane * 2 * 9) != hipSuccess ||
+        hipMalloc(&s->d_part, sizeof(double) * 2 * kRedBlocks) != hipSuccess ||
+        hipMalloc(&s->d_obs_part, sizeof(double) * 2 * (size_t)((Nx + kTile - 1) / kTile) * ((Ny + kTile - 1) / kTile)) !=
+            hipSuccess)
+        return bail(fail(TDSEZ_ENOMEM, "2D workspace allocation failed"));
+    *out = s;
+    return TDSEZ_OK;
+}
+
+tdsez_status tdsez_system2d_size(tdsez_system2d s, int* nx, int* ny, int* halfbw) {
+    if (!s) return fail(TDSEZ_EINVAL, "system is NULL");
+    if (nx) *nx = s->Nx;
+    if (ny) *ny = s->Ny;
+    if (halfbw) *halfbw = s->p;
+    return TDSEZ_OK;
+}
+
+tdsez_status tdsez_get_v2(tdsez_system2d s, double* host_out) {
+    if (!s || !host_out) return fail(TDSEZ_EINVAL, "NULL argument");
+    const int p = s->p, w = 2 * p + 1, nh = half_count(p);
+    const long long plane = (long long)s->Nx * s->Ny;
+    std::vector<double> h((size_t)nh * plane);
+    TDSEZ_HIP_TRY(hipMemcpy(h.data(), s->d_V2h, sizeof(double) * h.size(), hipMemcpyDeviceToHost));
+    for (int iy = 0; iy < s->Ny; ++iy)
+        for (int ix = 0; ix < s->Nx; ++ix) {
+            const long long row = (long long)iy * s->Nx + ix;
+            for (int dy = -p; dy <= p; ++dy)
+                for (int dx = -p; dx <= p; ++dx) {
+                    const int jy = iy + dy, jx = ix + dx;
+                    double v = 0.0;
+                    if (jy >= 0 && jy < s->Ny && jx >= 0 && jx < s->Nx) {
+                        if (dy > 0 || (dy == 0 && dx >= 0))
+                            v = h[(size_t)half_index(p, dy, dx) * plane + row];
+                        else
+                            v = h[(size_t)half_index(p, -dy, -dx) * plane + (long long)jy * s->Nx + jx];
+                    }
+                    host_out[row * w * w + (dy + p) * w + (dx + p)] = v;
+                }
+        }
+    return TDSEZ_OK;
+}
+
+tdsez_status tdsez_propagate_2d(tdsez_system2d s, double* psi, const double* E, double dt, int nsteps,
+                                tdsez_precision prec, unsigned obs, double* obs_out, double tol, int maxit,
+                                void* stream_v) {
+    if (!s || !psi || !E) return fail(TDSEZ_EINVAL, "NULL argument");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(TDSEZ_EINVAL, "dt must be > 0");
+    if (nsteps < 0) return fail(TDSEZ_EINVAL, "nsteps < 0");
+    if (obs & ~3u) return fail(TDSEZ_EINVAL, "2D observables: TDSEZ_OBS_NORM and TDSEZ_OBS_DIPOLE only");
+    if (obs && !obs_out) return fail(TDSEZ_EINVAL, "obs requested but obs_out is NULL");
+    if (prec == TDSEZ_FP32_REFINED) return fail(TDSEZ_EUNSUPPORTED, "the 2D path runs in FP64 only");
+    if (prec != TDSEZ_FP64) return fail(TDSEZ_EINVAL, "unknown precision %d", (int)prec);
+    if (!(tol > 0.0) || maxit < 1) return fail(TDSEZ_EINVAL, "tol must be > 0 and maxit >= 1");
+    hipStream_t stream = (hipStream_t)stream_v;
+    const int Nx = s->Nx, Ny = s->Ny, p = s->p;
+    const long long n = (long long)Nx * Ny;
+    double* w = s->d_work;
+    auto vre = [&](int k) { return w + (size_t)(2 * k) * n; };
+    auto vim = [&](int k) { return w + (size_t)(2 * k + 1) * n; };
+    enum { C = 0, X = 1, R = 2, Z = 3, PV = 4, Q = 5, B = 6, T1 = 7, T2 = 8 };
+    const int g = grid_for(n);
+    to_planar_kernel<<<g, 256, 0, stream>>>(psi, n, vre(C), vim(C));
+    TDSEZ_HIP_TRY(hipMemsetAsync(vre(X), 0, sizeof(double) * 2 * n, stream));
+    const dim3 sgrid((Nx + kTile - 1) / kTile, (Ny + kTile - 1) / kTile);
+    const int nblk = (int)(sgrid.x * sgrid.y);
+    const double alpha = 0.5 * dt;
+    const double* Sx = s->ax.d_band[0];
+    const double* Tx = s->ax.d_band[1];
+    const double* Dx = s->ax.d_band[3];
+    const double* Sy = s->ay.d_band[0];
+    const double* Ty = s->ay.d_band[1];
+    auto apply = [&](int in, int yv, double wr, double wi, double ar, double ai, double br, double bi, double Eb,
+                     int outv, double* obsp) {
+        const double* yr = yv >= 0 ? vre(yv) : nullptr;
+        const double* yi = yv >= 0 ? vim(yv) : nullptr;
+        switch (p) {
+#define TD2_CASE(PV_)                                                                                     \
+    case PV_:                                                                                             \
+        apply_kernel<PV_><<<sgrid, kStencilThreads, 0, stream>>>(Nx, Ny, Sx, Tx, Dx, Sy, Ty, s->d_V2h,     \
+                                                                 vre(in), vim(in), yr, yi, wr, wi, ar, ai, \
+                                                                 br, bi, Eb, vre(outv), vim(outv), obsp); \
+        break;
+            TD2_CASE(1) TD2_CASE(2) TD2_CASE(3) TD2_CASE(4) TD2_CASE(5) TD2_CASE(6) TD2_CASE(7)
+#undef TD2_CASE
+            default: break;
+        }
+    };
+    auto dot = [&](int u, int v, bool abs2, double out[2]) -> tdsez_status {
+        dot_kernel<<<kRedBlocks, kRedThreads, 0, stream>>>(n, vre(u), vim(u), vre(v), vim(v), abs2, s->d_part);
+        double h[2 * kRedBlocks];
+        TDSEZ_HIP_TRY(hipMemcpyAsync(h, s->d_part, sizeof(h), hipMemcpyDeviceToHost, stream));
+        TDSEZ_HIP_TRY(hipStreamSynchronize(stream));
+        out[0] = out[1] = 0.0;
+        for (int b = 0; b < kRedBlocks; ++b) {
+            out[0] += h[2 * b];
+            out[1] += h[2 * b + 1];
+        }
+        return TDSEZ_OK;
+    };
+    // z = P^-1 r
+    TD2_BLAS(rocblas_set_stream(s->blas, stream));
+    auto precond = [&](int rin, int zout) -> tdsez_status {
+        const double one = 1.0, zero = 0.0;
+        // column-major view: a planar Ny x Nx row-major plane is the Nx x Ny matrix R^T
+        TD2_BLAS(rocblas_dgemm_strided_batched(s->blas, rocblas_operation_transpose, rocblas_operation_none, Nx, Ny,
+                                               Nx, &one, s->d_Qx, Nx, 0, vre(rin), Nx, n, &zero, vre(T1), Nx, n, 2));
+        TD2_BLAS(rocblas_dgemm_strided_batched(s->blas, rocblas_operation_none, rocblas_operation_none, Nx, Ny, Ny,
+                                               &one, vre(T1), Nx, n, s->d_Qy, Ny, 0, &zero, vre(T2), Nx, n, 2));
+        fdm_scale_kernel<<<g, 256, 0, stream>>>(Nx, Ny, alpha, s->d_lx, s->d_my, vre(T2), vim(T2));
+        TD2_BLAS(rocblas_dgemm_strided_batched(s->blas, rocblas_operation_none, rocblas_operation_none, Nx, Ny, Nx,
+                                               &one, s->d_Qx, Nx, 0, vre(T2), Nx, n, &zero, vre(T1), Nx, n, 2));
+        TD2_BLAS(rocblas_dgemm_strided_batched(s->blas, rocblas_operation_none, rocblas_operation_transpose, Nx, Ny,
+                                               Ny, &one, vre(T1), Nx, n, s->d_Qy, Ny, 0, &zero, vre(zout), Nx, n, 2));
+        return TDSEZ_OK;
+    };
+    const long long stride = (long long)(vim(0) - vre(0));
+    (void)stride;
+    double obs_host[3];
+    for (int step = 0; step <= nsteps; ++step) {
+        double En, Enext;
+        TDSEZ_HIP_TRY(hipMemcpyAsync(&En, E + step, sizeof(double), hipMemcpyDeviceToHost, stream));
+        Enext = En;
+        if (step < nsteps) TDSEZ_HIP_TRY(hipMemcpyAsync(&Enext, E + step + 1, sizeof(double), hipMemcpyDeviceToHost, stream));
+        TDSEZ_HIP_TRY(hipStreamSynchronize(stream));
+        const double Eb = 0.5 * (En + Enext);
+        // b = -i dt H c (and the observables of c)
+        apply(C, -1, 0.0, 0.0, 0.0, 0.0, 0.0, -2.0 * alpha, Eb, B, s->d_obs_part);
+        if (obs) {
+            obs_finish_kernel<<<1, 1, 0, stream>>>(s->d_obs_part, nblk, obs_out + 3 * (size_t)step, obs);
+            TDSEZ_HIP_TRY(hipGetLastError());
+        }
+        if (step == nsteps) break;
+        // COCG on A x = b, A = S2 + i a H, warm start from the previous increment
+        apply(X, B, 1.0, 0.0, -1.0, 0.0, 0.0, -alpha, Eb, R, nullptr);  // r = b - A x
+        double bn[2], rn[2];
+        tdsez_status st;
+        if ((st = dot(B, B, true, bn))) return st;
+        if ((st = dot(R, R, true, rn))) return st;
+        const double stop = tol * tol * (bn[0] > 0.0 ? bn[0] : 1.0);
+        int it = 0;
+        if (rn[0] > stop) {
+            if ((st = precond(R, Z))) return st;
+            TDSEZ_HIP_TRY(hipMemcpyAsync(vre(PV), vre(Z), sizeof(double) * 2 * n, hipMemcpyDeviceToDevice, stream));
+            double rho[2];
+            if ((st = dot(R, Z, false, rho))) return st;
+            for (;;) {
+                ++it;
+                if (it > maxit) {
+                    return fail(TDSEZ_ENOCONV, "2D step %d: no convergence to %g in %d iterations (residual %g)", step,
+                                tol, maxit, std::sqrt(rn[0] / (bn[0] > 0 ? bn[0] : 1.0)));
+                }
+                apply(PV, -1, 0.0, 0.0, 1.0, 0.0, 0.0, alpha, Eb, Q, nullptr);  // q = A p
+                double pq[2];
+                if ((st = dot(PV, Q, false, pq))) return st;
+                const double den = pq[0] * pq[0] + pq[1] * pq[1];
+                if (!(den > 0.0) || !std::isfinite(den))
+                    return fail(TDSEZ_ENONFINITE, "2D step %d: COCG breakdown", step);
+                const double alr = (rho[0] * pq[0] + rho[1] * pq[1]) / den;
+                const double ali = (rho[1] * pq[0] - rho[0] * pq[1]) / den;
+                cocg_xr_kernel<<<g, 256, 0, stream>>>(n, alr, ali, vre(PV), vim(PV), vre(Q), vim(Q), vre(X), vim(X),
+                                                     vre(R), vim(R));
+                if ((st = dot(R, R, true, rn))) return st;
+                if (!std::isfinite(rn[0])) return fail(TDSEZ_ENONFINITE, "2D step %d: non-finite residual", step);
+                if (rn[0] <= stop) break;
+                if ((st = precond(R, Z))) return st;
+                double rho2[2];
+                if ((st = dot(R, Z, false, rho2))) return st;
+                const double dd = rho[0] * rho[0] + rho[1] * rho[1];
+                const double ber = (rho2[0] * rho[0] + rho2[1] * rho[1]) / dd;
+                const double bei = (rho2[1] * rho[0] - rho2[0] * rho[1]) / dd;
+                cocg_p_kernel<<<g, 256, 0, stream>>>(n, ber, bei, vre(Z), vim(Z), vre(PV), vim(PV));
+                rho[0] = rho2[0];
+                rho[1] = rho2[1];
+            }
+        }
+        s->iters_total += it;
+        if (it > s->iters_max) s->iters_max = it;
+        s->steps_total += 1;
+        add_kernel<<<g, 256, 0, stream>>>(n, vre(X), vim(X), vre(C), vim(C));
+        TDSEZ_HIP_TRY(hipGetLastError());
+    }
+    (void)obs_host;
+    from_planar_kernel<<<g, 256, 0, stream>>>(vre(C), vim(C), n, psi);
+    TDSEZ_HIP_TRY(hipGetLastError());
+    return TDSEZ_OK;
+}
+
+tdsez_status tdsez_system2d_stats(tdsez_system2d s, long* steps, long* iterations, int* max_iterations) {
+    if (!s) return fail(TDSEZ_EINVAL, "system is NULL");
+    if (steps) *steps = (long)s->steps_total;
+    if (iterations) *iterations = (long)s->iters_total;
+    if (max_iterations) *max_iterations = s->iters_max;
+    s->steps_total = s->iters_total = 0;
+    s->iters_max = 0;
+    return TDSEZ_OK;
+}
+
+void tdsez_system2d_destroy(tdsez_system2d s) {
+    if (!s) return;
+    (void)hipDeviceSynchronize();
+    free2d(s);
+    delete s;
+}
+
+}  // extern "C"

@@ -57,6 +57,11 @@ def lib():
         "tdsez_propagate_batched": [vp, vp, lp, vp, lp, dp, ip, i, u, vp, lp, vp],
         "tdsez_propagate": [vp, vp, vp, d, i, i, u, vp, vp],
         "tdsez_adjoint_batched": [vp, vp, lp, vp, lp, dp, ip, i, u, vp, lp, vp, vp, i, vp],
+        "tdsez_assemble_2d": [dp, i, dp, i, i, i, dp, ctypes.POINTER(vp)],
+        "tdsez_system2d_size": [vp, ip, ip, ip],
+        "tdsez_get_v2": [vp, dp],
+        "tdsez_propagate_2d": [vp, vp, vp, d, i, i, u, vp, d, i, vp],
+        "tdsez_system2d_stats": [vp, lp, lp, ip],
         "tdsez_batch_status": [vp, vp, ip, ip],
         "tdsez_batch_profile": [vp, vp, dp],
         "tdsez_system_status": [vp, vp, ip],
@@ -69,6 +74,8 @@ def lib():
     L.tdsez_batch_destroy.restype = None
     L.tdsez_system_destroy.argtypes = [vp]
     L.tdsez_system_destroy.restype = None
+    L.tdsez_system2d_destroy.argtypes = [vp]
+    L.tdsez_system2d_destroy.restype = None
     _lib = L
     return L
 
@@ -355,3 +362,66 @@ def pack_batch_inputs(systems_defs, psi0_list, device="cuda"):
     E = torch.from_numpy(np.concatenate([s.E[: s.nsteps + 1] for s in systems_defs]).astype(np.float64)).to(device)
     obs = torch.zeros(3 * int(E.numel()), dtype=torch.float64, device=device)
     return psi, psi_off, E, E_off, obs, obs_off
+
+
+# --------------------------------------------------------------------- 2D
+class System2D:
+    """An assembled 2D tensor-product problem (owns its device data)."""
+
+    def __init__(self, handle):
+        self.handle = handle
+        nx, ny, p = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(lib().tdsez_system2d_size(handle, ctypes.byref(nx), ctypes.byref(ny), ctypes.byref(p)))
+        self.Nx, self.Ny, self.p = nx.value, ny.value, p.value
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.tdsez_system2d_destroy(self.handle)
+            self.handle = None
+
+
+def assemble_2d(breaks_x, breaks_y, order, nq, V_q):
+    bx, by = _f64(breaks_x), _f64(breaks_y)
+    vq = _f64(V_q)
+    h = ctypes.c_void_p()
+    _check(lib().tdsez_assemble_2d(_dptr(bx), len(bx), _dptr(by), len(by), order, nq, _dptr(vq), ctypes.byref(h)))
+    return System2D(h)
+
+
+def assemble_workload_2d(sysdef):
+    """Assemble a workloads.System2D: sample V on the tensor grid of the
+    library's own per-axis quadrature points."""
+    xq = quad_points(sysdef.breaks_x, sysdef.nq)
+    yq = quad_points(sysdef.breaks_y, sysdef.nq)
+    X, Y = np.meshgrid(xq, yq)
+    return assemble_2d(sysdef.breaks_x, sysdef.breaks_y, sysdef.order, sysdef.nq, sysdef.V(X, Y))
+
+
+def get_v2(sys2d):
+    w = 2 * sys2d.p + 1
+    out = np.zeros(sys2d.Nx * sys2d.Ny * w * w)
+    _check(lib().tdsez_get_v2(sys2d.handle, _dptr(out)))
+    return out.reshape(sys2d.Nx * sys2d.Ny, w, w)
+
+
+def propagate_2d(sys2d, psi, E, dt, nsteps, prec=FP64, obs=OBS_NORM | OBS_DIPOLE, obs_out=None, tol=1e-12,
+                 maxit=200, stream=None):
+    """psi: device complex128 (Ny*Nx, in/out); E: device float64; obs_out:
+    device float64 [(nsteps+1)*3] or None."""
+    import torch
+    _check_dev(psi, torch.complex128)
+    _check_dev(E, torch.float64)
+    if obs:
+        _check_dev(obs_out, torch.float64)
+    _check(lib().tdsez_propagate_2d(sys2d.handle, ctypes.c_void_p(psi.data_ptr()), ctypes.c_void_p(E.data_ptr()),
+                                    float(dt), int(nsteps), int(prec), int(obs),
+                                    ctypes.c_void_p(obs_out.data_ptr()) if obs else None, float(tol), int(maxit),
+                                    _stream_handle(stream)))
+
+
+def system2d_stats(sys2d):
+    """(steps, COCG iterations, largest iteration count of one step) since
+    the last call."""
+    a, b, c = ctypes.c_long(), ctypes.c_long(), ctypes.c_int()
+    _check(lib().tdsez_system2d_stats(sys2d.handle, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+    return a.value, b.value, c.value

@@ -1,0 +1,138 @@
+"""GPU two-dimensional tensor-product path against the FP64 oracle.
+
+Tolerances: potential stencil to 1e-13 relative; nu and x-dipole series to
+1e-10 relative L2 (both sides converge each step's solve to 1e-13 or below,
+from different solvers: the oracle's numpy COCG and the library's GEMM
+preconditioned COCG)."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2608_18472_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2608_18472_amd import tdsez as T  # noqa: E402
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def product_ground_state(sd):
+    """Initial state: product of the 1D ground states of each axis with the
+    1D soft-Coulomb potential -1/sqrt(x^2 + 1) (oracle eigensolver)."""
+    vecs = []
+    for br in (sd.breaks_x, sd.breaks_y):
+        m = O.assemble(br, sd.order, sd.nq, V=lambda x: -1.0 / np.sqrt(x * x + 1.0))
+        ev, vec = O.eig_banded(m["H0"], m["S"], 1, -1.5)
+        vecs.append(vec[0])
+    return np.outer(vecs[1], vecs[0]).astype(np.complex128)
+
+
+def run_gpu_2d(sd, psi0, nsteps, tol=1e-13):
+    g = T.assemble_workload_2d(sd)
+    psi = torch.from_numpy(psi0.reshape(-1).copy()).cuda()
+    E = torch.from_numpy(np.asarray(sd.E[: nsteps + 1], np.float64).copy()).cuda()
+    o = torch.zeros(3 * (nsteps + 1), dtype=torch.float64, device="cuda")
+    T.propagate_2d(g, psi, E, sd.dt, nsteps, T.FP64, T.OBS_NORM | T.OBS_DIPOLE, o, tol=tol, maxit=300)
+    steps, its, mx = T.system2d_stats(g)
+    say("COCG iterations: %d steps, %.2f per step, max %d" % (steps, its / max(steps, 1), mx))
+    return o.cpu().numpy().reshape(-1, 3), psi.cpu().numpy().reshape(psi0.shape)
+
+
+def small_case(nsteps):
+    """40 x 36 unknowns, order 6, soft-Coulomb 2D, graded y knots, a strong
+    x field (carrier at full strength)."""
+    bx = W.breaks_uniform(40.0, 37)
+    by = W.breaks_symexp(35.0, 33, 1.5)
+    E = 0.08 * np.sin(0.3 * 0.05 * np.arange(nsteps + 1))
+    return W.System2D("small-2d", bx, by, 6, lambda x, y: -1.0 / np.sqrt(x * x + y * y + 1.0), 10, E, 0.05, nsteps)
+
+
+def test_potential_stencil_matches_oracle():
+    sd = small_case(1)
+    g = T.assemble_workload_2d(sd)
+    m2 = O.assemble_2d(sd.breaks_x, sd.breaks_y, sd.order, sd.nq, sd.V)
+    assert (g.Nx, g.Ny, g.p) == (m2["Nx"], m2["Ny"], m2["p"])
+    v = T.get_v2(g)
+    assert np.abs(v - m2["V2"]).max() < 1e-13 * np.abs(m2["V2"]).max()
+
+
+def test_small_grid_propagation_matches_oracle():
+    ns = 300
+    sd = small_case(ns)
+    psi0 = product_ground_state(sd)
+    m2 = O.assemble_2d(sd.breaks_x, sd.breaks_y, sd.order, sd.nq, sd.V)
+    ref, cref = O.propagate_2d(m2, psi0, sd.E, sd.dt, ns, tol=1e-14)
+    got, cgot = run_gpu_2d(sd, psi0, ns)
+    errs = [rel(got[:, k], ref[:, k]) for k in range(2)]
+    say("small 2D errors", errs, rel(cgot, cref))
+    assert errs[0] < 1e-10 and errs[1] < 1e-10
+    assert rel(cgot, cref) < 1e-10
+
+
+def test_config4_reduced_grid_matches_oracle():
+    """The 2D soft-Coulomb workload on a 128 x 128 grid (same box, order,
+    dt), 100 steps with the carrier at full amplitude (the sin^2 envelope is
+    ~1e-3 over the first steps, which would leave a dipole too small for a
+    relative comparison)."""
+    ns = 100
+    sd = W.config4(n=128, nsteps=ns)
+    sd.E = 0.05 * np.sin(0.057 * sd.dt * np.arange(ns + 1) + 0.3)
+    psi0 = product_ground_state(sd)
+    m2 = O.assemble_2d(sd.breaks_x, sd.breaks_y, sd.order, sd.nq, sd.V)
+    ref, _ = O.propagate_2d(m2, psi0, sd.E, sd.dt, ns, tol=1e-14)
+    got, _ = run_gpu_2d(sd, psi0, ns)
+    errs = [rel(got[:, k], ref[:, k]) for k in range(2)]
+    say("config4 128^2 errors", errs)
+    assert errs[0] < 1e-10 and errs[1] < 1e-10
+
+
+def test_config4_full_size_first_steps_match_oracle():
+    """The 512 x 512 workload itself, first 6 steps (oracle cost bound)."""
+    ns = 6
+    sd = W.config4(nsteps=ns)
+    psi0 = product_ground_state(sd)
+    # a non-zero field from the first step (the sin^2 pulse starts at zero)
+    sd.E = 0.05 * np.sin(0.057 * sd.dt * np.arange(ns + 1) + 0.3)
+    m2 = O.assemble_2d(sd.breaks_x, sd.breaks_y, sd.order, sd.nq, sd.V)
+    ref, cref = O.propagate_2d(m2, psi0, sd.E, sd.dt, ns, tol=1e-14)
+    got, cgot = run_gpu_2d(sd, psi0, ns)
+    errs = [rel(got[:, k], ref[:, k]) for k in range(2)]
+    say("config4 512^2 errors", errs, rel(cgot, cref))
+    assert errs[0] < 1e-10 and errs[1] < 1e-10
+    assert rel(cgot, cref) < 1e-10
+
+
+def test_2d_invalid_arguments():
+    sd = small_case(2)
+    g = T.assemble_workload_2d(sd)
+    psi = torch.zeros(g.Nx * g.Ny, dtype=torch.complex128, device="cuda")
+    E = torch.zeros(3, dtype=torch.float64, device="cuda")
+    o = torch.zeros(9, dtype=torch.float64, device="cuda")
+    with pytest.raises(T.TdsezError) as e:
+        T.propagate_2d(g, psi, E, 0.05, 2, T.FP32_REFINED, 3, o)
+    assert e.value.status == 7
+    for kw in ({"obs": 7}, {"tol": 0.0}, {"maxit": 0}):
+        args = dict(prec=T.FP64, obs=3, obs_out=o, tol=1e-12, maxit=10)
+        args.update(kw)
+        with pytest.raises(T.TdsezError) as e:
+            T.propagate_2d(g, psi, E, 0.05, 2, **args)
+        assert e.value.status == 1
+    with pytest.raises(T.TdsezError) as e:
+        T.assemble_2d(sd.breaks_x[:5], sd.breaks_y, 6, 10, np.zeros(4 * 10 * (len(sd.breaks_y) - 1) * 10))
+    assert e.value.status == 1
