@@ -293,29 +293,6 @@ __global__ __launch_bounds__(kRedThreads) void dot_kernel(long long n, const dou
     }
 }
 
-// x += al p, r -= al q   (planar complex, al complex)
-__global__ void cocg_xr_kernel(long long n, double alr, double ali, const double* __restrict__ pr,
-                               const double* __restrict__ pi, const double* __restrict__ qr,
-                               const double* __restrict__ qi, double* __restrict__ xr, double* __restrict__ xi,
-                               double* __restrict__ rr, double* __restrict__ ri) {
-    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x) {
-        xr[e] += alr * pr[e] - ali * pi[e];
-        xi[e] += alr * pi[e] + ali * pr[e];
-        rr[e] -= alr * qr[e] - ali * qi[e];
-        ri[e] -= alr * qi[e] + ali * qr[e];
-    }
-}
-
-// p = z + be p
-__global__ void cocg_p_kernel(long long n, double ber, double bei, const double* __restrict__ zr,
-                              const double* __restrict__ zi, double* __restrict__ pr, double* __restrict__ pi) {
-    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x) {
-        const double a = pr[e], b = pi[e];
-        pr[e] = zr[e] + ber * a - bei * b;
-        pi[e] = zi[e] + ber * b + bei * a;
-    }
-}
-
 // c += x
 __global__ void add_kernel(long long n, const double* __restrict__ xr, const double* __restrict__ xi,
                            double* __restrict__ cr, double* __restrict__ ci) {
@@ -339,17 +316,102 @@ __global__ void fdm_scale_kernel(int Nx, int Ny, double alpha, const double* __r
     }
 }
 
-// observables: sum the per-block partials of apply_kernel in a fixed order
-__global__ void obs_finish_kernel(const double* __restrict__ part, int nblk, double* __restrict__ out, unsigned mask) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// observables: sum the per-block partials of apply_kernel (fixed order per
+// thread, then a tree over the block: deterministic)
+__global__ __launch_bounds__(kRedThreads) void obs_finish_kernel(const double* __restrict__ part, int nblk,
+                                                                 double* __restrict__ out, unsigned mask) {
+    __shared__ double a[kRedThreads], b[kRedThreads];
     double nu = 0.0, d = 0.0;
-    for (int b = 0; b < nblk; ++b) {
-        nu += part[2 * b];
-        d += part[2 * b + 1];
+    for (int k = threadIdx.x; k < nblk; k += kRedThreads) {
+        nu += part[2 * k];
+        d += part[2 * k + 1];
     }
-    out[0] = (mask & TDSEZ_OBS_NORM) ? nu : 0.0;
-    out[1] = (mask & TDSEZ_OBS_DIPOLE) ? d : 0.0;
-    out[2] = 0.0;
+    a[threadIdx.x] = nu;
+    b[threadIdx.x] = d;
+    __syncthreads();
+    for (int s = kRedThreads / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            a[threadIdx.x] += a[threadIdx.x + s];
+            b[threadIdx.x] += b[threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = (mask & TDSEZ_OBS_NORM) ? a[0] : 0.0;
+        out[1] = (mask & TDSEZ_OBS_DIPOLE) ? b[0] : 0.0;
+        out[2] = 0.0;
+    }
+}
+
+// COCG scalars on the device.  sc[0..1] rho, sc[2..3] alpha, sc[4..5] beta,
+// sc[6] |r|^2, sc[7] |b|^2.  One block sums the partials of the last dot
+// (fixed order) and updates the scalars for `mode`:
+//   0: rho = sum          1: alpha = rho / sum
+//   2: beta = sum / rho, rho = sum            3: |r|^2 = sum (real)   4: |b|^2 = sum
+__global__ __launch_bounds__(kRedThreads) void cocg_scalar_kernel(const double* __restrict__ part, int nblk,
+                                                                  int mode, double* __restrict__ sc) {
+    __shared__ double a[kRedThreads], b[kRedThreads];
+    double re = 0.0, im = 0.0;
+    for (int k = threadIdx.x; k < nblk; k += kRedThreads) {
+        re += part[2 * k];
+        im += part[2 * k + 1];
+    }
+    a[threadIdx.x] = re;
+    b[threadIdx.x] = im;
+    __syncthreads();
+    for (int s = kRedThreads / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            a[threadIdx.x] += a[threadIdx.x + s];
+            b[threadIdx.x] += b[threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    const double sr = a[0], si = b[0];
+    if (mode == 0) {
+        sc[0] = sr;
+        sc[1] = si;
+    } else if (mode == 1) {
+        // a zero p^T q only arises with a zero residual (exact start): no step
+        const double den = sr * sr + si * si;
+        sc[2] = den > 0.0 ? (sc[0] * sr + sc[1] * si) / den : 0.0;
+        sc[3] = den > 0.0 ? (sc[1] * sr - sc[0] * si) / den : 0.0;
+    } else if (mode == 2) {
+        const double den = sc[0] * sc[0] + sc[1] * sc[1];
+        sc[4] = den > 0.0 ? (sr * sc[0] + si * sc[1]) / den : 0.0;
+        sc[5] = den > 0.0 ? (si * sc[0] - sr * sc[1]) / den : 0.0;
+        sc[0] = sr;
+        sc[1] = si;
+    } else if (mode == 3) {
+        sc[6] = sr;
+    } else {
+        sc[7] = sr;
+    }
+}
+
+// x += al p, r -= al q with al = sc[2..3]
+__global__ void cocg_xr_dev_kernel(long long n, const double* __restrict__ sc, const double* __restrict__ pr,
+                                   const double* __restrict__ pi, const double* __restrict__ qr,
+                                   const double* __restrict__ qi, double* __restrict__ xr, double* __restrict__ xi,
+                                   double* __restrict__ rr, double* __restrict__ ri) {
+    const double alr = sc[2], ali = sc[3];
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x) {
+        xr[e] += alr * pr[e] - ali * pi[e];
+        xi[e] += alr * pi[e] + ali * pr[e];
+        rr[e] -= alr * qr[e] - ali * qi[e];
+        ri[e] -= alr * qi[e] + ali * qr[e];
+    }
+}
+
+// p = z + be p with be = sc[4..5]
+__global__ void cocg_p_dev_kernel(long long n, const double* __restrict__ sc, const double* __restrict__ zr,
+                                  const double* __restrict__ zi, double* __restrict__ pr, double* __restrict__ pi) {
+    const double ber = sc[4], bei = sc[5];
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x) {
+        const double a = pr[e], b = pi[e];
+        pr[e] = zr[e] + ber * a - bei * b;
+        pi[e] = zi[e] + ber * b + bei * a;
+    }
 }
 
 }  // namespace
@@ -368,6 +430,7 @@ struct tdsez_system2d_s {
     double* d_work = nullptr;  // planar vectors: c, x, r, z, p, q, b, t1, t2 (2 planes each)
     double* d_part = nullptr;  // reduction partials
     double* d_obs_part = nullptr;
+    double* d_sc = nullptr;    // COCG scalars (device)
     rocblas_handle blas = nullptr;
     long long iters_total = 0;
     int iters_max = 0;
@@ -401,6 +464,7 @@ void free2d(tdsez_system2d_s* s) {
     (void)hipFree(s->d_work);
     (void)hipFree(s->d_part);
     (void)hipFree(s->d_obs_part);
+    (void)hipFree(s->d_sc);
     if (s->blas) rocblas_destroy_handle(s->blas);
 }
 
@@ -533,6 +597,7 @@ tdsez_status tdsez_assemble_2d(const double* breaks_x, int nbx, const double* br
     const long long plane = (long long)Nx * Ny;
     if (hipMalloc(&s->d_work, sizeof(double) * (size_t)plane * 2 * 9) != hipSuccess ||
         hipMalloc(&s->d_part, sizeof(double) * 2 * kRedBlocks) != hipSuccess ||
+        hipMalloc(&s->d_sc, sizeof(double) * 8) != hipSuccess ||
         hipMalloc(&s->d_obs_part, sizeof(double) * 2 * (size_t)((Nx + kTile - 1) / kTile) * ((Ny + kTile - 1) / kTile)) !=
             hipSuccess)
         return bail(fail(TDSEZ_ENOMEM, "2D workspace allocation failed"));
@@ -618,16 +683,14 @@ tdsez_status tdsez_propagate_2d(tdsez_system2d s, double* psi, const double* E, 
             default: break;
         }
     };
-    auto dot = [&](int u, int v, bool abs2, double out[2]) -> tdsez_status {
+    // partial sums of a dot into d_part, then the one-block scalar update
+    auto dot_dev = [&](int u, int v, bool abs2, int mode) {
         dot_kernel<<<kRedBlocks, kRedThreads, 0, stream>>>(n, vre(u), vim(u), vre(v), vim(v), abs2, s->d_part);
-        double h[2 * kRedBlocks];
-        TDSEZ_HIP_TRY(hipMemcpyAsync(h, s->d_part, sizeof(h), hipMemcpyDeviceToHost, stream));
+        cocg_scalar_kernel<<<1, kRedThreads, 0, stream>>>(s->d_part, kRedBlocks, mode, s->d_sc);
+    };
+    auto read_norms = [&](double out[2]) -> tdsez_status {
+        TDSEZ_HIP_TRY(hipMemcpyAsync(out, s->d_sc + 6, 2 * sizeof(double), hipMemcpyDeviceToHost, stream));
         TDSEZ_HIP_TRY(hipStreamSynchronize(stream));
-        out[0] = out[1] = 0.0;
-        for (int b = 0; b < kRedBlocks; ++b) {
-            out[0] += h[2 * b];
-            out[1] += h[2 * b + 1];
-        }
         return TDSEZ_OK;
     };
     // z = P^-1 r
@@ -646,73 +709,53 @@ tdsez_status tdsez_propagate_2d(tdsez_system2d s, double* psi, const double* E, 
                                                Ny, &one, vre(T1), Nx, n, s->d_Qy, Ny, 0, &zero, vre(zout), Nx, n, 2));
         return TDSEZ_OK;
     };
-    const long long stride = (long long)(vim(0) - vre(0));
-    (void)stride;
-    double obs_host[3];
+    std::vector<double> Eh((size_t)nsteps + 1);
+    TDSEZ_HIP_TRY(hipMemcpyAsync(Eh.data(), E, sizeof(double) * Eh.size(), hipMemcpyDeviceToHost, stream));
+    TDSEZ_HIP_TRY(hipStreamSynchronize(stream));
+    int guess = 1;  // iterations run before the first convergence check of a step
     for (int step = 0; step <= nsteps; ++step) {
-        double En, Enext;
-        TDSEZ_HIP_TRY(hipMemcpyAsync(&En, E + step, sizeof(double), hipMemcpyDeviceToHost, stream));
-        Enext = En;
-        if (step < nsteps) TDSEZ_HIP_TRY(hipMemcpyAsync(&Enext, E + step + 1, sizeof(double), hipMemcpyDeviceToHost, stream));
-        TDSEZ_HIP_TRY(hipStreamSynchronize(stream));
-        const double Eb = 0.5 * (En + Enext);
+        const double Eb = step < nsteps ? 0.5 * (Eh[step] + Eh[step + 1]) : Eh[step];
         // b = -i dt H c (and the observables of c)
         apply(C, -1, 0.0, 0.0, 0.0, 0.0, 0.0, -2.0 * alpha, Eb, B, s->d_obs_part);
-        if (obs) {
-            obs_finish_kernel<<<1, 1, 0, stream>>>(s->d_obs_part, nblk, obs_out + 3 * (size_t)step, obs);
-            TDSEZ_HIP_TRY(hipGetLastError());
-        }
+        if (obs) obs_finish_kernel<<<1, kRedThreads, 0, stream>>>(s->d_obs_part, nblk, obs_out + 3 * (size_t)step, obs);
         if (step == nsteps) break;
         // COCG on A x = b, A = S2 + i a H, warm start from the previous increment
         apply(X, B, 1.0, 0.0, -1.0, 0.0, 0.0, -alpha, Eb, R, nullptr);  // r = b - A x
-        double bn[2], rn[2];
+        dot_dev(B, B, true, 4);
+        dot_dev(R, R, true, 3);
         tdsez_status st;
-        if ((st = dot(B, B, true, bn))) return st;
-        if ((st = dot(R, R, true, rn))) return st;
-        const double stop = tol * tol * (bn[0] > 0.0 ? bn[0] : 1.0);
+        if ((st = precond(R, Z))) return st;
+        TDSEZ_HIP_TRY(hipMemcpyAsync(vre(PV), vre(Z), sizeof(double) * 2 * n, hipMemcpyDeviceToDevice, stream));
+        dot_dev(R, Z, false, 0);
         int it = 0;
-        if (rn[0] > stop) {
-            if ((st = precond(R, Z))) return st;
-            TDSEZ_HIP_TRY(hipMemcpyAsync(vre(PV), vre(Z), sizeof(double) * 2 * n, hipMemcpyDeviceToDevice, stream));
-            double rho[2];
-            if ((st = dot(R, Z, false, rho))) return st;
-            for (;;) {
-                ++it;
-                if (it > maxit) {
-                    return fail(TDSEZ_ENOCONV, "2D step %d: no convergence to %g in %d iterations (residual %g)", step,
-                                tol, maxit, std::sqrt(rn[0] / (bn[0] > 0 ? bn[0] : 1.0)));
-                }
-                apply(PV, -1, 0.0, 0.0, 1.0, 0.0, 0.0, alpha, Eb, Q, nullptr);  // q = A p
-                double pq[2];
-                if ((st = dot(PV, Q, false, pq))) return st;
-                const double den = pq[0] * pq[0] + pq[1] * pq[1];
-                if (!(den > 0.0) || !std::isfinite(den))
-                    return fail(TDSEZ_ENONFINITE, "2D step %d: COCG breakdown", step);
-                const double alr = (rho[0] * pq[0] + rho[1] * pq[1]) / den;
-                const double ali = (rho[1] * pq[0] - rho[0] * pq[1]) / den;
-                cocg_xr_kernel<<<g, 256, 0, stream>>>(n, alr, ali, vre(PV), vim(PV), vre(Q), vim(Q), vre(X), vim(X),
-                                                     vre(R), vim(R));
-                if ((st = dot(R, R, true, rn))) return st;
-                if (!std::isfinite(rn[0])) return fail(TDSEZ_ENONFINITE, "2D step %d: non-finite residual", step);
-                if (rn[0] <= stop) break;
-                if ((st = precond(R, Z))) return st;
-                double rho2[2];
-                if ((st = dot(R, Z, false, rho2))) return st;
-                const double dd = rho[0] * rho[0] + rho[1] * rho[1];
-                const double ber = (rho2[0] * rho[0] + rho2[1] * rho[1]) / dd;
-                const double bei = (rho2[1] * rho[0] - rho2[0] * rho[1]) / dd;
-                cocg_p_kernel<<<g, 256, 0, stream>>>(n, ber, bei, vre(Z), vim(Z), vre(PV), vim(PV));
-                rho[0] = rho2[0];
-                rho[1] = rho2[1];
+        for (;;) {
+            // one iteration, all scalars on the device
+            ++it;
+            apply(PV, -1, 0.0, 0.0, 1.0, 0.0, 0.0, alpha, Eb, Q, nullptr);  // q = A p
+            dot_dev(PV, Q, false, 1);                                        // alpha = rho / p^T q
+            cocg_xr_dev_kernel<<<g, 256, 0, stream>>>(n, s->d_sc, vre(PV), vim(PV), vre(Q), vim(Q), vre(X), vim(X),
+                                                      vre(R), vim(R));
+            dot_dev(R, R, true, 3);
+            if (it >= guess) {
+                double nrm[2];
+                if ((st = read_norms(nrm))) return st;
+                if (!std::isfinite(nrm[0])) return fail(TDSEZ_ENONFINITE, "2D step %d: non-finite residual", step);
+                if (nrm[0] <= tol * tol * (nrm[1] > 0.0 ? nrm[1] : 1.0)) break;
+                if (it >= maxit)
+                    return fail(TDSEZ_ENOCONV, "2D step %d: no convergence to %g in %d iterations (residual %g)",
+                                step, tol, maxit, std::sqrt(nrm[0] / (nrm[1] > 0 ? nrm[1] : 1.0)));
             }
+            if ((st = precond(R, Z))) return st;
+            dot_dev(R, Z, false, 2);  // beta = r^T z / rho, rho = r^T z
+            cocg_p_dev_kernel<<<g, 256, 0, stream>>>(n, s->d_sc, vre(Z), vim(Z), vre(PV), vim(PV));
         }
+        guess = it > 1 ? it - 1 : 1;
         s->iters_total += it;
         if (it > s->iters_max) s->iters_max = it;
         s->steps_total += 1;
         add_kernel<<<g, 256, 0, stream>>>(n, vre(X), vim(X), vre(C), vim(C));
         TDSEZ_HIP_TRY(hipGetLastError());
     }
-    (void)obs_host;
     from_planar_kernel<<<g, 256, 0, stream>>>(vre(C), vim(C), n, psi);
     TDSEZ_HIP_TRY(hipGetLastError());
     return TDSEZ_OK;

@@ -118,6 +118,17 @@ def test_config4_full_size_first_steps_match_oracle():
     assert rel(cgot, cref) < 1e-10
 
 
+def test_zero_state_stays_zero():
+    sd = small_case(5)
+    g = T.assemble_workload_2d(sd)
+    psi = torch.zeros(g.Nx * g.Ny, dtype=torch.complex128, device="cuda")
+    E = torch.from_numpy(sd.E.copy()).cuda()
+    o = torch.zeros(3 * 6, dtype=torch.float64, device="cuda")
+    T.propagate_2d(g, psi, E, sd.dt, 5, T.FP64, 3, o)
+    assert float(psi.abs().max()) == 0.0
+    assert float(o.abs().max()) == 0.0
+
+
 def test_2d_invalid_arguments():
     sd = small_case(2)
     g = T.assemble_workload_2d(sd)
