@@ -200,18 +200,22 @@ __device__ __forceinline__ void pass_rhs(const SysDesc& sd, int k, const FT* __r
             st_c(rs, at, cmk<FT>((FT)(2.0 * alpha * hacc[0].im), (FT)(-2.0 * alpha * hacc[0].re)));
         }
     };
+    // rows are loaded two ahead of their use
     RowIn cur = load_row(0);
+    RowIn nx1 = load_row(1);
     for (int r = 0; r < L; ++r) {
-        RowIn nxt = load_row(r + 1);
+        RowIn nx2 = load_row(r + 2);
         stream_row(cur, r, true);
-        cur = nxt;
+        cur = nx1;
+        nx1 = nx2;
     }
     if (want_rhs) {
 #pragma unroll
         for (int t = 0; t < PP; ++t) {
-            RowIn nxt = load_row(L + t + 1);
+            RowIn nx2 = load_row(L + t + 2);
             stream_row(cur, L + t, false);
-            cur = nxt;
+            cur = nx1;
+            nx1 = nx2;
         }
     }
     obs_part[0] = nu;
@@ -308,17 +312,21 @@ __device__ __forceinline__ void pass_elim(const SysDesc& sd, int k, const FT* __
         for (int i2 = 0; i2 <= PP; ++i2) W[PP][i2] = cmk<FT>(0, 0);
         y[PP] = cmk<FT>(0, 0);
     };
+    // rows are loaded two ahead of their use
     RowIn cur = load_row(0);
+    RowIn nx1 = load_row(1);
 #pragma unroll
     for (int r = 0; r < PP; ++r) {
-        RowIn nxt = load_row(r + 1);
+        RowIn nx2 = load_row(r + 2);
         row(cur, r, true, false);
-        cur = nxt;
+        cur = nx1;
+        nx1 = nx2;
     }
     for (int r = PP; r < L; ++r) {
-        RowIn nxt = load_row(r + 1);
+        RowIn nx2 = load_row(r + 2);
         row(cur, r, false, true);
-        cur = nxt;
+        cur = nx1;
+        nx1 = nx2;
     }
     // the window now holds the chunk's separator rows m..L-1
     FT* rb = red + 2 * (sd.red_off + (long long)k * RedLayout<FT>::chunk_block(PP));
@@ -402,8 +410,9 @@ __device__ __forceinline__ void pass_fill(const SysDesc& sd, int k, const FT* __
         return fr;
     };
     FRow cur = load_frow(0);
+    FRow nx1 = load_frow(1);
     for (int j = 0; j < m; ++j) {
-        FRow nxt = load_frow(j + 1);
+        FRow nx2 = load_frow(j + 2);
         cplx<FT> f[PP];
 #pragma unroll
         for (int t = 0; t < PP; ++t) f[t] = F[0][t];
@@ -432,7 +441,8 @@ __device__ __forceinline__ void pass_fill(const SysDesc& sd, int k, const FT* __
             for (int t = 0; t < PP; ++t) F[i - 1][t] = F[i][t];
 #pragma unroll
         for (int t = 0; t < PP; ++t) F[PP][t] = cmk<FT>(0, 0);
-        cur = nxt;
+        cur = nx1;
+        nx1 = nx2;
     }
     FT* rb = red + 2 * (sd.red_off + (long long)k * RedLayout<FT>::chunk_block(PP));
     const int pp = PP * PP;
@@ -733,25 +743,36 @@ __device__ __forceinline__ void pass_backsub(const SysDesc& sd, int k, const FT*
     auto fitem = [&](int j, int item) {
         return ld_c(fc, (unsigned)j * fstride + (unsigned)(item * P) + (unsigned)kk);
     };
-    auto update = [&](int lrow, cplx<FT> x) {
+    // the state (and increment) of a row are loaded ahead with its factor
+    // row, so that the update below is a plain store
+    const double* dsrc = (dst && !first) ? dst : cst;  // dummy source when unused
+    auto load_sd = [&](int lrow, cplx<double>& c, cplx<double>& d) {
+        const unsigned at = (unsigned)lrow * (unsigned)LS + (unsigned)col;
+        c = cmk<double>(cst[2 * at], cst[2 * at + 1]);
+        d = cmk<double>(dsrc[2 * at], dsrc[2 * at + 1]);
+    };
+    auto update = [&](int lrow, cplx<FT> x, cplx<double> c, cplx<double> d) {
         const unsigned at = (unsigned)lrow * (unsigned)LS + (unsigned)col;
         if (assign) {
             cst[2 * at] = (double)x.re;
             cst[2 * at + 1] = (double)x.im;
         } else {
-            cst[2 * at] += (double)x.re;
-            cst[2 * at + 1] += (double)x.im;
+            cst[2 * at] = c.re + (double)x.re;
+            cst[2 * at + 1] = c.im + (double)x.im;
         }
         if (dst) {
             if (first) {
                 dst[2 * at] = (double)x.re;
                 dst[2 * at + 1] = (double)x.im;
             } else {
-                dst[2 * at] += (double)x.re;
-                dst[2 * at + 1] += (double)x.im;
+                dst[2 * at] = d.re + (double)x.re;
+                dst[2 * at + 1] = d.im + (double)x.im;
             }
         }
     };
+    cplx<double> sepc[PP], sepd[PP];
+#pragma unroll
+    for (int t = 0; t < PP; ++t) load_sd(m + t, sepc[t], sepd[t]);
     // u = L^-1 A_{I,right} x_right on pivots m-p+q, q = 0..p-1
     cplx<FT> ur[PP];
 #pragma unroll
@@ -767,16 +788,19 @@ __device__ __forceinline__ void pass_backsub(const SysDesc& sd, int k, const FT*
         ur[q] = u;
     }
     // back substitution over the interior pivots, window of the next p
-    // values; each pivot's factor row is loaded one pivot ahead
+    // values; each pivot's factor row (with the row's state) is loaded two
+    // pivots ahead of its use
     struct FRow {
         cplx<FT> it[IT];  // items 0..p-1 l, p dinv, p+1 yhat, p+2..2p+1 f
+        cplx<double> c, d;
     };
     auto load_frow = [&](int j) {
-        // j = -1 (after the last pivot) reloads pivot 0; the row is not used
+        // j < 0 (past the last pivot) reloads pivot 0; the row is not used
         const int jj = j < 0 ? 0 : j;
         FRow r;
 #pragma unroll
         for (int it = 0; it < IT; ++it) r.it[it] = fitem(jj, it);
+        load_sd(jj, r.c, r.d);
         return r;
     };
     cplx<FT> xw[PP + 1];
@@ -792,22 +816,25 @@ __device__ __forceinline__ void pass_backsub(const SysDesc& sd, int k, const FT*
 #pragma unroll
         for (int i = PP; i >= 2; --i) xw[i] = xw[i - 1];
         xw[1] = xj;
-        update(j, xj);
+        update(j, xj, fr.c, fr.d);
     };
     FRow cur = load_frow(m - 1);
+    FRow nx1 = load_frow(m - 2);
 #pragma unroll
     for (int q = PP - 1; q >= 0; --q) {
-        FRow nxt = load_frow(m - PP + q - 1);
+        FRow nx2 = load_frow(m - PP + q - 2);
         back_row(m - PP + q, cur, ur[q]);
-        cur = nxt;
+        cur = nx1;
+        nx1 = nx2;
     }
     for (int j = m - PP - 1; j >= 0; --j) {
-        FRow nxt = load_frow(j - 1);
+        FRow nx2 = load_frow(j - 2);
         back_row(j, cur, cmk<FT>(0, 0));
-        cur = nxt;
+        cur = nx1;
+        nx1 = nx2;
     }
 #pragma unroll
-    for (int t = 0; t < PP; ++t) update(m + t, xr[t]);
+    for (int t = 0; t < PP; ++t) update(m + t, xr[t], sepc[t], sepd[t]);
 }
 
 // Pass C (refinement sweep): residual of the current iterate in FP64,
@@ -935,17 +962,20 @@ __device__ __forceinline__ void pass_residual(const SysDesc& sd, int k, const FT
         for (int t = 0; t < PP; ++t) fr.f[t] = fitem(j, PP + 2 + t);
         return fr;
     };
+    // band/state rows two ahead, factor rows one ahead of their use
     RowIn cur = load_row(0);
+    RowIn nx1 = load_row(1);
 #pragma unroll
     for (int r = 0; r < PP; ++r) {
-        RowIn nxt = load_row(r + 1);
+        RowIn nx2 = load_row(r + 2);
         (void)stream_row(cur, true);
         shift_y();
-        cur = nxt;
+        cur = nx1;
+        nx1 = nx2;
     }
     FRow fcur = load_frow(0);
     for (int r = PP; r < L; ++r) {
-        RowIn nxt = load_row(r + 1);
+        RowIn nx2 = load_row(r + 2);
         FRow fnxt = load_frow(r - PP + 1);
         const int j = r - PP;
         cplx<FT> yj = cadd(y[0], stream_row(cur, true));
@@ -956,14 +986,16 @@ __device__ __forceinline__ void pass_residual(const SysDesc& sd, int k, const FT
 #pragma unroll
         for (int t = 0; t < PP; ++t) gT[t] = cfms(gT[t], cmul(fcur.f[t], fcur.dinv), yj);
         shift_y();
-        cur = nxt;
+        cur = nx1;
+        nx1 = nx2;
         fcur = fnxt;
     }
 #pragma unroll
     for (int t = 0; t < PP; ++t) {
-        RowIn nxt = load_row(L + t + 1);
+        RowIn nx2 = load_row(L + t + 2);
         y[t] = cadd(y[t], stream_row(cur, false));
-        cur = nxt;
+        cur = nx1;
+        nx1 = nx2;
     }
     FT* rb = red + 2 * (sd.red_off + (long long)k * RedLayout<FT>::chunk_block(PP));
     const int pp = PP * PP;
