@@ -392,8 +392,7 @@ tdsez_status launch_adjoint(BatchData* b, const double* psi0, const double* E, c
         TDSEZ_HIP_TRY(hipMalloc(&b->d_seg, 2 * sizeof(double) * (size_t)seg_total));
         b->seg_elems = seg_total;
     }
-    TDSEZ_HIP_TRY(hipMemcpyAsync(b->d_desc, b->desc.data(), sizeof(SysDesc) * nsys, hipMemcpyHostToDevice,
-                                 stream));
+    if (tdsez_status st = upload_descriptors(b, stream)) return st;
     AdjArgs ka;
     ka.descs = b->d_desc;
     ka.band = b->d_band64;

@@ -67,6 +67,7 @@ static void free_batch_device(BatchData* b) {
     b->d_fac = nullptr;
     b->d_red = nullptr;
     b->d_desc = nullptr;
+    b->desc_on_device.clear();
     b->d_status = nullptr;
 }
 

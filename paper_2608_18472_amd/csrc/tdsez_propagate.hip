@@ -34,6 +34,7 @@
 //   state  [l][col]          complex128
 //   factor [j][item][k]      2p+2 items per interior pivot j (fac_items)
 #include <cmath>
+#include <cstring>
 
 #include "tdsez_passes.hpp"
 
@@ -309,11 +310,20 @@ tdsez_status pack_bands(BatchData* b) {
     return TDSEZ_OK;
 }
 
+tdsez_status upload_descriptors(BatchData* b, hipStream_t stream) {
+    const size_t n = b->desc.size();
+    if (b->desc_on_device.size() == n &&
+        std::memcmp(b->desc_on_device.data(), b->desc.data(), sizeof(SysDesc) * n) == 0)
+        return TDSEZ_OK;
+    TDSEZ_HIP_TRY(hipMemcpyAsync(b->d_desc, b->desc.data(), sizeof(SysDesc) * n, hipMemcpyHostToDevice, stream));
+    b->desc_on_device = b->desc;
+    return TDSEZ_OK;
+}
+
 tdsez_status launch_propagate(BatchData* b, double* psi, const double* E, double* obs,
                               tdsez_precision prec, unsigned obs_mask, hipStream_t stream) {
     const int nsys = (int)b->sys.size();
-    TDSEZ_HIP_TRY(hipMemcpyAsync(b->d_desc, b->desc.data(), sizeof(SysDesc) * nsys,
-                                 hipMemcpyHostToDevice, stream));
+    if (tdsez_status st = upload_descriptors(b, stream)) return st;
     long long maxL = 1, maxN = 1;
     for (const auto& pl : b->plan) {
         maxL = std::max<long long>(maxL, (long long)pl.L * pl.LS);
