@@ -168,6 +168,23 @@ tdsez_status tdsez_batch_create(const tdsez_system* sys, int nsys, tdsez_batch* 
  * on per-phase cycle counters read by tdsez_batch_profile, 0 off). */
 tdsez_status tdsez_batch_set(tdsez_batch b, const char* key, double value);
 
+/* Partition autotuner (fills the batch's plan cache).  The partitioned solve
+ * of section V.B's Crank-Nicolson system splits each system into P chunks;
+ * the best P balances the per-chunk sweeps against the serial chain over the
+ * P separator blocks and depends on N, p, the precision and the rest of the
+ * batch.  Runs short profiled propagations of the whole batch (scratch
+ * inputs; the caller's buffers are not touched) for up to five chunk-length
+ * rules, the default rule first, until budget_ms of wall time is spent, and
+ * keeps for every system the chunk count with the fewest cycles per step.
+ * Later calls of either precision use the tuned plan; tdsez_batch_set
+ * "chunks" overrides and clears it.  Synchronous (default stream).  EINVAL
+ * for budget_ms <= 0 or an unknown precision. */
+tdsez_status tdsez_autotune(tdsez_batch b, tdsez_precision prec, double budget_ms);
+
+/* Chunk count P of every system under the batch's current plan (host array
+ * of nsys ints). */
+tdsez_status tdsez_batch_chunks(tdsez_batch b, int* chunks_out);
+
 /* Crank-Nicolson propagation of every system of the batch in one persistent
  * kernel launch (one workgroup per system), section V.B eq. cn_system with
  * H^{n+1/2} = H0 + (E_n + E_{n+1})/2 D.
@@ -180,6 +197,8 @@ tdsez_status tdsez_batch_set(tdsez_batch b, const char* key, double value);
  *   obs_packed (device, out): FP64 series, system s at obs_packed + obs_off[s]
  *       (host offsets, in doubles), (nsteps_s + 1) x 3 as described at
  *       TDSEZ_OBS_*; may be NULL when obs == 0.
+ * Workgroups start in order of decreasing cost N (p + 1) nsteps, so a batch
+ * with more systems than the device holds at once runs longest first.
  * Asynchronous on `stream`.  EINVAL on bad arguments (detected on the host);
  * device-side failures are latched (tdsez_batch_status). */
 tdsez_status tdsez_propagate_batched(tdsez_batch b, double* psi_packed, const long* psi_off,
@@ -248,19 +267,29 @@ tdsez_status tdsez_system2d_size(tdsez_system2d s, int* nx, int* ny, int* halfbw
 tdsez_status tdsez_get_v2(tdsez_system2d s, double* host_out);
 /* Crank-Nicolson propagation of psi (device complex128 [Ny][Nx], in/out)
  * over nsteps steps of dt with E (device FP64 [nsteps+1]).  Each step solves
- * A_n (c_{n+1} - c_n) = -i dt H_n c_n by COCG preconditioned with the exact
+ * A_n (c_{n+1} - c_n) = -i dt H_n c_n to relative residual tol, starting
+ * from the previous step's increment, with the preconditioner P = exact
  * inverse of S2 + i dt/2 T2 (per-axis eigenvectors, GEMMs on the matrix
- * cores), to relative residual tol (at most maxit iterations, else
- * ENOCONV).  obs: TDSEZ_OBS_NORM | TDSEZ_OBS_DIPOLE (x dipole);
- * obs_out[n*3 + 0..2] = (nu_n, d_n, 0) on the device.  FP64 only
- * (TDSEZ_FP32_REFINED: EUNSUPPORTED).  Enqueued on `stream`, but the host
- * waits for the iteration scalars, so the call returns when done. */
+ * cores):
+ *   TDSEZ_FP64: COCG in FP64, at most maxit iterations per step;
+ *   TDSEZ_FP32_REFINED: iterative refinement, each sweep forms the FP64
+ *     residual r = b - A x, solves A e = r by COCG in FP32 (FP32 copies of
+ *     the operator and of P, made by the first such call) to a relative
+ *     1e-5, and adds e to x in FP64; at most maxit sweeps per step.
+ * Either way the result meets the same FP64 residual bound; ENOCONV when
+ * the bound is not met.  obs: TDSEZ_OBS_NORM | TDSEZ_OBS_DIPOLE (x dipole);
+ * obs_out[n*3 + 0..2] = (nu_n, d_n, 0) on the device, always FP64.
+ * Enqueued on `stream`, but the host waits for the iteration scalars, so
+ * the call returns when done. */
 tdsez_status tdsez_propagate_2d(tdsez_system2d s, double* psi, const double* E, double dt, int nsteps,
                                 tdsez_precision prec, unsigned obs, double* obs_out, double tol, int maxit,
                                 void* stream);
-/* Steps and COCG iterations of the 2D propagations since the last call, and
- * the largest iteration count of one step; resets the counters. */
-tdsez_status tdsez_system2d_stats(tdsez_system2d s, long* steps, long* iterations, int* max_iterations);
+/* Steps, Krylov iterations (FP32 inner iterations for TDSEZ_FP32_REFINED),
+ * the largest iteration count of one step and the refinement sweeps of the
+ * 2D propagations since the last call (any pointer may be NULL); resets the
+ * counters. */
+tdsez_status tdsez_system2d_stats(tdsez_system2d s, long* steps, long* iterations, int* max_iterations,
+                                  long* sweeps);
 void tdsez_system2d_destroy(tdsez_system2d s);
 
 /* Phase profile of the last propagation of a profiled batch (see

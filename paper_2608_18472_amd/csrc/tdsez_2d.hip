@@ -136,33 +136,50 @@ __global__ void from_planar_kernel(const double* __restrict__ re, const double* 
 constexpr int kTile = 16;          // output tile edge of the stencil kernel
 constexpr int kStencilThreads = kTile * kTile;
 
-struct Cd {
-    double re, im;
-};
-__device__ inline Cd cd_mul(Cd a, Cd b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+// M[i][j] of a 1D lower half band by rows, for |i - j| <= p; pairs with an
+// index outside 0..n-1 give 0 (the load index is clamped, so no branch)
+template <typename FT>
+__device__ inline FT band_at(const FT* __restrict__ band, int p, int n, int i, int j) {
+    const bool ok = i >= 0 && i < n && j >= 0 && j < n;
+    const int hi = i > j ? i : j;
+    const int d = i > j ? i - j : j - i;
+    const FT v = band[ok ? hi * (p + 1) + d : 0];
+    return ok ? v : FT(0);
+}
 
-// out = w * y + a S2 c + b (T2 + V2 + Ebar D2) c   (all planar complex; y may
-// be null).  With obs != null each block also writes partial sums of
-// Re c^H S2 c and Re c^H D2 c (the observables of c).
-template <int PP>
+// out = w y + a S2 c + b (T2 + V2 + Ebar D2) c   (planar complex; y may be
+// null), for one 16 x 16 tile of outputs with the input tile and a p-wide
+// halo in LDS, in three stages:
+//  (1) x pass: every row of the haloed tile is convolved with the x bands at
+//      the thread's column, s = Sx c and h = (Tx + Ebar Dx) c (and Dx c for
+//      the observables), kept in LDS;
+//  (2) y pass: S2 c = Sy s and (T2 + Ebar D2) c = Sy h + Ty s at the output,
+//      so the separable part costs O(p) per unknown instead of O(p^2);
+//  (3) the potential: the (2p+1)^2 neighbours times V2 from the half
+//      stencil, the mirrored half read at the neighbour's row (clamped into
+//      the plane where the neighbour is outside: c is zero there).
+// With obs != null every block writes partial sums of Re c^H S2 c and
+// Re c^H D2 c (FP64).
+template <int PP, typename FT>
 __global__ __launch_bounds__(kStencilThreads) void apply_kernel(
-    int Nx, int Ny, const double* __restrict__ Sxb, const double* __restrict__ Txb,
-    const double* __restrict__ Dxb, const double* __restrict__ Syb, const double* __restrict__ Tyb,
-    const double* __restrict__ V2h, const double* __restrict__ cre, const double* __restrict__ cim,
-    const double* __restrict__ yre, const double* __restrict__ yim, double wre, double wim, double are,
-    double aim, double bre, double bim, double Ebar, double* __restrict__ ore, double* __restrict__ oim,
-    double* __restrict__ obs) {
+    int Nx, int Ny, const FT* __restrict__ Sxb, const FT* __restrict__ Txb, const FT* __restrict__ Dxb,
+    const FT* __restrict__ Syb, const FT* __restrict__ Tyb, const FT* __restrict__ V2h, const FT* __restrict__ cre,
+    const FT* __restrict__ cim, const FT* __restrict__ yre, const FT* __restrict__ yim, FT wre, FT wim, FT are,
+    FT aim, FT bre, FT bim, FT Ebar, FT* __restrict__ ore, FT* __restrict__ oim, double* __restrict__ obs) {
+    constexpr int K = 2 * PP + 1;
     constexpr int W = kTile + 2 * PP;
-    constexpr int NH = (PP + 1) + PP * (2 * PP + 1);
-    __shared__ double tre[W][W], tim[W][W];
+    __shared__ FT tre[W][W], tim[W][W];
+    __shared__ FT s_re[W][kTile], s_im[W][kTile], h_re[W][kTile], h_im[W][kTile];
+    __shared__ FT d_re[W][kTile], d_im[W][kTile];
     __shared__ double red[2][kStencilThreads];
     const int tx = threadIdx.x % kTile, ty = threadIdx.x / kTile;
     const int x0 = blockIdx.x * kTile, y0 = blockIdx.y * kTile;
+    const int ix = x0 + tx, iy = y0 + ty;
     const long long plane = (long long)Nx * Ny;
     for (int t = threadIdx.x; t < W * W; t += kStencilThreads) {
         const int ly = t / W, lx = t % W;
         const int gy = y0 + ly - PP, gx = x0 + lx - PP;
-        double vr = 0.0, vi = 0.0;
+        FT vr = 0, vi = 0;
         if (gy >= 0 && gy < Ny && gx >= 0 && gx < Nx) {
             vr = cre[(long long)gy * Nx + gx];
             vi = cim[(long long)gy * Nx + gx];
@@ -170,73 +187,121 @@ __global__ __launch_bounds__(kStencilThreads) void apply_kernel(
         tre[ly][lx] = vr;
         tim[ly][lx] = vi;
     }
+    // x factors of the thread's column
+    FT sx[K], hx[K], dx[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int jx = ix + k - PP;
+        sx[k] = band_at(Sxb, PP, Nx, ix, jx);
+        dx[k] = band_at(Dxb, PP, Nx, ix, jx);
+        hx[k] = band_at(Txb, PP, Nx, ix, jx) + Ebar * dx[k];
+    }
     __syncthreads();
-    const int ix = x0 + tx, iy = y0 + ty;
-    const bool inside = ix < Nx && iy < Ny;
+    // (1) x pass over the tile rows (halo rows included)
+    for (int ly = ty; ly < W; ly += kTile) {
+        FT sr = 0, si = 0, hr = 0, hi = 0, dr = 0, di = 0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const FT zr = tre[ly][tx + k], zi = tim[ly][tx + k];
+            sr += sx[k] * zr;
+            si += sx[k] * zi;
+            hr += hx[k] * zr;
+            hi += hx[k] * zi;
+            dr += dx[k] * zr;
+            di += dx[k] * zi;
+        }
+        s_re[ly][tx] = sr;
+        s_im[ly][tx] = si;
+        h_re[ly][tx] = hr;
+        h_im[ly][tx] = hi;
+        d_re[ly][tx] = dr;
+        d_im[ly][tx] = di;
+    }
+    // (3) potential, from the input tile (independent of the x pass).  Rows
+    // of offsets are kept rolled (11 loads in flight per row, not 121) so
+    // that the kernel keeps a small register footprint.
+    const int ixc = ix < Nx ? ix : Nx - 1, iyc = iy < Ny ? iy : Ny - 1;
+    const long long row = (long long)iyc * Nx + ixc;
+    FT vr = 0, vi = 0;
+    // dy < 0: the mirrored half, read at the neighbour's row (clamped into
+    // the plane where the neighbour is outside; c is zero there)
+#pragma unroll 1
+    for (int ky = 0; ky < PP; ++ky) {
+        const int dy = ky - PP;
+        int jy = iyc + dy;
+        jy = jy < 0 ? 0 : jy;
+        const FT* __restrict__ vrow = V2h + (long long)half_index(PP, -dy, 0) * plane + (long long)jy * Nx;
+#pragma unroll
+        for (int kx = 0; kx < K; ++kx) {
+            const int dxo = kx - PP;
+            int jx = ixc + dxo;
+            jx = jx < 0 ? 0 : (jx >= Nx ? Nx - 1 : jx);
+            // offset (-dy, -dxo) is stored -dxo planes after (-dy, 0)
+            const FT v = vrow[(long long)(-dxo) * plane + jx];
+            vr += v * tre[ty + ky][tx + kx];
+            vi += v * tim[ty + ky][tx + kx];
+        }
+    }
+    // dy == 0: dx < 0 mirrored (same row of the tile), dx >= 0 direct
+#pragma unroll
+    for (int kx = 0; kx < K; ++kx) {
+        const int dxo = kx - PP;
+        FT v;
+        if (dxo >= 0) {
+            v = V2h[(long long)half_index(PP, 0, dxo) * plane + row];
+        } else {
+            const int jx = ixc + dxo < 0 ? 0 : ixc + dxo;
+            v = V2h[(long long)half_index(PP, 0, -dxo) * plane + (long long)iyc * Nx + jx];
+        }
+        vr += v * tre[ty + PP][tx + kx];
+        vi += v * tim[ty + PP][tx + kx];
+    }
+    // dy > 0: the stored half at this row
+#pragma unroll 1
+    for (int ky = PP + 1; ky < K; ++ky) {
+        const FT* __restrict__ vrow = V2h + (long long)half_index(PP, ky - PP, -PP) * plane + row;
+#pragma unroll
+        for (int kx = 0; kx < K; ++kx) {
+            const FT v = vrow[(long long)kx * plane];
+            vr += v * tre[ty + ky][tx + kx];
+            vi += v * tim[ty + ky][tx + kx];
+        }
+    }
+    __syncthreads();
+    // (2) y pass
+    FT Sr = 0, Si = 0, Hr = 0, Hi = 0, Dr = 0, Di = 0;
+#pragma unroll
+    for (int ky = 0; ky < K; ++ky) {
+        const int jy = iy + ky - PP;
+        const FT sy = band_at(Syb, PP, Ny, iy, jy), tyv = band_at(Tyb, PP, Ny, iy, jy);
+        const FT a_r = s_re[ty + ky][tx], a_i = s_im[ty + ky][tx];
+        Sr += sy * a_r;
+        Si += sy * a_i;
+        Hr += sy * h_re[ty + ky][tx] + tyv * a_r;
+        Hi += sy * h_im[ty + ky][tx] + tyv * a_i;
+        if (obs) {
+            Dr += sy * d_re[ty + ky][tx];
+            Di += sy * d_im[ty + ky][tx];
+        }
+    }
     double nu = 0.0, dip = 0.0;
-    if (inside) {
-        const Cd a = {are, aim}, b = {bre, bim};
-        // x factors: X1 = a Sx + b (Tx + Ebar Dx), X2 = b Sx; observables use Sx, Dx
-        Cd X1[2 * PP + 1], X2[2 * PP + 1];
-        double sxv[2 * PP + 1], dxv[2 * PP + 1];
-#pragma unroll
-        for (int k = 0; k <= 2 * PP; ++k) {
-            const int jx = ix + k - PP;
-            double s = 0.0, t = 0.0, d = 0.0;
-            if (jx >= 0 && jx < Nx) {
-                s = band_ij(Sxb, PP, ix, jx);
-                t = band_ij(Txb, PP, ix, jx);
-                d = band_ij(Dxb, PP, ix, jx);
-            }
-            sxv[k] = s;
-            dxv[k] = d;
-            const double h = t + Ebar * d;
-            X1[k] = {a.re * s + b.re * h, a.im * s + b.im * h};
-            X2[k] = {b.re * s, b.im * s};
-        }
-        const long long row = (long long)iy * Nx + ix;
-        double accr = 0.0, acci = 0.0, sr = 0.0, si = 0.0, dr = 0.0, di = 0.0;
-#pragma unroll
-        for (int ky = 0; ky <= 2 * PP; ++ky) {
-            const int dy = ky - PP, jy = iy + dy;
-            if (jy < 0 || jy >= Ny) continue;
-            const double sy = band_ij(Syb, PP, iy, jy), tyv = band_ij(Tyb, PP, iy, jy);
-#pragma unroll
-            for (int kx = 0; kx <= 2 * PP; ++kx) {
-                const int dx = kx - PP, jx = ix + dx;
-                if (jx < 0 || jx >= Nx) continue;
-                // V2 entry: stored at this row or, mirrored, at the neighbour's
-                double v;
-                if (dy > 0 || (dy == 0 && dx >= 0))
-                    v = V2h[(long long)half_index(PP, dy, dx) * plane + row];
-                else
-                    v = V2h[(long long)half_index(PP, -dy, -dx) * plane + (long long)jy * Nx + jx];
-                const double cr = sy * X1[kx].re + tyv * X2[kx].re + b.re * v;
-                const double ci = sy * X1[kx].im + tyv * X2[kx].im + b.im * v;
-                const double zr = tre[ty + ky][tx + kx], zi = tim[ty + ky][tx + kx];
-                accr += cr * zr - ci * zi;
-                acci += cr * zi + ci * zr;
-                if (obs) {
-                    const double s2 = sy * sxv[kx], d2 = sy * dxv[kx];
-                    sr += s2 * zr;
-                    si += s2 * zi;
-                    dr += d2 * zr;
-                    di += d2 * zi;
-                }
-            }
-        }
-        (void)NH;
+    if (ix < Nx && iy < Ny) {
+        // a S2 c + b ((T2 + Ebar D2) c + V2 c)
+        const FT gr = Hr + vr, gi = Hi + vi;
+        FT accr = are * Sr - aim * Si + bre * gr - bim * gi;
+        FT acci = are * Si + aim * Sr + bre * gi + bim * gr;
+        const long long orow = (long long)iy * Nx + ix;
         if (yre) {
-            const double vr = yre[row], vi = yim[row];
-            accr += wre * vr - wim * vi;
-            acci += wre * vi + wim * vr;
+            const FT yr = yre[orow], yi = yim[orow];
+            accr += wre * yr - wim * yi;
+            acci += wre * yi + wim * yr;
         }
-        ore[row] = accr;
-        oim[row] = acci;
+        ore[orow] = accr;
+        oim[orow] = acci;
         if (obs) {
             const double c0r = tre[ty + PP][tx + PP], c0i = tim[ty + PP][tx + PP];
-            nu = c0r * sr + c0i * si;
-            dip = c0r * dr + c0i * di;
+            nu = c0r * (double)Sr + c0i * (double)Si;
+            dip = c0r * (double)Dr + c0i * (double)Di;
         }
     }
     if (obs) {
@@ -261,20 +326,23 @@ __global__ __launch_bounds__(kStencilThreads) void apply_kernel(
 constexpr int kRedThreads = 256;
 constexpr int kRedBlocks = 512;
 
-// partial sums over blocks: sum u v (complex, unconjugated) or sum |u|^2
-__global__ __launch_bounds__(kRedThreads) void dot_kernel(long long n, const double* __restrict__ ur,
-                                                          const double* __restrict__ ui,
-                                                          const double* __restrict__ vr,
-                                                          const double* __restrict__ vi, bool abs2,
+// partial sums over blocks: sum u v (complex, unconjugated) or sum |u|^2,
+// accumulated in FP64 whatever the storage precision
+template <typename FT>
+__global__ __launch_bounds__(kRedThreads) void dot_kernel(long long n, const FT* __restrict__ ur,
+                                                          const FT* __restrict__ ui, const FT* __restrict__ vr,
+                                                          const FT* __restrict__ vi, bool abs2,
                                                           double* __restrict__ part) {
     __shared__ double sr[kRedThreads], si[kRedThreads];
     double ar = 0.0, ai = 0.0;
     for (long long e = blockIdx.x * (long long)kRedThreads + threadIdx.x; e < n; e += (long long)gridDim.x * kRedThreads) {
+        const double a = ur[e], b = ui[e];
         if (abs2) {
-            ar += ur[e] * ur[e] + ui[e] * ui[e];
+            ar += a * a + b * b;
         } else {
-            ar += ur[e] * vr[e] - ui[e] * vi[e];
-            ai += ur[e] * vi[e] + ui[e] * vr[e];
+            const double c = vr[e], d = vi[e];
+            ar += a * c - b * d;
+            ai += a * d + b * c;
         }
     }
     sr[threadIdx.x] = ar;
@@ -293,26 +361,34 @@ __global__ __launch_bounds__(kRedThreads) void dot_kernel(long long n, const dou
     }
 }
 
-// c += x
-__global__ void add_kernel(long long n, const double* __restrict__ xr, const double* __restrict__ xi,
+// c += x (x in FT, c in FP64)
+template <typename FT>
+__global__ void add_kernel(long long n, const FT* __restrict__ xr, const FT* __restrict__ xi,
                            double* __restrict__ cr, double* __restrict__ ci) {
     for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x) {
-        cr[e] += xr[e];
-        ci[e] += xi[e];
+        cr[e] += (double)xr[e];
+        ci[e] += (double)xi[e];
     }
 }
 
+// FP64 -> FP32 copy
+__global__ void to_fp32_kernel(long long n, const double* __restrict__ src, float* __restrict__ dst) {
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x)
+        dst[e] = (float)src[e];
+}
+
 // Z (column-major Nx x Ny, both planes) /= 1 + i a (lambda_ix + mu_iy)
+template <typename FT>
 __global__ void fdm_scale_kernel(int Nx, int Ny, double alpha, const double* __restrict__ lx,
-                                 const double* __restrict__ my, double* __restrict__ zr, double* __restrict__ zi) {
+                                 const double* __restrict__ my, FT* __restrict__ zr, FT* __restrict__ zi) {
     const long long n = (long long)Nx * Ny;
     for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x) {
         const int ix = (int)(e % Nx), iy = (int)(e / Nx);
         const double t = alpha * (lx[ix] + my[iy]);
         const double s = 1.0 / (1.0 + t * t);
         const double a = zr[e], b = zi[e];
-        zr[e] = (a + t * b) * s;
-        zi[e] = (b - t * a) * s;
+        zr[e] = (FT)((a + t * b) * s);
+        zi[e] = (FT)((b - t * a) * s);
     }
 }
 
@@ -390,11 +466,12 @@ __global__ __launch_bounds__(kRedThreads) void cocg_scalar_kernel(const double* 
 }
 
 // x += al p, r -= al q with al = sc[2..3]
-__global__ void cocg_xr_dev_kernel(long long n, const double* __restrict__ sc, const double* __restrict__ pr,
-                                   const double* __restrict__ pi, const double* __restrict__ qr,
-                                   const double* __restrict__ qi, double* __restrict__ xr, double* __restrict__ xi,
-                                   double* __restrict__ rr, double* __restrict__ ri) {
-    const double alr = sc[2], ali = sc[3];
+template <typename FT>
+__global__ void cocg_xr_dev_kernel(long long n, const double* __restrict__ sc, const FT* __restrict__ pr,
+                                   const FT* __restrict__ pi, const FT* __restrict__ qr, const FT* __restrict__ qi,
+                                   FT* __restrict__ xr, FT* __restrict__ xi, FT* __restrict__ rr,
+                                   FT* __restrict__ ri) {
+    const FT alr = (FT)sc[2], ali = (FT)sc[3];
     for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x) {
         xr[e] += alr * pr[e] - ali * pi[e];
         xi[e] += alr * pi[e] + ali * pr[e];
@@ -404,11 +481,12 @@ __global__ void cocg_xr_dev_kernel(long long n, const double* __restrict__ sc, c
 }
 
 // p = z + be p with be = sc[4..5]
-__global__ void cocg_p_dev_kernel(long long n, const double* __restrict__ sc, const double* __restrict__ zr,
-                                  const double* __restrict__ zi, double* __restrict__ pr, double* __restrict__ pi) {
-    const double ber = sc[4], bei = sc[5];
+template <typename FT>
+__global__ void cocg_p_dev_kernel(long long n, const double* __restrict__ sc, const FT* __restrict__ zr,
+                                  const FT* __restrict__ zi, FT* __restrict__ pr, FT* __restrict__ pi) {
+    const FT ber = (FT)sc[4], bei = (FT)sc[5];
     for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x) {
-        const double a = pr[e], b = pi[e];
+        const FT a = pr[e], b = pi[e];
         pr[e] = zr[e] + ber * a - bei * b;
         pi[e] = zi[e] + ber * b + bei * a;
     }
@@ -431,10 +509,17 @@ struct tdsez_system2d_s {
     double* d_part = nullptr;  // reduction partials
     double* d_obs_part = nullptr;
     double* d_sc = nullptr;    // COCG scalars (device)
+    // FP32 copies for TDSEZ_FP32_REFINED, made by the first such call
+    float* d_V2h32 = nullptr;
+    float* d_bands32 = nullptr;  // Sx, Tx, Dx (Nx (p+1) each), then Sy, Ty (Ny (p+1) each)
+    float* d_Qx32 = nullptr;
+    float* d_Qy32 = nullptr;
+    float* d_work32 = nullptr;   // planar FP32 vectors: r, z, p, q, e, t1, t2 (2 planes each)
     rocblas_handle blas = nullptr;
     long long iters_total = 0;
     int iters_max = 0;
     long long steps_total = 0;
+    long long sweeps_total = 0;
 };
 
 namespace {
@@ -465,6 +550,11 @@ void free2d(tdsez_system2d_s* s) {
     (void)hipFree(s->d_part);
     (void)hipFree(s->d_obs_part);
     (void)hipFree(s->d_sc);
+    (void)hipFree(s->d_V2h32);
+    (void)hipFree(s->d_bands32);
+    (void)hipFree(s->d_Qx32);
+    (void)hipFree(s->d_Qy32);
+    (void)hipFree(s->d_work32);
     if (s->blas) rocblas_destroy_handle(s->blas);
 }
 
@@ -497,6 +587,45 @@ tdsez_status axis_eigen(tdsez_system2d_s* s, const SystemData& ax, double** d_Q,
     if (bs != rocblas_status_success) return blas_fail(bs, "rocsolver_dsygvd");
     if (he != hipSuccess) return fail(TDSEZ_EHIP, "hipMemcpy failed: %s", hipGetErrorString(he));
     if (info != 0) return fail(TDSEZ_ENOCONV, "per-axis generalised eigensolve failed (info %d)", (int)info);
+    return TDSEZ_OK;
+}
+
+// FP32 copies of the operator and preconditioner data (first
+// TDSEZ_FP32_REFINED call; synchronous)
+tdsez_status ensure_fp32(tdsez_system2d_s* s) {
+    if (s->d_work32) return TDSEZ_OK;
+    const int Nx = s->Nx, Ny = s->Ny, p = s->p;
+    const long long plane = (long long)Nx * Ny;
+    const long long nv2 = (long long)half_count(p) * plane;
+    const long long bx = (long long)Nx * (p + 1), by = (long long)Ny * (p + 1);
+    float *v2 = nullptr, *bands = nullptr, *qx = nullptr, *qy = nullptr, *work = nullptr;
+    hipError_t he = hipSuccess;
+    auto H = [&](hipError_t e) { if (he == hipSuccess) he = e; };
+    H(hipMalloc(&v2, sizeof(float) * nv2));
+    H(hipMalloc(&bands, sizeof(float) * (3 * bx + 2 * by)));
+    H(hipMalloc(&qx, sizeof(float) * (size_t)Nx * Nx));
+    H(hipMalloc(&qy, sizeof(float) * (size_t)Ny * Ny));
+    H(hipMalloc(&work, sizeof(float) * (size_t)plane * 2 * 7));
+    if (he != hipSuccess) {
+        (void)hipFree(v2); (void)hipFree(bands); (void)hipFree(qx); (void)hipFree(qy); (void)hipFree(work);
+        return fail(TDSEZ_ENOMEM, "2D FP32 workspace allocation failed");
+    }
+    to_fp32_kernel<<<grid_for(nv2), 256>>>(nv2, s->d_V2h, v2);
+    to_fp32_kernel<<<grid_for(bx), 256>>>(bx, s->ax.d_band[0], bands);
+    to_fp32_kernel<<<grid_for(bx), 256>>>(bx, s->ax.d_band[1], bands + bx);
+    to_fp32_kernel<<<grid_for(bx), 256>>>(bx, s->ax.d_band[3], bands + 2 * bx);
+    to_fp32_kernel<<<grid_for(by), 256>>>(by, s->ay.d_band[0], bands + 3 * bx);
+    to_fp32_kernel<<<grid_for(by), 256>>>(by, s->ay.d_band[1], bands + 3 * bx + by);
+    to_fp32_kernel<<<grid_for((long long)Nx * Nx), 256>>>((long long)Nx * Nx, s->d_Qx, qx);
+    to_fp32_kernel<<<grid_for((long long)Ny * Ny), 256>>>((long long)Ny * Ny, s->d_Qy, qy);
+    H(hipGetLastError());
+    H(hipDeviceSynchronize());
+    s->d_V2h32 = v2;
+    s->d_bands32 = bands;
+    s->d_Qx32 = qx;
+    s->d_Qy32 = qy;
+    s->d_work32 = work;
+    if (he != hipSuccess) return fail(TDSEZ_EHIP, "2D FP32 copies: %s", hipGetErrorString(he));
     return TDSEZ_OK;
 }
 
@@ -646,16 +775,23 @@ tdsez_status tdsez_propagate_2d(tdsez_system2d s, double* psi, const double* E, 
     if (nsteps < 0) return fail(TDSEZ_EINVAL, "nsteps < 0");
     if (obs & ~3u) return fail(TDSEZ_EINVAL, "2D observables: TDSEZ_OBS_NORM and TDSEZ_OBS_DIPOLE only");
     if (obs && !obs_out) return fail(TDSEZ_EINVAL, "obs requested but obs_out is NULL");
-    if (prec == TDSEZ_FP32_REFINED) return fail(TDSEZ_EUNSUPPORTED, "the 2D path runs in FP64 only");
-    if (prec != TDSEZ_FP64) return fail(TDSEZ_EINVAL, "unknown precision %d", (int)prec);
+    if (prec != TDSEZ_FP64 && prec != TDSEZ_FP32_REFINED) return fail(TDSEZ_EINVAL, "unknown precision %d", (int)prec);
     if (!(tol > 0.0) || maxit < 1) return fail(TDSEZ_EINVAL, "tol must be > 0 and maxit >= 1");
+    const bool mixed = prec == TDSEZ_FP32_REFINED;
+    if (mixed) {
+        if (tdsez_status st = ensure_fp32(s)) return st;
+    }
     hipStream_t stream = (hipStream_t)stream_v;
     const int Nx = s->Nx, Ny = s->Ny, p = s->p;
     const long long n = (long long)Nx * Ny;
     double* w = s->d_work;
     auto vre = [&](int k) { return w + (size_t)(2 * k) * n; };
     auto vim = [&](int k) { return w + (size_t)(2 * k + 1) * n; };
-    enum { C = 0, X = 1, R = 2, Z = 3, PV = 4, Q = 5, B = 6, T1 = 7, T2 = 8 };
+    float* w32 = s->d_work32;
+    auto fre = [&](int k) { return w32 + (size_t)(2 * k) * n; };
+    auto fim = [&](int k) { return w32 + (size_t)(2 * k + 1) * n; };
+    enum { C = 0, X = 1, R = 2, Z = 3, PV = 4, Q = 5, B = 6, T1 = 7, T2 = 8 };   // FP64 vectors
+    enum { R32 = 0, Z32 = 1, P32 = 2, Q32 = 3, E32 = 4, T132 = 5, T232 = 6 };  // FP32 vectors
     const int g = grid_for(n);
     to_planar_kernel<<<g, 256, 0, stream>>>(psi, n, vre(C), vim(C));
     TDSEZ_HIP_TRY(hipMemsetAsync(vre(X), 0, sizeof(double) * 2 * n, stream));
@@ -667,16 +803,33 @@ tdsez_status tdsez_propagate_2d(tdsez_system2d s, double* psi, const double* E, 
     const double* Dx = s->ax.d_band[3];
     const double* Sy = s->ay.d_band[0];
     const double* Ty = s->ay.d_band[1];
+    const long long bx = (long long)Nx * (p + 1), by = (long long)Ny * (p + 1);
+    const float* b32 = s->d_bands32;
+    // out = w y + a S2 in + b (T2 + V2 + Eb D2) in, in FP64 (apply) or FP32 (apply32)
     auto apply = [&](int in, int yv, double wr, double wi, double ar, double ai, double br, double bi, double Eb,
                      int outv, double* obsp) {
         const double* yr = yv >= 0 ? vre(yv) : nullptr;
         const double* yi = yv >= 0 ? vim(yv) : nullptr;
         switch (p) {
-#define TD2_CASE(PV_)                                                                                     \
-    case PV_:                                                                                             \
-        apply_kernel<PV_><<<sgrid, kStencilThreads, 0, stream>>>(Nx, Ny, Sx, Tx, Dx, Sy, Ty, s->d_V2h,     \
-                                                                 vre(in), vim(in), yr, yi, wr, wi, ar, ai, \
-                                                                 br, bi, Eb, vre(outv), vim(outv), obsp); \
+#define TD2_CASE(PV_)                                                                                        \
+    case PV_:                                                                                                \
+        apply_kernel<PV_, double><<<sgrid, kStencilThreads, 0, stream>>>(                                    \
+            Nx, Ny, Sx, Tx, Dx, Sy, Ty, s->d_V2h, vre(in), vim(in), yr, yi, wr, wi, ar, ai, br, bi, Eb,       \
+            vre(outv), vim(outv), obsp);                                                                     \
+        break;
+            TD2_CASE(1) TD2_CASE(2) TD2_CASE(3) TD2_CASE(4) TD2_CASE(5) TD2_CASE(6) TD2_CASE(7)
+#undef TD2_CASE
+            default: break;
+        }
+    };
+    auto apply32 = [&](int in, double ar, double ai, double br, double bi, double Eb, int outv) {
+        switch (p) {
+#define TD2_CASE(PV_)                                                                                         \
+    case PV_:                                                                                                 \
+        apply_kernel<PV_, float><<<sgrid, kStencilThreads, 0, stream>>>(                                      \
+            Nx, Ny, b32, b32 + bx, b32 + 2 * bx, b32 + 3 * bx, b32 + 3 * bx + by, s->d_V2h32, fre(in), fim(in), \
+            nullptr, nullptr, 0.f, 0.f, (float)ar, (float)ai, (float)br, (float)bi, (float)Eb, fre(outv),      \
+            fim(outv), nullptr);                                                                              \
         break;
             TD2_CASE(1) TD2_CASE(2) TD2_CASE(3) TD2_CASE(4) TD2_CASE(5) TD2_CASE(6) TD2_CASE(7)
 #undef TD2_CASE
@@ -685,7 +838,11 @@ tdsez_status tdsez_propagate_2d(tdsez_system2d s, double* psi, const double* E, 
     };
     // partial sums of a dot into d_part, then the one-block scalar update
     auto dot_dev = [&](int u, int v, bool abs2, int mode) {
-        dot_kernel<<<kRedBlocks, kRedThreads, 0, stream>>>(n, vre(u), vim(u), vre(v), vim(v), abs2, s->d_part);
+        dot_kernel<double><<<kRedBlocks, kRedThreads, 0, stream>>>(n, vre(u), vim(u), vre(v), vim(v), abs2, s->d_part);
+        cocg_scalar_kernel<<<1, kRedThreads, 0, stream>>>(s->d_part, kRedBlocks, mode, s->d_sc);
+    };
+    auto dot32 = [&](int u, int v, bool abs2, int mode) {
+        dot_kernel<float><<<kRedBlocks, kRedThreads, 0, stream>>>(n, fre(u), fim(u), fre(v), fim(v), abs2, s->d_part);
         cocg_scalar_kernel<<<1, kRedThreads, 0, stream>>>(s->d_part, kRedBlocks, mode, s->d_sc);
     };
     auto read_norms = [&](double out[2]) -> tdsez_status {
@@ -702,58 +859,133 @@ tdsez_status tdsez_propagate_2d(tdsez_system2d s, double* psi, const double* E, 
                                                Nx, &one, s->d_Qx, Nx, 0, vre(rin), Nx, n, &zero, vre(T1), Nx, n, 2));
         TD2_BLAS(rocblas_dgemm_strided_batched(s->blas, rocblas_operation_none, rocblas_operation_none, Nx, Ny, Ny,
                                                &one, vre(T1), Nx, n, s->d_Qy, Ny, 0, &zero, vre(T2), Nx, n, 2));
-        fdm_scale_kernel<<<g, 256, 0, stream>>>(Nx, Ny, alpha, s->d_lx, s->d_my, vre(T2), vim(T2));
+        fdm_scale_kernel<double><<<g, 256, 0, stream>>>(Nx, Ny, alpha, s->d_lx, s->d_my, vre(T2), vim(T2));
         TD2_BLAS(rocblas_dgemm_strided_batched(s->blas, rocblas_operation_none, rocblas_operation_none, Nx, Ny, Nx,
                                                &one, s->d_Qx, Nx, 0, vre(T2), Nx, n, &zero, vre(T1), Nx, n, 2));
         TD2_BLAS(rocblas_dgemm_strided_batched(s->blas, rocblas_operation_none, rocblas_operation_transpose, Nx, Ny,
                                                Ny, &one, vre(T1), Nx, n, s->d_Qy, Ny, 0, &zero, vre(zout), Nx, n, 2));
         return TDSEZ_OK;
     };
+    auto precond32 = [&](int rin, int zout) -> tdsez_status {
+        const float one = 1.f, zero = 0.f;
+        TD2_BLAS(rocblas_sgemm_strided_batched(s->blas, rocblas_operation_transpose, rocblas_operation_none, Nx, Ny,
+                                               Nx, &one, s->d_Qx32, Nx, 0, fre(rin), Nx, n, &zero, fre(T132), Nx, n,
+                                               2));
+        TD2_BLAS(rocblas_sgemm_strided_batched(s->blas, rocblas_operation_none, rocblas_operation_none, Nx, Ny, Ny,
+                                               &one, fre(T132), Nx, n, s->d_Qy32, Ny, 0, &zero, fre(T232), Nx, n, 2));
+        fdm_scale_kernel<float><<<g, 256, 0, stream>>>(Nx, Ny, alpha, s->d_lx, s->d_my, fre(T232), fim(T232));
+        TD2_BLAS(rocblas_sgemm_strided_batched(s->blas, rocblas_operation_none, rocblas_operation_none, Nx, Ny, Nx,
+                                               &one, s->d_Qx32, Nx, 0, fre(T232), Nx, n, &zero, fre(T132), Nx, n, 2));
+        TD2_BLAS(rocblas_sgemm_strided_batched(s->blas, rocblas_operation_none, rocblas_operation_transpose, Nx, Ny,
+                                               Ny, &one, fre(T132), Nx, n, s->d_Qy32, Ny, 0, &zero, fre(zout), Nx, n,
+                                               2));
+        return TDSEZ_OK;
+    };
     std::vector<double> Eh((size_t)nsteps + 1);
     TDSEZ_HIP_TRY(hipMemcpyAsync(Eh.data(), E, sizeof(double) * Eh.size(), hipMemcpyDeviceToHost, stream));
     TDSEZ_HIP_TRY(hipStreamSynchronize(stream));
-    int guess = 1;  // iterations run before the first convergence check of a step
+    // FP32 inner solves reduce the FP64 residual by this factor per sweep
+    // (near the FP32 accuracy of the inner operator)
+    constexpr double kInnerTol = 1e-5;
+    int guess = 1;     // iterations run before the first convergence check of a solve
+    int guess_in = 1;
     for (int step = 0; step <= nsteps; ++step) {
         const double Eb = step < nsteps ? 0.5 * (Eh[step] + Eh[step + 1]) : Eh[step];
         // b = -i dt H c (and the observables of c)
         apply(C, -1, 0.0, 0.0, 0.0, 0.0, 0.0, -2.0 * alpha, Eb, B, s->d_obs_part);
         if (obs) obs_finish_kernel<<<1, kRedThreads, 0, stream>>>(s->d_obs_part, nblk, obs_out + 3 * (size_t)step, obs);
         if (step == nsteps) break;
-        // COCG on A x = b, A = S2 + i a H, warm start from the previous increment
+        // A x = b, A = S2 + i a H, warm start from the previous increment
         apply(X, B, 1.0, 0.0, -1.0, 0.0, 0.0, -alpha, Eb, R, nullptr);  // r = b - A x
         dot_dev(B, B, true, 4);
         dot_dev(R, R, true, 3);
         tdsez_status st;
-        if ((st = precond(R, Z))) return st;
-        TDSEZ_HIP_TRY(hipMemcpyAsync(vre(PV), vre(Z), sizeof(double) * 2 * n, hipMemcpyDeviceToDevice, stream));
-        dot_dev(R, Z, false, 0);
         int it = 0;
-        for (;;) {
-            // one iteration, all scalars on the device
-            ++it;
-            apply(PV, -1, 0.0, 0.0, 1.0, 0.0, 0.0, alpha, Eb, Q, nullptr);  // q = A p
-            dot_dev(PV, Q, false, 1);                                        // alpha = rho / p^T q
-            cocg_xr_dev_kernel<<<g, 256, 0, stream>>>(n, s->d_sc, vre(PV), vim(PV), vre(Q), vim(Q), vre(X), vim(X),
-                                                      vre(R), vim(R));
-            dot_dev(R, R, true, 3);
-            if (it >= guess) {
-                double nrm[2];
-                if ((st = read_norms(nrm))) return st;
-                if (!std::isfinite(nrm[0])) return fail(TDSEZ_ENONFINITE, "2D step %d: non-finite residual", step);
-                if (nrm[0] <= tol * tol * (nrm[1] > 0.0 ? nrm[1] : 1.0)) break;
-                if (it >= maxit)
-                    return fail(TDSEZ_ENOCONV, "2D step %d: no convergence to %g in %d iterations (residual %g)",
-                                step, tol, maxit, std::sqrt(nrm[0] / (nrm[1] > 0 ? nrm[1] : 1.0)));
-            }
+        if (!mixed) {
+            // COCG in FP64
             if ((st = precond(R, Z))) return st;
-            dot_dev(R, Z, false, 2);  // beta = r^T z / rho, rho = r^T z
-            cocg_p_dev_kernel<<<g, 256, 0, stream>>>(n, s->d_sc, vre(Z), vim(Z), vre(PV), vim(PV));
+            TDSEZ_HIP_TRY(hipMemcpyAsync(vre(PV), vre(Z), sizeof(double) * 2 * n, hipMemcpyDeviceToDevice, stream));
+            dot_dev(R, Z, false, 0);
+            for (;;) {
+                // one iteration, all scalars on the device
+                ++it;
+                apply(PV, -1, 0.0, 0.0, 1.0, 0.0, 0.0, alpha, Eb, Q, nullptr);  // q = A p
+                dot_dev(PV, Q, false, 1);                                        // alpha = rho / p^T q
+                cocg_xr_dev_kernel<double><<<g, 256, 0, stream>>>(n, s->d_sc, vre(PV), vim(PV), vre(Q), vim(Q),
+                                                                  vre(X), vim(X), vre(R), vim(R));
+                dot_dev(R, R, true, 3);
+                if (it >= guess) {
+                    double nrm[2];
+                    if ((st = read_norms(nrm))) return st;
+                    if (!std::isfinite(nrm[0])) return fail(TDSEZ_ENONFINITE, "2D step %d: non-finite residual", step);
+                    if (nrm[0] <= tol * tol * (nrm[1] > 0.0 ? nrm[1] : 1.0)) break;
+                    if (it >= maxit)
+                        return fail(TDSEZ_ENOCONV, "2D step %d: no convergence to %g in %d iterations (residual %g)",
+                                    step, tol, maxit, std::sqrt(nrm[0] / (nrm[1] > 0 ? nrm[1] : 1.0)));
+                }
+                if ((st = precond(R, Z))) return st;
+                dot_dev(R, Z, false, 2);  // beta = r^T z / rho, rho = r^T z
+                cocg_p_dev_kernel<double><<<g, 256, 0, stream>>>(n, s->d_sc, vre(Z), vim(Z), vre(PV), vim(PV));
+            }
+            guess = it > 1 ? it - 1 : 1;
+        } else {
+            // iterative refinement: FP64 residual r = b - A x, FP32 COCG on
+            // A e = r (same preconditioner in FP32) to kInnerTol, x += e
+            double nrm[2];
+            if ((st = read_norms(nrm))) return st;
+            const double bn2 = nrm[1] > 0.0 ? nrm[1] : 1.0;
+            int sweeps = 0;
+            while (true) {
+                if (!std::isfinite(nrm[0])) return fail(TDSEZ_ENONFINITE, "2D step %d: non-finite residual", step);
+                if (nrm[0] <= tol * tol * bn2) break;
+                if (sweeps >= maxit)
+                    return fail(TDSEZ_ENOCONV, "2D step %d: no convergence to %g in %d refinement sweeps (residual %g)",
+                                step, tol, maxit, std::sqrt(nrm[0] / bn2));
+                ++sweeps;
+                // inner target: kInnerTol, or less work when that already reaches tol
+                double in_tol = 0.5 * tol * std::sqrt(bn2 / nrm[0]);
+                if (in_tol < kInnerTol) in_tol = kInnerTol;
+                to_fp32_kernel<<<g, 256, 0, stream>>>(2 * n, vre(R), fre(R32));
+                TDSEZ_HIP_TRY(hipMemsetAsync(fre(E32), 0, sizeof(float) * 2 * n, stream));
+                dot32(R32, R32, true, 4);
+                if ((st = precond32(R32, Z32))) return st;
+                TDSEZ_HIP_TRY(hipMemcpyAsync(fre(P32), fre(Z32), sizeof(float) * 2 * n, hipMemcpyDeviceToDevice,
+                                             stream));
+                dot32(R32, Z32, false, 0);
+                int iti = 0;
+                for (;;) {
+                    ++iti;
+                    apply32(P32, 1.0, 0.0, 0.0, alpha, Eb, Q32);  // q = A p
+                    dot32(P32, Q32, false, 1);
+                    cocg_xr_dev_kernel<float><<<g, 256, 0, stream>>>(n, s->d_sc, fre(P32), fim(P32), fre(Q32),
+                                                                     fim(Q32), fre(E32), fim(E32), fre(R32),
+                                                                     fim(R32));
+                    dot32(R32, R32, true, 3);
+                    if (iti >= guess_in) {
+                        double in[2];
+                        if ((st = read_norms(in))) return st;
+                        if (!std::isfinite(in[0]))
+                            return fail(TDSEZ_ENONFINITE, "2D step %d: non-finite inner residual", step);
+                        if (in[0] <= in_tol * in_tol * (in[1] > 0.0 ? in[1] : 1.0) || iti >= maxit) break;
+                    }
+                    if ((st = precond32(R32, Z32))) return st;
+                    dot32(R32, Z32, false, 2);
+                    cocg_p_dev_kernel<float><<<g, 256, 0, stream>>>(n, s->d_sc, fre(Z32), fim(Z32), fre(P32),
+                                                                    fim(P32));
+                }
+                guess_in = iti > 1 ? iti - 1 : 1;
+                it += iti;
+                add_kernel<float><<<g, 256, 0, stream>>>(n, fre(E32), fim(E32), vre(X), vim(X));
+                apply(X, B, 1.0, 0.0, -1.0, 0.0, 0.0, -alpha, Eb, R, nullptr);  // r = b - A x
+                dot_dev(R, R, true, 3);
+                if ((st = read_norms(nrm))) return st;
+            }
+            s->sweeps_total += sweeps;
         }
-        guess = it > 1 ? it - 1 : 1;
         s->iters_total += it;
         if (it > s->iters_max) s->iters_max = it;
         s->steps_total += 1;
-        add_kernel<<<g, 256, 0, stream>>>(n, vre(X), vim(X), vre(C), vim(C));
+        add_kernel<double><<<g, 256, 0, stream>>>(n, vre(X), vim(X), vre(C), vim(C));
         TDSEZ_HIP_TRY(hipGetLastError());
     }
     from_planar_kernel<<<g, 256, 0, stream>>>(vre(C), vim(C), n, psi);
@@ -761,12 +993,14 @@ tdsez_status tdsez_propagate_2d(tdsez_system2d s, double* psi, const double* E, 
     return TDSEZ_OK;
 }
 
-tdsez_status tdsez_system2d_stats(tdsez_system2d s, long* steps, long* iterations, int* max_iterations) {
+tdsez_status tdsez_system2d_stats(tdsez_system2d s, long* steps, long* iterations, int* max_iterations,
+                                  long* sweeps) {
     if (!s) return fail(TDSEZ_EINVAL, "system is NULL");
     if (steps) *steps = (long)s->steps_total;
     if (iterations) *iterations = (long)s->iters_total;
     if (max_iterations) *max_iterations = s->iters_max;
-    s->steps_total = s->iters_total = 0;
+    if (sweeps) *sweeps = (long)s->sweeps_total;
+    s->steps_total = s->iters_total = s->sweeps_total = 0;
     s->iters_max = 0;
     return TDSEZ_OK;
 }

@@ -31,6 +31,7 @@ namespace {
 
 struct AdjArgs {
     const SysDesc* descs;
+    const int* order;     // workgroup -> system index (longest first)
     const double* band;   // FP64 bands
     double* st;           // working state (interleaved)
     double* rhs;          // right-hand side of the forward steps
@@ -337,7 +338,7 @@ __device__ __forceinline__ void run_adjoint(const AdjArgs& ka, const SysDesc& sd
 }
 
 __global__ __launch_bounds__(kWave) void adjoint_kernel(AdjArgs ka) {
-    const int sidx = blockIdx.x;
+    const int sidx = ka.order[blockIdx.x];
     const SysDesc sd = ka.descs[sidx];
     switch (sd.p) {
         case 1: run_adjoint<1>(ka, sd, sidx); break;
@@ -395,6 +396,7 @@ tdsez_status launch_adjoint(BatchData* b, const double* psi0, const double* E, c
     if (tdsez_status st = upload_descriptors(b, stream)) return st;
     AdjArgs ka;
     ka.descs = b->d_desc;
+    ka.order = b->d_order;
     ka.band = b->d_band64;
     ka.st = b->d_state;
     ka.rhs = (double*)b->d_rhs;

@@ -1,5 +1,6 @@
 // C ABI of libtdsez (declared in include/tdsez.h): argument checking, handle
 // management and error reporting around the device code of tdsez_*.hip.
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -56,6 +57,8 @@ static void free_batch_device(BatchData* b) {
     (void)hipFree(b->d_fac);
     (void)hipFree(b->d_red);
     (void)hipFree(b->d_desc);
+    (void)hipFree(b->d_order);
+    b->d_order = nullptr;
     (void)hipFree(b->d_status);
     (void)hipFree(b->d_prof);
     b->d_prof = nullptr;
@@ -229,6 +232,7 @@ tdsez_status tdsez_batch_set(tdsez_batch b, const char* key, double value) {
         bool prof = b->d.d_prof != nullptr;
         if (value < 0 || value > kMaxChunks) return fail(TDSEZ_EINVAL, "chunks must be in 0..%d", kMaxChunks);
         b->d.force_chunks = (int)value;
+        b->d.tuned_chunks.clear();
         free_batch_device(&b->d);
         tdsez_status st = pack_bands(&b->d);
         if (st == TDSEZ_OK && prof) return tdsez_batch_set(b, "profile", 1.0);
@@ -307,6 +311,137 @@ tdsez_status tdsez_propagate(tdsez_system sys, double* psi, const double* E, dou
     long zero = 0;
     return tdsez_propagate_batched(sys->d.solo, psi, &zero, E, &zero, &dt, &nsteps, prec, obs, obs_out,
                                    &zero, stream);
+}
+
+// Partition autotuner.  The chunk count P of a system trades the lane-serial
+// sweeps (about N / P rows each) against the serial separator chain (P
+// blocks); the best balance depends on p, N, the precision and on how much
+// of the device the rest of the batch occupies.  Each trial re-packs the
+// whole batch with one rule for the chunk length, runs a short profiled
+// propagation of all systems together (so every trial sees the batch's own
+// contention), and every system keeps the chunk count of the trial with the
+// fewest shader cycles per step.
+tdsez_status tdsez_autotune(tdsez_batch b, tdsez_precision prec, double budget_ms) {
+    if (!b) return fail(TDSEZ_EINVAL, "b is NULL");
+    if (prec != TDSEZ_FP64 && prec != TDSEZ_FP32_REFINED)
+        return fail(TDSEZ_EINVAL, "unknown precision %d", (int)prec);
+    if (!(budget_ms > 0.0) || !std::isfinite(budget_ms)) return fail(TDSEZ_EINVAL, "budget_ms must be > 0");
+    BatchData* d = &b->d;
+    const int nsys = (int)d->sys.size();
+    const auto t_start = std::chrono::steady_clock::now();
+    auto elapsed_ms = [&]() {
+        return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    };
+    // chunk length rules L = sqrt(c N), the default rule (c = 0.6) first
+    static const double kRule[] = {0.6, 0.3, 1.2, 0.15, 2.4};
+    constexpr int kTrials = sizeof(kRule) / sizeof(kRule[0]);
+    constexpr int kWarm = 4, kProbe = 16;
+    auto chunks_for = [&](int s, double c) {
+        const int N = d->sys[s]->N, p = d->sys[s]->p;
+        double L = std::sqrt(c * N);
+        if (L < 2.0 * p + 2) L = 2.0 * p + 2;
+        int P = (int)std::lround(N / L);
+        return make_plan(N, p, P < 1 ? 1 : P).P;
+    };
+    // scratch inputs: a smooth finite state, zero field (the timing does not
+    // depend on the values)
+    std::vector<long> psi_off(nsys), E_off(nsys), obs_off(nsys);
+    long npsi = 0;
+    for (int s = 0; s < nsys; ++s) {
+        psi_off[s] = npsi;
+        npsi += d->sys[s]->N;
+        E_off[s] = (long)s * (kProbe + 1);
+        obs_off[s] = (long)s * 3 * (kProbe + 1);
+    }
+    std::vector<double> psi_h(2 * (size_t)npsi, 0.0);
+    for (int s = 0; s < nsys; ++s) {
+        const int N = d->sys[s]->N;
+        for (int j = 0; j < N; ++j) psi_h[2 * (size_t)(psi_off[s] + j)] = std::sin(3.141592653589793 * (j + 1.0) / (N + 1.0));
+    }
+    double *d_psi = nullptr, *d_E = nullptr, *d_obs = nullptr;
+    auto release = [&]() {
+        (void)hipFree(d_psi);
+        (void)hipFree(d_E);
+        (void)hipFree(d_obs);
+    };
+    if (hipMalloc(&d_psi, sizeof(double) * psi_h.size()) != hipSuccess ||
+        hipMalloc(&d_E, sizeof(double) * (size_t)nsys * (kProbe + 1)) != hipSuccess ||
+        hipMalloc(&d_obs, sizeof(double) * (size_t)nsys * 3 * (kProbe + 1)) != hipSuccess) {
+        release();
+        return fail(TDSEZ_ENOMEM, "autotune scratch allocation failed");
+    }
+    if (hipMemset(d_E, 0, sizeof(double) * (size_t)nsys * (kProbe + 1)) != hipSuccess) {
+        release();
+        return fail(TDSEZ_EHIP, "hipMemset failed");
+    }
+    const bool had_prof = d->d_prof != nullptr;
+    const double norm_tol = d->norm_tol;
+    d->norm_tol = 0.0;
+    d->force_chunks = 0;
+    std::vector<double> best_cyc(nsys, INFINITY);
+    std::vector<int> best_P(nsys, 0);
+    std::vector<double> prof(9 * (size_t)nsys);
+    tdsez_status st = TDSEZ_OK;
+    for (int t = 0; t < kTrials && st == TDSEZ_OK; ++t) {
+        if (t > 0 && elapsed_ms() > budget_ms) break;
+        d->tuned_chunks.resize(nsys);
+        bool differs = (t == 0);
+        for (int s = 0; s < nsys; ++s) {
+            const int P = chunks_for(s, kRule[t]);
+            differs = differs || (P != best_P[s]);
+            d->tuned_chunks[s] = P;
+        }
+        if (!differs) continue;
+        free_batch_device(d);
+        if ((st = pack_bands(d)) != TDSEZ_OK) break;
+        if ((st = tdsez_batch_set(b, "profile", 1.0)) != TDSEZ_OK) break;
+        for (int rep = 0; rep < 2 && st == TDSEZ_OK; ++rep) {
+            if (hipMemcpy(d_psi, psi_h.data(), sizeof(double) * psi_h.size(), hipMemcpyHostToDevice) !=
+                hipSuccess) {
+                st = fail(TDSEZ_EHIP, "hipMemcpy failed");
+                break;
+            }
+            for (int s = 0; s < nsys; ++s) {
+                SysDesc& sd = d->desc[s];
+                sd.nsteps = rep == 0 ? kWarm : kProbe;
+                sd.dt = 0.05;
+                sd.psi_off = psi_off[s];
+                sd.E_off = E_off[s];
+                sd.obs_off = obs_off[s];
+            }
+            st = launch_propagate(d, d_psi, d_E, d_obs, prec, TDSEZ_OBS_NORM | TDSEZ_OBS_DIPOLE | TDSEZ_OBS_ACCEL,
+                                  nullptr);
+        }
+        if (st != TDSEZ_OK) break;
+        if ((st = tdsez_batch_profile(b, nullptr, prof.data())) != TDSEZ_OK) break;
+        for (int s = 0; s < nsys; ++s) {
+            double cyc = 0.0;
+            for (int k = 0; k < 8; ++k) cyc += prof[9 * (size_t)s + k];
+            if (cyc < best_cyc[s]) {
+                best_cyc[s] = cyc;
+                best_P[s] = d->plan[s].P;
+            }
+        }
+    }
+    release();
+    d->norm_tol = norm_tol;
+    if (st == TDSEZ_OK) {
+        int sys_fail = 0, step_fail = 0;
+        st = tdsez_batch_status(b, nullptr, &sys_fail, &step_fail);
+    }
+    // keep the winners (or, after a failure, the rule) and re-pack
+    if (st == TDSEZ_OK) d->tuned_chunks = best_P;
+    else d->tuned_chunks.clear();
+    free_batch_device(d);
+    tdsez_status st2 = pack_bands(d);
+    if (st2 == TDSEZ_OK && had_prof) st2 = tdsez_batch_set(b, "profile", 1.0);
+    return st != TDSEZ_OK ? st : st2;
+}
+
+tdsez_status tdsez_batch_chunks(tdsez_batch b, int* chunks_out) {
+    if (!b || !chunks_out) return fail(TDSEZ_EINVAL, "NULL argument");
+    for (size_t s = 0; s < b->d.plan.size(); ++s) chunks_out[s] = b->d.plan[s].P;
+    return TDSEZ_OK;
 }
 
 tdsez_status tdsez_batch_profile(tdsez_batch b, void* stream, double* out) {

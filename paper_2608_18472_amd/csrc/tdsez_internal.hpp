@@ -128,8 +128,11 @@ struct BatchData {
     void* d_red = nullptr;           // reduced-system workspace (sized for FP64)
     SysDesc* d_desc = nullptr;
     std::vector<SysDesc> desc_on_device;  // last uploaded descriptors (skip identical uploads)
+    int* d_order = nullptr;          // workgroup -> system, longest first
+    std::vector<int> order_host;     // host copy of d_order (pageable; uploaded asynchronously)
+    std::vector<int> tuned_chunks;   // plan cache of tdsez_autotune (0 = rule), per system
     int* d_status = nullptr;         // [0] code, [1] system, [2] step
-    unsigned long long* d_prof = nullptr;  // optional phase cycle counters, 5 per system
+    unsigned long long* d_prof = nullptr;  // optional phase cycle counters, 9 per system
     int nsys_alloc_desc = 0;
 };
 
@@ -147,9 +150,10 @@ tdsez_status pack_bands(BatchData* b);
 tdsez_status launch_propagate(BatchData* b, double* psi, const double* E, double* obs,
                               tdsez_precision prec, unsigned obs_mask, hipStream_t stream);
 // Adjoint (tdsez_adjoint.hip): descriptors already hold nsteps, dt and offsets
-// Upload the batch descriptors if they differ from the last upload (a
-// repeated call with the same arguments then enqueues kernels only, so it can
-// be captured into a graph after a warm-up call).
+// Upload the batch descriptors, and the longest-first workgroup order derived
+// from them, if they differ from the last upload (a repeated call with the
+// same arguments then enqueues kernels only, so it can be captured into a
+// graph after a warm-up call).
 tdsez_status upload_descriptors(BatchData* b, hipStream_t stream);
 tdsez_status launch_adjoint(BatchData* b, const double* psi0, const double* E, const double* dJdobs,
                             unsigned obs_mask, double* dJdE, double* dJdpsi0, int ckpt_stride,

@@ -33,6 +33,7 @@
 //                           row = k*L + l
 //   state  [l][col]          complex128
 //   factor [j][item][k]      2p+2 items per interior pivot j (fac_items)
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 
@@ -142,7 +143,7 @@ __device__ __forceinline__ void run_system(const KernelArgs& ka, const SysDesc& 
 
 template <typename FT>
 __global__ __launch_bounds__(kWave) void propagate_kernel(KernelArgs ka) {
-    const int sidx = blockIdx.x;
+    const int sidx = ka.order[blockIdx.x];
     const SysDesc sd = ka.descs[sidx];
     switch (sd.p) {
         case 1: run_system<1, FT>(ka, sd, sidx); break;
@@ -262,7 +263,8 @@ tdsez_status pack_bands(BatchData* b) {
     b->maxp = 0;
     for (int s = 0; s < nsys; ++s) {
         SystemData* sy = b->sys[s];
-        Plan pl = make_plan(sy->N, sy->p, b->force_chunks);
+        const int tuned = s < (int)b->tuned_chunks.size() ? b->tuned_chunks[s] : 0;
+        Plan pl = make_plan(sy->N, sy->p, b->force_chunks > 0 ? b->force_chunks : tuned);
         b->plan[s] = pl;
         SysDesc& d = b->desc[s];
         d = SysDesc{};
@@ -291,6 +293,7 @@ tdsez_status pack_bands(BatchData* b) {
     TDSEZ_HIP_TRY(hipMalloc(&b->d_fac, 2 * sizeof(double) * (size_t)(foff > 0 ? foff : 1)));
     TDSEZ_HIP_TRY(hipMalloc(&b->d_red, 2 * sizeof(double) * (size_t)roff));
     TDSEZ_HIP_TRY(hipMalloc(&b->d_desc, sizeof(SysDesc) * nsys));
+    TDSEZ_HIP_TRY(hipMalloc(&b->d_order, sizeof(int) * nsys));
     TDSEZ_HIP_TRY(hipMalloc(&b->d_status, sizeof(int) * 4));
     TDSEZ_HIP_TRY(hipMemset(b->d_status, 0, sizeof(int) * 4));
     b->nsys_alloc_desc = nsys;
@@ -315,7 +318,20 @@ tdsez_status upload_descriptors(BatchData* b, hipStream_t stream) {
     if (b->desc_on_device.size() == n &&
         std::memcmp(b->desc_on_device.data(), b->desc.data(), sizeof(SysDesc) * n) == 0)
         return TDSEZ_OK;
+    // Workgroups are dispatched in index order, so when the batch holds more
+    // systems than the device has wave slots the costliest ones (cost
+    // N (p + 1) nsteps) start first and the short ones fill in behind them.
+    b->order_host.resize(n);
+    for (size_t s = 0; s < n; ++s) b->order_host[s] = (int)s;
+    auto cost = [&](int s) {
+        const SysDesc& d = b->desc[s];
+        return (double)d.N * (d.p + 1) * (double)d.nsteps;
+    };
+    std::stable_sort(b->order_host.begin(), b->order_host.end(),
+                     [&](int x, int y) { return cost(x) > cost(y); });
     TDSEZ_HIP_TRY(hipMemcpyAsync(b->d_desc, b->desc.data(), sizeof(SysDesc) * n, hipMemcpyHostToDevice, stream));
+    TDSEZ_HIP_TRY(hipMemcpyAsync(b->d_order, b->order_host.data(), sizeof(int) * n, hipMemcpyHostToDevice,
+                                 stream));
     b->desc_on_device = b->desc;
     return TDSEZ_OK;
 }
@@ -336,6 +352,7 @@ tdsez_status launch_propagate(BatchData* b, double* psi, const double* E, double
     }
     KernelArgs ka;
     ka.descs = b->d_desc;
+    ka.order = b->d_order;
     ka.band64 = b->d_band64;
     ka.st = b->d_state;
     ka.dtot = b->d_dtot;

@@ -61,9 +61,11 @@ def lib():
         "tdsez_system2d_size": [vp, ip, ip, ip],
         "tdsez_get_v2": [vp, dp],
         "tdsez_propagate_2d": [vp, vp, vp, d, i, i, u, vp, d, i, vp],
-        "tdsez_system2d_stats": [vp, lp, lp, ip],
+        "tdsez_system2d_stats": [vp, lp, lp, ip, lp],
         "tdsez_batch_status": [vp, vp, ip, ip],
         "tdsez_batch_profile": [vp, vp, dp],
+        "tdsez_autotune": [vp, i, d],
+        "tdsez_batch_chunks": [vp, ip],
         "tdsez_system_status": [vp, vp, ip],
     }
     for name, args in sigs.items():
@@ -346,6 +348,22 @@ def batch_profile(batch, stream=None):
     return out.reshape(-1, 9)
 
 
+def autotune(batch, prec=None, budget_ms=2000.0):
+    """Choose every system's partition count by timing short propagations of
+    the whole batch (tdsez_autotune); returns the chosen counts."""
+    if prec is None:
+        prec = FP32_REFINED
+    _check(lib().tdsez_autotune(batch.handle, int(prec), float(budget_ms)))
+    return batch_chunks(batch)
+
+
+def batch_chunks(batch):
+    """Partition count P of every system under the batch's current plan."""
+    out = np.zeros(len(batch.systems), dtype=np.int32)
+    _check(lib().tdsez_batch_chunks(batch.handle, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int))))
+    return out
+
+
 def system_status(sys, stream=None):
     n = ctypes.c_int()
     _check(lib().tdsez_system_status(sys.handle, _stream_handle(stream), ctypes.byref(n)))
@@ -420,8 +438,9 @@ def propagate_2d(sys2d, psi, E, dt, nsteps, prec=FP64, obs=OBS_NORM | OBS_DIPOLE
 
 
 def system2d_stats(sys2d):
-    """(steps, COCG iterations, largest iteration count of one step) since
-    the last call."""
-    a, b, c = ctypes.c_long(), ctypes.c_long(), ctypes.c_int()
-    _check(lib().tdsez_system2d_stats(sys2d.handle, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
-    return a.value, b.value, c.value
+    """(steps, Krylov iterations, largest iteration count of one step,
+    refinement sweeps) since the last call."""
+    a, b, c, d = ctypes.c_long(), ctypes.c_long(), ctypes.c_int(), ctypes.c_long()
+    _check(lib().tdsez_system2d_stats(sys2d.handle, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),
+                                      ctypes.byref(d)))
+    return a.value, b.value, c.value, d.value

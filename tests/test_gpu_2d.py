@@ -1,9 +1,11 @@
 """GPU two-dimensional tensor-product path against the FP64 oracle.
 
 Tolerances: potential stencil to 1e-13 relative; nu and x-dipole series to
-1e-10 relative L2 (both sides converge each step's solve to 1e-13 or below,
-from different solvers: the oracle's numpy COCG and the library's GEMM
-preconditioned COCG)."""
+1e-10 relative L2 for the FP64 path (both sides converge each step's solve
+to 1e-13 or below, from different solvers: the oracle's numpy COCG and the
+library's GEMM preconditioned COCG).  The FP32-refined path must meet the
+1e-5 dipole bar; since its refinement sweeps drive the same FP64 residual
+below the same tolerance, it is held to 1e-8 here."""
 import math
 import sys
 
@@ -43,14 +45,17 @@ def product_ground_state(sd):
     return np.outer(vecs[1], vecs[0]).astype(np.complex128)
 
 
-def run_gpu_2d(sd, psi0, nsteps, tol=1e-13):
-    g = T.assemble_workload_2d(sd)
+def run_gpu_2d(sd, psi0, nsteps, tol=1e-13, prec=T.FP64, g=None):
+    g = g if g is not None else T.assemble_workload_2d(sd)
     psi = torch.from_numpy(psi0.reshape(-1).copy()).cuda()
     E = torch.from_numpy(np.asarray(sd.E[: nsteps + 1], np.float64).copy()).cuda()
     o = torch.zeros(3 * (nsteps + 1), dtype=torch.float64, device="cuda")
-    T.propagate_2d(g, psi, E, sd.dt, nsteps, T.FP64, T.OBS_NORM | T.OBS_DIPOLE, o, tol=tol, maxit=300)
-    steps, its, mx = T.system2d_stats(g)
-    say("COCG iterations: %d steps, %.2f per step, max %d" % (steps, its / max(steps, 1), mx))
+    T.propagate_2d(g, psi, E, sd.dt, nsteps, prec, T.OBS_NORM | T.OBS_DIPOLE, o, tol=tol, maxit=300)
+    steps, its, mx, sweeps = T.system2d_stats(g)
+    say("prec %d: %d steps, %.2f Krylov iterations per step (max %d), %.2f refinement sweeps per step" % (
+        prec, steps, its / max(steps, 1), mx, sweeps / max(steps, 1)))
+    if prec == T.FP32_REFINED:
+        assert sweeps >= steps
     return o.cpu().numpy().reshape(-1, 3), psi.cpu().numpy().reshape(psi0.shape)
 
 
@@ -72,34 +77,38 @@ def test_potential_stencil_matches_oracle():
     assert np.abs(v - m2["V2"]).max() < 1e-13 * np.abs(m2["V2"]).max()
 
 
-def test_small_grid_propagation_matches_oracle():
+@pytest.mark.parametrize("prec", [T.FP64, T.FP32_REFINED])
+def test_small_grid_propagation_matches_oracle(prec):
     ns = 300
     sd = small_case(ns)
     psi0 = product_ground_state(sd)
     m2 = O.assemble_2d(sd.breaks_x, sd.breaks_y, sd.order, sd.nq, sd.V)
     ref, cref = O.propagate_2d(m2, psi0, sd.E, sd.dt, ns, tol=1e-14)
-    got, cgot = run_gpu_2d(sd, psi0, ns)
+    got, cgot = run_gpu_2d(sd, psi0, ns, prec=prec)
     errs = [rel(got[:, k], ref[:, k]) for k in range(2)]
-    say("small 2D errors", errs, rel(cgot, cref))
-    assert errs[0] < 1e-10 and errs[1] < 1e-10
-    assert rel(cgot, cref) < 1e-10
+    say("small 2D errors", prec, errs, rel(cgot, cref))
+    tol = 1e-10 if prec == T.FP64 else 1e-8
+    assert errs[0] < tol and errs[1] < tol
+    assert rel(cgot, cref) < tol
 
 
 def test_config4_reduced_grid_matches_oracle():
     """The 2D soft-Coulomb workload on a 128 x 128 grid (same box, order,
     dt), 100 steps with the carrier at full amplitude (the sin^2 envelope is
     ~1e-3 over the first steps, which would leave a dipole too small for a
-    relative comparison)."""
+    relative comparison); FP64 and FP32-refined on one assembled system."""
     ns = 100
     sd = W.config4(n=128, nsteps=ns)
     sd.E = 0.05 * np.sin(0.057 * sd.dt * np.arange(ns + 1) + 0.3)
     psi0 = product_ground_state(sd)
     m2 = O.assemble_2d(sd.breaks_x, sd.breaks_y, sd.order, sd.nq, sd.V)
     ref, _ = O.propagate_2d(m2, psi0, sd.E, sd.dt, ns, tol=1e-14)
-    got, _ = run_gpu_2d(sd, psi0, ns)
-    errs = [rel(got[:, k], ref[:, k]) for k in range(2)]
-    say("config4 128^2 errors", errs)
-    assert errs[0] < 1e-10 and errs[1] < 1e-10
+    g = T.assemble_workload_2d(sd)
+    for prec, tol in ((T.FP64, 1e-10), (T.FP32_REFINED, 1e-8)):
+        got, _ = run_gpu_2d(sd, psi0, ns, prec=prec, g=g)
+        errs = [rel(got[:, k], ref[:, k]) for k in range(2)]
+        say("config4 128^2 errors", prec, errs)
+        assert errs[0] < tol and errs[1] < tol
 
 
 def test_config4_full_size_first_steps_match_oracle():
@@ -111,20 +120,23 @@ def test_config4_full_size_first_steps_match_oracle():
     sd.E = 0.05 * np.sin(0.057 * sd.dt * np.arange(ns + 1) + 0.3)
     m2 = O.assemble_2d(sd.breaks_x, sd.breaks_y, sd.order, sd.nq, sd.V)
     ref, cref = O.propagate_2d(m2, psi0, sd.E, sd.dt, ns, tol=1e-14)
-    got, cgot = run_gpu_2d(sd, psi0, ns)
-    errs = [rel(got[:, k], ref[:, k]) for k in range(2)]
-    say("config4 512^2 errors", errs, rel(cgot, cref))
-    assert errs[0] < 1e-10 and errs[1] < 1e-10
-    assert rel(cgot, cref) < 1e-10
+    g = T.assemble_workload_2d(sd)
+    for prec, tol in ((T.FP64, 1e-10), (T.FP32_REFINED, 1e-8)):
+        got, cgot = run_gpu_2d(sd, psi0, ns, prec=prec, g=g)
+        errs = [rel(got[:, k], ref[:, k]) for k in range(2)]
+        say("config4 512^2 errors", prec, errs, rel(cgot, cref))
+        assert errs[0] < tol and errs[1] < tol
+        assert rel(cgot, cref) < tol
 
 
-def test_zero_state_stays_zero():
+@pytest.mark.parametrize("prec", [T.FP64, T.FP32_REFINED])
+def test_zero_state_stays_zero(prec):
     sd = small_case(5)
     g = T.assemble_workload_2d(sd)
     psi = torch.zeros(g.Nx * g.Ny, dtype=torch.complex128, device="cuda")
     E = torch.from_numpy(sd.E.copy()).cuda()
     o = torch.zeros(3 * 6, dtype=torch.float64, device="cuda")
-    T.propagate_2d(g, psi, E, sd.dt, 5, T.FP64, 3, o)
+    T.propagate_2d(g, psi, E, sd.dt, 5, prec, 3, o)
     assert float(psi.abs().max()) == 0.0
     assert float(o.abs().max()) == 0.0
 
@@ -135,10 +147,7 @@ def test_2d_invalid_arguments():
     psi = torch.zeros(g.Nx * g.Ny, dtype=torch.complex128, device="cuda")
     E = torch.zeros(3, dtype=torch.float64, device="cuda")
     o = torch.zeros(9, dtype=torch.float64, device="cuda")
-    with pytest.raises(T.TdsezError) as e:
-        T.propagate_2d(g, psi, E, 0.05, 2, T.FP32_REFINED, 3, o)
-    assert e.value.status == 7
-    for kw in ({"obs": 7}, {"tol": 0.0}, {"maxit": 0}):
+    for kw in ({"obs": 7}, {"tol": 0.0}, {"maxit": 0}, {"prec": 5}):
         args = dict(prec=T.FP64, obs=3, obs_out=o, tol=1e-12, maxit=10)
         args.update(kw)
         with pytest.raises(T.TdsezError) as e:
