@@ -34,8 +34,8 @@ CALIB_COPY_BYTES = 512 * 2 ** 20
 # two rocprofv3 --pmc runs of this script (FETCH_SIZE, then WRITE_SIZE) scaled
 # by the copy calibration; valid only for the kernel sources they were taken
 # on (sha256 of the listed files).  See profiles/propagate_kernel_fp32_batch1024_pmc.md.
-TRAFFIC = {"sources_sha256": "7b2274036231c04085cb4bee5f28fc2a89d7347b518bf08da375e32ac626fe3e",
-           "bytes_per_launch": 2.7145e13}
+TRAFFIC = {"sources_sha256": "bcab249fa2e34449d4da39deaa9a4a72ab7cefe5c78ec4f53266fa84c7424569",
+           "bytes_per_launch": 2.7199e13}
 KERNEL_SOURCES = ["paper_2608_18472_amd/csrc/tdsez_passes.hpp", "paper_2608_18472_amd/csrc/tdsez_propagate.hip",
                   "paper_2608_18472_amd/csrc/tdsez_internal.hpp"]
 
@@ -107,11 +107,20 @@ def main():
     ap.add_argument("--cpu-systems", type=int, default=96)
     ap.add_argument("--cpu-steps", type=int, default=6000)
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--tune-ms", type=float, default=3000.0,
+                    help="partition autotuner budget per precision (setup, untimed); 0 keeps the default rule")
+    ap.add_argument("--workload", choices=["batch1d", "2d"], default="batch1d",
+                    help="batch1d: the batched 1D benchmark (default); 2d: a segment of the 512 x 512 "
+                         "tensor-product workload")
+    ap.add_argument("--steps-2d", type=int, default=400, help="time steps of the 2D segment")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the batched propagation has no multi-GPU path in this "
               "build (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "2d":
+        run_2d(args)
+        return
 
     import torch
     from paper_2608_18472_amd import tdsez as T
@@ -162,7 +171,15 @@ def main():
     results = {}
     precs = [("fp32-refined", T.FP32_REFINED)] + ([] if args.no_fp64 else [("fp64", T.FP64)])
     obs_by = {}
+    rule_chunks = T.batch_chunks(batch).copy()
+    tuned = {}
     for name, prec in precs:
+        if args.tune_ms > 0:
+            # setup: per-system partition counts from short probe launches
+            t_tune = time.perf_counter()
+            ch = T.autotune(batch, prec, args.tune_ms)
+            tuned[name] = {"seconds": time.perf_counter() - t_tune,
+                           "systems_changed": int(np.sum(ch != rule_chunks))}
         ob = torch.zeros_like(obs)
         if args.warmup > 0:
             run(prec, args.warmup, ob)
@@ -210,6 +227,7 @@ def main():
             "fp64_ms_per_step": results["fp64"] * 1000.0 if "fp64" in results else None,
             "dipole_rel_err_fp32_vs_fp64": eps_d,
             "refine_sweeps": 1,
+            "autotune": tuned if tuned else None,
             "algorithmic_bytes_per_launch": alg_bytes,
             "setup_s": t_setup,
             "ground_state_s": t_gs,
@@ -225,6 +243,75 @@ def main():
     }
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(args.cpu_systems, args.cpu_steps)
+    print(json.dumps(line), flush=True)
+
+
+def run_2d(args):
+    """A segment of the 2D soft-Coulomb workload (512 x 512 order-6 splines on
+    [-120, 120]^2, x-polarised sin^2 pulse E0 0.05, w 0.057, 4 cycles, dt
+    0.05): steps 2000 .. 2000 + steps_2d of the pulse (field on), FP64 COCG
+    and FP32-refined, both to relative residual 1e-12 per step."""
+    import torch
+    from paper_2608_18472_amd import tdsez as T
+    from paper_2608_18472_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    sd = W.config4()
+    g = T.assemble_workload_2d(sd)
+    # initial state: product of the per-axis 1D ground states (library eigensolver)
+    vecs = []
+    for br in (sd.breaks_x, sd.breaks_y):
+        xq = T.quad_points(br, sd.nq)
+        s1 = T.assemble(br, sd.order, sd.nq, None, -1.0 / np.sqrt(xq * xq + 1.0), 0.0 * xq)
+        ev, vec = T.ground_state(s1)
+        vecs.append(vec[0])
+    psi0 = torch.from_numpy(np.outer(vecs[1], vecs[0]).astype(np.complex128).reshape(-1)).cuda()
+    n0, ns = 2000, args.steps_2d
+    E = torch.from_numpy(np.ascontiguousarray(sd.E[n0: n0 + ns + 1])).cuda()
+    stream = torch.cuda.current_stream()
+    out = {}
+    for name, prec in (("fp32-refined", T.FP32_REFINED), ("fp64", T.FP64)):
+        o = torch.zeros(3 * (ns + 1), dtype=torch.float64, device="cuda")
+        T.propagate_2d(g, psi0.clone(), E[:4].contiguous(), sd.dt, 3, prec, 3, o[:12], tol=1e-12)  # warm-up
+        T.system2d_stats(g)
+        psi = psi0.clone()
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        T.propagate_2d(g, psi, E, sd.dt, ns, prec, 3, o, tol=1e-12, stream=stream)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        sec = ev0.elapsed_time(ev1) / 1000.0
+        steps, its, mx, sweeps = T.system2d_stats(g)
+        out[name] = {"sec": sec, "its": its / steps, "sweeps": sweeps / steps, "obs": o.cpu().numpy()}
+    d64 = out["fp64"]["obs"].reshape(-1, 3)[:, 1]
+    d32 = out["fp32-refined"]["obs"].reshape(-1, 3)[:, 1]
+    n = g.Nx * g.Ny
+    line = {
+        "metric": "complex DOF-steps/s per GPU (2D tensor-product segment)",
+        "value": n * ns / out["fp32-refined"]["sec"],
+        "unit": "DOF-steps/s",
+        "n_gpus": 1,
+        "steps": ns,
+        "warmup": 3,
+        "ms_per_step": 1000.0 * out["fp32-refined"]["sec"] / ns,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "2D soft-Coulomb, 512 x 512 order-6 splines on [-120,120]^2, x-polarised sin^2 pulse "
+                        "E0 0.05 w 0.057 4 cycles, dt 0.05, steps %d..%d, residual 1e-12" % (n0, n0 + ns),
+            "fp32_refined": {"ms_per_step": 1000.0 * out["fp32-refined"]["sec"] / ns,
+                             "inner_iterations_per_step": out["fp32-refined"]["its"],
+                             "sweeps_per_step": out["fp32-refined"]["sweeps"]},
+            "fp64": {"value": n * ns / out["fp64"]["sec"], "ms_per_step": 1000.0 * out["fp64"]["sec"] / ns,
+                     "iterations_per_step": out["fp64"]["its"]},
+            "dipole_rel_err_fp32_vs_fp64": float(np.linalg.norm(d32 - d64) / np.linalg.norm(d64)),
+        },
+    }
     print(json.dumps(line), flush=True)
 
 

@@ -410,7 +410,7 @@ tdsez_status tdsez_autotune(tdsez_batch b, tdsez_precision prec, double budget_m
                 sd.obs_off = obs_off[s];
             }
             st = launch_propagate(d, d_psi, d_E, d_obs, prec, TDSEZ_OBS_NORM | TDSEZ_OBS_DIPOLE | TDSEZ_OBS_ACCEL,
-                                  nullptr);
+                                  nullptr, true);
         }
         if (st != TDSEZ_OK) break;
         if ((st = tdsez_batch_profile(b, nullptr, prof.data())) != TDSEZ_OK) break;

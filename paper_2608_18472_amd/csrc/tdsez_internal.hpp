@@ -147,8 +147,9 @@ int gauss_legendre_host(int nq, double* x, double* w);
 // Propagation (tdsez_propagate.hip)
 Plan make_plan(int N, int p, int force_chunks);
 tdsez_status pack_bands(BatchData* b);
+// probe: launch the autotuner's separately named copy of the kernel
 tdsez_status launch_propagate(BatchData* b, double* psi, const double* E, double* obs,
-                              tdsez_precision prec, unsigned obs_mask, hipStream_t stream);
+                              tdsez_precision prec, unsigned obs_mask, hipStream_t stream, bool probe = false);
 // Adjoint (tdsez_adjoint.hip): descriptors already hold nsteps, dt and offsets
 // Upload the batch descriptors, and the longest-first workgroup order derived
 // from them, if they differ from the last upload (a repeated call with the

@@ -614,19 +614,12 @@ __device__ __forceinline__ void pass_reduced(const SysDesc& sd, int lane, FT* __
         return r;
     };
 
-    // forward sweep; block inputs are loaded kAhead blocks ahead (a few
-    // registers each), which hides the memory latency behind the chain
-    constexpr int kAhead = 4;
+    // forward sweep
     cplx<FT> dprev = zero;  // Delta_{s-1}^-1 entry
     cplx<FT> zc = zero;     // z_{s-1} in column layout
-    Fwd fq[kAhead];
-#pragma unroll
-    for (int t = 0; t < kAhead; ++t) fq[t] = load_fwd(t);
+    Fwd cur = load_fwd(0);
     for (int s = 0; s < P; ++s) {
-        const Fwd cur = fq[0];
-#pragma unroll
-        for (int t = 0; t + 1 < kAhead; ++t) fq[t] = fq[t + 1];
-        fq[kAhead - 1] = load_fwd(s + kAhead);
+        Fwd nxt = load_fwd(s + 1);
         const bool more = s + 1 < P;
         const cplx<FT> g = csel(i < p, cadd(cur.y, csel(more, cur.gt, zero)), zero);
         const cplx<FT> fv = csel(valid, cur.f, zero);
@@ -671,6 +664,7 @@ __device__ __forceinline__ void pass_reduced(const SysDesc& sd, int lane, FT* __
         cplx<FT> zr = csub(g, row_sum(cmul(mm, zc)));
         if (j == 0 && i < p) st_c(z_base, (unsigned)(s * p + i), zr);
         zc = shfl_c(zr, 8 * j);
+        cur = nxt;
     }
     __syncthreads();  // z_s written by other lanes
     // backward sweep: lane (i, j) loads F_{s+1}[j][i] (transposed) so that
@@ -689,14 +683,9 @@ __device__ __forceinline__ void pass_reduced(const SysDesc& sd, int lane, FT* __
         return r;
     };
     cplx<FT> xc = zero;  // x_{s+1} in column layout
-    Bwd bq[kAhead];
-#pragma unroll
-    for (int t = 0; t < kAhead; ++t) bq[t] = load_bwd(P - 1 - t);
+    Bwd bc = load_bwd(P - 1);
     for (int s = P - 1; s >= 0; --s) {
-        const Bwd bc = bq[0];
-#pragma unroll
-        for (int t = 0; t + 1 < kAhead; ++t) bq[t] = bq[t + 1];
-        bq[kAhead - 1] = load_bwd(s - kAhead);
+        Bwd bn = load_bwd(s - 1);
         const cplx<FT> dv = csel(valid, bc.dv, ident);
         const cplx<FT> fnt = csel(valid && s + 1 < P, bc.fnt, zero);
         const cplx<FT> zs = csel(i < p, bc.zs, zero);
@@ -707,6 +696,7 @@ __device__ __forceinline__ void pass_reduced(const SysDesc& sd, int lane, FT* __
         const cplx<FT> xr = row_sum(cmul(dv, wc));
         if (j == 0 && i < p) st_c(x_base, (unsigned)(s * p + i), xr);
         xc = shfl_c(xr, 8 * j);
+        bc = bn;
     }
 }
 
