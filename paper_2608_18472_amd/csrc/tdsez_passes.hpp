@@ -788,8 +788,8 @@ __device__ __forceinline__ void pass_backsub(const SysDesc& sd, int k, const FT*
         ur[q] = u;
     }
     // back substitution over the interior pivots, window of the next p
-    // values; each pivot's factor row (with the row's state) is loaded two
-    // pivots ahead of its use
+    // values; each pivot's factor row (with the row's state) is loaded ahead
+    // of its use through a ring of row buffers
     struct FRow {
         cplx<FT> it[IT];  // items 0..p-1 l, p dinv, p+1 yhat, p+2..2p+1 f
         cplx<double> c, d;
@@ -818,21 +818,32 @@ __device__ __forceinline__ void pass_backsub(const SysDesc& sd, int k, const FT*
         xw[1] = xj;
         update(j, xj, fr.c, fr.d);
     };
-    FRow cur = load_frow(m - 1);
-    FRow nx1 = load_frow(m - 2);
+    // Pivots are visited in order j = m-1, m-2, ..., 0; the one with ordinal
+    // t = m-1-j uses ring slot t % kRing, which is refilled with the pivot
+    // kRing further on right after its use.  Slot indices are compile-time
+    // constants (no register moves) and kRing - 1 rows stay in flight (two
+    // for FP64, whose rows are twice the size).
+    constexpr int kRing = sizeof(FT) == 4 ? 4 : 3;
+    FRow fr[kRing];
+#pragma unroll
+    for (int t = 0; t < kRing; ++t) fr[t] = load_frow(m - 1 - t);
 #pragma unroll
     for (int q = PP - 1; q >= 0; --q) {
-        FRow nx2 = load_frow(m - PP + q - 2);
-        back_row(m - PP + q, cur, ur[q]);
-        cur = nx1;
-        nx1 = nx2;
+        const int t = PP - 1 - q;
+        back_row(m - PP + q, fr[t % kRing], ur[q]);
+        fr[t % kRing] = load_frow(m - 1 - t - kRing);
     }
-    for (int j = m - PP - 1; j >= 0; --j) {
-        FRow nx2 = load_frow(j - 2);
-        back_row(j, cur, cmk<FT>(0, 0));
-        cur = nx1;
-        nx1 = nx2;
+    int j = m - PP - 1;
+    for (; j >= kRing - 1; j -= kRing) {
+#pragma unroll
+        for (int u = 0; u < kRing; ++u) {
+            back_row(j - u, fr[(PP + u) % kRing], cmk<FT>(0, 0));
+            fr[(PP + u) % kRing] = load_frow(j - u - kRing);
+        }
     }
+#pragma unroll
+    for (int u = 0; u + 1 < kRing; ++u)
+        if (j - u >= 0) back_row(j - u, fr[(PP + u) % kRing], cmk<FT>(0, 0));
 #pragma unroll
     for (int t = 0; t < PP; ++t) update(m + t, xr[t], sepc[t], sepd[t]);
 }

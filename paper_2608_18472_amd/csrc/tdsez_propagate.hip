@@ -119,7 +119,9 @@ __device__ __forceinline__ void run_system(const KernelArgs& ka, const SysDesc& 
         if (active) pass_backsub<PP, FT>(sd, lane, band, st, dtot, true, fac, red, alpha, Ebar);
         __syncthreads();
         mark(4);
-        for (int sweep = 0; sweep < refine; ++sweep) {
+        // refinement sweeps exist for the FP32 factorisation only (FP64
+        // launches pass refine = 0); FP64 code is built without them
+        for (int sweep = 0; sizeof(FT) == 4 && sweep < refine; ++sweep) {
             if (active)
                 pass_residual<PP, FT>(sd, lane, band, ka.band64, st, dtot, fac, red, alpha, Ebar);
             __syncthreads();
