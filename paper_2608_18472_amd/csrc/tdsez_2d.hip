@@ -217,56 +217,50 @@ __global__ __launch_bounds__(kStencilThreads) void apply_kernel(
         d_re[ly][tx] = dr;
         d_im[ly][tx] = di;
     }
-    // (3) potential, from the input tile (independent of the x pass).  Rows
-    // of offsets are kept rolled (11 loads in flight per row, not 121) so
-    // that the kernel keeps a small register footprint.
+    // (3) potential, from the input tile (independent of the x pass), one
+    // row of 2p+1 offsets at a time with the next row's loads in flight.
+    // Offset (dy, dx) is stored at this row when dy > 0 or (dy = 0, dx >= 0);
+    // otherwise the mirrored offset is read at the neighbour's row, clamped
+    // into the plane where the neighbour is outside (c is zero there).
     const int ixc = ix < Nx ? ix : Nx - 1, iyc = iy < Ny ? iy : Ny - 1;
     const long long row = (long long)iyc * Nx + ixc;
-    FT vr = 0, vi = 0;
-    // dy < 0: the mirrored half, read at the neighbour's row (clamped into
-    // the plane where the neighbour is outside; c is zero there)
-#pragma unroll 1
-    for (int ky = 0; ky < PP; ++ky) {
+    int jxc[K];
+#pragma unroll
+    for (int kx = 0; kx < K; ++kx) {
+        const int jx = ixc + kx - PP;
+        jxc[kx] = jx < 0 ? 0 : (jx >= Nx ? Nx - 1 : jx);
+    }
+    auto vrow = [&](int ky, FT v[K]) {
         const int dy = ky - PP;
         int jy = iyc + dy;
-        jy = jy < 0 ? 0 : jy;
-        const FT* __restrict__ vrow = V2h + (long long)half_index(PP, -dy, 0) * plane + (long long)jy * Nx;
+        jy = jy < 0 ? 0 : (jy >= Ny ? Ny - 1 : jy);
+        const long long nrow = (long long)jy * Nx;
 #pragma unroll
         for (int kx = 0; kx < K; ++kx) {
             const int dxo = kx - PP;
-            int jx = ixc + dxo;
-            jx = jx < 0 ? 0 : (jx >= Nx ? Nx - 1 : jx);
-            // offset (-dy, -dxo) is stored -dxo planes after (-dy, 0)
-            const FT v = vrow[(long long)(-dxo) * plane + jx];
-            vr += v * tre[ty + ky][tx + kx];
-            vi += v * tim[ty + ky][tx + kx];
+            const bool direct = dy > 0 || (dy == 0 && dxo >= 0);
+            const int h = direct ? half_index(PP, dy, dxo) : half_index(PP, -dy, -dxo);
+            v[kx] = V2h[(long long)h * plane + (direct ? row : nrow + jxc[kx])];
         }
-    }
-    // dy == 0: dx < 0 mirrored (same row of the tile), dx >= 0 direct
-#pragma unroll
-    for (int kx = 0; kx < K; ++kx) {
-        const int dxo = kx - PP;
-        FT v;
-        if (dxo >= 0) {
-            v = V2h[(long long)half_index(PP, 0, dxo) * plane + row];
-        } else {
-            const int jx = ixc + dxo < 0 ? 0 : ixc + dxo;
-            v = V2h[(long long)half_index(PP, 0, -dxo) * plane + (long long)iyc * Nx + jx];
-        }
-        vr += v * tre[ty + PP][tx + kx];
-        vi += v * tim[ty + PP][tx + kx];
-    }
-    // dy > 0: the stored half at this row
-#pragma unroll 1
-    for (int ky = PP + 1; ky < K; ++ky) {
-        const FT* __restrict__ vrow = V2h + (long long)half_index(PP, ky - PP, -PP) * plane + row;
+    };
+    FT vr = 0, vi = 0;
+    auto vacc = [&](int ky, const FT v[K]) {
 #pragma unroll
         for (int kx = 0; kx < K; ++kx) {
-            const FT v = vrow[(long long)kx * plane];
-            vr += v * tre[ty + ky][tx + kx];
-            vi += v * tim[ty + ky][tx + kx];
+            vr += v[kx] * tre[ty + ky][tx + kx];
+            vi += v[kx] * tim[ty + ky][tx + kx];
         }
+    };
+    FT va[K], vb[K];
+    vrow(0, va);
+#pragma unroll 1
+    for (int ky = 0; ky + 1 < K; ky += 2) {
+        vrow(ky + 1, vb);
+        vacc(ky, va);
+        vrow(ky + 2, va);
+        vacc(ky + 1, vb);
     }
+    vacc(K - 1, va);
     __syncthreads();
     // (2) y pass
     FT Sr = 0, Si = 0, Hr = 0, Hi = 0, Dr = 0, Di = 0;

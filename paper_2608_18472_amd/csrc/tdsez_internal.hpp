@@ -91,7 +91,7 @@ struct Plan {
 struct SysDesc {
     int N, p, P, L, m, LS;
     int nsteps;
-    int pad_;
+    int mi_is_s;          // constant mass: Mi equals S bit for bit (m^-1 = 1 at every point)
     double dt;
     long long band_off;   // elements into the FP64/FP32 packed band buffers
     long long state_off;  // complex elements into the interleaved state buffer

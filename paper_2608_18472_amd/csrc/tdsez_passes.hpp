@@ -93,6 +93,7 @@ __device__ __forceinline__ void pass_rhs(const SysDesc& sd, int k, const FT* __r
                          double Ebar, double En, bool want_acc, bool want_rhs, double obs_part[3]) {
     constexpr int NM = kNumMats;
     const int L = sd.L, LS = sd.LS;
+    const bool mi_is_s = sd.mi_is_s != 0;
     int col = k + 1;
     // Per-lane addresses are rebuilt every step instead of being hoisted out
     // of the time loop (that would keep hundreds of them live in registers).
@@ -136,9 +137,11 @@ __device__ __forceinline__ void pass_rhs(const SysDesc& sd, int k, const FT* __r
         }
         if (want_acc && own) {
 #pragma unroll
-            for (int d = 0; d <= PP; ++d) {
-                in.bG[d] = bnd[rb + (unsigned)((3 * (PP + 1) + d) * LS)];
-                in.bM[d] = bnd[rb + (unsigned)((4 * (PP + 1) + d) * LS)];
+            for (int d = 0; d <= PP; ++d) in.bG[d] = bnd[rb + (unsigned)((3 * (PP + 1) + d) * LS)];
+            // with constant mass Mi is S, whose row is already loaded
+            if (!mi_is_s) {
+#pragma unroll
+                for (int d = 0; d <= PP; ++d) in.bM[d] = bnd[rb + (unsigned)((4 * (PP + 1) + d) * LS)];
             }
         }
         const unsigned sat = (unsigned)lr * (unsigned)LS + cc;
@@ -189,9 +192,9 @@ __device__ __forceinline__ void pass_rhs(const SysDesc& sd, int k, const FT* __r
                 for (int d = 0; d <= PP; ++d) {
                     double w = d == 0 ? 1.0 : 2.0;
                     sg += w * (double)in.bG[d] * o[d];
-                    sm += w * (double)in.bM[d] * o[d];
+                    if (!mi_is_s) sm += w * (double)in.bM[d] * o[d];
                 }
-                acc -= sg + En * sm;
+                acc -= sg + En * (mi_is_s ? sn : sm);
             }
         }
         // row r - p is complete: -i dt H c = (2a Im, -2a Re)

@@ -283,6 +283,7 @@ tdsez_status pack_bands(BatchData* b) {
         SysDesc& d = b->desc[s];
         d = SysDesc{};
         d.N = pl.N; d.p = pl.p; d.P = pl.P; d.L = pl.L; d.m = pl.m; d.LS = pl.LS;
+        d.mi_is_s = sy->const_mass ? 1 : 0;
         d.band_off = boff;
         d.state_off = soff;
         d.fac_off = foff;
