@@ -345,6 +345,215 @@ __device__ __forceinline__ void pass_elim(const SysDesc& sd, int k, const FT* __
     }
 }
 
+// Passes H and A1 in one sweep (propagation steps that continue): each band
+// row and state row of the chunk (and of a p-row halo of the next chunk) is
+// read once to
+//  - accumulate the FP64 observables of c_n, as pass_rhs;
+//  - build the right-hand side -i dt (H0 + Ebar D) c_n inside the
+//    elimination window instead of storing it: row r receives the part from
+//    c_{r-p..r} when it enters the window and the parts from c_{r+1..r+p} in
+//    the next p steps, all before it leaves the window as pivot r; the
+//    elimination updates of earlier pivots arrive in between, which is
+//    harmless since both are additive;
+//  - eliminate as pass_elim (multipliers, 1/D_j, yhat_j; Schur block W and
+//    right-hand side yR of the separator rows).
+template <int PP, typename FT>
+__device__ __forceinline__ void pass_rhs_elim(const SysDesc& sd, int k, const FT* __restrict__ band,
+                                              const double* __restrict__ st, FT* __restrict__ fac,
+                                              FT* __restrict__ red, double alpha, double Ebar, double En,
+                                              bool want_acc, double obs_part[3]) {
+    constexpr int NM = kNumMats;
+    constexpr int IT = 2 * PP + 2;
+    const int L = sd.L, LS = sd.LS, P = sd.P;
+    const bool mi_is_s = sd.mi_is_s != 0;
+    int col = k + 1;
+    asm volatile("" : "+v"(col));
+    const int kk = col - 1;
+    const FT* __restrict__ bnd = band + sd.band_off;
+    const double* __restrict__ cst = st + 2 * sd.state_off;
+    FT* __restrict__ fc = fac + 2 * sd.fac_off;
+    const unsigned rowstride = (unsigned)(NM * (PP + 1) * LS);
+    const unsigned fstride = (unsigned)(IT * P);
+    const FT a_f = (FT)alpha;
+    const FT eb_f = (FT)Ebar;
+    const double twoa = 2.0 * alpha;
+    // -i 2a z, rounded to the factor precision
+    auto rhs_of = [&](double zr, double zi) { return cmk<FT>((FT)(twoa * zi), (FT)(-twoa * zr)); };
+
+    cplx<double> cw[PP + 1];     // c rows r-p..r (slot PP newest)
+    cplx<FT> W[PP + 1][PP + 1];  // lower triangle used: rows r-p..r in slots 0..PP
+    cplx<FT> y[PP + 1];
+#pragma unroll
+    for (int i = 0; i <= PP; ++i) {
+#pragma unroll
+        for (int i2 = 0; i2 <= PP; ++i2) W[i][i2] = cmk<FT>(0, 0);
+        y[i] = cmk<FT>(0, 0);
+    }
+    // c rows -p..-1 come from the previous chunk (column k; zero for k = 0)
+    cw[0] = cmk<double>(0, 0);
+#pragma unroll
+    for (int d = 0; d < PP; ++d) {
+        unsigned at = (unsigned)(L - PP + d) * (unsigned)LS + (unsigned)(col - 1);
+        cw[d + 1] = cmk<double>(cst[2 * at], cst[2 * at + 1]);
+    }
+    double nu = 0.0, dip = 0.0, acc = 0.0;
+
+    struct RowIn {
+        FT bS[PP + 1], bH[PP + 1], bD[PP + 1], bG[PP + 1], bM[PP + 1];
+        cplx<double> cr;
+    };
+    auto load_row = [&](int r) {
+        if (r >= L + PP) r = L + PP - 1;  // past the end: reload the last row (unused)
+        const bool own = r < L;
+        const int lr = own ? r : r - L;
+        const unsigned cc = (unsigned)(own ? col : col + 1);
+        const unsigned rb = (unsigned)lr * rowstride + cc;
+        RowIn in;
+#pragma unroll
+        for (int d = 0; d <= PP; ++d) {
+            in.bS[d] = bnd[rb + (unsigned)((0 * (PP + 1) + d) * LS)];
+            in.bH[d] = bnd[rb + (unsigned)((1 * (PP + 1) + d) * LS)];
+            in.bD[d] = bnd[rb + (unsigned)((2 * (PP + 1) + d) * LS)];
+            in.bG[d] = (FT)0;
+            in.bM[d] = (FT)0;
+        }
+        if (want_acc && own) {
+#pragma unroll
+            for (int d = 0; d <= PP; ++d) in.bG[d] = bnd[rb + (unsigned)((3 * (PP + 1) + d) * LS)];
+            if (!mi_is_s) {
+#pragma unroll
+                for (int d = 0; d <= PP; ++d) in.bM[d] = bnd[rb + (unsigned)((4 * (PP + 1) + d) * LS)];
+            }
+        }
+        const unsigned sat = (unsigned)lr * (unsigned)LS + cc;
+        in.cr = cmk<double>(cst[2 * sat], cst[2 * sat + 1]);
+        return in;
+    };
+    // own row r: observables, right-hand-side parts, insertion, elimination
+    // of pivot r - p, shift
+    auto own_row = [&](const RowIn& in, int r, bool first_rows, bool elim) {
+        const cplx<double> cr = in.cr;
+#pragma unroll
+        for (int d = 0; d < PP; ++d) cw[d] = cw[d + 1];
+        cw[PP] = cr;
+        double h[PP + 1];
+#pragma unroll
+        for (int d = 0; d <= PP; ++d) h[d] = (double)in.bH[d] + Ebar * (double)in.bD[d];
+        {
+            // row r: sum_d M[r][r-d] c_{r-d}
+            double sr = 0.0, si = 0.0;
+#pragma unroll
+            for (int d = 0; d <= PP; ++d) {
+                sr += h[d] * cw[PP - d].re;
+                si += h[d] * cw[PP - d].im;
+            }
+            y[PP] = cadd(y[PP], rhs_of(sr, si));
+        }
+        // rows r-d receive M[r-d][r] c_r = M[r][r-d] c_r
+#pragma unroll
+        for (int d = 1; d <= PP; ++d) y[PP - d] = cadd(y[PP - d], rhs_of(h[d] * cr.re, h[d] * cr.im));
+        {
+            double o[PP + 1];
+#pragma unroll
+            for (int d = 0; d <= PP; ++d) o[d] = cr.re * cw[PP - d].re + cr.im * cw[PP - d].im;
+            double sn = (double)in.bS[0] * o[0], sdp = (double)in.bD[0] * o[0];
+#pragma unroll
+            for (int d = 1; d <= PP; ++d) {
+                sn += 2.0 * (double)in.bS[d] * o[d];
+                sdp += 2.0 * (double)in.bD[d] * o[d];
+            }
+            nu += sn;
+            dip += sdp;
+            if (want_acc) {
+                double sg = 0.0, sm = 0.0;
+#pragma unroll
+                for (int d = 0; d <= PP; ++d) {
+                    double w = d == 0 ? 1.0 : 2.0;
+                    sg += w * (double)in.bG[d] * o[d];
+                    if (!mi_is_s) sm += w * (double)in.bM[d] * o[d];
+                }
+                acc -= sg + En * (mi_is_s ? sn : sm);
+            }
+        }
+        // insert row r of A_n = S + i a (H0 + Ebar D)
+#pragma unroll
+        for (int d = 0; d <= PP; ++d) {
+            const cplx<FT> a = cmk<FT>(in.bS[d], a_f * (in.bH[d] + eb_f * in.bD[d]));
+            if (!first_rows || r - d >= 0) W[PP][PP - d] = a;
+        }
+        if (elim) {
+            const int j = r - PP;
+            const cplx<FT> dinv = cinv_dev(W[0][0]);
+            cplx<FT> l[PP + 1];
+#pragma unroll
+            for (int i = 1; i <= PP; ++i) l[i] = cmul(W[i][0], dinv);
+#pragma unroll
+            for (int i = 1; i <= PP; ++i)
+#pragma unroll
+                for (int i2 = 1; i2 <= i; ++i2) W[i][i2] = cfms(W[i][i2], l[i], W[i2][0]);
+            const cplx<FT> yj = y[0];
+#pragma unroll
+            for (int i = 1; i <= PP; ++i) y[i] = cfms(y[i], l[i], yj);
+            const unsigned fb = (unsigned)j * fstride + (unsigned)kk;
+#pragma unroll
+            for (int i = 1; i <= PP; ++i) st_c(fc, fb + (unsigned)((i - 1) * P), l[i]);
+            st_c(fc, fb + (unsigned)(PP * P), dinv);
+            st_c(fc, fb + (unsigned)((PP + 1) * P), yj);
+        }
+        // shift the window by one row
+#pragma unroll
+        for (int i = 1; i <= PP; ++i) {
+#pragma unroll
+            for (int i2 = 1; i2 <= i; ++i2) W[i - 1][i2 - 1] = W[i][i2];
+            y[i - 1] = y[i];
+        }
+#pragma unroll
+        for (int i2 = 0; i2 <= PP; ++i2) W[PP][i2] = cmk<FT>(0, 0);
+        y[PP] = cmk<FT>(0, 0);
+    };
+    // rows are loaded one ahead of their use (the work per row covers the
+    // latency; a deeper prefetch does not fit the register file)
+    RowIn cur = load_row(0);
+#pragma unroll
+    for (int r = 0; r < PP; ++r) {
+        RowIn nxt = load_row(r + 1);
+        own_row(cur, r, true, false);
+        cur = nxt;
+    }
+    for (int r = PP; r < L; ++r) {
+        RowIn nxt = load_row(r + 1);
+        own_row(cur, r, false, true);
+        cur = nxt;
+    }
+    // halo rows L + t of the next chunk: their c reaches the separator rows
+    // L - p .. L - 1, which now sit in window slots 0 .. p-1
+#pragma unroll
+    for (int t = 0; t < PP; ++t) {
+        RowIn nxt = load_row(L + t + 1);
+        const cplx<double> cr = cur.cr;
+#pragma unroll
+        for (int d = t + 1; d <= PP; ++d) {
+            const double hd = (double)cur.bH[d] + Ebar * (double)cur.bD[d];
+            y[PP + t - d] = cadd(y[PP + t - d], rhs_of(hd * cr.re, hd * cr.im));
+        }
+        cur = nxt;
+    }
+    FT* rb = red + 2 * (sd.red_off + (long long)k * RedLayout<FT>::chunk_block(PP));
+    const int pp = PP * PP;
+#pragma unroll
+    for (int i = 0; i < PP; ++i) {
+#pragma unroll
+        for (int i2 = 0; i2 <= i; ++i2) {
+            st_c(rb, (unsigned)(i * PP + i2), W[i][i2]);
+            st_c(rb, (unsigned)(i2 * PP + i), W[i][i2]);
+        }
+        st_c(rb, (unsigned)(3 * pp + i), y[i]);
+    }
+    obs_part[0] = nu;
+    obs_part[1] = dip;
+    obs_part[2] = acc;
+}
+
 // Pass A2: the fill of the chunk's rows towards the left separator,
 //   F = L^-1 A_{I,left}  (row j of F is stored with pivot j as f_j),
 // the separator rows' part of it (block F of the reduced system) and the

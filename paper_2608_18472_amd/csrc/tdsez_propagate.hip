@@ -49,7 +49,8 @@ constexpr int kProfSlots = 9;
 template <int PP, typename FT>
 __device__ __forceinline__ void run_system(const KernelArgs& ka, const SysDesc& sd, int sidx) {
     // optional phase profile: shader-clock cycles summed over the steps for
-    // the passes H, A1, A2, R, B and, per refinement sweep, C, R, B
+    // the passes H, A1 (FP32: one fused sweep counted under H), A2, R, B and,
+    // per refinement sweep, C, R, B
     unsigned long long tp[kProfSlots - 1] = {0, 0, 0, 0, 0, 0, 0, 0};
     unsigned long long t0 = 0;
     const FT* band = (const FT*)ka.band;
@@ -84,9 +85,18 @@ __device__ __forceinline__ void run_system(const KernelArgs& ka, const SysDesc& 
         const double Ebar = last ? En : 0.5 * (En + Es[n + 1]);
         double part[3] = {0.0, 0.0, 0.0};
         if (prof) t0 = clock64();
-        if (active) pass_rhs<PP, FT>(sd, lane, band, st, rhs, alpha, Ebar, En, want_acc, !last, part);
+        // FP32: right-hand side, observables and elimination in one sweep
+        // (FP64 rows are twice the size and keep two passes); the last time
+        // level needs the observables only
+        constexpr bool kOneSweep = sizeof(FT) == 4;
+        if (active) {
+            if (kOneSweep && !last)
+                pass_rhs_elim<PP, FT>(sd, lane, band, st, fac, red, alpha, Ebar, En, want_acc, part);
+            else
+                pass_rhs<PP, FT>(sd, lane, band, st, rhs, alpha, Ebar, En, want_acc, !last, part);
+        }
         mark(0);
-        if (active && !last) pass_elim<PP, FT>(sd, lane, band, rhs, fac, red, alpha, Ebar);
+        if (!kOneSweep && active && !last) pass_elim<PP, FT>(sd, lane, band, rhs, fac, red, alpha, Ebar);
         mark(1);
         if (active && !last) {
             constexpr bool kFused = sizeof(FT) == 4;
