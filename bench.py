@@ -34,8 +34,8 @@ CALIB_COPY_BYTES = 512 * 2 ** 20
 # two rocprofv3 --pmc runs of this script (FETCH_SIZE, then WRITE_SIZE) scaled
 # by the copy calibration; valid only for the kernel sources they were taken
 # on (sha256 of the listed files).  See profiles/propagate_kernel_fp32_batch1024_pmc.md.
-TRAFFIC = {"sources_sha256": "6bd5709a0dfdbec73ef028d86eb9f55c1a3f37d9073ee5b746124a07696ee83e",
-           "bytes_per_launch": 2.6665e13}
+TRAFFIC = {"sources_sha256": "c71ec40efccc522bed4cceb6b48c83973969af2f2782c2770330700e0af47c3f",
+           "bytes_per_launch": 2.4427e13}
 KERNEL_SOURCES = ["paper_2608_18472_amd/csrc/tdsez_passes.hpp", "paper_2608_18472_amd/csrc/tdsez_propagate.hip",
                   "paper_2608_18472_amd/csrc/tdsez_internal.hpp"]
 
