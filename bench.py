@@ -266,6 +266,13 @@ def run_2d(args):
         ev, vec = T.ground_state(s1)
         vecs.append(vec[0])
     psi0 = torch.from_numpy(np.outer(vecs[1], vecs[0]).astype(np.complex128).reshape(-1)).cuda()
+    # calibration copy for the HBM byte counters (outside the timed region)
+    src = torch.empty(CALIB_COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+    src.fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
     n0, ns = 2000, args.steps_2d
     E = torch.from_numpy(np.ascontiguousarray(sd.E[n0: n0 + ns + 1])).cuda()
     stream = torch.cuda.current_stream()

@@ -295,7 +295,8 @@ void tdsez_system2d_destroy(tdsez_system2d s);
 /* Phase profile of the last propagation of a profiled batch (see
  * tdsez_batch_set "profile").  Synchronises `stream`; out[9*s + 0..8] =
  * average shader-clock cycles per time step spent by system s in: the
- * right-hand-side/observables pass, the elimination pass, the fill pass, the
+ * right-hand-side/observables pass, the elimination pass (TDSEZ_FP32_REFINED
+ * runs both as one sweep, counted in the first column), the fill pass, the
  * separator (reduced) solve, the back substitution, and summed over the
  * refinement sweeps their residual pass, separator solve and back
  * substitution; then the partition count.  Profiling adds a barrier per

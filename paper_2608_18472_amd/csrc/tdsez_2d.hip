@@ -133,8 +133,18 @@ __global__ void from_planar_kernel(const double* __restrict__ re, const double* 
     }
 }
 
-constexpr int kTile = 16;          // output tile edge of the stencil kernel
-constexpr int kStencilThreads = kTile * kTile;
+constexpr int kStencilThreads = 256;  // threads (and outputs) per stencil tile
+// Tile shape: a tile row spans one 128-byte line of a plane (16 FP64 or 32
+// FP32 values), so every stencil load uses whole lines.
+template <typename FT>
+struct TileShape {
+    static constexpr int TX = 128 / (int)sizeof(FT);
+    static constexpr int TY = kStencilThreads / TX;
+};
+template <typename FT>
+dim3 stencil_grid(int Nx, int Ny) {
+    return dim3((Nx + TileShape<FT>::TX - 1) / TileShape<FT>::TX, (Ny + TileShape<FT>::TY - 1) / TileShape<FT>::TY);
+}
 
 // M[i][j] of a 1D lower half band by rows, for |i - j| <= p; pairs with an
 // index outside 0..n-1 give 0 (the load index is clamped, so no branch)
@@ -148,36 +158,41 @@ __device__ inline FT band_at(const FT* __restrict__ band, int p, int n, int i, i
 }
 
 // out = w y + a S2 c + b (T2 + V2 + Ebar D2) c   (planar complex; y may be
-// null), for one 16 x 16 tile of outputs with the input tile and a p-wide
+// null), for one TX x TY tile of outputs with the input tile and a p-wide
 // halo in LDS, in three stages:
 //  (1) x pass: every row of the haloed tile is convolved with the x bands at
 //      the thread's column, s = Sx c and h = (Tx + Ebar Dx) c (and Dx c for
 //      the observables), kept in LDS;
 //  (2) y pass: S2 c = Sy s and (T2 + Ebar D2) c = Sy h + Ty s at the output,
 //      so the separable part costs O(p) per unknown instead of O(p^2);
-//  (3) the potential: the (2p+1)^2 neighbours times V2 from the half
-//      stencil, the mirrored half read at the neighbour's row (clamped into
-//      the plane where the neighbour is outside: c is zero there).
+//  (3) the potential, over the stored half of the stencil: for each stored
+//      offset e = (dy, dx), V2[i][i+e] c_{i+e} from this row's plane entry
+//      and V2[i][i-e] c_{i-e} = V2[i-e][i] c_{i-e} from the same plane at
+//      row i - e (clamped into the plane where i - e is outside: c is zero
+//      there).  The two reads of a plane are issued together, so the second
+//      finds most of its lines already on their way.
 // With obs != null every block writes partial sums of Re c^H S2 c and
-// Re c^H D2 c (FP64).
+// Re c^H D2 c (FP64).  Four tiles per CU (<= 128 VGPRs) let the 1024 tiles
+// of a 512 x 512 grid run in one round.
 template <int PP, typename FT>
-__global__ __launch_bounds__(kStencilThreads) void apply_kernel(
+__global__ __launch_bounds__(kStencilThreads, 4) void apply_kernel(
     int Nx, int Ny, const FT* __restrict__ Sxb, const FT* __restrict__ Txb, const FT* __restrict__ Dxb,
     const FT* __restrict__ Syb, const FT* __restrict__ Tyb, const FT* __restrict__ V2h, const FT* __restrict__ cre,
     const FT* __restrict__ cim, const FT* __restrict__ yre, const FT* __restrict__ yim, FT wre, FT wim, FT are,
     FT aim, FT bre, FT bim, FT Ebar, FT* __restrict__ ore, FT* __restrict__ oim, double* __restrict__ obs) {
+    constexpr int TX = TileShape<FT>::TX, TY = TileShape<FT>::TY;
     constexpr int K = 2 * PP + 1;
-    constexpr int W = kTile + 2 * PP;
-    __shared__ FT tre[W][W], tim[W][W];
-    __shared__ FT s_re[W][kTile], s_im[W][kTile], h_re[W][kTile], h_im[W][kTile];
-    __shared__ FT d_re[W][kTile], d_im[W][kTile];
+    constexpr int WX = TX + 2 * PP, WY = TY + 2 * PP;
+    __shared__ FT tre[WY][WX], tim[WY][WX];
+    __shared__ FT s_re[WY][TX], s_im[WY][TX], h_re[WY][TX], h_im[WY][TX];
+    __shared__ FT d_re[WY][TX], d_im[WY][TX];
     __shared__ double red[2][kStencilThreads];
-    const int tx = threadIdx.x % kTile, ty = threadIdx.x / kTile;
-    const int x0 = blockIdx.x * kTile, y0 = blockIdx.y * kTile;
+    const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
     const int ix = x0 + tx, iy = y0 + ty;
     const long long plane = (long long)Nx * Ny;
-    for (int t = threadIdx.x; t < W * W; t += kStencilThreads) {
-        const int ly = t / W, lx = t % W;
+    for (int t = threadIdx.x; t < WX * WY; t += kStencilThreads) {
+        const int ly = t / WX, lx = t % WX;
         const int gy = y0 + ly - PP, gx = x0 + lx - PP;
         FT vr = 0, vi = 0;
         if (gy >= 0 && gy < Ny && gx >= 0 && gx < Nx) {
@@ -198,7 +213,7 @@ __global__ __launch_bounds__(kStencilThreads) void apply_kernel(
     }
     __syncthreads();
     // (1) x pass over the tile rows (halo rows included)
-    for (int ly = ty; ly < W; ly += kTile) {
+    for (int ly = ty; ly < WY; ly += TY) {
         FT sr = 0, si = 0, hr = 0, hi = 0, dr = 0, di = 0;
 #pragma unroll
         for (int k = 0; k < K; ++k) {
@@ -217,50 +232,42 @@ __global__ __launch_bounds__(kStencilThreads) void apply_kernel(
         d_re[ly][tx] = dr;
         d_im[ly][tx] = di;
     }
-    // (3) potential, from the input tile (independent of the x pass), one
-    // row of 2p+1 offsets at a time with the next row's loads in flight.
-    // Offset (dy, dx) is stored at this row when dy > 0 or (dy = 0, dx >= 0);
-    // otherwise the mirrored offset is read at the neighbour's row, clamped
-    // into the plane where the neighbour is outside (c is zero there).
+    // (3) potential, from the input tile (independent of the x pass)
     const int ixc = ix < Nx ? ix : Nx - 1, iyc = iy < Ny ? iy : Ny - 1;
     const long long row = (long long)iyc * Nx + ixc;
-    int jxc[K];
-#pragma unroll
-    for (int kx = 0; kx < K; ++kx) {
-        const int jx = ixc + kx - PP;
-        jxc[kx] = jx < 0 ? 0 : (jx >= Nx ? Nx - 1 : jx);
-    }
-    auto vrow = [&](int ky, FT v[K]) {
-        const int dy = ky - PP;
-        int jy = iyc + dy;
-        jy = jy < 0 ? 0 : (jy >= Ny ? Ny - 1 : jy);
-        const long long nrow = (long long)jy * Nx;
-#pragma unroll
-        for (int kx = 0; kx < K; ++kx) {
-            const int dxo = kx - PP;
-            const bool direct = dy > 0 || (dy == 0 && dxo >= 0);
-            const int h = direct ? half_index(PP, dy, dxo) : half_index(PP, -dy, -dxo);
-            v[kx] = V2h[(long long)h * plane + (direct ? row : nrow + jxc[kx])];
-        }
-    };
+    const int cy = ty + PP, cx = tx + PP;  // this unknown in the tile
     FT vr = 0, vi = 0;
-    auto vacc = [&](int ky, const FT v[K]) {
+    {
+        // dy = 0: the diagonal, then e = (0, dx) and its mirror (0, -dx)
+        const FT v0 = V2h[row];
+        vr += v0 * tre[cy][cx];
+        vi += v0 * tim[cy][cx];
+#pragma unroll
+        for (int e = 1; e <= PP; ++e) {
+            const FT* __restrict__ pl = V2h + (long long)half_index(PP, 0, e) * plane;
+            const int jx = ixc - e < 0 ? 0 : ixc - e;
+            const FT vd = pl[row];
+            const FT vm = pl[(long long)iyc * Nx + jx];
+            vr += vd * tre[cy][cx + e] + vm * tre[cy][cx - e];
+            vi += vd * tim[cy][cx + e] + vm * tim[cy][cx - e];
+        }
+    }
+    // dy = 1..p: e = (dy, dx), dx = -p..p, and the mirrors -e
+#pragma unroll 1
+    for (int dy = 1; dy <= PP; ++dy) {
+        const FT* __restrict__ pl = V2h + (long long)half_index(PP, dy, -PP) * plane;
+        const long long mrow = (long long)(iyc - dy < 0 ? 0 : iyc - dy) * Nx;
 #pragma unroll
         for (int kx = 0; kx < K; ++kx) {
-            vr += v[kx] * tre[ty + ky][tx + kx];
-            vi += v[kx] * tim[ty + ky][tx + kx];
+            const int e = kx - PP;
+            int jx = ixc - e;
+            jx = jx < 0 ? 0 : (jx >= Nx ? Nx - 1 : jx);
+            const FT vd = pl[(long long)kx * plane + row];
+            const FT vm = pl[(long long)kx * plane + mrow + jx];
+            vr += vd * tre[cy + dy][cx + e] + vm * tre[cy - dy][cx - e];
+            vi += vd * tim[cy + dy][cx + e] + vm * tim[cy - dy][cx - e];
         }
-    };
-    FT va[K], vb[K];
-    vrow(0, va);
-#pragma unroll 1
-    for (int ky = 0; ky + 1 < K; ky += 2) {
-        vrow(ky + 1, vb);
-        vacc(ky, va);
-        vrow(ky + 2, va);
-        vacc(ky + 1, vb);
     }
-    vacc(K - 1, va);
     __syncthreads();
     // (2) y pass
     FT Sr = 0, Si = 0, Hr = 0, Hi = 0, Dr = 0, Di = 0;
@@ -293,7 +300,7 @@ __global__ __launch_bounds__(kStencilThreads) void apply_kernel(
         ore[orow] = accr;
         oim[orow] = acci;
         if (obs) {
-            const double c0r = tre[ty + PP][tx + PP], c0i = tim[ty + PP][tx + PP];
+            const double c0r = tre[cy][cx], c0i = tim[cy][cx];
             nu = c0r * (double)Sr + c0i * (double)Si;
             dip = c0r * (double)Dr + c0i * (double)Di;
         }
@@ -721,7 +728,8 @@ tdsez_status tdsez_assemble_2d(const double* breaks_x, int nbx, const double* br
     if (hipMalloc(&s->d_work, sizeof(double) * (size_t)plane * 2 * 9) != hipSuccess ||
         hipMalloc(&s->d_part, sizeof(double) * 2 * kRedBlocks) != hipSuccess ||
         hipMalloc(&s->d_sc, sizeof(double) * 8) != hipSuccess ||
-        hipMalloc(&s->d_obs_part, sizeof(double) * 2 * (size_t)((Nx + kTile - 1) / kTile) * ((Ny + kTile - 1) / kTile)) !=
+        hipMalloc(&s->d_obs_part, sizeof(double) * 2 * (size_t)stencil_grid<double>(Nx, Ny).x *
+                                      stencil_grid<double>(Nx, Ny).y) !=
             hipSuccess)
         return bail(fail(TDSEZ_ENOMEM, "2D workspace allocation failed"));
     *out = s;
@@ -789,7 +797,8 @@ tdsez_status tdsez_propagate_2d(tdsez_system2d s, double* psi, const double* E, 
     const int g = grid_for(n);
     to_planar_kernel<<<g, 256, 0, stream>>>(psi, n, vre(C), vim(C));
     TDSEZ_HIP_TRY(hipMemsetAsync(vre(X), 0, sizeof(double) * 2 * n, stream));
-    const dim3 sgrid((Nx + kTile - 1) / kTile, (Ny + kTile - 1) / kTile);
+    const dim3 sgrid = stencil_grid<double>(Nx, Ny);
+    const dim3 sgrid32 = stencil_grid<float>(Nx, Ny);
     const int nblk = (int)(sgrid.x * sgrid.y);
     const double alpha = 0.5 * dt;
     const double* Sx = s->ax.d_band[0];
@@ -820,7 +829,7 @@ tdsez_status tdsez_propagate_2d(tdsez_system2d s, double* psi, const double* E, 
         switch (p) {
 #define TD2_CASE(PV_)                                                                                         \
     case PV_:                                                                                                 \
-        apply_kernel<PV_, float><<<sgrid, kStencilThreads, 0, stream>>>(                                      \
+        apply_kernel<PV_, float><<<sgrid32, kStencilThreads, 0, stream>>>(                                      \
             Nx, Ny, b32, b32 + bx, b32 + 2 * bx, b32 + 3 * bx, b32 + 3 * bx + by, s->d_V2h32, fre(in), fim(in), \
             nullptr, nullptr, 0.f, 0.f, (float)ar, (float)ai, (float)br, (float)bi, (float)Eb, fre(outv),      \
             fim(outv), nullptr);                                                                              \
