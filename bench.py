@@ -35,7 +35,7 @@ CALIB_COPY_BYTES = 512 * 2 ** 20
 # by the copy calibration; valid only for the kernel sources they were taken
 # on (sha256 of the listed files).  See profiles/propagate_kernel_fp32_batch1024_pmc.md.
 TRAFFIC = {"sources_sha256": "c71ec40efccc522bed4cceb6b48c83973969af2f2782c2770330700e0af47c3f",
-           "bytes_per_launch": 2.4427e13}
+           "bytes_per_launch": 2.4367e13}
 KERNEL_SOURCES = ["paper_2608_18472_amd/csrc/tdsez_passes.hpp", "paper_2608_18472_amd/csrc/tdsez_propagate.hip",
                   "paper_2608_18472_amd/csrc/tdsez_internal.hpp"]
 
