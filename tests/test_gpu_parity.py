@@ -276,6 +276,34 @@ def test_nonfinite_state_is_latched():
     T.system_status(g)  # cleared
 
 
+def test_norm_drift_is_latched():
+    """ENORMDRIFT, forced from the host by a tolerance below the FP32-refined
+    path's norm conservation (~1e-9 relative); a loose tolerance passes and
+    the latched step is within the run."""
+    defs = W.config3(nsys=2, seed=0)
+    ns = 40
+    for s in defs:
+        s.nsteps = ns
+        s.E = s.meta["E0"] * np.sin(s.meta["omega"] * s.dt * np.arange(ns + 1))
+    b = T.batch_create([T.assemble_workload(s) for s in defs])
+    psi, po, E, eo, obs, oo = T.pack_batch_inputs(defs, [np.zeros(s.ndof) for s in defs])
+    T.ground_state_batched(b, psi, po)
+    psi0 = psi.clone()
+    say("norm drift")
+    for tol, latched in ((0.5, False), (1e-14, True)):
+        T.batch_set(b, "norm_tol", tol)
+        psi.copy_(psi0)
+        T.propagate_batched(b, psi, po, E, eo, [s.dt for s in defs], [ns] * 2, T.FP32_REFINED, T.OBS_ALL, obs, oo)
+        if latched:
+            with pytest.raises(T.TdsezError) as e:
+                T.batch_status(b)
+            assert e.value.status == 6
+            T.batch_status(b)  # cleared
+        else:
+            T.batch_status(b)
+    T.batch_set(b, "norm_tol", 0.0)
+
+
 def test_invalid_arguments():
     sd = W.config1(nsteps=5)
     g = T.assemble_workload(sd)
