@@ -295,6 +295,7 @@ def run_2d(args):
     d64 = out["fp64"]["obs"].reshape(-1, 3)[:, 1]
     d32 = out["fp32-refined"]["obs"].reshape(-1, 3)[:, 1]
     n = g.Nx * g.Ny
+    cpu = None if args.no_cpu else cpu_baseline_2d(60)
     line = {
         "metric": "complex DOF-steps/s per GPU (2D tensor-product segment)",
         "value": n * ns / out["fp32-refined"]["sec"],
@@ -319,7 +320,35 @@ def run_2d(args):
             "dipole_rel_err_fp32_vs_fp64": float(np.linalg.norm(d32 - d64) / np.linalg.norm(d64)),
         },
     }
+    if cpu is not None:
+        line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)
+
+
+def cpu_baseline_2d(nsteps):
+    """The oracle's 2D propagation (C operator, NumPy/BLAS preconditioner
+    transforms, COCG to 1e-12) on the 128 x 128 reduced grid of the same
+    workload, field on; DOF-steps/s with the BLAS thread count as cores."""
+    from oracle import oracle as O
+    from paper_2608_18472_amd import workloads as W
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([int(i.get("num_threads", 1)) for i in threadpool_info()] or [1])
+    except Exception:
+        cores = 1
+    sd = W.config4(n=128, nsteps=nsteps)
+    m2 = O.assemble_2d(sd.breaks_x, sd.breaks_y, sd.order, sd.nq, sd.V)
+    vx = np.exp(-0.5 * np.linspace(-4, 4, m2["Nx"]) ** 2)
+    vy = np.exp(-0.5 * np.linspace(-4, 4, m2["Ny"]) ** 2)
+    psi0 = np.outer(vy, vx).astype(np.complex128)
+    E = 0.05 * np.sin(0.057 * sd.dt * np.arange(nsteps + 1) + 0.3)
+    t0 = time.perf_counter()
+    O.propagate_2d(m2, psi0, E, sd.dt, nsteps, tol=1e-12)
+    wall = time.perf_counter() - t0
+    dof = m2["Nx"] * m2["Ny"] * nsteps
+    return {"value": dof / wall, "unit": "DOF-steps/s", "cores": cores, "kind": "oracle",
+            "sample": "128 x 128 reduced grid of the 2D workload, %d steps (%.3g DOF-steps), C operator with "
+                      "NumPy/BLAS preconditioner transforms, wall %.1f s" % (nsteps, dof, wall)}
 
 
 def _symband_mul(band, c):
