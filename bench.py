@@ -109,6 +109,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--tune-ms", type=float, default=3000.0,
                     help="partition autotuner budget per precision (setup, untimed); 0 keeps the default rule")
+    ap.add_argument("--split", type=int, default=0,
+                    help="run this many of the costliest systems on two waves each (setup, untimed)")
     ap.add_argument("--workload", choices=["batch1d", "2d"], default="batch1d",
                     help="batch1d: the batched 1D benchmark (default); 2d: a segment of the 512 x 512 "
                          "tensor-product workload")
@@ -142,6 +144,8 @@ def main():
     dts = [s.dt for s in defs]
     nsteps = [s.nsteps for s in defs]
     dofsteps = float(sum(s.ndof * s.nsteps for s in defs))
+    if args.split > 0:
+        T.batch_split(batch, nsteps, args.split)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t_setup
 
@@ -227,6 +231,7 @@ def main():
             "fp64_ms_per_step": results["fp64"] * 1000.0 if "fp64" in results else None,
             "dipole_rel_err_fp32_vs_fp64": eps_d,
             "refine_sweeps": 1,
+            "two_wave_systems": int(T.batch_two_wave(batch).sum()),
             "autotune": tuned if tuned else None,
             "algorithmic_bytes_per_launch": alg_bytes,
             "setup_s": t_setup,

@@ -185,6 +185,33 @@ tdsez_status tdsez_autotune(tdsez_batch b, tdsez_precision prec, double budget_m
  * of nsys ints). */
 tdsez_status tdsez_batch_chunks(tdsez_batch b, int* chunks_out);
 
+/* Two waves for the costliest systems.  A batch launch ends when its
+ * longest system ends; in the partitioned solve of section V.B's
+ * Crank-Nicolson system the per-step time of one system is bounded below by
+ * the serial chain over its P separator blocks and the lane-serial sweep of
+ * its N/P-row chunks, with P at most 64 (one chunk per lane of one wave).
+ * This call marks the `count` systems with the largest cost N (p + 1)
+ * nsteps[s] to run on a workgroup of two waves: up to 128 chunks, chunk
+ * length rule L = sqrt(0.3 N), and the separator system eliminated from both
+ * ends at once (each wave half of the chain, joined at the middle block).
+ * A marked system whose plan still has at most 64 chunks stays on one wave.
+ * Two-wave systems run in a launch of their own on the caller's stream,
+ * concurrently with the one-wave launch on an internal side stream forked
+ * from and joined back into it (both at the default priority), so the
+ * `stream` semantics of the propagation calls are unchanged and the calls
+ * stay capturable into a graph.  Results equal the one-wave results up to
+ * rounding.  count = 0 restores one wave per system.  Re-packs the batch and
+ * clears the autotuner's plans (run tdsez_autotune afterwards to tune the
+ * new plan; it keeps the marks).  The adjoint refuses a batch with two-wave
+ * systems (EUNSUPPORTED).  nsteps: host array of nsys step counts (may be
+ * NULL when count = 0).  Synchronous.  EINVAL for count outside 0..nsys or a
+ * negative step count. */
+tdsez_status tdsez_batch_split(tdsez_batch b, const int* nsteps, int count);
+
+/* 1 for every system that runs on two waves under the current plan, else 0
+ * (host array of nsys ints). */
+tdsez_status tdsez_batch_two_wave(tdsez_batch b, int* flags_out);
+
 /* Crank-Nicolson propagation of every system of the batch in one persistent
  * kernel launch (one workgroup per system), section V.B eq. cn_system with
  * H^{n+1/2} = H0 + (E_n + E_{n+1})/2 D.

@@ -277,6 +277,8 @@ tdsez_status tdsez_adjoint_batched(tdsez_batch b, const double* psi0_packed, con
     if (!b || !psi0_packed || !psi_off || !E_packed || !E_off || !dt || !nsteps || !dJdobs_packed ||
         !obs_off || !dJdE_packed)
         return fail(TDSEZ_EINVAL, "NULL argument");
+    if (b->d.nsplit > 0)
+        return fail(TDSEZ_EUNSUPPORTED, "the adjoint runs one wave per system; clear tdsez_batch_split first");
     if (prec == TDSEZ_FP32_REFINED)
         return fail(TDSEZ_EUNSUPPORTED, "the adjoint runs in FP64 only (use TDSEZ_FP64)");
     if (prec != TDSEZ_FP64) return fail(TDSEZ_EINVAL, "unknown precision %d", (int)prec);
@@ -336,12 +338,14 @@ tdsez_status tdsez_autotune(tdsez_batch b, tdsez_precision prec, double budget_m
     static const double kRule[] = {0.6, 0.3, 1.2, 0.15, 2.4};
     constexpr int kTrials = sizeof(kRule) / sizeof(kRule[0]);
     constexpr int kWarm = 4, kProbe = 16;
+    // (systems that may run on two waves: half the constant, up to 128 chunks)
     auto chunks_for = [&](int s, double c) {
         const int N = d->sys[s]->N, p = d->sys[s]->p;
-        double L = std::sqrt(c * N);
+        const bool req = s < (int)d->two_wave_req.size() && d->two_wave_req[s];
+        double L = std::sqrt((req ? 0.5 : 1.0) * c * N);
         if (L < 2.0 * p + 2) L = 2.0 * p + 2;
         int P = (int)std::lround(N / L);
-        return make_plan(N, p, P < 1 ? 1 : P).P;
+        return make_plan(N, p, P < 1 ? 1 : P, req ? kMaxChunks2 : kMaxChunks).P;
     };
     // scratch inputs: a smooth finite state, zero field (the timing does not
     // depend on the values)
@@ -482,7 +486,40 @@ tdsez_status tdsez_system_status(tdsez_system sys, void* stream, int* step_out) 
 void tdsez_batch_destroy(tdsez_batch b) {
     if (!b) return;
     free_batch_device(&b->d);
+    if (b->d.side) (void)hipStreamDestroy(b->d.side);
+    if (b->d.ev_fork) (void)hipEventDestroy(b->d.ev_fork);
+    if (b->d.ev_join) (void)hipEventDestroy(b->d.ev_join);
     delete b;
+}
+
+tdsez_status tdsez_batch_split(tdsez_batch b, const int* nsteps, int count) {
+    if (!b) return fail(TDSEZ_EINVAL, "b is NULL");
+    BatchData* d = &b->d;
+    const int nsys = (int)d->sys.size();
+    if (count < 0 || count > nsys) return fail(TDSEZ_EINVAL, "count must be in 0..%d", nsys);
+    if (count > 0 && !nsteps) return fail(TDSEZ_EINVAL, "nsteps is NULL");
+    for (int s = 0; count > 0 && s < nsys; ++s)
+        if (nsteps[s] < 0) return fail(TDSEZ_EINVAL, "nsteps[%d] < 0", s);
+    std::vector<int> idx(nsys);
+    for (int s = 0; s < nsys; ++s) idx[s] = s;
+    auto cost = [&](int s) { return (double)d->sys[s]->N * (d->sys[s]->p + 1) * (double)nsteps[s]; };
+    if (count > 0)
+        std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return cost(x) > cost(y); });
+    d->two_wave_req.assign(nsys, 0);
+    for (int r = 0; r < count; ++r) d->two_wave_req[idx[r]] = 1;
+    const bool prof = d->d_prof != nullptr;
+    d->tuned_chunks.clear();
+    free_batch_device(d);
+    tdsez_status st = pack_bands(d);
+    if (st == TDSEZ_OK && prof) return tdsez_batch_set(b, "profile", 1.0);
+    return st;
+}
+
+tdsez_status tdsez_batch_two_wave(tdsez_batch b, int* flags_out) {
+    if (!b || !flags_out) return fail(TDSEZ_EINVAL, "NULL argument");
+    for (size_t s = 0; s < b->d.sys.size(); ++s)
+        flags_out[s] = s < b->d.two_wave.size() ? (int)b->d.two_wave[s] : 0;
+    return TDSEZ_OK;
 }
 
 void tdsez_system_destroy(tdsez_system sys) {

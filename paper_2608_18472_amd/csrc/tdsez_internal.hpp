@@ -19,6 +19,8 @@ constexpr int kMaxP = 7;
 constexpr int kWave = 64;
 // Largest partition count of one system (one chunk per lane).
 constexpr int kMaxChunks = 64;
+// Largest partition count of a system run on two waves (tdsez_batch_split).
+constexpr int kMaxChunks2 = 2 * kWave;
 // Matrices stored per band row in the propagation layout: S, H0, D, G, Mi.
 constexpr int kNumMats = 5;
 
@@ -131,6 +133,11 @@ struct BatchData {
     int* d_order = nullptr;          // workgroup -> system, longest first
     std::vector<int> order_host;     // host copy of d_order (pageable; uploaded asynchronously)
     std::vector<int> tuned_chunks;   // plan cache of tdsez_autotune (0 = rule), per system
+    std::vector<char> two_wave_req;  // per system: may run on two waves (tdsez_batch_split)
+    std::vector<char> two_wave;      // per system: plan has more than 64 chunks, runs on two waves
+    int nsplit = 0;                  // systems with two_wave set (first nsplit entries of d_order)
+    hipStream_t side = nullptr;      // second stream for the two-wave launch (default priority)
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     int* d_status = nullptr;         // [0] code, [1] system, [2] step
     unsigned long long* d_prof = nullptr;  // optional phase cycle counters, 9 per system
     int nsys_alloc_desc = 0;
@@ -145,7 +152,8 @@ tdsez_status assemble_device(const double* breaks, int nbreaks, int order, int n
 int gauss_legendre_host(int nq, double* x, double* w);
 
 // Propagation (tdsez_propagate.hip)
-Plan make_plan(int N, int p, int force_chunks);
+// rule c: chunk length L = sqrt(c N); max_chunks: kMaxChunks or kMaxChunks2
+Plan make_plan(int N, int p, int force_chunks, int max_chunks = kMaxChunks, double rule = 0.6);
 tdsez_status pack_bands(BatchData* b);
 // probe: launch the autotuner's separately named copy of the kernel
 tdsez_status launch_propagate(BatchData* b, double* psi, const double* E, double* obs,

@@ -912,6 +912,213 @@ __device__ __forceinline__ void pass_reduced(const SysDesc& sd, int lane, FT* __
     }
 }
 
+// Pass R over two waves (systems with more than 64 chunks): the separator
+// system is eliminated from both ends at once.  Wave 0 runs the recurrence
+// of pass_reduced over blocks 0..h-1 (h = P/2); wave 1 runs it backwards
+// over blocks P-1..h, where the coupling of block s to the block eliminated
+// before it is F_{s+1}^T (the system is symmetric, so the step is the same
+// with the coupling transposed):
+//   G_{P-1} = Sigma_{P-1},  N_s = F_{s+1}^T G_{s+1}^-1,
+//   G_s = Sigma_s - N_s F_{s+1},  w_s = g_s - N_s w_{s+1}.
+// Wave 1 then joins the halves at block h:
+//   M_h = F_h Delta_{h-1}^-1,  Delta'_h = G_h - M_h F_h^T,
+//   z'_h = w_h - M_h z_{h-1},  x_h = Delta'_h^-1 z'_h,
+// and the waves back-substitute outwards:
+//   x_s = Delta_s^-1 (z_s - F_{s+1}^T x_{s+1}),  s = h-1 .. 0     (wave 0)
+//   x_s = G_s^-1 (w_s - F_s x_{s-1}),            s = h+1 .. P-1   (wave 1).
+// Storage: Delta_s^-1 and G_s^-1 in the Dinv slots (Delta'_h^-1 at h), M_s
+// and N_s in the M slots (M_h in the otherwise unused slot P-1), z_s and w_s
+// in z (z'_h at h).  Both waves reach the same two barriers.
+template <int PP, typename FT>
+__device__ __forceinline__ void pass_reduced2(const SysDesc& sd, int tid, FT* __restrict__ red, bool factor) {
+    constexpr int p = PP;
+    const int P = sd.P, h = P / 2;
+    const int wv = tid >> 6, lane = tid & 63;
+    const long long cb = RedLayout<FT>::chunk_block(p);
+    FT* rbase = red + 2 * sd.red_off;
+    FT* dinv_base = rbase + 2 * RedLayout<FT>::dinv(p, P);
+    FT* m_base = rbase + 2 * RedLayout<FT>::mblk(p, P);
+    FT* z_base = rbase + 2 * RedLayout<FT>::zvec(p, P);
+    FT* x_base = rbase + 2 * RedLayout<FT>::xvec(p, P);
+    const int i = lane >> 3, j = lane & 7;
+    const bool valid = (i < p) && (j < p);
+    constexpr unsigned pp = (unsigned)(p * p);
+    const unsigned eij = (unsigned)(i * p + j);
+    const cplx<FT> zero = cmk<FT>(0, 0);
+    const cplx<FT> ident = cmk<FT>(i == j ? (FT)1 : (FT)0, 0);
+    auto blk = [&](int s) { return rbase + 2 * ((long long)s * cb); };
+    const unsigned ii = (unsigned)(i < p ? i : 0);
+    const unsigned ee = valid ? eij : 0u;
+    const unsigned et = valid ? (unsigned)(j * p + i) : 0u;
+
+    // C D (lane (i, j) holds C[i][j] and D[i][j])
+    auto prod_cd = [&](cplx<FT> cv, cplx<FT> dv) {
+        cplx<FT> cr[p], dc[p];
+#pragma unroll
+        for (int l = 0; l < p; ++l) {
+            cr[l] = shfl_c(cv, 8 * i + l);
+            dc[l] = shfl_c(dv, 8 * l + j);
+        }
+        cplx<FT> mm = zero;
+#pragma unroll
+        for (int l = 0; l < p; ++l) mm = cfma(mm, cr[l], dc[l]);
+        return mm;
+    };
+    // A - M C^T
+    auto sub_mct = [&](cplx<FT> a, cplx<FT> mm, cplx<FT> cv) {
+        cplx<FT> mr[p], fc[p];
+#pragma unroll
+        for (int l = 0; l < p; ++l) {
+            mr[l] = shfl_c(mm, 8 * i + l);
+            fc[l] = shfl_c(cv, 8 * j + l);
+        }
+#pragma unroll
+        for (int l = 0; l < p; ++l) a = cfms(a, mr[l], fc[l]);
+        return a;
+    };
+    // Gauss-Jordan inverse of the (identity padded) block, no pivoting
+    auto gj_inverse = [&](cplx<FT> a) {
+#pragma unroll
+        for (int q = 0; q < p; ++q) {
+            const cplx<FT> aiq = shfl_c(a, 8 * i + q);
+            const cplx<FT> aqj = shfl_c(a, 8 * q + j);
+            const cplx<FT> piv = cinv_dev(bcast_c(a, 9 * q));
+            const cplx<FT> t = cmul(aiq, piv);
+            const cplx<FT> rowq = csel(j == q, piv, cmul(aqj, piv));
+            const cplx<FT> other = csel(j == q, cmk<FT>(-t.re, -t.im), cfms(a, t, aqj));
+            a = csel(i == q, rowq, other);
+        }
+        return a;
+    };
+    // elimination chain over blocks s = s0 + dir t, t = 0..count-1; the
+    // coupling of block s to the block before it in the chain is F_s
+    // (dir > 0) or F_{s+1}^T (dir < 0); with keep_last_raw the last block is
+    // stored uninverted (for the join)
+    auto chain = [&](int s0, int count, int dir, bool keep_last_raw) {
+        struct In {
+            cplx<FT> y, gt, w, tl, f;
+        };
+        auto load = [&](int t) {
+            const int tt = t < count ? t : count - 1;
+            const int sc = s0 + dir * tt;
+            const int s1 = sc + 1 < P ? sc + 1 : P - 1;
+            const FT* bs = blk(sc);
+            const FT* b1 = blk(s1);
+            In r;
+            r.y = ld_c(bs, 3 * pp + ii);
+            r.gt = ld_c(b1, 3 * pp + (unsigned)p + ii);
+            if (factor) {
+                r.w = ld_c(bs, ee);
+                r.tl = ld_c(b1, 2 * pp + ee);
+                r.f = dir > 0 ? ld_c(bs, pp + ee) : ld_c(b1, pp + et);
+            } else {
+                r.w = r.tl = zero;
+                r.f = ld_c(m_base, (unsigned)sc * pp + ee);  // stored M_s or N_s
+            }
+            return r;
+        };
+        cplx<FT> dprev = zero;  // inverse of the previous block of the chain
+        cplx<FT> zc = zero;     // previous z (or w) in column layout
+        In cur = load(0);
+        for (int t = 0; t < count; ++t) {
+            In nxt = load(t + 1);
+            const int s = s0 + dir * t;
+            const bool more = s + 1 < P;
+            const cplx<FT> g = csel(i < p, cadd(cur.y, csel(more, cur.gt, zero)), zero);
+            const cplx<FT> fv = csel(valid, cur.f, zero);
+            cplx<FT> mm = zero;
+            if (factor) {
+                cplx<FT> a = csel(valid, cadd(cur.w, csel(more, cur.tl, zero)), ident);
+                if (t >= 1) {
+                    mm = prod_cd(fv, dprev);
+                    a = sub_mct(a, mm, fv);
+                    if (valid) st_c(m_base, (unsigned)s * pp + eij, mm);
+                }
+                if (!(keep_last_raw && t == count - 1)) a = gj_inverse(a);
+                if (valid) st_c(dinv_base, (unsigned)s * pp + eij, a);
+                dprev = a;
+            } else {
+                mm = csel(t >= 1, fv, zero);
+            }
+            const cplx<FT> zr = csub(g, row_sum(cmul(mm, zc)));
+            if (j == 0 && i < p) st_c(z_base, (unsigned)(s * p + i), zr);
+            zc = shfl_c(zr, 8 * j);
+            cur = nxt;
+        }
+    };
+    // x_s = D_s^-1 (z_s - C x_prev) for s = s0 + dir t, where x_prev is the
+    // solution of the block before s (xc, column layout) and C = F_{s+1}^T
+    // (dir < 0) or F_s (dir > 0)
+    auto backsub = [&](int s0, int count, int dir, cplx<FT> xc) {
+        struct In {
+            cplx<FT> dv, cf, zs;
+        };
+        auto load = [&](int t) {
+            const int tt = t < count ? t : count - 1;
+            const int sc = s0 + dir * tt;
+            const int s1 = sc + 1 < P ? sc + 1 : P - 1;
+            In r;
+            r.dv = ld_c(dinv_base, (unsigned)sc * pp + ee);
+            r.cf = dir < 0 ? ld_c(blk(s1), pp + et) : ld_c(blk(sc), pp + ee);
+            r.zs = ld_c(z_base, (unsigned)(sc * p) + ii);
+            return r;
+        };
+        In bc = load(0);
+        for (int t = 0; t < count; ++t) {
+            In bn = load(t + 1);
+            const int s = s0 + dir * t;
+            const bool has_prev = dir < 0 ? (s + 1 < P) : (s >= 1);
+            const cplx<FT> dv = csel(valid, bc.dv, ident);
+            const cplx<FT> cf = csel(valid && has_prev, bc.cf, zero);
+            const cplx<FT> zs = csel(i < p, bc.zs, zero);
+            const cplx<FT> wr = csub(zs, row_sum(cmul(cf, xc)));
+            const cplx<FT> wc = shfl_c(wr, 8 * j);
+            const cplx<FT> xr = row_sum(cmul(dv, wc));
+            if (j == 0 && i < p) st_c(x_base, (unsigned)(s * p + i), xr);
+            xc = shfl_c(xr, 8 * j);
+            bc = bn;
+        }
+    };
+
+    if (wv == 0) chain(0, h, 1, false);
+    else chain(P - 1, P - h, -1, true);
+    __syncthreads();  // both halves eliminated
+    if (wv == 1) {
+        // join at block h
+        const cplx<FT> dv = csel(valid, ld_c(dinv_base, (unsigned)(h - 1) * pp + ee), ident);
+        const cplx<FT> fh = csel(valid, ld_c(blk(h), pp + ee), zero);
+        const cplx<FT> zprev = csel(i < p, ld_c(z_base, (unsigned)((h - 1) * p) + ii), zero);
+        const cplx<FT> wh = csel(i < p, ld_c(z_base, (unsigned)(h * p) + ii), zero);
+        const cplx<FT> zpc = shfl_c(zprev, 8 * j);
+        cplx<FT> mh, dinvh;
+        if (factor) {
+            mh = prod_cd(fh, dv);
+            cplx<FT> a = csel(valid, ld_c(dinv_base, (unsigned)h * pp + ee), ident);  // G_h
+            a = sub_mct(a, mh, fh);
+            dinvh = gj_inverse(a);
+            if (valid) {
+                st_c(m_base, (unsigned)(P - 1) * pp + eij, mh);
+                st_c(dinv_base, (unsigned)h * pp + eij, dinvh);
+            }
+        } else {
+            mh = csel(valid, ld_c(m_base, (unsigned)(P - 1) * pp + ee), zero);
+            dinvh = csel(valid, ld_c(dinv_base, (unsigned)h * pp + ee), ident);
+        }
+        const cplx<FT> zr = csub(wh, row_sum(cmul(mh, zpc)));
+        const cplx<FT> zcol = shfl_c(zr, 8 * j);
+        const cplx<FT> xr = row_sum(cmul(dinvh, zcol));
+        if (j == 0 && i < p) {
+            st_c(z_base, (unsigned)(h * p + i), zr);
+            st_c(x_base, (unsigned)(h * p + i), xr);
+        }
+    }
+    __syncthreads();  // x_h written
+    const cplx<FT> xh = csel(i < p, ld_c(x_base, (unsigned)(h * p) + ii), zero);
+    const cplx<FT> xhc = shfl_c(xh, 8 * j);
+    if (wv == 0) backsub(h - 1, h, -1, xhc);
+    else if (P - h - 1 > 0) backsub(h + 1, P - h - 1, 1, xhc);
+}
+
 // Pass B: interior values of the chunk from its separator values.
 //   x_I = L^-T D^-1 (yhat - F x_left - L^-1 A_{I,right} x_right)
 // The fill rows make the left-separator term a dot product per row; the
@@ -1239,6 +1446,7 @@ __device__ inline void latch(int* status, int code, int sys, int step) {
 struct KernelArgs {
     const SysDesc* descs;
     const int* order;          // workgroup -> system index (longest first)
+    int order_off;             // first entry of order read by this launch
     const void* band;          // FT bands (factorisation, solve, right-hand side)
     const double* band64;      // FP64 bands (S of the refinement residual)
     double* st;

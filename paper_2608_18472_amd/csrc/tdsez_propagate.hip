@@ -46,7 +46,11 @@ namespace {
 // number of per-system counters of the optional phase profile
 constexpr int kProfSlots = 9;
 
-template <int PP, typename FT>
+// NW = 1: one wave owns the system (P <= 64).  NW = 2: two waves (P in
+// 65..128); thread t owns chunk t in the lane-serial passes, the separator
+// system is solved from both ends (pass_reduced2) and the observable sums
+// are combined across the waves through LDS.
+template <int PP, typename FT, int NW>
 __device__ __forceinline__ void run_system(const KernelArgs& ka, const SysDesc& sd, int sidx) {
     // optional phase profile: shader-clock cycles summed over the steps for
     // the passes H, A1 (FP32: one fused sweep counted under H), A2, R, B and,
@@ -58,7 +62,7 @@ __device__ __forceinline__ void run_system(const KernelArgs& ka, const SysDesc& 
     FT* red = (FT*)ka.red;
     FT* rhs = (FT*)ka.rhs;
     double* st = ka.st;
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x;  // chunk index
     const bool active = lane < sd.P;
     const double alpha = 0.5 * sd.dt;
     const double* Es = ka.E + sd.E_off;
@@ -106,6 +110,21 @@ __device__ __forceinline__ void run_system(const KernelArgs& ka, const SysDesc& 
         double nu = wave_sum(part[0]);
         double dip = wave_sum(part[1]);
         double acc = wave_sum(part[2]);
+        if constexpr (NW == 2) {
+            // both waves add the two partial sums in the same order, so they
+            // take the same decisions below; the slots are rewritten one step
+            // later, after further barriers
+            __shared__ double wsum[2][3];
+            if ((lane & (kWave - 1)) == 0) {
+                wsum[lane / kWave][0] = nu;
+                wsum[lane / kWave][1] = dip;
+                wsum[lane / kWave][2] = acc;
+            }
+            __syncthreads();
+            nu = wsum[0][0] + wsum[1][0];
+            dip = wsum[0][1] + wsum[1][1];
+            acc = wsum[0][2] + wsum[1][2];
+        }
         if (lane == 0 && os) {
             os[3 * n + 0] = (mask & TDSEZ_OBS_NORM) ? nu : 0.0;
             os[3 * n + 1] = (mask & TDSEZ_OBS_DIPOLE) ? dip : 0.0;
@@ -123,7 +142,8 @@ __device__ __forceinline__ void run_system(const KernelArgs& ka, const SysDesc& 
         if (last) break;
         __syncthreads();
         mark(2);
-        pass_reduced<PP, FT>(sd, lane, red, true);
+        if constexpr (NW == 2) pass_reduced2<PP, FT>(sd, lane, red, true);
+        else pass_reduced<PP, FT>(sd, lane, red, true);
         __syncthreads();
         mark(3);
         if (active) pass_backsub<PP, FT>(sd, lane, band, st, dtot, true, fac, red, alpha, Ebar);
@@ -136,7 +156,8 @@ __device__ __forceinline__ void run_system(const KernelArgs& ka, const SysDesc& 
                 pass_residual<PP, FT>(sd, lane, band, ka.band64, st, dtot, fac, red, alpha, Ebar);
             __syncthreads();
             mark(5);
-            pass_reduced<PP, FT>(sd, lane, red, false);
+            if constexpr (NW == 2) pass_reduced2<PP, FT>(sd, lane, red, false);
+            else pass_reduced<PP, FT>(sd, lane, red, false);
             __syncthreads();
             mark(6);
             if (active)
@@ -153,32 +174,43 @@ __device__ __forceinline__ void run_system(const KernelArgs& ka, const SysDesc& 
     }
 }
 
-template <typename FT>
+template <typename FT, int NW>
 __device__ __forceinline__ void dispatch_system(const KernelArgs& ka) {
-    const int sidx = ka.order[blockIdx.x];
+    const int sidx = ka.order[ka.order_off + blockIdx.x];
     const SysDesc sd = ka.descs[sidx];
     switch (sd.p) {
-        case 1: run_system<1, FT>(ka, sd, sidx); break;
-        case 2: run_system<2, FT>(ka, sd, sidx); break;
-        case 3: run_system<3, FT>(ka, sd, sidx); break;
-        case 4: run_system<4, FT>(ka, sd, sidx); break;
-        case 5: run_system<5, FT>(ka, sd, sidx); break;
-        case 6: run_system<6, FT>(ka, sd, sidx); break;
-        case 7: run_system<7, FT>(ka, sd, sidx); break;
+        case 1: run_system<1, FT, NW>(ka, sd, sidx); break;
+        case 2: run_system<2, FT, NW>(ka, sd, sidx); break;
+        case 3: run_system<3, FT, NW>(ka, sd, sidx); break;
+        case 4: run_system<4, FT, NW>(ka, sd, sidx); break;
+        case 5: run_system<5, FT, NW>(ka, sd, sidx); break;
+        case 6: run_system<6, FT, NW>(ka, sd, sidx); break;
+        case 7: run_system<7, FT, NW>(ka, sd, sidx); break;
         default: break;
     }
 }
 
 template <typename FT>
 __global__ __launch_bounds__(kWave) void propagate_kernel(KernelArgs ka) {
-    dispatch_system<FT>(ka);
+    dispatch_system<FT, 1>(ka);
 }
 
-// The same computation under its own name: the short probe launches of the
-// partition autotuner, kept apart from production launches in kernel traces.
+// Systems partitioned into more than 64 chunks: two waves per system.
+template <typename FT>
+__global__ __launch_bounds__(2 * kWave) void propagate2_kernel(KernelArgs ka) {
+    dispatch_system<FT, 2>(ka);
+}
+
+// The same computations under their own names: the short probe launches of
+// the partition autotuner, kept apart from production launches in kernel
+// traces.
 template <typename FT>
 __global__ __launch_bounds__(kWave) void tune_probe_kernel(KernelArgs ka) {
-    dispatch_system<FT>(ka);
+    dispatch_system<FT, 1>(ka);
+}
+template <typename FT>
+__global__ __launch_bounds__(2 * kWave) void tune_probe2_kernel(KernelArgs ka) {
+    dispatch_system<FT, 2>(ka);
 }
 
 // psi (natural order, complex128) <-> interleaved padded state
@@ -248,7 +280,7 @@ __global__ void pack_band_kernel(const double* __restrict__ S, const double* __r
 
 }  // namespace
 
-Plan make_plan(int N, int p, int force_chunks) {
+Plan make_plan(int N, int p, int force_chunks, int max_chunks, double rule) {
     Plan pl;
     pl.N = N;
     pl.p = p;
@@ -257,13 +289,14 @@ Plan make_plan(int N, int p, int force_chunks) {
         P = force_chunks;
     } else {
         // balance the lane-serial sweep (~L rows) against the serial block
-        // chain of the reduced system (~P blocks)
-        double Lopt = std::sqrt(0.6 * N);
+        // chain of the reduced system (~P blocks; P/2 on two waves, hence
+        // half the rule constant there)
+        double Lopt = std::sqrt(rule * N);
         if (Lopt < 2.0 * p + 2) Lopt = 2.0 * p + 2;
         P = (int)std::lround(N / Lopt);
     }
     if (P < 1) P = 1;
-    if (P > kMaxChunks) P = kMaxChunks;
+    if (P > max_chunks) P = max_chunks;
     for (;;) {
         int L = (N + P - 1) / P;
         if (L < 2 * p) L = 2 * p;
@@ -285,11 +318,19 @@ tdsez_status pack_bands(BatchData* b) {
     b->desc.resize(nsys);
     long long boff = 0, soff = 0, foff = 0, roff = 0;
     b->maxp = 0;
+    b->two_wave.assign(nsys, 0);
+    b->nsplit = 0;
     for (int s = 0; s < nsys; ++s) {
         SystemData* sy = b->sys[s];
         const int tuned = s < (int)b->tuned_chunks.size() ? b->tuned_chunks[s] : 0;
-        Plan pl = make_plan(sy->N, sy->p, b->force_chunks > 0 ? b->force_chunks : tuned);
+        const bool req = s < (int)b->two_wave_req.size() && b->two_wave_req[s];
+        Plan pl = make_plan(sy->N, sy->p, b->force_chunks > 0 ? b->force_chunks : tuned,
+                            req ? kMaxChunks2 : kMaxChunks, req ? 0.3 : 0.6);
         b->plan[s] = pl;
+        if (pl.P > kMaxChunks) {
+            b->two_wave[s] = 1;
+            ++b->nsplit;
+        }
         SysDesc& d = b->desc[s];
         d = SysDesc{};
         d.N = pl.N; d.p = pl.p; d.P = pl.P; d.L = pl.L; d.m = pl.m; d.LS = pl.LS;
@@ -322,6 +363,12 @@ tdsez_status pack_bands(BatchData* b) {
     TDSEZ_HIP_TRY(hipMalloc(&b->d_status, sizeof(int) * 4));
     TDSEZ_HIP_TRY(hipMemset(b->d_status, 0, sizeof(int) * 4));
     b->nsys_alloc_desc = nsys;
+    b->desc_on_device.clear();
+    if (b->nsplit > 0 && !b->side) {
+        TDSEZ_HIP_TRY(hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking));
+        TDSEZ_HIP_TRY(hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming));
+        TDSEZ_HIP_TRY(hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming));
+    }
     for (int s = 0; s < nsys; ++s) {
         SystemData* sy = b->sys[s];
         const Plan& pl = b->plan[s];
@@ -346,14 +393,19 @@ tdsez_status upload_descriptors(BatchData* b, hipStream_t stream) {
     // Workgroups are dispatched in index order, so when the batch holds more
     // systems than the device has wave slots the costliest ones (cost
     // N (p + 1) nsteps) start first and the short ones fill in behind them.
+    // Two-wave systems come first (their own launch reads entries
+    // 0..nsplit-1), each group longest first.
     b->order_host.resize(n);
     for (size_t s = 0; s < n; ++s) b->order_host[s] = (int)s;
     auto cost = [&](int s) {
         const SysDesc& d = b->desc[s];
         return (double)d.N * (d.p + 1) * (double)d.nsteps;
     };
-    std::stable_sort(b->order_host.begin(), b->order_host.end(),
-                     [&](int x, int y) { return cost(x) > cost(y); });
+    auto two = [&](int s) { return s < (int)b->two_wave.size() && b->two_wave[s]; };
+    std::stable_sort(b->order_host.begin(), b->order_host.end(), [&](int x, int y) {
+        if (two(x) != two(y)) return two(x);
+        return cost(x) > cost(y);
+    });
     TDSEZ_HIP_TRY(hipMemcpyAsync(b->d_desc, b->desc.data(), sizeof(SysDesc) * n, hipMemcpyHostToDevice, stream));
     TDSEZ_HIP_TRY(hipMemcpyAsync(b->d_order, b->order_host.data(), sizeof(int) * n, hipMemcpyHostToDevice,
                                  stream));
@@ -378,6 +430,7 @@ tdsez_status launch_propagate(BatchData* b, double* psi, const double* E, double
     KernelArgs ka;
     ka.descs = b->d_desc;
     ka.order = b->d_order;
+    ka.order_off = 0;
     ka.band64 = b->d_band64;
     ka.st = b->d_state;
     ka.dtot = b->d_dtot;
@@ -390,18 +443,43 @@ tdsez_status launch_propagate(BatchData* b, double* psi, const double* E, double
     ka.norm_tol = b->norm_tol;
     ka.status = b->d_status;
     ka.prof = b->d_prof;
-    if (prec == TDSEZ_FP64) {
-        ka.band = b->d_band64;
-        ka.refine = 0;
-        if (probe) tune_probe_kernel<double><<<nsys, kWave, 0, stream>>>(ka);
-        else propagate_kernel<double><<<nsys, kWave, 0, stream>>>(ka);
-    } else {
-        ka.band = b->d_band32;
-        ka.refine = b->refine;
-        if (probe) tune_probe_kernel<float><<<nsys, kWave, 0, stream>>>(ka);
-        else propagate_kernel<float><<<nsys, kWave, 0, stream>>>(ka);
+    const bool fp64 = prec == TDSEZ_FP64;
+    ka.band = fp64 ? (const void*)b->d_band64 : (const void*)b->d_band32;
+    ka.refine = fp64 ? 0 : b->refine;
+    // Two-wave systems (the costliest of the batch) are launched first, on
+    // the caller's stream; the one-wave systems run concurrently on a side
+    // stream forked from and joined back into the caller's stream (both
+    // streams at the default priority).
+    const int n2 = b->nsplit, n1 = nsys - b->nsplit;
+    hipStream_t s1 = stream;
+    if (n2 > 0) {
+        TDSEZ_HIP_TRY(hipEventRecord(b->ev_fork, stream));
+        TDSEZ_HIP_TRY(hipStreamWaitEvent(b->side, b->ev_fork, 0));
+        s1 = b->side;
+        if (fp64) {
+            if (probe) tune_probe2_kernel<double><<<n2, 2 * kWave, 0, stream>>>(ka);
+            else propagate2_kernel<double><<<n2, 2 * kWave, 0, stream>>>(ka);
+        } else {
+            if (probe) tune_probe2_kernel<float><<<n2, 2 * kWave, 0, stream>>>(ka);
+            else propagate2_kernel<float><<<n2, 2 * kWave, 0, stream>>>(ka);
+        }
+        TDSEZ_HIP_TRY(hipGetLastError());
     }
-    TDSEZ_HIP_TRY(hipGetLastError());
+    if (n1 > 0) {
+        ka.order_off = n2;
+        if (fp64) {
+            if (probe) tune_probe_kernel<double><<<n1, kWave, 0, s1>>>(ka);
+            else propagate_kernel<double><<<n1, kWave, 0, s1>>>(ka);
+        } else {
+            if (probe) tune_probe_kernel<float><<<n1, kWave, 0, s1>>>(ka);
+            else propagate_kernel<float><<<n1, kWave, 0, s1>>>(ka);
+        }
+        TDSEZ_HIP_TRY(hipGetLastError());
+    }
+    if (n2 > 0) {
+        TDSEZ_HIP_TRY(hipEventRecord(b->ev_join, b->side));
+        TDSEZ_HIP_TRY(hipStreamWaitEvent(stream, b->ev_join, 0));
+    }
     {
         dim3 grid((unsigned)std::min<long long>((maxN + 255) / 256, 1024), nsys);
         unpack_state_kernel<<<grid, 256, 0, stream>>>(b->d_desc, b->d_state, psi);

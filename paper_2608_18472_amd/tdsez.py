@@ -66,6 +66,8 @@ def lib():
         "tdsez_batch_profile": [vp, vp, dp],
         "tdsez_autotune": [vp, i, d],
         "tdsez_batch_chunks": [vp, ip],
+        "tdsez_batch_split": [vp, ip, ctypes.c_int],
+        "tdsez_batch_two_wave": [vp, ip],
         "tdsez_system_status": [vp, vp, ip],
     }
     for name, args in sigs.items():
@@ -361,6 +363,25 @@ def batch_chunks(batch):
     """Partition count P of every system under the batch's current plan."""
     out = np.zeros(len(batch.systems), dtype=np.int32)
     _check(lib().tdsez_batch_chunks(batch.handle, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int))))
+    return out
+
+
+def batch_split(batch, nsteps, count):
+    """Run the `count` systems with the largest N (p + 1) nsteps on two waves
+    (nsteps may be None with count = 0)."""
+    if nsteps is None:
+        _check(lib().tdsez_batch_split(batch.handle, None, int(count)))
+        return
+    ns = np.ascontiguousarray(nsteps, dtype=np.int32)
+    if ns.shape != (len(batch.systems),):
+        raise ValueError("nsteps must hold one count per system")
+    _check(lib().tdsez_batch_split(batch.handle, ns.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), int(count)))
+
+
+def batch_two_wave(batch):
+    """1 for every system running on two waves under the current plan."""
+    out = np.zeros(len(batch.systems), dtype=np.int32)
+    _check(lib().tdsez_batch_two_wave(batch.handle, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int))))
     return out
 
 
