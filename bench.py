@@ -30,12 +30,13 @@ HBM_PEAK_GBS = 8000.0
 # device copy launched before the timed region: the calibration kernel of the
 # HBM byte counters (FETCH_SIZE / WRITE_SIZE read this many bytes each way)
 CALIB_COPY_BYTES = 512 * 2 ** 20
-# HBM bytes per launch of the FP32 propagation kernel on this workload, from
-# two rocprofv3 --pmc runs of this script (FETCH_SIZE, then WRITE_SIZE) scaled
-# by the copy calibration; valid only for the kernel sources they were taken
-# on (sha256 of the listed files).  See profiles/propagate_kernel_fp32_batch1024_pmc.md.
-TRAFFIC = {"sources_sha256": "c71ec40efccc522bed4cceb6b48c83973969af2f2782c2770330700e0af47c3f",
-           "bytes_per_launch": 2.4367e13}
+# HBM bytes of one FP32 batch call on this workload (the two-wave and the
+# one-wave launch together), from two rocprofv3 --pmc runs of this script
+# (FETCH_SIZE, then WRITE_SIZE) scaled by the copy calibration; valid only for
+# the kernel sources they were taken on (sha256 of the listed files) and the
+# default --split.  See profiles/propagate_kernel_fp32_batch1024_pmc.md.
+TRAFFIC = {"sources_sha256": "92a6d0b5c01860342bcf9c52041756b270c047781a64ceac8c83dca17136796a",
+           "bytes_per_launch": 2.4276e13, "split": 160}
 KERNEL_SOURCES = ["paper_2608_18472_amd/csrc/tdsez_passes.hpp", "paper_2608_18472_amd/csrc/tdsez_propagate.hip",
                   "paper_2608_18472_amd/csrc/tdsez_internal.hpp"]
 
@@ -109,8 +110,9 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--tune-ms", type=float, default=3000.0,
                     help="partition autotuner budget per precision (setup, untimed); 0 keeps the default rule")
-    ap.add_argument("--split", type=int, default=0,
-                    help="run this many of the costliest systems on two waves each (setup, untimed)")
+    ap.add_argument("--split", type=int, default=160,
+                    help="run this many of the costliest systems on two waves each (setup, untimed; "
+                         "160 of 1024 measured best, 0 = one wave per system)")
     ap.add_argument("--workload", choices=["batch1d", "2d"], default="batch1d",
                     help="batch1d: the batched 1D benchmark (default); 2d: a segment of the 512 x 512 "
                          "tensor-product workload")
@@ -205,7 +207,8 @@ def main():
     alg_bytes = sum(s.ndof * s.nsteps * algorithmic_bytes(s.order, 4, 8) for s in defs)
     achieved = alg_bytes / results["fp32-refined"] / 1e9
     traffic = None
-    if TRAFFIC["bytes_per_launch"] is not None and TRAFFIC["sources_sha256"] == kernel_sources_sha():
+    if (TRAFFIC["bytes_per_launch"] is not None and TRAFFIC["sources_sha256"] == kernel_sources_sha()
+            and TRAFFIC["split"] == args.split):
         traffic = TRAFFIC["bytes_per_launch"]
     line = {
         "metric": METRIC,

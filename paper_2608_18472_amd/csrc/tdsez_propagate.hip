@@ -1,7 +1,8 @@
 // Crank-Nicolson propagation kernels (the paper's section V.B, eq. cn_system).
 //
-// One workgroup (one wave64) per system; every system of a batch runs all
-// its time steps inside one persistent launch.  Per step n, with
+// One workgroup per system (one wave64, or two for systems partitioned into
+// more than 64 chunks); every system of a batch runs all its time steps
+// inside one persistent launch (one launch per workgroup size).  Per step n, with
 // H_n = H0 + Ebar_n D, Ebar_n = (E_n + E_{n+1})/2, A_n = S + i(dt/2) H_n:
 //
 //   A_n (c_{n+1} - c_n) = -i dt H_n c_n                               (1)
