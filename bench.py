@@ -35,8 +35,8 @@ CALIB_COPY_BYTES = 512 * 2 ** 20
 # (FETCH_SIZE, then WRITE_SIZE) scaled by the copy calibration; valid only for
 # the kernel sources they were taken on (sha256 of the listed files) and the
 # default --split.  See profiles/propagate_kernel_fp32_batch1024_pmc.md.
-TRAFFIC = {"sources_sha256": "92a6d0b5c01860342bcf9c52041756b270c047781a64ceac8c83dca17136796a",
-           "bytes_per_launch": 2.4276e13, "split": 160}
+TRAFFIC = {"sources_sha256": "150861fd385f210fbb052deea3e6a564287aa2b079f25b08ec53c058df5cce6b",
+           "bytes_per_launch": 2.4227e13, "split": 160}
 KERNEL_SOURCES = ["paper_2608_18472_amd/csrc/tdsez_passes.hpp", "paper_2608_18472_amd/csrc/tdsez_propagate.hip",
                   "paper_2608_18472_amd/csrc/tdsez_internal.hpp"]
 

@@ -194,7 +194,8 @@ tdsez_status tdsez_batch_chunks(tdsez_batch b, int* chunks_out);
  * nsteps[s] to run on a workgroup of two waves: up to 128 chunks, chunk
  * length rule L = sqrt(0.3 N), and the separator system eliminated from both
  * ends at once (each wave half of the chain, joined at the middle block).
- * A marked system whose plan still has at most 64 chunks stays on one wave.
+ * A marked system whose two-wave plan has at most 64 chunks stays on one
+ * wave with its one-wave plan.
  * Two-wave systems run in a launch of their own on the caller's stream,
  * concurrently with the one-wave launch on an internal side stream forked
  * from and joined back into it (both at the default priority), so the
@@ -235,9 +236,11 @@ tdsez_status tdsez_propagate_batched(tdsez_batch b, double* psi_packed, const lo
                                      void* stream);
 
 /* Single-system convenience form of tdsez_propagate_batched (the library
- * keeps a one-system plan inside the system handle).  psi: device complex128
- * [N] in/out; E: device FP64 [nsteps+1]; obs_out: device FP64 [(nsteps+1)*3]
- * or NULL.  Asynchronous on `stream`. */
+ * keeps a one-system plan inside the system handle, created by the first
+ * call).  The system runs on two waves when its two-wave plan has more than
+ * 64 chunks (N above about 1290; see tdsez_batch_split).  psi: device
+ * complex128 [N] in/out; E: device FP64 [nsteps+1]; obs_out: device FP64
+ * [(nsteps+1)*3] or NULL.  Asynchronous on `stream`. */
 tdsez_status tdsez_propagate(tdsez_system sys, double* psi, const double* E, double dt, int nsteps,
                              tdsez_precision prec, unsigned obs, double* obs_out, void* stream);
 

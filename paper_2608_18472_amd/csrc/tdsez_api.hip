@@ -309,6 +309,10 @@ tdsez_status tdsez_propagate(tdsez_system sys, double* psi, const double* E, dou
         tdsez_system one = sys;
         tdsez_status st = tdsez_batch_create(&one, 1, &sys->d.solo);
         if (st) return st;
+        // a lone system has the device to itself: two waves whenever its
+        // two-wave plan has more than 64 chunks
+        int nsteps_one = 1;
+        if ((st = tdsez_batch_split(sys->d.solo, &nsteps_one, 1)) != TDSEZ_OK) return st;
     }
     long zero = 0;
     return tdsez_propagate_batched(sys->d.solo, psi, &zero, E, &zero, &dt, &nsteps, prec, obs, obs_out,

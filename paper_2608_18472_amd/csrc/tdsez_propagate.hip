@@ -325,8 +325,11 @@ tdsez_status pack_bands(BatchData* b) {
         SystemData* sy = b->sys[s];
         const int tuned = s < (int)b->tuned_chunks.size() ? b->tuned_chunks[s] : 0;
         const bool req = s < (int)b->two_wave_req.size() && b->two_wave_req[s];
-        Plan pl = make_plan(sy->N, sy->p, b->force_chunks > 0 ? b->force_chunks : tuned,
-                            req ? kMaxChunks2 : kMaxChunks, req ? 0.3 : 0.6);
+        const int force = b->force_chunks > 0 ? b->force_chunks : tuned;
+        Plan pl = make_plan(sy->N, sy->p, force, req ? kMaxChunks2 : kMaxChunks, req ? 0.3 : 0.6);
+        // a marked system whose two-wave rule gives at most 64 chunks stays
+        // on one wave, with the one-wave rule
+        if (req && force == 0 && pl.P <= kMaxChunks) pl = make_plan(sy->N, sy->p, 0);
         b->plan[s] = pl;
         if (pl.P > kMaxChunks) {
             b->two_wave[s] = 1;

@@ -176,3 +176,82 @@ def test_two_wave_graph_replays_match_eager(prec):
         dobs = float((ob - obs_ref).abs().max())
         say("replay", rep, dpsi, dobs)
         assert dpsi == 0.0 and dobs == 0.0
+
+
+def test_all_two_wave_batch_odd_chunks_and_zero_steps():
+    """Every system on two waves (the one-wave launch is empty), an odd
+    chunk count (the backward half of the separator chain holds one block
+    more than the forward half) and per-system step counts 0, 25 and 40;
+    FP64 against the oracle."""
+    V, dV = W.soft_coulomb(2.0)
+    defs = []
+    for n_el, order, ns in ((1270, 7, 25), (1600, 8, 0), (2300, 6, 40)):
+        E = 0.06 * np.sin(0.05 * 0.05 * np.arange(ns + 1) + 0.4)
+        defs.append(W.System("two-%d" % n_el, W.breaks_uniform(200.0, n_el - order + 3), order,
+                             lambda x: np.ones_like(x), V, dV, 10, E, 0.05, ns, True))
+    b = T.batch_create([T.assemble_workload(s) for s in defs])
+    nss = [s.nsteps for s in defs]
+    T.batch_split(b, nss, len(defs))
+    chunks = T.batch_chunks(b)
+    say("N", [s.ndof for s in defs], "chunks", chunks.tolist())
+    assert T.batch_two_wave(b).tolist() == [1, 1, 1]
+    assert chunks[0] % 2 == 1
+    refs, psi0s = [], []
+    for s in defs:
+        m, p0 = _oracle(s)
+        psi0s.append(p0)
+        refs.append(O.propagate(m, p0, s.E, s.dt, s.nsteps))
+    psi, po, E, eo, obs, oo = T.pack_batch_inputs(defs, psi0s)
+    T.propagate_batched(b, psi, po, E, eo, [s.dt for s in defs], nss, T.FP64, T.OBS_ALL, obs, oo)
+    T.batch_status(b)
+    o = obs.cpu().numpy()
+    c = psi.cpu().numpy()
+    for i, (r, cr) in enumerate(refs):
+        ns = defs[i].nsteps
+        gi = o[3 * eo[i]: 3 * eo[i] + 3 * (ns + 1)].reshape(-1, 3)
+        assert rel(c[po[i]: po[i] + len(cr)], cr) < 1e-10, i
+        say("system", i, "steps", ns, "max |obs - oracle|", np.abs(gi - r).max(0).tolist())
+        if ns == 0:
+            # only the initial state's observables: its dipole and acceleration
+            # vanish up to rounding (symmetric potential and knots), so they are
+            # compared in absolute terms
+            assert np.abs(gi - r).max() < 1e-12, i
+            continue
+        for k in range(3):
+            assert rel(gi[:, k], r[:, k]) < 1e-10, (i, k)
+
+
+def test_marked_small_system_keeps_its_one_wave_plan():
+    """A system marked for two waves whose two-wave plan has at most 64
+    chunks (N = 1004: 58) keeps the one-wave plan (41 chunks)."""
+    sd = W.config1(nsteps=4)
+    b = T.batch_create([T.assemble_workload(sd)])
+    one = T.batch_chunks(b).copy()
+    T.batch_split(b, [4], 1)
+    assert T.batch_two_wave(b).tolist() == [0]
+    assert np.array_equal(T.batch_chunks(b), one)
+
+
+def test_single_system_runs_on_two_waves():
+    """tdsez_propagate on a system above the two-wave threshold (N = 2000):
+    FP64 and FP32-refined against the oracle over 200 steps."""
+    V, dV = W.soft_coulomb(2.0)
+    ns = 200
+    E = 0.06 * np.sin(0.05 * 0.05 * np.arange(ns + 1) + 0.4)
+    sd = W.System("lone", W.breaks_uniform(200.0, 2000 - 8 + 3), 8, lambda x: np.ones_like(x), V, dV, 10, E,
+                  0.05, ns, True)
+    g = T.assemble_workload(sd)
+    m, p0 = _oracle(sd)
+    ref, cref = O.propagate(m, p0, sd.E, sd.dt, ns)
+    for prec, tol in ((T.FP64, 1e-10), (T.FP32_REFINED, 1e-5)):
+        psi = torch.from_numpy(p0.copy()).cuda()
+        Et = torch.from_numpy(E.copy()).cuda()
+        o = torch.zeros(3 * (ns + 1), dtype=torch.float64, device="cuda")
+        T.propagate(g, psi, Et, sd.dt, ns, prec, T.OBS_ALL, o)
+        T.system_status(g)
+        got = o.cpu().numpy().reshape(-1, 3)
+        errs = [rel(got[:, k], ref[:, k]) for k in range(3)]
+        say("lone system", sd.ndof, prec, errs)
+        assert max(errs) < tol
+        if prec == T.FP64:
+            assert rel(psi.cpu().numpy(), cref) < 1e-10
