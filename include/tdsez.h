@@ -214,7 +214,8 @@ tdsez_status tdsez_batch_split(tdsez_batch b, const int* nsteps, int count);
 tdsez_status tdsez_batch_two_wave(tdsez_batch b, int* flags_out);
 
 /* Crank-Nicolson propagation of every system of the batch in one persistent
- * kernel launch (one workgroup per system), section V.B eq. cn_system with
+ * kernel launch (one workgroup per system; two-wave systems in a concurrent
+ * launch of their own, see tdsez_batch_split), section V.B eq. cn_system with
  * H^{n+1/2} = H0 + (E_n + E_{n+1})/2 D.
  *   psi_packed (device, in/out): complex128 states; system s starts at
  *       element psi_off[s] (host array of nsys offsets, in complex elements)

@@ -15,7 +15,7 @@ namespace tdsez {
 
 // Largest supported half-bandwidth (order 8 B-splines).
 constexpr int kMaxP = 7;
-// Lanes of one propagation workgroup (one wave64 per system).
+// Lanes of one wave64 (a propagation workgroup holds one or two waves).
 constexpr int kWave = 64;
 // Largest partition count of one system (one chunk per lane).
 constexpr int kMaxChunks = 64;
