@@ -106,6 +106,21 @@ def sin2_pulse(E0, omega, ncycles, dt, nsteps=None):
     return E, nsteps, Tp
 
 
+def trapezoid_pulse(E0, omega, ncycles, ramp_cycles, dt, nsteps=None):
+    """E(t) = E0 f(t) sin(omega t) on [0, Tp], 0 afterwards, Tp = ncycles
+    2 pi / omega, with an envelope f rising linearly over the first
+    ramp_cycles cycles, flat, and falling linearly over the last ramp_cycles;
+    nsteps defaults to ceil(Tp/dt)."""
+    T1 = 2.0 * math.pi / omega
+    Tp = ncycles * T1
+    Tr = ramp_cycles * T1
+    if nsteps is None:
+        nsteps = int(math.ceil(Tp / dt - 1e-9))
+    t = dt * np.arange(nsteps + 1)
+    f = np.clip(np.minimum(t / Tr, (Tp - t) / Tr), 0.0, 1.0)
+    return np.where(t <= Tp, E0 * f * np.sin(omega * t), 0.0), nsteps, Tp
+
+
 def fourier_pulse(theta, Tp, dt, nsteps):
     """E(t; theta) = sum_j theta_j sin(j pi t / Tp) on [0, Tp] (j = 1..len(theta))."""
     t = dt * np.arange(nsteps + 1)
@@ -165,6 +180,33 @@ def harmonic(omega=1.0):
 # --------------------------------------------------------------------------
 # Workloads.
 # --------------------------------------------------------------------------
+def soft_core_two_centre(R, eps):
+    """1D two-centre soft-core potential of H2+ along the molecular axis,
+    V(x) = -1/sqrt((x + R/2)^2 + eps) - 1/sqrt((x - R/2)^2 + eps), and dV/dx."""
+    def V(x):
+        return -1.0 / np.sqrt((x + 0.5 * R) ** 2 + eps) - 1.0 / np.sqrt((x - 0.5 * R) ** 2 + eps)
+
+    def dV(x):
+        return (x + 0.5 * R) / ((x + 0.5 * R) ** 2 + eps) ** 1.5 + (x - 0.5 * R) / ((x - 0.5 * R) ** 2 + eps) ** 1.5
+    return V, dV
+
+
+def h2p_1d(nsteps=None, dt=0.05, r1=0.2, nlin=5000):
+    """1D H2+ model of the molecular-HHG section: nuclei clamped at R = 2,
+    soft-core eps = 1.472, 30 007 degree-7 B-splines on [-4000, 4000] with the
+    hydrogenic grading mirrored about 0 (linear steps r1 up to nlin r1, then
+    exponential), 6-cycle trapezoidal pulse w = 0.057, 1e14 W/cm^2
+    (E0 = 0.0534) with one-cycle linear ramps, dt = 0.05 (13 228 steps)."""
+    order = 8
+    p = order - 1
+    nel = 30007 - p + 2                      # N = nel + p - 2
+    nexp = nel // 2 - nlin
+    V, dV = soft_core_two_centre(2.0, 1.472)
+    E, ns, Tp = trapezoid_pulse(0.0534, 0.057, 6, 1, dt, nsteps)
+    return System("h2p-1d", breaks_hydrogenic_symmetric(r1, nlin, nexp, 4000.0), order, _ones, V, dV, 10, E, dt,
+                  ns, True, {"R": 2.0, "eps": 1.472, "E0": 0.0534, "omega": 0.057, "Tp": Tp})
+
+
 def config1(nsteps=None):
     """1D soft-Coulomb atom V = -1/sqrt(x^2+2), order 8, 1000 uniform
     breakpoints on [-200, 200] (N = 1004), sin^2 pulse w = 0.057, E0 = 0.0534,

@@ -72,6 +72,24 @@ def test_quesne_pdm_oscillator_table3():
     assert np.abs((ev2 - ex) / ex).max() < 5e-14
 
 
+def test_h2p_1d_levels_molecular_hhg_section():
+    """The 1D H2+ model's two lowest levels against the printed values, and
+    their parity: the potential and the knots are symmetric, so the basis is
+    mirror-symmetric (B_i(-x) = B_{N-1-i}(x)) and the ground state is gerade
+    (coefficients symmetric), the first excited state ungerade."""
+    g = json.load(open(os.path.join(GOLDEN, "h2p_1d_levels.json")))
+    s = W.h2p_1d(nsteps=1)
+    assert s.ndof == g["splines"] and s.order == g["degree"] + 1
+    assert s.meta["R"] == g["R"] and s.meta["eps"] == g["eps"]
+    m = O.assemble(s.breaks, s.order, s.nq, s.minv, s.V, s.dV)
+    ev, vec = O.eig_banded(m["H0"], m["S"], 2, -1.2)
+    assert abs(ev[0] - g["E0"]) < g["tol_E0"], ev
+    assert abs(ev[1] - g["E1"]) < g["tol_E1"], ev
+    c0, c1 = vec[0], vec[1]
+    assert np.abs(c0 - c0[::-1]).max() < 1e-9 * np.abs(c0).max()
+    assert np.abs(c1 + c1[::-1]).max() < 1e-9 * np.abs(c1).max()
+
+
 def _bdd_square_well_ground(a, mw, mb, V0):
     """Even ground state of a square well |x| < a/2 (mass mw, V = 0) in a
     barrier (mass mb, V = V0): psi and psi'/m continuous give
