@@ -113,17 +113,21 @@ def main():
     ap.add_argument("--split", type=int, default=160,
                     help="run this many of the costliest systems on two waves each (setup, untimed; "
                          "160 of 1024 measured best, 0 = one wave per system)")
-    ap.add_argument("--workload", choices=["batch1d", "2d"], default="batch1d",
+    ap.add_argument("--workload", choices=["batch1d", "2d", "h2p"], default="batch1d",
                     help="batch1d: the batched 1D benchmark (default); 2d: a segment of the 512 x 512 "
-                         "tensor-product workload")
+                         "tensor-product workload; h2p: the 1D H2+ model (30 007 splines, one long "
+                         "chain) over its whole pulse")
     ap.add_argument("--steps-2d", type=int, default=400, help="time steps of the 2D segment")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: the batched propagation has no multi-GPU path in this "
-              "build (run with --gpus 1)", file=sys.stderr)
+        print("bench.py measures one GPU only: the propagation runs on a single device "
+              "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
     if args.workload == "2d":
         run_2d(args)
+        return
+    if args.workload == "h2p":
+        run_h2p(args)
         return
 
     import torch
@@ -331,6 +335,90 @@ def run_2d(args):
     if cpu is not None:
         line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)
+
+
+def run_h2p(args):
+    """One long chain: the 1D H2+ model (N = 30 007, p = 7) over its whole
+    6-cycle trapezoidal pulse (13 228 steps), FP32-refined then FP64, through
+    the single-system call (two waves, 128 chunks of 235 rows)."""
+    import torch
+    from paper_2608_18472_amd import tdsez as T
+    from paper_2608_18472_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    sd = W.h2p_1d()
+    g = T.assemble_workload(sd)
+    ev, vec = T.ground_state(g, 2)
+    psi0 = torch.from_numpy(vec[0].astype(np.complex128)).cuda()
+    E = torch.from_numpy(np.ascontiguousarray(sd.E[: sd.nsteps + 1])).cuda()
+    stream = torch.cuda.current_stream()
+    ns = sd.nsteps
+    out = {}
+    for name, prec in (("fp32-refined", T.FP32_REFINED), ("fp64", T.FP64)):
+        o = torch.zeros(3 * (ns + 1), dtype=torch.float64, device="cuda")
+        T.propagate(g, psi0.clone(), E, sd.dt, 20, prec, T.OBS_ALL, o, stream)  # warm-up
+        psi = psi0.clone()
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        T.propagate(g, psi, E, sd.dt, ns, prec, T.OBS_ALL, o, stream)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        T.system_status(g)
+        out[name] = {"sec": ev0.elapsed_time(ev1) / 1000.0, "obs": o.cpu().numpy().reshape(-1, 3)}
+    d64 = out["fp64"]["obs"][:, 1]
+    d32 = out["fp32-refined"]["obs"][:, 1]
+    n = sd.ndof
+    sec = out["fp32-refined"]["sec"]
+    alg = n * ns * algorithmic_bytes(sd.order, 4, 8)
+    cpu = None if args.no_cpu else cpu_baseline_h2p(400)
+    line = {
+        "metric": "complex DOF-steps/s per GPU (1D H2+ model, one long chain)",
+        "value": n * ns / sec,
+        "unit": "DOF-steps/s",
+        "n_gpus": 1,
+        "steps": ns,
+        "warmup": 20,
+        "ms_per_step": 1000.0 * sec / ns,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "1D H2+ (R 2, soft-core eps 1.472), 30 007 degree-7 splines on [-4000,4000], mirrored "
+                        "hydrogenic knots, 6-cycle trapezoidal pulse w 0.057 E0 0.0534, dt 0.05, whole pulse",
+            "levels": [float(ev[0]), float(ev[1])],
+            "fp64_value": n * ns / out["fp64"]["sec"],
+            "fp64_ms_per_step": 1000.0 * out["fp64"]["sec"] / ns,
+            "dipole_rel_err_fp32_vs_fp64": float(np.linalg.norm(d32 - d64) / np.linalg.norm(d64)),
+            "final_norm_fp64": float(out["fp64"]["obs"][-1, 0]),
+        },
+        "roofline": {"bound": "hbm", "achieved": alg / sec / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": alg / sec / 1e9 / HBM_PEAK_GBS, "traffic": None},
+    }
+    if cpu is not None:
+        line["cpu_baseline"] = cpu
+    print(json.dumps(line), flush=True)
+
+
+def cpu_baseline_h2p(nsteps):
+    """The oracle (serial FP64 C, one core: a single system) on the first
+    nsteps steps of the H2+ workload."""
+    from oracle import oracle as O
+    from paper_2608_18472_amd import workloads as W
+    O.build()
+    sd = W.h2p_1d()
+    m = O.assemble(sd.breaks, sd.order, sd.nq, sd.minv, sd.V, sd.dV)
+    ev, vec = O.eig_banded(m["H0"], m["S"], 1, -1.2)
+    t0 = time.perf_counter()
+    O.propagate(m, vec[0].astype(np.complex128), sd.E, sd.dt, nsteps)
+    wall = time.perf_counter() - t0
+    dof = sd.ndof * nsteps
+    return {"value": dof / wall, "unit": "DOF-steps/s", "cores": 1, "kind": "oracle",
+            "sample": "first %d steps of the H2+ pulse (%.3g DOF-steps), serial FP64 C, wall %.1f s"
+                      % (nsteps, dof, wall)}
 
 
 def cpu_baseline_2d(nsteps):
