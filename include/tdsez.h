@@ -228,8 +228,11 @@ tdsez_status tdsez_batch_two_wave(tdsez_batch b, int* flags_out);
  *       TDSEZ_OBS_*; may be NULL when obs == 0.
  * Workgroups start in order of decreasing cost N (p + 1) nsteps, so a batch
  * with more systems than the device holds at once runs longest first.
- * Asynchronous on `stream`.  EINVAL on bad arguments (detected on the host);
- * device-side failures are latched (tdsez_batch_status). */
+ * Asynchronous on `stream`.  Calls on one batch must not overlap (they share
+ * the batch's working state, and its side stream and events when it holds
+ * two-wave systems); different batches may run concurrently.  EINVAL on bad
+ * arguments (detected on the host); device-side failures are latched
+ * (tdsez_batch_status). */
 tdsez_status tdsez_propagate_batched(tdsez_batch b, double* psi_packed, const long* psi_off,
                                      const double* E_packed, const long* E_off,
                                      const double* dt, const int* nsteps, tdsez_precision prec,
