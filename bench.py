@@ -35,8 +35,8 @@ CALIB_COPY_BYTES = 512 * 2 ** 20
 # (FETCH_SIZE, then WRITE_SIZE) scaled by the copy calibration; valid only for
 # the kernel sources they were taken on (sha256 of the listed files) and the
 # default --split.  See profiles/propagate_kernel_fp32_batch1024_pmc.md.
-TRAFFIC = {"sources_sha256": "8831d3fa596367d43b3e89b2bcc788978f7d7be0b95c37223416331d2b734996",
-           "bytes_per_launch": 2.4227e13, "split": 160}
+TRAFFIC = {"sources_sha256": "2a4ce85a0e4e3f7767fe1d4a564169950bf2744c047da1adba9306ae49815cc8",
+           "bytes_per_launch": 2.4232e13, "split": 160}
 KERNEL_SOURCES = ["paper_2608_18472_amd/csrc/tdsez_passes.hpp", "paper_2608_18472_amd/csrc/tdsez_propagate.hip",
                   "paper_2608_18472_amd/csrc/tdsez_internal.hpp"]
 

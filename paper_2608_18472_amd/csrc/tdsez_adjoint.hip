@@ -195,7 +195,8 @@ __device__ __forceinline__ void pass_adjoint_update(const SysDesc& sd, int k, co
 
 // one forward step n -> n+1 in place on st (FP64, no refinement)
 template <int PP>
-__device__ __forceinline__ void forward_step(const AdjArgs& ka, const SysDesc& sd, int lane, double alpha, double Ebar) {
+__device__ __forceinline__ void forward_step(const AdjArgs& ka, const SysDesc& sd, int lane, double alpha, double Ebar,
+                                             double* zl) {
     const bool active = lane < sd.P;
     double part[3];
     if (active) {
@@ -205,14 +206,14 @@ __device__ __forceinline__ void forward_step(const AdjArgs& ka, const SysDesc& s
         pass_schur<PP, double>(sd, lane, ka.fac, ka.red);
     }
     __syncthreads();
-    pass_reduced<PP, double>(sd, lane, ka.red, true);
+    pass_reduced<PP, double>(sd, lane, ka.red, true, zl);
     __syncthreads();
     if (active) pass_backsub<PP, double>(sd, lane, ka.band, ka.st, nullptr, true, ka.fac, ka.red, alpha, Ebar);
     __syncthreads();
 }
 
 template <int PP>
-__device__ __forceinline__ void run_adjoint(const AdjArgs& ka, const SysDesc& sd, int sidx) {
+__device__ __forceinline__ void run_adjoint(const AdjArgs& ka, const SysDesc& sd, int sidx, double* zl) {
     const int lane = threadIdx.x;
     const bool active = lane < sd.P;
     const int N = sd.N, L = sd.L, LS = sd.LS, ns = sd.nsteps, ck = sd.ck;
@@ -261,7 +262,7 @@ __device__ __forceinline__ void run_adjoint(const AdjArgs& ka, const SysDesc& sd
     copy_state(sd, lane, ka.st, state_at(ckpt, 0));
     __syncthreads();
     for (int n = 0; n < ns; ++n) {
-        forward_step<PP>(ka, sd, lane, alpha, ebar(n));
+        forward_step<PP>(ka, sd, lane, alpha, ebar(n), zl);
         if ((n + 1) % ck == 0 && n + 1 < ns) {
             copy_state(sd, lane, ka.st, state_at(ckpt, (n + 1) / ck));
             __syncthreads();
@@ -285,7 +286,7 @@ __device__ __forceinline__ void run_adjoint(const AdjArgs& ka, const SysDesc& sd
         copy_state(sd, lane, state_at(ckpt, sgi), state_at(seg, 0));
         __syncthreads();
         for (int n = n0; n < n1; ++n) {
-            forward_step<PP>(ka, sd, lane, alpha, ebar(n));
+            forward_step<PP>(ka, sd, lane, alpha, ebar(n), zl);
             copy_state(sd, lane, ka.st, state_at(seg, n - n0 + 1));
             __syncthreads();
         }
@@ -298,7 +299,7 @@ __device__ __forceinline__ void run_adjoint(const AdjArgs& ka, const SysDesc& sd
                 pass_schur<PP, double>(sd, lane, ka.fac, ka.red);
             }
             __syncthreads();
-            pass_reduced<PP, double>(sd, lane, ka.red, true);
+            pass_reduced<PP, double>(sd, lane, ka.red, true, zl);
             __syncthreads();
             if (active)
                 pass_backsub<PP, double>(sd, lane, ka.band, ka.wsol, nullptr, true, ka.fac, ka.red, alpha, Eb,
@@ -338,16 +339,18 @@ __device__ __forceinline__ void run_adjoint(const AdjArgs& ka, const SysDesc& sd
 }
 
 __global__ __launch_bounds__(kWave) void adjoint_kernel(AdjArgs ka) {
+    // the separator recurrence's right-hand-side vector (P * p complex)
+    __shared__ double zl[2 * kMaxP * kMaxChunks];
     const int sidx = ka.order[blockIdx.x];
     const SysDesc sd = ka.descs[sidx];
     switch (sd.p) {
-        case 1: run_adjoint<1>(ka, sd, sidx); break;
-        case 2: run_adjoint<2>(ka, sd, sidx); break;
-        case 3: run_adjoint<3>(ka, sd, sidx); break;
-        case 4: run_adjoint<4>(ka, sd, sidx); break;
-        case 5: run_adjoint<5>(ka, sd, sidx); break;
-        case 6: run_adjoint<6>(ka, sd, sidx); break;
-        case 7: run_adjoint<7>(ka, sd, sidx); break;
+        case 1: run_adjoint<1>(ka, sd, sidx, zl); break;
+        case 2: run_adjoint<2>(ka, sd, sidx, zl); break;
+        case 3: run_adjoint<3>(ka, sd, sidx, zl); break;
+        case 4: run_adjoint<4>(ka, sd, sidx, zl); break;
+        case 5: run_adjoint<5>(ka, sd, sidx, zl); break;
+        case 6: run_adjoint<6>(ka, sd, sidx, zl); break;
+        case 7: run_adjoint<7>(ka, sd, sidx, zl); break;
         default: break;
     }
 }

@@ -780,144 +780,13 @@ __device__ inline cplx<FT> row_sum(cplx<FT> v) {
     return cadd(v, dpp_c<kDppRowHalfMirror>(v));
 }
 
-template <int PP, typename FT>
-__device__ __forceinline__ void pass_reduced(const SysDesc& sd, int lane, FT* __restrict__ red, bool factor) {
-    constexpr int p = PP;
-    const int P = sd.P;
-    const long long cb = RedLayout<FT>::chunk_block(p);
-    FT* rbase = red + 2 * sd.red_off;
-    FT* dinv_base = rbase + 2 * RedLayout<FT>::dinv(p, P);
-    FT* m_base = rbase + 2 * RedLayout<FT>::mblk(p, P);
-    FT* z_base = rbase + 2 * RedLayout<FT>::zvec(p, P);
-    FT* x_base = rbase + 2 * RedLayout<FT>::xvec(p, P);
-    const int i = lane >> 3, j = lane & 7;
-    const bool valid = (i < p) && (j < p);
-    constexpr unsigned pp = (unsigned)(p * p);
-    const unsigned eij = (unsigned)(i * p + j);
-    const cplx<FT> zero = cmk<FT>(0, 0);
-    const cplx<FT> ident = cmk<FT>(i == j ? (FT)1 : (FT)0, 0);
-    auto blk = [&](int s) { return rbase + 2 * ((long long)s * cb); };
-
-    // the raw inputs of block s, loaded one block ahead of their use; loads
-    // are unconditional (indices clamped into the workspace) and the
-    // padding/boundary masks are applied when the values are used, so that no
-    // load sits in a branch that would force an early wait
-    const unsigned ii = (unsigned)(i < p ? i : 0);
-    const unsigned ee = valid ? eij : 0u;
-    struct Fwd {
-        cplx<FT> y, gt, w, tl, f;
-    };
-    auto load_fwd = [&](int s) {
-        const int sc = s < P ? s : P - 1;
-        const int s1 = s + 1 < P ? s + 1 : P - 1;
-        const FT* bs = blk(sc);
-        const FT* b1 = blk(s1);
-        Fwd r;
-        r.y = ld_c(bs, 3 * pp + ii);
-        r.gt = ld_c(b1, 3 * pp + (unsigned)p + ii);
-        if (factor) {
-            r.w = ld_c(bs, ee);
-            r.tl = ld_c(b1, 2 * pp + ee);
-            r.f = ld_c(bs, pp + ee);
-        } else {
-            r.w = r.tl = zero;
-            r.f = ld_c(m_base, (unsigned)sc * pp + ee);  // stored M_s
-        }
-        return r;
-    };
-
-    // forward sweep
-    cplx<FT> dprev = zero;  // Delta_{s-1}^-1 entry
-    cplx<FT> zc = zero;     // z_{s-1} in column layout
-    Fwd cur = load_fwd(0);
-    for (int s = 0; s < P; ++s) {
-        Fwd nxt = load_fwd(s + 1);
-        const bool more = s + 1 < P;
-        const cplx<FT> g = csel(i < p, cadd(cur.y, csel(more, cur.gt, zero)), zero);
-        const cplx<FT> fv = csel(valid, cur.f, zero);
-        cplx<FT> mm = zero;
-        if (factor) {
-            cplx<FT> a = csel(valid, cadd(cur.w, csel(more, cur.tl, zero)), ident);
-            if (s >= 1) {
-                cplx<FT> fr[p], dc[p];
-#pragma unroll
-                for (int l = 0; l < p; ++l) {
-                    fr[l] = shfl_c(fv, 8 * i + l);
-                    dc[l] = shfl_c(dprev, 8 * l + j);
-                }
-#pragma unroll
-                for (int l = 0; l < p; ++l) mm = cfma(mm, fr[l], dc[l]);
-                cplx<FT> mr[p], fc2[p];
-#pragma unroll
-                for (int l = 0; l < p; ++l) {
-                    mr[l] = shfl_c(mm, 8 * i + l);
-                    fc2[l] = shfl_c(fv, 8 * j + l);
-                }
-#pragma unroll
-                for (int l = 0; l < p; ++l) a = cfms(a, mr[l], fc2[l]);
-                if (valid) st_c(m_base, (unsigned)s * pp + eij, mm);
-            }
-            // Gauss-Jordan inverse of the (identity padded) block, no pivoting
-#pragma unroll
-            for (int q = 0; q < p; ++q) {
-                const cplx<FT> aiq = shfl_c(a, 8 * i + q);
-                const cplx<FT> aqj = shfl_c(a, 8 * q + j);
-                const cplx<FT> piv = cinv_dev(bcast_c(a, 9 * q));
-                const cplx<FT> t = cmul(aiq, piv);
-                const cplx<FT> rowq = csel(j == q, piv, cmul(aqj, piv));
-                const cplx<FT> other = csel(j == q, cmk<FT>(-t.re, -t.im), cfms(a, t, aqj));
-                a = csel(i == q, rowq, other);
-            }
-            if (valid) st_c(dinv_base, (unsigned)s * pp + eij, a);
-            dprev = a;
-        } else {
-            mm = csel(s >= 1, fv, zero);
-        }
-        cplx<FT> zr = csub(g, row_sum(cmul(mm, zc)));
-        if (j == 0 && i < p) st_c(z_base, (unsigned)(s * p + i), zr);
-        zc = shfl_c(zr, 8 * j);
-        cur = nxt;
-    }
-    __syncthreads();  // z_s written by other lanes
-    // backward sweep: lane (i, j) loads F_{s+1}[j][i] (transposed) so that
-    // both products are row sums; x and w change layout with one shuffle each
-    const unsigned eji = valid ? (unsigned)(j * p + i) : 0u;
-    struct Bwd {
-        cplx<FT> dv, fnt, zs;
-    };
-    auto load_bwd = [&](int s) {
-        const int sc = s < 0 ? 0 : s;
-        const int s1 = sc + 1 < P ? sc + 1 : P - 1;
-        Bwd r;
-        r.dv = ld_c(dinv_base, (unsigned)sc * pp + ee);
-        r.fnt = ld_c(blk(s1), pp + eji);
-        r.zs = ld_c(z_base, (unsigned)(sc * p) + ii);
-        return r;
-    };
-    cplx<FT> xc = zero;  // x_{s+1} in column layout
-    Bwd bc = load_bwd(P - 1);
-    for (int s = P - 1; s >= 0; --s) {
-        Bwd bn = load_bwd(s - 1);
-        const cplx<FT> dv = csel(valid, bc.dv, ident);
-        const cplx<FT> fnt = csel(valid && s + 1 < P, bc.fnt, zero);
-        const cplx<FT> zs = csel(i < p, bc.zs, zero);
-        // w_s = z_s - F_{s+1}^T x_{s+1}  (row layout), then column layout
-        const cplx<FT> wr = csub(zs, row_sum(cmul(fnt, xc)));
-        const cplx<FT> wc = shfl_c(wr, 8 * j);
-        // x_s = Delta_s^-1 w_s  (row layout), then column layout
-        const cplx<FT> xr = row_sum(cmul(dv, wc));
-        if (j == 0 && i < p) st_c(x_base, (unsigned)(s * p + i), xr);
-        xc = shfl_c(xr, 8 * j);
-        bc = bn;
-    }
-}
-
-// Pass R over two waves (systems with more than 64 chunks): the separator
-// system is eliminated from both ends at once.  Wave 0 runs the recurrence
-// of pass_reduced over blocks 0..h-1 (h = P/2); wave 1 runs it backwards
-// over blocks P-1..h, where the coupling of block s to the block eliminated
-// before it is F_{s+1}^T (the system is symmetric, so the step is the same
-// with the coupling transposed):
+// Pass R over one or two waves.  One wave (NW = 1): the recurrence above
+// over blocks 0..P-1, then the backward sweep.  Two waves (NW = 2, systems
+// with more than 64 chunks): the separator system is eliminated from both
+// ends at once.  Wave 0 runs the recurrence over blocks 0..h-1 (h = P/2);
+// wave 1 runs it backwards over blocks P-1..h, where the coupling of block s
+// to the block eliminated before it is F_{s+1}^T (the system is symmetric,
+// so the step is the same with the coupling transposed):
 //   G_{P-1} = Sigma_{P-1},  N_s = F_{s+1}^T G_{s+1}^-1,
 //   G_s = Sigma_s - N_s F_{s+1},  w_s = g_s - N_s w_{s+1}.
 // Wave 1 then joins the halves at block h:
@@ -928,17 +797,21 @@ __device__ __forceinline__ void pass_reduced(const SysDesc& sd, int lane, FT* __
 //   x_s = G_s^-1 (w_s - F_s x_{s-1}),            s = h+1 .. P-1   (wave 1).
 // Storage: Delta_s^-1 and G_s^-1 in the Dinv slots (Delta'_h^-1 at h), M_s
 // and N_s in the M slots (M_h in the otherwise unused slot P-1), z_s and w_s
-// in z (z'_h at h).  Both waves reach the same two barriers.
-template <int PP, typename FT>
-__device__ __forceinline__ void pass_reduced2(const SysDesc& sd, int tid, FT* __restrict__ red, bool factor) {
+// in z (z'_h at h).  Both waves reach the same two barriers.  z lives in
+// LDS (zl: P * p complex, declared once per kernel): it is written and read
+// back within the pass, and LDS traffic does not queue behind the streaming
+// passes of the other waves of the CU.
+template <int PP, typename FT, int NW>
+__device__ __forceinline__ void pass_reduced_w(const SysDesc& sd, int tid, FT* __restrict__ red, bool factor,
+                                               FT* __restrict__ zl) {
     constexpr int p = PP;
-    const int P = sd.P, h = P / 2;
-    const int wv = tid >> 6, lane = tid & 63;
+    const int P = sd.P, h = NW == 2 ? P / 2 : P;
+    const int wv = NW == 2 ? tid >> 6 : 0, lane = tid & 63;
     const long long cb = RedLayout<FT>::chunk_block(p);
     FT* rbase = red + 2 * sd.red_off;
     FT* dinv_base = rbase + 2 * RedLayout<FT>::dinv(p, P);
     FT* m_base = rbase + 2 * RedLayout<FT>::mblk(p, P);
-    FT* z_base = rbase + 2 * RedLayout<FT>::zvec(p, P);
+    FT* z_base = zl;
     FT* x_base = rbase + 2 * RedLayout<FT>::xvec(p, P);
     const int i = lane >> 3, j = lane & 7;
     const bool valid = (i < p) && (j < p);
@@ -1080,6 +953,12 @@ __device__ __forceinline__ void pass_reduced2(const SysDesc& sd, int tid, FT* __
         }
     };
 
+    if constexpr (NW == 1) {
+        chain(0, P, 1, false);
+        __syncthreads();  // z_s and the block factors written by other lanes
+        backsub(P - 1, P, -1, zero);
+        return;
+    }
     if (wv == 0) chain(0, h, 1, false);
     else chain(P - 1, P - h, -1, true);
     __syncthreads();  // both halves eliminated
@@ -1117,6 +996,17 @@ __device__ __forceinline__ void pass_reduced2(const SysDesc& sd, int tid, FT* __
     const cplx<FT> xhc = shfl_c(xh, 8 * j);
     if (wv == 0) backsub(h - 1, h, -1, xhc);
     else if (P - h - 1 > 0) backsub(h + 1, P - h - 1, 1, xhc);
+}
+
+template <int PP, typename FT>
+__device__ __forceinline__ void pass_reduced(const SysDesc& sd, int lane, FT* __restrict__ red, bool factor,
+                                             FT* __restrict__ zl) {
+    pass_reduced_w<PP, FT, 1>(sd, lane, red, factor, zl);
+}
+template <int PP, typename FT>
+__device__ __forceinline__ void pass_reduced2(const SysDesc& sd, int tid, FT* __restrict__ red, bool factor,
+                                              FT* __restrict__ zl) {
+    pass_reduced_w<PP, FT, 2>(sd, tid, red, factor, zl);
 }
 
 // Pass B: interior values of the chunk from its separator values.

@@ -52,7 +52,7 @@ constexpr int kProfSlots = 9;
 // system is solved from both ends (pass_reduced2) and the observable sums
 // are combined across the waves through LDS.
 template <int PP, typename FT, int NW>
-__device__ __forceinline__ void run_system(const KernelArgs& ka, const SysDesc& sd, int sidx) {
+__device__ __forceinline__ void run_system(const KernelArgs& ka, const SysDesc& sd, int sidx, FT* zl) {
     // optional phase profile: shader-clock cycles summed over the steps for
     // the passes H, A1 (FP32: one fused sweep counted under H), A2, R, B and,
     // per refinement sweep, C, R, B
@@ -143,8 +143,8 @@ __device__ __forceinline__ void run_system(const KernelArgs& ka, const SysDesc& 
         if (last) break;
         __syncthreads();
         mark(2);
-        if constexpr (NW == 2) pass_reduced2<PP, FT>(sd, lane, red, true);
-        else pass_reduced<PP, FT>(sd, lane, red, true);
+        if constexpr (NW == 2) pass_reduced2<PP, FT>(sd, lane, red, true, zl);
+        else pass_reduced<PP, FT>(sd, lane, red, true, zl);
         __syncthreads();
         mark(3);
         if (active) pass_backsub<PP, FT>(sd, lane, band, st, dtot, true, fac, red, alpha, Ebar);
@@ -157,8 +157,8 @@ __device__ __forceinline__ void run_system(const KernelArgs& ka, const SysDesc& 
                 pass_residual<PP, FT>(sd, lane, band, ka.band64, st, dtot, fac, red, alpha, Ebar);
             __syncthreads();
             mark(5);
-            if constexpr (NW == 2) pass_reduced2<PP, FT>(sd, lane, red, false);
-            else pass_reduced<PP, FT>(sd, lane, red, false);
+            if constexpr (NW == 2) pass_reduced2<PP, FT>(sd, lane, red, false, zl);
+            else pass_reduced<PP, FT>(sd, lane, red, false, zl);
             __syncthreads();
             mark(6);
             if (active)
@@ -175,18 +175,21 @@ __device__ __forceinline__ void run_system(const KernelArgs& ka, const SysDesc& 
     }
 }
 
+// zl: the separator recurrence's right-hand-side vector, P * p complex in
+// LDS, one array per kernel (shared by the p variants)
 template <typename FT, int NW>
 __device__ __forceinline__ void dispatch_system(const KernelArgs& ka) {
+    __shared__ FT zl[2 * kMaxP * (NW == 2 ? kMaxChunks2 : kMaxChunks)];
     const int sidx = ka.order[ka.order_off + blockIdx.x];
     const SysDesc sd = ka.descs[sidx];
     switch (sd.p) {
-        case 1: run_system<1, FT, NW>(ka, sd, sidx); break;
-        case 2: run_system<2, FT, NW>(ka, sd, sidx); break;
-        case 3: run_system<3, FT, NW>(ka, sd, sidx); break;
-        case 4: run_system<4, FT, NW>(ka, sd, sidx); break;
-        case 5: run_system<5, FT, NW>(ka, sd, sidx); break;
-        case 6: run_system<6, FT, NW>(ka, sd, sidx); break;
-        case 7: run_system<7, FT, NW>(ka, sd, sidx); break;
+        case 1: run_system<1, FT, NW>(ka, sd, sidx, zl); break;
+        case 2: run_system<2, FT, NW>(ka, sd, sidx, zl); break;
+        case 3: run_system<3, FT, NW>(ka, sd, sidx, zl); break;
+        case 4: run_system<4, FT, NW>(ka, sd, sidx, zl); break;
+        case 5: run_system<5, FT, NW>(ka, sd, sidx, zl); break;
+        case 6: run_system<6, FT, NW>(ka, sd, sidx, zl); break;
+        case 7: run_system<7, FT, NW>(ka, sd, sidx, zl); break;
         default: break;
     }
 }
