@@ -51,6 +51,12 @@ def lib():
         L.orc_propagate.argtypes = [i, i, dp, dp, dp, dp, dp, dp, dp, d, i, dp, dp]
         L.orc_adjoint.argtypes = [i, i, dp, dp, dp, dp, dp, dp, dp, d, i, dp, dp, dp]
         L.orc_assemble_v2.argtypes = [dp, i, dp, i, i, i, dp, dp]
+        L.orc_assemble_extra.argtypes = [dp, i, i, i, dp, dp, dp, dp, dp, dp, dp]
+        L.orc_velocity.argtypes = [i, i, dp, dp]
+        L.orc_velocity.restype = d
+        L.orc_ext_columns.argtypes = [i]
+        L.orc_propagate_ext.argtypes = [i, i, dp, dp, dp, dp, dp, dp, dp, dp, dp, i, dp, dp, dp, d, i, dp, dp,
+                                        dp]
         L.orc_apply_2d.argtypes = [i, i, i, dp, dp, dp, dp, dp, dp, d, d, d, d, d, dp, dp]
         _lib = L
     return _lib
@@ -204,6 +210,58 @@ def adjoint(m, psi0, E, dt, nsteps, dJdobs, with_accel=True):
                              _p(psi0.view(np.float64)), _p(E), float(dt), int(nsteps), _p(dJdobs),
                              _p(dJdE), _p(lam0.view(np.float64))), "adjoint")
     return dJdE, lam0
+
+
+def assemble_extra(breaks, order, nq, minv=None, eta=None, g=None, h=None):
+    """Half bands of the CAP weight W (mask eta), the velocity matrix's real
+    antisymmetric part K (Vel = -(i/2) K, upper half band) and the a_Q
+    matrix Q, from the samples g = mu mu' and h = mu' mu'' + mu mu''' of
+    mu = m^-1 and its derivatives (see orc_assemble_extra).  Each argument is
+    a callable of x or None."""
+    br = _f64(breaks)
+    N = ndof(len(br), order)
+    p = order - 1
+    xq, _ = quad_points(br, nq)
+    smp = [None if f is None else _f64(f(xq)) for f in (minv, eta, g, h)]
+    out = {k: np.zeros((p + 1, N)) for k in ("W", "K", "Q")}
+    _check(lib().orc_assemble_extra(_p(br), len(br), order, nq, *[_p(a) for a in smp], _p(out["W"]), _p(out["K"]),
+                                    _p(out["Q"])), "assemble_extra")
+    return out
+
+
+def velocity(K, c):
+    """c^H Vel c with Vel = -(i/2) K (eq. vel_elem)."""
+    K = _f64(K)
+    c = _c128(c)
+    p1, N = K.shape
+    return lib().orc_velocity(N, p1 - 1, _p(K), _p(c.view(np.float64)))
+
+
+EXT_COLUMNS = ("E_kin", "E_pot", "E_int", "E_tot", "minv", "velocity", "a_Q", "W", "auto_re", "auto_im")
+
+
+def propagate_ext(m, psi0, E, dt, nsteps, W=None, K=None, Q=None, pop=None, with_accel=True):
+    """CN propagation with an optional absorber W and the extended series.
+    m = dict from assemble(); W, K, Q half bands from assemble_extra (or
+    None); pop: (npop, N) real projection states or None.  Returns
+    (obs[nsteps+1, 3], ext[nsteps+1, 10 + npop], psi_final)."""
+    N, p = m["N"], m["p"]
+    psi0 = _c128(psi0)
+    E = _f64(E)
+    assert E.shape[0] >= nsteps + 1
+    npop = 0 if pop is None else int(np.asarray(pop).shape[0])
+    popa = None if pop is None else _f64(np.asarray(pop).reshape(npop, N))
+    obs = np.zeros((nsteps + 1, 3))
+    ext = np.zeros((nsteps + 1, lib().orc_ext_columns(npop)))
+    out = np.zeros(N, dtype=np.complex128)
+    G = _f64(m["G"]) if with_accel else None
+    Mi = _f64(m["Mi"]) if with_accel else None
+    opt = [None if a is None else _f64(a) for a in (W, K, Q)]
+    _check(lib().orc_propagate_ext(N, p, _p(_f64(m["S"])), _p(_f64(m["T"])), _p(_f64(m["V"])), _p(_f64(m["D"])),
+                                   _p(G), _p(Mi), *[_p(a) for a in opt], npop, _p(popa),
+                                   _p(psi0.view(np.float64)), _p(E), float(dt), int(nsteps), _p(obs), _p(ext),
+                                   _p(out.view(np.float64))), "propagate_ext")
+    return obs, ext, out
 
 
 # --------------------------------------------------------------------------

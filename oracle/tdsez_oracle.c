@@ -982,3 +982,211 @@ int orc_apply_2d(int Nx, int Ny, int p, const double *Sx, const double *Tx, cons
         }
     return ORC_OK;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Further 1D matrices (section V.A element formulas; section IV.A-B).       */
+/*                                                                          */
+/*  W   CAP weight:  W_ab = sum_q w eta(x_q) N_a N_b.  The paper's CAP       */
+/*      matrix is -i W (element formula for W^e with the mask eta), so with  */
+/*      the absorber H = H0 + E D - i W.                                     */
+/*  K   velocity:    K_ab = sum_q w m^-1 (N_a N_b' - N_a' N_b), real and     */
+/*      antisymmetric; the velocity matrix of eq. vel_elem is Vel = -(i/2) K. */
+/*      Stored as its upper half band, band[d*N + i] = K[i][i+d].            */
+/*  Q   a_Q term of eq. pdm_acceleration.  For one dimension and smooth      */
+/*      m^-1 = mu, eq. aQ_definition reads (i/4) <[p mu p, p mu + mu p]>.    */
+/*      With p = -i d/dx the commutator is the differential operator         */
+/*        [p mu p, p mu + mu p] f = i ( h f + 2 (g f')' ),                   */
+/*        g = mu mu',   h = mu' mu'' + mu mu''',                             */
+/*      so, after one integration by parts (psi vanishes at the ends),       */
+/*        a_Q = 1/2 <psi'| g |psi'> - 1/4 <psi| h |psi>,                     */
+/*      so Q_ab = sum_q w (g N_a' N_b' / 2 - h N_a N_b / 4).  The caller     */
+/*      samples g and h at the quadrature points.  Jumps of mu (the          */
+/*      heterostructure interfaces) contribute interface terms that this     */
+/*      form leaves out: with piecewise-constant mass g = h = 0.             */
+/* Any input sample array and any output may be NULL (NULL samples count as  */
+/* zero, NULL minv as 1).                                                    */
+/* ------------------------------------------------------------------------ */
+int orc_assemble_extra(const double *br, int nbr, int order, int nq, const double *minv_q,
+                       const double *eta_q, const double *g_q, const double *h_q,
+                       double *W, double *K, double *Q)
+{
+    if (check_breaks(br, nbr) != ORC_OK || order < 2 || order > 15 || nq < 1 || nq > 64)
+        return ORC_EINVAL;
+    int p = order - 1;
+    int N = orc_ndof(nbr, order);
+    if (N < 1) return ORC_EINVAL;
+    int nel = nbr - 1;
+    double *out[3] = {W, K, Q};
+    for (int m = 0; m < 3; ++m)
+        if (out[m]) memset(out[m], 0, sizeof(double) * (size_t)(p + 1) * N);
+    double *t = malloc(sizeof(double) * (nbr + 2 * p));
+    double *xq = malloc(sizeof(double) * nel * nq);
+    double *wq = malloc(sizeof(double) * nel * nq);
+    if (!t || !xq || !wq) { free(t); free(xq); free(wq); return ORC_ENOMEM; }
+    make_knots(br, nbr, order, t);
+    orc_quad_points(br, nbr, nq, xq, wq);
+    for (int e = 0; e < nel; ++e) {
+        int mu = p + e;
+        for (int q = 0; q < nq; ++q) {
+            int iq = e * nq + q;
+            double x = xq[iq], w = wq[iq];
+            double Nv[16], dN[16];
+            bspline_span_eval(t, order, mu, x, Nv, dN);
+            double minv = minv_q ? minv_q[iq] : 1.0;
+            double eta = eta_q ? eta_q[iq] : 0.0;
+            double g = g_q ? g_q[iq] : 0.0;
+            double h = h_q ? h_q[iq] : 0.0;
+            for (int a = 0; a <= p; ++a) {
+                int i = e + a - 1;
+                if (i < 0 || i >= N) continue;
+                for (int b = a; b <= p; ++b) {
+                    int j = e + b - 1;
+                    if (j < 0 || j >= N) continue;
+                    size_t at = (size_t)(b - a) * N + i;     /* entry (i, j), j >= i */
+                    if (W) W[at] += w * eta * Nv[a] * Nv[b];
+                    if (K) K[at] += w * minv * (Nv[a] * dN[b] - dN[a] * Nv[b]);
+                    if (Q) Q[at] += w * (0.5 * g * dN[a] * dN[b] - 0.25 * h * Nv[a] * Nv[b]);
+                }
+            }
+        }
+    }
+    free(t); free(xq); free(wq);
+    return ORC_OK;
+}
+
+/* y = K x for a real antisymmetric matrix given by its upper half band
+ * (K[j][i] = -K[i][j], zero diagonal). */
+static void antiband_mul_cplx(int N, int p, const double *K, const zd *x, zd *y)
+{
+    for (int i = 0; i < N; ++i) {
+        zd s = 0.0;
+        for (int d = 1; d <= p; ++d) {
+            if (i + d < N) s += K[(size_t)d * N + i] * x[i + d];
+            if (i - d >= 0) s -= K[(size_t)d * N + i - d] * x[i - d];
+        }
+        y[i] = s;
+    }
+}
+
+/* <v> = c^H Vel c with Vel = -(i/2) K (eq. vel_elem). */
+double orc_velocity(int N, int p, const double *K, const double *xin)
+{
+    const zd *x = (const zd *)xin;
+    zd *y = malloc(sizeof(zd) * N);
+    antiband_mul_cplx(N, p, K, x, y);
+    zd s = 0.0;
+    for (int i = 0; i < N; ++i) s += conj(x[i]) * y[i];
+    free(y);
+    return creal(-0.5 * I * s);
+}
+
+/* a[i][j] += s M[i][j] for a real symmetric half band M and a general
+ * complex band a (row-major, 2p+1 per row). */
+static void add_real_band(int N, int p, const double *M, double s, zd *a)
+{
+    int w = 2 * p + 1;
+    for (int i = 0; i < N; ++i)
+        for (int d = -p; d <= p; ++d) {
+            int j = i + d;
+            if (j < 0 || j >= N) continue;
+            int lo = i < j ? i : j, dd = d < 0 ? -d : d;
+            a[(size_t)i * w + d + p] += s * M[(size_t)dd * N + lo];
+        }
+}
+
+/* Number of columns of the extended series for npop projection states. */
+int orc_ext_columns(int npop) { return 10 + npop; }
+
+/* Crank-Nicolson propagation with an optional complex absorbing potential
+ * and the per-step time series of section V.D.  With the absorber,
+ *   H_n = H0 + Ebar_n D - i W,
+ *   (S + i a H_n) c_{n+1} = (S - i a H_n) c_n       (eq. cn_system),
+ * i.e. A_n = S + a W + i a (H0 + Ebar_n D), B_n = S - a W - i a (H0 + Ebar_n D),
+ * solved by the same banded LU (the real part S + a W of A_n is positive
+ * definite for W >= 0).  W may be NULL (no absorber).
+ * obs (may be NULL): [nsteps+1][3] as orc_propagate, with the a_Q term
+ *   c^H Q c added to the acceleration when Q is given.
+ * ext (may be NULL): [nsteps+1][10 + npop] (section V.D "energy",
+ *   "dipoles"/"currents", "autocorrelation", "populations"):
+ *   0 E_kin = c^H T c     1 E_pot = c^H V c     2 E_int = E_n c^H D c
+ *   3 E_tot = E_kin + E_pot + E_int              4 <m^-1> = c^H Mi c
+ *   5 <v> = c^H Vel c (K given, else 0)          6 a_Q = c^H Q c (else 0)
+ *   7 <W> = c^H W c (else 0)
+ *   8, 9 Re, Im of the autocorrelation c_0^H S c_n (M-weighted overlap)
+ *   10 + k |phi_k^T S c_n|^2, phi_k = row k of pop (npop x N, real)
+ * Expectation values are not divided by the norm. */
+int orc_propagate_ext(int N, int p, const double *S, const double *T, const double *V,
+                      const double *D, const double *G, const double *Mi, const double *W,
+                      const double *K, const double *Q, int npop, const double *pop,
+                      const double *psi0, const double *E, double dt, int nsteps,
+                      double *obs, double *ext, double *psi_out)
+{
+    if (N < 1 || p < 0 || nsteps < 0 || npop < 0 || !S || !T || !V || !D) return ORC_EINVAL;
+    int w = 2 * p + 1;
+    int nc = orc_ext_columns(npop);
+    double alpha = 0.5 * dt;
+    zd *c = malloc(sizeof(zd) * N), *b = malloc(sizeof(zd) * N), *c0 = malloc(sizeof(zd) * N);
+    zd *y = malloc(sizeof(zd) * N);
+    zd *A = malloc(sizeof(zd) * (size_t)N * w), *B = malloc(sizeof(zd) * (size_t)N * w);
+    double *H0 = malloc(sizeof(double) * (size_t)(p + 1) * N);
+    if (!c || !b || !c0 || !y || !A || !B || !H0) {
+        free(c); free(b); free(c0); free(y); free(A); free(B); free(H0);
+        return ORC_ENOMEM;
+    }
+    for (size_t i = 0; i < (size_t)(p + 1) * N; ++i) H0[i] = T[i] + V[i];
+    memcpy(c, psi0, sizeof(zd) * N);
+    memcpy(c0, psi0, sizeof(zd) * N);
+    int rc = ORC_OK;
+    for (int n = 0; n <= nsteps; ++n) {
+        const double *cd = (const double *)c;
+        if (obs || ext) {
+            double nu = orc_expect(N, p, S, cd), dip = orc_expect(N, p, D, cd);
+            double acc = 0.0, aq = Q ? orc_expect(N, p, Q, cd) : 0.0;
+            if (G) acc -= orc_expect(N, p, G, cd);
+            if (Mi) acc -= E[n] * orc_expect(N, p, Mi, cd);
+            acc += aq;
+            if (obs) {
+                obs[(size_t)n * 3 + 0] = nu;
+                obs[(size_t)n * 3 + 1] = dip;
+                obs[(size_t)n * 3 + 2] = acc;
+            }
+            if (ext) {
+                double *o = ext + (size_t)n * nc;
+                o[0] = orc_expect(N, p, T, cd);
+                o[1] = orc_expect(N, p, V, cd);
+                o[2] = E[n] * dip;
+                o[3] = o[0] + o[1] + o[2];
+                o[4] = Mi ? orc_expect(N, p, Mi, cd) : nu;
+                o[5] = K ? orc_velocity(N, p, K, cd) : 0.0;
+                o[6] = aq;
+                o[7] = W ? orc_expect(N, p, W, cd) : 0.0;
+                symband_mul_cplx(N, p, S, c, y);
+                zd ac = 0.0;
+                for (int i = 0; i < N; ++i) ac += conj(c0[i]) * y[i];
+                o[8] = creal(ac);
+                o[9] = cimag(ac);
+                for (int k = 0; k < npop; ++k) {
+                    zd s = 0.0;
+                    for (int i = 0; i < N; ++i) s += pop[(size_t)k * N + i] * y[i];
+                    o[10 + k] = creal(s) * creal(s) + cimag(s) * cimag(s);
+                }
+            }
+        }
+        if (n == nsteps) break;
+        double Eb = 0.5 * (E[n] + E[n + 1]);
+        build_cn(N, p, S, H0, D, Eb, alpha, -1.0, B);
+        build_cn(N, p, S, H0, D, Eb, alpha, +1.0, A);
+        if (W) {
+            add_real_band(N, p, W, -alpha, B);
+            add_real_band(N, p, W, +alpha, A);
+        }
+        zband_mul(N, p, B, c, b);
+        rc = zband_lu(N, p, A);
+        if (rc) break;
+        zband_lu_solve(N, p, A, b);
+        memcpy(c, b, sizeof(zd) * N);
+    }
+    if (!rc && psi_out) memcpy(psi_out, c, sizeof(zd) * N);
+    free(c); free(b); free(c0); free(y); free(A); free(B); free(H0);
+    return rc;
+}

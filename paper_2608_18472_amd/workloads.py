@@ -343,15 +343,16 @@ def config5(nsys=64, N=1500, nsteps=20000, ntheta=64, seed=1, wb_nm=4.0):
     return systems, np.array(thetas), basis
 
 
-def harmonic_yield(d, dt, omega, qmin=15, qmax=35):
+def harmonic_yield(d, dt, omega, qmin=15, qmax=35, beta=8.0):
     """J = sum over DFT frequencies w_q in [qmin w, qmax w] of w_q^4 |X(w_q)|^2,
-    X(w) = sum_n W_n d_n exp(i w t_n) dt with a Hann window W over the series
-    and the DFT grid zero-padded to 2^ceil(log2(4 (n+1))) points.  d: torch
-    tensor (any device, float64); differentiable."""
+    X(w) = sum_n W_n d_n exp(i w t_n) dt with the apodisation window of
+    section IV.A read as a Kaiser window (beta = 8, numpy's convention) over
+    the series, and the DFT grid zero-padded to 2^ceil(log2(4 (n+1)))
+    points.  d: torch tensor (any device, float64); differentiable."""
     import torch
     n1 = d.shape[-1]
     nfft = 1 << int(math.ceil(math.log2(4 * n1)))
-    win = torch.hann_window(n1, periodic=False, dtype=d.dtype, device=d.device)
+    win = torch.kaiser_window(n1, periodic=False, beta=beta, dtype=d.dtype, device=d.device)
     X = torch.fft.fft(win * d, n=nfft) * dt
     w = 2.0 * math.pi * torch.fft.fftfreq(nfft, d=dt, device=d.device).to(d.dtype)
     sel = (w >= qmin * omega) & (w <= qmax * omega)
@@ -374,3 +375,66 @@ def quesne(nel=8000, order=8, a=2.0, omega=1.0, xmax=50.0):
     minv = lambda x: 1.0 + x / a
     V = lambda x: 0.5 * a * omega * omega * x * x / (4.0 * (x + a))
     return System("quesne", np.linspace(-a, xmax, nel + 1), order, minv, V, _zeros, 10, const_mass=False)
+
+
+# --------------------------------------------------------------------------
+# Absorbing boundary layers and smooth position-dependent masses.
+# --------------------------------------------------------------------------
+MANOLOPOULOS_C = 2.62206
+
+
+def manolopoulos_cap(x1, L):
+    """Mask eta(x) of a Manolopoulos-type transmission-free absorber on the
+    layers x1 <= |x| < L (zero for |x| < x1), m = 1:
+        eta(x) = (1/2) (2 pi / delta)^2 f(y),  y = c (|x| - x1) / delta,
+        f(y) = 4/(c - y)^2 + 4/(c + y)^2 - 8/c^2,  c = 2.62206,
+    delta = L - x1.  f(0) = f'(0) = 0 (smooth onset); eta diverges at the box
+    edge |x| = L, where the Dirichlet basis functions vanish to order p, so
+    the CAP matrix stays finite."""
+    c = MANOLOPOULOS_C
+    delta = float(L - x1)
+    pref = 0.5 * (2.0 * math.pi / delta) ** 2
+
+    def eta(x):
+        ax = np.abs(np.asarray(x, dtype=float))
+        y = np.clip(c * (ax - x1) / delta, 0.0, c * (1.0 - 1e-14))
+        f = 4.0 / (c - y) ** 2 + 4.0 / (c + y) ** 2 - 8.0 / (c * c)
+        return np.where(ax > x1, pref * f, 0.0)
+    return eta
+
+
+def config1_cap(nsteps=None, width=50.0):
+    """Config 1 with absorbing layers of `width` bohr at both ends of the
+    [-200, 200] box (mask manolopoulos_cap(200 - width, 200))."""
+    sd = config1(nsteps)
+    sd.meta["eta"] = manolopoulos_cap(200.0 - width, 200.0)
+    sd.meta["cap_width"] = width
+    return sd
+
+
+def quesne_aq(a=2.0):
+    """Samples for the a_Q matrix of the Quesne mass m^-1 = 1 + x/a:
+    g = mu mu' = (1 + x/a)/a and h = mu' mu'' + mu mu''' = 0."""
+    return (lambda x: (1.0 + x / a) / a), (lambda x: np.zeros_like(x))
+
+
+def tanh_mass(b=0.3, s=2.0):
+    """Smooth position-dependent inverse mass mu(x) = 1 + b tanh(x/s) and the
+    a_Q samples g = mu mu', h = mu' mu'' + mu mu''' (closed-form derivatives
+    of tanh).  Returns (mu, dmu, g, h)."""
+    def mu(x):
+        return 1.0 + b * np.tanh(x / s)
+
+    def d1(x):
+        u = np.tanh(x / s)
+        return (b / s) * (1.0 - u * u)
+
+    def d2(x):
+        u = np.tanh(x / s)
+        return -(2.0 * b / s ** 2) * u * (1.0 - u * u)
+
+    def d3(x):
+        u = np.tanh(x / s)
+        return -(2.0 * b / s ** 3) * (1.0 - u * u) * (1.0 - 3.0 * u * u)
+
+    return mu, d1, (lambda x: mu(x) * d1(x)), (lambda x: d1(x) * d2(x) + mu(x) * d3(x))
