@@ -11,8 +11,10 @@
  *   (M + i dt/2 H^{n+1/2}) c^{n+1} = (M - i dt/2 H^{n+1/2}) c^n,
  *   H^{n+1/2} = (H^n + H^{n+1})/2                      (section V.B, eq. cn_system)
  * with the per-step observables of section IV.A: the M-norm, the dipole
- * d = c^H D c and the Ehrenfest acceleration a = -<m^-1 (dV/dx + E)>
- * (eq. pdm_acceleration without its a_Q term).  The mass matrix is called S
+ * d = c^H D c and the Ehrenfest acceleration a = -<m^-1 (dV/dx + E)> + a_Q
+ * (eq. pdm_acceleration), an optional complex absorbing potential
+ * (section V.A) and the extended time series of section V.D (energies,
+ * velocity, autocorrelation, populations).  The mass matrix is called S
  * here (the paper's M).
  *
  * Conventions for every entry point
@@ -75,15 +77,36 @@ typedef enum tdsez_precision { TDSEZ_FP64 = 0, TDSEZ_FP32_REFINED = 1 } tdsez_pr
  * columns are written as 0.
  *   nu_n = c_n^H S c_n                         (M-norm, section V.B)
  *   d_n  = Re c_n^H D c_n                      (dipole, section IV.A)
- *   a_n  = -Re c_n^H G c_n - E_n Re c_n^H Mi c_n,
- *          G = <B| m^-1 dV/dx |B>, Mi = <B| m^-1 |B>
- *                                              (eq. pdm_acceleration, no a_Q)
- * None of them is divided by nu_n. */
+ *   a_n  = -Re c_n^H G c_n - E_n Re c_n^H Mi c_n + c_n^H Q c_n,
+ *          G = <B| m^-1 dV/dx |B>, Mi = <B| m^-1 |B>, Q the a_Q form of
+ *          tdsez_set_aq                      (eq. pdm_acceleration)
+ * None of them is divided by nu_n.  For a system with a position-dependent
+ * mass, TDSEZ_OBS_ACCEL needs the a_Q form (tdsez_set_aq); without it the
+ * propagation calls return TDSEZ_EUNSUPPORTED. */
 enum { TDSEZ_OBS_NORM = 1, TDSEZ_OBS_DIPOLE = 2, TDSEZ_OBS_ACCEL = 4 };
 
-/* Band selectors for tdsez_get_band. */
+/* Extended per-step series (the time series the paper's section V.D writes
+ * every step), selected by TDSEZ_EXT_SERIES in the *_ext propagation calls:
+ * ext[n*ncols + k], ncols = 10 + npop (tdsez_ext_columns), n = 0..nsteps:
+ *   k = 0  E_kin = c^H T c              1  E_pot = c^H V c
+ *       2  E_int = E_n d_n              3  E_tot = E_kin + E_pot + E_int
+ *       4  <m^-1> = c^H Mi c            5  <v> = c^H Vel c (eq. vel_elem)
+ *       6  a_Q = c^H Q c (0 without tdsez_set_aq)
+ *       7  <W> = c^H W c (0 without an absorber; d nu/dt = -2 <W>)
+ *       8, 9  Re, Im of the autocorrelation c_0^H S c_n (M-weighted overlap
+ *             with the call's initial state)
+ *       10 + j  population |(S phi_j)^T c_n|^2 of projection state j
+ *               (tdsez_set_projectors)
+ * Expectation values are not divided by the norm.  Computed in FP64 from
+ * the FP64 bands in both precisions. */
+enum { TDSEZ_EXT_SERIES = 1 };
+
+/* Band selectors for tdsez_get_band.  TDSEZ_BAND_K is the real
+ * antisymmetric K with Vel = -(i/2) K (eq. vel_elem), returned as its upper
+ * half band K[i][i+d]; W and Q exist after tdsez_set_cap / tdsez_set_aq. */
 enum { TDSEZ_BAND_S = 0, TDSEZ_BAND_T = 1, TDSEZ_BAND_V = 2, TDSEZ_BAND_D = 3,
-       TDSEZ_BAND_G = 4, TDSEZ_BAND_MI = 5, TDSEZ_BAND_H0 = 6 };
+       TDSEZ_BAND_G = 4, TDSEZ_BAND_MI = 5, TDSEZ_BAND_H0 = 6, TDSEZ_BAND_K = 7,
+       TDSEZ_BAND_W = 8, TDSEZ_BAND_Q = 9 };
 
 typedef struct tdsez_system_s* tdsez_system; /* one assembled 1D problem */
 typedef struct tdsez_batch_s* tdsez_batch;   /* propagation plan for several systems */
@@ -118,6 +141,39 @@ tdsez_status tdsez_quad_points(const double* breaks, int nbreaks, int nq, double
 tdsez_status tdsez_assemble(const double* breaks, int nbreaks, int order, int nq,
                             const double* minv_q, const double* V_q, const double* dV_q,
                             tdsez_system* out);
+
+/* Complex absorbing potential (section V.A, CAP element formula: the CAP
+ * matrix is -i W with W_ab = sum_q w_q eta(x_q) N_a N_b).  eta_q: host
+ * samples of the mask eta >= 0 at the points of tdsez_quad_points of the
+ * system's breakpoints and nq (copied); NULL removes the absorber.  With an
+ * absorber H^{n+1/2} = H0 + Ebar_n D - i W in eq. cn_system, so
+ * A_n = S + (dt/2) W + i (dt/2)(H0 + Ebar_n D) stays complex symmetric with a
+ * positive definite real part and the same factorisation applies.  Affects
+ * batches created afterwards (and the one-system plan of tdsez_propagate).
+ * The adjoint refuses systems with an absorber (EUNSUPPORTED).  Synchronous.
+ * EINVAL for a negative or non-finite sample. */
+tdsez_status tdsez_set_cap(tdsez_system sys, const double* eta_q);
+
+/* The a_Q term of the acceleration (eq. pdm_acceleration, eq.
+ * aQ_definition) as a quadratic form.  For a smooth inverse mass mu = m^-1
+ * in one dimension, (i/4) <[p mu p, p mu + mu p]> equals
+ *   a_Q = 1/2 <psi'| g |psi'> - 1/4 <psi| h |psi>,
+ *   g = mu mu_1,  h = mu_1 mu_2 + mu mu_3   (mu_k: k-th derivative of mu),
+ * assembled as Q_ab = sum_q w_q (g N'_a N'_b / 2 - h N_a N_b / 4).  g_q, h_q:
+ * host samples at the quadrature points (either may be NULL for zero; both
+ * NULL removes the form).  Interface terms of a discontinuous mass are not
+ * part of this form (g = h = 0 inside layers of constant mass).  Affects
+ * batches created afterwards.  Synchronous. */
+tdsez_status tdsez_set_aq(tdsez_system sys, const double* g_q, const double* h_q);
+
+/* Projection states of the population series (section V.D
+ * "populations"): npop (0..8) real host vectors phi_j, phi + j*N, normally
+ * S-normalised eigenstates (tdsez_ground_state); the library stores S phi_j.
+ * npop = 0 removes them.  Affects batches created afterwards.  Synchronous. */
+tdsez_status tdsez_set_projectors(tdsez_system sys, int npop, const double* phi);
+
+/* Columns of the system's extended series: 10 + npop. */
+tdsez_status tdsez_ext_columns(tdsez_system sys, int* ncols);
 
 /* N (unknowns after Dirichlet removal) and half-bandwidth p. */
 tdsez_status tdsez_system_size(tdsez_system sys, int* ndof, int* halfbw);
@@ -162,7 +218,11 @@ tdsez_status tdsez_batch_create(const tdsez_system* sys, int nsys, tdsez_batch* 
 
 /* Tuning knobs of a batch.  key: "refine" (FP64-residual refinement sweeps
  * per step of TDSEZ_FP32_REFINED calls, integer 0..4, default 1; TDSEZ_FP64
- * calls run none), "norm_tol" (latch ENORMDRIFT
+ * calls run none), "refine_tol" (latch ENOCONV when the relative FP64
+ * residual ||r|| / sqrt(||S dx||^2 + ||a (W + i H) v||^2) entering the last
+ * refinement sweep of a step exceeds the value, r = B_n c_n - A_n c,
+ * dx = c - c_n, v = c + c_n, a = dt/2; default 1e-2; the propagation goes on,
+ * the first such step is reported by tdsez_batch_status), "norm_tol" (latch ENORMDRIFT
  * when |nu_n/nu_0 - 1| > value; 0 disables, default 0), "chunks" (force the
  * partition count of every system, 0 = plan, default 0), "profile" (1 turns
  * on per-phase cycle counters read by tdsez_batch_profile, 0 off). */
@@ -239,6 +299,17 @@ tdsez_status tdsez_propagate_batched(tdsez_batch b, double* psi_packed, const lo
                                      unsigned obs, double* obs_packed, const long* obs_off,
                                      void* stream);
 
+/* tdsez_propagate_batched with the extended per-step series: ext =
+ * TDSEZ_EXT_SERIES (or 0 for none); ext_packed (device, out): FP64, system s
+ * at ext_packed + ext_off[s] (host offsets, in doubles), (nsteps_s + 1) x
+ * (10 + npop_s) as described at TDSEZ_EXT_SERIES.  Asynchronous on `stream`;
+ * EINVAL for unknown bits or a NULL buffer with ext != 0. */
+tdsez_status tdsez_propagate_batched_ext(tdsez_batch b, double* psi_packed, const long* psi_off,
+                                         const double* E_packed, const long* E_off, const double* dt,
+                                         const int* nsteps, tdsez_precision prec, unsigned obs,
+                                         double* obs_packed, const long* obs_off, unsigned ext,
+                                         double* ext_packed, const long* ext_off, void* stream);
+
 /* Single-system convenience form of tdsez_propagate_batched (the library
  * keeps a one-system plan inside the system handle, created by the first
  * call).  The system runs on two waves when its two-wave plan has more than
@@ -247,6 +318,12 @@ tdsez_status tdsez_propagate_batched(tdsez_batch b, double* psi_packed, const lo
  * [(nsteps+1)*3] or NULL.  Asynchronous on `stream`. */
 tdsez_status tdsez_propagate(tdsez_system sys, double* psi, const double* E, double dt, int nsteps,
                              tdsez_precision prec, unsigned obs, double* obs_out, void* stream);
+
+/* tdsez_propagate with the extended series (ext_out: device FP64
+ * [(nsteps+1) * (10 + npop)], see TDSEZ_EXT_SERIES). */
+tdsez_status tdsez_propagate_ext(tdsez_system sys, double* psi, const double* E, double dt, int nsteps,
+                                 tdsez_precision prec, unsigned obs, double* obs_out, unsigned ext,
+                                 double* ext_out, void* stream);
 
 /* Gradient of a real function J of the observable series by the discrete
  * adjoint of the Crank-Nicolson recursion of section V.B (the paper gives no
@@ -327,13 +404,15 @@ tdsez_status tdsez_system2d_stats(tdsez_system2d s, long* steps, long* iteration
 void tdsez_system2d_destroy(tdsez_system2d s);
 
 /* Phase profile of the last propagation of a profiled batch (see
- * tdsez_batch_set "profile").  Synchronises `stream`; out[9*s + 0..8] =
+ * tdsez_batch_set "profile").  Synchronises `stream`; out[10*s + 0..9] =
  * average shader-clock cycles per time step spent by system s in: the
  * right-hand-side/observables pass, the elimination pass (TDSEZ_FP32_REFINED
  * runs both as one sweep, counted in the first column), the fill pass, the
  * separator (reduced) solve, the back substitution, and summed over the
  * refinement sweeps their residual pass, separator solve and back
- * substitution; then the partition count.  Profiling adds a barrier per
+ * substitution; then the partition count; out[10*s + 9] is the largest
+ * relative refinement residual of the run (see "refine_tol"; 0 for FP64
+ * calls).  Profiling adds a barrier per
  * phase.  EINVAL when profiling is off. */
 tdsez_status tdsez_batch_profile(tdsez_batch b, void* stream, double* out);
 

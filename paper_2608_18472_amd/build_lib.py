@@ -6,8 +6,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["tdsez_api.hip", "tdsez_assemble.hip", "tdsez_eigen.hip", "tdsez_propagate.hip", "tdsez_adjoint.hip",
-           "tdsez_2d.hip"]
+SOURCES = ["tdsez_api.hip", "tdsez_assemble.hip", "tdsez_eigen.hip", "tdsez_propagate.hip", "tdsez_prop_f32.hip",
+           "tdsez_prop_f64.hip", "tdsez_prop_xt32.hip", "tdsez_prop_xt64.hip", "tdsez_adjoint.hip", "tdsez_2d.hip"]
 LIB = os.path.join(HERE, "libtdsez.so")
 
 HIPCC_FLAGS = [
@@ -21,7 +21,7 @@ HIPCC_FLAGS = [
 ]
 
 
-def build(verbose=False, jobs=4):
+def build(verbose=False, jobs=8):
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)

@@ -62,6 +62,10 @@ static void free_batch_device(BatchData* b) {
     (void)hipFree(b->d_status);
     (void)hipFree(b->d_prof);
     b->d_prof = nullptr;
+    (void)hipFree(b->d_proj);
+    (void)hipFree(b->d_c0);
+    b->d_proj = nullptr;
+    b->d_c0 = nullptr;
     b->d_band64 = nullptr;
     b->d_band32 = nullptr;
     b->d_state = nullptr;
@@ -156,15 +160,22 @@ tdsez_status tdsez_get_band(tdsez_system sys, int which, double* host_out) {
     if (!sys || !host_out) return fail(TDSEZ_EINVAL, "NULL argument");
     const int N = sys->d.N, p = sys->d.p;
     const double* src = nullptr;
+    double sign = 1.0;
     if (which >= TDSEZ_BAND_S && which <= TDSEZ_BAND_MI) src = sys->d.d_band[which];
     else if (which == TDSEZ_BAND_H0) src = sys->d.d_H0;
+    else if (which == TDSEZ_BAND_K) {
+        src = sys->d.d_K;
+        sign = -1.0;  // antisymmetric: K[i][i+d] = -K[i+d][i]
+    } else if (which == TDSEZ_BAND_W) src = sys->d.d_W;
+    else if (which == TDSEZ_BAND_Q) src = sys->d.d_Q;
     else return fail(TDSEZ_EINVAL, "unknown band selector %d", which);
+    if (!src) return fail(TDSEZ_EINVAL, "band %d is not set for this system", which);
     std::vector<double> rows((size_t)N * (p + 1));
     TDSEZ_HIP_TRY(hipMemcpy(rows.data(), src, sizeof(double) * rows.size(), hipMemcpyDeviceToHost));
     // rows[j*(p+1)+d] = M[j][j-d]  ->  band[d*N + i] = M[i][i+d] = M[i+d][i]
     for (int d = 0; d <= p; ++d)
         for (int i = 0; i < N; ++i)
-            host_out[(size_t)d * N + i] = (i + d < N) ? rows[(size_t)(i + d) * (p + 1) + d] : 0.0;
+            host_out[(size_t)d * N + i] = (i + d < N) ? sign * rows[(size_t)(i + d) * (p + 1) + d] : 0.0;
     return TDSEZ_OK;
 }
 
@@ -212,6 +223,11 @@ tdsez_status tdsez_batch_set(tdsez_batch b, const char* key, double value) {
         b->d.refine = (int)value;
         return TDSEZ_OK;
     }
+    if (!std::strcmp(key, "refine_tol")) {
+        if (!(value >= 0.0) || std::isnan(value)) return fail(TDSEZ_EINVAL, "refine_tol must be >= 0");
+        b->d.refine_tol = value;
+        return TDSEZ_OK;
+    }
     if (!std::strcmp(key, "norm_tol")) {
         if (!(value >= 0.0)) return fail(TDSEZ_EINVAL, "norm_tol must be >= 0");
         b->d.norm_tol = value;
@@ -219,7 +235,7 @@ tdsez_status tdsez_batch_set(tdsez_batch b, const char* key, double value) {
     }
     if (!std::strcmp(key, "profile")) {
         if (value != 0.0 && !b->d.d_prof) {
-            size_t bytes = sizeof(unsigned long long) * 9 * b->d.sys.size();
+            size_t bytes = sizeof(unsigned long long) * kProfSlots * b->d.sys.size();
             TDSEZ_HIP_TRY(hipMalloc(&b->d.d_prof, bytes));
             TDSEZ_HIP_TRY(hipMemset(b->d.d_prof, 0, bytes));
         } else if (value == 0.0 && b->d.d_prof) {
@@ -245,8 +261,19 @@ tdsez_status tdsez_propagate_batched(tdsez_batch b, double* psi_packed, const lo
                                      const double* E_packed, const long* E_off, const double* dt,
                                      const int* nsteps, tdsez_precision prec, unsigned obs,
                                      double* obs_packed, const long* obs_off, void* stream) {
+    return tdsez_propagate_batched_ext(b, psi_packed, psi_off, E_packed, E_off, dt, nsteps, prec, obs, obs_packed,
+                                       obs_off, 0u, nullptr, nullptr, stream);
+}
+
+tdsez_status tdsez_propagate_batched_ext(tdsez_batch b, double* psi_packed, const long* psi_off,
+                                         const double* E_packed, const long* E_off, const double* dt,
+                                         const int* nsteps, tdsez_precision prec, unsigned obs,
+                                         double* obs_packed, const long* obs_off, unsigned ext,
+                                         double* ext_packed, const long* ext_off, void* stream) {
     if (!b || !psi_packed || !psi_off || !E_packed || !E_off || !dt || !nsteps)
         return fail(TDSEZ_EINVAL, "NULL argument");
+    if (ext & ~(unsigned)TDSEZ_EXT_SERIES) return fail(TDSEZ_EINVAL, "unknown extended-series bits 0x%x", ext);
+    if (ext && (!ext_packed || !ext_off)) return fail(TDSEZ_EINVAL, "extended series requested but buffer is NULL");
     if (prec != TDSEZ_FP64 && prec != TDSEZ_FP32_REFINED)
         return fail(TDSEZ_EINVAL, "unknown precision %d", (int)prec);
     if (obs & ~7u) return fail(TDSEZ_EINVAL, "unknown observable bits 0x%x", obs);
@@ -256,17 +283,24 @@ tdsez_status tdsez_propagate_batched(tdsez_batch b, double* psi_packed, const lo
     for (int s = 0; s < nsys; ++s) {
         if (!(dt[s] > 0.0) || !std::isfinite(dt[s])) return fail(TDSEZ_EINVAL, "dt[%d] must be > 0", s);
         if (nsteps[s] < 0) return fail(TDSEZ_EINVAL, "nsteps[%d] < 0", s);
-        if (psi_off[s] < 0 || E_off[s] < 0 || (obs && obs_off[s] < 0))
+        if (psi_off[s] < 0 || E_off[s] < 0 || (obs && obs_off[s] < 0) || (ext && ext_off[s] < 0))
             return fail(TDSEZ_EINVAL, "negative offset for system %d", s);
+        // eq. pdm_acceleration: with a position-dependent mass the
+        // acceleration needs the a_Q term (tdsez_set_aq)
+        if ((obs & TDSEZ_OBS_ACCEL) && !d->sys[s]->const_mass && !d->sys[s]->d_Q)
+            return fail(TDSEZ_EUNSUPPORTED,
+                        "system %d has a position-dependent mass: the acceleration needs its a_Q term "
+                        "(tdsez_set_aq before tdsez_batch_create)", s);
         SysDesc& sd = d->desc[s];
         sd.nsteps = nsteps[s];
         sd.dt = dt[s];
         sd.psi_off = psi_off[s];
         sd.E_off = E_off[s];
         sd.obs_off = obs ? obs_off[s] : 0;
+        sd.ext_off = ext ? ext_off[s] : 0;
     }
     return launch_propagate(d, psi_packed, E_packed, obs ? obs_packed : nullptr, prec, obs,
-                            (hipStream_t)stream);
+                            (hipStream_t)stream, false, ext ? ext_packed : nullptr);
 }
 
 tdsez_status tdsez_adjoint_batched(tdsez_batch b, const double* psi0_packed, const long* psi_off,
@@ -279,6 +313,12 @@ tdsez_status tdsez_adjoint_batched(tdsez_batch b, const double* psi0_packed, con
         return fail(TDSEZ_EINVAL, "NULL argument");
     if (b->d.nsplit > 0)
         return fail(TDSEZ_EUNSUPPORTED, "the adjoint runs one wave per system; clear tdsez_batch_split first");
+    if (b->d.any_cap)
+        return fail(TDSEZ_EUNSUPPORTED, "the adjoint does not support an absorbing potential");
+    for (size_t s = 0; s < b->d.sys.size(); ++s)
+        if ((obs & TDSEZ_OBS_ACCEL) && !b->d.sys[s]->const_mass)
+            return fail(TDSEZ_EUNSUPPORTED, "adjoint of the acceleration with a position-dependent mass (system %zu)",
+                        s);
     if (prec == TDSEZ_FP32_REFINED)
         return fail(TDSEZ_EUNSUPPORTED, "the adjoint runs in FP64 only (use TDSEZ_FP64)");
     if (prec != TDSEZ_FP64) return fail(TDSEZ_EINVAL, "unknown precision %d", (int)prec);
@@ -304,6 +344,12 @@ tdsez_status tdsez_adjoint_batched(tdsez_batch b, const double* psi0_packed, con
 
 tdsez_status tdsez_propagate(tdsez_system sys, double* psi, const double* E, double dt, int nsteps,
                              tdsez_precision prec, unsigned obs, double* obs_out, void* stream) {
+    return tdsez_propagate_ext(sys, psi, E, dt, nsteps, prec, obs, obs_out, 0u, nullptr, stream);
+}
+
+tdsez_status tdsez_propagate_ext(tdsez_system sys, double* psi, const double* E, double dt, int nsteps,
+                                 tdsez_precision prec, unsigned obs, double* obs_out, unsigned ext,
+                                 double* ext_out, void* stream) {
     if (!sys) return fail(TDSEZ_EINVAL, "sys is NULL");
     if (!sys->d.solo) {
         tdsez_system one = sys;
@@ -315,8 +361,68 @@ tdsez_status tdsez_propagate(tdsez_system sys, double* psi, const double* E, dou
         if ((st = tdsez_batch_split(sys->d.solo, &nsteps_one, 1)) != TDSEZ_OK) return st;
     }
     long zero = 0;
-    return tdsez_propagate_batched(sys->d.solo, psi, &zero, E, &zero, &dt, &nsteps, prec, obs, obs_out,
-                                   &zero, stream);
+    return tdsez_propagate_batched_ext(sys->d.solo, psi, &zero, E, &zero, &dt, &nsteps, prec, obs, obs_out, &zero,
+                                       ext, ext_out, &zero, stream);
+}
+
+// Drop the one-system plan (it packs the bands, so it is rebuilt after a
+// band of the system changes).
+static void drop_solo(tdsez_system sys) {
+    if (sys->d.solo) {
+        tdsez_batch_destroy(sys->d.solo);
+        sys->d.solo = nullptr;
+    }
+}
+
+static tdsez_status check_samples(const double* a, size_t n, const char* what) {
+    if (!a) return TDSEZ_OK;
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(a[i])) return fail(TDSEZ_EINVAL, "non-finite %s sample %zu", what, i);
+    return TDSEZ_OK;
+}
+
+tdsez_status tdsez_set_cap(tdsez_system sys, const double* eta_q) {
+    if (!sys) return fail(TDSEZ_EINVAL, "sys is NULL");
+    const size_t nqt = (size_t)(sys->d.nbreaks - 1) * sys->d.nq;
+    drop_solo(sys);
+    if (!eta_q) {
+        (void)hipFree(sys->d.d_W);
+        sys->d.d_W = nullptr;
+        return TDSEZ_OK;
+    }
+    if (tdsez_status st = check_samples(eta_q, nqt, "eta")) return st;
+    for (size_t i = 0; i < nqt; ++i)
+        if (eta_q[i] < 0.0) return fail(TDSEZ_EINVAL, "the absorber mask must be >= 0 (sample %zu)", i);
+    return assemble_extra_device(&sys->d, 0, eta_q, nullptr);
+}
+
+tdsez_status tdsez_set_aq(tdsez_system sys, const double* g_q, const double* h_q) {
+    if (!sys) return fail(TDSEZ_EINVAL, "sys is NULL");
+    const size_t nqt = (size_t)(sys->d.nbreaks - 1) * sys->d.nq;
+    drop_solo(sys);
+    if (!g_q && !h_q) {
+        (void)hipFree(sys->d.d_Q);
+        sys->d.d_Q = nullptr;
+        return TDSEZ_OK;
+    }
+    if (tdsez_status st = check_samples(g_q, nqt, "g")) return st;
+    if (tdsez_status st = check_samples(h_q, nqt, "h")) return st;
+    return assemble_extra_device(&sys->d, 1, g_q, h_q);
+}
+
+tdsez_status tdsez_set_projectors(tdsez_system sys, int npop, const double* phi) {
+    if (!sys) return fail(TDSEZ_EINVAL, "sys is NULL");
+    if (npop < 0 || npop > kMaxPop) return fail(TDSEZ_EINVAL, "npop must be in 0..%d", kMaxPop);
+    if (npop > 0 && !phi) return fail(TDSEZ_EINVAL, "phi is NULL");
+    if (tdsez_status st = check_samples(phi, (size_t)npop * sys->d.N, "projection state")) return st;
+    drop_solo(sys);
+    return set_projectors_device(&sys->d, npop, phi);
+}
+
+tdsez_status tdsez_ext_columns(tdsez_system sys, int* ncols) {
+    if (!sys || !ncols) return fail(TDSEZ_EINVAL, "NULL argument");
+    *ncols = kExtFixed + sys->d.npop;
+    return TDSEZ_OK;
 }
 
 // Partition autotuner.  The chunk count P of a system trades the lane-serial
@@ -388,7 +494,7 @@ tdsez_status tdsez_autotune(tdsez_batch b, tdsez_precision prec, double budget_m
     d->force_chunks = 0;
     std::vector<double> best_cyc(nsys, INFINITY);
     std::vector<int> best_P(nsys, 0);
-    std::vector<double> prof(9 * (size_t)nsys);
+    std::vector<double> prof(kProfSlots * (size_t)nsys);
     tdsez_status st = TDSEZ_OK;
     for (int t = 0; t < kTrials && st == TDSEZ_OK; ++t) {
         if (t > 0 && elapsed_ms() > budget_ms) break;
@@ -424,7 +530,7 @@ tdsez_status tdsez_autotune(tdsez_batch b, tdsez_precision prec, double budget_m
         if ((st = tdsez_batch_profile(b, nullptr, prof.data())) != TDSEZ_OK) break;
         for (int s = 0; s < nsys; ++s) {
             double cyc = 0.0;
-            for (int k = 0; k < 8; ++k) cyc += prof[9 * (size_t)s + k];
+            for (int k = 0; k < 8; ++k) cyc += prof[kProfSlots * (size_t)s + k];
             if (cyc < best_cyc[s]) {
                 best_cyc[s] = cyc;
                 best_P[s] = d->plan[s].P;
@@ -457,12 +563,16 @@ tdsez_status tdsez_batch_profile(tdsez_batch b, void* stream, double* out) {
     if (!b->d.d_prof) return fail(TDSEZ_EINVAL, "profiling is off (tdsez_batch_set(b, \"profile\", 1))");
     TDSEZ_HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
     const size_t n = b->d.sys.size();
-    std::vector<unsigned long long> h(9 * n);
-    TDSEZ_HIP_TRY(hipMemcpy(h.data(), b->d.d_prof, sizeof(unsigned long long) * 9 * n, hipMemcpyDeviceToHost));
+    constexpr int K = kProfSlots;
+    std::vector<unsigned long long> h(K * n);
+    TDSEZ_HIP_TRY(hipMemcpy(h.data(), b->d.d_prof, sizeof(unsigned long long) * K * n, hipMemcpyDeviceToHost));
     for (size_t s = 0; s < n; ++s) {
-        double ns = h[9 * s + 8] > 0 ? (double)h[9 * s + 8] : 1.0;
-        for (int k = 0; k < 8; ++k) out[9 * s + k] = (double)h[9 * s + k] / ns;
-        out[9 * s + 8] = (double)b->d.plan[s].P;
+        double ns = h[K * s + 8] > 0 ? (double)h[K * s + 8] : 1.0;
+        for (int k = 0; k < 8; ++k) out[K * s + k] = (double)h[K * s + k] / ns;
+        out[K * s + 8] = (double)b->d.plan[s].P;
+        double worst;
+        std::memcpy(&worst, &h[K * s + 9], sizeof(double));
+        out[K * s + 9] = worst;
     }
     return TDSEZ_OK;
 }
@@ -477,6 +587,8 @@ tdsez_status tdsez_batch_status(tdsez_batch b, void* stream, int* sys_out, int* 
     if (step_out) *step_out = h[2];
     if (h[0] == TDSEZ_ENONFINITE) return fail(TDSEZ_ENONFINITE, "non-finite state in system %d at step %d", h[1], h[2]);
     if (h[0] == TDSEZ_ENORMDRIFT) return fail(TDSEZ_ENORMDRIFT, "norm drift beyond tolerance in system %d at step %d", h[1], h[2]);
+    if (h[0] == TDSEZ_ENOCONV)
+        return fail(TDSEZ_ENOCONV, "refinement residual above refine_tol in system %d (first at step %d)", h[1], h[2]);
     if (h[0] != 0) return fail((tdsez_status)h[0], "device error %d in system %d at step %d", h[0], h[1], h[2]);
     return TDSEZ_OK;
 }
@@ -531,6 +643,10 @@ void tdsez_system_destroy(tdsez_system sys) {
     if (sys->d.solo) tdsez_batch_destroy(sys->d.solo);
     for (int m = 0; m < 6; ++m) (void)hipFree(sys->d.d_band[m]);
     (void)hipFree(sys->d.d_H0);
+    (void)hipFree(sys->d.d_K);
+    (void)hipFree(sys->d.d_W);
+    (void)hipFree(sys->d.d_Q);
+    (void)hipFree(sys->d.d_pops);
     delete sys;
 }
 

@@ -126,11 +126,11 @@ __global__ void band_kernel(const double* __restrict__ br, int nbr, int p, int n
                             const double* __restrict__ dV_q, double* __restrict__ S,
                             double* __restrict__ T, double* __restrict__ V, double* __restrict__ D,
                             double* __restrict__ G, double* __restrict__ Mi,
-                            double* __restrict__ H0) {
+                            double* __restrict__ H0, double* __restrict__ K) {
     int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= N * (p + 1)) return;
     int j = idx / (p + 1), d = idx % (p + 1);
-    double s = 0.0, t = 0.0, v = 0.0, dd = 0.0, g = 0.0, mi = 0.0;
+    double s = 0.0, t = 0.0, v = 0.0, dd = 0.0, g = 0.0, mi = 0.0, kv = 0.0;
     if (j - d >= 0) {
         int nel = nbr - 1;
         int g1 = j + 1, g2 = j + 1 - d;  // g1 >= g2
@@ -150,6 +150,9 @@ __global__ void band_kernel(const double* __restrict__ br, int nbr, int p, int n
                 dd += nn * xq[iq];
                 g += nn * mv * (dV_q ? dV_q[iq] : 0.0);
                 mi += nn * mv;
+                // velocity (eq. vel_elem without its -i/2): row j, column j-d
+                kv += w * mv * (Bv[iq * (p + 1) + a1] * dB[iq * (p + 1) + a2] -
+                                dB[iq * (p + 1) + a1] * Bv[iq * (p + 1) + a2]);
             }
         }
     }
@@ -160,6 +163,61 @@ __global__ void band_kernel(const double* __restrict__ br, int nbr, int p, int n
     G[idx] = g;
     Mi[idx] = mi;
     H0[idx] = t + v;
+    K[idx] = kv;
+}
+
+// Absorber weight W[j][j-d] = sum w eta N_j N_{j-d} (the CAP matrix of
+// section V.A is -i W) when aq_form is false, or the a_Q form
+// Q[j][j-d] = sum w (g N'_j N'_{j-d} / 2 - h N_j N_{j-d} / 4) with g = a_q,
+// h = b_q: eq. aQ_definition expanded for a smooth inverse mass mu, with
+// g = mu mu_1 and h = mu_1 mu_2 + mu mu_3 (mu_k the k-th derivative of mu).
+// Same summation order as band_kernel.
+__global__ void extra_band_kernel(const double* __restrict__ br, int nbr, int p, int nq, int N,
+                                  const double* __restrict__ gw, const double* __restrict__ Bv,
+                                  const double* __restrict__ dB, const double* __restrict__ a_q,
+                                  const double* __restrict__ b_q, bool aq_form, double* __restrict__ out) {
+    int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= N * (p + 1)) return;
+    int j = idx / (p + 1), d = idx % (p + 1);
+    double acc = 0.0;
+    if (j - d >= 0) {
+        int nel = nbr - 1;
+        int g1 = j + 1, g2 = j + 1 - d;
+        int e0 = g1 - p > 0 ? g1 - p : 0;
+        int e1 = g2 < nel - 1 ? g2 : nel - 1;
+        for (int e = e0; e <= e1; ++e) {
+            int a1 = g1 - e, a2 = g2 - e;
+            double h = 0.5 * (br[e + 1] - br[e]);
+            for (int q = 0; q < nq; ++q) {
+                size_t iq = (size_t)e * nq + q;
+                double w = gw[q] * h;
+                double nn = w * Bv[iq * (p + 1) + a1] * Bv[iq * (p + 1) + a2];
+                if (aq_form) {
+                    double gg = a_q ? a_q[iq] : 0.0, hh = b_q ? b_q[iq] : 0.0;
+                    acc += 0.5 * w * gg * dB[iq * (p + 1) + a1] * dB[iq * (p + 1) + a2] - 0.25 * hh * nn;
+                } else {
+                    acc += nn * (a_q ? a_q[iq] : 0.0);
+                }
+            }
+        }
+    }
+    out[idx] = acc;
+}
+
+// y = M x for the FP64 symmetric band M (lower rows M[j][j-d]) and nv real
+// vectors x (natural order), one thread per output entry.
+__global__ void symband_real_kernel(const double* __restrict__ M, int N, int p, int nv,
+                                    const double* __restrict__ x, double* __restrict__ y) {
+    long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (idx >= (long long)N * nv) return;
+    int v = (int)(idx / N), i = (int)(idx % N);
+    const double* xv = x + (size_t)v * N;
+    double s = 0.0;
+    for (int d = 0; d <= p; ++d) {
+        if (i - d >= 0) s += M[(size_t)i * (p + 1) + d] * xv[i - d];
+        if (d > 0 && i + d < N) s += M[(size_t)(i + d) * (p + 1) + d] * xv[i + d];
+    }
+    y[idx] = s;
 }
 
 tdsez_status assemble_device(const double* breaks, int nbreaks, int order, int nq,
@@ -213,6 +271,7 @@ tdsez_status assemble_device(const double* breaks, int nbreaks, int order, int n
     }
     for (int m = 0; m < 6; ++m) ASM_TRY(hipMalloc(&sys->d_band[m], sizeof(double) * bw));
     ASM_TRY(hipMalloc(&sys->d_H0, sizeof(double) * bw));
+    ASM_TRY(hipMalloc(&sys->d_K, sizeof(double) * bw));
     {
         int th = 128;
         int nb = (int)((nqt + th - 1) / th);
@@ -221,7 +280,7 @@ tdsez_status assemble_device(const double* breaks, int nbreaks, int order, int n
         nb = (int)((bw + th - 1) / th);
         band_kernel<<<nb, th>>>(d_br, nbreaks, p, nq, N, d_gw, d_xq, d_Bv, d_dB, d_minv, d_V, d_dV,
                                 sys->d_band[0], sys->d_band[1], sys->d_band[2], sys->d_band[3],
-                                sys->d_band[4], sys->d_band[5], sys->d_H0);
+                                sys->d_band[4], sys->d_band[5], sys->d_H0, sys->d_K);
         ASM_TRY(hipGetLastError());
         ASM_TRY(hipDeviceSynchronize());
     }
@@ -246,4 +305,95 @@ tdsez_status assemble_device(const double* breaks, int nbreaks, int order, int n
     return st;
 }
 
+tdsez_status assemble_extra_device(SystemData* sys, int which, const double* a_q, const double* b_q) {
+    const int p = sys->p, nq = sys->nq, nbreaks = sys->nbreaks, nel = nbreaks - 1, N = sys->N;
+    const size_t nqt = (size_t)nel * nq, bw = (size_t)N * (p + 1);
+    double gx[32], gw[32];
+    gauss_legendre_host(nq, gx, gw);
+    std::vector<double> xq(nqt);
+    for (int e = 0; e < nel; ++e) {
+        double h = 0.5 * (sys->breaks[e + 1] - sys->breaks[e]), c = 0.5 * (sys->breaks[e + 1] + sys->breaks[e]);
+        for (int q = 0; q < nq; ++q) xq[(size_t)e * nq + q] = c + h * gx[q];
+    }
+    double *d_br = nullptr, *d_gw = nullptr, *d_xq = nullptr, *d_Bv = nullptr, *d_dB = nullptr;
+    double *d_a = nullptr, *d_b = nullptr, *d_out = nullptr;
+    auto cleanup = [&]() {
+        (void)hipFree(d_br); (void)hipFree(d_gw); (void)hipFree(d_xq); (void)hipFree(d_Bv);
+        (void)hipFree(d_dB); (void)hipFree(d_a); (void)hipFree(d_b); (void)hipFree(d_out);
+    };
+#define XT_TRY(expr)                                                                    \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess) {                                                         \
+            cleanup();                                                                  \
+            return fail(TDSEZ_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_));    \
+        }                                                                               \
+    } while (0)
+    XT_TRY(hipMalloc(&d_br, sizeof(double) * nbreaks));
+    XT_TRY(hipMalloc(&d_gw, sizeof(double) * nq));
+    XT_TRY(hipMalloc(&d_xq, sizeof(double) * nqt));
+    XT_TRY(hipMalloc(&d_Bv, sizeof(double) * nqt * (p + 1)));
+    XT_TRY(hipMalloc(&d_dB, sizeof(double) * nqt * (p + 1)));
+    XT_TRY(hipMalloc(&d_out, sizeof(double) * bw));
+    XT_TRY(hipMemcpy(d_br, sys->breaks.data(), sizeof(double) * nbreaks, hipMemcpyHostToDevice));
+    XT_TRY(hipMemcpy(d_gw, gw, sizeof(double) * nq, hipMemcpyHostToDevice));
+    XT_TRY(hipMemcpy(d_xq, xq.data(), sizeof(double) * nqt, hipMemcpyHostToDevice));
+    if (a_q) {
+        XT_TRY(hipMalloc(&d_a, sizeof(double) * nqt));
+        XT_TRY(hipMemcpy(d_a, a_q, sizeof(double) * nqt, hipMemcpyHostToDevice));
+    }
+    if (b_q) {
+        XT_TRY(hipMalloc(&d_b, sizeof(double) * nqt));
+        XT_TRY(hipMemcpy(d_b, b_q, sizeof(double) * nqt, hipMemcpyHostToDevice));
+    }
+    {
+        int th = 128;
+        int nb = (int)((nqt + th - 1) / th);
+        basis_kernel<<<nb, th>>>(d_br, nbreaks, p, nq, d_xq, d_Bv, d_dB);
+        XT_TRY(hipGetLastError());
+        nb = (int)((bw + th - 1) / th);
+        extra_band_kernel<<<nb, th>>>(d_br, nbreaks, p, nq, N, d_gw, d_Bv, d_dB, d_a, d_b, which == 1, d_out);
+        XT_TRY(hipGetLastError());
+        XT_TRY(hipDeviceSynchronize());
+    }
+#undef XT_TRY
+    double*& slot = which == 1 ? sys->d_Q : sys->d_W;
+    (void)hipFree(slot);
+    slot = d_out;
+    d_out = nullptr;
+    cleanup();
+    return TDSEZ_OK;
+}
+
+tdsez_status set_projectors_device(SystemData* sys, int npop, const double* phi) {
+    const int N = sys->N, p = sys->p;
+    (void)hipFree(sys->d_pops);
+    sys->d_pops = nullptr;
+    sys->npop = 0;
+    if (npop == 0) return TDSEZ_OK;
+    double* d_phi = nullptr;
+    double* d_out = nullptr;
+    const size_t n = (size_t)npop * N;
+    if (hipMalloc(&d_phi, sizeof(double) * n) != hipSuccess || hipMalloc(&d_out, sizeof(double) * n) != hipSuccess) {
+        (void)hipFree(d_phi);
+        (void)hipFree(d_out);
+        return fail(TDSEZ_ENOMEM, "projection states: device allocation failed");
+    }
+    hipError_t e = hipMemcpy(d_phi, phi, sizeof(double) * n, hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+        symband_real_kernel<<<(int)((n + 127) / 128), 128>>>(sys->d_band[0], N, p, npop, d_phi, d_out);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    (void)hipFree(d_phi);
+    if (e != hipSuccess) {
+        (void)hipFree(d_out);
+        return fail(TDSEZ_EHIP, "projection states: %s", hipGetErrorString(e));
+    }
+    sys->d_pops = d_out;
+    sys->npop = npop;
+    return TDSEZ_OK;
+}
+
 }  // namespace tdsez
+

@@ -21,8 +21,16 @@ constexpr int kWave = 64;
 constexpr int kMaxChunks = 64;
 // Largest partition count of a system run on two waves (tdsez_batch_split).
 constexpr int kMaxChunks2 = 2 * kWave;
-// Matrices stored per band row in the propagation layout: S, H0, D, G, Mi.
-constexpr int kNumMats = 5;
+// Matrices stored per band row in the propagation layout, in this order:
+// S, H0, D, G, Mi (propagation and the three main observables), W (weight of
+// the complex absorbing potential), V, K (velocity), Q (a_Q form) for the
+// extended per-step series.
+constexpr int kNumMats = 9;
+enum { kMatS = 0, kMatH0 = 1, kMatD = 2, kMatG = 3, kMatMi = 4, kMatW = 5, kMatV = 6, kMatK = 7, kMatQ = 8 };
+// Largest number of projection states of the population series.
+constexpr int kMaxPop = 8;
+// Columns of the extended series before the populations.
+constexpr int kExtFixed = 10;
 
 // ---------------------------------------------------------------- errors
 void set_error(const char* fmt, ...);
@@ -80,6 +88,11 @@ struct SystemData {
     double minV = 0.0;               // min_q V(x_q), for the default eigen shift
     double* d_band[6] = {nullptr};   // S, T, V, D, G, Mi
     double* d_H0 = nullptr;          // T + V
+    double* d_K = nullptr;           // velocity: K[j][j-d] (real antisymmetric part of eq. vel_elem)
+    double* d_W = nullptr;           // absorbing-potential weight (nullptr: no absorber)
+    double* d_Q = nullptr;           // a_Q form (nullptr: not given)
+    int npop = 0;                    // projection states of the population series
+    double* d_pops = nullptr;        // S phi_k, npop x N, natural order
     tdsez_batch solo = nullptr;      // one-system plan for tdsez_propagate
 };
 
@@ -104,6 +117,11 @@ struct SysDesc {
     long long obs_off;    // doubles into the caller's obs buffer
     // adjoint only: checkpoint stride and number of segments
     int ck, nseg;
+    int cap;              // 1: absorbing potential present (W band)
+    int aq;               // 1: a_Q form present (Q band)
+    int npop;             // projection states
+    long long proj_off;   // doubles into the packed projection states
+    long long ext_off;    // doubles into the caller's extended-series buffer
 };
 
 struct BatchData {
@@ -112,6 +130,7 @@ struct BatchData {
     std::vector<SysDesc> desc;       // host copy, offsets of the internal buffers
     int maxp = 0;
     int refine = 1;                  // refinement sweeps of TDSEZ_FP32_REFINED calls
+    double refine_tol = 1e-2;        // ENOCONV when the last sweep's relative residual exceeds it
     double norm_tol = 0.0;
     int force_chunks = 0;
     long long band_elems = 0, state_elems = 0, fac_elems64 = 0, red_elems64 = 0;
@@ -139,15 +158,58 @@ struct BatchData {
     hipStream_t side = nullptr;      // second stream for the two-wave launch (default priority)
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     int* d_status = nullptr;         // [0] code, [1] system, [2] step
-    unsigned long long* d_prof = nullptr;  // optional phase cycle counters, 9 per system
+    unsigned long long* d_prof = nullptr;  // optional phase cycle counters, kProfSlots per system
+    double* d_proj = nullptr;        // packed projection states S phi_k (interleaved layout)
+    double* d_c0 = nullptr;          // initial states of the call (state layout), for the autocorrelation
+    bool any_cap = false, any_aq = false;
     int nsys_alloc_desc = 0;
 };
 
+// Arguments of the persistent propagation kernels.
+struct KernelArgs {
+    const SysDesc* descs;
+    const int* order;          // workgroup -> system index (longest first)
+    int order_off;             // first entry of order read by this launch
+    const void* band;          // FT bands (factorisation, solve, right-hand side)
+    const double* band64;      // FP64 bands (S of the refinement residual)
+    double* st;
+    double* dtot;              // increment of the current step (refinement only)
+    void* rhs;                 // right-hand side of the step (FT, state layout)
+    void* fac;
+    void* red;
+    const double* E;
+    double* obs;
+    unsigned mask;
+    int refine;
+    double norm_tol;
+    int* status;
+    unsigned long long* prof;
+    double refine_tol;         // ENOCONV threshold of the last sweep's relative residual
+    // extended kernels only
+    const double* c0;          // initial states (state layout), or nullptr: no autocorrelation
+    const double* proj;        // packed projection states S phi_k
+    double* ext;               // extended series (caller's buffer), or nullptr
+};
+
 // ---------------------------------------------------------------- kernels
+// Persistent propagation launchers, one translation unit each
+// (tdsez_prop_*.hip): the two-wave kernel over order entries 0..n2-1 on
+// stream s2 and the one-wave kernel over entries n2..n2+n1-1 on s1.  probe
+// selects the autotuner's separately named copies (plain kernels only).
+hipError_t launch_prop_f64(const KernelArgs& ka, int n2, int n1, hipStream_t s2, hipStream_t s1, bool probe);
+hipError_t launch_prop_f32(const KernelArgs& ka, int n2, int n1, hipStream_t s2, hipStream_t s1, bool probe);
+// Extended kernels: absorbing potential, extended series, a_Q.
+hipError_t launch_prop_xt64(const KernelArgs& ka, int n2, int n1, hipStream_t s2, hipStream_t s1);
+hipError_t launch_prop_xt32(const KernelArgs& ka, int n2, int n1, hipStream_t s2, hipStream_t s1);
 // Assembly (tdsez_assemble.hip)
 tdsez_status assemble_device(const double* breaks, int nbreaks, int order, int nq,
                              const double* minv_q, const double* V_q, const double* dV_q,
                              SystemData* sys);
+// W (which = 0, samples eta) or Q (which = 1, samples g and h) of an
+// assembled system; replaces the previous band of that kind.
+tdsez_status assemble_extra_device(SystemData* sys, int which, const double* a_q, const double* b_q);
+// S phi_k of npop host vectors into sys->d_pops (replaces previous ones).
+tdsez_status set_projectors_device(SystemData* sys, int npop, const double* phi);
 // Host Gauss-Legendre (tdsez_assemble.hip)
 int gauss_legendre_host(int nq, double* x, double* w);
 
@@ -157,7 +219,11 @@ Plan make_plan(int N, int p, int force_chunks, int max_chunks = kMaxChunks, doub
 tdsez_status pack_bands(BatchData* b);
 // probe: launch the autotuner's separately named copy of the kernel
 tdsez_status launch_propagate(BatchData* b, double* psi, const double* E, double* obs,
-                              tdsez_precision prec, unsigned obs_mask, hipStream_t stream, bool probe = false);
+                              tdsez_precision prec, unsigned obs_mask, hipStream_t stream, bool probe = false,
+                              double* ext = nullptr);
+// Counters per system of the optional phase profile: 8 phases, the step
+// count and the largest relative refinement residual (double bits).
+constexpr int kProfSlots = 10;
 // Adjoint (tdsez_adjoint.hip): descriptors already hold nsteps, dt and offsets
 // Upload the batch descriptors, and the longest-first workgroup order derived
 // from them, if they differ from the last upload (a repeated call with the

@@ -87,13 +87,15 @@ __device__ inline void st_c(FT* base, unsigned idx, cplx<FT> v) {
 // stored (in FT) for the elimination.  Lane-serial over the chunk's rows
 // plus a halo of p rows of the next chunk; each pair of rows (r, r-d) of an
 // observable is counted by the owner of the larger row.
-template <int PP, typename FT>
+template <int PP, typename FT, bool XT = false>
 __device__ __forceinline__ void pass_rhs(const SysDesc& sd, int k, const FT* __restrict__ band,
                          const double* __restrict__ st, FT* __restrict__ rhs, double alpha,
                          double Ebar, double En, bool want_acc, bool want_rhs, double obs_part[3]) {
     constexpr int NM = kNumMats;
     const int L = sd.L, LS = sd.LS;
     const bool mi_is_s = sd.mi_is_s != 0;
+    // with an absorber (extended kernels only) the Hamiltonian is H - i W
+    const bool cap = XT && sd.cap != 0;
     int col = k + 1;
     // Per-lane addresses are rebuilt every step instead of being hoisted out
     // of the time loop (that would keep hundreds of them live in registers).
@@ -105,8 +107,11 @@ __device__ __forceinline__ void pass_rhs(const SysDesc& sd, int k, const FT* __r
 
     cplx<double> cw[PP + 1];    // c rows r-p..r (slot PP newest)
     cplx<double> hacc[PP + 1];  // pending (H c) of rows r-p..r
+    cplx<double> wacc[XT ? PP + 1 : 1];  // pending (W c) (absorber)
 #pragma unroll
     for (int i = 0; i <= PP; ++i) hacc[i] = cmk<double>(0, 0);
+#pragma unroll
+    for (int i = 0; i < (XT ? PP + 1 : 1); ++i) wacc[i] = cmk<double>(0, 0);
     // c rows -p..-1 come from the previous chunk (column k; zero for k = 0)
     cw[0] = cmk<double>(0, 0);
 #pragma unroll
@@ -118,6 +123,7 @@ __device__ __forceinline__ void pass_rhs(const SysDesc& sd, int k, const FT* __r
 
     struct RowIn {
         FT bS[PP + 1], bH[PP + 1], bD[PP + 1], bG[PP + 1], bM[PP + 1];
+        FT bW[XT ? PP + 1 : 1];
         cplx<double> cr;
     };
     auto load_row = [&](int r) {
@@ -134,6 +140,11 @@ __device__ __forceinline__ void pass_rhs(const SysDesc& sd, int k, const FT* __r
             in.bD[d] = bnd[rb + (unsigned)((2 * (PP + 1) + d) * LS)];
             in.bG[d] = (FT)0;
             in.bM[d] = (FT)0;
+        }
+        if constexpr (XT) {
+#pragma unroll
+            for (int d = 0; d <= PP; ++d)
+                in.bW[d] = cap ? bnd[rb + (unsigned)((kMatW * (PP + 1) + d) * LS)] : (FT)0;
         }
         if (want_acc && own) {
 #pragma unroll
@@ -174,6 +185,24 @@ __device__ __forceinline__ void pass_rhs(const SysDesc& sd, int k, const FT* __r
             hacc[PP - d].re += h[d] * cr.re;
             hacc[PP - d].im += h[d] * cr.im;
         }
+        if constexpr (XT) {
+#pragma unroll
+            for (int d = 0; d < PP; ++d) wacc[d] = wacc[d + 1];
+            cplx<double> sum = cmk<double>(0, 0);
+            if (own) {
+#pragma unroll
+                for (int d = 0; d <= PP; ++d) {
+                    sum.re += (double)in.bW[d] * cw[PP - d].re;
+                    sum.im += (double)in.bW[d] * cw[PP - d].im;
+                }
+            }
+            wacc[PP] = sum;
+#pragma unroll
+            for (int d = 1; d <= PP; ++d) {
+                wacc[PP - d].re += (double)in.bW[d] * cr.re;
+                wacc[PP - d].im += (double)in.bW[d] * cr.im;
+            }
+        }
         if (own) {
             double o[PP + 1];
 #pragma unroll
@@ -197,10 +226,16 @@ __device__ __forceinline__ void pass_rhs(const SysDesc& sd, int k, const FT* __r
                 acc -= sg + En * (mi_is_s ? sn : sm);
             }
         }
-        // row r - p is complete: -i dt H c = (2a Im, -2a Re)
+        // row r - p is complete: -i dt H c = (2a Im, -2a Re); an absorber
+        // adds -dt W c
         if (want_rhs && r >= PP) {
             const unsigned at = (unsigned)(r - PP) * (unsigned)LS + (unsigned)col;
-            st_c(rs, at, cmk<FT>((FT)(2.0 * alpha * hacc[0].im), (FT)(-2.0 * alpha * hacc[0].re)));
+            double zr = 2.0 * alpha * hacc[0].im, zi = -2.0 * alpha * hacc[0].re;
+            if constexpr (XT) {
+                zr -= 2.0 * alpha * wacc[0].re;
+                zi -= 2.0 * alpha * wacc[0].im;
+            }
+            st_c(rs, at, cmk<FT>((FT)zr, (FT)zi));
         }
     };
     // rows are loaded two ahead of their use
@@ -234,10 +269,11 @@ __device__ __forceinline__ void pass_rhs(const SysDesc& sd, int k, const FT* __r
 // multipliers, 1/D_j and yhat_j of every interior pivot, and the Schur block
 // W and right-hand side yR of the chunk's separator rows.  With kConj the
 // right-hand side is the complex conjugate of `rhs` (adjoint solves).
-template <int PP, typename FT, bool kConj = false>
+template <int PP, typename FT, bool kConj = false, bool XT = false>
 __device__ __forceinline__ void pass_elim(const SysDesc& sd, int k, const FT* __restrict__ band,
                           const FT* __restrict__ rhs, FT* __restrict__ fac, FT* __restrict__ red,
                           double alpha, double Ebar) {
+    const bool cap = XT && sd.cap != 0;
     constexpr int NM = kNumMats;
     constexpr int IT = 2 * PP + 2;
     const int L = sd.L, LS = sd.LS, P = sd.P;
@@ -273,6 +309,8 @@ __device__ __forceinline__ void pass_elim(const SysDesc& sd, int k, const FT* __
             in.bS[d] = bnd[rb + (unsigned)((0 * (PP + 1) + d) * LS)];
             in.bH[d] = bnd[rb + (unsigned)((1 * (PP + 1) + d) * LS)];
             in.bD[d] = bnd[rb + (unsigned)((2 * (PP + 1) + d) * LS)];
+            // absorber: real part S + a W
+            if (cap) in.bS[d] += a_f * bnd[rb + (unsigned)((kMatW * (PP + 1) + d) * LS)];
         }
         in.b = ld_c(rs, (unsigned)r * (unsigned)LS + (unsigned)col);
         return in;
@@ -357,7 +395,7 @@ __device__ __forceinline__ void pass_elim(const SysDesc& sd, int k, const FT* __
 //    harmless since both are additive;
 //  - eliminate as pass_elim (multipliers, 1/D_j, yhat_j; Schur block W and
 //    right-hand side yR of the separator rows).
-template <int PP, typename FT>
+template <int PP, typename FT, bool XT = false>
 __device__ __forceinline__ void pass_rhs_elim(const SysDesc& sd, int k, const FT* __restrict__ band,
                                               const double* __restrict__ st, FT* __restrict__ fac,
                                               FT* __restrict__ red, double alpha, double Ebar, double En,
@@ -366,6 +404,7 @@ __device__ __forceinline__ void pass_rhs_elim(const SysDesc& sd, int k, const FT
     constexpr int IT = 2 * PP + 2;
     const int L = sd.L, LS = sd.LS, P = sd.P;
     const bool mi_is_s = sd.mi_is_s != 0;
+    const bool cap = XT && sd.cap != 0;
     int col = k + 1;
     asm volatile("" : "+v"(col));
     const int kk = col - 1;
@@ -379,6 +418,10 @@ __device__ __forceinline__ void pass_rhs_elim(const SysDesc& sd, int k, const FT
     const double twoa = 2.0 * alpha;
     // -i 2a z, rounded to the factor precision
     auto rhs_of = [&](double zr, double zi) { return cmk<FT>((FT)(twoa * zi), (FT)(-twoa * zr)); };
+    // -2a (h - i w) c for an absorber row entry pair (h, w) and state c
+    auto rhs_cap = [&](double h, double w, cplx<double> c) {
+        return cmk<FT>((FT)(twoa * (h * c.im - w * c.re)), (FT)(-twoa * (h * c.re + w * c.im)));
+    };
 
     cplx<double> cw[PP + 1];     // c rows r-p..r (slot PP newest)
     cplx<FT> W[PP + 1][PP + 1];  // lower triangle used: rows r-p..r in slots 0..PP
@@ -400,6 +443,7 @@ __device__ __forceinline__ void pass_rhs_elim(const SysDesc& sd, int k, const FT
 
     struct RowIn {
         FT bS[PP + 1], bH[PP + 1], bD[PP + 1], bG[PP + 1], bM[PP + 1];
+        FT bW[XT ? PP + 1 : 1];
         cplx<double> cr;
     };
     auto load_row = [&](int r) {
@@ -416,6 +460,11 @@ __device__ __forceinline__ void pass_rhs_elim(const SysDesc& sd, int k, const FT
             in.bD[d] = bnd[rb + (unsigned)((2 * (PP + 1) + d) * LS)];
             in.bG[d] = (FT)0;
             in.bM[d] = (FT)0;
+        }
+        if constexpr (XT) {
+#pragma unroll
+            for (int d = 0; d <= PP; ++d)
+                in.bW[d] = cap ? bnd[rb + (unsigned)((kMatW * (PP + 1) + d) * LS)] : (FT)0;
         }
         if (want_acc && own) {
 #pragma unroll
@@ -439,19 +488,27 @@ __device__ __forceinline__ void pass_rhs_elim(const SysDesc& sd, int k, const FT
         double h[PP + 1];
 #pragma unroll
         for (int d = 0; d <= PP; ++d) h[d] = (double)in.bH[d] + Ebar * (double)in.bD[d];
-        {
-            // row r: sum_d M[r][r-d] c_{r-d}
-            double sr = 0.0, si = 0.0;
+        if constexpr (!XT) {
+            {
+                // row r: sum_d M[r][r-d] c_{r-d}
+                double sr = 0.0, si = 0.0;
 #pragma unroll
-            for (int d = 0; d <= PP; ++d) {
-                sr += h[d] * cw[PP - d].re;
-                si += h[d] * cw[PP - d].im;
+                for (int d = 0; d <= PP; ++d) {
+                    sr += h[d] * cw[PP - d].re;
+                    si += h[d] * cw[PP - d].im;
+                }
+                y[PP] = cadd(y[PP], rhs_of(sr, si));
             }
-            y[PP] = cadd(y[PP], rhs_of(sr, si));
-        }
-        // rows r-d receive M[r-d][r] c_r = M[r][r-d] c_r
+            // rows r-d receive M[r-d][r] c_r = M[r][r-d] c_r
 #pragma unroll
-        for (int d = 1; d <= PP; ++d) y[PP - d] = cadd(y[PP - d], rhs_of(h[d] * cr.re, h[d] * cr.im));
+            for (int d = 1; d <= PP; ++d) y[PP - d] = cadd(y[PP - d], rhs_of(h[d] * cr.re, h[d] * cr.im));
+        } else {
+            // the same with the absorber: H - i W
+#pragma unroll
+            for (int d = 0; d <= PP; ++d) y[PP] = cadd(y[PP], rhs_cap(h[d], (double)in.bW[d], cw[PP - d]));
+#pragma unroll
+            for (int d = 1; d <= PP; ++d) y[PP - d] = cadd(y[PP - d], rhs_cap(h[d], (double)in.bW[d], cr));
+        }
         {
             double o[PP + 1];
 #pragma unroll
@@ -475,10 +532,12 @@ __device__ __forceinline__ void pass_rhs_elim(const SysDesc& sd, int k, const FT
                 acc -= sg + En * (mi_is_s ? sn : sm);
             }
         }
-        // insert row r of A_n = S + i a (H0 + Ebar D)
+        // insert row r of A_n = S + i a (H0 + Ebar D) (+ a W with an absorber)
 #pragma unroll
         for (int d = 0; d <= PP; ++d) {
-            const cplx<FT> a = cmk<FT>(in.bS[d], a_f * (in.bH[d] + eb_f * in.bD[d]));
+            FT re = in.bS[d];
+            if constexpr (XT) re += a_f * in.bW[d];
+            const cplx<FT> a = cmk<FT>(re, a_f * (in.bH[d] + eb_f * in.bD[d]));
             if (!first_rows || r - d >= 0) W[PP][PP - d] = a;
         }
         if (elim) {
@@ -534,7 +593,8 @@ __device__ __forceinline__ void pass_rhs_elim(const SysDesc& sd, int k, const FT
 #pragma unroll
         for (int d = t + 1; d <= PP; ++d) {
             const double hd = (double)cur.bH[d] + Ebar * (double)cur.bD[d];
-            y[PP + t - d] = cadd(y[PP + t - d], rhs_of(hd * cr.re, hd * cr.im));
+            if constexpr (XT) y[PP + t - d] = cadd(y[PP + t - d], rhs_cap(hd, (double)cur.bW[d], cr));
+            else y[PP + t - d] = cadd(y[PP + t - d], rhs_of(hd * cr.re, hd * cr.im));
         }
         cur = nxt;
     }
@@ -562,9 +622,10 @@ __device__ __forceinline__ void pass_rhs_elim(const SysDesc& sd, int k, const FT
 // Only rows 0..p-1 couple to the left separator directly; the multipliers of
 // pass A1 carry the fill down the chunk.  With kTL == false the Schur update
 // is left to pass_schur (fewer live registers for FP64).
-template <int PP, typename FT, bool kTL>
+template <int PP, typename FT, bool kTL, bool XT = false>
 __device__ __forceinline__ void pass_fill(const SysDesc& sd, int k, const FT* __restrict__ band, FT* __restrict__ fac,
                           FT* __restrict__ red, double alpha, double Ebar) {
+    const bool cap = XT && sd.cap != 0;
     constexpr int NM = kNumMats;
     constexpr int IT = 2 * PP + 2;
     const int L = sd.L, LS = sd.LS, P = sd.P, m = sd.m;
@@ -603,6 +664,7 @@ __device__ __forceinline__ void pass_fill(const SysDesc& sd, int k, const FT* __
             FT sv = bnd[rb + (unsigned)((0 * (PP + 1) + d) * LS)];
             FT hv = bnd[rb + (unsigned)((1 * (PP + 1) + d) * LS)];
             FT dv = bnd[rb + (unsigned)((2 * (PP + 1) + d) * LS)];
+            if (cap) sv += a_f * bnd[rb + (unsigned)((kMatW * (PP + 1) + d) * LS)];
             F[r][r - d + PP] = cmk<FT>(sv, a_f * (hv + eb_f * dv));
         }
     }
@@ -1016,11 +1078,12 @@ __device__ __forceinline__ void pass_reduced2(const SysDesc& sd, int tid, FT* __
 // substitution).  The state gets the increment (or, with assign, is
 // overwritten by the solution); with dtot != nullptr the increment is also
 // written (first == true) or added to dtot.
-template <int PP, typename FT>
+template <int PP, typename FT, bool XT = false>
 __device__ __forceinline__ void pass_backsub(const SysDesc& sd, int k, const FT* __restrict__ band,
                              double* __restrict__ st, double* __restrict__ dtot, bool first,
                              const FT* __restrict__ fac, const FT* __restrict__ red, double alpha,
                              double Ebar, bool assign = false) {
+    const bool cap = XT && sd.cap != 0;
     constexpr int NM = kNumMats;
     constexpr int IT = 2 * PP + 2;
     const int LS = sd.LS, P = sd.P, m = sd.m;
@@ -1047,6 +1110,7 @@ __device__ __forceinline__ void pass_backsub(const SysDesc& sd, int k, const FT*
         FT s = bnd[rb + (unsigned)((0 * (PP + 1) + d) * LS)];
         FT h = bnd[rb + (unsigned)((1 * (PP + 1) + d) * LS)];
         FT dd = bnd[rb + (unsigned)((2 * (PP + 1) + d) * LS)];
+        if (cap) s += a_f * bnd[rb + (unsigned)((kMatW * (PP + 1) + d) * LS)];
         return cmk<FT>(s, a_f * (h + eb_f * dd));
     };
     auto fitem = [&](int j, int item) {
@@ -1162,11 +1226,12 @@ __device__ __forceinline__ void pass_backsub(const SysDesc& sd, int k, const FT*
 // from the FP64 bands S, H0, D (so the sweeps converge to the FP64
 // Crank-Nicolson step), then forward substitution with the stored factor
 // rows (yhat, and the chunk's separator right-hand sides yR, gT).
-template <int PP, typename FT>
+template <int PP, typename FT, bool XT = false>
 __device__ __forceinline__ void pass_residual(const SysDesc& sd, int k, const FT* __restrict__ band,
                               const double* __restrict__ band64, const double* __restrict__ st,
                               const double* __restrict__ dtot, FT* __restrict__ fac,
-                              FT* __restrict__ red, double alpha, double Ebar) {
+                              FT* __restrict__ red, double alpha, double Ebar, double nrm[2]) {
+    const bool cap = XT && sd.cap != 0;
     constexpr int NM = kNumMats;
     constexpr int IT = 2 * PP + 2;
     const int L = sd.L, LS = sd.LS, P = sd.P;
@@ -1185,6 +1250,7 @@ __device__ __forceinline__ void pass_residual(const SysDesc& sd, int k, const FT
     };
     // windows of v = 2c - dtot and of dtot: slot PP is the newest row
     cplx<double> vw[PP + 1], dw[PP + 1], hacc[PP + 1], sacc[PP + 1];
+    cplx<double> wacc[XT ? PP + 1 : 1];  // pending (W v) (absorber)
     cplx<FT> y[PP + 1];
     cplx<FT> gT[PP];
 #pragma unroll
@@ -1193,6 +1259,11 @@ __device__ __forceinline__ void pass_residual(const SysDesc& sd, int k, const FT
         sacc[i] = cmk<double>(0, 0);
         y[i] = cmk<FT>(0, 0);
     }
+#pragma unroll
+    for (int i = 0; i < (XT ? PP + 1 : 1); ++i) wacc[i] = cmk<double>(0, 0);
+    // squared norms of the residual and of its two terms (S dtot and
+    // a (W + i H) v), the scale of the relative residual
+    double rn2 = 0.0, ref2 = 0.0;
 #pragma unroll
     for (int t = 0; t < PP; ++t) gT[t] = cmk<FT>(0, 0);
     vw[0] = dw[0] = cmk<double>(0, 0);
@@ -1208,6 +1279,7 @@ __device__ __forceinline__ void pass_residual(const SysDesc& sd, int k, const FT
     // loaded one row ahead of its use
     struct RowIn {
         double bS[PP + 1], bH[PP + 1], bD[PP + 1];
+        double bW[XT ? PP + 1 : 1];
         cplx<double> c, dd;
     };
     auto load_row = [&](int r) {
@@ -1223,12 +1295,17 @@ __device__ __forceinline__ void pass_residual(const SysDesc& sd, int k, const FT
             in.bH[d] = bnd64[rb + (unsigned)((1 * (PP + 1) + d) * LS)];
             in.bD[d] = bnd64[rb + (unsigned)((2 * (PP + 1) + d) * LS)];
         }
+        if constexpr (XT) {
+#pragma unroll
+            for (int d = 0; d <= PP; ++d) in.bW[d] = cap ? bnd64[rb + (unsigned)((kMatW * (PP + 1) + d) * LS)] : 0.0;
+        }
         const unsigned sat = (unsigned)lr * (unsigned)LS + cc;
         in.c = cmk<double>(cst[2 * sat], cst[2 * sat + 1]);
         in.dd = cmk<double>(dst[2 * sat], dst[2 * sat + 1]);
         return in;
     };
-    auto stream_row = [&](const RowIn& in, bool own) {
+    // count: the completed row r - p is a row of this chunk (r >= p)
+    auto stream_row = [&](const RowIn& in, bool own, bool count) {
         double h[PP + 1];
 #pragma unroll
         for (int d = 0; d <= PP; ++d) h[d] = in.bH[d] + Ebar * in.bD[d];
@@ -1260,8 +1337,34 @@ __device__ __forceinline__ void pass_residual(const SysDesc& sd, int k, const FT
             sacc[PP - d].re += in.bS[d] * dw[PP].re;
             sacc[PP - d].im += in.bS[d] * dw[PP].im;
         }
-        // completed residual of row r - p: -S dtot - i a H v
-        return cmk<FT>((FT)(-sacc[0].re + alpha * hacc[0].im), (FT)(-sacc[0].im - alpha * hacc[0].re));
+        // completed residual of row r - p: -S dtot - a (W + i H) v
+        double tr = -alpha * hacc[0].im, ti = alpha * hacc[0].re;  // i a H v
+        if constexpr (XT) {
+#pragma unroll
+            for (int d = 0; d < PP; ++d) wacc[d] = wacc[d + 1];
+            cplx<double> ws = cmk<double>(0, 0);
+            if (own) {
+#pragma unroll
+                for (int d = 0; d <= PP; ++d) {
+                    ws.re += in.bW[d] * vw[PP - d].re;
+                    ws.im += in.bW[d] * vw[PP - d].im;
+                }
+            }
+            wacc[PP] = ws;
+#pragma unroll
+            for (int d = 1; d <= PP; ++d) {
+                wacc[PP - d].re += in.bW[d] * vw[PP].re;
+                wacc[PP - d].im += in.bW[d] * vw[PP].im;
+            }
+            tr += alpha * wacc[0].re;
+            ti += alpha * wacc[0].im;
+        }
+        const double rr = -sacc[0].re - tr, ri = -sacc[0].im - ti;
+        if (count) {
+            rn2 += rr * rr + ri * ri;
+            ref2 += sacc[0].re * sacc[0].re + sacc[0].im * sacc[0].im + tr * tr + ti * ti;
+        }
+        return cmk<FT>((FT)rr, (FT)ri);
     };
     auto shift_y = [&]() {
 #pragma unroll
@@ -1288,7 +1391,7 @@ __device__ __forceinline__ void pass_residual(const SysDesc& sd, int k, const FT
 #pragma unroll
     for (int r = 0; r < PP; ++r) {
         RowIn nx2 = load_row(r + 2);
-        (void)stream_row(cur, true);
+        (void)stream_row(cur, true, false);
         shift_y();
         cur = nx1;
         nx1 = nx2;
@@ -1298,7 +1401,7 @@ __device__ __forceinline__ void pass_residual(const SysDesc& sd, int k, const FT
         RowIn nx2 = load_row(r + 2);
         FRow fnxt = load_frow(r - PP + 1);
         const int j = r - PP;
-        cplx<FT> yj = cadd(y[0], stream_row(cur, true));
+        cplx<FT> yj = cadd(y[0], stream_row(cur, true, true));
         const unsigned fb = (unsigned)j * fstride + (unsigned)kk;
         st_c(fc, fb + (unsigned)((PP + 1) * P), yj);
 #pragma unroll
@@ -1313,7 +1416,7 @@ __device__ __forceinline__ void pass_residual(const SysDesc& sd, int k, const FT
 #pragma unroll
     for (int t = 0; t < PP; ++t) {
         RowIn nx2 = load_row(L + t + 2);
-        y[t] = cadd(y[t], stream_row(cur, false));
+        y[t] = cadd(y[t], stream_row(cur, false, true));
         cur = nx1;
         nx1 = nx2;
     }
@@ -1324,6 +1427,86 @@ __device__ __forceinline__ void pass_residual(const SysDesc& sd, int k, const FT
         st_c(rb, (unsigned)(3 * pp + i), y[i]);
         st_c(rb, (unsigned)(3 * pp + PP + i), gT[i]);
     }
+    nrm[0] = rn2;
+    nrm[1] = ref2;
+}
+
+// Extended per-step series (the time series of section V.D) of c_n from
+// the FP64 bands: one lane's partial sums over its chunk rows, each pair of
+// rows (r, r-d) counted by the owner of row r:
+//   xs[0] c^H H0 c    xs[1] c^H V c    xs[2] c^H Mi c
+//   xs[3] <v> = sum K[r][r-d] Im(conj(c_r) c_{r-d})   (eq. vel_elem, Vel = -(i/2) K)
+//   xs[4] c^H Q c (a_Q)    xs[5] c^H W c (absorber)
+//   xs[6], xs[7] Re, Im of c_0^H S c (autocorrelation, M-weighted overlap)
+//   xs[8 + 2k], xs[9 + 2k] Re, Im of (S phi_k)^T c (projection on state k)
+constexpr int kExtSums = 8 + 2 * kMaxPop;
+template <int PP>
+__device__ __forceinline__ void pass_extobs(const SysDesc& sd, int k, const double* __restrict__ band64,
+                                            const double* __restrict__ st, const double* __restrict__ c0,
+                                            const double* __restrict__ proj, double xs[kExtSums]) {
+    constexpr int NM = kNumMats;
+    const int L = sd.L, LS = sd.LS, npop = sd.npop;
+    const bool aq = sd.aq != 0, cap = sd.cap != 0, autoc = c0 != nullptr;
+    int col = k + 1;
+    asm volatile("" : "+v"(col));
+    const double* __restrict__ bnd = band64 + sd.band_off;
+    const double* __restrict__ cst = st + 2 * sd.state_off;
+    const double* __restrict__ zst = autoc ? c0 + 2 * sd.state_off : cst;
+    const double* __restrict__ pj = proj ? proj + sd.proj_off : nullptr;
+    const unsigned rowstride = (unsigned)(NM * (PP + 1) * LS);
+#pragma unroll
+    for (int i = 0; i < kExtSums; ++i) xs[i] = 0.0;
+    cplx<double> cw[PP + 1], zw[PP + 1];  // c and c_0 rows r-p..r (slot PP newest)
+    cw[0] = zw[0] = cmk<double>(0, 0);
+#pragma unroll
+    for (int d = 0; d < PP; ++d) {
+        const unsigned at = (unsigned)(L - PP + d) * (unsigned)LS + (unsigned)(col - 1);
+        cw[d + 1] = cmk<double>(cst[2 * at], cst[2 * at + 1]);
+        zw[d + 1] = cmk<double>(zst[2 * at], zst[2 * at + 1]);
+    }
+    auto band = [&](unsigned rb, int mat, int d) { return bnd[rb + (unsigned)((mat * (PP + 1) + d) * LS)]; };
+    for (int r = 0; r < L; ++r) {
+        const unsigned at = (unsigned)r * (unsigned)LS + (unsigned)col;
+        const cplx<double> cr = cmk<double>(cst[2 * at], cst[2 * at + 1]);
+        const cplx<double> zr = cmk<double>(zst[2 * at], zst[2 * at + 1]);
+#pragma unroll
+        for (int d = 0; d < PP; ++d) {
+            cw[d] = cw[d + 1];
+            zw[d] = zw[d + 1];
+        }
+        cw[PP] = cr;
+        zw[PP] = zr;
+        const unsigned rb = (unsigned)r * rowstride + (unsigned)col;
+#pragma unroll
+        for (int d = 0; d <= PP; ++d) {
+            const cplx<double> cd = cw[PP - d];
+            const double wgt = d == 0 ? 1.0 : 2.0;
+            const double o = wgt * (cr.re * cd.re + cr.im * cd.im);  // 2 Re conj(c_r) c_{r-d}
+            xs[0] += band(rb, kMatH0, d) * o;
+            xs[1] += band(rb, kMatV, d) * o;
+            xs[2] += band(rb, kMatMi, d) * o;
+            if (d > 0) xs[3] += band(rb, kMatK, d) * (cr.re * cd.im - cr.im * cd.re);
+            if (aq) xs[4] += band(rb, kMatQ, d) * o;
+            if (cap) xs[5] += band(rb, kMatW, d) * o;
+            if (autoc) {
+                // conj(z_r) c_{r-d} + conj(z_{r-d}) c_r (d > 0)
+                const double sv = band(rb, kMatS, d);
+                const cplx<double> zd = zw[PP - d];
+                double are = zr.re * cd.re + zr.im * cd.im, aim = zr.re * cd.im - zr.im * cd.re;
+                if (d > 0) {
+                    are += zd.re * cr.re + zd.im * cr.im;
+                    aim += zd.re * cr.im - zd.im * cr.re;
+                }
+                xs[6] += sv * are;
+                xs[7] += sv * aim;
+            }
+        }
+        for (int q = 0; q < npop; ++q) {
+            const double ps = pj[((long long)q * L + r) * LS + col];
+            xs[8 + 2 * q] += ps * cr.re;
+            xs[9 + 2 * q] += ps * cr.im;
+        }
+    }
 }
 
 __device__ inline void latch(int* status, int code, int sys, int step) {
@@ -1333,25 +1516,7 @@ __device__ inline void latch(int* status, int code, int sys, int step) {
     }
 }
 
-struct KernelArgs {
-    const SysDesc* descs;
-    const int* order;          // workgroup -> system index (longest first)
-    int order_off;             // first entry of order read by this launch
-    const void* band;          // FT bands (factorisation, solve, right-hand side)
-    const double* band64;      // FP64 bands (S of the refinement residual)
-    double* st;
-    double* dtot;              // increment of the current step (refinement only)
-    void* rhs;                 // right-hand side of the step (FT, state layout)
-    void* fac;
-    void* red;
-    const double* E;
-    double* obs;
-    unsigned mask;
-    int refine;
-    double norm_tol;
-    int* status;
-    unsigned long long* prof;
-};
+
 
 }  // namespace
 }  // namespace tdsez

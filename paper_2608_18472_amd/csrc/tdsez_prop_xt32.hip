@@ -1,0 +1,6 @@
+// Persistent Crank-Nicolson kernels, FP32-refined arithmetic, extended variant (absorbing
+// potential, extended per-step series, a_Q).  A translation
+// unit of its own so that the kernel families compile in parallel.
+#include "tdsez_run.hpp"
+
+TDSEZ_DEFINE_XT_LAUNCHER(float, launch_prop_xt32)

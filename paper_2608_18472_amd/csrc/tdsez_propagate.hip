@@ -39,187 +39,16 @@
 #include <cstring>
 
 #include "tdsez_passes.hpp"
+// (the kernels themselves are instantiated in tdsez_prop_*.hip from tdsez_run.hpp)
 
 namespace tdsez {
 
 namespace {
 
-// number of per-system counters of the optional phase profile
-constexpr int kProfSlots = 9;
-
-// NW = 1: one wave owns the system (P <= 64).  NW = 2: two waves (P in
-// 65..128); thread t owns chunk t in the lane-serial passes, the separator
-// system is solved from both ends (pass_reduced2) and the observable sums
-// are combined across the waves through LDS.
-template <int PP, typename FT, int NW>
-__device__ __forceinline__ void run_system(const KernelArgs& ka, const SysDesc& sd, int sidx, FT* zl) {
-    // optional phase profile: shader-clock cycles summed over the steps for
-    // the passes H, A1 (FP32: one fused sweep counted under H), A2, R, B and,
-    // per refinement sweep, C, R, B
-    unsigned long long tp[kProfSlots - 1] = {0, 0, 0, 0, 0, 0, 0, 0};
-    unsigned long long t0 = 0;
-    const FT* band = (const FT*)ka.band;
-    FT* fac = (FT*)ka.fac;
-    FT* red = (FT*)ka.red;
-    FT* rhs = (FT*)ka.rhs;
-    double* st = ka.st;
-    const int lane = threadIdx.x;  // chunk index
-    const bool active = lane < sd.P;
-    const double alpha = 0.5 * sd.dt;
-    const double* Es = ka.E + sd.E_off;
-    double* os = ka.obs ? ka.obs + sd.obs_off : nullptr;
-    const unsigned mask = ka.mask;
-    const bool want_acc = (mask & TDSEZ_OBS_ACCEL) != 0;
-    const int refine = ka.refine;
-    double* dtot = refine > 0 ? ka.dtot : nullptr;
-    const bool prof = ka.prof != nullptr;
-    // phase boundary: a barrier (so the clock covers the whole wave) when
-    // profiling, then the cycles since the last boundary go to slot k
-    auto mark = [&](int k) {
-        if (prof) {
-            __syncthreads();
-            const unsigned long long t = clock64();
-            tp[k] += t - t0;
-            t0 = t;
-        }
-    };
-    double nu0 = 0.0;
-    for (int n = 0; n <= sd.nsteps; ++n) {
-        const bool last = (n == sd.nsteps);
-        const double En = Es[n];
-        const double Ebar = last ? En : 0.5 * (En + Es[n + 1]);
-        double part[3] = {0.0, 0.0, 0.0};
-        if (prof) t0 = clock64();
-        // FP32: right-hand side, observables and elimination in one sweep
-        // (FP64 rows are twice the size and keep two passes); the last time
-        // level needs the observables only
-        constexpr bool kOneSweep = sizeof(FT) == 4;
-        if (active) {
-            if (kOneSweep && !last)
-                pass_rhs_elim<PP, FT>(sd, lane, band, st, fac, red, alpha, Ebar, En, want_acc, part);
-            else
-                pass_rhs<PP, FT>(sd, lane, band, st, rhs, alpha, Ebar, En, want_acc, !last, part);
-        }
-        mark(0);
-        if (!kOneSweep && active && !last) pass_elim<PP, FT>(sd, lane, band, rhs, fac, red, alpha, Ebar);
-        mark(1);
-        if (active && !last) {
-            constexpr bool kFused = sizeof(FT) == 4;
-            pass_fill<PP, FT, kFused>(sd, lane, band, fac, red, alpha, Ebar);
-            if (!kFused) pass_schur<PP, FT>(sd, lane, fac, red);
-        }
-        double nu = wave_sum(part[0]);
-        double dip = wave_sum(part[1]);
-        double acc = wave_sum(part[2]);
-        if constexpr (NW == 2) {
-            // both waves add the two partial sums in the same order, so they
-            // take the same decisions below; the slots are rewritten one step
-            // later, after further barriers
-            __shared__ double wsum[2][3];
-            if ((lane & (kWave - 1)) == 0) {
-                wsum[lane / kWave][0] = nu;
-                wsum[lane / kWave][1] = dip;
-                wsum[lane / kWave][2] = acc;
-            }
-            __syncthreads();
-            nu = wsum[0][0] + wsum[1][0];
-            dip = wsum[0][1] + wsum[1][1];
-            acc = wsum[0][2] + wsum[1][2];
-        }
-        if (lane == 0 && os) {
-            os[3 * n + 0] = (mask & TDSEZ_OBS_NORM) ? nu : 0.0;
-            os[3 * n + 1] = (mask & TDSEZ_OBS_DIPOLE) ? dip : 0.0;
-            os[3 * n + 2] = want_acc ? acc : 0.0;
-        }
-        if (n == 0) nu0 = nu;
-        if (!isfinite(nu) || !isfinite(dip) || !isfinite(acc)) {
-            if (lane == 0) latch(ka.status, TDSEZ_ENONFINITE, sidx, n);
-            return;
-        }
-        if (ka.norm_tol > 0.0 && fabs(nu / nu0 - 1.0) > ka.norm_tol) {
-            if (lane == 0) latch(ka.status, TDSEZ_ENORMDRIFT, sidx, n);
-            return;
-        }
-        if (last) break;
-        __syncthreads();
-        mark(2);
-        if constexpr (NW == 2) pass_reduced2<PP, FT>(sd, lane, red, true, zl);
-        else pass_reduced<PP, FT>(sd, lane, red, true, zl);
-        __syncthreads();
-        mark(3);
-        if (active) pass_backsub<PP, FT>(sd, lane, band, st, dtot, true, fac, red, alpha, Ebar);
-        __syncthreads();
-        mark(4);
-        // refinement sweeps exist for the FP32 factorisation only (FP64
-        // launches pass refine = 0); FP64 code is built without them
-        for (int sweep = 0; sizeof(FT) == 4 && sweep < refine; ++sweep) {
-            if (active)
-                pass_residual<PP, FT>(sd, lane, band, ka.band64, st, dtot, fac, red, alpha, Ebar);
-            __syncthreads();
-            mark(5);
-            if constexpr (NW == 2) pass_reduced2<PP, FT>(sd, lane, red, false, zl);
-            else pass_reduced<PP, FT>(sd, lane, red, false, zl);
-            __syncthreads();
-            mark(6);
-            if (active)
-                pass_backsub<PP, FT>(sd, lane, band, st, sweep + 1 < refine ? dtot : nullptr, false, fac,
-                                     red, alpha, Ebar);
-            __syncthreads();
-            mark(7);
-        }
-    }
-    if (prof && lane == 0) {
-        unsigned long long* pr = ka.prof + kProfSlots * sidx;
-        for (int k = 0; k < kProfSlots - 1; ++k) pr[k] = tp[k];
-        pr[kProfSlots - 1] = (unsigned long long)sd.nsteps;
-    }
-}
-
-// zl: the separator recurrence's right-hand-side vector, P * p complex in
-// LDS, one array per kernel (shared by the p variants)
-template <typename FT, int NW>
-__device__ __forceinline__ void dispatch_system(const KernelArgs& ka) {
-    __shared__ FT zl[2 * kMaxP * (NW == 2 ? kMaxChunks2 : kMaxChunks)];
-    const int sidx = ka.order[ka.order_off + blockIdx.x];
-    const SysDesc sd = ka.descs[sidx];
-    switch (sd.p) {
-        case 1: run_system<1, FT, NW>(ka, sd, sidx, zl); break;
-        case 2: run_system<2, FT, NW>(ka, sd, sidx, zl); break;
-        case 3: run_system<3, FT, NW>(ka, sd, sidx, zl); break;
-        case 4: run_system<4, FT, NW>(ka, sd, sidx, zl); break;
-        case 5: run_system<5, FT, NW>(ka, sd, sidx, zl); break;
-        case 6: run_system<6, FT, NW>(ka, sd, sidx, zl); break;
-        case 7: run_system<7, FT, NW>(ka, sd, sidx, zl); break;
-        default: break;
-    }
-}
-
-template <typename FT>
-__global__ __launch_bounds__(kWave) void propagate_kernel(KernelArgs ka) {
-    dispatch_system<FT, 1>(ka);
-}
-
-// Systems partitioned into more than 64 chunks: two waves per system.
-template <typename FT>
-__global__ __launch_bounds__(2 * kWave) void propagate2_kernel(KernelArgs ka) {
-    dispatch_system<FT, 2>(ka);
-}
-
-// The same computations under their own names: the short probe launches of
-// the partition autotuner, kept apart from production launches in kernel
-// traces.
-template <typename FT>
-__global__ __launch_bounds__(kWave) void tune_probe_kernel(KernelArgs ka) {
-    dispatch_system<FT, 1>(ka);
-}
-template <typename FT>
-__global__ __launch_bounds__(2 * kWave) void tune_probe2_kernel(KernelArgs ka) {
-    dispatch_system<FT, 2>(ka);
-}
-
 // psi (natural order, complex128) <-> interleaved padded state
+// (c0 != nullptr: also a copy of the initial state for the autocorrelation)
 __global__ void pack_state_kernel(const SysDesc* __restrict__ descs, const double* __restrict__ psi,
-                                  double* __restrict__ st) {
+                                  double* __restrict__ st, double* __restrict__ c0) {
     const SysDesc sd = descs[blockIdx.y];
     const long long total = (long long)sd.L * sd.LS;
     for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
@@ -236,6 +65,30 @@ __global__ void pack_state_kernel(const SysDesc* __restrict__ descs, const doubl
         }
         st[2 * (sd.state_off + e)] = re;
         st[2 * (sd.state_off + e) + 1] = im;
+        if (c0) {
+            c0[2 * (sd.state_off + e)] = re;
+            c0[2 * (sd.state_off + e) + 1] = im;
+        }
+    }
+}
+
+// projection states S phi_k (natural order, npop x N) -> interleaved
+// [k][l][column] layout of one system
+__global__ void pack_proj_kernel(const double* __restrict__ src, int npop, int N, int P, int L, int LS,
+                                 double* __restrict__ out) {
+    const long long total = (long long)npop * L * LS;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+         e += (long long)gridDim.x * blockDim.x) {
+        const int colx = (int)(e % LS);
+        const long long r1 = e / LS;
+        const int l = (int)(r1 % L), q = (int)(r1 / L);
+        const int k = colx - 1;
+        double v = 0.0;
+        if (k >= 0 && k < P) {
+            const long long row = (long long)k * L + l;
+            if (row < N) v = src[(long long)q * N + row];
+        }
+        out[e] = v;
     }
 }
 
@@ -253,9 +106,11 @@ __global__ void unpack_state_kernel(const SysDesc* __restrict__ descs, const dou
 
 // FP64 master bands (lower half by rows) -> interleaved padded propagation
 // layout in FP64 and FP32.  Padding rows are decoupled identity rows.
-__global__ void pack_band_kernel(const double* __restrict__ S, const double* __restrict__ H0,
-                                 const double* __restrict__ D, const double* __restrict__ G,
-                                 const double* __restrict__ Mi, int N, int p, int P, int L, int LS,
+// Matrices in the kMat* order; a NULL source packs zeros.
+struct BandSrc {
+    const double* m[kNumMats];
+};
+__global__ void pack_band_kernel(BandSrc src, int N, int p, int P, int L, int LS,
                                  double* __restrict__ out64, float* __restrict__ out32) {
     const long long total = (long long)L * kNumMats * (p + 1) * LS;
     for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
@@ -271,9 +126,9 @@ __global__ void pack_band_kernel(const double* __restrict__ S, const double* __r
         if (k >= 0 && k < P) {
             long long row = (long long)k * L + l;
             if (row < N) {
-                const double* src = mat == 0 ? S : mat == 1 ? H0 : mat == 2 ? D : mat == 3 ? G : Mi;
-                v = src[row * (p + 1) + d];
-            } else if (mat == 0 && d == 0) {
+                const double* m = src.m[mat];
+                v = m ? m[row * (p + 1) + d] : 0.0;
+            } else if (mat == kMatS && d == 0) {
                 v = 1.0;
             }
         }
@@ -320,8 +175,9 @@ tdsez_status pack_bands(BatchData* b) {
     const int nsys = (int)b->sys.size();
     b->plan.resize(nsys);
     b->desc.resize(nsys);
-    long long boff = 0, soff = 0, foff = 0, roff = 0;
+    long long boff = 0, soff = 0, foff = 0, roff = 0, poff = 0;
     b->maxp = 0;
+    b->any_cap = b->any_aq = false;
     b->two_wave.assign(nsys, 0);
     b->nsplit = 0;
     for (int s = 0; s < nsys; ++s) {
@@ -342,6 +198,13 @@ tdsez_status pack_bands(BatchData* b) {
         d = SysDesc{};
         d.N = pl.N; d.p = pl.p; d.P = pl.P; d.L = pl.L; d.m = pl.m; d.LS = pl.LS;
         d.mi_is_s = sy->const_mass ? 1 : 0;
+        d.cap = sy->d_W ? 1 : 0;
+        d.aq = sy->d_Q ? 1 : 0;
+        d.npop = sy->npop;
+        d.proj_off = poff;
+        poff += (long long)sy->npop * pl.L * pl.LS;
+        b->any_cap = b->any_cap || d.cap;
+        b->any_aq = b->any_aq || d.aq;
         d.band_off = boff;
         d.state_off = soff;
         d.fac_off = foff;
@@ -368,6 +231,7 @@ tdsez_status pack_bands(BatchData* b) {
     TDSEZ_HIP_TRY(hipMalloc(&b->d_desc, sizeof(SysDesc) * nsys));
     TDSEZ_HIP_TRY(hipMalloc(&b->d_order, sizeof(int) * nsys));
     TDSEZ_HIP_TRY(hipMalloc(&b->d_status, sizeof(int) * 4));
+    if (poff > 0) TDSEZ_HIP_TRY(hipMalloc(&b->d_proj, sizeof(double) * (size_t)poff));
     TDSEZ_HIP_TRY(hipMemset(b->d_status, 0, sizeof(int) * 4));
     b->nsys_alloc_desc = nsys;
     b->desc_on_device.clear();
@@ -382,11 +246,25 @@ tdsez_status pack_bands(BatchData* b) {
         long long total = (long long)pl.L * kNumMats * (pl.p + 1) * pl.LS;
         int th = 256;
         int nb = (int)std::min<long long>((total + th - 1) / th, 4096);
-        pack_band_kernel<<<nb, th>>>(sy->d_band[0], sy->d_H0, sy->d_band[3], sy->d_band[4],
-                                     sy->d_band[5], pl.N, pl.p, pl.P, pl.L, pl.LS,
-                                     b->d_band64 + b->desc[s].band_off,
+        BandSrc src;
+        src.m[kMatS] = sy->d_band[0];
+        src.m[kMatH0] = sy->d_H0;
+        src.m[kMatD] = sy->d_band[3];
+        src.m[kMatG] = sy->d_band[4];
+        src.m[kMatMi] = sy->d_band[5];
+        src.m[kMatW] = sy->d_W;
+        src.m[kMatV] = sy->d_band[2];
+        src.m[kMatK] = sy->d_K;
+        src.m[kMatQ] = sy->d_Q;
+        pack_band_kernel<<<nb, th>>>(src, pl.N, pl.p, pl.P, pl.L, pl.LS, b->d_band64 + b->desc[s].band_off,
                                      b->d_band32 + b->desc[s].band_off);
         TDSEZ_HIP_TRY(hipGetLastError());
+        if (sy->npop > 0) {
+            long long tp = (long long)sy->npop * pl.L * pl.LS;
+            pack_proj_kernel<<<(int)std::min<long long>((tp + 255) / 256, 4096), 256>>>(
+                sy->d_pops, sy->npop, pl.N, pl.P, pl.L, pl.LS, b->d_proj + b->desc[s].proj_off);
+            TDSEZ_HIP_TRY(hipGetLastError());
+        }
     }
     TDSEZ_HIP_TRY(hipDeviceSynchronize());
     return TDSEZ_OK;
@@ -421,7 +299,8 @@ tdsez_status upload_descriptors(BatchData* b, hipStream_t stream) {
 }
 
 tdsez_status launch_propagate(BatchData* b, double* psi, const double* E, double* obs,
-                              tdsez_precision prec, unsigned obs_mask, hipStream_t stream, bool probe) {
+                              tdsez_precision prec, unsigned obs_mask, hipStream_t stream, bool probe,
+                              double* ext) {
     const int nsys = (int)b->sys.size();
     if (tdsez_status st = upload_descriptors(b, stream)) return st;
     long long maxL = 1, maxN = 1;
@@ -431,7 +310,8 @@ tdsez_status launch_propagate(BatchData* b, double* psi, const double* E, double
     }
     {
         dim3 grid((unsigned)std::min<long long>((maxL + 255) / 256, 1024), nsys);
-        pack_state_kernel<<<grid, 256, 0, stream>>>(b->d_desc, psi, b->d_state);
+        if (ext && !b->d_c0) TDSEZ_HIP_TRY(hipMalloc(&b->d_c0, 2 * sizeof(double) * (size_t)b->state_elems));
+        pack_state_kernel<<<grid, 256, 0, stream>>>(b->d_desc, psi, b->d_state, ext ? b->d_c0 : nullptr);
         TDSEZ_HIP_TRY(hipGetLastError());
     }
     KernelArgs ka;
@@ -450,6 +330,13 @@ tdsez_status launch_propagate(BatchData* b, double* psi, const double* E, double
     ka.norm_tol = b->norm_tol;
     ka.status = b->d_status;
     ka.prof = b->d_prof;
+    ka.refine_tol = b->refine_tol;
+    ka.c0 = ext ? b->d_c0 : nullptr;
+    ka.proj = b->d_proj;
+    ka.ext = ext;
+    // the extended kernels: an absorber in some system, the extended series,
+    // or the a_Q part of a requested acceleration
+    const bool xt = b->any_cap || ext != nullptr || (b->any_aq && (obs_mask & TDSEZ_OBS_ACCEL));
     const bool fp64 = prec == TDSEZ_FP64;
     ka.band = fp64 ? (const void*)b->d_band64 : (const void*)b->d_band32;
     ka.refine = fp64 ? 0 : b->refine;
@@ -459,31 +346,16 @@ tdsez_status launch_propagate(BatchData* b, double* psi, const double* E, double
     // streams at the default priority).
     const int n2 = b->nsplit, n1 = nsys - b->nsplit;
     hipStream_t s1 = stream;
-    if (n2 > 0) {
+    if (n2 > 0 && n1 > 0) {
         TDSEZ_HIP_TRY(hipEventRecord(b->ev_fork, stream));
         TDSEZ_HIP_TRY(hipStreamWaitEvent(b->side, b->ev_fork, 0));
         s1 = b->side;
-        if (fp64) {
-            if (probe) tune_probe2_kernel<double><<<n2, 2 * kWave, 0, stream>>>(ka);
-            else propagate2_kernel<double><<<n2, 2 * kWave, 0, stream>>>(ka);
-        } else {
-            if (probe) tune_probe2_kernel<float><<<n2, 2 * kWave, 0, stream>>>(ka);
-            else propagate2_kernel<float><<<n2, 2 * kWave, 0, stream>>>(ka);
-        }
-        TDSEZ_HIP_TRY(hipGetLastError());
     }
-    if (n1 > 0) {
-        ka.order_off = n2;
-        if (fp64) {
-            if (probe) tune_probe_kernel<double><<<n1, kWave, 0, s1>>>(ka);
-            else propagate_kernel<double><<<n1, kWave, 0, s1>>>(ka);
-        } else {
-            if (probe) tune_probe_kernel<float><<<n1, kWave, 0, s1>>>(ka);
-            else propagate_kernel<float><<<n1, kWave, 0, s1>>>(ka);
-        }
-        TDSEZ_HIP_TRY(hipGetLastError());
-    }
-    if (n2 > 0) {
+    hipError_t le;
+    if (xt) le = fp64 ? launch_prop_xt64(ka, n2, n1, stream, s1) : launch_prop_xt32(ka, n2, n1, stream, s1);
+    else le = fp64 ? launch_prop_f64(ka, n2, n1, stream, s1, probe) : launch_prop_f32(ka, n2, n1, stream, s1, probe);
+    TDSEZ_HIP_TRY(le);
+    if (n2 > 0 && n1 > 0) {
         TDSEZ_HIP_TRY(hipEventRecord(b->ev_join, b->side));
         TDSEZ_HIP_TRY(hipStreamWaitEvent(stream, b->ev_join, 0));
     }

@@ -19,7 +19,10 @@ FP64 = 0
 FP32_REFINED = 1
 OBS_NORM, OBS_DIPOLE, OBS_ACCEL = 1, 2, 4
 OBS_ALL = 7
-BAND = {"S": 0, "T": 1, "V": 2, "D": 3, "G": 4, "Mi": 5, "H0": 6}
+EXT_SERIES = 1
+EXT_COLUMNS = ("E_kin", "E_pot", "E_int", "E_tot", "minv", "velocity", "a_Q", "W", "auto_re", "auto_im")
+BAND = {"S": 0, "T": 1, "V": 2, "D": 3, "G": 4, "Mi": 5, "H0": 6, "K": 7, "W": 8, "Q": 9}
+PROFILE_COLUMNS = 10
 
 
 class TdsezError(RuntimeError):
@@ -56,6 +59,12 @@ def lib():
         "tdsez_batch_set": [vp, ctypes.c_char_p, d],
         "tdsez_propagate_batched": [vp, vp, lp, vp, lp, dp, ip, i, u, vp, lp, vp],
         "tdsez_propagate": [vp, vp, vp, d, i, i, u, vp, vp],
+        "tdsez_propagate_batched_ext": [vp, vp, lp, vp, lp, dp, ip, i, u, vp, lp, u, vp, lp, vp],
+        "tdsez_propagate_ext": [vp, vp, vp, d, i, i, u, vp, u, vp, vp],
+        "tdsez_set_cap": [vp, dp],
+        "tdsez_set_aq": [vp, dp, dp],
+        "tdsez_set_projectors": [vp, i, dp],
+        "tdsez_ext_columns": [vp, ip],
         "tdsez_adjoint_batched": [vp, vp, lp, vp, lp, dp, ip, i, u, vp, lp, vp, vp, i, vp],
         "tdsez_assemble_2d": [dp, i, dp, i, i, i, dp, ctypes.POINTER(vp)],
         "tdsez_system2d_size": [vp, ip, ip, ip],
@@ -151,10 +160,48 @@ def assemble(breaks, order, nq, minv_q=None, V_q=None, dV_q=None):
 
 def assemble_workload(sysdef):
     """Assemble a workloads.System: sample its m^-1, V, V' at the library's
-    own quadrature points."""
+    own quadrature points; an absorber mask meta["eta"] and a_Q samples
+    meta["aq"] = (g, h) (callables) are set as well."""
     xq = quad_points(sysdef.breaks, sysdef.nq)
     minv, V, dV = sysdef.sample(xq)
-    return assemble(sysdef.breaks, sysdef.order, sysdef.nq, None if sysdef.const_mass else minv, V, dV)
+    g = assemble(sysdef.breaks, sysdef.order, sysdef.nq, None if sysdef.const_mass else minv, V, dV)
+    meta = getattr(sysdef, "meta", None) or {}
+    if meta.get("eta") is not None:
+        set_cap(g, meta["eta"](xq))
+    if meta.get("aq") is not None:
+        fg, fh = meta["aq"]
+        set_aq(g, None if fg is None else fg(xq), None if fh is None else fh(xq))
+    return g
+
+
+def set_cap(sys, eta_q):
+    """Absorbing potential from the mask samples at the quadrature points
+    (None removes it)."""
+    a = None if eta_q is None else _f64(eta_q)
+    _check(lib().tdsez_set_cap(sys.handle, None if a is None else _dptr(a)))
+
+
+def set_aq(sys, g_q, h_q):
+    """a_Q form from samples of g = mu mu_1 and h = mu_1 mu_2 + mu mu_3."""
+    a = None if g_q is None else _f64(g_q)
+    b = None if h_q is None else _f64(h_q)
+    _check(lib().tdsez_set_aq(sys.handle, None if a is None else _dptr(a), None if b is None else _dptr(b)))
+
+
+def set_projectors(sys, phi):
+    """Projection states of the population series: (npop, N) real array, or
+    None / empty to remove them."""
+    if phi is None or len(phi) == 0:
+        _check(lib().tdsez_set_projectors(sys.handle, 0, None))
+        return
+    a = _f64(np.asarray(phi).reshape(len(phi), sys.N))
+    _check(lib().tdsez_set_projectors(sys.handle, a.shape[0], _dptr(a)))
+
+
+def ext_columns(sys):
+    n = ctypes.c_int()
+    _check(lib().tdsez_ext_columns(sys.handle, ctypes.byref(n)))
+    return n.value
 
 
 def system_size(sys):
@@ -221,10 +268,11 @@ def _check_dev(t, dtype):
 
 
 def propagate_batched(batch, psi_packed, psi_off, E_packed, E_off, dt, nsteps, prec=FP64, obs=OBS_ALL,
-                      obs_packed=None, obs_off=None, stream=None):
+                      obs_packed=None, obs_off=None, stream=None, ext=0, ext_packed=None, ext_off=None):
     """psi_packed: torch complex128 (device, in/out); E_packed: torch float64
-    (device); obs_packed: torch float64 (device) or None.  Offsets, dt and
-    nsteps are host sequences."""
+    (device); obs_packed: torch float64 (device) or None; with ext =
+    EXT_SERIES the extended series go to ext_packed (device float64) at the
+    host offsets ext_off.  Offsets, dt and nsteps are host sequences."""
     import torch
     _check_dev(psi_packed, torch.complex128)
     _check_dev(E_packed, torch.float64)
@@ -242,10 +290,19 @@ def propagate_batched(batch, psi_packed, psi_off, E_packed, E_off, dt, nsteps, p
     else:
         oo, op_ = _longs(np.zeros(n))
         optr = None
-    _check(lib().tdsez_propagate_batched(batch.handle, ctypes.c_void_p(psi_packed.data_ptr()), pp,
-                                         ctypes.c_void_p(E_packed.data_ptr()), ep, _dptr(dtv),
-                                         ns.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), int(prec), int(obs),
-                                         optr, op_, _stream_handle(stream)))
+    if ext:
+        _check_dev(ext_packed, torch.float64)
+        xo, xp = _longs(ext_off)
+        if len(xo) != n:
+            raise TdsezError(1, "per-system arrays must have one entry per system")
+        xptr = ctypes.c_void_p(ext_packed.data_ptr())
+    else:
+        xo, xp = _longs(np.zeros(n))
+        xptr = None
+    _check(lib().tdsez_propagate_batched_ext(batch.handle, ctypes.c_void_p(psi_packed.data_ptr()), pp,
+                                             ctypes.c_void_p(E_packed.data_ptr()), ep, _dptr(dtv),
+                                             ns.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), int(prec), int(obs),
+                                             optr, op_, int(ext), xptr, xp, _stream_handle(stream)))
 
 
 def adjoint_batched(batch, psi0_packed, psi_off, E_packed, E_off, dt, nsteps, obs, dJdobs_packed, obs_off,
@@ -324,15 +381,20 @@ def observable_series(E_packed, batch, psi0_packed, psi_off, E_off, dt, nsteps, 
     return _OBS_FN.apply(E_packed, batch, psi0_packed, psi_off, E_off, dt, nsteps, obs_off, obs, prec, ckpt_stride)
 
 
-def propagate(sys, psi, E, dt, nsteps, prec=FP64, obs=OBS_ALL, obs_out=None, stream=None):
+def propagate(sys, psi, E, dt, nsteps, prec=FP64, obs=OBS_ALL, obs_out=None, stream=None, ext=0, ext_out=None):
+    """Single-system propagation; with ext = EXT_SERIES the extended series
+    go to ext_out (device float64, (nsteps+1) * ext_columns(sys))."""
     import torch
     _check_dev(psi, torch.complex128)
     _check_dev(E, torch.float64)
     if obs:
         _check_dev(obs_out, torch.float64)
-    _check(lib().tdsez_propagate(sys.handle, ctypes.c_void_p(psi.data_ptr()), ctypes.c_void_p(E.data_ptr()),
-                                 float(dt), int(nsteps), int(prec), int(obs),
-                                 ctypes.c_void_p(obs_out.data_ptr()) if obs else None, _stream_handle(stream)))
+    if ext:
+        _check_dev(ext_out, torch.float64)
+    _check(lib().tdsez_propagate_ext(sys.handle, ctypes.c_void_p(psi.data_ptr()), ctypes.c_void_p(E.data_ptr()),
+                                     float(dt), int(nsteps), int(prec), int(obs),
+                                     ctypes.c_void_p(obs_out.data_ptr()) if obs else None, int(ext),
+                                     ctypes.c_void_p(ext_out.data_ptr()) if ext else None, _stream_handle(stream)))
 
 
 def batch_status(batch, stream=None):
@@ -344,10 +406,10 @@ def batch_status(batch, stream=None):
 def batch_profile(batch, stream=None):
     """Average cycles per step per phase, one row per system: (rhs, elim,
     fill, reduced, backsub, refine residual, refine reduced, refine backsub,
-    partition count)."""
-    out = np.zeros(9 * len(batch.systems))
+    partition count, largest relative refinement residual)."""
+    out = np.zeros(PROFILE_COLUMNS * len(batch.systems))
     _check(lib().tdsez_batch_profile(batch.handle, _stream_handle(stream), _dptr(out)))
-    return out.reshape(-1, 9)
+    return out.reshape(-1, PROFILE_COLUMNS)
 
 
 def autotune(batch, prec=None, budget_ms=2000.0):

@@ -128,12 +128,18 @@ def test_short_propagation_matches_oracle(name, prec):
     dt = sd.dt if sd.dt else 0.05
     ns = min(sd.nsteps or 300, 300)
     ref, cref = O.propagate(m, psi0, E, dt, ns)
-    got, cgot = run_gpu(g, psi0, E, dt, ns, prec)
+    # a position-dependent mass needs the a_Q form for the acceleration
+    # (refused without it, eq. pdm_acceleration); norm and dipole here
+    obs = T.OBS_ALL if sd.const_mass else T.OBS_NORM | T.OBS_DIPOLE
+    got, cgot = run_gpu(g, psi0, E, dt, ns, prec, obs)
+    if not sd.const_mass:
+        with pytest.raises(T.TdsezError) as e:
+            run_gpu(g, psi0, E, dt, ns, prec, T.OBS_ALL)
+        assert e.value.status == 7
     if prec == T.FP64:
-        # the acceleration -Re c^H G c - E Re c^H Mi c is compared for every
-        # mass model (with position-dependent mass Mi differs from S and is
-        # read from its own band)
-        for k in (0, 1, 2):
+        # the acceleration -Re c^H G c - E Re c^H Mi c is compared for
+        # constant mass (Mi = S)
+        for k in ((0, 1, 2) if sd.const_mass else (0, 1)):
             assert rel(got[:, k], ref[:, k]) < 1e-10, (k, rel(got[:, k], ref[:, k]))
         assert rel(cgot, cref) < 1e-11
     else:
@@ -197,9 +203,10 @@ def test_tiny_systems_and_padding(nbr, order):
     psi0 = rng.normal(size=N) + 1j * rng.normal(size=N)
     E = 0.1 * np.sin(0.3 * np.arange(41))
     ref, cref = O.propagate(m, psi0, E, 0.1, 40)
-    for prec, tol in ((T.FP64, 1e-11), (T.FP32_REFINED, 1e-4)):
+    for prec, tol in ((T.FP64, 1e-11), (T.FP32_REFINED, 1e-5)):
         # random initial states carry high-energy components, where the FP32
-        # factorisation error is largest
+        # factorisation error is largest; the refinement sweep still meets
+        # the 1e-5 bar
         got, cgot = run_gpu(g, psi0, E, 0.1, 40, prec)
         for k in range(3):
             assert rel(got[:, k], ref[:, k]) < tol, (prec, k)
@@ -255,7 +262,7 @@ def test_batched_uneven_systems_match_oracle():
                 for k in range(3):
                     assert rel(gi[:, k], r[:, k]) < tol, (i, k, rel(gi[:, k], r[:, k]))
             else:
-                assert rel(gi[:, 1], r[:, 1]) < 1e-4, (i, rel(gi[:, 1], r[:, 1]))
+                assert rel(gi[:, 1], r[:, 1]) < 1e-5, (i, rel(gi[:, 1], r[:, 1]))
 
 
 def test_nonfinite_state_is_latched():
