@@ -80,22 +80,51 @@ def _oracle_worker(args):
     return sd.ndof * nsteps, time.perf_counter() - t0
 
 
+def host_info():
+    """Host core count and CPU model (the oracle's timing context)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:
+        affinity = os.cpu_count()
+    return {"nproc": affinity, "cpu_count": os.cpu_count(), "cpu_model": model}
+
+
+# worker processes of the oracle baseline: one per host core, at most 16
+# (the share of host cores that goes with one GPU)
+MAX_WORKERS = 16
+
+
 def cpu_baseline(nsys_sample, nsteps):
     """The oracle (serial FP64 C) on a bounded sample of the batch: one
-    system per worker process, one worker per host core (at most 16)."""
+    system per worker process, one worker per host core (at most
+    MAX_WORKERS).  The rate is DOF-steps of the sample per wall second; as a
+    per-DOF-step rate it stands for the whole batch (extrapolated, not run)."""
     import multiprocessing as mp
     from oracle import oracle as O
     O.build()
-    cores = min(16, os.cpu_count() or 1)
+    info = host_info()
+    cores = min(MAX_WORKERS, info["nproc"] or 1)
     jobs = [(i, nsteps) for i in range(nsys_sample)]
     t0 = time.perf_counter()
     with mp.get_context("fork").Pool(cores) as pool:
         res = pool.map(_oracle_worker, jobs)
     wall = time.perf_counter() - t0
     dofsteps = sum(r[0] for r in res)
-    return {"value": dofsteps / wall, "unit": "DOF-steps/s", "cores": cores, "kind": "oracle",
-            "sample": "first %d systems of the batch, %d steps each (%.3g DOF-steps), serial FP64 C, "
-                      "one system per process, wall %.1f s" % (nsys_sample, nsteps, dofsteps, wall)}
+    out = {"value": dofsteps / wall, "unit": "DOF-steps/s", "cores": cores, "kind": "oracle",
+           "sample": "first %d systems of the batch, %d steps each (%.3g DOF-steps), serial FP64 C, one system "
+                     "per worker process on %d workers, wall %.1f s; the per-DOF-step rate is extrapolated to the "
+                     "full batch, not run on it" % (nsys_sample, nsteps, dofsteps, cores, wall)}
+    out.update(info)
+    return out
 
 
 def main():
@@ -113,10 +142,11 @@ def main():
     ap.add_argument("--split", type=int, default=160,
                     help="run this many of the costliest systems on two waves each (setup, untimed; "
                          "160 of 1024 measured best, 0 = one wave per system)")
-    ap.add_argument("--workload", choices=["batch1d", "2d", "h2p"], default="batch1d",
+    ap.add_argument("--workload", choices=["batch1d", "2d", "h2p", "adjoint"], default="batch1d",
                     help="batch1d: the batched 1D benchmark (default); 2d: a segment of the 512 x 512 "
                          "tensor-product workload; h2p: the 1D H2+ model (30 007 splines, one long "
-                         "chain) over its whole pulse")
+                         "chain) over its whole pulse; adjoint: the pulse gradient of 64 double quantum "
+                         "wells (N 1500, 20 000 steps, 64 amplitudes)")
     ap.add_argument("--steps-2d", type=int, default=400, help="time steps of the 2D segment")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -128,6 +158,9 @@ def main():
         return
     if args.workload == "h2p":
         run_h2p(args)
+        return
+    if args.workload == "adjoint":
+        run_adjoint(args)
         return
 
     import torch
@@ -144,7 +177,7 @@ def main():
     psi_init, po, E, eo, obs, oo = T.pack_batch_inputs(defs, [np.zeros(s.ndof) for s in defs], dev)
     # initial states: every system's ground state (batched FP64 shift-and-invert on the GPU)
     t_gs = time.perf_counter()
-    T.ground_state_batched(batch, psi_init, po)
+    eps0 = T.ground_state_batched(batch, psi_init, po)
     torch.cuda.synchronize()
     t_gs = time.perf_counter() - t_gs
     dts = [s.dt for s in defs]
@@ -200,13 +233,18 @@ def main():
     ms32 = results["fp32-refined"] * 1000.0
     value = dofsteps / results["fp32-refined"]
     eps_d = None
+    eps_s = None
     if "fp64" in obs_by:
-        e = []
+        from paper_2608_18472_amd import spectrum as SP
+        e, es = [], []
         for i in range(len(defs)):
             a = obs_by["fp32-refined"][3 * eo[i]: 3 * eo[i] + 3 * (nsteps[i] + 1)].reshape(-1, 3)[:, 1]
             b = obs_by["fp64"][3 * eo[i]: 3 * eo[i] + 3 * (nsteps[i] + 1)].reshape(-1, 3)[:, 1]
             e.append(np.linalg.norm(a - b) / np.linalg.norm(b))
+            qc = SP.cutoff_order(-eps0[i], defs[i].meta["E0"], defs[i].meta["omega"])
+            es.append(SP.plateau_error(a, b, defs[i].dt, defs[i].meta["omega"], qc))
         eps_d = float(max(e))
+        eps_s = float(max(es))
     # algorithmic bytes of one launch (FP32: 4-byte reals, 8-byte complex)
     alg_bytes = sum(s.ndof * s.nsteps * algorithmic_bytes(s.order, 4, 8) for s in defs)
     achieved = alg_bytes / results["fp32-refined"] / 1e9
@@ -237,6 +275,9 @@ def main():
             "fp64_value": dofsteps / results["fp64"] if "fp64" in results else None,
             "fp64_ms_per_step": results["fp64"] * 1000.0 if "fp64" in results else None,
             "dipole_rel_err_fp32_vs_fp64": eps_d,
+            "spectrum_err_fp32_vs_fp64_dex": eps_s,
+            "spectrum_metric": "max over systems and odd harmonics 3..q_cut+6 of |log10 S_fp32 - log10 S_fp64|, "
+                               "S = w^4 |FT[d W]|^2, Kaiser window beta 8, q_cut = (Ip + 3.17 Up)/w",
             "refine_sweeps": 1,
             "two_wave_systems": int(T.batch_two_wave(batch).sum()),
             "autotune": tuned if tuned else None,
@@ -403,6 +444,145 @@ def run_h2p(args):
     print(json.dumps(line), flush=True)
 
 
+def run_adjoint(args):
+    """The pulse-gradient workload: 64 double quantum wells (N 1500, order 8,
+    20 000 steps, config-2 geometry) driven by 64-amplitude Fourier pulses;
+    one gradient = the differentiable forward series (one persistent
+    propagation launch, FP64) and its backward (the discrete-adjoint launch
+    with sqrt(Nt) checkpoints).  Metric: gradient DOF-steps/s = sum N nsteps
+    / (forward + adjoint time); roofline of the adjoint launch with
+    3 (3 (p+1) 8 + 2 16) = 672 algorithmic bytes per DOF-step (the
+    checkpointing forward sweep, the segment recomputation and the adjoint
+    step, each reading the S, H0, D bands and a state in and out)."""
+    import torch
+    from paper_2608_18472_amd import tdsez as T
+    from paper_2608_18472_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    defs, thetas, basis = W.config5()
+    omega = defs[0].meta["omega"]
+    gs = [T.assemble_workload(s) for s in defs]
+    ev, vec = T.ground_state(gs[0], 2)  # nev 2: the lowest doublet of the double well
+    psi0 = vec[0].astype(np.complex128)
+    b = T.batch_create(gs)
+    psi, po, E, eo, obs, oo = T.pack_batch_inputs(defs, [psi0] * len(defs))
+    Bt = torch.from_numpy(basis).cuda()
+    dt = [s.dt for s in defs]
+    ns = [s.nsteps for s in defs]
+    mask = T.OBS_NORM | T.OBS_DIPOLE
+    stream = torch.cuda.current_stream()
+    dofsteps = float(sum(s.ndof * s.nsteps for s in defs))
+
+    def gradient():
+        th = torch.from_numpy(thetas.copy()).cuda().requires_grad_(True)
+        Ep = torch.cat([Bt @ th[i] for i in range(len(defs))])
+        ev0, ev1, ev2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        ev0.record(stream)
+        ser = T.observable_series(Ep, b, psi, po, eo, dt, ns, oo, mask)
+        ev1.record(stream)
+        J = 0.0
+        for i in range(len(defs)):
+            d = ser[oo[i]: oo[i] + 3 * (ns[i] + 1)].reshape(-1, 3)[:, 1]
+            J = J + W.harmonic_yield(d, dt[i], omega)
+        J.backward()
+        ev2.record(stream)
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1) / 1e3, ev1.elapsed_time(ev2) / 1e3, th.grad
+
+    for _ in range(max(args.warmup, 1)):
+        gradient()
+    # the adjoint launch alone, timed with events on its stream, from the
+    # series' gradient of the last evaluation
+    ser = torch.zeros_like(obs)
+    psi_w = psi.clone()
+    Ep = torch.cat([Bt @ torch.from_numpy(thetas[i]).cuda() for i in range(len(defs))])
+    T.propagate_batched(b, psi_w, po, Ep, eo, dt, ns, T.FP64, mask, ser, oo)
+    T.batch_status(b)
+    sr = ser.clone().requires_grad_(True)
+    J = 0.0
+    for i in range(len(defs)):
+        d = sr[oo[i]: oo[i] + 3 * (ns[i] + 1)].reshape(-1, 3)[:, 1]
+        J = J + W.harmonic_yield(d, dt[i], omega)
+    J.backward()
+    dJ = sr.grad.contiguous()
+    gE = torch.zeros_like(Ep)
+    ta = []
+    for _ in range(max(args.steps, 1)):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        T.adjoint_batched(b, psi, po, Ep, eo, dt, ns, mask, dJ, oo, gE, None, 0, T.FP64, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        T.batch_status(b)
+        ta.append(e0.elapsed_time(e1) / 1e3)
+    t_adj = float(np.mean(ta))
+    tf, tb = [], []
+    for _ in range(max(args.steps, 1)):
+        f, bk, g = gradient()
+        tf.append(f)
+        tb.append(bk)
+    t_f, t_b = float(np.mean(tf)), float(np.mean(tb))
+    alg = dofsteps * 3 * (3 * 8 * 8 + 2 * 16)
+    cpu = None if args.no_cpu else cpu_baseline_adjoint(2000)
+    line = {
+        "metric": "gradient DOF-steps/s per GPU (discrete adjoint of the pulse-gradient workload, FP64)",
+        "value": dofsteps / (t_f + t_b),
+        "unit": "DOF-steps/s",
+        "n_gpus": 1,
+        "steps": max(args.steps, 1),
+        "warmup": max(args.warmup, 1),
+        "ms_per_step": 1000.0 * (t_f + t_b),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "64 GaAs/AlGaAs double quantum wells (10 nm wells, 4 nm barrier, N 1500, order 8), "
+                        "Fourier pulses with 64 amplitudes (8-cycle 0.3 eV sin^2 fit + 10% seeded noise), "
+                        "20000 steps, J = harmonic yield of orders 15-35, sqrt(Nt) checkpoints",
+            "systems": len(defs),
+            "dof_steps": dofsteps,
+            "forward_s": t_f,
+            "backward_s": t_b,
+            "adjoint_launch_s": t_adj,
+            "algorithmic_bytes_adjoint_launch": alg,
+        },
+        "roofline": {"bound": "hbm", "achieved": alg / t_adj / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": alg / t_adj / 1e9 / HBM_PEAK_GBS, "traffic": None},
+    }
+    if cpu is not None:
+        line["cpu_baseline"] = cpu
+    print(json.dumps(line), flush=True)
+
+
+def cpu_baseline_adjoint(nsteps):
+    """The oracle's FP64 adjoint (forward storing every state, then the
+    reverse sweep) on one system of the workload for its first nsteps steps,
+    one core; DOF-steps of the gradient per second."""
+    from oracle import oracle as O
+    from paper_2608_18472_amd import workloads as W
+    O.build()
+    defs, thetas, basis = W.config5(nsys=1)
+    sd = defs[0]
+    m = O.assemble(sd.breaks, sd.order, sd.nq, sd.minv, sd.V, sd.dV)
+    xq, _ = O.quad_points(sd.breaks, sd.nq)
+    vmin = float(np.min(sd.V(xq)))
+    ev, vec = O.eig_banded(m["H0"], m["S"], 2, vmin - 1e-3 * (abs(vmin) + 1.0))
+    rng = np.random.default_rng(0)
+    dJ = np.zeros((nsteps + 1, 3))
+    dJ[:, 1] = rng.normal(size=nsteps + 1)
+    t0 = time.perf_counter()
+    O.adjoint(m, vec[0].astype(np.complex128), sd.E, sd.dt, nsteps, dJ, with_accel=False)
+    wall = time.perf_counter() - t0
+    dof = sd.ndof * nsteps
+    out = {"value": dof / wall, "unit": "DOF-steps/s", "cores": 1, "kind": "oracle",
+           "sample": "oracle FP64 adjoint of one system, first %d steps (%.3g DOF-steps), one core, wall %.1f s; "
+                     "per-DOF-step rate" % (nsteps, dof, wall)}
+    out.update(host_info())
+    return out
+
+
 def cpu_baseline_h2p(nsteps):
     """The oracle (serial FP64 C, one core: a single system) on the first
     nsteps steps of the H2+ workload."""
@@ -416,9 +596,11 @@ def cpu_baseline_h2p(nsteps):
     O.propagate(m, vec[0].astype(np.complex128), sd.E, sd.dt, nsteps)
     wall = time.perf_counter() - t0
     dof = sd.ndof * nsteps
-    return {"value": dof / wall, "unit": "DOF-steps/s", "cores": 1, "kind": "oracle",
-            "sample": "first %d steps of the H2+ pulse (%.3g DOF-steps), serial FP64 C, wall %.1f s"
-                      % (nsteps, dof, wall)}
+    out = {"value": dof / wall, "unit": "DOF-steps/s", "cores": 1, "kind": "oracle",
+           "sample": "first %d steps of the H2+ pulse (%.3g DOF-steps), serial FP64 C, wall %.1f s"
+                     % (nsteps, dof, wall)}
+    out.update(host_info())
+    return out
 
 
 def cpu_baseline_2d(nsteps):
@@ -442,9 +624,11 @@ def cpu_baseline_2d(nsteps):
     O.propagate_2d(m2, psi0, E, sd.dt, nsteps, tol=1e-12)
     wall = time.perf_counter() - t0
     dof = m2["Nx"] * m2["Ny"] * nsteps
-    return {"value": dof / wall, "unit": "DOF-steps/s", "cores": cores, "kind": "oracle",
-            "sample": "128 x 128 reduced grid of the 2D workload, %d steps (%.3g DOF-steps), C operator with "
-                      "NumPy/BLAS preconditioner transforms, wall %.1f s" % (nsteps, dof, wall)}
+    out = {"value": dof / wall, "unit": "DOF-steps/s", "cores": cores, "kind": "oracle",
+           "sample": "128 x 128 reduced grid of the 2D workload, %d steps (%.3g DOF-steps), C operator with "
+                     "NumPy/BLAS preconditioner transforms, wall %.1f s" % (nsteps, dof, wall)}
+    out.update(host_info())
+    return out
 
 
 def _symband_mul(band, c):

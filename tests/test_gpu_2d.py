@@ -156,3 +156,44 @@ def test_2d_invalid_arguments():
     with pytest.raises(T.TdsezError) as e:
         T.assemble_2d(sd.breaks_x[:5], sd.breaks_y, 6, 10, np.zeros(4 * 10 * (len(sd.breaks_y) - 1) * 10))
     assert e.value.status == 1
+
+
+def test_separable_problem_needs_one_iteration():
+    """With V = 0 and no field the operator is the separable part itself,
+    whose exact inverse is the preconditioner (the per-axis contractions on
+    the matrix cores): every FP64 step converges in one iteration to 1e-13."""
+    bx = W.breaks_uniform(30.0, 70)
+    by = W.breaks_symexp(25.0, 60, 1.2)
+    ns = 20
+    sd = W.System2D("separable", bx, by, 6, lambda x, y: 0.0 * x, 10, np.zeros(ns + 1), 0.05, ns)
+    g = T.assemble_workload_2d(sd)
+    rng = np.random.default_rng(2)
+    psi0 = rng.normal(size=(g.Ny, g.Nx)) + 1j * rng.normal(size=(g.Ny, g.Nx))
+    T.system2d_stats(g)
+    got, _ = run_gpu_2d(sd, psi0, ns, tol=1e-13, g=g)
+    assert np.abs(got[:, 0] / got[0, 0] - 1.0).max() < 1e-11  # the norm is conserved
+    psi = torch.from_numpy(psi0.reshape(-1).copy()).cuda()
+    E = torch.zeros(ns + 1, dtype=torch.float64, device="cuda")
+    o = torch.zeros(3 * (ns + 1), dtype=torch.float64, device="cuda")
+    T.propagate_2d(g, psi, E, sd.dt, ns, T.FP64, 3, o, tol=1e-13, maxit=50)
+    steps, its, mx, sweeps = T.system2d_stats(g)
+    say("separable: %d steps, %d iterations, max %d" % (steps, its, mx))
+    assert steps == ns and mx == 1
+
+
+@pytest.mark.parametrize("prec", [T.FP64, T.FP32_REFINED])
+def test_exhausted_iteration_budget_latches_enoconv(prec):
+    """maxit caps every step's iteration budget; a solve that needs more
+    reports ENOCONV when the call ends (every kernel still completes)."""
+    sd = small_case(4)
+    g = T.assemble_workload_2d(sd)
+    psi0 = product_ground_state(sd)
+    psi = torch.from_numpy(psi0.reshape(-1).copy()).cuda()
+    E = torch.from_numpy(sd.E.copy()).cuda()
+    o = torch.zeros(3 * 5, dtype=torch.float64, device="cuda")
+    with pytest.raises(T.TdsezError) as e:
+        T.propagate_2d(g, psi, E, sd.dt, 4, prec, 3, o, tol=1e-14, maxit=1)
+    assert e.value.status == 4
+    # the same system with a sufficient budget converges
+    psi = torch.from_numpy(psi0.reshape(-1).copy()).cuda()
+    T.propagate_2d(g, psi, E, sd.dt, 4, prec, 3, o, tol=1e-13, maxit=100)
