@@ -52,6 +52,8 @@ def lib():
         L.orc_adjoint.argtypes = [i, i, dp, dp, dp, dp, dp, dp, dp, d, i, dp, dp, dp]
         L.orc_assemble_v2.argtypes = [dp, i, dp, i, i, i, dp, dp]
         L.orc_assemble_extra.argtypes = [dp, i, i, i, dp, dp, dp, dp, dp, dp, dp]
+        L.orc_assemble_v3.argtypes = [dp, i, dp, i, dp, i, i, i, dp, dp]
+        L.orc_apply_3d.argtypes = [i, i, i, i, dp, dp, dp, dp, dp, dp, dp, dp, d, d, d, d, d, dp, dp]
         L.orc_velocity.argtypes = [i, i, dp, dp]
         L.orc_velocity.restype = d
         L.orc_ext_columns.argtypes = [i]
@@ -374,3 +376,108 @@ def propagate_2d(m2, psi0, E, dt, nsteps, tol=1e-14):
         rhs = apply_2d(m2, c, 1.0, -1j * alpha, Eb)
         c, _ = cn_solve_2d(m2, rhs, alpha, Eb, x0=c, fdm=fdm, tol=tol)
     return obs, c.reshape(m2["Ny"], m2["Nx"])
+
+
+# --------------------------------------------------------------------------
+# Three dimensions (tensor-product basis, constant mass, x-polarised field)
+# --------------------------------------------------------------------------
+def assemble_3d(breaks_x, breaks_y, breaks_z, order, nq, V):
+    """Matrices of the 3D problem: per-axis S, T, D half bands (1D assembly
+    with V = 0) and the potential stencil V3 (orc_assemble_v3) for the
+    callable V(x, y, z) sampled on the tensor grid of the per-axis
+    quadrature points."""
+    bx, by, bz = _f64(breaks_x), _f64(breaks_y), _f64(breaks_z)
+    ms = [assemble(b, order, nq) for b in (bx, by, bz)]
+    qs = [quad_points(b, nq)[0] for b in (bx, by, bz)]
+    Z, Y, X = np.meshgrid(qs[2], qs[1], qs[0], indexing="ij")
+    Vq = _f64(V(X, Y, Z))
+    Nx, Ny, Nz, p = ms[0]["N"], ms[1]["N"], ms[2]["N"], ms[0]["p"]
+    w = 2 * p + 1
+    V3 = np.zeros((Nz * Ny * Nx, w, w, w))
+    _check(lib().orc_assemble_v3(_p(bx), len(bx), _p(by), len(by), _p(bz), len(bz), order, nq, _p(Vq), _p(V3)),
+           "assemble_v3")
+    return {"Nx": Nx, "Ny": Ny, "Nz": Nz, "p": p, "Sx": ms[0]["S"], "Tx": ms[0]["T"], "Dx": ms[0]["D"],
+            "Sy": ms[1]["S"], "Ty": ms[1]["T"], "Sz": ms[2]["S"], "Tz": ms[2]["T"], "V3": V3}
+
+
+def apply_3d(m3, c, a, b, Ebar, with_V=True):
+    """a S3 c + b (T3 + V3 + Ebar D3) c for complex scalars a, b."""
+    c = _c128(np.asarray(c).reshape(-1))
+    y = np.zeros_like(c)
+    _check(lib().orc_apply_3d(m3["Nx"], m3["Ny"], m3["Nz"], m3["p"], *[_p(_f64(m3[k])) for k in
+                                                                      ("Sx", "Tx", "Dx", "Sy", "Ty", "Sz", "Tz")],
+                              _p(_f64(m3["V3"])) if with_V else None, float(np.real(a)), float(np.imag(a)),
+                              float(np.real(b)), float(np.imag(b)), float(Ebar), _p(c.view(np.float64)),
+                              _p(y.view(np.float64))), "apply_3d")
+    return y
+
+
+def _fdm_factors_3d(m3):
+    """Per-axis generalised eigenpairs T Q = S Q Lambda (LAPACK via scipy):
+    S3 + i a T3 is diagonal in Qz (x) Qy (x) Qx."""
+    import scipy.linalg as sl
+    out = []
+    for ax in ("x", "y", "z"):
+        lam, Q = sl.eigh(band_to_dense(m3["T" + ax]), band_to_dense(m3["S" + ax]))
+        out += [lam, Q]
+    return out
+
+
+def cn_solve_3d(m3, rhs, alpha, Ebar, x0=None, fdm=None, tol=1e-14, maxit=500):
+    """Solve (S3 + i a H3(Ebar)) x = rhs by COCG preconditioned with the
+    exact inverse of the separable part S3 + i a T3 (section V.B, eq.
+    cn_system in 3D); stops at relative residual tol."""
+    Nx, Ny, Nz = m3["Nx"], m3["Ny"], m3["Nz"]
+    lx, Qx, ly, Qy, lz, Qz = fdm if fdm is not None else _fdm_factors_3d(m3)
+    den = 1.0 + 1j * alpha * (lz[:, None, None] + ly[None, :, None] + lx[None, None, :])
+
+    def A(v):
+        return apply_3d(m3, v, 1.0, 1j * alpha, Ebar)
+
+    def M(r):
+        R = r.reshape(Nz, Ny, Nx)
+        Z = np.einsum("zc,yb,xa,cba->zyx", Qz.T, Qy.T, Qx.T, R, optimize=True) / den
+        return np.einsum("zc,yb,xa,cba->zyx", Qz, Qy, Qx, Z, optimize=True).reshape(-1)
+
+    b = _c128(np.asarray(rhs).reshape(-1))
+    x = np.zeros_like(b) if x0 is None else _c128(np.asarray(x0).reshape(-1)).copy()
+    r = b - A(x)
+    nb = np.linalg.norm(b)
+    if nb == 0.0:
+        return x, 0
+    z = M(r)
+    pv = z.copy()
+    rho = np.sum(r * z)
+    for it in range(1, maxit + 1):
+        q = A(pv)
+        a = rho / np.sum(pv * q)
+        x += a * pv
+        r -= a * q
+        if np.linalg.norm(r) <= tol * nb:
+            return x, it
+        z = M(r)
+        rho_new = np.sum(r * z)
+        pv = z + (rho_new / rho) * pv
+        rho = rho_new
+    raise OracleError("cn_solve_3d: no convergence to %g in %d iterations" % (tol, maxit))
+
+
+def propagate_3d(m3, psi0, E, dt, nsteps, tol=1e-14):
+    """Crank-Nicolson propagation in 3D (section V.B, Ebar_n = (E_n +
+    E_{n+1})/2): obs[n] = (c^H S3 c, Re c^H D3 c) for n = 0..nsteps and the
+    final state (shape (Nz, Ny, Nx))."""
+    alpha = 0.5 * dt
+    c = _c128(np.asarray(psi0).reshape(-1)).copy()
+    fdm = _fdm_factors_3d(m3)
+    obs = np.zeros((nsteps + 1, 2))
+    for n in range(nsteps + 1):
+        Sc = apply_3d(m3, c, 1.0, 0.0, 0.0, with_V=False)
+        Dc = apply_3d(m3, c, 0.0, 1.0, 1.0) - apply_3d(m3, c, 0.0, 1.0, 0.0)
+        obs[n, 0] = np.real(np.vdot(c, Sc))
+        obs[n, 1] = np.real(np.vdot(c, Dc))
+        if n == nsteps:
+            break
+        Eb = 0.5 * (E[n] + E[n + 1])
+        rhs = apply_3d(m3, c, 1.0, -1j * alpha, Eb)
+        c, _ = cn_solve_3d(m3, rhs, alpha, Eb, x0=c, fdm=fdm, tol=tol)
+    return obs, c.reshape(m3["Nz"], m3["Ny"], m3["Nx"])

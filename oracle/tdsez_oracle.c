@@ -1190,3 +1190,165 @@ int orc_propagate_ext(int N, int p, const double *S, const double *T, const doub
     free(c); free(b); free(c0); free(y); free(A); free(B); free(H0);
     return rc;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Three dimensions: tensor-product basis N_ix(x) N_iy(y) N_iz(z) of the     */
+/* reduced 1D bases (section II.C, eq. tensor3d), constant mass, unknown     */
+/* (iz, iy, ix) at (iz*Ny + iy)*Nx + ix.  S3 = Sx Sy Sz, T3 = Tx Sy Sz +     */
+/* Sx Ty Sz + Sx Sy Tz, D3 = Dx Sy Sz (x-polarised field) from the 1D half   */
+/* bands, and the non-separable potential matrix by the tensor Gauss rule:  */
+/*   V3[(iz,iy,ix),(jz,jy,jx)] = sum_q wx wy wz V(xq,yq,zq)                  */
+/*       N_ix N_jx (xq) N_iy N_jy (yq) N_iz N_jz (zq),                      */
+/* stored as a (2p+1)^3 stencil per row:                                    */
+/*   V3[row*w^3 + ((dz+p)*w + (dy+p))*w + (dx+p)],  w = 2p+1.                */
+/* V_q[(qz*nqy + qy)*nqx + qx] holds the caller's samples on the tensor grid */
+/* of the per-axis quadrature points.  Within a triple of spans the x sum   */
+/* is taken first, then y, then z (a reassociation of the same tensor sum). */
+/* ------------------------------------------------------------------------ */
+int orc_assemble_v3(const double *brx, int nbrx, const double *bry, int nbry, const double *brz, int nbrz,
+                    int order, int nq, const double *V_q, double *V3)
+{
+    const double *br[3] = {brx, bry, brz};
+    int nbr[3] = {nbrx, nbry, nbrz};
+    for (int a = 0; a < 3; ++a)
+        if (check_breaks(br[a], nbr[a]) != ORC_OK) return ORC_EINVAL;
+    if (order < 2 || order > 8 || nq < 1 || nq > 64) return ORC_EINVAL;
+    int p = order - 1, w = 2 * p + 1, w3 = w * w * w, p1 = p + 1;
+    int N[3], nel[3], nqa[3];
+    double *B[3], *wq[3];
+    for (int a = 0; a < 3; ++a) {
+        N[a] = orc_ndof(nbr[a], order);
+        nel[a] = nbr[a] - 1;
+        nqa[a] = nel[a] * nq;
+        if (N[a] < 1) return ORC_EINVAL;
+    }
+    memset(V3, 0, sizeof(double) * (size_t)N[0] * N[1] * N[2] * w3);
+    int ok = 1;
+    for (int a = 0; a < 3; ++a) {
+        double *t = malloc(sizeof(double) * (nbr[a] + 2 * p));
+        double *xq = malloc(sizeof(double) * nqa[a]);
+        wq[a] = malloc(sizeof(double) * nqa[a]);
+        B[a] = malloc(sizeof(double) * (size_t)nqa[a] * p1);
+        if (!t || !xq || !wq[a] || !B[a]) ok = 0;
+        if (ok) {
+            make_knots(br[a], nbr[a], order, t);
+            orc_quad_points(br[a], nbr[a], nq, xq, wq[a]);
+            for (int e = 0; e < nel[a]; ++e)
+                for (int q = 0; q < nq; ++q) {
+                    double dN[16];
+                    bspline_span_eval(t, order, p + e, xq[e * nq + q], B[a] + (size_t)(e * nq + q) * p1, dN);
+                }
+        }
+        free(t); free(xq);
+    }
+    /* per span triple: X[a][b][qy][qz] = sum_qx wx Bx_a Bx_b V, then
+     * Y[a][b][c][d][qz] = sum_qy wy By_c By_d X, then the z sum */
+    double *X = malloc(sizeof(double) * (size_t)p1 * p1 * nq * nq);
+    double *Y = malloc(sizeof(double) * (size_t)p1 * p1 * p1 * p1 * nq);
+    if (!X || !Y) ok = 0;
+    for (int ez = 0; ok && ez < nel[2]; ++ez)
+        for (int ey = 0; ey < nel[1]; ++ey)
+            for (int ex = 0; ex < nel[0]; ++ex) {
+                for (int a = 0; a < p1; ++a)
+                    for (int b = 0; b < p1; ++b)
+                        for (int qz = 0; qz < nq; ++qz)
+                            for (int qy = 0; qy < nq; ++qy) {
+                                double s = 0.0;
+                                int iy = ey * nq + qy, iz = ez * nq + qz;
+                                for (int qx = 0; qx < nq; ++qx) {
+                                    int ix = ex * nq + qx;
+                                    s += wq[0][ix] * B[0][(size_t)ix * p1 + a] * B[0][(size_t)ix * p1 + b] *
+                                         V_q[((size_t)iz * nqa[1] + iy) * nqa[0] + ix];
+                                }
+                                X[((a * p1 + b) * nq + qy) * nq + qz] = s;
+                            }
+                for (int ab = 0; ab < p1 * p1; ++ab)
+                    for (int c = 0; c < p1; ++c)
+                        for (int d = 0; d < p1; ++d)
+                            for (int qz = 0; qz < nq; ++qz) {
+                                double s = 0.0;
+                                for (int qy = 0; qy < nq; ++qy) {
+                                    int iy = ey * nq + qy;
+                                    s += wq[1][iy] * B[1][(size_t)iy * p1 + c] * B[1][(size_t)iy * p1 + d] *
+                                         X[(ab * nq + qy) * nq + qz];
+                                }
+                                Y[((ab * p1 + c) * p1 + d) * nq + qz] = s;
+                            }
+                for (int e = 0; e < p1; ++e) {
+                    int iz = ez + e - 1;
+                    if (iz < 0 || iz >= N[2]) continue;
+                    for (int f = 0; f < p1; ++f) {
+                        int jz = ez + f - 1;
+                        if (jz < 0 || jz >= N[2]) continue;
+                        for (int c = 0; c < p1; ++c) {
+                            int iy = ey + c - 1;
+                            if (iy < 0 || iy >= N[1]) continue;
+                            for (int d = 0; d < p1; ++d) {
+                                int jy = ey + d - 1;
+                                if (jy < 0 || jy >= N[1]) continue;
+                                for (int a = 0; a < p1; ++a) {
+                                    int ix = ex + a - 1;
+                                    if (ix < 0 || ix >= N[0]) continue;
+                                    for (int b = 0; b < p1; ++b) {
+                                        int jx = ex + b - 1;
+                                        if (jx < 0 || jx >= N[0]) continue;
+                                        double s = 0.0;
+                                        for (int qz = 0; qz < nq; ++qz) {
+                                            int q = ez * nq + qz;
+                                            s += wq[2][q] * B[2][(size_t)q * p1 + e] * B[2][(size_t)q * p1 + f] *
+                                                 Y[(((a * p1 + b) * p1 + c) * p1 + d) * nq + qz];
+                                        }
+                                        size_t row = ((size_t)iz * N[1] + iy) * N[0] + ix;
+                                        V3[row * w3 + ((size_t)(jz - iz + p) * w + (jy - iy + p)) * w + (jx - ix + p)] += s;
+                                    }
+                                }
+                            }
+                        }
+                    }
+                }
+            }
+    for (int a = 0; a < 3; ++a) { free(B[a]); free(wq[a]); }
+    free(X); free(Y);
+    return ok ? ORC_OK : ORC_ENOMEM;
+}
+
+/* y = a S3 c + b (T3 + V3 + Ebar D3) c for complex a, b (the two sides of
+ * eq. cn_system in 3D).  c, y interleaved complex, (iz, iy, ix) row-major.
+ * V3 may be NULL (no potential). */
+int orc_apply_3d(int Nx, int Ny, int Nz, int p, const double *Sx, const double *Tx, const double *Dx,
+                 const double *Sy, const double *Ty, const double *Sz, const double *Tz, const double *V3,
+                 double are, double aim, double bre, double bim, double Ebar, const double *cin, double *yout)
+{
+    if (Nx < 1 || Ny < 1 || Nz < 1 || p < 1 || p > 7) return ORC_EINVAL;
+    int w = 2 * p + 1, w3 = w * w * w;
+    const zd *c = (const zd *)cin;
+    zd *y = (zd *)yout;
+    zd a = are + I * aim, b = bre + I * bim;
+    for (int iz = 0; iz < Nz; ++iz)
+        for (int iy = 0; iy < Ny; ++iy)
+            for (int ix = 0; ix < Nx; ++ix) {
+                size_t row = ((size_t)iz * Ny + iy) * Nx + ix;
+                zd s = 0.0;
+                for (int dz = -p; dz <= p; ++dz) {
+                    int jz = iz + dz;
+                    if (jz < 0 || jz >= Nz) continue;
+                    double sz = band_at(Nz, p, Sz, iz, jz), tz = band_at(Nz, p, Tz, iz, jz);
+                    for (int dy = -p; dy <= p; ++dy) {
+                        int jy = iy + dy;
+                        if (jy < 0 || jy >= Ny) continue;
+                        double sy = band_at(Ny, p, Sy, iy, jy), ty = band_at(Ny, p, Ty, iy, jy);
+                        for (int dx = -p; dx <= p; ++dx) {
+                            int jx = ix + dx;
+                            if (jx < 0 || jx >= Nx) continue;
+                            double sx = band_at(Nx, p, Sx, ix, jx), tx = band_at(Nx, p, Tx, ix, jx);
+                            double ddx = band_at(Nx, p, Dx, ix, jx);
+                            double h = tx * sy * sz + sx * ty * sz + sx * sy * tz + Ebar * ddx * sy * sz;
+                            if (V3) h += V3[row * w3 + ((size_t)(dz + p) * w + (dy + p)) * w + (dx + p)];
+                            s += (a * sx * sy * sz + b * h) * c[((size_t)jz * Ny + jy) * Nx + jx];
+                        }
+                    }
+                }
+                y[row] = s;
+            }
+    return ORC_OK;
+}
