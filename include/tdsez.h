@@ -319,6 +319,26 @@ tdsez_status tdsez_propagate_batched_ext(tdsez_batch b, double* psi_packed, cons
 tdsez_status tdsez_propagate(tdsez_system sys, double* psi, const double* E, double dt, int nsteps,
                              tdsez_precision prec, unsigned obs, double* obs_out, void* stream);
 
+/* tdsez_propagate for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  It allocates nothing, on its first call included: the
+ * working storage of the partitioned solve (packed bands, state, factor
+ * rows, separator system, descriptor) lives in one file-scope device array
+ * of 64 MiB per GPU, held until the process ends, and is filled from the
+ * system's bands on every call; the kernels and the plan are those of
+ * tdsez_propagate, so the results are the same.  A system that needs more
+ * than 64 MiB (N above about 50 000 at order 8) is refused with EINVAL.
+ * Every call on a GPU shares that GPU's array: calls that overlap on one
+ * GPU (different streams, threads or processes' graphs replayed
+ * concurrently) race; calls ordered on one stream do not.  dev_status
+ * (device int[4], caller-owned, may be NULL): cleared by the call, then
+ * receives the first latched device error (code, -, step, -) as
+ * tdsez_batch_status reports it.  No absorber, extended series or a_Q form
+ * (EUNSUPPORTED).  Arguments as tdsez_propagate; asynchronous on `stream`. */
+tdsez_status tdsez_propagate_noalloc(tdsez_system sys, double* psi, const double* E, double dt, int nsteps,
+                                     tdsez_precision prec, unsigned obs, double* obs_out, int* dev_status,
+                                     void* stream);
+
 /* tdsez_propagate with the extended series (ext_out: device FP64
  * [(nsteps+1) * (10 + npop)], see TDSEZ_EXT_SERIES). */
 tdsez_status tdsez_propagate_ext(tdsez_system sys, double* psi, const double* E, double dt, int nsteps,

@@ -82,12 +82,6 @@ static void free_batch_device(BatchData* b) {
 
 using namespace tdsez;
 
-struct tdsez_system_s {
-    SystemData d;
-};
-struct tdsez_batch_s {
-    BatchData d;
-};
 
 extern "C" {
 

@@ -241,3 +241,11 @@ tdsez_status ground_state_batched_device(BatchData* b, double sigma, double tol,
                                          double* psi, const long* psi_off);
 
 }  // namespace tdsez
+
+// The opaque handles of the ABI.
+struct tdsez_system_s {
+    tdsez::SystemData d;
+};
+struct tdsez_batch_s {
+    tdsez::BatchData d;
+};

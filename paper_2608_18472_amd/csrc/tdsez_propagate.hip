@@ -37,6 +37,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 
 #include "tdsez_passes.hpp"
 // (the kernels themselves are instantiated in tdsez_prop_*.hip from tdsez_run.hpp)
@@ -368,3 +369,150 @@ tdsez_status launch_propagate(BatchData* b, double* psi, const double* E, double
 }
 
 }  // namespace tdsez
+
+// ---------------------------------------------------------------- no-alloc
+// tdsez_propagate_noalloc: the single-system propagation with every working
+// buffer in one file-scope device array, for callers that cannot allocate.
+namespace tdsez {
+namespace {
+
+constexpr size_t kNoallocBytes = size_t(64) << 20;
+// The array's name is a host-side stand-in in host code: kernels get the
+// per-device address from hipGetSymbolAddress (g_noalloc_ptr), never the name.
+__device__ __align__(256) unsigned char scratch[kNoallocBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[kMaxDevices] = {nullptr};
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// descriptor, workgroup order and cleared status, from kernel arguments (no
+// host buffer outlives the call)
+__global__ void noalloc_setup_kernel(SysDesc d, SysDesc* __restrict__ desc, int* __restrict__ order,
+                                     int* __restrict__ status) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        *desc = d;
+        order[0] = 0;
+        for (int i = 0; i < 4; ++i) status[i] = 0;
+    }
+}
+
+}  // namespace
+}  // namespace tdsez
+
+extern "C" tdsez_status tdsez_propagate_noalloc(tdsez_system sys_h, double* psi, const double* E, double dt,
+                                                int nsteps, tdsez_precision prec, unsigned obs, double* obs_out,
+                                                int* dev_status, void* stream_v) {
+    using namespace tdsez;
+    if (!sys_h || !psi || !E) return fail(TDSEZ_EINVAL, "NULL argument");
+    SystemData* sy = &sys_h->d;
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(TDSEZ_EINVAL, "dt must be > 0");
+    if (nsteps < 0) return fail(TDSEZ_EINVAL, "nsteps < 0");
+    if (prec != TDSEZ_FP64 && prec != TDSEZ_FP32_REFINED) return fail(TDSEZ_EINVAL, "unknown precision %d", (int)prec);
+    if (obs & ~7u) return fail(TDSEZ_EINVAL, "unknown observable bits 0x%x", obs);
+    if (obs && !obs_out) return fail(TDSEZ_EINVAL, "obs requested but obs_out is NULL");
+    if (sy->d_W || sy->d_Q) return fail(TDSEZ_EUNSUPPORTED, "no-alloc propagation: no absorber or a_Q form");
+    if ((obs & TDSEZ_OBS_ACCEL) && !sy->const_mass)
+        return fail(TDSEZ_EUNSUPPORTED, "position-dependent mass: the acceleration needs the a_Q form");
+    // the plan of tdsez_propagate: two waves when that plan has more than 64 chunks
+    Plan pl = make_plan(sy->N, sy->p, 0, kMaxChunks2, 0.3);
+    if (pl.P <= kMaxChunks) pl = make_plan(sy->N, sy->p, 0);
+    const bool two = pl.P > kMaxChunks;
+    // scratch layout
+    const long long nband = (long long)pl.L * kNumMats * (pl.p + 1) * pl.LS;
+    const long long nstate = (long long)pl.L * pl.LS;
+    const long long nfac = (long long)pl.m * fac_items(pl.p) * pl.P;
+    const long long nred = RedLayout<double>::total(pl.p, pl.P);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off += align256(bytes);
+        return at;
+    };
+    const size_t o_desc = take(sizeof(SysDesc)), o_order = take(sizeof(int)), o_status = take(4 * sizeof(int));
+    const size_t o_b64 = take(sizeof(double) * nband), o_b32 = take(sizeof(float) * nband);
+    const size_t o_st = take(2 * sizeof(double) * nstate), o_dtot = take(2 * sizeof(double) * nstate);
+    const size_t o_rhs = take(2 * sizeof(double) * nstate), o_fac = take(2 * sizeof(double) * (nfac > 0 ? nfac : 1));
+    const size_t o_red = take(2 * sizeof(double) * nred);
+    if (off > kNoallocBytes)
+        return fail(TDSEZ_EINVAL, "no-alloc propagation: N = %d needs %zu bytes of scratch, the limit is %zu", sy->N,
+                    off, kNoallocBytes);
+    int dev = 0;
+    TDSEZ_HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(TDSEZ_EUNSUPPORTED, "device index %d", dev);
+    unsigned char* base = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_noalloc_mu);
+        if (!g_noalloc_ptr[dev]) {
+            void* p = nullptr;
+            TDSEZ_HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+            g_noalloc_ptr[dev] = p;
+        }
+        base = static_cast<unsigned char*>(g_noalloc_ptr[dev]);
+    }
+    hipStream_t stream = (hipStream_t)stream_v;
+    SysDesc d{};
+    d.N = pl.N; d.p = pl.p; d.P = pl.P; d.L = pl.L; d.m = pl.m; d.LS = pl.LS;
+    d.nsteps = nsteps;
+    d.dt = dt;
+    d.mi_is_s = sy->const_mass ? 1 : 0;
+    SysDesc* ddesc = reinterpret_cast<SysDesc*>(base + o_desc);
+    int* dorder = reinterpret_cast<int*>(base + o_order);
+    int* dstatus = dev_status ? dev_status : reinterpret_cast<int*>(base + o_status);
+    double* b64 = reinterpret_cast<double*>(base + o_b64);
+    float* b32 = reinterpret_cast<float*>(base + o_b32);
+    double* st = reinterpret_cast<double*>(base + o_st);
+    noalloc_setup_kernel<<<1, 64, 0, stream>>>(d, ddesc, dorder, dstatus);
+    TDSEZ_HIP_TRY(hipGetLastError());
+    {
+        BandSrc src;
+        src.m[kMatS] = sy->d_band[0];
+        src.m[kMatH0] = sy->d_H0;
+        src.m[kMatD] = sy->d_band[3];
+        src.m[kMatG] = sy->d_band[4];
+        src.m[kMatMi] = sy->d_band[5];
+        src.m[kMatW] = nullptr;
+        src.m[kMatV] = sy->d_band[2];
+        src.m[kMatK] = sy->d_K;
+        src.m[kMatQ] = nullptr;
+        const int nb = (int)std::min<long long>((nband + 255) / 256, 4096);
+        pack_band_kernel<<<nb, 256, 0, stream>>>(src, pl.N, pl.p, pl.P, pl.L, pl.LS, b64, b32);
+        TDSEZ_HIP_TRY(hipGetLastError());
+        dim3 grid((unsigned)std::min<long long>((nstate + 255) / 256, 1024), 1);
+        pack_state_kernel<<<grid, 256, 0, stream>>>(ddesc, psi, st, nullptr);
+        TDSEZ_HIP_TRY(hipGetLastError());
+    }
+    KernelArgs ka{};
+    ka.descs = ddesc;
+    ka.order = dorder;
+    ka.order_off = 0;
+    ka.band64 = b64;
+    ka.st = st;
+    ka.dtot = reinterpret_cast<double*>(base + o_dtot);
+    ka.rhs = base + o_rhs;
+    ka.fac = base + o_fac;
+    ka.red = base + o_red;
+    ka.E = E;
+    ka.obs = obs ? obs_out : nullptr;
+    ka.mask = obs;
+    ka.norm_tol = 0.0;
+    ka.status = dstatus;
+    ka.prof = nullptr;
+    ka.refine_tol = 1e-2;
+    ka.c0 = nullptr;
+    ka.proj = nullptr;
+    ka.ext = nullptr;
+    const bool fp64 = prec == TDSEZ_FP64;
+    ka.band = fp64 ? (const void*)b64 : (const void*)b32;
+    ka.refine = fp64 ? 0 : 1;
+    const int n2 = two ? 1 : 0, n1 = two ? 0 : 1;
+    TDSEZ_HIP_TRY(fp64 ? launch_prop_f64(ka, n2, n1, stream, stream, false)
+                       : launch_prop_f32(ka, n2, n1, stream, stream, false));
+    {
+        dim3 grid((unsigned)std::min<long long>(((long long)pl.N + 255) / 256, 1024), 1);
+        unpack_state_kernel<<<grid, 256, 0, stream>>>(ddesc, st, psi);
+        TDSEZ_HIP_TRY(hipGetLastError());
+    }
+    return TDSEZ_OK;
+}

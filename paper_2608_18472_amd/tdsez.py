@@ -61,6 +61,7 @@ def lib():
         "tdsez_propagate": [vp, vp, vp, d, i, i, u, vp, vp],
         "tdsez_propagate_batched_ext": [vp, vp, lp, vp, lp, dp, ip, i, u, vp, lp, u, vp, lp, vp],
         "tdsez_propagate_ext": [vp, vp, vp, d, i, i, u, vp, u, vp, vp],
+        "tdsez_propagate_noalloc": [vp, vp, vp, d, i, i, u, vp, vp, vp],
         "tdsez_set_cap": [vp, dp],
         "tdsez_set_aq": [vp, dp, dp],
         "tdsez_set_projectors": [vp, i, dp],
@@ -397,6 +398,25 @@ def propagate(sys, psi, E, dt, nsteps, prec=FP64, obs=OBS_ALL, obs_out=None, str
                                      ctypes.c_void_p(ext_out.data_ptr()) if ext else None, _stream_handle(stream)))
 
 
+def propagate_noalloc(sys, psi, E, dt, nsteps, prec=FP64, obs=OBS_ALL, obs_out=None, dev_status=None,
+                      stream=None):
+    """tdsez_propagate_noalloc: the same propagation with no device
+    allocation (working storage in the library's per-GPU scratch array);
+    dev_status: device int32 tensor of 4 entries, or None."""
+    import torch
+    _check_dev(psi, torch.complex128)
+    _check_dev(E, torch.float64)
+    if obs:
+        _check_dev(obs_out, torch.float64)
+    if dev_status is not None:
+        _check_dev(dev_status, torch.int32)
+    _check(lib().tdsez_propagate_noalloc(sys.handle, ctypes.c_void_p(psi.data_ptr()), ctypes.c_void_p(E.data_ptr()),
+                                         float(dt), int(nsteps), int(prec), int(obs),
+                                         ctypes.c_void_p(obs_out.data_ptr()) if obs else None,
+                                         None if dev_status is None else ctypes.c_void_p(dev_status.data_ptr()),
+                                         _stream_handle(stream)))
+
+
 def batch_status(batch, stream=None):
     s = ctypes.c_int()
     n = ctypes.c_int()
@@ -527,3 +547,4 @@ def system2d_stats(sys2d):
     _check(lib().tdsez_system2d_stats(sys2d.handle, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),
                                       ctypes.byref(d)))
     return a.value, b.value, c.value, d.value
+
