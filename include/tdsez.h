@@ -423,6 +423,52 @@ tdsez_status tdsez_system2d_stats(tdsez_system2d s, long* steps, long* iteration
                                   long* sweeps);
 void tdsez_system2d_destroy(tdsez_system2d s);
 
+/* ------------------------------------------------------------------ 3D
+ * Tensor-product problem on [x] x [y] x [z] breakpoints, same order on every
+ * axis, constant mass, x-polarised field: the three-factor basis of section
+ * II.C eq. tensor3d with the step of section V.B, as in the strong-scaling
+ * study of section VI (Table II: hydrogen, 97 cubic B-splines per axis,
+ * hydrogenic knots on [-25, 25]^3, 100 steps of 0.01).  Unknown (iz, iy, ix)
+ * has the row-major index (iz*Ny + iy)*Nx + ix.  S3 = Sz(x)Sy(x)Sx,
+ * T3 = Sz Sy Tx + Sz Ty Sx + Tz Sy Sx, D3 = Sz Sy Dx, and
+ * V3[i][j] = sum_q wx wy wz V N_i N_j by the tensor Gauss rule: a
+ * (2p+1)^3-point stencil per row (343 for cubic splines), of which the
+ * device keeps the symmetric half. */
+typedef struct tdsez_system3d_s* tdsez_system3d;
+
+/* Assemble a 3D problem on the device.  V_q: host FP64 samples of V at the
+ * tensor grid of the per-axis quadrature points, V_q[(qz*nqy + qy)*nqx + qx],
+ * nq* = (nb*-1)*nq (copied).  Also computes, once, the three per-axis
+ * generalised eigendecompositions of the preconditioner.  order <= 5; at
+ * least 2p+1 unknowns per axis.  Device memory: (w^3+1)/2 * N doubles for
+ * V3 (w = 2p+1; 1.26 GB at 97^3, p = 3), twice that while assembling, plus
+ * 18 N doubles of work vectors.  Synchronous. */
+tdsez_status tdsez_assemble_3d(const double* breaks_x, int nbx, const double* breaks_y, int nby,
+                               const double* breaks_z, int nbz, int order, int nq, const double* V_q,
+                               tdsez_system3d* out);
+tdsez_status tdsez_system3d_size(tdsez_system3d s, int* nx, int* ny, int* nz, int* halfbw);
+/* Rows of V3 as (2p+1)^3 stencils (host FP64, caller-owned, nrows*(2p+1)^3):
+ * out[r*w^3 + ((dz+p)*w + (dy+p))*w + (dx+p)] = V3[rows[r]][neighbour], 0 for
+ * a neighbour outside the grid.  EINVAL for a row outside 0..N-1. */
+tdsez_status tdsez_get_v3_rows(tdsez_system3d s, const long* rows, int nrows, double* host_out);
+/* out = a S3 c + b (T3 + V3 + Ebar D3) c for device complex128 c and out
+ * (N entries each, distinct); a = are + i aim, b = bre + i bim.  Shares the
+ * system's work vectors with tdsez_propagate_3d (do not overlap the two).
+ * Asynchronous on `stream`. */
+tdsez_status tdsez_apply_3d(tdsez_system3d s, const double* c, double* out, double are, double aim, double bre,
+                            double bim, double Ebar, void* stream);
+/* Crank-Nicolson propagation of psi (device complex128 [Nz][Ny][Nx], in/out);
+ * arguments, precisions, observables, convergence control and ENOCONV as
+ * for tdsez_propagate_2d, with the preconditioner the exact inverse of
+ * S3 + i dt/2 T3 (six per-axis contractions on the matrix cores). */
+tdsez_status tdsez_propagate_3d(tdsez_system3d s, double* psi, const double* E, double dt, int nsteps,
+                                tdsez_precision prec, unsigned obs, double* obs_out, double tol, int maxit,
+                                void* stream);
+/* As tdsez_system2d_stats, for the 3D propagations since the last call. */
+tdsez_status tdsez_system3d_stats(tdsez_system3d s, long* steps, long* iterations, int* max_iterations,
+                                  long* sweeps);
+void tdsez_system3d_destroy(tdsez_system3d s);
+
 /* Phase profile of the last propagation of a profiled batch (see
  * tdsez_batch_set "profile").  Synchronises `stream`; out[10*s + 0..9] =
  * average shader-clock cycles per time step spent by system s in: the

@@ -400,6 +400,66 @@ def assemble_3d(breaks_x, breaks_y, breaks_z, order, nq, V):
             "Sy": ms[1]["S"], "Ty": ms[1]["T"], "Sz": ms[2]["S"], "Tz": ms[2]["T"], "V3": V3}
 
 
+def v3_rows(breaks_x, breaks_y, breaks_z, order, nq, V, rows):
+    """Rows of the 3D potential matrix straight from its definition (section
+    II.C, eq. tensor3d with the tensor Gauss rule):
+    V3[i][j] = sum over every quadrature point q of w_q V(q) N_i(q) N_j(q),
+    restricted to the points where N_i is non-zero.  Returns
+    (len(rows), w, w, w) stencils indexed [dz+p][dy+p][dx+p] (zero for a
+    neighbour outside the grid), like the rows of assemble_3d's V3."""
+    brs = [_f64(b) for b in (breaks_x, breaks_y, breaks_z)]
+    p = order - 1
+    w = 2 * p + 1
+    axes = []
+    for br in brs:
+        xq, wq = quad_points(br, nq)
+        vals, _ = bspline_values(br, order, xq)
+        axes.append((xq, wq, vals[:, 1:-1]))  # reduced basis: first and last dropped
+    Nx, Ny, Nz = (a[2].shape[1] for a in axes)
+    out = np.zeros((len(rows), w, w, w))
+    for r, row in enumerate(rows):
+        iz, rem = divmod(int(row), Ny * Nx)
+        iy, ix = divmod(rem, Nx)
+        loc = []
+        for (xq, wq, B), i, n in zip(axes, (ix, iy, iz), (Nx, Ny, Nz)):
+            sel = np.nonzero(B[:, i])[0]
+            j = np.arange(i - p, i + p + 1)
+            ok = (j >= 0) & (j < n)
+            Bj = np.zeros((len(sel), w))
+            Bj[:, ok] = B[np.ix_(sel, j[ok])]
+            loc.append((xq[sel], wq[sel] * B[sel, i], Bj))
+        (x, ax, Bx), (y, ay, By), (z, az, Bz) = loc
+        Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+        Vl = _f64(V(X, Y, Z))
+        out[r] = np.einsum("zk,yl,xm,zyx->klm", az[:, None] * Bz, ay[:, None] * By, ax[:, None] * Bx, Vl)
+    return out
+
+
+def apply_3d_rows(m3, v3rows, rows, c, a, b, Ebar):
+    """Entries `rows` of a S3 c + b (T3 + V3 + Ebar D3) c from the per-axis
+    bands (Kronecker products written out entry by entry) and the given V3
+    rows (e.g. from v3_rows); c complex (Nz*Ny*Nx)."""
+    Nx, Ny, Nz, p = m3["Nx"], m3["Ny"], m3["Nz"], m3["p"]
+    D = {k: band_to_dense(m3[k]) for k in ("Sx", "Tx", "Dx", "Sy", "Ty", "Sz", "Tz")}
+    C = _c128(np.asarray(c)).reshape(Nz, Ny, Nx)
+    out = np.zeros(len(rows), dtype=np.complex128)
+    for r, row in enumerate(rows):
+        iz, rem = divmod(int(row), Ny * Nx)
+        iy, ix = divmod(rem, Nx)
+        js = [np.arange(max(i - p, 0), min(i + p, n - 1) + 1) for i, n in ((iz, Nz), (iy, Ny), (ix, Nx))]
+        jz, jy, jx = js
+        sz, tz = D["Sz"][iz, jz], D["Tz"][iz, jz]
+        sy, ty = D["Sy"][iy, jy], D["Ty"][iy, jy]
+        sx, tx, dx = D["Sx"][ix, jx], D["Tx"][ix, jx], D["Dx"][ix, jx]
+        blk = C[np.ix_(jz, jy, jx)]
+        S3 = np.einsum("k,l,m->klm", sz, sy, sx)
+        H3 = (np.einsum("k,l,m->klm", sz, sy, tx + Ebar * dx) + np.einsum("k,l,m->klm", sz, ty, sx)
+              + np.einsum("k,l,m->klm", tz, sy, sx))
+        V = v3rows[r][np.ix_(jz - iz + p, jy - iy + p, jx - ix + p)]
+        out[r] = a * np.sum(S3 * blk) + b * np.sum((H3 + V) * blk)
+    return out
+
+
 def apply_3d(m3, c, a, b, Ebar, with_V=True):
     """a S3 c + b (T3 + V3 + Ebar D3) c for complex scalars a, b."""
     c = _c128(np.asarray(c).reshape(-1))

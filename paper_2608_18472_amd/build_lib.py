@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 SOURCES = ["tdsez_api.hip", "tdsez_assemble.hip", "tdsez_eigen.hip", "tdsez_propagate.hip", "tdsez_prop_f32.hip",
-           "tdsez_prop_f64.hip", "tdsez_prop_xt32.hip", "tdsez_prop_xt64.hip", "tdsez_adjoint.hip", "tdsez_2d.hip"]
+           "tdsez_prop_f64.hip", "tdsez_prop_xt32.hip", "tdsez_prop_xt64.hip", "tdsez_adjoint.hip", "tdsez_2d.hip", "tdsez_3d.hip"]
 LIB = os.path.join(HERE, "libtdsez.so")
 
 HIPCC_FLAGS = [

@@ -72,6 +72,12 @@ def lib():
         "tdsez_get_v2": [vp, dp],
         "tdsez_propagate_2d": [vp, vp, vp, d, i, i, u, vp, d, i, vp],
         "tdsez_system2d_stats": [vp, lp, lp, ip, lp],
+        "tdsez_assemble_3d": [dp, i, dp, i, dp, i, i, i, dp, ctypes.POINTER(vp)],
+        "tdsez_system3d_size": [vp, ip, ip, ip, ip],
+        "tdsez_get_v3_rows": [vp, lp, i, dp],
+        "tdsez_apply_3d": [vp, vp, vp, d, d, d, d, d, vp],
+        "tdsez_propagate_3d": [vp, vp, vp, d, i, i, u, vp, d, i, vp],
+        "tdsez_system3d_stats": [vp, lp, lp, ip, lp],
         "tdsez_batch_status": [vp, vp, ip, ip],
         "tdsez_batch_profile": [vp, vp, dp],
         "tdsez_autotune": [vp, i, d],
@@ -90,6 +96,8 @@ def lib():
     L.tdsez_system_destroy.restype = None
     L.tdsez_system2d_destroy.argtypes = [vp]
     L.tdsez_system2d_destroy.restype = None
+    L.tdsez_system3d_destroy.argtypes = [vp]
+    L.tdsez_system3d_destroy.restype = None
     _lib = L
     return L
 
@@ -548,3 +556,96 @@ def system2d_stats(sys2d):
                                       ctypes.byref(d)))
     return a.value, b.value, c.value, d.value
 
+
+# --------------------------------------------------------------------- 3D
+class System3D:
+    """An assembled 3D tensor-product problem (owns its device data)."""
+
+    def __init__(self, handle):
+        self.handle = handle
+        nx, ny, nz, p = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(lib().tdsez_system3d_size(handle, ctypes.byref(nx), ctypes.byref(ny), ctypes.byref(nz),
+                                         ctypes.byref(p)))
+        self.Nx, self.Ny, self.Nz, self.p = nx.value, ny.value, nz.value, p.value
+
+    @property
+    def N(self):
+        return self.Nx * self.Ny * self.Nz
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.tdsez_system3d_destroy(self.handle)
+            self.handle = None
+
+
+def assemble_3d(breaks_x, breaks_y, breaks_z, order, nq, V_q):
+    """V_q: host samples at the tensor grid of the per-axis quadrature
+    points, indexed [qz][qy][qx]."""
+    bx, by, bz = _f64(breaks_x), _f64(breaks_y), _f64(breaks_z)
+    vq = _f64(V_q)
+    h = ctypes.c_void_p()
+    _check(lib().tdsez_assemble_3d(_dptr(bx), len(bx), _dptr(by), len(by), _dptr(bz), len(bz), order, nq,
+                                   _dptr(vq), ctypes.byref(h)))
+    return System3D(h)
+
+
+def sample_3d(V, xq, yq, zq):
+    """V(x, y, z) on the tensor grid, [qz][qy][qx], one z plane at a time."""
+    out = np.empty((len(zq), len(yq), len(xq)))
+    Y, X = np.meshgrid(yq, xq, indexing="ij")
+    for k, z in enumerate(zq):
+        out[k] = V(X, Y, np.full_like(X, z))
+    return out
+
+
+def assemble_workload_3d(sysdef):
+    """Assemble a workloads.System3D on the library's own per-axis
+    quadrature points."""
+    xq = quad_points(sysdef.breaks_x, sysdef.nq)
+    yq = quad_points(sysdef.breaks_y, sysdef.nq)
+    zq = quad_points(sysdef.breaks_z, sysdef.nq)
+    return assemble_3d(sysdef.breaks_x, sysdef.breaks_y, sysdef.breaks_z, sysdef.order, sysdef.nq,
+                       sample_3d(sysdef.V, xq, yq, zq))
+
+
+def get_v3_rows(sys3d, rows):
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    w = 2 * sys3d.p + 1
+    out = np.zeros(len(rows) * w ** 3)
+    _check(lib().tdsez_get_v3_rows(sys3d.handle, rows.ctypes.data_as(ctypes.POINTER(ctypes.c_long)), len(rows),
+                                   _dptr(out)))
+    return out.reshape(len(rows), w, w, w)
+
+
+def apply_3d(sys3d, c, out, a, b, Ebar=0.0, stream=None):
+    """out = a S3 c + b (T3 + V3 + Ebar D3) c (device complex128 vectors)."""
+    import torch
+    _check_dev(c, torch.complex128)
+    _check_dev(out, torch.complex128)
+    a, b = complex(a), complex(b)
+    _check(lib().tdsez_apply_3d(sys3d.handle, ctypes.c_void_p(c.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                a.real, a.imag, b.real, b.imag, float(Ebar), _stream_handle(stream)))
+
+
+def propagate_3d(sys3d, psi, E, dt, nsteps, prec=FP64, obs=OBS_NORM | OBS_DIPOLE, obs_out=None, tol=1e-12,
+                 maxit=200, stream=None):
+    """psi: device complex128 (Nz*Ny*Nx, in/out); E: device float64; obs_out:
+    device float64 [(nsteps+1)*3] or None."""
+    import torch
+    _check_dev(psi, torch.complex128)
+    _check_dev(E, torch.float64)
+    if obs:
+        _check_dev(obs_out, torch.float64)
+    _check(lib().tdsez_propagate_3d(sys3d.handle, ctypes.c_void_p(psi.data_ptr()), ctypes.c_void_p(E.data_ptr()),
+                                    float(dt), int(nsteps), int(prec), int(obs),
+                                    ctypes.c_void_p(obs_out.data_ptr()) if obs else None, float(tol), int(maxit),
+                                    _stream_handle(stream)))
+
+
+def system3d_stats(sys3d):
+    """(steps, Krylov iterations, largest iteration count of one step,
+    refinement sweeps) since the last call."""
+    a, b, c, d = ctypes.c_long(), ctypes.c_long(), ctypes.c_int(), ctypes.c_long()
+    _check(lib().tdsez_system3d_stats(sys3d.handle, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),
+                                      ctypes.byref(d)))
+    return a.value, b.value, c.value, d.value

@@ -321,6 +321,65 @@ def config4(n=512, nsteps=None, L=120.0, order=6):
                     10, E, 0.05, ns, {"E0": 0.05, "omega": 0.057, "Tp": Tp})
 
 
+@dataclass
+class System3D:
+    """Tensor-product 3D problem with constant mass and an x-polarised field."""
+    name: str
+    breaks_x: np.ndarray
+    breaks_y: np.ndarray
+    breaks_z: np.ndarray
+    order: int
+    V: Callable  # V(x, y, z), vectorised
+    nq: int = 4
+    E: Optional[np.ndarray] = None
+    dt: float = 0.0
+    nsteps: int = 0
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def p(self):
+        return self.order - 1
+
+    @property
+    def shape(self):
+        """(Nz, Ny, Nx) unknowns."""
+        n = lambda b: len(b) - 1 + self.p - 2
+        return n(self.breaks_z), n(self.breaks_y), n(self.breaks_x)
+
+
+def coulomb_3d(x, y, z):
+    """Hydrogen, V = -1/r (no regularisation: the quadrature points of
+    knots placed on 0 never reach r = 0)."""
+    return -1.0 / np.sqrt(x * x + y * y + z * z)
+
+
+def hydrogen_3d(nsteps=100, dt=0.01, L=25.0, r1=0.25, nlin=20, nexp=28, order=4, nq=4, E0=0.05, omega=0.057):
+    """The strong-scaling workload of section VI (Table II): hydrogen on
+    cubic B-splines (order 4), the hydrogenic grading mirrored about 0 on
+    every axis of [-L, L]^3 (2 (nlin + nexp) spans: 97 unknowns per axis with
+    the defaults; linear steps r1 up to nlin r1 = 5, then exponential to L),
+    nq = p + 1 Gauss points per span and axis, 100 steps of dt = 0.01 under
+    an x-polarised field E(t) = E0 sin(omega t)."""
+    br = breaks_hydrogenic_symmetric(r1, nlin, nexp, L)
+    t = dt * np.arange(nsteps + 1)
+    E = E0 * np.sin(omega * t)
+    return System3D("hydrogen-3d", br, br.copy(), br.copy(), order, coulomb_3d, nq, E, dt, nsteps,
+                    {"E0": E0, "omega": omega, "r1": r1, "nlin": nlin, "nexp": nexp, "L": L})
+
+
+def hydrogen_3d_small(n=(8, 7, 6), L=(9.0, 8.0, 7.0), nsteps=20, dt=0.05, order=4, nq=4, E0=0.05, omega=0.3):
+    """A reduced anisotropic hydrogen box for parity runs: per axis the
+    hydrogenic grading mirrored about 0 with n = nlin + nexp spans a side
+    (nlin = n // 2, r1 = 0.5), different lengths per axis so that an axis
+    mix-up changes the result; a faster field so that the dipole moves."""
+    def axis(k, Lk):
+        nl = k // 2
+        return breaks_hydrogenic_symmetric(0.5, nl, k - nl, Lk)
+    t = dt * np.arange(nsteps + 1)
+    return System3D("hydrogen-3d-small", axis(n[0], L[0]), axis(n[1], L[1]), axis(n[2], L[2]), order,
+                    coulomb_3d, nq, E0 * np.sin(omega * t), dt, nsteps, {"E0": E0, "omega": omega})
+
+
 def config5(nsys=64, N=1500, nsteps=20000, ntheta=64, seed=1, wb_nm=4.0):
     """Batch for the pulse-gradient workload: config2 double quantum wells
     (all systems share the geometry) driven by Fourier pulses
