@@ -38,7 +38,22 @@ CALIB_COPY_BYTES = 512 * 2 ** 20
 TRAFFIC = {"sources_sha256": "2a4ce85a0e4e3f7767fe1d4a564169950bf2744c047da1adba9306ae49815cc8",
            "bytes_per_launch": 2.4232e13, "split": 160}
 KERNEL_SOURCES = ["paper_2608_18472_amd/csrc/tdsez_passes.hpp", "paper_2608_18472_amd/csrc/tdsez_propagate.hip",
-                  "paper_2608_18472_amd/csrc/tdsez_internal.hpp"]
+                  "paper_2608_18472_amd/csrc/tdsez_internal.hpp", "paper_2608_18472_amd/csrc/tdsez_run.hpp",
+                  "paper_2608_18472_amd/csrc/tdsez_prop_f32.hip"]
+# Algorithmic bytes of one tensor-product operator application per unknown:
+# the stored half of the potential stencil plus the input and output
+# vectors (complex).  2D, order 6: 61 stored offsets.
+STENCIL2D_BYTES = {4: 61 * 4 + 2 * 8, 8: 61 * 8 + 2 * 16}
+
+
+def stencil3d_bytes(p, real_bytes):
+    """3D: ((2p+1)^3 + 1) / 2 stored offsets (172 for cubic splines)."""
+    w = 2 * p + 1
+    return (w ** 3 + 1) // 2 * real_bytes + 2 * 2 * real_bytes
+
+
+# The paper's Table II: 912 673 unknowns x 100 steps in 48.4 s on 256 Zen 4 cores.
+TABLE2_DOFSTEPS_256 = 912673 * 100 / 48.4
 
 
 def kernel_sources_sha():
@@ -142,11 +157,12 @@ def main():
     ap.add_argument("--split", type=int, default=160,
                     help="run this many of the costliest systems on two waves each (setup, untimed; "
                          "160 of 1024 measured best, 0 = one wave per system)")
-    ap.add_argument("--workload", choices=["batch1d", "2d", "h2p", "adjoint"], default="batch1d",
+    ap.add_argument("--workload", choices=["batch1d", "2d", "3d", "h2p", "adjoint"], default="batch1d",
                     help="batch1d: the batched 1D benchmark (default); 2d: a segment of the 512 x 512 "
                          "tensor-product workload; h2p: the 1D H2+ model (30 007 splines, one long "
                          "chain) over its whole pulse; adjoint: the pulse gradient of 64 double quantum "
-                         "wells (N 1500, 20 000 steps, 64 amplitudes)")
+                         "wells (N 1500, 20 000 steps, 64 amplitudes); 3d: hydrogen on 97^3 cubic "
+                         "splines, 100 steps (the paper's strong-scaling workload)")
     ap.add_argument("--steps-2d", type=int, default=400, help="time steps of the 2D segment")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -158,6 +174,9 @@ def main():
         return
     if args.workload == "h2p":
         run_h2p(args)
+        return
+    if args.workload == "3d":
+        run_3d(args)
         return
     if args.workload == "adjoint":
         run_adjoint(args)
@@ -348,6 +367,13 @@ def run_2d(args):
     d64 = out["fp64"]["obs"].reshape(-1, 3)[:, 1]
     d32 = out["fp32-refined"]["obs"].reshape(-1, 3)[:, 1]
     n = g.Nx * g.Ny
+    # the operator kernel (dominant): algorithmic bytes per launch over its
+    # event-timed average launch, FP32 as in the inner iterations
+    ms32 = T.time_apply(g, T.FP32_REFINED, 50, stream)
+    ms64 = T.time_apply(g, T.FP64, 50, stream)
+    b32, b64 = n * STENCIL2D_BYTES[4], n * STENCIL2D_BYTES[8]
+    # floor: two operator applications per step at HBM peak (per precision)
+    floor = lambda b, sec: (2 * b / (HBM_PEAK_GBS * 1e9)) / (sec / ns)
     cpu = None if args.no_cpu else cpu_baseline_2d(60)
     line = {
         "metric": "complex DOF-steps/s per GPU (2D tensor-product segment)",
@@ -371,11 +397,137 @@ def run_2d(args):
             "fp64": {"value": n * ns / out["fp64"]["sec"], "ms_per_step": 1000.0 * out["fp64"]["sec"] / ns,
                      "iterations_per_step": out["fp64"]["its"]},
             "dipole_rel_err_fp32_vs_fp64": float(np.linalg.norm(d32 - d64) / np.linalg.norm(d64)),
+            "floor_fraction_fp32_refined": floor(b32, out["fp32-refined"]["sec"]),
+            "floor_fraction_fp64": floor(b64, out["fp64"]["sec"]),
+            "operator_kernel_ms": {"fp32": ms32, "fp64": ms64},
         },
+        "roofline": {"bound": "hbm", "achieved": b32 / (ms32 * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": b32 / (ms32 * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "apply_kernel<5, float> (FP32 operator of the inner iterations), %d B/unknown"
+                               % STENCIL2D_BYTES[4]},
     }
     if cpu is not None:
         line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)
+
+
+def run_3d(args):
+    """The strong-scaling workload of the paper's Table II: hydrogen on 97^3
+    cubic splines (hydrogenic knots on [-25, 25]^3, 912 673 unknowns, 343
+    couplings per row), 100 Crank-Nicolson steps of 0.01 under the 800 nm
+    field E0 sin(w t) (E0 0.053, w 0.057), relative residual 1e-12 per step
+    (the paper's solver tolerance); FP32-refined and FP64."""
+    import torch
+    from paper_2608_18472_amd import tdsez as T
+    from paper_2608_18472_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    sd = W.hydrogen_3d()
+    t0 = time.perf_counter()
+    g = T.assemble_workload_3d(sd)
+    t_asm = time.perf_counter() - t0
+    # initial state: product of the per-axis 1D ground states of -1/sqrt(x^2+1)
+    # (library eigensolver)
+    vecs = []
+    for br in (sd.breaks_x, sd.breaks_y, sd.breaks_z):
+        xq = T.quad_points(br, sd.nq)
+        s1 = T.assemble(br, sd.order, sd.nq, None, -1.0 / np.sqrt(xq * xq + 1.0), 0.0 * xq)
+        ev, vec = T.ground_state(s1)
+        vecs.append(vec[0])
+    psi0 = torch.from_numpy(np.einsum("z,y,x->zyx", vecs[2], vecs[1], vecs[0]).astype(np.complex128)
+                            .reshape(-1)).cuda()
+    ns = sd.nsteps
+    E = torch.from_numpy(np.ascontiguousarray(sd.E[: ns + 1])).cuda()
+    stream = torch.cuda.current_stream()
+    out = {}
+    for name, prec in (("fp32-refined", T.FP32_REFINED), ("fp64", T.FP64)):
+        o = torch.zeros(3 * (ns + 1), dtype=torch.float64, device="cuda")
+        T.propagate_3d(g, psi0.clone(), E[:4].contiguous(), sd.dt, 3, prec, 3, o[:12], tol=1e-12)  # warm-up
+        T.system3d_stats(g)
+        psi = psi0.clone()
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        T.propagate_3d(g, psi, E, sd.dt, ns, prec, 3, o, tol=1e-12, stream=stream)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        sec = ev0.elapsed_time(ev1) / 1000.0
+        steps, its, mx, sweeps = T.system3d_stats(g)
+        out[name] = {"sec": sec, "its": its / steps, "sweeps": sweeps / steps, "obs": o.cpu().numpy()}
+    d64 = out["fp64"]["obs"].reshape(-1, 3)[:, 1]
+    d32 = out["fp32-refined"]["obs"].reshape(-1, 3)[:, 1]
+    n = g.N
+    ms32 = T.time_apply(g, T.FP32_REFINED, 20, stream)
+    ms64 = T.time_apply(g, T.FP64, 20, stream)
+    b32, b64 = n * stencil3d_bytes(g.p, 4), n * stencil3d_bytes(g.p, 8)
+    floor = lambda b, sec: (2 * b / (HBM_PEAK_GBS * 1e9)) / (sec / ns)
+    cpu = None if args.no_cpu else cpu_baseline_3d()
+    sec = out["fp32-refined"]["sec"]
+    line = {
+        "metric": "complex DOF-steps/s per GPU (3D hydrogen, the paper's strong-scaling workload)",
+        "value": n * ns / sec,
+        "unit": "DOF-steps/s",
+        "n_gpus": 1,
+        "steps": ns,
+        "warmup": 3,
+        "ms_per_step": 1000.0 * sec / ns,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": n * ns / sec / TABLE2_DOFSTEPS_256,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "3D hydrogen -1/r, 97^3 cubic splines (hydrogenic knots r1 0.25, 20 linear + 28 "
+                        "exponential spans a side on [-25,25]), nq 4, 100 steps dt 0.01, x field 0.053 sin(0.057 t), "
+                        "residual 1e-12",
+            "unknowns": n,
+            "assembly_s": t_asm,
+            "fp32_refined": {"ms_per_step": 1000.0 * sec / ns, "inner_iterations_per_step": out["fp32-refined"]["its"],
+                             "sweeps_per_step": out["fp32-refined"]["sweeps"],
+                             "floor_fraction": floor(b32, sec)},
+            "fp64": {"value": n * ns / out["fp64"]["sec"], "ms_per_step": 1000.0 * out["fp64"]["sec"] / ns,
+                     "iterations_per_step": out["fp64"]["its"], "floor_fraction": floor(b64, out["fp64"]["sec"])},
+            "dipole_rel_err_fp32_vs_fp64": float(np.linalg.norm(d32 - d64) / np.linalg.norm(d64)),
+            "operator_kernel_ms": {"fp32": ms32, "fp64": ms64},
+            "vs_baseline_reference": "Table II: 48.4 s for the 100 steps on 256 Zen 4 cores (1.89e6 DOF-steps/s); "
+                                     "another machine, context",
+        },
+        "roofline": {"bound": "hbm", "achieved": b32 / (ms32 * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": b32 / (ms32 * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "apply3_kernel<3, float> (FP32 operator of the inner iterations), %d B/unknown"
+                               % stencil3d_bytes(g.p, 4)},
+    }
+    if cpu is not None:
+        line["cpu_baseline"] = cpu
+    print(json.dumps(line), flush=True)
+
+
+def cpu_baseline_3d(nsteps=1):
+    """The oracle's 3D propagation (C operator over the 343-point rows,
+    NumPy preconditioner transforms, COCG to 1e-12) on the full 97^3
+    workload for `nsteps` steps (its assembly untimed)."""
+    from oracle import oracle as O
+    from paper_2608_18472_amd import workloads as W
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([int(i.get("num_threads", 1)) for i in threadpool_info()] or [1])
+    except Exception:
+        cores = 1
+    sd = W.hydrogen_3d(nsteps=nsteps)
+    m3 = O.assemble_3d(sd.breaks_x, sd.breaks_y, sd.breaks_z, sd.order, sd.nq, sd.V)
+    Nz, Ny, Nx = sd.shape
+    g = [np.exp(-0.5 * np.linspace(-4, 4, k) ** 2) for k in (Nz, Ny, Nx)]
+    psi0 = np.einsum("z,y,x->zyx", *g).astype(np.complex128)
+    t0 = time.perf_counter()
+    O.propagate_3d(m3, psi0, sd.E, sd.dt, nsteps, tol=1e-12)
+    wall = time.perf_counter() - t0
+    dof = Nx * Ny * Nz * nsteps
+    out = {"value": dof / wall, "unit": "DOF-steps/s", "cores": cores, "kind": "oracle",
+           "sample": "%d step(s) of the full 97^3 workload (%.3g DOF-steps), serial C operator with NumPy/BLAS "
+                     "preconditioner transforms, wall %.1f s (assembly untimed)" % (nsteps, dof, wall)}
+    out.update(host_info())
+    return out
 
 
 def run_h2p(args):

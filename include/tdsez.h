@@ -421,6 +421,8 @@ tdsez_status tdsez_propagate_2d(tdsez_system2d s, double* psi, const double* E, 
  * counters. */
 tdsez_status tdsez_system2d_stats(tdsez_system2d s, long* steps, long* iterations, int* max_iterations,
                                   long* sweeps);
+/* As tdsez_time_apply_3d, for the 2D operator kernel. */
+tdsez_status tdsez_time_apply_2d(tdsez_system2d s, tdsez_precision prec, int reps, void* stream, double* ms_out);
 void tdsez_system2d_destroy(tdsez_system2d s);
 
 /* ------------------------------------------------------------------ 3D
@@ -464,6 +466,12 @@ tdsez_status tdsez_apply_3d(tdsez_system3d s, const double* c, double* out, doub
 tdsez_status tdsez_propagate_3d(tdsez_system3d s, double* psi, const double* E, double dt, int nsteps,
                                 tdsez_precision prec, unsigned obs, double* obs_out, double tol, int maxit,
                                 void* stream);
+/* Average duration (ms, HIP events on `stream`) of `reps` back-to-back
+ * launches of the operator kernel q = A p exactly as a Krylov iteration of
+ * tdsez_propagate_3d launches it (FP64 or, for TDSEZ_FP32_REFINED, the FP32
+ * operator); for roofline accounting.  Uses the work vectors; synchronises
+ * `stream`. */
+tdsez_status tdsez_time_apply_3d(tdsez_system3d s, tdsez_precision prec, int reps, void* stream, double* ms_out);
 /* As tdsez_system2d_stats, for the 3D propagations since the last call. */
 tdsez_status tdsez_system3d_stats(tdsez_system3d s, long* steps, long* iterations, int* max_iterations,
                                   long* sweeps);

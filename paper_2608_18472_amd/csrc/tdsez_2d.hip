@@ -587,6 +587,42 @@ tdsez_status tdsez_get_v2(tdsez_system2d s, double* host_out) {
     return TDSEZ_OK;
 }
 
+tdsez_status tdsez_time_apply_2d(tdsez_system2d s, tdsez_precision prec, int reps, void* stream_v, double* ms_out) {
+    if (!s || !ms_out) return fail(TDSEZ_EINVAL, "NULL argument");
+    if (reps < 1) return fail(TDSEZ_EINVAL, "reps must be >= 1");
+    if (prec != TDSEZ_FP64 && prec != TDSEZ_FP32_REFINED) return fail(TDSEZ_EINVAL, "unknown precision %d", (int)prec);
+    const bool mixed = prec == TDSEZ_FP32_REFINED;
+    if (mixed) {
+        if (tdsez_status st = ensure_fp32(s)) return st;
+    }
+    hipStream_t stream = (hipStream_t)stream_v;
+    CnWork cw;
+    cw.n = (long long)s->Nx * s->Ny;
+    cw.w = s->d_work;
+    cw.w32 = s->d_work32;
+    Op2D op{s, cw, 0.0};
+    const int g = grid_for(2 * cw.n);
+    // q = A p as in a Krylov iteration (inputs: a filled vector)
+    if (mixed) copy_kernel<float><<<g, 256, 0, stream>>>(2 * cw.n, nullptr, cw.re32(kP32), nullptr);
+    else copy_kernel<double><<<g, 256, 0, stream>>>(2 * cw.n, nullptr, cw.re(kP), nullptr);
+    hipEvent_t e0, e1;
+    TDSEZ_HIP_TRY(hipEventCreate(&e0));
+    TDSEZ_HIP_TRY(hipEventCreate(&e1));
+    TDSEZ_HIP_TRY(hipEventRecord(e0, stream));
+    for (int r = 0; r < reps; ++r) {
+        if (mixed) op.apply32(kP32, 1.0, 0.0, 0.0, 0.005, 0.01, kQ32, nullptr, stream);
+        else op.apply(kP, -1, 0.0, 0.0, 1.0, 0.0, 0.0, 0.005, 0.01, kQ, nullptr, nullptr, stream);
+    }
+    TDSEZ_HIP_TRY(hipEventRecord(e1, stream));
+    TDSEZ_HIP_TRY(hipEventSynchronize(e1));
+    float ms = 0.f;
+    TDSEZ_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *ms_out = (double)ms / reps;
+    return TDSEZ_OK;
+}
+
 tdsez_status tdsez_propagate_2d(tdsez_system2d s, double* psi, const double* E, double dt, int nsteps,
                                 tdsez_precision prec, unsigned obs, double* obs_out, double tol, int maxit,
                                 void* stream_v) {

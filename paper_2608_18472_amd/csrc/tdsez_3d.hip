@@ -138,12 +138,11 @@ __global__ void v3_a2_kernel(int Nx, int Ny, int p, int nq, int nely, int nqz, c
 __global__ void v3_z_kernel(int Nx, int Ny, int Nz, int p, int nq, int nelz, int es0, int es1, int iz0, int iz1,
                             const double* __restrict__ brz, const double* __restrict__ gw,
                             const double* __restrict__ Bz, const double* __restrict__ A2,
-                            double* __restrict__ V3h) {
+                            double* __restrict__ V3h, long long vstride) {
     const int w = 2 * p + 1;
     const int lc = (w * w * w - 1) / 2;
     const int nh = half3_count(p);
     const long long plane = (long long)Nx * Ny;
-    const long long N = plane * Nz;
     const long long nrow = (long long)(iz1 - iz0 + 1) * plane;
     const long long total = nrow * nh;
     for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
@@ -169,7 +168,7 @@ __global__ void v3_z_kernel(int Nx, int Ny, int Nz, int p, int nq, int nelz, int
                 sum += wz * A2[((((lz * Ny + iy) * w + ky) * Nx + ix) * w) + kx];
             }
         }
-        V3h[(long long)h * N + row] += sum;
+        V3h[(long long)h * vstride + row] += sum;
     }
 }
 
@@ -183,9 +182,29 @@ struct Tile3 {
     static constexpr int TZ = 256 / (TX * TY);
 };
 template <typename FT>
+struct Cplx2;
+template <>
+struct Cplx2<double> {
+    typedef double2 type;
+};
+template <>
+struct Cplx2<float> {
+    typedef float2 type;
+};
+template <typename FT>
 dim3 stencil3_grid(int Nx, int Ny, int Nz) {
     return dim3((Nx + Tile3<FT>::TX - 1) / Tile3<FT>::TX, (Ny + Tile3<FT>::TY - 1) / Tile3<FT>::TY,
                 (Nz + Tile3<FT>::TZ - 1) / Tile3<FT>::TZ);
+}
+// Tiles are launched on a 1D grid of 8 ceil(tiles / 8) workgroups.
+// Workgroups go to the eight XCDs in turn (workgroup b to XCD b mod 8), so
+// tile = (b mod 8) ceil(tiles / 8) + b / 8 gives each XCD a contiguous run of
+// tiles, i.e. a slab of z planes: the halo of the input, and the mirrored
+// potential rows of the offsets below the centre, are then mostly in that
+// XCD's own L2.
+inline unsigned stencil3_launch(dim3 tiles) {
+    const unsigned nb = tiles.x * tiles.y * tiles.z;
+    return 8 * ((nb + 7) / 8);
 }
 
 // out = w y + a S3 c + b (T3 + V3 + Ebar D3) c (planar complex; y may be
@@ -198,22 +217,27 @@ dim3 stencil3_grid(int Nx, int Ny, int Nz) {
 // partial sums of Re c^H S3 c and Re c^H D3 c (FP64).
 template <int PP, typename FT, bool OBS>
 __global__ __launch_bounds__(256, 2) void apply3_kernel(
-    int Nx, int Ny, int Nz, const FT* __restrict__ Sxb, const FT* __restrict__ Txb, const FT* __restrict__ Dxb,
+    int Nx, int Ny, int Nz, dim3 tiles, const FT* __restrict__ Sxb, const FT* __restrict__ Txb, const FT* __restrict__ Dxb,
     const FT* __restrict__ Syb, const FT* __restrict__ Tyb, const FT* __restrict__ Szb, const FT* __restrict__ Tzb,
-    const FT* __restrict__ V3h, const FT* __restrict__ cre, const FT* __restrict__ cim, const FT* __restrict__ yre,
-    const FT* __restrict__ yim, FT wre, FT wim, FT are, FT aim, FT bre, FT bim, FT Ebar, FT* __restrict__ ore,
-    FT* __restrict__ oim, double* __restrict__ obs, const double* __restrict__ flag) {
+    const FT* __restrict__ V3h, long long vstride, const FT* __restrict__ cre, const FT* __restrict__ cim,
+    const FT* __restrict__ yre, const FT* __restrict__ yim, FT wre, FT wim, FT are, FT aim, FT bre, FT bim, FT Ebar,
+    FT* __restrict__ ore, FT* __restrict__ oim, double* __restrict__ obs, const double* __restrict__ flag) {
     if (flag && *flag != 0.0) return;  // the solve has converged
     constexpr int TX = Tile3<FT>::TX, TY = Tile3<FT>::TY, TZ = Tile3<FT>::TZ;
     constexpr int K = 2 * PP + 1;
     constexpr int WX = TX + 2 * PP, WY = TY + 2 * PP, WZ = TZ + 2 * PP;
     constexpr int LC = (K * K * K - 1) / 2;
-    __shared__ FT tre[WZ][WY][WX], tim[WZ][WY][WX];
+    typedef typename Cplx2<FT>::type C2;
+    __shared__ C2 tc[WZ][WY][WX];  // the input tile, (re, im) pairs
+    const int nb = (int)(tiles.x * tiles.y * tiles.z);
+    const int tile = (int)(blockIdx.x % 8) * ((nb + 7) / 8) + (int)(blockIdx.x / 8);
+    if (tile >= nb) return;  // padding of the launch to a multiple of 8
+    const int bx = tile % (int)tiles.x, by = (tile / (int)tiles.x) % (int)tiles.y,
+              bz = tile / (int)(tiles.x * tiles.y);
     const int tx = threadIdx.x % TX, ty = (threadIdx.x / TX) % TY, tz = threadIdx.x / (TX * TY);
-    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, z0 = blockIdx.z * TZ;
+    const int x0 = bx * TX, y0 = by * TY, z0 = bz * TZ;
     const int ix = x0 + tx, iy = y0 + ty, iz = z0 + tz;
     const long long plane = (long long)Nx * Ny;
-    const long long N = plane * Nz;
     for (int t = threadIdx.x; t < WX * WY * WZ; t += 256) {
         const int lz = t / (WX * WY), ly = (t / WX) % WY, lx = t % WX;
         const int gz = z0 + lz - PP, gy = y0 + ly - PP, gx = x0 + lx - PP;
@@ -223,69 +247,124 @@ __global__ __launch_bounds__(256, 2) void apply3_kernel(
             vr = cre[at];
             vi = cim[at];
         }
-        tre[lz][ly][lx] = vr;
-        tim[lz][ly][lx] = vi;
+        tc[lz][ly][lx] = C2{vr, vi};
     }
     const int ixc = ix < Nx ? ix : Nx - 1, iyc = iy < Ny ? iy : Ny - 1, izc = iz < Nz ? iz : Nz - 1;
     const long long row = ((long long)izc * Ny + iyc) * Nx + ixc;
-    // x factors of the thread's column; which x neighbours exist
+    const unsigned urow = (unsigned)row;  // N < 2^31
+    // x factors of the thread's column; y and z factors of the tile's rows
+    // and planes in LDS (read once per line instead of a global load)
+    __shared__ FT fy[2][TY][K], fz[2][TZ][K];
+    if (threadIdx.x < TY * K) {
+        const int r = threadIdx.x / K, k = threadIdx.x % K;
+        const int gy = y0 + r < Ny ? y0 + r : Ny - 1;
+        fy[0][r][k] = band_at(Syb, PP, Ny, gy, gy + k - PP);
+        fy[1][r][k] = band_at(Tyb, PP, Ny, gy, gy + k - PP);
+    } else if (threadIdx.x >= 64 && threadIdx.x < 64 + TZ * K) {
+        const int r = (threadIdx.x - 64) / K, k = (threadIdx.x - 64) % K;
+        const int gz = z0 + r < Nz ? z0 + r : Nz - 1;
+        fz[0][r][k] = band_at(Szb, PP, Nz, gz, gz + k - PP);
+        fz[1][r][k] = band_at(Tzb, PP, Nz, gz, gz + k - PP);
+    }
     FT sx[K], hx[K], dxv[K];
-    unsigned xok = 0;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const int jx = ixc + k - PP;
         sx[k] = band_at(Sxb, PP, Nx, ixc, jx);
         dxv[k] = band_at(Dxb, PP, Nx, ixc, jx);
         hx[k] = band_at(Txb, PP, Nx, ixc, jx) + Ebar * dxv[k];
-        if (jx >= 0 && jx < Nx) xok |= 1u << k;
     }
     __syncthreads();
+    constexpr int CL = (K * K - 1) / 2;  // the line (dz, dy) = (0, 0)
+    // (global address space: plain loads rather than flat ones, whose
+    // completion the LDS waits would also wait for)
+    typedef const __attribute__((address_space(1))) FT* gptr;
     FT Sr = 0, Si = 0, Hr = 0, Hi = 0, Dr = 0, Di = 0, Vr = 0, Vi = 0;
+    // One (dz, dy) line of x sums, weighted by its y and z factors.
+    auto line_sums = [&](int kz, int ky, FT usr, FT usi, FT uhr, FT uhi, FT udr, FT udi) {
+        const FT sz = fz[0][tz][kz], tzv = fz[1][tz][kz];
+        const FT sy = fy[0][ty][ky], tyv = fy[1][ty][ky];
+        const FT szy = sz * sy, hzy = sz * tyv + tzv * sy;
+        Sr += szy * usr;
+        Si += szy * usi;
+        Hr += szy * uhr + hzy * usr;
+        Hi += szy * uhi + hzy * usi;
+        if constexpr (OBS) {
+            Dr += szy * udr;
+            Di += szy * udi;
+        }
+    };
+    // Lines after the centre line, each with its mirror line: the stored
+    // offset d = (dz, dy, dx) of a line gives this row's V3[i][i+d] from row
+    // i of plane d, and V3[i][i-d] = V3[i-d][i] from row i-d of the same
+    // plane, read in the same step (row i-d is mostly another row of this
+    // tile, or of a neighbouring tile working at the same time, so the
+    // second read is served by the cache).  Rows i-d off the grid stay
+    // inside the plane's margins and meet a zero input.
 #pragma unroll 1
-    for (int kz = 0; kz < K; ++kz) {
-        const int jz = izc + kz - PP;
-        const FT sz = band_at(Szb, PP, Nz, izc, jz), tzv = band_at(Tzb, PP, Nz, izc, jz);
-        const bool zok = jz >= 0 && jz < Nz;
-#pragma unroll 1
-        for (int ky = 0; ky < K; ++ky) {
-            const int jy = iyc + ky - PP;
-            const FT sy = band_at(Syb, PP, Ny, iyc, jy), tyv = band_at(Tyb, PP, Ny, iyc, jy);
-            const bool yzok = zok && jy >= 0 && jy < Ny;
-            const long long lrow = row + ((long long)(kz - PP) * Ny + (ky - PP)) * Nx;
-            FT usr = 0, usi = 0, uhr = 0, uhi = 0, udr = 0, udi = 0;
+    for (int li = CL + 1; li < K * K; ++li) {
+        const int kz = li / K, ky = li % K;        // direct line
+        const int mz = K - 1 - kz, my = K - 1 - ky;  // its mirror
+        const long long fline = ((long long)(kz - PP) * Ny + (ky - PP)) * Nx;
+        const FT* __restrict__ p0 = V3h + (long long)(li * K - LC) * vstride;
+        FT a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0, a5 = 0;  // direct line: S, H, D sums
+        FT b0 = 0, b1 = 0, b2 = 0, b3 = 0, b4 = 0, b5 = 0;  // mirror line
 #pragma unroll
-            for (int kx = 0; kx < K; ++kx) {
-                const FT zr = tre[tz + kz][ty + ky][tx + kx], zi = tim[tz + kz][ty + ky][tx + kx];
-                usr += sx[kx] * zr;
-                usi += sx[kx] * zi;
-                uhr += hx[kx] * zr;
-                uhi += hx[kx] * zi;
-                if constexpr (OBS) {
-                    udr += dxv[kx] * zr;
-                    udi += dxv[kx] * zi;
-                }
-                const int l = (kz * K + ky) * K + kx;
-                FT v;
-                if (l >= LC) {
-                    v = V3h[(long long)(l - LC) * N + row];
-                } else {
-                    // V3[i][i+o] = V3[i+o][i]: the stored offset -o at row i+o
-                    const bool ok = yzok && ((xok >> kx) & 1u);
-                    v = V3h[(long long)(LC - l) * N + (ok ? lrow + (kx - PP) : row)];
-                }
-                Vr += v * zr;
-                Vi += v * zi;
-            }
-            const FT szy = sz * sy, hzy = sz * tyv + tzv * sy;
-            Sr += szy * usr;
-            Si += szy * usi;
-            Hr += szy * uhr + hzy * usr;
-            Hi += szy * uhi + hzy * usi;
+        for (int kx = 0; kx < K; ++kx) {
+            const gptr pd = (gptr)(p0 + (long long)kx * vstride);
+            const gptr pm = (gptr)(p0 + (long long)kx * vstride - fline - (kx - PP));
+            const FT vd = pd[urow], vm = pm[urow];
+            const C2 zd = tc[tz + kz][ty + ky][tx + kx];
+            const C2 zm = tc[tz + mz][ty + my][tx + K - 1 - kx];
+            Vr += vd * zd.x + vm * zm.x;
+            Vi += vd * zd.y + vm * zm.y;
+            a0 += sx[kx] * zd.x;
+            a1 += sx[kx] * zd.y;
+            a2 += hx[kx] * zd.x;
+            a3 += hx[kx] * zd.y;
+            b0 += sx[K - 1 - kx] * zm.x;
+            b1 += sx[K - 1 - kx] * zm.y;
+            b2 += hx[K - 1 - kx] * zm.x;
+            b3 += hx[K - 1 - kx] * zm.y;
             if constexpr (OBS) {
-                Dr += szy * udr;
-                Di += szy * udi;
+                a4 += dxv[kx] * zd.x;
+                a5 += dxv[kx] * zd.y;
+                b4 += dxv[K - 1 - kx] * zm.x;
+                b5 += dxv[K - 1 - kx] * zm.y;
             }
         }
+        line_sums(kz, ky, a0, a1, a2, a3, a4, a5);
+        line_sums(mz, my, b0, b1, b2, b3, b4, b5);
+    }
+    {
+        // the centre line: the diagonal, and dx > 0 with its mirror -dx
+        FT a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0, a5 = 0;
+        const FT* __restrict__ p0 = V3h;
+#pragma unroll
+        for (int kx = 0; kx < K; ++kx) {
+            const C2 z = tc[tz + PP][ty + PP][tx + kx];
+            a0 += sx[kx] * z.x;
+            a1 += sx[kx] * z.y;
+            a2 += hx[kx] * z.x;
+            a3 += hx[kx] * z.y;
+            if constexpr (OBS) {
+                a4 += dxv[kx] * z.x;
+                a5 += dxv[kx] * z.y;
+            }
+        }
+        const FT v0 = ((gptr)p0)[urow];
+        const C2 z0 = tc[tz + PP][ty + PP][tx + PP];
+        Vr += v0 * z0.x;
+        Vi += v0 * z0.y;
+#pragma unroll
+        for (int e = 1; e <= PP; ++e) {
+            const gptr pd = (gptr)(p0 + (long long)e * vstride);
+            const FT vd = pd[urow], vm = (pd - e)[urow];
+            const C2 zd = tc[tz + PP][ty + PP][tx + PP + e], zm = tc[tz + PP][ty + PP][tx + PP - e];
+            Vr += vd * zd.x + vm * zm.x;
+            Vi += vd * zd.y + vm * zm.y;
+        }
+        line_sums(PP, PP, a0, a1, a2, a3, a4, a5);
     }
     double nu = 0.0, dip = 0.0;
     if (ix < Nx && iy < Ny && iz < Nz) {
@@ -300,7 +379,8 @@ __global__ __launch_bounds__(256, 2) void apply3_kernel(
         ore[row] = accr;
         oim[row] = acci;
         if constexpr (OBS) {
-            const double c0r = tre[tz + PP][ty + PP][tx + PP], c0i = tim[tz + PP][ty + PP][tx + PP];
+            const C2 c0 = tc[tz + PP][ty + PP][tx + PP];
+            const double c0r = c0.x, c0i = c0.y;
             nu = c0r * (double)Sr + c0i * (double)Si;
             dip = c0r * (double)Dr + c0i * (double)Di;
         }
@@ -318,9 +398,8 @@ __global__ __launch_bounds__(256, 2) void apply3_kernel(
             __syncthreads();
         }
         if (threadIdx.x == 0) {
-            const long long blk = ((long long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-            obs[2 * blk] = red[0][0];
-            obs[2 * blk + 1] = red[1][0];
+            obs[2 * tile] = red[0][0];
+            obs[2 * tile + 1] = red[1][0];
         }
     }
 }
@@ -333,7 +412,9 @@ using namespace tdsez;
 struct tdsez_system3d_s {
     SystemData ax, ay, az;     // per-axis 1D matrices (V = 0, m = 1)
     int Nx = 0, Ny = 0, Nz = 0, p = 0, order = 0, nq = 0;
-    double* d_V3h = nullptr;   // half stencil, [offset][row]
+    double* d_V3h = nullptr;   // half stencil, [offset][margin + row + margin]
+    long long v3_margin = 0;   // p (Ny Nx + Nx + 1): the largest row offset of a neighbour
+    long long v3_stride = 0;   // N + 2 margin
     double* d_Qx = nullptr;    // per-axis generalised eigenvectors (column-major)
     double* d_Qy = nullptr;
     double* d_Qz = nullptr;
@@ -381,7 +462,7 @@ tdsez_status ensure_fp32_3d(tdsez_system3d_s* s) {
     if (s->d_work32) return TDSEZ_OK;
     const int Nx = s->Nx, Ny = s->Ny, Nz = s->Nz, p = s->p;
     const long long n = (long long)Nx * Ny * Nz;
-    const long long nv = (long long)half3_count(p) * n;
+    const long long nv = (long long)half3_count(p) * s->v3_stride;
     const long long bx = (long long)Nx * (p + 1), by = (long long)Ny * (p + 1), bz = (long long)Nz * (p + 1);
     float *v3 = nullptr, *bands = nullptr, *qx = nullptr, *qy = nullptr, *qz = nullptr, *work = nullptr;
     hipError_t he = hipSuccess;
@@ -427,17 +508,18 @@ struct Op3D {
     const CnWork& cw;
     double alpha;
     template <typename FT>
-    void apply_t(const FT* const* b, const FT* V3h, const FT* cr, const FT* ci, const FT* yr, const FT* yi, double wr,
+    void apply_t(const FT* const* b, const FT* V3pad, const FT* cr, const FT* ci, const FT* yr, const FT* yi, double wr,
                  double wi, double ar, double ai, double br, double bi, double Eb, FT* outr, FT* outi, double* obsp,
                  const double* flag, hipStream_t stream) {
         const int Nx = s->Nx, Ny = s->Ny, Nz = s->Nz;
-        const dim3 grid = stencil3_grid<FT>(Nx, Ny, Nz);
+        const dim3 tiles = stencil3_grid<FT>(Nx, Ny, Nz);
+        const unsigned grid = stencil3_launch(tiles);
         const bool ob = obsp != nullptr;
         switch (s->p * 2 + (ob ? 1 : 0)) {
 #define TD3_CASE(PV_, OB_)                                                                                       \
     case PV_ * 2 + OB_:                                                                                          \
-        apply3_kernel<PV_, FT, OB_><<<grid, 256, 0, stream>>>(Nx, Ny, Nz, b[0], b[1], b[2], b[3], b[4], b[5],     \
-                                                                b[6], V3h, cr, ci, yr, yi, (FT)wr, (FT)wi, (FT)ar, \
+        apply3_kernel<PV_, FT, OB_><<<grid, 256, 0, stream>>>(Nx, Ny, Nz, tiles, b[0], b[1], b[2], b[3], b[4], b[5], \
+                                                                b[6], V3pad + s->v3_margin, s->v3_stride, cr, ci, yr, yi, (FT)wr, (FT)wi, (FT)ar, \
                                                                 (FT)ai, (FT)br, (FT)bi, (FT)Eb, outr, outi, obsp, \
                                                                 flag);                                           \
         break;
@@ -608,14 +690,16 @@ tdsez_status tdsez_assemble_3d(const double* breaks_x, int nbx, const double* br
         H(hipMalloc(&dVq, sizeof(double) * nV));
         H(hipMalloc(&dA1, sizeof(double) * (size_t)slab * nq * nqy * Nx * w));
         H(hipMalloc(&dA2, sizeof(double) * (size_t)slab * nq * per_qz));
-        H(hipMalloc(&s->d_V3h, sizeof(double) * (size_t)half3_count(p) * n));
+        s->v3_margin = (long long)p * ((long long)Ny * Nx + Nx + 1);
+        s->v3_stride = n + 2 * s->v3_margin;
+        const long long nv3 = (long long)half3_count(p) * s->v3_stride;
+        H(hipMalloc(&s->d_V3h, sizeof(double) * (size_t)nv3));
         if (he == hipSuccess) {
             H(hipMemcpy(dgw, gw, sizeof(double) * nq, hipMemcpyHostToDevice));
             H(hipMemcpy(dVq, V_q, sizeof(double) * nV, hipMemcpyHostToDevice));
         }
         if (he == hipSuccess) {
-            copy_kernel<double><<<grid_for((long long)half3_count(p) * n), 256>>>((long long)half3_count(p) * n,
-                                                                                  nullptr, s->d_V3h, nullptr);
+            copy_kernel<double><<<grid_for(nv3), 256>>>(nv3, nullptr, s->d_V3h, nullptr);
             const int nelz = nbz - 1;
             for (int es0 = 0; es0 < nelz && he == hipSuccess; es0 += slab) {
                 const int es1 = std::min(es0 + slab, nelz) - 1;
@@ -625,7 +709,8 @@ tdsez_status tdsez_assemble_3d(const double* breaks_x, int nbx, const double* br
                 // rows whose z B-spline (global index iz + 1, spans iz + 1 - p .. iz + 1)
                 // meets the slab
                 const int iz0 = std::max(0, es0 - 1), iz1 = std::min(Nz - 1, es1 + p - 1);
-                v3_z_kernel<<<4096, 256>>>(Nx, Ny, Nz, p, nq, nelz, es0, es1, iz0, iz1, dbz, dgw, dBz, dA2, s->d_V3h);
+                v3_z_kernel<<<4096, 256>>>(Nx, Ny, Nz, p, nq, nelz, es0, es1, iz0, iz1, dbz, dgw, dBz, dA2,
+                                           s->d_V3h + s->v3_margin, s->v3_stride);
                 H(hipGetLastError());
             }
             H(hipDeviceSynchronize());
@@ -668,8 +753,9 @@ tdsez_status tdsez_get_v3_rows(tdsez_system3d s, const long* rows, int nrows, do
     // small systems: one copy of the whole half stencil; large ones: the
     // needed entries one by one (meant for a few sampled rows)
     std::vector<double> all;
-    if ((long long)nh * n <= (32ll << 20)) {
-        all.resize((size_t)nh * n);
+    const long long M = s->v3_margin, vs = s->v3_stride;
+    if ((long long)nh * vs <= (32ll << 20)) {
+        all.resize((size_t)nh * vs);
         TDSEZ_HIP_TRY(hipMemcpy(all.data(), s->d_V3h, sizeof(double) * all.size(), hipMemcpyDeviceToHost));
     }
     for (int r = 0; r < nrows; ++r) {
@@ -680,8 +766,8 @@ tdsez_status tdsez_get_v3_rows(tdsez_system3d s, const long* rows, int nrows, do
             const int jz = iz + dz, jy = iy + dy, jx = ix + dx;
             double v = 0.0;
             if (jz >= 0 && jz < Nz && jy >= 0 && jy < Ny && jx >= 0 && jx < Nx) {
-                const long long at = l >= lc ? (long long)(l - lc) * n + row
-                                             : (long long)(lc - l) * n + ((long long)jz * Ny + jy) * Nx + jx;
+                const long long at = M + (l >= lc ? (long long)(l - lc) * vs + row
+                                                  : (long long)(lc - l) * vs + ((long long)jz * Ny + jy) * Nx + jx);
                 if (!all.empty())
                     v = all[(size_t)at];
                 else
@@ -706,6 +792,42 @@ tdsez_status tdsez_apply_3d(tdsez_system3d s, const double* c, double* out, doub
     op.apply(kC, -1, 0.0, 0.0, are, aim, bre, bim, Ebar, kB, nullptr, nullptr, stream);
     from_planar_kernel<<<g, 256, 0, stream>>>(cw.re(kB), cw.im(kB), cw.n, out);
     TDSEZ_HIP_TRY(hipGetLastError());
+    return TDSEZ_OK;
+}
+
+tdsez_status tdsez_time_apply_3d(tdsez_system3d s, tdsez_precision prec, int reps, void* stream_v, double* ms_out) {
+    if (!s || !ms_out) return fail(TDSEZ_EINVAL, "NULL argument");
+    if (reps < 1) return fail(TDSEZ_EINVAL, "reps must be >= 1");
+    if (prec != TDSEZ_FP64 && prec != TDSEZ_FP32_REFINED) return fail(TDSEZ_EINVAL, "unknown precision %d", (int)prec);
+    const bool mixed = prec == TDSEZ_FP32_REFINED;
+    if (mixed) {
+        if (tdsez_status st = ensure_fp32_3d(s)) return st;
+    }
+    hipStream_t stream = (hipStream_t)stream_v;
+    CnWork cw;
+    cw.n = (long long)s->Nx * s->Ny * s->Nz;
+    cw.w = s->d_work;
+    cw.w32 = s->d_work32;
+    Op3D op{s, cw, 0.0};
+    const int g = grid_for(2 * cw.n);
+    // q = A p as in a Krylov iteration (inputs: a filled vector)
+    if (mixed) copy_kernel<float><<<g, 256, 0, stream>>>(2 * cw.n, nullptr, cw.re32(kP32), nullptr);
+    else copy_kernel<double><<<g, 256, 0, stream>>>(2 * cw.n, nullptr, cw.re(kP), nullptr);
+    hipEvent_t e0, e1;
+    TDSEZ_HIP_TRY(hipEventCreate(&e0));
+    TDSEZ_HIP_TRY(hipEventCreate(&e1));
+    TDSEZ_HIP_TRY(hipEventRecord(e0, stream));
+    for (int r = 0; r < reps; ++r) {
+        if (mixed) op.apply32(kP32, 1.0, 0.0, 0.0, 0.005, 0.01, kQ32, nullptr, stream);
+        else op.apply(kP, -1, 0.0, 0.0, 1.0, 0.0, 0.0, 0.005, 0.01, kQ, nullptr, nullptr, stream);
+    }
+    TDSEZ_HIP_TRY(hipEventRecord(e1, stream));
+    TDSEZ_HIP_TRY(hipEventSynchronize(e1));
+    float ms = 0.f;
+    TDSEZ_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *ms_out = (double)ms / reps;
     return TDSEZ_OK;
 }
 

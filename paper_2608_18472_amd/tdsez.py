@@ -78,6 +78,8 @@ def lib():
         "tdsez_apply_3d": [vp, vp, vp, d, d, d, d, d, vp],
         "tdsez_propagate_3d": [vp, vp, vp, d, i, i, u, vp, d, i, vp],
         "tdsez_system3d_stats": [vp, lp, lp, ip, lp],
+        "tdsez_time_apply_3d": [vp, i, i, vp, dp],
+        "tdsez_time_apply_2d": [vp, i, i, vp, dp],
         "tdsez_batch_status": [vp, vp, ip, ip],
         "tdsez_batch_profile": [vp, vp, dp],
         "tdsez_autotune": [vp, i, d],
@@ -649,3 +651,11 @@ def system3d_stats(sys3d):
     _check(lib().tdsez_system3d_stats(sys3d.handle, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),
                                       ctypes.byref(d)))
     return a.value, b.value, c.value, d.value
+
+
+def time_apply(sys_nd, prec=FP64, reps=20, stream=None):
+    """Average ms per launch of the 2D or 3D operator kernel (HIP events)."""
+    ms = ctypes.c_double()
+    f = lib().tdsez_time_apply_3d if isinstance(sys_nd, System3D) else lib().tdsez_time_apply_2d
+    _check(f(sys_nd.handle, int(prec), int(reps), _stream_handle(stream), ctypes.byref(ms)))
+    return ms.value
