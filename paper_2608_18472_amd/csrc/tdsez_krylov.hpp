@@ -130,6 +130,13 @@ __global__ void add_kernel(long long n, const FT* __restrict__ xr, const FT* __r
     }
 }
 
+// r = b - q (q in FP32, r and b in FP64; planar, 2n values)
+__global__ void sub32_kernel(long long n2, const double* __restrict__ b, const float* __restrict__ q,
+                             double* __restrict__ r) {
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n2; e += (long long)gridDim.x * blockDim.x)
+        r[e] = b[e] - (double)q[e];
+}
+
 // FP64 -> FP32 copy
 __global__ void to_fp32_kernel(long long n, const double* __restrict__ src, float* __restrict__ dst,
                                const double* __restrict__ flag = nullptr) {
@@ -359,7 +366,8 @@ __global__ __launch_bounds__(kRedThreads) void obs_finish_kernel(const double* _
 // iterations (of the step; of the current sweep for the inner block),
 // sc[10] squared relative tolerance, sc[11] refinement sweeps of the step,
 // inner block only: sc[12] largest and sc[13] total inner iterations of the
-// step's sweeps.  One block sums the partials of the last
+// step's sweeps, sc[16 + s] the inner iterations of sweep s < kLogSweeps.
+// One block sums the partials of the last
 // dot (fixed order) and updates the scalars for `mode`:
 //   0: rho = sum          1: alpha = rho / sum
 //   2: beta = sum / rho, rho = sum
@@ -367,7 +375,11 @@ __global__ __launch_bounds__(kRedThreads) void obs_finish_kernel(const double* _
 //      |r|^2 <= sc[10] |b|^2
 //   4: |b|^2 = sum
 enum { kScRho = 0, kScAlpha = 2, kScBeta = 4, kScR2 = 6, kScB2 = 7, kScDone = 8, kScIts = 9, kScTol2 = 10,
-       kScSweeps = 11, kScItsMax = 12, kScItsSum = 13, kScBlock = 16 };
+       kScSweeps = 11, kScItsMax = 12, kScItsSum = 13, kScSweepIts = 16, kScBlock = 24 };
+// Refinement sweeps whose inner iteration counts are logged per step, and the
+// ints of the per-step log: FP64 iterations, largest inner iterations of a
+// sweep, sweeps, total inner iterations, then one count per logged sweep.
+constexpr int kLogSweeps = 4, kLogStride = 4 + kLogSweeps;
 __global__ __launch_bounds__(kRedThreads) void cocg_scalar_kernel(const double* __restrict__ part, int nblk,
                                                                   int mode, double* __restrict__ sc, bool count) {
     if (sc[kScDone] != 0.0) return;
@@ -420,6 +432,8 @@ __global__ __launch_bounds__(kRedThreads) void cocg_scalar_kernel(const double* 
 __global__ void sweep_start_kernel(double* __restrict__ outer, double* __restrict__ inner, double kInner) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     // fold the previous sweep's inner iterations into the step's counts
+    const int prev = (int)outer[kScSweeps] - 1;
+    if (prev >= 0 && prev < kLogSweeps) inner[kScSweepIts + prev] = fmax(inner[kScSweepIts + prev], inner[kScIts]);
     inner[kScItsMax] = fmax(inner[kScItsMax], inner[kScIts]);
     inner[kScItsSum] += inner[kScIts];
     inner[kScIts] = 0.0;
@@ -434,9 +448,8 @@ __global__ void sweep_start_kernel(double* __restrict__ outer, double* __restric
 }
 
 // End of a step: an unconverged solve latches ENOCONV (first step only);
-// the step's counts (FP64 iterations, largest inner iterations of a sweep,
-// sweeps, total inner iterations) go to the host-visible log; the flags and
-// counters are reset for the next step.
+// the step's counts (kLogStride ints) go to the host-visible log; the flags
+// and counters are reset for the next step.
 __global__ void step_end_kernel(double* __restrict__ outer, double* __restrict__ inner, int step,
                                 int* __restrict__ status, int* __restrict__ log) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
@@ -444,10 +457,19 @@ __global__ void step_end_kernel(double* __restrict__ outer, double* __restrict__
         status[0] = TDSEZ_ENOCONV;
         status[1] = step;
     }
-    log[4 * step + 0] = (int)outer[kScIts];
-    log[4 * step + 1] = (int)fmax(inner[kScItsMax], inner[kScIts]);
-    log[4 * step + 2] = (int)outer[kScSweeps];
-    log[4 * step + 3] = (int)(inner[kScItsSum] + inner[kScIts]);
+    const int last = (int)outer[kScSweeps] - 1;
+    if (last >= 0 && last < kLogSweeps) inner[kScSweepIts + last] = fmax(inner[kScSweepIts + last], inner[kScIts]);
+    int* lg = log + (size_t)kLogStride * step;
+    lg[1] = (int)fmax(inner[kScItsMax], inner[kScIts]);
+    lg[2] = (int)outer[kScSweeps];
+    lg[3] = (int)(inner[kScItsSum] + inner[kScIts]);
+    for (int k = 0; k < kLogSweeps; ++k) {
+        lg[4 + k] = (int)inner[kScSweepIts + k];
+        inner[kScSweepIts + k] = 0.0;
+    }
+    // written last: the host takes a non-negative entry 0 as "the row is complete"
+    __threadfence_system();
+    lg[0] = (int)outer[kScIts];
     outer[kScDone] = 0.0;
     outer[kScIts] = 0.0;
     outer[kScSweeps] = 0.0;
@@ -569,13 +591,13 @@ tdsez_status cn_cocg_propagate(const CnWork& cw, Op& op, double* psi, const doub
     const double* fi = inner + kScDone;
     int* log = nullptr;
     int* log_dev = nullptr;
-    TDSEZ_HIP_TRY(hipHostMalloc((void**)&log, sizeof(int) * 4 * ((size_t)nsteps + 1),
+    TDSEZ_HIP_TRY(hipHostMalloc((void**)&log, sizeof(int) * kLogStride * ((size_t)nsteps + 1),
                                 hipHostMallocMapped | hipHostMallocCoherent));
     struct LogGuard {
         int* p;
         ~LogGuard() { (void)hipHostFree(p); }
     } guard{log};
-    for (size_t i = 0; i < 4 * ((size_t)nsteps + 1); ++i) log[i] = -1;
+    for (size_t i = 0; i < kLogStride * ((size_t)nsteps + 1); ++i) log[i] = -1;
     TDSEZ_HIP_TRY(hipHostGetDevicePointer((void**)&log_dev, log, 0));
     const int g = grid_for(n);
     {
@@ -612,9 +634,9 @@ tdsez_status cn_cocg_propagate(const CnWork& cw, Op& op, double* psi, const doub
     int known = -1;  // last step whose log entry has arrived
     auto budget = [&](int col, int first, int margin) {
         volatile const int* lg = log;
-        while (known + 1 < nsteps && lg[4 * (known + 1) + 0] >= 0) ++known;
+        while (known + 1 < nsteps && lg[kLogStride * (known + 1) + 0] >= 0) ++known;
         int mx = -1;
-        for (int j = known; j >= 0 && j > known - kWindow; --j) mx = std::max(mx, (int)lg[4 * j + col]);
+        for (int j = known; j >= 0 && j > known - kWindow; --j) mx = std::max(mx, (int)lg[kLogStride * j + col]);
         const int b = mx < 0 ? first : mx + margin;
         return std::min(std::max(b, 1), maxit);
     };
@@ -626,8 +648,17 @@ tdsez_status cn_cocg_propagate(const CnWork& cw, Op& op, double* psi, const doub
             obs_finish_kernel<<<1, kRedThreads, 0, stream>>>(cw.obs_part, cw.nblk_obs, obs_out + 3 * (size_t)step,
                                                              obs);
         if (step == nsteps) break;
-        // A x = b, A = S + i a H, warm start from the previous increment
-        op.apply(kX, kB, 1.0, 0.0, -1.0, 0.0, 0.0, -alpha, Eb, kR, nullptr, nullptr, stream);  // r = b - A x
+        // A x = b, A = S + i a H, warm start from the previous increment: r = b - A x.
+        // The refined path forms this first residual with the FP32 operator: its
+        // rounding (relative 1e-7 of A x) only perturbs the first sweep's right-hand
+        // side, and the FP64 residual that ends the sweep removes it.
+        if (!mixed) {
+            op.apply(kX, kB, 1.0, 0.0, -1.0, 0.0, 0.0, -alpha, Eb, kR, nullptr, nullptr, stream);
+        } else {
+            to_fp32_kernel<<<g, 256, 0, stream>>>(2 * n, cw.re(kX), cw.re32(kE32), nullptr);
+            op.apply32(kE32, 1.0, 0.0, 0.0, alpha, Eb, kQ32, nullptr, stream);
+            sub32_kernel<<<g, 256, 0, stream>>>(2 * n, cw.re(kB), cw.re32(kQ32), cw.re(kR));
+        }
         dot_dev(kB, kB, true, 4, false, nullptr);
         dot_dev(kR, kR, true, 3, false, nullptr);
         if (!mixed) {
@@ -651,9 +682,15 @@ tdsez_status cn_cocg_propagate(const CnWork& cw, Op& op, double* psi, const doub
         } else {
             // iterative refinement: FP64 residual r = b - A x, FP32 COCG on
             // A e = r (same preconditioner in FP32), x += e
-            const int Ki = budget(1, 12, kMargin);
+            // per sweep: a margin of 2 over that sweep's recent counts (the
+            // counts of successive sweeps differ; one budget for all would
+            // enqueue the first sweep's count for every sweep)
+            const int Kall = budget(1, 12, kMargin);
             const int Ks = budget(2, 3, 1);
             for (int sw = 0; sw < Ks; ++sw) {
+                // a sweep that recent steps did not need (count 0) keeps the full budget
+                const int Kw = sw < kLogSweeps ? budget(4 + sw, 12, 2) : 0;
+                const int Ki = Kw > 2 ? std::min(Kw, Kall) : Kall;
                 sweep_start_kernel<<<1, 64, 0, stream>>>(outer, inner, kInnerTol);
                 to_fp32_kernel<<<g, 256, 0, stream>>>(2 * n, cw.re(kR), cw.re32(kR32), fo);
                 copy_kernel<float><<<g, 256, 0, stream>>>(2 * n, nullptr, cw.re32(kE32), fo);
@@ -689,10 +726,11 @@ tdsez_status cn_cocg_propagate(const CnWork& cw, Op& op, double* psi, const doub
     int stat[4] = {0, 0, 0, 0};
     TDSEZ_HIP_TRY(hipMemcpy(stat, cw.status, sizeof(stat), hipMemcpyDeviceToHost));
     for (int st = 0; st < nsteps; ++st) {
-        const int it = mixed ? log[4 * st + 3] : log[4 * st + 0];
+        const int* lg = log + (size_t)kLogStride * st;
+        const int it = mixed ? lg[3] : lg[0];
         stats->iters_total += it;
         stats->iters_max = std::max(stats->iters_max, it);
-        stats->sweeps_total += log[4 * st + 2];
+        stats->sweeps_total += lg[2];
         stats->steps_total += 1;
     }
     if (stat[0] == TDSEZ_ENOCONV)
