@@ -35,8 +35,8 @@ CALIB_COPY_BYTES = 512 * 2 ** 20
 # (FETCH_SIZE, then WRITE_SIZE) scaled by the copy calibration; valid only for
 # the kernel sources they were taken on (sha256 of the listed files) and the
 # default --split.  See profiles/propagate_kernel_fp32_batch1024_pmc.md.
-TRAFFIC = {"sources_sha256": "2a4ce85a0e4e3f7767fe1d4a564169950bf2744c047da1adba9306ae49815cc8",
-           "bytes_per_launch": 2.4232e13, "split": 160}
+TRAFFIC = {"sources_sha256": "d249a4f2d43b42c2ddec4a01d29231563de1efd9bf85b98bd53c75b92ae3f8d4",
+           "bytes_per_launch": 2.4251e+13, "split": 160}
 KERNEL_SOURCES = ["paper_2608_18472_amd/csrc/tdsez_passes.hpp", "paper_2608_18472_amd/csrc/tdsez_propagate.hip",
                   "paper_2608_18472_amd/csrc/tdsez_internal.hpp", "paper_2608_18472_amd/csrc/tdsez_run.hpp",
                   "paper_2608_18472_amd/csrc/tdsez_prop_f32.hip"]
