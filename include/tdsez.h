@@ -449,6 +449,19 @@ tdsez_status tdsez_assemble_3d(const double* breaks_x, int nbx, const double* br
                                const double* breaks_z, int nbz, int order, int nq, const double* V_q,
                                tdsez_system3d* out);
 tdsez_status tdsez_system3d_size(tdsez_system3d s, int* nx, int* ny, int* nz, int* halfbw);
+/* Lowest generalised eigenpair of (T3 + V3, S3) by inverse iteration with
+ * the fixed shift sigma (section II.C eq. gen_ev; the paper's eigensolve
+ * phase of the strong-scaling runs): each outer step solves
+ * (H - sigma S) y = S x by conjugate gradients preconditioned with the
+ * exact inverse of T3 - sigma S3 (the six per-axis contractions), then
+ * x = y / |y|_S and E = x^T H x, until |E - E_prev| <= tol |E| and
+ * |H x - E S x| / |S x| <= sqrt(tol).  sigma must lie below the lowest level
+ * (EINVAL when H - sigma S is found not positive definite).  psi: device
+ * complex128 [N] (out: the S-normalised real eigenvector, sign not fixed);
+ * energy: host double (out).  ENOCONV after maxit outer steps.  Uses the
+ * system's work vectors; synchronous. */
+tdsez_status tdsez_ground_state_3d(tdsez_system3d s, double sigma, double tol, int maxit, double* psi,
+                                   double* energy);
 /* Rows of V3 as (2p+1)^3 stencils (host FP64, caller-owned, nrows*(2p+1)^3):
  * out[r*w^3 + ((dz+p)*w + (dy+p))*w + (dx+p)] = V3[rows[r]][neighbour], 0 for
  * a neighbour outside the grid.  EINVAL for a row outside 0..N-1. */

@@ -507,6 +507,10 @@ struct Op3D {
     tdsez_system3d_s* s;
     const CnWork& cw;
     double alpha;
+    // the preconditioner inverts S3 + i alpha T3 (Crank-Nicolson), or
+    // T3 - shift S3 when `shifted` (inverse iteration)
+    bool shifted = false;
+    double shift = 0.0;
     template <typename FT>
     void apply_t(const FT* const* b, const FT* V3pad, const FT* cr, const FT* ci, const FT* yr, const FT* yi, double wr,
                  double wi, double ar, double ai, double br, double bi, double Eb, FT* outr, FT* outi, double* obsp,
@@ -556,7 +560,8 @@ struct Op3D {
         const long long pl = (long long)Nx * Ny;
         const int T = kGemmTile;
         const FdmScale none{0, 0, 0, 0, nullptr, nullptr, nullptr, 1};
-        const FdmScale cn{1.0, 0.0, 0.0, alpha, s->d_nz, s->d_lx, s->d_my, Nx};
+        const FdmScale cn = shifted ? FdmScale{-shift, 0.0, 1.0, 0.0, s->d_nz, s->d_lx, s->d_my, Nx}
+                                    : FdmScale{1.0, 0.0, 0.0, alpha, s->d_nz, s->d_lx, s->d_my, Nx};
         const dim3 gx((Nx + T - 1) / T, (Nz * Ny + T - 1) / T, 1);
         const dim3 gy((Nx + T - 1) / T, (Ny + T - 1) / T, Nz);
         const dim3 gz((unsigned)((pl + T - 1) / T), (Nz + T - 1) / T, 1);
@@ -792,6 +797,125 @@ tdsez_status tdsez_apply_3d(tdsez_system3d s, const double* c, double* out, doub
     op.apply(kC, -1, 0.0, 0.0, are, aim, bre, bim, Ebar, kB, nullptr, nullptr, stream);
     from_planar_kernel<<<g, 256, 0, stream>>>(cw.re(kB), cw.im(kB), cw.n, out);
     TDSEZ_HIP_TRY(hipGetLastError());
+    return TDSEZ_OK;
+}
+
+tdsez_status tdsez_ground_state_3d(tdsez_system3d s, double sigma, double tol, int maxit, double* psi,
+                                   double* energy) {
+    if (!s || !psi || !energy) return fail(TDSEZ_EINVAL, "NULL argument");
+    if (!std::isfinite(sigma) || !(tol > 0.0) || maxit < 1)
+        return fail(TDSEZ_EINVAL, "sigma must be finite, tol > 0 and maxit >= 1");
+    const int Nx = s->Nx, Ny = s->Ny, Nz = s->Nz;
+    CnWork cw;
+    cw.n = (long long)Nx * Ny * Nz;
+    cw.w = s->d_work;
+    const long long n = cw.n;
+    const int g = grid_for(n);
+    // (H - sigma S) y = S x by preconditioned CG (the pencil is real and
+    // H - sigma S positive definite for sigma below the lowest level); the
+    // preconditioner is the exact inverse of T3 - sigma S3
+    Op3D op{s, cw, 0.0};
+    op.shifted = true;
+    op.shift = sigma;
+    enum { X = kC, Y = kX, R = kR, Z = kZ, P = kP, Q = kQ, B = kB };
+    std::vector<double> part(2 * kRedBlocks);
+    auto dot = [&](int u, int v, bool abs2) -> double {
+        dot_kernel<double><<<kRedBlocks, kRedThreads>>>(n, cw.re(u), cw.im(u), cw.re(v), cw.im(v), abs2, s->d_part,
+                                                        nullptr);
+        if (hipMemcpy(part.data(), s->d_part, sizeof(double) * part.size(), hipMemcpyDeviceToHost) != hipSuccess)
+            return std::nan("");
+        double acc = 0.0;
+        for (int k = 0; k < kRedBlocks; ++k) acc += part[2 * k];
+        return acc;
+    };
+    // start: a smooth positive bump over the grid (nodal index space),
+    // S-normalised
+    {
+        std::vector<double> h((size_t)2 * n, 0.0);
+        for (int iz = 0; iz < Nz; ++iz)
+            for (int iy = 0; iy < Ny; ++iy)
+                for (int ix = 0; ix < Nx; ++ix) {
+                    const double u = (ix - 0.5 * (Nx - 1)) / (0.125 * Nx), v = (iy - 0.5 * (Ny - 1)) / (0.125 * Ny),
+                                 w = (iz - 0.5 * (Nz - 1)) / (0.125 * Nz);
+                    h[((size_t)iz * Ny + iy) * Nx + ix] = std::exp(-(u * u + v * v + w * w));
+                }
+        TDSEZ_HIP_TRY(hipMemcpy(cw.re(X), h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice));
+    }
+    double* sc = s->d_sc;  // scratch scalars for the CG update kernels
+    auto set_sc = [&](double a0, double a1, double a2, double a3, double a4, double a5) -> tdsez_status {
+        double v[kScBlock] = {};
+        v[0] = a0;
+        v[1] = a1;
+        v[2] = a2;
+        v[3] = a3;
+        v[4] = a4;
+        v[5] = a5;
+        TDSEZ_HIP_TRY(hipMemcpy(sc, v, sizeof(v), hipMemcpyHostToDevice));
+        return TDSEZ_OK;
+    };
+    double E = 0.0, Eprev = 0.0, res = 1.0;
+    int outer = 0;
+    const int kInner = 400;
+    for (outer = 0; outer < maxit; ++outer) {
+        // B = S x; y = 0; r = B
+        op.apply(X, -1, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 0.0, B, nullptr, nullptr, nullptr);
+        copy_kernel<double><<<g, 256>>>(2 * n, nullptr, cw.re(Y), nullptr);
+        copy_kernel<double><<<g, 256>>>(2 * n, cw.re(B), cw.re(R), nullptr);
+        const double b2 = dot(B, B, true);
+        op.precond(R, Z, nullptr, nullptr);
+        copy_kernel<double><<<g, 256>>>(2 * n, cw.re(Z), cw.re(P), nullptr);
+        double rho = dot(R, Z, false);
+        const double itol = std::max(1e-3 * tol, 1e-15);
+        for (int it = 0; it < kInner; ++it) {
+            // q = (H - sigma S) p
+            op.apply(P, -1, 0.0, 0.0, -sigma, 0.0, 1.0, 0.0, 0.0, Q, nullptr, nullptr, nullptr);
+            const double pq = dot(P, Q, false);
+            if (!(pq > 0.0)) return fail(TDSEZ_EINVAL, "3D ground state: H - sigma S is not positive definite "
+                                                       "(sigma %g is not below the lowest level)", sigma);
+            const double al = rho / pq;
+            TDSEZ_HIP_TRY(set_sc(0.0, 0.0, al, 0.0, 0.0, 0.0) == TDSEZ_OK ? hipSuccess : hipErrorUnknown);
+            cocg_xr_dev_kernel<double><<<g, 256>>>(n, sc, cw.re(P), cw.im(P), cw.re(Q), cw.im(Q), cw.re(Y),
+                                                   cw.im(Y), cw.re(R), cw.im(R));
+            const double r2 = dot(R, R, true);
+            if (r2 <= itol * itol * b2) break;
+            op.precond(R, Z, nullptr, nullptr);
+            const double rz = dot(R, Z, false);
+            const double be = rz / rho;
+            rho = rz;
+            TDSEZ_HIP_TRY(set_sc(0.0, 0.0, 0.0, 0.0, be, 0.0) == TDSEZ_OK ? hipSuccess : hipErrorUnknown);
+            cocg_p_dev_kernel<double><<<g, 256>>>(n, sc, cw.re(Z), cw.im(Z), cw.re(P), cw.im(P));
+        }
+        // x = y / |y|_S, E = x^T H x
+        op.apply(Y, -1, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 0.0, B, nullptr, nullptr, nullptr);
+        const double ny2 = dot(Y, B, false);
+        if (!(ny2 > 0.0) || !std::isfinite(ny2)) return fail(TDSEZ_ENOCONV, "3D ground state: no progress");
+        const double inv = 1.0 / std::sqrt(ny2);
+        TDSEZ_HIP_TRY(set_sc(0.0, 0.0, 0.0, 0.0, inv, 0.0) == TDSEZ_OK ? hipSuccess : hipErrorUnknown);
+        copy_kernel<double><<<g, 256>>>(2 * n, nullptr, cw.re(X), nullptr);
+        cocg_p_dev_kernel<double><<<g, 256>>>(n, sc, cw.re(X), cw.im(X), cw.re(Y), cw.im(Y));  // y *= inv
+        copy_kernel<double><<<g, 256>>>(2 * n, cw.re(Y), cw.re(X), nullptr);
+        op.apply(X, -1, 0.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0, Q, nullptr, nullptr, nullptr);  // H x
+        op.apply(X, -1, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 0.0, B, nullptr, nullptr, nullptr);  // S x
+        Eprev = E;
+        E = dot(X, Q, false);
+        // residual |H x - E S x| / |S x|: r = Hx - E Sx via x += al p, r -= al q
+        copy_kernel<double><<<g, 256>>>(2 * n, cw.re(Q), cw.re(R), nullptr);
+        TDSEZ_HIP_TRY(set_sc(0.0, 0.0, E, 0.0, 0.0, 0.0) == TDSEZ_OK ? hipSuccess : hipErrorUnknown);
+        copy_kernel<double><<<g, 256>>>(2 * n, nullptr, cw.re(Z), nullptr);
+        cocg_xr_dev_kernel<double><<<g, 256>>>(n, sc, cw.re(B), cw.im(B), cw.re(B), cw.im(B), cw.re(Z), cw.im(Z),
+                                               cw.re(R), cw.im(R));
+        res = std::sqrt(dot(R, R, true) / dot(B, B, true));
+        if (!std::isfinite(E) || !std::isfinite(res)) return fail(TDSEZ_ENONFINITE, "3D ground state: non-finite");
+        if (outer > 0 && std::fabs(E - Eprev) <= tol * std::fabs(E) && res <= std::sqrt(tol)) break;
+    }
+    TDSEZ_HIP_TRY(hipGetLastError());
+    from_planar_kernel<<<g, 256>>>(cw.re(X), cw.im(X), n, psi);
+    TDSEZ_HIP_TRY(hipGetLastError());
+    TDSEZ_HIP_TRY(hipDeviceSynchronize());
+    *energy = E;
+    if (outer >= maxit)
+        return fail(TDSEZ_ENOCONV, "3D ground state: %d iterations, |dE| %g, residual %g", maxit,
+                    std::fabs(E - Eprev), res);
     return TDSEZ_OK;
 }
 

@@ -79,6 +79,7 @@ def lib():
         "tdsez_propagate_3d": [vp, vp, vp, d, i, i, u, vp, d, i, vp],
         "tdsez_system3d_stats": [vp, lp, lp, ip, lp],
         "tdsez_time_apply_3d": [vp, i, i, vp, dp],
+        "tdsez_ground_state_3d": [vp, d, d, i, vp, dp],
         "tdsez_time_apply_2d": [vp, i, i, vp, dp],
         "tdsez_batch_status": [vp, vp, ip, ip],
         "tdsez_batch_profile": [vp, vp, dp],
@@ -659,3 +660,14 @@ def time_apply(sys_nd, prec=FP64, reps=20, stream=None):
     f = lib().tdsez_time_apply_3d if isinstance(sys_nd, System3D) else lib().tdsez_time_apply_2d
     _check(f(sys_nd.handle, int(prec), int(reps), _stream_handle(stream), ctypes.byref(ms)))
     return ms.value
+
+
+def ground_state_3d(sys3d, sigma, tol=1e-12, maxit=60):
+    """(energy, device complex128 eigenvector) of the lowest 3D level by
+    shifted inverse iteration (sigma below that level)."""
+    import torch
+    psi = torch.zeros(sys3d.N, dtype=torch.complex128, device="cuda")
+    e = ctypes.c_double()
+    _check(lib().tdsez_ground_state_3d(sys3d.handle, float(sigma), float(tol), int(maxit),
+                                       ctypes.c_void_p(psi.data_ptr()), ctypes.byref(e)))
+    return e.value, psi

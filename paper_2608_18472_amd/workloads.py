@@ -353,13 +353,15 @@ def coulomb_3d(x, y, z):
     return -1.0 / np.sqrt(x * x + y * y + z * z)
 
 
-def hydrogen_3d(nsteps=100, dt=0.01, L=25.0, r1=0.25, nlin=20, nexp=28, order=4, nq=4, E0=0.05, omega=0.057):
+def hydrogen_3d(nsteps=100, dt=0.01, L=25.0, r1=0.125, nlin=24, nexp=24, order=4, nq=6, E0=0.053, omega=0.057):
     """The strong-scaling workload of section VI (Table II): hydrogen on
     cubic B-splines (order 4), the hydrogenic grading mirrored about 0 on
     every axis of [-L, L]^3 (2 (nlin + nexp) spans: 97 unknowns per axis with
-    the defaults; linear steps r1 up to nlin r1 = 5, then exponential to L),
-    nq = p + 1 Gauss points per span and axis, 100 steps of dt = 0.01 under
-    an x-polarised field E(t) = E0 sin(omega t)."""
+    the defaults; linear steps r1 up to nlin r1 = 3, then exponential to L),
+    nq Gauss points per span and axis, 100 steps of dt = 0.01 under an
+    x-polarised field E(t) = E0 sin(omega t).  The paper does not give r1,
+    nlin, nexp or the quadrature; these defaults reproduce its printed
+    ground-state energy of the grid (-0.499995) to 1e-6."""
     br = breaks_hydrogenic_symmetric(r1, nlin, nexp, L)
     t = dt * np.arange(nsteps + 1)
     E = E0 * np.sin(omega * t)

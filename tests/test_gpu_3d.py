@@ -206,3 +206,61 @@ def test_full_size_rows_operator_and_100_steps():
     assert np.abs(o32[:, 0] / o32[0, 0] - 1.0).max() < 1e-10
     assert rel(o32[:, 1], o64[:, 1]) < 1e-5
     assert np.abs(o64[-1, 1]) > 1e-6  # the field moved the dipole
+
+
+def test_ground_state_matches_oracle_dense_pencil(small):
+    """Lowest level of the reduced box: the library's shifted inverse
+    iteration against the oracle's dense generalised eigensolve of the same
+    Kronecker-assembled pencil (LAPACK, the definition)."""
+    import scipy.linalg as sl
+    sd, g, m3 = small
+    D = {k: O.band_to_dense(m3[k]) for k in ("Sx", "Tx", "Sy", "Ty", "Sz", "Tz")}
+    S3 = np.kron(D["Sz"], np.kron(D["Sy"], D["Sx"]))
+    H3 = (np.kron(D["Sz"], np.kron(D["Sy"], D["Tx"])) + np.kron(D["Sz"], np.kron(D["Ty"], D["Sx"]))
+          + np.kron(D["Tz"], np.kron(D["Sy"], D["Sx"])))
+    n = g.N
+    p = m3["p"]
+    for row in range(n):  # the potential from the oracle's stencil rows
+        iz, rem = divmod(row, g.Ny * g.Nx)
+        iy, ix = divmod(rem, g.Nx)
+        for dz in range(-p, p + 1):
+            for dy in range(-p, p + 1):
+                jz, jy = iz + dz, iy + dy
+                if not (0 <= jz < g.Nz and 0 <= jy < g.Ny):
+                    continue
+                for dx in range(-p, p + 1):
+                    jx = ix + dx
+                    if 0 <= jx < g.Nx:
+                        H3[row, (jz * g.Ny + jy) * g.Nx + jx] += m3["V3"][row, dz + p, dy + p, dx + p]
+    ev, vec = sl.eigh(H3, S3, subset_by_index=[0, 0])
+    e_ref, x_ref = ev[0], vec[:, 0]
+    e, psi = T.ground_state_3d(g, -0.8, tol=1e-13, maxit=80)
+    x = psi.cpu().numpy().real
+    say("3D ground state: library %.15f oracle %.15f" % (e, e_ref))
+    assert abs(e - e_ref) < 1e-12 * abs(e_ref)
+    x = x * np.sign(x @ S3 @ x_ref)
+    assert np.abs(x - x_ref).max() < 1e-7 * np.abs(x_ref).max()
+    assert float(psi.imag.abs().max()) == 0.0
+
+
+def test_ground_state_full_size():
+    """97^3 hydrogen: the lowest level of the grid and an eigen-residual
+    check through the operator.  The quadrature of the Coulomb singularity
+    (knots on the nucleus) is not exact, so the Galerkin upper bound -1/2
+    does not hold strictly; the paper prints -0.499995 for this grid, and the
+    workload's unstated knot and quadrature parameters were read so as to
+    reproduce it (a reading, so this comparison checks that the reading
+    stays in force rather than pinning the method)."""
+    sd = W.hydrogen_3d(nsteps=1)
+    g = T.assemble_workload_3d(sd)
+    e, psi = T.ground_state_3d(g, -0.6, tol=1e-12)
+    say("97^3 hydrogen ground state %.9f (printed: -0.499995)" % e)
+    assert abs(e - (-0.499995)) < 2e-6
+    out = torch.zeros_like(psi)
+    T.apply_3d(g, psi, out, -e, 1.0)  # (H - e S) psi
+    s_psi = torch.zeros_like(psi)
+    T.apply_3d(g, psi, s_psi, 1.0, 0.0)
+    torch.cuda.synchronize()
+    res = float(out.abs().norm() / s_psi.abs().norm())
+    say("eigen-residual |(H - E S) x| / |S x| = %.2e" % res)
+    assert res < 1e-5
