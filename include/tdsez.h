@@ -175,11 +175,17 @@ tdsez_status tdsez_set_projectors(tdsez_system sys, int npop, const double* phi)
 /* Columns of the system's extended series: 10 + npop. */
 tdsez_status tdsez_ext_columns(tdsez_system sys, int* ncols);
 
-/* N (unknowns after Dirichlet removal) and half-bandwidth p. */
+/* N (unknowns after Dirichlet removal) and half-bandwidth p: the size of the
+ * Galerkin system of section II.C (eq. matrixODE) after the homogeneous
+ * Dirichlet conditions, and the band half-width p of every matrix of
+ * section V.A (B-splines of degree p overlap p neighbours). */
 tdsez_status tdsez_system_size(tdsez_system sys, int* ndof, int* halfbw);
 
 /* Copy one assembled band to host memory, (p+1)*N doubles in the header's
- * band convention; `which` is a TDSEZ_BAND_* selector.  Synchronous. */
+ * band convention; `which` is a TDSEZ_BAND_* selector (the element
+ * matrices of section V.A, the velocity K of eq. vel_elem, the absorber W
+ * of the CAP element formula, the a_Q form of eq. aQ_definition).
+ * Synchronous. */
 tdsez_status tdsez_get_band(tdsez_system sys, int which, double* host_out);
 
 /* Lowest `nev` eigenpairs of the generalised problem H0 c = e S c
@@ -211,9 +217,10 @@ tdsez_status tdsez_ground_state_batched(tdsez_batch b, double sigma, double tol,
                                         double* eps_out, double* psi_packed, const long* psi_off);
 
 /* Create a propagation plan for nsys systems (copied handles are borrowed:
- * the systems must outlive the batch).  Packs every system's bands into the
- * propagation layout in FP64 and FP32 and sizes the device workspaces.
- * Synchronous. */
+ * the systems must outlive the batch): the batched form of the
+ * Crank-Nicolson step of section V.B (eq. cn_system), one independent
+ * system per workgroup.  Packs every system's bands into the propagation
+ * layout in FP64 and FP32 and sizes the device workspaces.  Synchronous. */
 tdsez_status tdsez_batch_create(const tdsez_system* sys, int nsys, tdsez_batch* out);
 
 /* Tuning knobs of a batch.  key: "refine" (FP64-residual refinement sweeps
