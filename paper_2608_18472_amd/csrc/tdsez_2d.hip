@@ -126,7 +126,8 @@ dim3 stencil_grid(int Nx, int Ny) {
 //      there).  The two reads of a plane are issued together, so the second
 //      finds most of its lines already on their way.
 // With obs != null every block writes partial sums of Re c^H S2 c and
-// Re c^H D2 c (FP64).  Four tiles per CU (<= 128 VGPRs) let the 1024 tiles
+// Re c^H D2 c (FP64); with dotp != null (and obs null) the partial sum of
+// c^T out (unconjugated, FP64).  Four tiles per CU (<= 128 VGPRs) let the 1024 tiles
 // of a 512 x 512 grid run in one round.
 template <int PP, typename FT>
 __global__ __launch_bounds__(kStencilThreads, 4) void apply_kernel(
@@ -134,7 +135,7 @@ __global__ __launch_bounds__(kStencilThreads, 4) void apply_kernel(
     const FT* __restrict__ Syb, const FT* __restrict__ Tyb, const FT* __restrict__ V2h, const FT* __restrict__ cre,
     const FT* __restrict__ cim, const FT* __restrict__ yre, const FT* __restrict__ yim, FT wre, FT wim, FT are,
     FT aim, FT bre, FT bim, FT Ebar, FT* __restrict__ ore, FT* __restrict__ oim, double* __restrict__ obs,
-    const double* __restrict__ flag) {
+    const double* __restrict__ flag, double* __restrict__ dotp) {
     if (flag && *flag != 0.0) return;  // the solve has converged
     constexpr int TX = TileShape<FT>::TX, TY = TileShape<FT>::TY;
     constexpr int K = 2 * PP + 1;
@@ -255,13 +256,18 @@ __global__ __launch_bounds__(kStencilThreads, 4) void apply_kernel(
         }
         ore[orow] = accr;
         oim[orow] = acci;
+        const double c0r = tre[cy][cx], c0i = tim[cy][cx];
         if (obs) {
-            const double c0r = tre[cy][cx], c0i = tim[cy][cx];
             nu = c0r * (double)Sr + c0i * (double)Si;
             dip = c0r * (double)Dr + c0i * (double)Di;
+        } else if (dotp) {
+            // c^T (A c), unconjugated (the Krylov step's p^T q)
+            nu = c0r * (double)accr - c0i * (double)acci;
+            dip = c0r * (double)acci + c0i * (double)accr;
         }
     }
-    if (obs) {
+    double* const red_out = obs ? obs : dotp;
+    if (red_out) {
         red[0][threadIdx.x] = nu;
         red[1][threadIdx.x] = dip;
         __syncthreads();
@@ -274,8 +280,8 @@ __global__ __launch_bounds__(kStencilThreads, 4) void apply_kernel(
         }
         if (threadIdx.x == 0) {
             const long long blk = (long long)blockIdx.y * gridDim.x + blockIdx.x;
-            obs[2 * blk] = red[0][0];
-            obs[2 * blk + 1] = red[1][0];
+            red_out[2 * blk] = red[0][0];
+            red_out[2 * blk + 1] = red[1][0];
         }
     }
 }
@@ -296,6 +302,7 @@ struct tdsez_system2d_s {
     double* d_work = nullptr;  // planar vectors: c, x, r, z, p, q, b, t1, t2 (2 planes each)
     double* d_part = nullptr;  // reduction partials
     double* d_obs_part = nullptr;
+    double* d_dpart = nullptr;  // partial sums of the dot products fused into the operator and preconditioner
     double* d_sc = nullptr;    // COCG scalars and flags (device), two slot blocks
     int* d_status = nullptr;   // latched failure of a propagation: code, step
     // FP32 copies for TDSEZ_FP32_REFINED, made by the first such call
@@ -325,6 +332,7 @@ void free2d(tdsez_system2d_s* s) {
     (void)hipFree(s->d_work);
     (void)hipFree(s->d_part);
     (void)hipFree(s->d_obs_part);
+    (void)hipFree(s->d_dpart);
     (void)hipFree(s->d_sc);
     (void)hipFree(s->d_status);
     (void)hipFree(s->d_V2h32);
@@ -380,8 +388,15 @@ struct Op2D {
     const CnWork& cw;
     double alpha;
     // out = w y + a S2 in + b (T2 + V2 + Eb D2) in
+    int nblk_apply(bool fp32) const {
+        const dim3 g = fp32 ? stencil_grid<float>(s->Nx, s->Ny) : stencil_grid<double>(s->Nx, s->Ny);
+        return (int)(g.x * g.y);
+    }
+    int nblk_precond() const {
+        return ((s->Nx + kGemmTile - 1) / kGemmTile) * ((s->Ny + kGemmTile - 1) / kGemmTile);
+    }
     void apply(int in, int yv, double wr, double wi, double ar, double ai, double br, double bi, double Eb, int outv,
-               double* obsp, const double* flag, hipStream_t stream) {
+               double* obsp, const double* flag, hipStream_t stream, double* dotp = nullptr) {
         const int Nx = s->Nx, Ny = s->Ny;
         const double* yr = yv >= 0 ? cw.re(yv) : nullptr;
         const double* yi = yv >= 0 ? cw.im(yv) : nullptr;
@@ -393,7 +408,7 @@ struct Op2D {
     case PV_:                                                                                                \
         apply_kernel<PV_, double><<<sgrid, kStencilThreads, 0, stream>>>(                                    \
             Nx, Ny, Sx, Tx, Dx, Sy, Ty, s->d_V2h, cw.re(in), cw.im(in), yr, yi, wr, wi, ar, ai, br, bi, Eb,   \
-            cw.re(outv), cw.im(outv), obsp, flag);                                                           \
+            cw.re(outv), cw.im(outv), obsp, flag, dotp);                                                     \
         break;
             TD2_CASE(1) TD2_CASE(2) TD2_CASE(3) TD2_CASE(4) TD2_CASE(5) TD2_CASE(6) TD2_CASE(7)
 #undef TD2_CASE
@@ -401,7 +416,7 @@ struct Op2D {
         }
     }
     void apply32(int in, double ar, double ai, double br, double bi, double Eb, int outv, const double* flag,
-                 hipStream_t stream) {
+                 hipStream_t stream, double* dotp = nullptr) {
         const int Nx = s->Nx, Ny = s->Ny, p = s->p;
         const dim3 sgrid32 = stencil_grid<float>(Nx, Ny);
         const long long bx = (long long)Nx * (p + 1), by = (long long)Ny * (p + 1);
@@ -412,7 +427,7 @@ struct Op2D {
         apply_kernel<PV_, float><<<sgrid32, kStencilThreads, 0, stream>>>(                                        \
             Nx, Ny, b32, b32 + bx, b32 + 2 * bx, b32 + 3 * bx, b32 + 3 * bx + by, s->d_V2h32, cw.re32(in),        \
             cw.im32(in), nullptr, nullptr, 0.f, 0.f, (float)ar, (float)ai, (float)br, (float)bi, (float)Eb,      \
-            cw.re32(outv), cw.im32(outv), nullptr, flag);                                                       \
+            cw.re32(outv), cw.im32(outv), nullptr, flag, dotp);                                                 \
         break;
             TD2_CASE(1) TD2_CASE(2) TD2_CASE(3) TD2_CASE(4) TD2_CASE(5) TD2_CASE(6) TD2_CASE(7)
 #undef TD2_CASE
@@ -423,7 +438,7 @@ struct Op2D {
     // the scaling 1 / (1 + i a (mu + lambda)) fused into the second
     template <typename FT>
     void precond_t(const FT* Qx, const FT* Qy, const FT* rr, const FT* ri, FT* t1r, FT* t1i, FT* t2r, FT* t2i, FT* zr,
-                   FT* zi, const double* flag, hipStream_t stream) {
+                   FT* zi, const double* flag, hipStream_t stream, double* rzp) {
         const int Nx = s->Nx, Ny = s->Ny;
         const dim3 gg((Nx + kGemmTile - 1) / kGemmTile, (Ny + kGemmTile - 1) / kGemmTile);
         const FdmScale none{0, 0, 0, 0, nullptr, nullptr, nullptr, 1};
@@ -434,16 +449,20 @@ struct Op2D {
                                                                          cn, flag);
         fdm_gemm_kernel<FT, false, false><<<gg, kGemmThreads, 0, stream>>>(Ny, Nx, Nx, Qx, Nx, 1, t2r, t2i, t1r, t1i, 0,
                                                                            0, none, flag);
-        fdm_gemm_kernel<FT, true, false><<<gg, kGemmThreads, 0, stream>>>(Ny, Nx, Ny, Qy, 1, Ny, t1r, t1i, zr, zi, 0, 0,
-                                                                          none, flag);
+        if (rzp)
+            fdm_gemm_kernel<FT, true, false, true><<<gg, kGemmThreads, 0, stream>>>(
+                Ny, Nx, Ny, Qy, 1, Ny, t1r, t1i, zr, zi, 0, 0, none, flag, rr, ri, rzp);
+        else
+            fdm_gemm_kernel<FT, true, false><<<gg, kGemmThreads, 0, stream>>>(Ny, Nx, Ny, Qy, 1, Ny, t1r, t1i, zr, zi, 0,
+                                                                              0, none, flag);
     }
-    void precond(int rin, int zout, const double* flag, hipStream_t stream) {
+    void precond(int rin, int zout, const double* flag, hipStream_t stream, double* rzp = nullptr) {
         precond_t<double>(s->d_Qx, s->d_Qy, cw.re(rin), cw.im(rin), cw.re(kT1), cw.im(kT1), cw.re(kT2), cw.im(kT2),
-                          cw.re(zout), cw.im(zout), flag, stream);
+                          cw.re(zout), cw.im(zout), flag, stream, rzp);
     }
-    void precond32(int rin, int zout, const double* flag, hipStream_t stream) {
+    void precond32(int rin, int zout, const double* flag, hipStream_t stream, double* rzp = nullptr) {
         precond_t<float>(s->d_Qx32, s->d_Qy32, cw.re32(rin), cw.im32(rin), cw.re32(kT132), cw.im32(kT132),
-                         cw.re32(kT232), cw.im32(kT232), cw.re32(zout), cw.im32(zout), flag, stream);
+                         cw.re32(kT232), cw.im32(kT232), cw.re32(zout), cw.im32(zout), flag, stream, rzp);
     }
 };
 
@@ -547,9 +566,15 @@ tdsez_status tdsez_assemble_2d(const double* breaks_x, int nbx, const double* br
         hipMalloc(&s->d_sc, sizeof(double) * 2 * kScBlock) != hipSuccess ||
         hipMalloc(&s->d_status, sizeof(int) * 4) != hipSuccess ||
         hipMalloc(&s->d_obs_part, sizeof(double) * 2 * (size_t)stencil_grid<double>(Nx, Ny).x *
-                                      stencil_grid<double>(Nx, Ny).y) !=
-            hipSuccess)
+                                      stencil_grid<double>(Nx, Ny).y) != hipSuccess)
         return bail(fail(TDSEZ_ENOMEM, "2D workspace allocation failed"));
+    {
+        const dim3 g64 = stencil_grid<double>(Nx, Ny), g32 = stencil_grid<float>(Nx, Ny);
+        const size_t nb = std::max<size_t>({(size_t)g64.x * g64.y, (size_t)g32.x * g32.y,
+                                            (size_t)((Nx + kGemmTile - 1) / kGemmTile) * ((Ny + kGemmTile - 1) / kGemmTile)});
+        if (hipMalloc(&s->d_dpart, sizeof(double) * 2 * nb) != hipSuccess)
+            return bail(fail(TDSEZ_ENOMEM, "2D workspace allocation failed"));
+    }
     *out = s;
     return TDSEZ_OK;
 }
@@ -645,6 +670,7 @@ tdsez_status tdsez_propagate_2d(tdsez_system2d s, double* psi, const double* E, 
     cw.sc = s->d_sc;
     cw.status = s->d_status;
     cw.obs_part = s->d_obs_part;
+    cw.dpart = s->d_dpart;
     const dim3 sgrid = stencil_grid<double>(s->Nx, s->Ny);
     cw.nblk_obs = (int)(sgrid.x * sgrid.y);
     Op2D op{s, cw, 0.5 * dt};

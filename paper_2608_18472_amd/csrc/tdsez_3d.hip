@@ -221,7 +221,8 @@ __global__ __launch_bounds__(256, 2) void apply3_kernel(
     const FT* __restrict__ Syb, const FT* __restrict__ Tyb, const FT* __restrict__ Szb, const FT* __restrict__ Tzb,
     const FT* __restrict__ V3h, long long vstride, const FT* __restrict__ cre, const FT* __restrict__ cim,
     const FT* __restrict__ yre, const FT* __restrict__ yim, FT wre, FT wim, FT are, FT aim, FT bre, FT bim, FT Ebar,
-    FT* __restrict__ ore, FT* __restrict__ oim, double* __restrict__ obs, const double* __restrict__ flag) {
+    FT* __restrict__ ore, FT* __restrict__ oim, double* __restrict__ obs, const double* __restrict__ flag,
+    double* __restrict__ dotp) {
     if (flag && *flag != 0.0) return;  // the solve has converged
     constexpr int TX = Tile3<FT>::TX, TY = Tile3<FT>::TY, TZ = Tile3<FT>::TZ;
     constexpr int K = 2 * PP + 1;
@@ -378,14 +379,19 @@ __global__ __launch_bounds__(256, 2) void apply3_kernel(
         }
         ore[row] = accr;
         oim[row] = acci;
+        const C2 c0 = tc[tz + PP][ty + PP][tx + PP];
+        const double c0r = c0.x, c0i = c0.y;
         if constexpr (OBS) {
-            const C2 c0 = tc[tz + PP][ty + PP][tx + PP];
-            const double c0r = c0.x, c0i = c0.y;
             nu = c0r * (double)Sr + c0i * (double)Si;
             dip = c0r * (double)Dr + c0i * (double)Di;
+        } else if (dotp) {
+            // c^T (A c), unconjugated (the Krylov step's p^T q)
+            nu = c0r * (double)accr - c0i * (double)acci;
+            dip = c0r * (double)acci + c0i * (double)accr;
         }
     }
-    if constexpr (OBS) {
+    double* const red_out = OBS ? obs : dotp;
+    if (red_out) {
         __shared__ double red[2][256];
         red[0][threadIdx.x] = nu;
         red[1][threadIdx.x] = dip;
@@ -398,8 +404,8 @@ __global__ __launch_bounds__(256, 2) void apply3_kernel(
             __syncthreads();
         }
         if (threadIdx.x == 0) {
-            obs[2 * tile] = red[0][0];
-            obs[2 * tile + 1] = red[1][0];
+            red_out[2 * tile] = red[0][0];
+            red_out[2 * tile + 1] = red[1][0];
         }
     }
 }
@@ -424,6 +430,7 @@ struct tdsez_system3d_s {
     double* d_work = nullptr;  // kNumVec64 planar FP64 vectors
     double* d_part = nullptr;
     double* d_obs_part = nullptr;
+    double* d_dpart = nullptr;  // partial sums of the dot products fused into the operator and preconditioner
     double* d_sc = nullptr;
     int* d_status = nullptr;
     // FP32 copies for TDSEZ_FP32_REFINED, made by the first such call
@@ -450,7 +457,7 @@ void free3d(tdsez_system3d_s* s) {
     free_axis(s->ay);
     free_axis(s->az);
     void* ptrs[] = {s->d_V3h, s->d_Qx, s->d_Qy, s->d_Qz, s->d_lx, s->d_my, s->d_nz, s->d_work, s->d_part,
-                    s->d_obs_part, s->d_sc, s->d_status, s->d_V3h32, s->d_bands32, s->d_Qx32, s->d_Qy32,
+                    s->d_obs_part, s->d_dpart, s->d_sc, s->d_status, s->d_V3h32, s->d_bands32, s->d_Qx32, s->d_Qy32,
                     s->d_Qz32, s->d_work32};
     for (void* q : ptrs) (void)hipFree(q);
     if (s->blas) rocblas_destroy_handle(s->blas);
@@ -511,10 +518,18 @@ struct Op3D {
     // T3 - shift S3 when `shifted` (inverse iteration)
     bool shifted = false;
     double shift = 0.0;
+    int nblk_apply(bool fp32) const {
+        const dim3 t = fp32 ? stencil3_grid<float>(s->Nx, s->Ny, s->Nz) : stencil3_grid<double>(s->Nx, s->Ny, s->Nz);
+        return (int)(t.x * t.y * t.z);
+    }
+    int nblk_precond() const {
+        // the last contraction: x, over the rows of all planes
+        return ((s->Nx + kGemmTile - 1) / kGemmTile) * ((s->Nz * s->Ny + kGemmTile - 1) / kGemmTile);
+    }
     template <typename FT>
     void apply_t(const FT* const* b, const FT* V3pad, const FT* cr, const FT* ci, const FT* yr, const FT* yi, double wr,
                  double wi, double ar, double ai, double br, double bi, double Eb, FT* outr, FT* outi, double* obsp,
-                 const double* flag, hipStream_t stream) {
+                 const double* flag, hipStream_t stream, double* dotp = nullptr) {
         const int Nx = s->Nx, Ny = s->Ny, Nz = s->Nz;
         const dim3 tiles = stencil3_grid<FT>(Nx, Ny, Nz);
         const unsigned grid = stencil3_launch(tiles);
@@ -525,7 +540,7 @@ struct Op3D {
         apply3_kernel<PV_, FT, OB_><<<grid, 256, 0, stream>>>(Nx, Ny, Nz, tiles, b[0], b[1], b[2], b[3], b[4], b[5], \
                                                                 b[6], V3pad + s->v3_margin, s->v3_stride, cr, ci, yr, yi, (FT)wr, (FT)wi, (FT)ar, \
                                                                 (FT)ai, (FT)br, (FT)bi, (FT)Eb, outr, outi, obsp, \
-                                                                flag);                                           \
+                                                                flag, dotp);                                     \
         break;
             TD3_CASE(1, 0) TD3_CASE(1, 1) TD3_CASE(2, 0) TD3_CASE(2, 1) TD3_CASE(3, 0) TD3_CASE(3, 1)
             TD3_CASE(4, 0) TD3_CASE(4, 1)
@@ -534,28 +549,28 @@ struct Op3D {
         }
     }
     void apply(int in, int yv, double wr, double wi, double ar, double ai, double br, double bi, double Eb, int outv,
-               double* obsp, const double* flag, hipStream_t stream) {
+               double* obsp, const double* flag, hipStream_t stream, double* dotp = nullptr) {
         const double* b[7] = {s->ax.d_band[0], s->ax.d_band[1], s->ax.d_band[3], s->ay.d_band[0],
                               s->ay.d_band[1], s->az.d_band[0], s->az.d_band[1]};
         apply_t<double>(b, s->d_V3h, cw.re(in), cw.im(in), yv >= 0 ? cw.re(yv) : nullptr,
                         yv >= 0 ? cw.im(yv) : nullptr, wr, wi, ar, ai, br, bi, Eb, cw.re(outv), cw.im(outv), obsp,
-                        flag, stream);
+                        flag, stream, dotp);
     }
     void apply32(int in, double ar, double ai, double br, double bi, double Eb, int outv, const double* flag,
-                 hipStream_t stream) {
+                 hipStream_t stream, double* dotp = nullptr) {
         const int p = s->p;
         const long long bx = (long long)s->Nx * (p + 1), by = (long long)s->Ny * (p + 1);
         const float* f = s->d_bands32;
         const float* b[7] = {f, f + bx, f + 2 * bx, f + 3 * bx, f + 3 * bx + by, f + 3 * bx + 2 * by,
                              f + 3 * bx + 2 * by + (long long)s->Nz * (p + 1)};
         apply_t<float>(b, s->d_V3h32, cw.re32(in), cw.im32(in), nullptr, nullptr, 0.0, 0.0, ar, ai, br, bi, Eb,
-                       cw.re32(outv), cw.im32(outv), nullptr, flag, stream);
+                       cw.re32(outv), cw.im32(outv), nullptr, flag, stream, dotp);
     }
     // z = P^-1 r, the planes of r as (Nz Ny) x Nx, per-plane Ny x Nx and
     // Nz x (Ny Nx) row-major matrices for the x, y and z contractions
     template <typename FT>
     void precond_t(const FT* Qx, const FT* Qy, const FT* Qz, const FT* rr, const FT* ri, FT* ar_, FT* ai_, FT* br_,
-                   FT* bi_, FT* zr, FT* zi, const double* flag, hipStream_t stream) {
+                   FT* bi_, FT* zr, FT* zi, const double* flag, hipStream_t stream, double* rzp) {
         const int Nx = s->Nx, Ny = s->Ny, Nz = s->Nz;
         const long long pl = (long long)Nx * Ny;
         const int T = kGemmTile;
@@ -577,16 +592,21 @@ struct Op3D {
                                                                           bi_, 0, 0, none, flag);
         fdm_gemm_kernel<FT, true, false><<<gy, kGemmThreads, 0, stream>>>(Ny, Nx, Ny, Qy, 1, Ny, br_, bi_, ar_, ai_, pl,
                                                                           pl, none, flag);
-        fdm_gemm_kernel<FT, false, false><<<gx, kGemmThreads, 0, stream>>>(Nz * Ny, Nx, Nx, Qx, Nx, 1, ar_, ai_, zr, zi,
-                                                                           0, 0, none, flag);
+        if (rzp)
+            fdm_gemm_kernel<FT, false, false, true><<<gx, kGemmThreads, 0, stream>>>(
+                Nz * Ny, Nx, Nx, Qx, Nx, 1, ar_, ai_, zr, zi, 0, 0, none, flag, rr, ri, rzp);
+        else
+            fdm_gemm_kernel<FT, false, false><<<gx, kGemmThreads, 0, stream>>>(Nz * Ny, Nx, Nx, Qx, Nx, 1, ar_, ai_, zr,
+                                                                               zi, 0, 0, none, flag);
     }
-    void precond(int rin, int zout, const double* flag, hipStream_t stream) {
+    void precond(int rin, int zout, const double* flag, hipStream_t stream, double* rzp = nullptr) {
         precond_t<double>(s->d_Qx, s->d_Qy, s->d_Qz, cw.re(rin), cw.im(rin), cw.re(kT1), cw.im(kT1), cw.re(kT2),
-                          cw.im(kT2), cw.re(zout), cw.im(zout), flag, stream);
+                          cw.im(kT2), cw.re(zout), cw.im(zout), flag, stream, rzp);
     }
-    void precond32(int rin, int zout, const double* flag, hipStream_t stream) {
+    void precond32(int rin, int zout, const double* flag, hipStream_t stream, double* rzp = nullptr) {
         precond_t<float>(s->d_Qx32, s->d_Qy32, s->d_Qz32, cw.re32(rin), cw.im32(rin), cw.re32(kT132),
-                         cw.im32(kT132), cw.re32(kT232), cw.im32(kT232), cw.re32(zout), cw.im32(zout), flag, stream);
+                         cw.im32(kT132), cw.re32(kT232), cw.im32(kT232), cw.re32(zout), cw.im32(zout), flag, stream,
+                         rzp);
     }
 };
 
@@ -734,6 +754,14 @@ tdsez_status tdsez_assemble_3d(const double* breaks_x, int nbx, const double* br
         hipMalloc(&s->d_status, sizeof(int) * 4) != hipSuccess ||
         hipMalloc(&s->d_obs_part, sizeof(double) * 2 * (size_t)sg.x * sg.y * sg.z) != hipSuccess)
         return bail(fail(TDSEZ_ENOMEM, "3D workspace allocation failed"));
+    {
+        const dim3 s32 = stencil3_grid<float>(Nx, Ny, Nz);
+        const size_t nb = std::max<size_t>({(size_t)sg.x * sg.y * sg.z, (size_t)s32.x * s32.y * s32.z,
+                                            (size_t)((Nx + kGemmTile - 1) / kGemmTile) *
+                                                ((Nz * Ny + kGemmTile - 1) / kGemmTile)});
+        if (hipMalloc(&s->d_dpart, sizeof(double) * 2 * nb) != hipSuccess)
+            return bail(fail(TDSEZ_ENOMEM, "3D workspace allocation failed"));
+    }
     *out = s;
     return TDSEZ_OK;
 }
@@ -977,6 +1005,7 @@ tdsez_status tdsez_propagate_3d(tdsez_system3d s, double* psi, const double* E, 
     cw.sc = s->d_sc;
     cw.status = s->d_status;
     cw.obs_part = s->d_obs_part;
+    cw.dpart = s->d_dpart;
     const dim3 sg = stencil3_grid<double>(s->Nx, s->Ny, s->Nz);
     cw.nblk_obs = (int)(sg.x * sg.y * sg.z);
     Op3D op{s, cw, 0.5 * dt};

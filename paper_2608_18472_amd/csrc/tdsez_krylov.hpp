@@ -6,13 +6,17 @@
 // (section V.B in the increment form A_n Delta = -i dt H_n c_n).
 //
 // A tensor-product system supplies its own operator and preconditioner
-// through an object with four members (FP64 and FP32 versions of each):
-//   apply(in, y, w, a, b, Ebar, out, obs_part, flag):
+// through an object with these members (FP64 and FP32 versions of the
+// first two):
+//   apply(in, y, w, a, b, Ebar, out, obs_part, flag, stream, dotp):
 //       out = w y + a S c_in + b (H0 + Ebar D) c_in   (y optional),
 //       with per-block partial sums of Re c^H S c and Re c^H D c when
-//       obs_part is given;
-//   precond(in, out, flag): out = P^-1 in, P the separable part;
-// both returning at once when *flag is set (the solve has converged).
+//       obs_part is given, or of c_in^T out when dotp is given;
+//   precond(in, out, flag, stream, rzp): out = P^-1 in, P the separable
+//       part, with per-block partial sums of in^T out when rzp is given;
+//   nblk_apply(fp32), nblk_precond(): the number of those partial sums;
+// apply and precond return at once when *flag is set (the solve has
+// converged).
 // Complex vectors are planar (real plane, then imaginary plane).
 //
 // Everything here has internal linkage: each translation unit that
@@ -204,11 +208,16 @@ struct FdmScale {
     const double* lam_hi;
     int nx;
 };
-template <typename FT, bool LEFTQ, bool SCALE>
+// DOT (the last contraction of a preconditioner application z = P^-1 r):
+// the workgroup also writes the partial sum of r^T z over its tile
+// (unconjugated, FP64) to part[2 b], part[2 b + 1], b its block index,
+// reading r (dr, di: same layout as the result) at the tile's entries.
+template <typename FT, bool LEFTQ, bool SCALE, bool DOT = false>
 __global__ __launch_bounds__(kGemmThreads) void fdm_gemm_kernel(
     int M, int N, int K, const FT* __restrict__ Q, int qs0, int qs1, const FT* __restrict__ vr,
     const FT* __restrict__ vi, FT* __restrict__ cr, FT* __restrict__ ci, long long vbs, long long cbs,
-    FdmScale sc, const double* __restrict__ flag) {
+    FdmScale sc, const double* __restrict__ flag, const FT* __restrict__ dr = nullptr,
+    const FT* __restrict__ di = nullptr, double* __restrict__ part = nullptr) {
     if (flag && *flag != 0.0) return;
     // batch blockIdx.z: the vector operand and the result advance by vbs, cbs
     vr += blockIdx.z * vbs;
@@ -314,6 +323,7 @@ __global__ __launch_bounds__(kGemmThreads) void fdm_gemm_kernel(
         }
     }
     const int gn = n0 + wn + li;
+    double pr = 0.0, pi = 0.0;
     for (int r = 0; r < 4; ++r) {
         const int gm = m0 + wm + MfmaOps<FT>::row(lk, r);
         if (gm >= M || gn >= N) continue;
@@ -321,14 +331,38 @@ __global__ __launch_bounds__(kGemmThreads) void fdm_gemm_kernel(
         if constexpr (SCALE) {
             double L = sc.mu_m[gm] + sc.lam_n[gn % sc.nx];
             if (sc.lam_hi) L += sc.lam_hi[gn / sc.nx];
-            const double dr = sc.c0r + sc.c1r * L, di = sc.c0i + sc.c1i * L;
-            const double s = 1.0 / (dr * dr + di * di);
+            const double er = sc.c0r + sc.c1r * L, ei = sc.c0i + sc.c1i * L;
+            const double s = 1.0 / (er * er + ei * ei);
             const double ad = a, bd = b;
-            a = (FT)((ad * dr + bd * di) * s);
-            b = (FT)((bd * dr - ad * di) * s);
+            a = (FT)((ad * er + bd * ei) * s);
+            b = (FT)((bd * er - ad * ei) * s);
         }
-        cr[(long long)gm * N + gn] = a;
-        ci[(long long)gm * N + gn] = b;
+        const long long at = (long long)gm * N + gn;
+        cr[at] = a;
+        ci[at] = b;
+        if constexpr (DOT) {
+            const double xr = dr[blockIdx.z * cbs + at], xi = di[blockIdx.z * cbs + at];
+            pr += xr * (double)a - xi * (double)b;
+            pi += xr * (double)b + xi * (double)a;
+        }
+    }
+    if constexpr (DOT) {
+        __shared__ double red[2][kGemmThreads];
+        red[0][tid] = pr;
+        red[1][tid] = pi;
+        __syncthreads();
+        for (int s2 = kGemmThreads / 2; s2 > 0; s2 >>= 1) {
+            if (tid < s2) {
+                red[0][tid] += red[0][tid + s2];
+                red[1][tid] += red[1][tid + s2];
+            }
+            __syncthreads();
+        }
+        if (tid == 0) {
+            const long long b = ((long long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+            part[2 * b] = red[0][0];
+            part[2 * b + 1] = red[1][0];
+        }
     }
 }
 
@@ -494,6 +528,68 @@ __global__ void cocg_xr_dev_kernel(long long n, const double* __restrict__ sc, c
     }
 }
 
+// x += al p, r -= al q with al = sc[2..3], and the partial sums of |r|^2
+// (FP64) per block into part[2 b] (part[2 b + 1] = 0); grid kRedBlocks
+template <typename FT>
+__global__ __launch_bounds__(kRedThreads) void cocg_xr_norm_kernel(long long n, const double* __restrict__ sc,
+                                                                   const FT* __restrict__ pr, const FT* __restrict__ pi,
+                                                                   const FT* __restrict__ qr, const FT* __restrict__ qi,
+                                                                   FT* __restrict__ xr, FT* __restrict__ xi,
+                                                                   FT* __restrict__ rr, FT* __restrict__ ri,
+                                                                   double* __restrict__ part) {
+    if (sc[kScDone] != 0.0) return;
+    __shared__ double red[kRedThreads];
+    const FT alr = (FT)sc[2], ali = (FT)sc[3];
+    double acc = 0.0;
+    for (long long e = blockIdx.x * (long long)kRedThreads + threadIdx.x; e < n; e += (long long)gridDim.x * kRedThreads) {
+        xr[e] += alr * pr[e] - ali * pi[e];
+        xi[e] += alr * pi[e] + ali * pr[e];
+        const FT a = rr[e] - (alr * qr[e] - ali * qi[e]);
+        const FT b = ri[e] - (alr * qi[e] + ali * qr[e]);
+        rr[e] = a;
+        ri[e] = b;
+        acc += (double)a * (double)a + (double)b * (double)b;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = kRedThreads / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = red[0];
+        part[2 * blockIdx.x + 1] = 0.0;
+    }
+}
+
+// Start of an inner solve: r32 = (float) r, e32 = 0, and the partial sums of
+// |r32|^2 (FP64) per block into part; 2n values (both planes); grid
+// kRedBlocks; skipped when *flag is set
+__global__ __launch_bounds__(kRedThreads) void sweep_setup_kernel(long long n2, const double* __restrict__ r,
+                                                                  float* __restrict__ r32, float* __restrict__ e32,
+                                                                  double* __restrict__ part,
+                                                                  const double* __restrict__ flag) {
+    if (flag && *flag != 0.0) return;
+    __shared__ double red[kRedThreads];
+    double acc = 0.0;
+    for (long long e = blockIdx.x * (long long)kRedThreads + threadIdx.x; e < n2; e += (long long)gridDim.x * kRedThreads) {
+        const float v = (float)r[e];
+        r32[e] = v;
+        e32[e] = 0.f;
+        acc += (double)v * (double)v;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = kRedThreads / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = red[0];
+        part[2 * blockIdx.x + 1] = 0.0;
+    }
+}
+
 // p = z + be p with be = sc[4..5]
 template <typename FT>
 __global__ void cocg_p_dev_kernel(long long n, const double* __restrict__ sc, const FT* __restrict__ zr,
@@ -559,6 +655,7 @@ struct CnWork {
     int* status = nullptr;    // 4 ints: latched code, step
     double* obs_part = nullptr;
     int nblk_obs = 0;         // per-block observable partials written by apply
+    double* dpart = nullptr;  // partials of the dot products fused into apply and the preconditioner
     double* re(int k) const { return w + (size_t)(2 * k) * n; }
     double* im(int k) const { return w + (size_t)(2 * k + 1) * n; }
     float* re32(int k) const { return w32 + (size_t)(2 * k) * n; }
@@ -616,17 +713,13 @@ tdsez_status cn_cocg_propagate(const CnWork& cw, Op& op, double* psi, const doub
                                                                    cw.part, flag);
         cocg_scalar_kernel<<<1, kRedThreads, 0, stream>>>(cw.part, kRedBlocks, mode, outer, count);
     };
-    auto dot32 = [&](int u, int v, bool abs2, int mode, bool count) {
-        dot_kernel<float><<<kRedBlocks, kRedThreads, 0, stream>>>(n, cw.re32(u), cw.im32(u), cw.re32(v), cw.im32(v),
-                                                                  abs2, cw.part, fi);
-        cocg_scalar_kernel<<<1, kRedThreads, 0, stream>>>(cw.part, kRedBlocks, mode, inner, count);
-    };
     std::vector<double> Eh((size_t)nsteps + 1);
     TDSEZ_HIP_TRY(hipMemcpyAsync(Eh.data(), E, sizeof(double) * Eh.size(), hipMemcpyDeviceToHost, stream));
     TDSEZ_HIP_TRY(hipStreamSynchronize(stream));
     // FP32 inner solves reduce the FP64 residual by this factor per sweep
-    // (near the FP32 accuracy of the inner operator)
-    constexpr double kInnerTol = 1e-5;
+    // (within an order of the FP32 accuracy of the inner operator: two
+    // sweeps then reach 1e-12 from a residual of 1e-1)
+    constexpr double kInnerTol = 2e-6;
     // iteration budgets of a step: a margin above the largest count among
     // the last logged steps (the log lags the host by however many steps are
     // queued), capped by maxit; sweeps: a fixed budget
@@ -661,21 +754,26 @@ tdsez_status cn_cocg_propagate(const CnWork& cw, Op& op, double* psi, const doub
         }
         dot_dev(kB, kB, true, 4, false, nullptr);
         dot_dev(kR, kR, true, 3, false, nullptr);
+        // The dot products of an iteration are fused into the kernels that
+        // produce their operands (p^T q into the operator, |r|^2 into the
+        // update, r^T z into the last preconditioner contraction); one block
+        // then sums the partials in a fixed order and updates the scalars.
+        const int na64 = op.nblk_apply(false), na32 = op.nblk_apply(true), nz = op.nblk_precond();
         if (!mixed) {
             // COCG in FP64; every kernel returns once the residual has met tol
             const int K = budget(0, 12, kMargin);
-            op.precond(kR, kZ, fo, stream);
+            op.precond(kR, kZ, fo, stream, cw.dpart);
+            cocg_scalar_kernel<<<1, kRedThreads, 0, stream>>>(cw.dpart, nz, 0, outer, false);  // rho = r^T z
             copy_kernel<double><<<g, 256, 0, stream>>>(2 * n, cw.re(kZ), cw.re(kP), fo);
-            dot_dev(kR, kZ, false, 0, false, fo);
             for (int it = 0; it < K; ++it) {
-                op.apply(kP, -1, 0.0, 0.0, 1.0, 0.0, 0.0, alpha, Eb, kQ, nullptr, fo, stream);  // q = A p
-                dot_dev(kP, kQ, false, 1, false, fo);                                      // alpha = rho / p^T q
-                cocg_xr_dev_kernel<double><<<g, 256, 0, stream>>>(n, outer, cw.re(kP), cw.im(kP), cw.re(kQ),
-                                                                  cw.im(kQ), cw.re(kX), cw.im(kX), cw.re(kR),
-                                                                  cw.im(kR));
-                dot_dev(kR, kR, true, 3, true, fo);  // converged?
-                op.precond(kR, kZ, fo, stream);
-                dot_dev(kR, kZ, false, 2, false, fo);  // beta = r^T z / rho, rho = r^T z
+                op.apply(kP, -1, 0.0, 0.0, 1.0, 0.0, 0.0, alpha, Eb, kQ, nullptr, fo, stream, cw.dpart);  // q = A p
+                cocg_scalar_kernel<<<1, kRedThreads, 0, stream>>>(cw.dpart, na64, 1, outer, false);  // alpha
+                cocg_xr_norm_kernel<double><<<kRedBlocks, kRedThreads, 0, stream>>>(
+                    n, outer, cw.re(kP), cw.im(kP), cw.re(kQ), cw.im(kQ), cw.re(kX), cw.im(kX), cw.re(kR), cw.im(kR),
+                    cw.part);
+                cocg_scalar_kernel<<<1, kRedThreads, 0, stream>>>(cw.part, kRedBlocks, 3, outer, true);  // converged?
+                op.precond(kR, kZ, fo, stream, cw.dpart);
+                cocg_scalar_kernel<<<1, kRedThreads, 0, stream>>>(cw.dpart, nz, 2, outer, false);  // beta, rho
                 cocg_p_dev_kernel<double><<<g, 256, 0, stream>>>(n, outer, cw.re(kZ), cw.im(kZ), cw.re(kP),
                                                                  cw.im(kP));
             }
@@ -688,25 +786,27 @@ tdsez_status cn_cocg_propagate(const CnWork& cw, Op& op, double* psi, const doub
             const int Kall = budget(1, 12, kMargin);
             const int Ks = budget(2, 3, 1);
             for (int sw = 0; sw < Ks; ++sw) {
-                // a sweep that recent steps did not need (count 0) keeps the full budget
+                // a sweep that no recent step needed (count 0) only has to
+                // finish a residual that the sweeps before it nearly met: a
+                // short budget (a step that still misses tol latches ENOCONV)
                 const int Kw = sw < kLogSweeps ? budget(4 + sw, 12, 2) : 0;
-                const int Ki = Kw > 2 ? std::min(Kw, Kall) : Kall;
+                const int Ki = Kw > 2 ? std::min(Kw, Kall) : std::min(4, Kall);
                 sweep_start_kernel<<<1, 64, 0, stream>>>(outer, inner, kInnerTol);
-                to_fp32_kernel<<<g, 256, 0, stream>>>(2 * n, cw.re(kR), cw.re32(kR32), fo);
-                copy_kernel<float><<<g, 256, 0, stream>>>(2 * n, nullptr, cw.re32(kE32), fo);
-                dot32(kR32, kR32, true, 4, false);
-                op.precond32(kR32, kZ32, fi, stream);
+                sweep_setup_kernel<<<kRedBlocks, kRedThreads, 0, stream>>>(2 * n, cw.re(kR), cw.re32(kR32),
+                                                                           cw.re32(kE32), cw.part, fo);
+                cocg_scalar_kernel<<<1, kRedThreads, 0, stream>>>(cw.part, kRedBlocks, 4, inner, false);  // |b|^2
+                op.precond32(kR32, kZ32, fi, stream, cw.dpart);
+                cocg_scalar_kernel<<<1, kRedThreads, 0, stream>>>(cw.dpart, nz, 0, inner, false);
                 copy_kernel<float><<<g, 256, 0, stream>>>(2 * n, cw.re32(kZ32), cw.re32(kP32), fi);
-                dot32(kR32, kZ32, false, 0, false);
                 for (int it = 0; it < Ki; ++it) {
-                    op.apply32(kP32, 1.0, 0.0, 0.0, alpha, Eb, kQ32, fi, stream);  // q = A p
-                    dot32(kP32, kQ32, false, 1, false);
-                    cocg_xr_dev_kernel<float><<<g, 256, 0, stream>>>(n, inner, cw.re32(kP32), cw.im32(kP32),
-                                                                     cw.re32(kQ32), cw.im32(kQ32), cw.re32(kE32),
-                                                                     cw.im32(kE32), cw.re32(kR32), cw.im32(kR32));
-                    dot32(kR32, kR32, true, 3, true);
-                    op.precond32(kR32, kZ32, fi, stream);
-                    dot32(kR32, kZ32, false, 2, false);
+                    op.apply32(kP32, 1.0, 0.0, 0.0, alpha, Eb, kQ32, fi, stream, cw.dpart);  // q = A p
+                    cocg_scalar_kernel<<<1, kRedThreads, 0, stream>>>(cw.dpart, na32, 1, inner, false);
+                    cocg_xr_norm_kernel<float><<<kRedBlocks, kRedThreads, 0, stream>>>(
+                        n, inner, cw.re32(kP32), cw.im32(kP32), cw.re32(kQ32), cw.im32(kQ32), cw.re32(kE32),
+                        cw.im32(kE32), cw.re32(kR32), cw.im32(kR32), cw.part);
+                    cocg_scalar_kernel<<<1, kRedThreads, 0, stream>>>(cw.part, kRedBlocks, 3, inner, true);
+                    op.precond32(kR32, kZ32, fi, stream, cw.dpart);
+                    cocg_scalar_kernel<<<1, kRedThreads, 0, stream>>>(cw.dpart, nz, 2, inner, false);
                     cocg_p_dev_kernel<float><<<g, 256, 0, stream>>>(n, inner, cw.re32(kZ32), cw.im32(kZ32),
                                                                     cw.re32(kP32), cw.im32(kP32));
                 }
