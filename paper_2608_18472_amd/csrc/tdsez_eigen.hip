@@ -355,7 +355,7 @@ namespace {
 struct GsDesc {
     const double* S;
     const double* H0;
-    double* work;      // (p+1)*N factor + 3*N vectors
+    double* work;      // (p+1)*N factor + 5*N vectors
     long long psi_off; // complex elements into the packed state buffer
     int N, p;
     double sigma;
@@ -384,6 +384,29 @@ __device__ void band_mv(const double* __restrict__ M, int N, int p, const double
     }
 }
 
+// K^-1 y for the banded LDL^T factor K (one thread: the rows are serial)
+__device__ void ldl_solve_serial(const double* __restrict__ Kf, int N, int p, const double* __restrict__ y,
+                                 double* __restrict__ z) {
+    for (int i = 0; i < N; ++i) {
+        double s = y[i];
+        for (int d = 1; d <= p && i - d >= 0; ++d) s -= Kf[(long long)i * (p + 1) + d] * z[i - d];
+        z[i] = s;
+    }
+    for (int i = 0; i < N; ++i) z[i] /= Kf[(long long)i * (p + 1)];
+    for (int i = N - 1; i >= 0; --i) {
+        double s = z[i];
+        for (int d = 1; d <= p && i + d < N; ++d) s -= Kf[(long long)(i + d) * (p + 1) + d] * z[i + d];
+        z[i] = s;
+    }
+}
+
+// One system per workgroup: the lowest eigenpair of H0 c = e S c by
+// shift-and-invert subspace iteration on two vectors with a 2 x 2
+// Rayleigh-Ritz step: Z = K^-1 S X (K = H0 - sigma S, factorised once), then
+// the Ritz pairs of (Z^T H0 Z, Z^T S Z) give the next X (S-orthonormal).
+// The lowest Ritz value converges with the ratio (e0 - sigma)/(e2 - sigma),
+// so a near-degenerate lowest pair (a double well's doublet) costs no more
+// than a well separated level.
 __global__ __launch_bounds__(256) void ground_batched_kernel(const GsDesc* __restrict__ descs, double tol,
                                                              int maxit, double* __restrict__ psi,
                                                              double* __restrict__ eps_out,
@@ -391,17 +414,20 @@ __global__ __launch_bounds__(256) void ground_batched_kernel(const GsDesc* __res
     const GsDesc g = descs[blockIdx.x];
     const int N = g.N, p = g.p;
     double* Kf = g.work;
-    double* x = Kf + (long long)N * (p + 1);
-    double* y = x + N;
-    double* z = y + N;
+    double* x1 = Kf + (long long)N * (p + 1);
+    double* x2 = x1 + N;
+    double* y = x2 + N;
+    double* z1 = y + N;
+    double* z2 = z1 + N;
     __shared__ double red[4];
     __shared__ int bad;
     if (threadIdx.x == 0) bad = 0;
     for (long long e = threadIdx.x; e < (long long)N * (p + 1); e += blockDim.x)
         Kf[e] = g.H0[e] - g.sigma * g.S[e];
     for (int i = threadIdx.x; i < N; i += blockDim.x) {
-        double t = (i + 1.0) / (N + 1.0);
-        x[i] = t * (1.0 - t);  // positive, smooth start (not orthogonal to the ground state)
+        const double t = (i + 1.0) / (N + 1.0);
+        x1[i] = t * (1.0 - t);                // positive, smooth: not orthogonal to the ground state
+        x2[i] = t * (1.0 - t) * (t - 0.5);    // odd about the middle: the partner of a symmetric doublet
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -421,46 +447,97 @@ __global__ __launch_bounds__(256) void ground_batched_kernel(const GsDesc* __res
         if (threadIdx.x == 0) status[blockIdx.x] = 1;
         return;
     }
+    // u^T M v for a band matrix M (y is scratch)
+    auto form = [&](const double* M, const double* u, const double* v) {
+        band_mv(M, N, p, v, y);
+        __syncthreads();
+        double a = 0.0;
+        for (int i = threadIdx.x; i < N; i += blockDim.x) a += u[i] * y[i];
+        a = block_sum(a, red);
+        __syncthreads();
+        return a;
+    };
     double e = 0.0;
     int it = 0, converged = 0;
     for (; it < maxit && !converged; ++it) {
-        band_mv(g.S, N, p, x, y);
+        // Z = K^-1 S X
+        band_mv(g.S, N, p, x1, y);
         __syncthreads();
-        if (threadIdx.x == 0) {  // z = K^-1 y
-            for (int i = 0; i < N; ++i) {
-                double s = y[i];
-                for (int d = 1; d <= p && i - d >= 0; ++d) s -= Kf[(long long)i * (p + 1) + d] * z[i - d];
-                z[i] = s;
-            }
-            for (int i = 0; i < N; ++i) z[i] /= Kf[(long long)i * (p + 1)];
-            for (int i = N - 1; i >= 0; --i) {
-                double s = z[i];
-                for (int d = 1; d <= p && i + d < N; ++d) s -= Kf[(long long)(i + d) * (p + 1) + d] * z[i + d];
-                z[i] = s;
+        if (threadIdx.x == 0) ldl_solve_serial(Kf, N, p, y, z1);
+        __syncthreads();
+        band_mv(g.S, N, p, x2, y);
+        __syncthreads();
+        if (threadIdx.x == 0) ldl_solve_serial(Kf, N, p, y, z2);
+        __syncthreads();
+        // Rayleigh-Ritz on span(z1, z2): A = Z^T H0 Z, B = Z^T S Z
+        const double a11 = form(g.H0, z1, z1), a12 = form(g.H0, z1, z2), a22 = form(g.H0, z2, z2);
+        const double b11 = form(g.S, z1, z1), b12 = form(g.S, z1, z2), b22 = form(g.S, z2, z2);
+        // det(A - l B) = 0: qa l^2 + qb l + qc = 0, qa = det B > 0
+        const double qa = b11 * b22 - b12 * b12;
+        const double qb = -(a11 * b22 + a22 * b11 - 2.0 * a12 * b12);
+        const double qc = a11 * a22 - a12 * a12;
+        double l0, u1, u2, w1, w2;
+        if (qa > 1e-30 * b11 * b22) {
+            const double disc = sqrt(fmax(qb * qb - 4.0 * qa * qc, 0.0));
+            // the two roots without cancellation
+            const double q = -0.5 * (qb + (qb < 0.0 ? -disc : disc));
+            const double r1 = q / qa, r2 = qc / q;
+            l0 = fmin(r1, r2);
+            const double l1 = fmax(r1, r2);
+            // (A - l B) u = 0 from the better-conditioned row
+            auto vec = [&](double l, double* v1, double* v2) {
+                const double m11 = a11 - l * b11, m12 = a12 - l * b12, m22 = a22 - l * b22;
+                if (fabs(m11) + fabs(m12) >= fabs(m12) + fabs(m22)) { *v1 = -m12; *v2 = m11; }
+                else { *v1 = m22; *v2 = -m12; }
+                const double nn = (*v1) * (*v1) * b11 + 2.0 * (*v1) * (*v2) * b12 + (*v2) * (*v2) * b22;
+                const double sc = nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
+                *v1 *= sc;
+                *v2 *= sc;
+            };
+            vec(l0, &u1, &u2);
+            vec(l1, &w1, &w2);
+            // the pair is B-orthogonal up to rounding; make it exact for the second
+            const double o = u1 * w1 * b11 + (u1 * w2 + u2 * w1) * b12 + u2 * w2 * b22;
+            w1 -= o * u1;
+            w2 -= o * u2;
+            const double nn = w1 * w1 * b11 + 2.0 * w1 * w2 * b12 + w2 * w2 * b22;
+            const double sc = nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
+            w1 *= sc;
+            w2 *= sc;
+        } else {
+            // z2 has no component left outside z1 (a one-dimensional
+            // subspace): plain power step on z1, restart z2 from the odd start
+            l0 = a11 / b11;
+            u1 = 1.0 / sqrt(b11);
+            u2 = 0.0;
+            w1 = 0.0;
+            w2 = 0.0;
+        }
+        for (int i = threadIdx.x; i < N; i += blockDim.x) {
+            const double v1 = z1[i], v2 = z2[i];
+            x1[i] = u1 * v1 + u2 * v2;
+            if (w1 != 0.0 || w2 != 0.0) x2[i] = w1 * v1 + w2 * v2;
+            else {
+                const double t = (i + 1.0) / (N + 1.0);
+                x2[i] = t * (1.0 - t) * (t - 0.5);
             }
         }
         __syncthreads();
-        band_mv(g.S, N, p, z, y);
-        __syncthreads();
-        double nz = 0.0;
-        for (int i = threadIdx.x; i < N; i += blockDim.x) nz += z[i] * y[i];
-        nz = block_sum(nz, red);
-        const double sc = 1.0 / sqrt(nz);
-        for (int i = threadIdx.x; i < N; i += blockDim.x) x[i] = z[i] * sc;
-        __syncthreads();
+        // 1/(l0) is the Ritz value of K^-1 S; the eigenvalue of the pencil
+        // is the Rayleigh quotient of x1, checked with its residual
         if ((it & 3) == 3 || it == maxit - 1) {
-            band_mv(g.H0, N, p, x, y);  // y = H0 x
-            band_mv(g.S, N, p, x, z);   // z = S x
+            band_mv(g.H0, N, p, x1, y);  // y = H0 x1
+            band_mv(g.S, N, p, x1, z1);  // z1 = S x1
             __syncthreads();
             double ev = 0.0;
-            for (int i = threadIdx.x; i < N; i += blockDim.x) ev += x[i] * y[i];
+            for (int i = threadIdx.x; i < N; i += blockDim.x) ev += x1[i] * y[i];
             ev = block_sum(ev, red);
             double r2 = 0.0, h2 = 0.0, s2 = 0.0;
             for (int i = threadIdx.x; i < N; i += blockDim.x) {
-                double r = y[i] - ev * z[i];
+                double r = y[i] - ev * z1[i];
                 r2 += r * r;
                 h2 += y[i] * y[i];
-                s2 += z[i] * z[i];
+                s2 += z1[i] * z1[i];
             }
             r2 = block_sum(r2, red);
             h2 = block_sum(h2, red);
@@ -469,21 +546,22 @@ __global__ __launch_bounds__(256) void ground_batched_kernel(const GsDesc* __res
             if (sqrt(r2) < tol * (sqrt(h2) + fabs(ev) * sqrt(s2))) converged = 1;
             __syncthreads();
         }
+        (void)l0;
     }
     // sign convention: largest-magnitude component positive (lowest index on ties)
     double best = 0.0;
     int bi = 0;
     if (threadIdx.x == 0) {
         for (int i = 0; i < N; ++i)
-            if (fabs(x[i]) > best) { best = fabs(x[i]); bi = i; }
-        red[0] = x[bi] < 0.0 ? -1.0 : 1.0;
+            if (fabs(x1[i]) > best) { best = fabs(x1[i]); bi = i; }
+        red[0] = x1[bi] < 0.0 ? -1.0 : 1.0;
         eps_out[blockIdx.x] = e;
         status[blockIdx.x] = converged ? 0 : 2;
     }
     __syncthreads();
     const double sg = red[0];
     for (int i = threadIdx.x; i < N; i += blockDim.x) {
-        psi[2 * (g.psi_off + i)] = sg * x[i];
+        psi[2 * (g.psi_off + i)] = sg * x1[i];
         psi[2 * (g.psi_off + i) + 1] = 0.0;
     }
 }
@@ -495,7 +573,7 @@ tdsez_status ground_state_batched_device(BatchData* b, double sigma, double tol,
     const int nsys = (int)b->sys.size();
     std::vector<GsDesc> hd(nsys);
     long long wtot = 0;
-    for (int s = 0; s < nsys; ++s) wtot += (long long)b->sys[s]->N * (b->sys[s]->p + 4);
+    for (int s = 0; s < nsys; ++s) wtot += (long long)b->sys[s]->N * (b->sys[s]->p + 6);
     double* work = nullptr;
     GsDesc* dd = nullptr;
     double* dev_eps = nullptr;
@@ -515,7 +593,7 @@ tdsez_status ground_state_batched_device(BatchData* b, double sigma, double tol,
         SystemData* sy = b->sys[s];
         double sg = sigma >= 1e300 ? sy->minV - 1e-3 * (std::fabs(sy->minV) + 1.0) : sigma;
         hd[s] = GsDesc{sy->d_band[0], sy->d_H0, work + woff, (long long)psi_off[s], sy->N, sy->p, sg};
-        woff += (long long)sy->N * (sy->p + 4);
+        woff += (long long)sy->N * (sy->p + 6);
     }
     GB_TRY(hipMalloc(&dd, sizeof(GsDesc) * nsys));
     GB_TRY(hipMalloc(&dev_eps, sizeof(double) * nsys));
