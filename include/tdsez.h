@@ -231,8 +231,12 @@ tdsez_status tdsez_batch_create(const tdsez_system* sys, int nsys, tdsez_batch* 
  * dx = c - c_n, v = c + c_n, a = dt/2; default 1e-2; the propagation goes on,
  * the first such step is reported by tdsez_batch_status), "norm_tol" (latch ENORMDRIFT
  * when |nu_n/nu_0 - 1| > value; 0 disables, default 0), "chunks" (force the
- * partition count of every system, 0 = plan, default 0), "profile" (1 turns
- * on per-phase cycle counters read by tdsez_batch_profile, 0 off). */
+ * partition count of every system, 0 = plan, default 0; capped at 64 for a
+ * one-wave system, at 128 or 256 for a system marked by tdsez_batch_split,
+ * by max_waves), "max_waves" (2 or 4, default 2: the most waves a system
+ * marked by tdsez_batch_split may run on; re-packs the batch and clears the
+ * autotuner's plans), "profile" (1 turns on per-phase cycle counters read by
+ * tdsez_batch_profile, 0 off). */
 tdsez_status tdsez_batch_set(tdsez_batch b, const char* key, double value);
 
 /* Partition autotuner (fills the batch's plan cache).  The partitioned solve
@@ -262,27 +266,35 @@ tdsez_status tdsez_batch_chunks(tdsez_batch b, int* chunks_out);
  * length rule L = sqrt(0.3 N), and the separator system eliminated from both
  * ends at once (each wave half of the chain, joined at the middle block).
  * A marked system whose two-wave plan has at most 64 chunks stays on one
- * wave with its one-wave plan.
- * Two-wave systems run in a launch of their own on the caller's stream,
- * concurrently with the one-wave launch on an internal side stream forked
- * from and joined back into it (both at the default priority), so the
- * `stream` semantics of the propagation calls are unchanged and the calls
- * stay capturable into a graph.  Results equal the one-wave results up to
- * rounding.  count = 0 restores one wave per system.  Re-packs the batch and
- * clears the autotuner's plans (run tdsez_autotune afterwards to tune the
- * new plan; it keeps the marks).  The adjoint refuses a batch with two-wave
- * systems (EUNSUPPORTED).  nsteps: host array of nsys step counts (may be
- * NULL when count = 0).  Synchronous.  EINVAL for count outside 0..nsys or a
- * negative step count. */
+ * wave with its one-wave plan.  With the batch key max_waves = 4 a marked
+ * system whose four-wave rule L = sqrt(0.15 N) gives more than 128 chunks
+ * runs on four waves instead (up to 256 chunks), and its separator system
+ * is solved by block cyclic reduction: log2(P) levels, each level's block
+ * eliminations shared by the four waves.
+ * Multi-wave systems run in launches of their own (four-wave first, on the
+ * caller's stream), concurrently with the one-wave launch on internal side
+ * streams forked from and joined back into it (all at the default
+ * priority), so the `stream` semantics of the propagation calls are
+ * unchanged and the calls stay capturable into a graph.  Results equal the
+ * one-wave results up to rounding.  count = 0 restores one wave per system.
+ * Re-packs the batch and clears the autotuner's plans (run tdsez_autotune
+ * afterwards to tune the new plan; it keeps the marks).  The adjoint refuses
+ * a batch with multi-wave systems (EUNSUPPORTED).  nsteps: host array of
+ * nsys step counts (may be NULL when count = 0).  Synchronous.  EINVAL for
+ * count outside 0..nsys or a negative step count. */
 tdsez_status tdsez_batch_split(tdsez_batch b, const int* nsteps, int count);
 
-/* 1 for every system that runs on two waves under the current plan, else 0
- * (host array of nsys ints). */
+/* 1 for every system that runs on more than one wave under the current
+ * plan, else 0 (host array of nsys ints). */
 tdsez_status tdsez_batch_two_wave(tdsez_batch b, int* flags_out);
 
+/* Waves (1, 2 or 4) of every system under the current plan (host array of
+ * nsys ints); see tdsez_batch_split. */
+tdsez_status tdsez_batch_waves(tdsez_batch b, int* waves_out);
+
 /* Crank-Nicolson propagation of every system of the batch in one persistent
- * kernel launch (one workgroup per system; two-wave systems in a concurrent
- * launch of their own, see tdsez_batch_split), section V.B eq. cn_system with
+ * kernel launch (one workgroup per system; multi-wave systems in concurrent
+ * launches of their own, see tdsez_batch_split), section V.B eq. cn_system with
  * H^{n+1/2} = H0 + (E_n + E_{n+1})/2 D.
  *   psi_packed (device, in/out): complex128 states; system s starts at
  *       element psi_off[s] (host array of nsys offsets, in complex elements)
@@ -296,8 +308,8 @@ tdsez_status tdsez_batch_two_wave(tdsez_batch b, int* flags_out);
  * Workgroups start in order of decreasing cost N (p + 1) nsteps, so a batch
  * with more systems than the device holds at once runs longest first.
  * Asynchronous on `stream`.  Calls on one batch must not overlap (they share
- * the batch's working state, and its side stream and events when it holds
- * two-wave systems); different batches may run concurrently.  EINVAL on bad
+ * the batch's working state, and its side streams and events when it holds
+ * multi-wave systems); different batches may run concurrently.  EINVAL on bad
  * arguments (detected on the host); device-side failures are latched
  * (tdsez_batch_status). */
 tdsez_status tdsez_propagate_batched(tdsez_batch b, double* psi_packed, const long* psi_off,
@@ -319,8 +331,9 @@ tdsez_status tdsez_propagate_batched_ext(tdsez_batch b, double* psi_packed, cons
 
 /* Single-system convenience form of tdsez_propagate_batched (the library
  * keeps a one-system plan inside the system handle, created by the first
- * call).  The system runs on two waves when its two-wave plan has more than
- * 64 chunks (N above about 1290; see tdsez_batch_split).  psi: device
+ * call).  The system runs on four waves when its four-wave plan has more
+ * than 128 chunks (N above about 2460), else on two when its two-wave plan
+ * has more than 64 (N above about 1230; see tdsez_batch_split).  psi: device
  * complex128 [N] in/out; E: device FP64 [nsteps+1]; obs_out: device FP64
  * [(nsteps+1)*3] or NULL.  Asynchronous on `stream`. */
 tdsez_status tdsez_propagate(tdsez_system sys, double* psi, const double* E, double dt, int nsteps,

@@ -238,9 +238,20 @@ tdsez_status tdsez_batch_set(tdsez_batch b, const char* key, double value) {
         }
         return TDSEZ_OK;
     }
+    if (!std::strcmp(key, "max_waves")) {
+        if (value != 2.0 && value != 4.0) return fail(TDSEZ_EINVAL, "max_waves must be 2 or 4");
+        bool prof = b->d.d_prof != nullptr;
+        b->d.max_waves = (int)value;
+        b->d.tuned_chunks.clear();
+        free_batch_device(&b->d);
+        tdsez_status st = pack_bands(&b->d);
+        if (st == TDSEZ_OK && prof) return tdsez_batch_set(b, "profile", 1.0);
+        return st;
+    }
     if (!std::strcmp(key, "chunks")) {
         bool prof = b->d.d_prof != nullptr;
-        if (value < 0 || value > kMaxChunks) return fail(TDSEZ_EINVAL, "chunks must be in 0..%d", kMaxChunks);
+        if (value < 0 || value > kMaxChunks4 || value != std::floor(value))
+            return fail(TDSEZ_EINVAL, "chunks must be an integer in 0..%d", kMaxChunks4);
         b->d.force_chunks = (int)value;
         b->d.tuned_chunks.clear();
         free_batch_device(&b->d);
@@ -349,8 +360,9 @@ tdsez_status tdsez_propagate_ext(tdsez_system sys, double* psi, const double* E,
         tdsez_system one = sys;
         tdsez_status st = tdsez_batch_create(&one, 1, &sys->d.solo);
         if (st) return st;
-        // a lone system has the device to itself: two waves whenever its
-        // two-wave plan has more than 64 chunks
+        // a lone system has the device to itself: up to four waves
+        // (multi_wave_plan)
+        sys->d.solo->d.max_waves = 4;
         int nsteps_one = 1;
         if ((st = tdsez_batch_split(sys->d.solo, &nsteps_one, 1)) != TDSEZ_OK) return st;
     }
@@ -442,14 +454,16 @@ tdsez_status tdsez_autotune(tdsez_batch b, tdsez_precision prec, double budget_m
     static const double kRule[] = {0.6, 0.3, 1.2, 0.15, 2.4};
     constexpr int kTrials = sizeof(kRule) / sizeof(kRule[0]);
     constexpr int kWarm = 4, kProbe = 16;
-    // (systems that may run on two waves: half the constant, up to 128 chunks)
+    // (systems that may run on more waves: half the constant, up to 128
+    // chunks on two waves, a quarter and up to 256 on four)
     auto chunks_for = [&](int s, double c) {
         const int N = d->sys[s]->N, p = d->sys[s]->p;
         const bool req = s < (int)d->two_wave_req.size() && d->two_wave_req[s];
-        double L = std::sqrt((req ? 0.5 : 1.0) * c * N);
+        const int mw = req ? d->max_waves : 1;
+        double L = std::sqrt((mw >= 4 ? 0.25 : mw == 2 ? 0.5 : 1.0) * c * N);
         if (L < 2.0 * p + 2) L = 2.0 * p + 2;
         int P = (int)std::lround(N / L);
-        return make_plan(N, p, P < 1 ? 1 : P, req ? kMaxChunks2 : kMaxChunks).P;
+        return make_plan(N, p, P < 1 ? 1 : P, mw >= 4 ? kMaxChunks4 : mw == 2 ? kMaxChunks2 : kMaxChunks).P;
     };
     // scratch inputs: a smooth finite state, zero field (the timing does not
     // depend on the values)
@@ -597,8 +611,10 @@ void tdsez_batch_destroy(tdsez_batch b) {
     if (!b) return;
     free_batch_device(&b->d);
     if (b->d.side) (void)hipStreamDestroy(b->d.side);
+    if (b->d.side2) (void)hipStreamDestroy(b->d.side2);
     if (b->d.ev_fork) (void)hipEventDestroy(b->d.ev_fork);
     if (b->d.ev_join) (void)hipEventDestroy(b->d.ev_join);
+    if (b->d.ev_join2) (void)hipEventDestroy(b->d.ev_join2);
     delete b;
 }
 
@@ -628,7 +644,13 @@ tdsez_status tdsez_batch_split(tdsez_batch b, const int* nsteps, int count) {
 tdsez_status tdsez_batch_two_wave(tdsez_batch b, int* flags_out) {
     if (!b || !flags_out) return fail(TDSEZ_EINVAL, "NULL argument");
     for (size_t s = 0; s < b->d.sys.size(); ++s)
-        flags_out[s] = s < b->d.two_wave.size() ? (int)b->d.two_wave[s] : 0;
+        flags_out[s] = s < b->d.waves.size() && b->d.waves[s] > 1 ? 1 : 0;
+    return TDSEZ_OK;
+}
+
+tdsez_status tdsez_batch_waves(tdsez_batch b, int* waves_out) {
+    if (!b || !waves_out) return fail(TDSEZ_EINVAL, "NULL argument");
+    for (size_t s = 0; s < b->d.sys.size(); ++s) waves_out[s] = s < b->d.waves.size() ? (int)b->d.waves[s] : 1;
     return TDSEZ_OK;
 }
 

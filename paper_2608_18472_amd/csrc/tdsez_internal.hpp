@@ -15,12 +15,16 @@ namespace tdsez {
 
 // Largest supported half-bandwidth (order 8 B-splines).
 constexpr int kMaxP = 7;
-// Lanes of one wave64 (a propagation workgroup holds one or two waves).
+// Lanes of one wave64 (a propagation workgroup holds one, two or four waves).
 constexpr int kWave = 64;
 // Largest partition count of one system (one chunk per lane).
 constexpr int kMaxChunks = 64;
 // Largest partition count of a system run on two waves (tdsez_batch_split).
 constexpr int kMaxChunks2 = 2 * kWave;
+// Largest partition count of a system run on four waves (max_waves = 4).
+constexpr int kMaxChunks4 = 4 * kWave;
+// Chunk-length rules L = sqrt(c N) of one, two and four waves per system.
+constexpr double kRule1 = 0.6, kRule2 = 0.3, kRule4 = 0.15;
 // Matrices stored per band row in the propagation layout, in this order:
 // S, H0, D, G, Mi (propagation and the three main observables), W (weight of
 // the complex absorbing potential), V, K (velocity), Q (a_Q form) for the
@@ -152,11 +156,13 @@ struct BatchData {
     int* d_order = nullptr;          // workgroup -> system, longest first
     std::vector<int> order_host;     // host copy of d_order (pageable; uploaded asynchronously)
     std::vector<int> tuned_chunks;   // plan cache of tdsez_autotune (0 = rule), per system
-    std::vector<char> two_wave_req;  // per system: may run on two waves (tdsez_batch_split)
-    std::vector<char> two_wave;      // per system: plan has more than 64 chunks, runs on two waves
-    int nsplit = 0;                  // systems with two_wave set (first nsplit entries of d_order)
-    hipStream_t side = nullptr;      // second stream for the two-wave launch (default priority)
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    std::vector<char> two_wave_req;  // per system: may run on more than one wave (tdsez_batch_split)
+    int max_waves = 2;               // waves a marked system may use (2 or 4; key max_waves)
+    std::vector<char> waves;         // per system: waves of its plan (1; 2: 65..128 chunks; 4: 129..256)
+    int nsplit = 0;                  // systems on more than one wave (first nsplit entries of d_order)
+    int n4 = 0;                      // of those, systems on four waves (the first n4 entries)
+    hipStream_t side = nullptr, side2 = nullptr;  // further streams of a split launch (default priority)
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_join2 = nullptr;
     int* d_status = nullptr;         // [0] code, [1] system, [2] step
     unsigned long long* d_prof = nullptr;  // optional phase cycle counters, kProfSlots per system
     double* d_proj = nullptr;        // packed projection states S phi_k (interleaved layout)
@@ -193,14 +199,19 @@ struct KernelArgs {
 
 // ---------------------------------------------------------------- kernels
 // Persistent propagation launchers, one translation unit each
-// (tdsez_prop_*.hip): the two-wave kernel over order entries 0..n2-1 on
-// stream s2 and the one-wave kernel over entries n2..n2+n1-1 on s1.  probe
-// selects the autotuner's separately named copies (plain kernels only).
-hipError_t launch_prop_f64(const KernelArgs& ka, int n2, int n1, hipStream_t s2, hipStream_t s1, bool probe);
-hipError_t launch_prop_f32(const KernelArgs& ka, int n2, int n1, hipStream_t s2, hipStream_t s1, bool probe);
+// (tdsez_prop_*.hip): the four-wave kernel over order entries 0..n4-1 on
+// stream s4, the two-wave kernel over the next n2 entries on s2 and the
+// one-wave kernel over the n1 after them on s1.  probe selects the
+// autotuner's separately named copies (plain kernels only).
+hipError_t launch_prop_f64(const KernelArgs& ka, int n4, int n2, int n1, hipStream_t s4, hipStream_t s2,
+                           hipStream_t s1, bool probe);
+hipError_t launch_prop_f32(const KernelArgs& ka, int n4, int n2, int n1, hipStream_t s4, hipStream_t s2,
+                           hipStream_t s1, bool probe);
 // Extended kernels: absorbing potential, extended series, a_Q.
-hipError_t launch_prop_xt64(const KernelArgs& ka, int n2, int n1, hipStream_t s2, hipStream_t s1);
-hipError_t launch_prop_xt32(const KernelArgs& ka, int n2, int n1, hipStream_t s2, hipStream_t s1);
+hipError_t launch_prop_xt64(const KernelArgs& ka, int n4, int n2, int n1, hipStream_t s4, hipStream_t s2,
+                            hipStream_t s1);
+hipError_t launch_prop_xt32(const KernelArgs& ka, int n4, int n2, int n1, hipStream_t s4, hipStream_t s2,
+                            hipStream_t s1);
 // Assembly (tdsez_assemble.hip)
 tdsez_status assemble_device(const double* breaks, int nbreaks, int order, int nq,
                              const double* minv_q, const double* V_q, const double* dV_q,
@@ -214,8 +225,14 @@ tdsez_status set_projectors_device(SystemData* sys, int npop, const double* phi)
 int gauss_legendre_host(int nq, double* x, double* w);
 
 // Propagation (tdsez_propagate.hip)
-// rule c: chunk length L = sqrt(c N); max_chunks: kMaxChunks or kMaxChunks2
-Plan make_plan(int N, int p, int force_chunks, int max_chunks = kMaxChunks, double rule = 0.6);
+// rule c: chunk length L = sqrt(c N); max_chunks: kMaxChunks, kMaxChunks2 or kMaxChunks4
+Plan make_plan(int N, int p, int force_chunks, int max_chunks = kMaxChunks, double rule = kRule1);
+// Plan of a system that may use up to max_waves (1, 2 or 4) waves: the
+// rule of the most waves whose plan needs more chunks than the next fewer
+// waves hold.  force_chunks > 0 overrides the rule (capped by max_waves).
+Plan multi_wave_plan(int N, int p, int force_chunks, int max_waves);
+// Waves that a plan runs on.
+inline int plan_waves(const Plan& pl) { return pl.P > kMaxChunks2 ? 4 : pl.P > kMaxChunks ? 2 : 1; }
 tdsez_status pack_bands(BatchData* b);
 // probe: launch the autotuner's separately named copy of the kernel
 tdsez_status launch_propagate(BatchData* b, double* psi, const double* E, double* obs,

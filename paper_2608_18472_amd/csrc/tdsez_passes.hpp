@@ -20,7 +20,10 @@ struct RedLayout {
     __host__ __device__ static long long mblk(int p, int P) { return dinv(p, P) + (long long)P * p * p; }
     __host__ __device__ static long long zvec(int p, int P) { return mblk(p, P) + (long long)P * p * p; }
     __host__ __device__ static long long xvec(int p, int P) { return zvec(p, P) + (long long)P * p; }
-    __host__ __device__ static long long total(int p, int P) { return xvec(p, P) + (long long)P * p; }
+    // third block factor per separator, used by the cyclic reduction of
+    // four-wave systems (the Dinv and M slots hold the other two)
+    __host__ __device__ static long long vblk(int p, int P) { return xvec(p, P) + (long long)P * p; }
+    __host__ __device__ static long long total(int p, int P) { return vblk(p, P) + (long long)P * p * p; }
 };
 
 // Factor rows: pivot j of chunk k stores, at fb = j * IT * P + item * P + k
@@ -1058,6 +1061,326 @@ __device__ __forceinline__ void pass_reduced_w(const SysDesc& sd, int tid, FT* _
     const cplx<FT> xhc = shfl_c(xh, 8 * j);
     if (wv == 0) backsub(h - 1, h, -1, xhc);
     else if (P - h - 1 > 0) backsub(h + 1, P - h - 1, 1, xhc);
+}
+
+// Entry-parallel block operations for the cyclic reduction below (lane
+// 8i + j holds entry (i, j); the same layout as pass R above), on K
+// independent blocks at once.  The operands are staged in a per-wave LDS
+// area (rows padded to 9 entries, so the eight rows of a column read sit in
+// different banks) and every lane reads the row and column entries it needs
+// directly: a product costs one write per operand and 2p reads, of which the
+// row reads are broadcasts within a row group, against 2p wave shuffles
+// (each a full crossbar pass) in the shuffle form.  The item loops run
+// innermost, so the K blocks' LDS traffic and arithmetic interleave.
+template <typename FT, int K>
+struct BlkStage {
+    FT* base;  // this wave's area: slots x K blocks of 8 x 9 complex
+    int i, j;
+    __device__ __forceinline__ unsigned at(int slot, int c, int r, int col) const {
+        return (unsigned)(((slot * K + c) * 8 + r) * 9 + col);
+    }
+    __device__ __forceinline__ void put(int slot, int c, cplx<FT> v) const { st_c(base, at(slot, c, i, j), v); }
+    __device__ __forceinline__ cplx<FT> get(int slot, int c, int r, int col) const {
+        return ld_c(base, at(slot, c, r, col));
+    }
+};
+// orders one wave's LDS accesses (written entries become visible to the
+// wave's other lanes; later writes wait for earlier reads)
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+// out = C D for the staged slots sc (C) and sd (D)
+template <int p, typename FT, int K>
+__device__ __forceinline__ void stage_prod(const BlkStage<FT, K>& S, int sc, int sd, cplx<FT> (&out)[K]) {
+#pragma unroll
+    for (int c = 0; c < K; ++c) out[c] = cmk<FT>(0, 0);
+#pragma unroll
+    for (int l = 0; l < p; ++l) {
+#pragma unroll
+        for (int c = 0; c < K; ++c) out[c] = cfma(out[c], S.get(sc, c, S.i, l), S.get(sd, c, l, S.j));
+    }
+}
+// Gauss-Jordan inverses of identity-padded blocks through LDS slot `slot`,
+// no pivoting (every block is a Schur complement of A_n, whose Hermitian
+// part is definite)
+template <int p, typename FT, int K>
+__device__ __forceinline__ void stage_inverse(const BlkStage<FT, K>& S, int slot, cplx<FT> (&a)[K]) {
+    const int i = S.i, j = S.j;
+#pragma unroll
+    for (int q = 0; q < p; ++q) {
+#pragma unroll
+        for (int c = 0; c < K; ++c) S.put(slot, c, a[c]);
+        wave_lds_sync();
+        cplx<FT> aiq[K], aqj[K], piv[K];
+#pragma unroll
+        for (int c = 0; c < K; ++c) {
+            aiq[c] = S.get(slot, c, i, q);
+            aqj[c] = S.get(slot, c, q, j);
+            piv[c] = cinv_dev(S.get(slot, c, q, q));
+        }
+        wave_lds_sync();
+#pragma unroll
+        for (int c = 0; c < K; ++c) {
+            const cplx<FT> t = cmul(aiq[c], piv[c]);
+            const cplx<FT> rowq = csel(j == q, piv[c], cmul(aqj[c], piv[c]));
+            const cplx<FT> other = csel(j == q, cmk<FT>(-t.re, -t.im), cfms(a[c], t, aqj[c]));
+            a[c] = csel(i == q, rowq, other);
+        }
+    }
+}
+// LDS of the four-wave reduction: the g vectors (P * p complex) and five
+// staging slots of K blocks per wave
+template <typename FT>
+struct CrLds {
+    static constexpr int kK = sizeof(FT) == 4 ? 4 : 2;
+    static constexpr int kSlots = 5;
+    static constexpr int kG = 2 * kMaxP * kWave * 4;               // FT elements of g
+    static constexpr int kWaveStage = 2 * kSlots * kK * 8 * 9;      // FT elements per wave
+    static constexpr int kTotal = kG + 4 * kWaveStage;
+};
+
+// Pass R on four waves (systems with more than 128 chunks): block cyclic
+// reduction of the separator system, so that the solve is log2(P) levels
+// deep and every level's block operations are shared by the four waves.
+// Level l works on the active blocks a_0 < ... < a_n, n = ceil(P / 2^l) - 1,
+// a_q = (q + 1) 2^l - 1 for q < n and a_n = P - 1 (the last block stays to
+// the end).  The blocks at even positions q < n are eliminated; with Sigma_e
+// the current diagonal block, C_e its coupling to the active block on its
+// left (T[e][left]) and C_r that of the active block r on its right
+// (T[r][e]):
+//   D_e = Sigma_e^-1,  U_e = D_e C_e,  V_e = D_e C_r^T,  h_e = D_e g_e.
+// Every kept block r, with eliminated neighbours e (left) and e' (right)
+// where they exist:
+//   Sigma_r -= C_r V_e + C_e'^T U_e',   g_r -= V_e^T g_e + U_e'^T g_e',
+//   C_r <- -C_r U_e   (its coupling to the next active block on the left).
+// The blocks stay complex symmetric (D_e^T = D_e), which gives the
+// transposes above.  At the top x_{P-1} = Sigma_{P-1}^-1 g_{P-1}; then, from
+// the top level down, x_e = h_e - U_e x_left - V_e x_right.  Level 0 reads
+// Sigma_s = W_s + TL_{s+1} and g_s = yR_s + gT_{s+1} from the chunk blocks;
+// the updated Sigma and C overwrite the W and F slots, g lives in LDS (gl:
+// P * p complex) and h, then x, in the x slots.  D, U and V are stored (Dinv,
+// M and V slots), so a solve with the same matrix (factor == false) repeats
+// only the g updates and the back substitution.  Each wave takes K items of
+// a phase at a time (absent neighbours enter as zero blocks, so there are
+// no per-item branches).  Two barriers per level on the way up, one on the
+// way down; every wave reaches all of them.
+template <int PP, typename FT, int NW>
+__device__ __forceinline__ void pass_reduced_cr(const SysDesc& sd, int tid, FT* __restrict__ red, bool factor,
+                                                FT* __restrict__ lds) {
+    static_assert(NW == 4, "the LDS layout holds four waves");
+    constexpr int p = PP;
+    constexpr int K = CrLds<FT>::kK;
+    FT* gl = lds;
+    const int P = sd.P;
+    const int wv = tid >> 6, lane = tid & 63;
+    const long long cb = RedLayout<FT>::chunk_block(p);
+    FT* rbase = red + 2 * sd.red_off;
+    FT* d_base = rbase + 2 * RedLayout<FT>::dinv(p, P);
+    FT* u_base = rbase + 2 * RedLayout<FT>::mblk(p, P);
+    FT* v_base = rbase + 2 * RedLayout<FT>::vblk(p, P);
+    FT* x_base = rbase + 2 * RedLayout<FT>::xvec(p, P);
+    const int i = lane >> 3, j = lane & 7;
+    const bool valid = (i < p) && (j < p);
+    constexpr unsigned pp = (unsigned)(p * p);
+    const unsigned ii = (unsigned)(i < p ? i : 0);
+    const unsigned ee = valid ? (unsigned)(i * p + j) : 0u;
+    const unsigned et = valid ? (unsigned)(j * p + i) : 0u;
+    const cplx<FT> zero = cmk<FT>(0, 0);
+    const cplx<FT> ident = cmk<FT>(i == j ? (FT)1 : (FT)0, 0);
+    const BlkStage<FT, K> S{lds + CrLds<FT>::kG + wv * CrLds<FT>::kWaveStage, i, j};
+    auto blk = [&](int s) { return rbase + 2 * ((long long)s * cb); };
+    // entry e of stored block s of a factor array, zero where `on` is false
+    auto ld_f = [&](const FT* base, int s, unsigned e, bool on) {
+        return csel(valid && on, ld_c(base, (unsigned)s * pp + e), zero);
+    };
+    auto st_blk = [&](FT* base, int s, cplx<FT> v) {
+        if (valid) st_c(base, (unsigned)s * pp + ee, v);
+    };
+    auto load_sig = [&](int s, int l) {
+        cplx<FT> a = ld_c(blk(s), ee);
+        if (l == 0 && s + 1 < P) a = cadd(a, ld_c(blk(s + 1), 2 * pp + ee));
+        return csel(valid, a, ident);
+    };
+    // g_s in row layout (lane (i, j) holds g_s[i]), zero where `on` is false
+    auto load_g = [&](int s, int l, bool on) {
+        cplx<FT> g;
+        if (l == 0) {
+            g = ld_c(blk(s), 3 * pp + ii);
+            if (s + 1 < P) g = cadd(g, ld_c(blk(s + 1), 3 * pp + (unsigned)p + ii));
+        } else {
+            g = ld_c(gl, (unsigned)(s * p) + ii);
+        }
+        return csel(i < p && on, g, zero);
+    };
+    // row layout -> column layout (lane (i, j) gets v[j])
+    auto colv = [&](cplx<FT> v) { return shfl_c(v, 8 * j); };
+    auto ld_x = [&](int s, bool on) { return csel(i < p && on, ld_c(x_base, (unsigned)(s * p) + ii), zero); };
+    auto st_vec = [&](FT* base, int s, cplx<FT> v) {
+        if (j == 0 && i < p) st_c(base, (unsigned)(s * p + i), v);
+    };
+
+    int nlev = 0;
+    while ((1 << nlev) < P) ++nlev;
+    for (int l = 0; l < nlev; ++l) {
+        const int st = 1 << l;
+        const int n = (P + st - 1) / st - 1;
+        // eliminations: positions q = 0, 2, .. < n
+        const int ne = (n + 1) / 2;
+        for (int t0 = wv; t0 < ne; t0 += NW * K) {
+            int e[K];
+            bool ok[K];
+            cplx<FT> a[K], g[K], ce[K], crt[K], h[K];
+#pragma unroll
+            for (int c = 0; c < K; ++c) {
+                const int t = t0 + NW * c;
+                ok[c] = t < ne;
+                const int q = 2 * (ok[c] ? t : t0);
+                e[c] = (q + 1) * st - 1;
+                const int r = q + 1 < n ? e[c] + st : P - 1;
+                a[c] = factor ? load_sig(e[c], l) : csel(valid, ld_c(d_base, (unsigned)e[c] * pp + ee), ident);
+                g[c] = load_g(e[c], l, true);
+                if (factor) {
+                    ce[c] = csel(valid && q > 0, ld_c(blk(e[c]), pp + ee), zero);
+                    crt[c] = csel(valid, ld_c(blk(r), pp + et), zero);
+                }
+            }
+            if (factor) stage_inverse<p, FT, K>(S, 0, a);
+#pragma unroll
+            for (int c = 0; c < K; ++c) h[c] = row_sum(cmul(a[c], colv(g[c])));
+            if (factor) {
+                cplx<FT> u[K], v[K];
+#pragma unroll
+                for (int c = 0; c < K; ++c) {
+                    S.put(0, c, a[c]);
+                    S.put(1, c, ce[c]);
+                    S.put(2, c, crt[c]);
+                }
+                wave_lds_sync();
+                stage_prod<p, FT, K>(S, 0, 1, u);
+                stage_prod<p, FT, K>(S, 0, 2, v);
+                wave_lds_sync();
+#pragma unroll
+                for (int c = 0; c < K; ++c) {
+                    if (ok[c]) {
+                        st_blk(d_base, e[c], a[c]);
+                        st_blk(u_base, e[c], u[c]);
+                        st_blk(v_base, e[c], v[c]);
+                    }
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < K; ++c)
+                if (ok[c]) st_vec(x_base, e[c], h[c]);
+        }
+        __syncthreads();
+        // kept blocks: odd positions, and the last one (P - 1)
+        const int nk = n / 2 + 1;
+        for (int t0 = wv; t0 < nk; t0 += NW * K) {
+            int r[K];
+            bool ok[K], hl[K];
+            cplx<FT> g[K], ge[K], ge2[K], vte[K], ute2[K];
+            cplx<FT> sg[K], cr[K], ve[K], ue[K], c2t[K], ue2[K];
+#pragma unroll
+            for (int c = 0; c < K; ++c) {
+                const int t = t0 + NW * c;
+                ok[c] = t < nk;
+                const int tt = ok[c] ? t : t0;
+                const int q = 2 * tt + 1 < n ? 2 * tt + 1 : n;
+                r[c] = q < n ? (q + 1) * st - 1 : P - 1;
+                hl[c] = (q & 1) != 0;                    // eliminated left neighbour
+                const bool hr = hl[c] && q + 1 < n;      // eliminated right neighbour
+                const int e = q * st - 1;
+                const int e2 = hr ? (q + 2) * st - 1 : e;
+                g[c] = load_g(r[c], l, true);
+                ge[c] = load_g(e, l, hl[c]);
+                ge2[c] = load_g(e2, l, hr);
+                vte[c] = ld_f(v_base, e, et, hl[c]);
+                ute2[c] = ld_f(u_base, e2, et, hr);
+                if (factor) {
+                    sg[c] = load_sig(r[c], l);
+                    cr[c] = csel(valid && hl[c], ld_c(blk(r[c]), pp + ee), zero);
+                    ve[c] = ld_f(v_base, e, ee, hl[c]);
+                    ue[c] = ld_f(u_base, e, ee, hl[c]);
+                    c2t[c] = csel(valid && hr, ld_c(blk(e2), pp + et), zero);
+                    ue2[c] = ld_f(u_base, e2, ee, hr);
+                }
+            }
+            if (factor) {
+                cplx<FT> p1[K], p2[K], p3[K];
+#pragma unroll
+                for (int c = 0; c < K; ++c) {
+                    S.put(0, c, cr[c]);
+                    S.put(1, c, ve[c]);
+                    S.put(2, c, ue[c]);
+                    S.put(3, c, c2t[c]);
+                    S.put(4, c, ue2[c]);
+                }
+                wave_lds_sync();
+                stage_prod<p, FT, K>(S, 0, 1, p1);
+                stage_prod<p, FT, K>(S, 0, 2, p2);
+                stage_prod<p, FT, K>(S, 3, 4, p3);
+                wave_lds_sync();
+#pragma unroll
+                for (int c = 0; c < K; ++c) {
+                    if (ok[c]) {
+                        if (valid) st_c(blk(r[c]), ee, csub(csub(sg[c], p1[c]), p3[c]));
+                        if (valid && hl[c]) st_c(blk(r[c]), pp + ee, cmk<FT>(-p2[c].re, -p2[c].im));
+                    }
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < K; ++c) {
+                const cplx<FT> gn = csub(csub(g[c], row_sum(cmul(vte[c], colv(ge[c])))),
+                                         row_sum(cmul(ute2[c], colv(ge2[c]))));
+                if (ok[c]) st_vec(gl, r[c], gn);
+            }
+        }
+        __syncthreads();
+    }
+    if (wv == 0) {
+        cplx<FT> d[K];
+        d[0] = factor ? load_sig(P - 1, nlev) : csel(valid, ld_c(d_base, (unsigned)(P - 1) * pp + ee), ident);
+#pragma unroll
+        for (int c = 1; c < K; ++c) d[c] = ident;
+        if (factor) {
+            stage_inverse<p, FT, K>(S, 0, d);
+            st_blk(d_base, P - 1, d[0]);
+        }
+        st_vec(x_base, P - 1, row_sum(cmul(d[0], colv(load_g(P - 1, nlev, true)))));
+    }
+    __syncthreads();
+    for (int l = nlev - 1; l >= 0; --l) {
+        const int st = 1 << l;
+        const int n = (P + st - 1) / st - 1;
+        const int ne = (n + 1) / 2;
+        for (int t0 = wv; t0 < ne; t0 += NW * K) {
+            int e[K];
+            bool ok[K];
+            cplx<FT> xe[K], xr[K], xl[K], u[K], v[K];
+#pragma unroll
+            for (int c = 0; c < K; ++c) {
+                const int t = t0 + NW * c;
+                ok[c] = t < ne;
+                const int q = 2 * (ok[c] ? t : t0);
+                e[c] = (q + 1) * st - 1;
+                const int r = q + 1 < n ? e[c] + st : P - 1;
+                const int lft = q > 0 ? e[c] - st : e[c];
+                xe[c] = ld_x(e[c], true);
+                xr[c] = ld_x(r, true);
+                xl[c] = ld_x(lft, q > 0);
+                u[c] = ld_f(u_base, e[c], ee, q > 0);
+                v[c] = ld_f(v_base, e[c], ee, true);
+            }
+#pragma unroll
+            for (int c = 0; c < K; ++c) {
+                const cplx<FT> x = csub(csub(xe[c], row_sum(cmul(v[c], colv(xr[c])))), row_sum(cmul(u[c], colv(xl[c]))));
+                if (ok[c]) st_vec(x_base, e[c], x);
+            }
+        }
+        __syncthreads();
+    }
 }
 
 template <int PP, typename FT>

@@ -1,8 +1,9 @@
 // Crank-Nicolson propagation kernels (the paper's section V.B, eq. cn_system).
 //
-// One workgroup per system (one wave64, or two for systems partitioned into
-// more than 64 chunks); every system of a batch runs all its time steps
-// inside one persistent launch (one launch per workgroup size).  Per step n, with
+// One workgroup per system (one wave64, or two or four for systems
+// partitioned into more than 64 or 128 chunks); every system of a batch runs
+// all its time steps inside one persistent launch (one launch per workgroup
+// size).  Per step n, with
 // H_n = H0 + Ebar_n D, Ebar_n = (E_n + E_{n+1})/2, A_n = S + i(dt/2) H_n:
 //
 //   A_n (c_{n+1} - c_n) = -i dt H_n c_n                               (1)
@@ -24,7 +25,8 @@
 //     definite), carrying the coupling to the left separator as fill,
 //   - leaves the 2p x 2p Schur complement on its two separators.
 // The separators form a block tridiagonal system (p x p blocks) that the
-// whole wave solves by block LDL^T with entry-parallel block operations.
+// workgroup solves with entry-parallel block operations: by block LDL^T
+// (one wave, or from both ends on two) or by block cyclic reduction (four).
 // Two more lane-serial sweeps (forward correction for the separator values,
 // then back substitution) recover the interior increments.
 //
@@ -172,6 +174,20 @@ Plan make_plan(int N, int p, int force_chunks, int max_chunks, double rule) {
     return pl;
 }
 
+Plan multi_wave_plan(int N, int p, int force_chunks, int max_waves) {
+    const int cap = max_waves >= 4 ? kMaxChunks4 : max_waves == 2 ? kMaxChunks2 : kMaxChunks;
+    if (force_chunks > 0) return make_plan(N, p, force_chunks, cap);
+    if (max_waves >= 4) {
+        Plan p4 = make_plan(N, p, 0, kMaxChunks4, kRule4);
+        if (p4.P > kMaxChunks2) return p4;
+    }
+    if (max_waves >= 2) {
+        Plan p2 = make_plan(N, p, 0, kMaxChunks2, kRule2);
+        if (p2.P > kMaxChunks) return p2;
+    }
+    return make_plan(N, p, 0);
+}
+
 tdsez_status pack_bands(BatchData* b) {
     const int nsys = (int)b->sys.size();
     b->plan.resize(nsys);
@@ -179,22 +195,22 @@ tdsez_status pack_bands(BatchData* b) {
     long long boff = 0, soff = 0, foff = 0, roff = 0, poff = 0;
     b->maxp = 0;
     b->any_cap = b->any_aq = false;
-    b->two_wave.assign(nsys, 0);
+    b->waves.assign(nsys, 1);
     b->nsplit = 0;
+    b->n4 = 0;
     for (int s = 0; s < nsys; ++s) {
         SystemData* sy = b->sys[s];
         const int tuned = s < (int)b->tuned_chunks.size() ? b->tuned_chunks[s] : 0;
         const bool req = s < (int)b->two_wave_req.size() && b->two_wave_req[s];
         const int force = b->force_chunks > 0 ? b->force_chunks : tuned;
-        Plan pl = make_plan(sy->N, sy->p, force, req ? kMaxChunks2 : kMaxChunks, req ? 0.3 : 0.6);
-        // a marked system whose two-wave rule gives at most 64 chunks stays
-        // on one wave, with the one-wave rule
-        if (req && force == 0 && pl.P <= kMaxChunks) pl = make_plan(sy->N, sy->p, 0);
+        // a marked system runs on the most waves whose rule needs them (a
+        // system whose two-wave rule gives at most 64 chunks stays on one
+        // wave, with the one-wave rule); an unmarked one on one wave
+        const Plan pl = multi_wave_plan(sy->N, sy->p, force, req ? b->max_waves : 1);
         b->plan[s] = pl;
-        if (pl.P > kMaxChunks) {
-            b->two_wave[s] = 1;
-            ++b->nsplit;
-        }
+        b->waves[s] = (char)plan_waves(pl);
+        if (b->waves[s] > 1) ++b->nsplit;
+        if (b->waves[s] == 4) ++b->n4;
         SysDesc& d = b->desc[s];
         d = SysDesc{};
         d.N = pl.N; d.p = pl.p; d.P = pl.P; d.L = pl.L; d.m = pl.m; d.LS = pl.LS;
@@ -241,6 +257,10 @@ tdsez_status pack_bands(BatchData* b) {
         TDSEZ_HIP_TRY(hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming));
         TDSEZ_HIP_TRY(hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming));
     }
+    if (b->n4 > 0 && b->nsplit > b->n4 && !b->side2) {
+        TDSEZ_HIP_TRY(hipStreamCreateWithFlags(&b->side2, hipStreamNonBlocking));
+        TDSEZ_HIP_TRY(hipEventCreateWithFlags(&b->ev_join2, hipEventDisableTiming));
+    }
     for (int s = 0; s < nsys; ++s) {
         SystemData* sy = b->sys[s];
         const Plan& pl = b->plan[s];
@@ -279,17 +299,17 @@ tdsez_status upload_descriptors(BatchData* b, hipStream_t stream) {
     // Workgroups are dispatched in index order, so when the batch holds more
     // systems than the device has wave slots the costliest ones (cost
     // N (p + 1) nsteps) start first and the short ones fill in behind them.
-    // Two-wave systems come first (their own launch reads entries
-    // 0..nsplit-1), each group longest first.
+    // Four-wave systems come first, then two-wave systems (each launch reads
+    // its own range of entries), each group longest first.
     b->order_host.resize(n);
     for (size_t s = 0; s < n; ++s) b->order_host[s] = (int)s;
     auto cost = [&](int s) {
         const SysDesc& d = b->desc[s];
         return (double)d.N * (d.p + 1) * (double)d.nsteps;
     };
-    auto two = [&](int s) { return s < (int)b->two_wave.size() && b->two_wave[s]; };
+    auto waves = [&](int s) { return s < (int)b->waves.size() ? (int)b->waves[s] : 1; };
     std::stable_sort(b->order_host.begin(), b->order_host.end(), [&](int x, int y) {
-        if (two(x) != two(y)) return two(x);
+        if (waves(x) != waves(y)) return waves(x) > waves(y);
         return cost(x) > cost(y);
     });
     TDSEZ_HIP_TRY(hipMemcpyAsync(b->d_desc, b->desc.data(), sizeof(SysDesc) * n, hipMemcpyHostToDevice, stream));
@@ -341,24 +361,38 @@ tdsez_status launch_propagate(BatchData* b, double* psi, const double* E, double
     const bool fp64 = prec == TDSEZ_FP64;
     ka.band = fp64 ? (const void*)b->d_band64 : (const void*)b->d_band32;
     ka.refine = fp64 ? 0 : b->refine;
-    // Two-wave systems (the costliest of the batch) are launched first, on
-    // the caller's stream; the one-wave systems run concurrently on a side
-    // stream forked from and joined back into the caller's stream (both
-    // streams at the default priority).
-    const int n2 = b->nsplit, n1 = nsys - b->nsplit;
-    hipStream_t s1 = stream;
-    if (n2 > 0 && n1 > 0) {
-        TDSEZ_HIP_TRY(hipEventRecord(b->ev_fork, stream));
-        TDSEZ_HIP_TRY(hipStreamWaitEvent(b->side, b->ev_fork, 0));
-        s1 = b->side;
+    // Multi-wave systems (the costliest of the batch) are launched first,
+    // the first group on the caller's stream; the other groups run
+    // concurrently on side streams forked from and joined back into the
+    // caller's stream (all streams at the default priority).
+    const int n4 = b->n4, n2 = b->nsplit - b->n4, n1 = nsys - b->nsplit;
+    hipStream_t grp[3] = {stream, stream, stream};  // streams of the 4-, 2- and 1-wave launches
+    hipStream_t sides[2] = {b->side, b->side2};
+    hipEvent_t joins[2] = {b->ev_join, b->ev_join2};
+    int nside = 0;
+    {
+        const int cnt[3] = {n4, n2, n1};
+        bool first = true;
+        for (int g = 0; g < 3; ++g) {
+            if (cnt[g] == 0) continue;
+            if (first) {
+                first = false;
+                continue;
+            }
+            if (nside == 0) TDSEZ_HIP_TRY(hipEventRecord(b->ev_fork, stream));
+            TDSEZ_HIP_TRY(hipStreamWaitEvent(sides[nside], b->ev_fork, 0));
+            grp[g] = sides[nside++];
+        }
     }
     hipError_t le;
-    if (xt) le = fp64 ? launch_prop_xt64(ka, n2, n1, stream, s1) : launch_prop_xt32(ka, n2, n1, stream, s1);
-    else le = fp64 ? launch_prop_f64(ka, n2, n1, stream, s1, probe) : launch_prop_f32(ka, n2, n1, stream, s1, probe);
+    if (xt) le = fp64 ? launch_prop_xt64(ka, n4, n2, n1, grp[0], grp[1], grp[2])
+                      : launch_prop_xt32(ka, n4, n2, n1, grp[0], grp[1], grp[2]);
+    else le = fp64 ? launch_prop_f64(ka, n4, n2, n1, grp[0], grp[1], grp[2], probe)
+                   : launch_prop_f32(ka, n4, n2, n1, grp[0], grp[1], grp[2], probe);
     TDSEZ_HIP_TRY(le);
-    if (n2 > 0 && n1 > 0) {
-        TDSEZ_HIP_TRY(hipEventRecord(b->ev_join, b->side));
-        TDSEZ_HIP_TRY(hipStreamWaitEvent(stream, b->ev_join, 0));
+    for (int k = 0; k < nside; ++k) {
+        TDSEZ_HIP_TRY(hipEventRecord(joins[k], sides[k]));
+        TDSEZ_HIP_TRY(hipStreamWaitEvent(stream, joins[k], 0));
     }
     {
         dim3 grid((unsigned)std::min<long long>((maxN + 255) / 256, 1024), nsys);
@@ -415,10 +449,9 @@ extern "C" tdsez_status tdsez_propagate_noalloc(tdsez_system sys_h, double* psi,
     if (sy->d_W || sy->d_Q) return fail(TDSEZ_EUNSUPPORTED, "no-alloc propagation: no absorber or a_Q form");
     if ((obs & TDSEZ_OBS_ACCEL) && !sy->const_mass)
         return fail(TDSEZ_EUNSUPPORTED, "position-dependent mass: the acceleration needs the a_Q form");
-    // the plan of tdsez_propagate: two waves when that plan has more than 64 chunks
-    Plan pl = make_plan(sy->N, sy->p, 0, kMaxChunks2, 0.3);
-    if (pl.P <= kMaxChunks) pl = make_plan(sy->N, sy->p, 0);
-    const bool two = pl.P > kMaxChunks;
+    // the plan of tdsez_propagate (up to four waves)
+    const Plan pl = multi_wave_plan(sy->N, sy->p, 0, 4);
+    const int nw = plan_waves(pl);
     // scratch layout
     const long long nband = (long long)pl.L * kNumMats * (pl.p + 1) * pl.LS;
     const long long nstate = (long long)pl.L * pl.LS;
@@ -506,9 +539,9 @@ extern "C" tdsez_status tdsez_propagate_noalloc(tdsez_system sys_h, double* psi,
     const bool fp64 = prec == TDSEZ_FP64;
     ka.band = fp64 ? (const void*)b64 : (const void*)b32;
     ka.refine = fp64 ? 0 : 1;
-    const int n2 = two ? 1 : 0, n1 = two ? 0 : 1;
-    TDSEZ_HIP_TRY(fp64 ? launch_prop_f64(ka, n2, n1, stream, stream, false)
-                       : launch_prop_f32(ka, n2, n1, stream, stream, false));
+    const int n4 = nw == 4 ? 1 : 0, n2 = nw == 2 ? 1 : 0, n1 = nw == 1 ? 1 : 0;
+    TDSEZ_HIP_TRY(fp64 ? launch_prop_f64(ka, n4, n2, n1, stream, stream, stream, false)
+                       : launch_prop_f32(ka, n4, n2, n1, stream, stream, stream, false));
     {
         dim3 grid((unsigned)std::min<long long>(((long long)pl.N + 255) / 256, 1024), 1);
         unpack_state_kernel<<<grid, 256, 0, stream>>>(ddesc, st, psi);

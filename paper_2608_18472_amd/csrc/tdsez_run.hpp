@@ -10,25 +10,38 @@
 namespace tdsez {
 namespace {
 
-// Combine wave-uniform partial sums of the two waves of a workgroup through
-// LDS.  Both waves add the two halves in the same order, so they take the
-// same decisions afterwards.  A no-op for one wave.
+// Combine wave-uniform partial sums of the waves of a workgroup through
+// LDS.  Every wave adds the parts in wave order, so all waves take the same
+// decisions afterwards.  A no-op for one wave.
 template <int NW, int CAP>
 __device__ __forceinline__ void combine_waves(double (&v)[CAP], int cnt, int tid) {
-    if constexpr (NW == 2) {
-        __shared__ double buf[2][CAP];
+    if constexpr (NW > 1) {
+        __shared__ double buf[NW][CAP];
         if ((tid & (kWave - 1)) == 0)
             for (int i = 0; i < cnt; ++i) buf[tid / kWave][i] = v[i];
         __syncthreads();
-        for (int i = 0; i < cnt; ++i) v[i] = buf[0][i] + buf[1][i];
+        for (int i = 0; i < cnt; ++i) {
+            double a = buf[0][i];
+            for (int w = 1; w < NW; ++w) a += buf[w][i];
+            v[i] = a;
+        }
         __syncthreads();  // the slots are free again
     }
+}
+
+template <int PP, typename FT, int NW>
+__device__ __forceinline__ void reduced_solve(const SysDesc& sd, int tid, FT* red, bool factor, FT* zl) {
+    if constexpr (NW == 4) pass_reduced_cr<PP, FT, 4>(sd, tid, red, factor, zl);
+    else if constexpr (NW == 2) pass_reduced2<PP, FT>(sd, tid, red, factor, zl);
+    else pass_reduced<PP, FT>(sd, tid, red, factor, zl);
 }
 
 // NW = 1: one wave owns the system (P <= 64).  NW = 2: two waves (P in
 // 65..128); thread t owns chunk t in the lane-serial passes, the separator
 // system is solved from both ends (pass_reduced2) and the observable sums
-// are combined across the waves through LDS.  XT: the extended kernels (an
+// are combined across the waves through LDS.  NW = 4: four waves (P in
+// 129..256), the separator system by block cyclic reduction
+// (pass_reduced_cr).  XT: the extended kernels (an
 // absorbing potential in A_n and B_n, the extended series of section V.D,
 // the a_Q term of the acceleration).
 template <int PP, typename FT, int NW, bool XT>
@@ -144,8 +157,7 @@ __device__ __forceinline__ void run_system(const KernelArgs& ka, const SysDesc& 
         if (last) break;
         __syncthreads();
         mark(2);
-        if constexpr (NW == 2) pass_reduced2<PP, FT>(sd, lane, red, true, zl);
-        else pass_reduced<PP, FT>(sd, lane, red, true, zl);
+        reduced_solve<PP, FT, NW>(sd, lane, red, true, zl);
         __syncthreads();
         mark(3);
         if (active) pass_backsub<PP, FT, XT>(sd, lane, band, st, dtot, true, fac, red, alpha, Ebar);
@@ -169,8 +181,7 @@ __device__ __forceinline__ void run_system(const KernelArgs& ka, const SysDesc& 
                 worst_rel = fmax(worst_rel, rel);
                 if (!(rel <= ka.refine_tol) && lane == 0) latch(ka.status, TDSEZ_ENOCONV, sidx, n);
             }
-            if constexpr (NW == 2) pass_reduced2<PP, FT>(sd, lane, red, false, zl);
-            else pass_reduced<PP, FT>(sd, lane, red, false, zl);
+            reduced_solve<PP, FT, NW>(sd, lane, red, false, zl);
             __syncthreads();
             mark(6);
             if (active)
@@ -192,7 +203,8 @@ __device__ __forceinline__ void run_system(const KernelArgs& ka, const SysDesc& 
 // LDS, one array per kernel (shared by the p variants)
 template <typename FT, int NW, bool XT>
 __device__ __forceinline__ void dispatch_system(const KernelArgs& ka) {
-    __shared__ FT zl[2 * kMaxP * (NW == 2 ? kMaxChunks2 : kMaxChunks)];
+    // (four waves: the cyclic reduction's g vectors and block staging)
+    __shared__ FT zl[NW == 4 ? CrLds<FT>::kTotal : 2 * kMaxP * kWave * NW];
     const int sidx = ka.order[ka.order_off + blockIdx.x];
     const SysDesc sd = ka.descs[sidx];
     switch (sd.p) {
@@ -211,9 +223,19 @@ __device__ __forceinline__ void dispatch_system(const KernelArgs& ka) {
 }  // namespace tdsez
 
 // Kernel names are per translation unit: the plain kernels keep the names
-// propagate_kernel / propagate2_kernel (one and two waves per system) and
-// tune_probe_kernel / tune_probe2_kernel (the autotuner's probes), the
-// extended ones propagate_xt_kernel / propagate2_xt_kernel.
+// propagate_kernel / propagate2_kernel / propagate4_kernel (one, two and four
+// waves per system) and tune_probe*_kernel (the autotuner's probes), the
+// extended ones propagate_xt_kernel / propagate2_xt_kernel /
+// propagate4_xt_kernel.  Launch groups: entries 0..n4-1 of the order on s4,
+// the next n2 on s2, the n1 after them on s1.
+#define TDSEZ_LAUNCH_GROUP(KERNEL, T, NWAVES, COUNT, OFF, STREAM)                                           \
+    if ((COUNT) > 0) {                                                                                     \
+        k.order_off = (OFF);                                                                               \
+        KERNEL<T><<<(COUNT), (NWAVES) * kWave, 0, (STREAM)>>>(k);                                         \
+        hipError_t e = hipGetLastError();                                                                  \
+        if (e != hipSuccess) return e;                                                                     \
+    }
+
 #define TDSEZ_DEFINE_PLAIN_LAUNCHER(FT, NAME)                                                               \
     namespace tdsez {                                                                                      \
     namespace {                                                                                            \
@@ -224,6 +246,10 @@ __device__ __forceinline__ void dispatch_system(const KernelArgs& ka) {
         dispatch_system<T, 2, false>(ka);                                                                  \
     }                                                                                                      \
     template <typename T>                                                                                  \
+    __global__ __launch_bounds__(4 * kWave) void propagate4_kernel(KernelArgs ka) {                        \
+        dispatch_system<T, 4, false>(ka);                                                                  \
+    }                                                                                                      \
+    template <typename T>                                                                                  \
     __global__ __launch_bounds__(kWave) void tune_probe_kernel(KernelArgs ka) {                            \
         dispatch_system<T, 1, false>(ka);                                                                  \
     }                                                                                                      \
@@ -231,21 +257,22 @@ __device__ __forceinline__ void dispatch_system(const KernelArgs& ka) {
     __global__ __launch_bounds__(2 * kWave) void tune_probe2_kernel(KernelArgs ka) {                       \
         dispatch_system<T, 2, false>(ka);                                                                  \
     }                                                                                                      \
+    template <typename T>                                                                                  \
+    __global__ __launch_bounds__(4 * kWave) void tune_probe4_kernel(KernelArgs ka) {                       \
+        dispatch_system<T, 4, false>(ka);                                                                  \
     }                                                                                                      \
-    hipError_t NAME(const KernelArgs& ka, int n2, int n1, hipStream_t s2, hipStream_t s1, bool probe) {    \
+    }                                                                                                      \
+    hipError_t NAME(const KernelArgs& ka, int n4, int n2, int n1, hipStream_t s4, hipStream_t s2,         \
+                    hipStream_t s1, bool probe) {                                                          \
         KernelArgs k = ka;                                                                                 \
-        if (n2 > 0) {                                                                                      \
-            k.order_off = 0;                                                                               \
-            if (probe) tune_probe2_kernel<FT><<<n2, 2 * kWave, 0, s2>>>(k);                                \
-            else propagate2_kernel<FT><<<n2, 2 * kWave, 0, s2>>>(k);                                       \
-            hipError_t e = hipGetLastError();                                                              \
-            if (e != hipSuccess) return e;                                                                 \
-        }                                                                                                  \
-        if (n1 > 0) {                                                                                      \
-            k.order_off = n2;                                                                              \
-            if (probe) tune_probe_kernel<FT><<<n1, kWave, 0, s1>>>(k);                                     \
-            else propagate_kernel<FT><<<n1, kWave, 0, s1>>>(k);                                            \
-            return hipGetLastError();                                                                      \
+        if (probe) {                                                                                       \
+            TDSEZ_LAUNCH_GROUP(tune_probe4_kernel, FT, 4, n4, 0, s4)                                           \
+            TDSEZ_LAUNCH_GROUP(tune_probe2_kernel, FT, 2, n2, n4, s2)                                          \
+            TDSEZ_LAUNCH_GROUP(tune_probe_kernel, FT, 1, n1, n4 + n2, s1)                                      \
+        } else {                                                                                           \
+            TDSEZ_LAUNCH_GROUP(propagate4_kernel, FT, 4, n4, 0, s4)                                            \
+            TDSEZ_LAUNCH_GROUP(propagate2_kernel, FT, 2, n2, n4, s2)                                           \
+            TDSEZ_LAUNCH_GROUP(propagate_kernel, FT, 1, n1, n4 + n2, s1)                                       \
         }                                                                                                  \
         return hipSuccess;                                                                                 \
     }                                                                                                      \
@@ -262,20 +289,17 @@ __device__ __forceinline__ void dispatch_system(const KernelArgs& ka) {
     __global__ __launch_bounds__(2 * kWave) void propagate2_xt_kernel(KernelArgs ka) {                     \
         dispatch_system<T, 2, true>(ka);                                                                   \
     }                                                                                                      \
+    template <typename T>                                                                                  \
+    __global__ __launch_bounds__(4 * kWave) void propagate4_xt_kernel(KernelArgs ka) {                     \
+        dispatch_system<T, 4, true>(ka);                                                                   \
     }                                                                                                      \
-    hipError_t NAME(const KernelArgs& ka, int n2, int n1, hipStream_t s2, hipStream_t s1) {                \
+    }                                                                                                      \
+    hipError_t NAME(const KernelArgs& ka, int n4, int n2, int n1, hipStream_t s4, hipStream_t s2,         \
+                    hipStream_t s1) {                                                                      \
         KernelArgs k = ka;                                                                                 \
-        if (n2 > 0) {                                                                                      \
-            k.order_off = 0;                                                                               \
-            propagate2_xt_kernel<FT><<<n2, 2 * kWave, 0, s2>>>(k);                                         \
-            hipError_t e = hipGetLastError();                                                              \
-            if (e != hipSuccess) return e;                                                                 \
-        }                                                                                                  \
-        if (n1 > 0) {                                                                                      \
-            k.order_off = n2;                                                                              \
-            propagate_xt_kernel<FT><<<n1, kWave, 0, s1>>>(k);                                              \
-            return hipGetLastError();                                                                      \
-        }                                                                                                  \
+        TDSEZ_LAUNCH_GROUP(propagate4_xt_kernel, FT, 4, n4, 0, s4)                                             \
+        TDSEZ_LAUNCH_GROUP(propagate2_xt_kernel, FT, 2, n2, n4, s2)                                            \
+        TDSEZ_LAUNCH_GROUP(propagate_xt_kernel, FT, 1, n1, n4 + n2, s1)                                        \
         return hipSuccess;                                                                                 \
     }                                                                                                      \
     }

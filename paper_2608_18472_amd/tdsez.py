@@ -87,6 +87,7 @@ def lib():
         "tdsez_batch_chunks": [vp, ip],
         "tdsez_batch_split": [vp, ip, ctypes.c_int],
         "tdsez_batch_two_wave": [vp, ip],
+        "tdsez_batch_waves": [vp, ip],
         "tdsez_system_status": [vp, vp, ip],
     }
     for name, args in sigs.items():
@@ -460,8 +461,9 @@ def batch_chunks(batch):
 
 
 def batch_split(batch, nsteps, count):
-    """Run the `count` systems with the largest N (p + 1) nsteps on two waves
-    (nsteps may be None with count = 0)."""
+    """Run the `count` systems with the largest N (p + 1) nsteps on two waves,
+    or four with the batch key max_waves = 4 (nsteps may be None with
+    count = 0)."""
     if nsteps is None:
         _check(lib().tdsez_batch_split(batch.handle, None, int(count)))
         return
@@ -472,9 +474,16 @@ def batch_split(batch, nsteps, count):
 
 
 def batch_two_wave(batch):
-    """1 for every system running on two waves under the current plan."""
+    """1 for every system running on more than one wave under the current plan."""
     out = np.zeros(len(batch.systems), dtype=np.int32)
     _check(lib().tdsez_batch_two_wave(batch.handle, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int))))
+    return out
+
+
+def batch_waves(batch):
+    """Waves (1, 2 or 4) of every system under the current plan."""
+    out = np.zeros(len(batch.systems), dtype=np.int32)
+    _check(lib().tdsez_batch_waves(batch.handle, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int))))
     return out
 
 

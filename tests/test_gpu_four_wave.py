@@ -1,0 +1,205 @@
+"""Four-wave systems (max_waves = 4) on the GPU.
+
+A system marked by tdsez_batch_split in a batch with max_waves = 4 runs on
+four waves when its four-wave plan has more than 128 chunks; its separator
+system is then solved by block cyclic reduction instead of the block LDL^T
+chain.  The propagation must meet the oracle bars of the other plans:
+FP64 1e-10 relative L2 on the state and every observable series,
+FP32-refined 1e-5 on the series, for chunk counts that are odd, prime, a
+power of two and the largest (256), in batches that mix four-, two- and
+one-wave systems (three concurrent launches), in a captured graph, and
+through tdsez_propagate on a lone long system.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2608_18472_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2608_18472_amd import tdsez as T  # noqa: E402
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def _oracle(sd):
+    m = O.assemble(sd.breaks, sd.order, sd.nq, None, sd.V, sd.dV)
+    xq, _ = O.quad_points(sd.breaks, sd.nq)
+    vmin = float(np.min(sd.V(xq)))
+    ev, vec = O.eig_banded(m["H0"], m["S"], 1, vmin - 1e-3 * (abs(vmin) + 1.0))
+    return m, vec[0].astype(np.complex128)
+
+
+def _system(N, order, ns, omega=0.05, amp=0.06, L=300.0):
+    V, dV = W.soft_coulomb(2.0)
+    E = amp * np.sin(omega * 0.05 * np.arange(ns + 1) + 0.4)
+    return W.System("N%d-k%d" % (N, order), W.breaks_uniform(L, N - order + 3), order, lambda x: np.ones_like(x),
+                    V, dV, 10, E, 0.05, ns, True)
+
+
+def _run(b, defs, psi0s, prec):
+    psi, po, E, eo, obs, oo = T.pack_batch_inputs(defs, psi0s)
+    T.propagate_batched(b, psi, po, E, eo, [s.dt for s in defs], [s.nsteps for s in defs], prec, T.OBS_ALL, obs,
+                        oo)
+    T.batch_status(b)
+    return psi.cpu().numpy(), po, obs.cpu().numpy(), eo
+
+
+def _check(defs, refs, res, prec, label):
+    c, po, o, eo = res
+    for i, (r, cr) in enumerate(refs):
+        ns = defs[i].nsteps
+        gi = o[3 * eo[i]: 3 * eo[i] + 3 * (ns + 1)].reshape(-1, 3)
+        errs = [rel(gi[:, k], r[:, k]) for k in range(3)]
+        es = rel(c[po[i]: po[i] + len(cr)], cr)
+        say(label, "system", i, "N", defs[i].ndof, "state", es, "series", errs)
+        if prec == T.FP64:
+            assert es < 1e-10, (label, i, es)
+            assert max(errs) < 1e-10, (label, i, errs)
+        else:
+            assert max(errs) < 1e-5, (label, i, errs)
+
+
+def test_mixed_batch_runs_four_two_and_one_wave_systems():
+    """N = 6000 (four waves), 1800 (two) and 800 (one wave) in one batch: the
+    three launch groups run concurrently and each system matches the oracle
+    in both precisions."""
+    ns = 40
+    defs = [_system(6000, 8, ns), _system(1800, 7, ns, omega=0.08), _system(800, 6, ns, amp=0.03)]
+    b = T.batch_create([T.assemble_workload(s) for s in defs])
+    T.batch_set(b, "max_waves", 4)
+    T.batch_split(b, [ns] * 3, 3)
+    waves = T.batch_waves(b)
+    chunks = T.batch_chunks(b)
+    say("waves", waves.tolist(), "chunks", chunks.tolist())
+    assert waves.tolist() == [4, 2, 1]
+    assert 128 < chunks[0] <= 256 and 64 < chunks[1] <= 128 and chunks[2] <= 64
+    assert T.batch_two_wave(b).tolist() == [1, 1, 0]
+    refs, psi0s = [], []
+    for s in defs:
+        m, p0 = _oracle(s)
+        psi0s.append(p0)
+        refs.append(O.propagate(m, p0, s.E, s.dt, ns))
+    T.batch_set(b, "profile", 1)
+    for prec in (T.FP64, T.FP32_REFINED):
+        res = _run(b, defs, psi0s, prec)
+        _check(defs, refs, res, prec, "mixed %d" % prec)
+    prof = T.batch_profile(b)
+    assert np.array_equal(prof[:, 8].astype(int), chunks)
+    # max_waves = 2 brings the large system back to two waves
+    T.batch_set(b, "max_waves", 2)
+    assert T.batch_waves(b).tolist() == [2, 2, 1]
+
+
+@pytest.mark.parametrize("P", [129, 131, 200, 256])
+def test_forced_chunk_counts_match_oracle(P):
+    """Cyclic reduction over an odd, a prime, an even non-power-of-two and
+    the largest block count (the last block stays to the top level, and
+    blocks with no eliminated neighbour carry over), both precisions."""
+    ns = 30
+    defs = [_system(7000, 8, ns)]
+    b = T.batch_create([T.assemble_workload(s) for s in defs])
+    T.batch_set(b, "max_waves", 4)
+    T.batch_split(b, [ns], 1)
+    T.batch_set(b, "chunks", P)
+    assert T.batch_waves(b).tolist() == [4]
+    assert T.batch_chunks(b).tolist() == [P]
+    m, p0 = _oracle(defs[0])
+    refs = [O.propagate(m, p0, defs[0].E, defs[0].dt, ns)]
+    for prec in (T.FP64, T.FP32_REFINED):
+        _check(defs, refs, _run(b, defs, [p0], prec), prec, "P=%d prec %d" % (P, prec))
+
+
+@pytest.mark.parametrize("prec", [T.FP64, T.FP32_REFINED])
+def test_four_wave_graph_replays_match_eager(prec):
+    ns = 30
+    defs = [_system(6000, 8, ns), _system(1800, 7, ns), _system(800, 6, ns)]
+    b = T.batch_create([T.assemble_workload(s) for s in defs])
+    T.batch_set(b, "max_waves", 4)
+    T.batch_split(b, [ns] * 3, 3)
+    assert T.batch_waves(b).tolist() == [4, 2, 1]
+    psi0, po, E, eo, obs, oo = T.pack_batch_inputs(defs, [np.zeros(s.ndof) for s in defs])
+    T.ground_state_batched(b, psi0, po)
+    dts = [s.dt for s in defs]
+    nss = [ns] * 3
+    psi_ref = psi0.clone()
+    obs_ref = torch.zeros_like(obs)
+    T.propagate_batched(b, psi_ref, po, E, eo, dts, nss, prec, T.OBS_ALL, obs_ref, oo)
+    T.batch_status(b)
+    torch.cuda.synchronize()
+    psi = psi0.clone()
+    ob = torch.zeros_like(obs)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        T.propagate_batched(b, psi, po, E, eo, dts, nss, prec, T.OBS_ALL, ob, oo, side)  # warm-up
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    psi.copy_(psi0)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(graph):
+        T.propagate_batched(b, psi, po, E, eo, dts, nss, prec, T.OBS_ALL, ob, oo, torch.cuda.current_stream())
+    for rep in range(3):
+        psi.copy_(psi0)
+        ob.zero_()
+        scratch = torch.randn(1 << 20, device="cuda", dtype=torch.float64)
+        scratch.mul_(2.0).sum().item()
+        graph.replay()
+        torch.cuda.synchronize()
+        T.batch_status(b)
+        dpsi = float((psi - psi_ref).abs().max())
+        dobs = float((ob - obs_ref).abs().max())
+        say("replay", rep, dpsi, dobs)
+        assert dpsi == 0.0 and dobs == 0.0
+
+
+def test_single_long_system_runs_on_four_waves_and_adjoint_refuses():
+    """tdsez_propagate on N = 9000 (four-wave plan) against the oracle over
+    150 steps in both precisions; a batch holding a four-wave system is
+    refused by the adjoint."""
+    ns = 150
+    sd = _system(9000, 8, ns, L=600.0)
+    g = T.assemble_workload(sd)
+    m, p0 = _oracle(sd)
+    ref, cref = O.propagate(m, p0, sd.E, sd.dt, ns)
+    for prec, tol in ((T.FP64, 1e-10), (T.FP32_REFINED, 1e-5)):
+        psi = torch.from_numpy(p0.copy()).cuda()
+        Et = torch.from_numpy(sd.E.copy()).cuda()
+        o = torch.zeros(3 * (ns + 1), dtype=torch.float64, device="cuda")
+        T.propagate(g, psi, Et, sd.dt, ns, prec, T.OBS_ALL, o)
+        T.system_status(g)
+        got = o.cpu().numpy().reshape(-1, 3)
+        errs = [rel(got[:, k], ref[:, k]) for k in range(3)]
+        say("lone system", sd.ndof, prec, errs)
+        assert max(errs) < tol
+        if prec == T.FP64:
+            assert rel(psi.cpu().numpy(), cref) < 1e-10
+    b = T.batch_create([g])
+    T.batch_set(b, "max_waves", 4)
+    T.batch_split(b, [ns], 1)
+    assert T.batch_waves(b).tolist() == [4]
+    psi, po, E, eo, obs, oo = T.pack_batch_inputs([sd], [p0])
+    dJ = torch.ones_like(obs)
+    dE = torch.zeros_like(E)
+    with pytest.raises(T.TdsezError) as e:
+        T.adjoint_batched(b, psi, po, E, eo, [sd.dt], [ns], T.OBS_DIPOLE, dJ, oo, dE)
+    assert e.value.status == 7
+    with pytest.raises(T.TdsezError) as e:
+        T.batch_set(b, "max_waves", 3)
+    assert e.value.status == 1
