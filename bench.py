@@ -154,6 +154,9 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--tune-ms", type=float, default=3000.0,
                     help="partition autotuner budget per precision (setup, untimed); 0 keeps the default rule")
+    ap.add_argument("--max-waves", type=int, choices=[2, 4], default=2,
+                    help="batch1d: the most waves a --split system may run on (4: cyclic reduction of the "
+                         "separator system for systems whose four-wave plan has more than 128 chunks)")
     ap.add_argument("--split", type=int, default=160,
                     help="run this many of the costliest systems on two waves each (setup, untimed; "
                          "160 of 1024 measured best, 0 = one wave per system)")
@@ -204,6 +207,8 @@ def main():
     dts = [s.dt for s in defs]
     nsteps = [s.nsteps for s in defs]
     dofsteps = float(sum(s.ndof * s.nsteps for s in defs))
+    if args.max_waves != 2:
+        T.batch_set(batch, "max_waves", args.max_waves)
     if args.split > 0:
         T.batch_split(batch, nsteps, args.split)
     torch.cuda.synchronize()
@@ -300,7 +305,8 @@ def main():
             "spectrum_metric": "max over systems and odd harmonics 3..q_cut+6 of |log10 S_fp32 - log10 S_fp64|, "
                                "S = w^4 |FT[d W]|^2, Kaiser window beta 8, q_cut = (Ip + 3.17 Up)/w",
             "refine_sweeps": 1,
-            "two_wave_systems": int(T.batch_two_wave(batch).sum()),
+            "two_wave_systems": int((T.batch_waves(batch) == 2).sum()),
+            "four_wave_systems": int((T.batch_waves(batch) == 4).sum()),
             "autotune": tuned if tuned else None,
             "algorithmic_bytes_per_launch": alg_bytes,
             "setup_s": t_setup,
@@ -543,7 +549,9 @@ def cpu_baseline_3d(nsteps=1):
 def run_h2p(args):
     """One long chain: the 1D H2+ model (N = 30 007, p = 7) over its whole
     6-cycle trapezoidal pulse (13 228 steps), FP32-refined then FP64, through
-    the single-system call (two waves, 128 chunks of 235 rows)."""
+    the single-system call, whose plan spreads the chain over several
+    workgroups (64 chunks of about 20 rows each, one grid-wide exchange of
+    the workgroups' last separator blocks per solve)."""
     import torch
     from paper_2608_18472_amd import tdsez as T
     from paper_2608_18472_amd import workloads as W
@@ -593,6 +601,7 @@ def run_h2p(args):
             "workload": "1D H2+ (R 2, soft-core eps 1.472), 30 007 degree-7 splines on [-4000,4000], mirrored "
                         "hydrogenic knots, 6-cycle trapezoidal pulse w 0.057 E0 0.0534, dt 0.05, whole pulse",
             "levels": [float(ev[0]), float(ev[1])],
+            "workgroups_and_chunks": list(T.system_workgroups(g)),
             "fp64_value": n * ns / out["fp64"]["sec"],
             "fp64_ms_per_step": 1000.0 * out["fp64"]["sec"] / ns,
             "dipole_rel_err_fp32_vs_fp64": float(np.linalg.norm(d32 - d64) / np.linalg.norm(d64)),

@@ -531,6 +531,32 @@ tdsez_status tdsez_batch_status(tdsez_batch b, void* stream, int* sys_out, int* 
 /* Same for the one-system plan of tdsez_propagate. */
 tdsez_status tdsez_system_status(tdsez_system sys, void* stream, int* step_out);
 
+/* Partition of tdsez_propagate's one-system plan for a long chain (the
+ * Crank-Nicolson system of section V.B, eq. cn_system, on one N-row band).
+ * By default a system whose four-wave plan would hold chunks of more than 48
+ * rows (N above about 12 000 at order 8) is spread over G workgroups of four
+ * waves on different compute units, launched cooperatively (all resident
+ * at once): workgroup g owns Pl consecutive chunks (chunks of about 2p + 6
+ * rows), reduces its part of the separator system by block cyclic reduction
+ * down to its last separator block, and after a grid barrier every
+ * workgroup solves the G-block system of those blocks itself; a second
+ * grid barrier follows each back substitution (the next pass reads the
+ * neighbouring workgroups' rows).  Observable sums are formed per
+ * workgroup and added in workgroup order after the launch; a non-finite
+ * series is latched after the launch (the workgroups cannot leave early)
+ * and the refinement residual check of "refine_tol" applies per
+ * workgroup.  Spanning calls run the plain kernels only: the extended
+ * series, an absorber or the a_Q form return EUNSUPPORTED (set
+ * "workgroups" to 1).  Keys: "workgroups" (0: automatic, 1: one workgroup,
+ * 2..64: that many), "chunks_per_workgroup" (0: automatic = 64, else
+ * 2..256).  Drops the one-system plan (rebuilt by the next call).  EINVAL
+ * for an unknown key or a value out of range. */
+tdsez_status tdsez_system_set(tdsez_system sys, const char* key, double value);
+
+/* Workgroups and chunk count of tdsez_propagate's one-system plan (built
+ * here if needed); either pointer may be NULL. */
+tdsez_status tdsez_system_workgroups(tdsez_system sys, int* workgroups, int* chunks);
+
 void tdsez_batch_destroy(tdsez_batch b);
 void tdsez_system_destroy(tdsez_system sys);
 

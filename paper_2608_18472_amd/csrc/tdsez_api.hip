@@ -76,6 +76,12 @@ static void free_batch_device(BatchData* b) {
     b->d_desc = nullptr;
     b->desc_on_device.clear();
     b->d_status = nullptr;
+    (void)hipFree(b->d_xch);
+    (void)hipFree(b->d_gfac);
+    (void)hipFree(b->d_obs_part);
+    b->d_xch = b->d_gfac = nullptr;
+    b->d_obs_part = nullptr;
+    b->obs_part_elems = 0;
 }
 
 }  // namespace tdsez
@@ -347,6 +353,49 @@ tdsez_status tdsez_adjoint_batched(tdsez_batch b, const double* psi0_packed, con
                           (hipStream_t)stream);
 }
 
+// The one-system plan of tdsez_propagate: a lone system has the device to
+// itself, so up to four waves (multi_wave_plan), or several workgroups for a
+// long chain (span_plan).
+static tdsez_status ensure_solo(tdsez_system sys) {
+    if (sys->d.solo) return TDSEZ_OK;
+    tdsez_system one = sys;
+    tdsez_status st = tdsez_batch_create(&one, 1, &sys->d.solo);
+    if (st) return st;
+    sys->d.solo->d.max_waves = 4;
+    sys->d.solo->d.solo = true;
+    int nsteps_one = 1;
+    return tdsez_batch_split(sys->d.solo, &nsteps_one, 1);
+}
+
+tdsez_status tdsez_system_set(tdsez_system sys, const char* key, double value) {
+    if (!sys || !key) return fail(TDSEZ_EINVAL, "NULL argument");
+    if (!std::strcmp(key, "workgroups")) {
+        if (!(value >= 0.0 && value <= kMaxSpan) || value != std::floor(value))
+            return fail(TDSEZ_EINVAL, "workgroups must be an integer in 0..%d", kMaxSpan);
+        sys->d.span_G = (int)value;
+    } else if (!std::strcmp(key, "chunks_per_workgroup")) {
+        if (!(value == 0.0 || (value >= 2.0 && value <= kMaxChunks4)) || value != std::floor(value))
+            return fail(TDSEZ_EINVAL, "chunks_per_workgroup must be 0 or an integer in 2..%d", kMaxChunks4);
+        sys->d.span_Pl = (int)value;
+    } else {
+        return fail(TDSEZ_EINVAL, "unknown key '%s'", key);
+    }
+    if (sys->d.solo) {
+        tdsez_batch_destroy(sys->d.solo);
+        sys->d.solo = nullptr;
+    }
+    return TDSEZ_OK;
+}
+
+tdsez_status tdsez_system_workgroups(tdsez_system sys, int* workgroups, int* chunks) {
+    if (!sys) return fail(TDSEZ_EINVAL, "sys is NULL");
+    if (tdsez_status st = ensure_solo(sys)) return st;
+    const BatchData& d = sys->d.solo->d;
+    if (workgroups) *workgroups = d.span_G > 1 ? d.span_G : 1;
+    if (chunks) *chunks = d.plan.empty() ? 0 : d.plan[0].P;
+    return TDSEZ_OK;
+}
+
 tdsez_status tdsez_propagate(tdsez_system sys, double* psi, const double* E, double dt, int nsteps,
                              tdsez_precision prec, unsigned obs, double* obs_out, void* stream) {
     return tdsez_propagate_ext(sys, psi, E, dt, nsteps, prec, obs, obs_out, 0u, nullptr, stream);
@@ -356,16 +405,7 @@ tdsez_status tdsez_propagate_ext(tdsez_system sys, double* psi, const double* E,
                                  tdsez_precision prec, unsigned obs, double* obs_out, unsigned ext,
                                  double* ext_out, void* stream) {
     if (!sys) return fail(TDSEZ_EINVAL, "sys is NULL");
-    if (!sys->d.solo) {
-        tdsez_system one = sys;
-        tdsez_status st = tdsez_batch_create(&one, 1, &sys->d.solo);
-        if (st) return st;
-        // a lone system has the device to itself: up to four waves
-        // (multi_wave_plan)
-        sys->d.solo->d.max_waves = 4;
-        int nsteps_one = 1;
-        if ((st = tdsez_batch_split(sys->d.solo, &nsteps_one, 1)) != TDSEZ_OK) return st;
-    }
+    if (tdsez_status st = ensure_solo(sys)) return st;
     long zero = 0;
     return tdsez_propagate_batched_ext(sys->d.solo, psi, &zero, E, &zero, &dt, &nsteps, prec, obs, obs_out, &zero,
                                        ext, ext_out, &zero, stream);

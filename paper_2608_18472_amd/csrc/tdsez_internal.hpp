@@ -23,6 +23,8 @@ constexpr int kMaxChunks = 64;
 constexpr int kMaxChunks2 = 2 * kWave;
 // Largest partition count of a system run on four waves (max_waves = 4).
 constexpr int kMaxChunks4 = 4 * kWave;
+// Most workgroups one spanning system may use.
+constexpr int kMaxSpan = 64;
 // Chunk-length rules L = sqrt(c N) of one, two and four waves per system.
 constexpr double kRule1 = 0.6, kRule2 = 0.3, kRule4 = 0.15;
 // Matrices stored per band row in the propagation layout, in this order:
@@ -98,6 +100,8 @@ struct SystemData {
     int npop = 0;                    // projection states of the population series
     double* d_pops = nullptr;        // S phi_k, npop x N, natural order
     tdsez_batch solo = nullptr;      // one-system plan for tdsez_propagate
+    int span_G = 0;                  // tdsez_system_set "workgroups" (0: automatic, 1: one workgroup)
+    int span_Pl = 0;                 // tdsez_system_set "chunks_per_workgroup" (0: automatic)
 };
 
 // Per-system plan of the partitioned solve.
@@ -109,6 +113,7 @@ struct Plan {
 // Device descriptor of one system of a batch (read by the propagation kernel).
 struct SysDesc {
     int N, p, P, L, m, LS;
+    int G, Pl;            // workgroups of a spanning system (else 1) and chunks per workgroup
     int nsteps;
     int mi_is_s;          // constant mass: Mi equals S bit for bit (m^-1 = 1 at every point)
     double dt;
@@ -161,6 +166,12 @@ struct BatchData {
     std::vector<char> waves;         // per system: waves of its plan (1; 2: 65..128 chunks; 4: 129..256)
     int nsplit = 0;                  // systems on more than one wave (first nsplit entries of d_order)
     int n4 = 0;                      // of those, systems on four waves (the first n4 entries)
+    bool solo = false;               // the one-system plan of tdsez_propagate (may span workgroups)
+    int span_G = 0;                  // > 1: the single system spans this many workgroups
+    void* d_xch = nullptr;           // spanning launch: exchange buffers, super-block factors, step parts
+    void* d_gfac = nullptr;
+    double* d_obs_part = nullptr;
+    long long obs_part_elems = 0;
     hipStream_t side = nullptr, side2 = nullptr;  // further streams of a split launch (default priority)
     hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_join2 = nullptr;
     int* d_status = nullptr;         // [0] code, [1] system, [2] step
@@ -191,6 +202,10 @@ struct KernelArgs {
     int* status;
     unsigned long long* prof;
     double refine_tol;         // ENOCONV threshold of the last sweep's relative residual
+    // spanning launch only (one system on several workgroups)
+    void* xch;                 // exchanged super-block data, two buffers (FT)
+    void* gfac;                // per workgroup: factors of the super-block system (FT)
+    double* obs_part;          // per step and workgroup: norm, dipole, acceleration parts
     // extended kernels only
     const double* c0;          // initial states (state layout), or nullptr: no autocorrelation
     const double* proj;        // packed projection states S phi_k
@@ -207,6 +222,9 @@ hipError_t launch_prop_f64(const KernelArgs& ka, int n4, int n2, int n1, hipStre
                            hipStream_t s1, bool probe);
 hipError_t launch_prop_f32(const KernelArgs& ka, int n4, int n2, int n1, hipStream_t s4, hipStream_t s2,
                            hipStream_t s1, bool probe);
+// One system on G cooperative workgroups of four waves (sd.G = G).
+hipError_t launch_prop_f64_span(const KernelArgs& ka, int G, hipStream_t s);
+hipError_t launch_prop_f32_span(const KernelArgs& ka, int G, hipStream_t s);
 // Extended kernels: absorbing potential, extended series, a_Q.
 hipError_t launch_prop_xt64(const KernelArgs& ka, int n4, int n2, int n1, hipStream_t s4, hipStream_t s2,
                             hipStream_t s1);
@@ -231,6 +249,10 @@ Plan make_plan(int N, int p, int force_chunks, int max_chunks = kMaxChunks, doub
 // rule of the most waves whose plan needs more chunks than the next fewer
 // waves hold.  force_chunks > 0 overrides the rule (capped by max_waves).
 Plan multi_wave_plan(int N, int p, int force_chunks, int max_waves);
+// Plan of one system spread over G workgroups of Pl chunks each (G Pl
+// chunks in all); G = 0 or Pl = 0 pick them from N and p.  Returns G (1
+// when the system does not need more than one workgroup).
+int span_plan(int N, int p, int G, int Pl, Plan* out);
 // Waves that a plan runs on.
 inline int plan_waves(const Plan& pl) { return pl.P > kMaxChunks2 ? 4 : pl.P > kMaxChunks ? 2 : 1; }
 tdsez_status pack_bands(BatchData* b);

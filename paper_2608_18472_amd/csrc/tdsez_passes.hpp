@@ -4,6 +4,8 @@
 // tdsez_propagate.hip.
 #pragma once
 
+#include <hip/hip_cooperative_groups.h>
+
 #include <cmath>
 
 #include "tdsez_internal.hpp"
@@ -1141,6 +1143,29 @@ struct CrLds {
     static constexpr int kTotal = kG + 4 * kWaveStage;
 };
 
+// One system spread over G workgroups (a lone long chain, see
+// tdsez_propagate): workgroup g owns the blocks k0 .. k0 + Pl - 1 of the
+// separator system, k0 = g Pl.  Its last block ("super" block of g) stays to
+// the top of the local reduction; block k0 - 1, the super block of g - 1,
+// enters as a kept neighbour on the left that is never eliminated (its
+// diagonal and right-hand-side contributions from this workgroup's side
+// accumulate in dS, dg).  The G super blocks then form a block tridiagonal
+// system that every workgroup solves itself (so only one grid barrier is
+// needed), and the local back substitution follows.
+template <typename FT>
+struct SpanCtx {
+    int k0, Pl, g, G;
+    FT* xch;   // this solve's exchange entries (G of XchLayout), or nullptr
+    FT* gfac;  // this workgroup's factors of the super-block system
+};
+// per workgroup: reduced S, C (coupling to the left super block), dS (pp
+// each), g and dg (p each), complex
+__host__ __device__ inline long long xch_entry(int p) { return 3LL * p * p + 2LL * p; }
+// per super block j: Dinv, M, C (pp each) and z (p), complex
+__host__ __device__ inline long long gfac_entry(int p) { return 3LL * p * p + p; }
+
+__device__ __forceinline__ void grid_barrier() { cooperative_groups::this_grid().sync(); }
+
 // Pass R on four waves (systems with more than 128 chunks): block cyclic
 // reduction of the separator system, so that the solve is log2(P) levels
 // deep and every level's block operations are shared by the four waves.
@@ -1165,15 +1190,19 @@ struct CrLds {
 // only the g updates and the back substitution.  Each wave takes K items of
 // a phase at a time (absent neighbours enter as zero blocks, so there are
 // no per-item branches).  Two barriers per level on the way up, one on the
-// way down; every wave reaches all of them.
-template <int PP, typename FT, int NW>
+// way down; every wave reaches all of them.  SPAN: the workgroup's share of
+// a system on several workgroups (SpanCtx); the levels run over its Pl
+// blocks, the left neighbour block k0 - 1 is kept at every level.
+template <int PP, typename FT, int NW, bool SPAN>
 __device__ __forceinline__ void pass_reduced_cr(const SysDesc& sd, int tid, FT* __restrict__ red, bool factor,
-                                                FT* __restrict__ lds) {
+                                                FT* __restrict__ lds, const SpanCtx<FT>& sc) {
     static_assert(NW == 4, "the LDS layout holds four waves");
     constexpr int p = PP;
     constexpr int K = CrLds<FT>::kK;
     FT* gl = lds;
     const int P = sd.P;
+    const int k0 = sc.k0, Pl = sc.Pl;
+    const bool ext = SPAN && sc.g > 0;  // a kept neighbour block on the left (k0 - 1)
     const int wv = tid >> 6, lane = tid & 63;
     const long long cb = RedLayout<FT>::chunk_block(p);
     FT* rbase = red + 2 * sd.red_off;
@@ -1190,17 +1219,20 @@ __device__ __forceinline__ void pass_reduced_cr(const SysDesc& sd, int tid, FT* 
     const cplx<FT> zero = cmk<FT>(0, 0);
     const cplx<FT> ident = cmk<FT>(i == j ? (FT)1 : (FT)0, 0);
     const BlkStage<FT, K> S{lds + CrLds<FT>::kG + wv * CrLds<FT>::kWaveStage, i, j};
-    auto blk = [&](int s) { return rbase + 2 * ((long long)s * cb); };
-    // entry e of stored block s of a factor array, zero where `on` is false
+    // local block s -> its chunk block (global index k0 + s)
+    auto blk = [&](int s) { return rbase + 2 * ((long long)(k0 + s) * cb); };
+    // entry e of stored local block s of a factor array, zero where `on` is false
     auto ld_f = [&](const FT* base, int s, unsigned e, bool on) {
-        return csel(valid && on, ld_c(base, (unsigned)s * pp + e), zero);
+        return csel(valid && on, ld_c(base, (unsigned)(k0 + s) * pp + e), zero);
     };
     auto st_blk = [&](FT* base, int s, cplx<FT> v) {
-        if (valid) st_c(base, (unsigned)s * pp + ee, v);
+        if (valid) st_c(base, (unsigned)(k0 + s) * pp + ee, v);
     };
+    // (a workgroup's last block takes no TL / gT from the next workgroup's
+    // first chunk: that workgroup adds them to its dS, dg)
     auto load_sig = [&](int s, int l) {
         cplx<FT> a = ld_c(blk(s), ee);
-        if (l == 0 && s + 1 < P) a = cadd(a, ld_c(blk(s + 1), 2 * pp + ee));
+        if (l == 0 && s + 1 < Pl) a = cadd(a, ld_c(blk(s + 1), 2 * pp + ee));
         return csel(valid, a, ident);
     };
     // g_s in row layout (lane (i, j) holds g_s[i]), zero where `on` is false
@@ -1208,7 +1240,7 @@ __device__ __forceinline__ void pass_reduced_cr(const SysDesc& sd, int tid, FT* 
         cplx<FT> g;
         if (l == 0) {
             g = ld_c(blk(s), 3 * pp + ii);
-            if (s + 1 < P) g = cadd(g, ld_c(blk(s + 1), 3 * pp + (unsigned)p + ii));
+            if (s + 1 < Pl) g = cadd(g, ld_c(blk(s + 1), 3 * pp + (unsigned)p + ii));
         } else {
             g = ld_c(gl, (unsigned)(s * p) + ii);
         }
@@ -1216,16 +1248,21 @@ __device__ __forceinline__ void pass_reduced_cr(const SysDesc& sd, int tid, FT* 
     };
     // row layout -> column layout (lane (i, j) gets v[j])
     auto colv = [&](cplx<FT> v) { return shfl_c(v, 8 * j); };
-    auto ld_x = [&](int s, bool on) { return csel(i < p && on, ld_c(x_base, (unsigned)(s * p) + ii), zero); };
-    auto st_vec = [&](FT* base, int s, cplx<FT> v) {
-        if (j == 0 && i < p) st_c(base, (unsigned)(s * p + i), v);
+    auto ld_x = [&](int s, bool on) { return csel(i < p && on, ld_c(x_base, (unsigned)((k0 + s) * p) + ii), zero); };
+    auto st_x = [&](int s, cplx<FT> v) {
+        if (j == 0 && i < p) st_c(x_base, (unsigned)((k0 + s) * p + i), v);
     };
+    auto st_gl = [&](int s, cplx<FT> v) {
+        if (j == 0 && i < p) st_c(gl, (unsigned)(s * p + i), v);
+    };
+    // exchange entry of workgroup w (SPAN)
+    auto xe = [&](int w) { return sc.xch + 2 * (long long)w * xch_entry(p); };
 
     int nlev = 0;
-    while ((1 << nlev) < P) ++nlev;
+    while ((1 << nlev) < Pl) ++nlev;
     for (int l = 0; l < nlev; ++l) {
         const int st = 1 << l;
-        const int n = (P + st - 1) / st - 1;
+        const int n = (Pl + st - 1) / st - 1;
         // eliminations: positions q = 0, 2, .. < n
         const int ne = (n + 1) / 2;
         for (int t0 = wv; t0 < ne; t0 += NW * K) {
@@ -1238,11 +1275,11 @@ __device__ __forceinline__ void pass_reduced_cr(const SysDesc& sd, int tid, FT* 
                 ok[c] = t < ne;
                 const int q = 2 * (ok[c] ? t : t0);
                 e[c] = (q + 1) * st - 1;
-                const int r = q + 1 < n ? e[c] + st : P - 1;
-                a[c] = factor ? load_sig(e[c], l) : csel(valid, ld_c(d_base, (unsigned)e[c] * pp + ee), ident);
+                const int r = q + 1 < n ? e[c] + st : Pl - 1;
+                a[c] = factor ? load_sig(e[c], l) : csel(valid, ld_c(d_base, (unsigned)(k0 + e[c]) * pp + ee), ident);
                 g[c] = load_g(e[c], l, true);
                 if (factor) {
-                    ce[c] = csel(valid && q > 0, ld_c(blk(e[c]), pp + ee), zero);
+                    ce[c] = csel(valid && (q > 0 || ext), ld_c(blk(e[c]), pp + ee), zero);
                     crt[c] = csel(valid, ld_c(blk(r), pp + et), zero);
                 }
             }
@@ -1272,35 +1309,49 @@ __device__ __forceinline__ void pass_reduced_cr(const SysDesc& sd, int tid, FT* 
             }
 #pragma unroll
             for (int c = 0; c < K; ++c)
-                if (ok[c]) st_vec(x_base, e[c], h[c]);
+                if (ok[c]) st_x(e[c], h[c]);
         }
         __syncthreads();
-        // kept blocks: odd positions, and the last one (P - 1)
+        // kept blocks: odd positions, and the last one (Pl - 1); with ext one
+        // more item (t == nk) for the left neighbour block
         const int nk = n / 2 + 1;
-        for (int t0 = wv; t0 < nk; t0 += NW * K) {
+        const int nit = nk + (ext ? 1 : 0);
+        for (int t0 = wv; t0 < nit; t0 += NW * K) {
             int r[K];
-            bool ok[K], hl[K];
+            bool ok[K], hl[K], isl[K];
             cplx<FT> g[K], ge[K], ge2[K], vte[K], ute2[K];
             cplx<FT> sg[K], cr[K], ve[K], ue[K], c2t[K], ue2[K];
 #pragma unroll
             for (int c = 0; c < K; ++c) {
                 const int t = t0 + NW * c;
-                ok[c] = t < nk;
+                ok[c] = t < nit;
                 const int tt = ok[c] ? t : t0;
-                const int q = 2 * tt + 1 < n ? 2 * tt + 1 : n;
-                r[c] = q < n ? (q + 1) * st - 1 : P - 1;
-                hl[c] = (q & 1) != 0;                    // eliminated left neighbour
-                const bool hr = hl[c] && q + 1 < n;      // eliminated right neighbour
-                const int e = q * st - 1;
+                isl[c] = ext && tt == nk;
+                const int q = isl[c] ? -1 : (2 * tt + 1 < n ? 2 * tt + 1 : n);
+                r[c] = isl[c] ? -1 : (q < n ? (q + 1) * st - 1 : Pl - 1);
+                hl[c] = !isl[c] && (q & 1) != 0;                 // eliminated left neighbour
+                const bool hr = isl[c] || (hl[c] && q + 1 < n);  // eliminated right neighbour
+                const int e = isl[c] ? 0 : q * st - 1;
                 const int e2 = hr ? (q + 2) * st - 1 : e;
-                g[c] = load_g(r[c], l, true);
+                const int rr = isl[c] ? 0 : r[c];
+                if (isl[c]) {
+                    // the left neighbour's partial sums (level 0: chunk k0's
+                    // TL and gT, its contribution to block k0 - 1)
+                    g[c] = csel(i < p, l == 0 ? ld_c(blk(0), 3 * pp + (unsigned)p + ii) : ld_c(xe(sc.g), 3 * pp + ii + (unsigned)p),
+                                zero);
+                } else {
+                    g[c] = load_g(rr, l, true);
+                }
                 ge[c] = load_g(e, l, hl[c]);
                 ge2[c] = load_g(e2, l, hr);
                 vte[c] = ld_f(v_base, e, et, hl[c]);
                 ute2[c] = ld_f(u_base, e2, et, hr);
                 if (factor) {
-                    sg[c] = load_sig(r[c], l);
-                    cr[c] = csel(valid && hl[c], ld_c(blk(r[c]), pp + ee), zero);
+                    if (isl[c])
+                        sg[c] = csel(valid, l == 0 ? ld_c(blk(0), 2 * pp + ee) : ld_c(xe(sc.g), 2 * pp + ee), zero);
+                    else
+                        sg[c] = load_sig(rr, l);
+                    cr[c] = csel(valid && hl[c], ld_c(blk(rr), pp + ee), zero);
                     ve[c] = ld_f(v_base, e, ee, hl[c]);
                     ue[c] = ld_f(u_base, e, ee, hl[c]);
                     c2t[c] = csel(valid && hr, ld_c(blk(e2), pp + et), zero);
@@ -1325,8 +1376,13 @@ __device__ __forceinline__ void pass_reduced_cr(const SysDesc& sd, int tid, FT* 
 #pragma unroll
                 for (int c = 0; c < K; ++c) {
                     if (ok[c]) {
-                        if (valid) st_c(blk(r[c]), ee, csub(csub(sg[c], p1[c]), p3[c]));
-                        if (valid && hl[c]) st_c(blk(r[c]), pp + ee, cmk<FT>(-p2[c].re, -p2[c].im));
+                        const cplx<FT> sn = csub(csub(sg[c], p1[c]), p3[c]);
+                        if (isl[c]) {
+                            if (valid) st_c(xe(sc.g), 2 * pp + ee, sn);
+                        } else {
+                            if (valid) st_c(blk(r[c]), ee, sn);
+                            if (valid && hl[c]) st_c(blk(r[c]), pp + ee, cmk<FT>(-p2[c].re, -p2[c].im));
+                        }
                     }
                 }
             }
@@ -1334,49 +1390,146 @@ __device__ __forceinline__ void pass_reduced_cr(const SysDesc& sd, int tid, FT* 
             for (int c = 0; c < K; ++c) {
                 const cplx<FT> gn = csub(csub(g[c], row_sum(cmul(vte[c], colv(ge[c])))),
                                          row_sum(cmul(ute2[c], colv(ge2[c]))));
-                if (ok[c]) st_vec(gl, r[c], gn);
+                if (ok[c]) {
+                    if (isl[c]) {
+                        if (j == 0 && i < p) st_c(xe(sc.g), 3 * pp + (unsigned)p + (unsigned)i, gn);
+                    } else {
+                        st_gl(r[c], gn);
+                    }
+                }
             }
         }
         __syncthreads();
     }
-    if (wv == 0) {
-        cplx<FT> d[K];
-        d[0] = factor ? load_sig(P - 1, nlev) : csel(valid, ld_c(d_base, (unsigned)(P - 1) * pp + ee), ident);
-#pragma unroll
-        for (int c = 1; c < K; ++c) d[c] = ident;
-        if (factor) {
-            stage_inverse<p, FT, K>(S, 0, d);
-            st_blk(d_base, P - 1, d[0]);
+    if constexpr (SPAN) {
+        // export this workgroup's reduced super block (and, with a single
+        // block, the left neighbour's contribution), then solve the super
+        // system redundantly in every workgroup
+        if (wv == 0) {
+            FT* xw = xe(sc.g);
+            if (factor) {
+                const cplx<FT> sgm = load_sig(Pl - 1, nlev);
+                if (valid) {
+                    st_c(xw, ee, sgm);
+                    st_c(xw, pp + ee, ld_c(blk(Pl - 1), pp + ee));
+                }
+                if (nlev == 0 && ext && valid) st_c(xw, 2 * pp + ee, ld_c(blk(0), 2 * pp + ee));
+            }
+            const cplx<FT> gs = load_g(Pl - 1, nlev, true);
+            if (j == 0 && i < p) st_c(xw, 3 * pp + (unsigned)i, gs);
+            if (nlev == 0 && ext && j == 0 && i < p) st_c(xw, 3 * pp + (unsigned)(p + i), ld_c(blk(0), 3 * pp + (unsigned)(p + i)));
         }
-        st_vec(x_base, P - 1, row_sum(cmul(d[0], colv(load_g(P - 1, nlev, true)))));
+        grid_barrier();
+        if (wv == 0) {
+            const BlkStage<FT, 1> S1{lds + CrLds<FT>::kG, i, j};
+            const int G = sc.G;
+            auto gf = [&](int jj) { return sc.gfac + 2 * (long long)jj * gfac_entry(p); };
+            // forward: Delta_j = diag_j - M_j C_j^T, M_j = C_j Delta_{j-1}^-1,
+            // z_j = rhs_j - M_j z_{j-1}
+            cplx<FT> dprev = zero, zprev = zero;  // Delta_{j-1}^-1 (entry), z_{j-1} (row)
+            for (int jj = 0; jj < G; ++jj) {
+                const FT* x0 = xe(jj);
+                const bool more = jj + 1 < G;
+                cplx<FT> rhs = csel(i < p, ld_c(x0, 3 * pp + ii), zero);
+                if (more) rhs = cadd(rhs, csel(i < p, ld_c(xe(jj + 1), 3 * pp + (unsigned)p + ii), zero));
+                cplx<FT> m = zero;
+                if (factor) {
+                    cplx<FT> a[1] = {csel(valid, ld_c(x0, ee), ident)};
+                    if (more) a[0] = cadd(a[0], csel(valid, ld_c(xe(jj + 1), 2 * pp + ee), zero));
+                    const cplx<FT> cj = csel(valid && jj > 0, ld_c(x0, pp + ee), zero);
+                    if (jj > 0) {
+                        cplx<FT> cc[1] = {cj}, dd[1] = {dprev}, mm[1];
+                        S1.put(0, 0, cc[0]);
+                        S1.put(1, 0, dd[0]);
+                        wave_lds_sync();
+                        stage_prod<p, FT, 1>(S1, 0, 1, mm);
+                        wave_lds_sync();
+                        m = mm[0];
+                        // a -= M C^T: stage M and C^T
+                        S1.put(0, 0, m);
+                        S1.put(1, 0, csel(valid, ld_c(x0, pp + et), zero));
+                        wave_lds_sync();
+                        cplx<FT> mc[1];
+                        stage_prod<p, FT, 1>(S1, 0, 1, mc);
+                        wave_lds_sync();
+                        a[0] = csub(a[0], mc[0]);
+                    }
+                    stage_inverse<p, FT, 1>(S1, 0, a);
+                    FT* gj = gf(jj);
+                    if (valid) {
+                        st_c(gj, ee, a[0]);
+                        st_c(gj, pp + ee, m);
+                        st_c(gj, 2 * pp + ee, cj);
+                    }
+                    dprev = a[0];
+                } else {
+                    m = csel(valid && jj > 0, ld_c(gf(jj), pp + ee), zero);
+                }
+                const cplx<FT> z = csub(rhs, row_sum(cmul(m, colv(zprev))));
+                if (j == 0 && i < p) st_c(gf(jj), 3 * pp + (unsigned)i, z);
+                zprev = z;
+            }
+            // backward: x_j = Delta_j^-1 (z_j - C_{j+1}^T x_{j+1}), down to
+            // this workgroup's left neighbour
+            cplx<FT> xnext = zero;  // x_{j+1}, row layout
+            const int jlo = sc.g > 0 ? sc.g - 1 : 0;
+            for (int jj = G - 1; jj >= jlo; --jj) {
+                const FT* gj = gf(jj);
+                cplx<FT> w = csel(i < p, ld_c(gj, 3 * pp + ii), zero);
+                if (jj + 1 < G) {
+                    const cplx<FT> ct = csel(valid, ld_c(gf(jj + 1), 2 * pp + et), zero);  // C_{j+1}^T
+                    w = csub(w, row_sum(cmul(ct, colv(xnext))));
+                }
+                const cplx<FT> dv = csel(valid, ld_c(gj, ee), ident);
+                const cplx<FT> x = row_sum(cmul(dv, colv(w)));
+                if (jj == sc.g || jj == sc.g - 1) {
+                    if (j == 0 && i < p) st_c(x_base, (unsigned)(((jj + 1) * Pl - 1) * p + i), x);
+                }
+                xnext = x;
+            }
+        }
+        __syncthreads();
+    } else {
+        if (wv == 0) {
+            cplx<FT> d[K];
+            d[0] = factor ? load_sig(Pl - 1, nlev) : csel(valid, ld_c(d_base, (unsigned)(k0 + Pl - 1) * pp + ee), ident);
+#pragma unroll
+            for (int c = 1; c < K; ++c) d[c] = ident;
+            if (factor) {
+                stage_inverse<p, FT, K>(S, 0, d);
+                st_blk(d_base, Pl - 1, d[0]);
+            }
+            st_x(Pl - 1, row_sum(cmul(d[0], colv(load_g(Pl - 1, nlev, true)))));
+        }
+        __syncthreads();
     }
-    __syncthreads();
     for (int l = nlev - 1; l >= 0; --l) {
         const int st = 1 << l;
-        const int n = (P + st - 1) / st - 1;
+        const int n = (Pl + st - 1) / st - 1;
         const int ne = (n + 1) / 2;
         for (int t0 = wv; t0 < ne; t0 += NW * K) {
             int e[K];
             bool ok[K];
-            cplx<FT> xe[K], xr[K], xl[K], u[K], v[K];
+            cplx<FT> xe_[K], xr[K], xl[K], u[K], v[K];
 #pragma unroll
             for (int c = 0; c < K; ++c) {
                 const int t = t0 + NW * c;
                 ok[c] = t < ne;
                 const int q = 2 * (ok[c] ? t : t0);
                 e[c] = (q + 1) * st - 1;
-                const int r = q + 1 < n ? e[c] + st : P - 1;
-                const int lft = q > 0 ? e[c] - st : e[c];
-                xe[c] = ld_x(e[c], true);
+                const int r = q + 1 < n ? e[c] + st : Pl - 1;
+                const bool hasl = q > 0 || ext;
+                const int lft = q > 0 ? e[c] - st : -1;  // -1: the left neighbour block k0 - 1
+                xe_[c] = ld_x(e[c], true);
                 xr[c] = ld_x(r, true);
-                xl[c] = ld_x(lft, q > 0);
-                u[c] = ld_f(u_base, e[c], ee, q > 0);
+                xl[c] = ld_x(hasl ? lft : e[c], hasl);
+                u[c] = ld_f(u_base, e[c], ee, hasl);
                 v[c] = ld_f(v_base, e[c], ee, true);
             }
 #pragma unroll
             for (int c = 0; c < K; ++c) {
-                const cplx<FT> x = csub(csub(xe[c], row_sum(cmul(v[c], colv(xr[c])))), row_sum(cmul(u[c], colv(xl[c]))));
-                if (ok[c]) st_vec(x_base, e[c], x);
+                const cplx<FT> x = csub(csub(xe_[c], row_sum(cmul(v[c], colv(xr[c])))), row_sum(cmul(u[c], colv(xl[c]))));
+                if (ok[c]) st_x(e[c], x);
             }
         }
         __syncthreads();

@@ -142,6 +142,33 @@ __global__ void pack_band_kernel(BandSrc src, int N, int p, int P, int L, int LS
 
 }  // namespace
 
+// Observables of a spanning system: the per-workgroup parts of every step
+// added in workgroup order; the earliest non-finite step is latched as in
+// the one-workgroup kernels.  One workgroup of 256 threads.
+__global__ void span_sum_kernel(const double* __restrict__ part, int G, int nsteps, double* __restrict__ obs,
+                                unsigned mask, int* __restrict__ status) {
+    __shared__ int first[256];
+    int bad = nsteps + 1;
+    for (int n = threadIdx.x; n <= nsteps; n += blockDim.x) {
+        double v[3] = {0.0, 0.0, 0.0};
+        for (int g = 0; g < G; ++g)
+            for (int c = 0; c < 3; ++c) v[c] += part[3 * ((long long)n * G + g) + c];
+        if (obs) {
+            obs[3 * n + 0] = (mask & TDSEZ_OBS_NORM) ? v[0] : 0.0;
+            obs[3 * n + 1] = (mask & TDSEZ_OBS_DIPOLE) ? v[1] : 0.0;
+            obs[3 * n + 2] = (mask & TDSEZ_OBS_ACCEL) ? v[2] : 0.0;
+        }
+        if ((!isfinite(v[0]) || !isfinite(v[1]) || !isfinite(v[2])) && n < bad) bad = n;
+    }
+    first[threadIdx.x] = bad;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int m = nsteps + 1;
+        for (int t = 0; t < (int)blockDim.x; ++t) m = first[t] < m ? first[t] : m;
+        if (m <= nsteps) latch(status, TDSEZ_ENONFINITE, 0, m);
+    }
+}
+
 Plan make_plan(int N, int p, int force_chunks, int max_chunks, double rule) {
     Plan pl;
     pl.N = N;
@@ -188,6 +215,24 @@ Plan multi_wave_plan(int N, int p, int force_chunks, int max_waves) {
     return make_plan(N, p, 0);
 }
 
+int span_plan(int N, int p, int G, int Pl, Plan* out) {
+    if (Pl <= 0) Pl = 64;
+    if (Pl > kMaxChunks4) Pl = kMaxChunks4;
+    if (G <= 0) {
+        // chunks of about 2p + 6 rows (measured on the 30 007-row H2+ chain:
+        // 64 chunks per workgroup and 20-row chunks beat 32, 128 or 256
+        // chunks per workgroup and 15- or 19-row chunks)
+        const double Lt = 2.0 * p + 6.0;
+        G = (int)std::lround(N / (Lt * Pl));
+        if (G > kMaxSpan) G = kMaxSpan;
+    }
+    // every chunk needs at least 2p rows
+    while (G > 1 && (long long)G * Pl * 2 * p > N) --G;
+    if (G < 2) return 1;
+    *out = make_plan(N, p, G * Pl, G * Pl);
+    return out->P == G * Pl ? G : 1;
+}
+
 tdsez_status pack_bands(BatchData* b) {
     const int nsys = (int)b->sys.size();
     b->plan.resize(nsys);
@@ -198,6 +243,7 @@ tdsez_status pack_bands(BatchData* b) {
     b->waves.assign(nsys, 1);
     b->nsplit = 0;
     b->n4 = 0;
+    b->span_G = 1;
     for (int s = 0; s < nsys; ++s) {
         SystemData* sy = b->sys[s];
         const int tuned = s < (int)b->tuned_chunks.size() ? b->tuned_chunks[s] : 0;
@@ -206,7 +252,21 @@ tdsez_status pack_bands(BatchData* b) {
         // a marked system runs on the most waves whose rule needs them (a
         // system whose two-wave rule gives at most 64 chunks stays on one
         // wave, with the one-wave rule); an unmarked one on one wave
-        const Plan pl = multi_wave_plan(sy->N, sy->p, force, req ? b->max_waves : 1);
+        Plan pl = multi_wave_plan(sy->N, sy->p, force, req ? b->max_waves : 1);
+        // the one-system plan of tdsez_propagate spreads a long chain over
+        // several workgroups: automatically once the four-wave plan holds
+        // chunks of more than 48 rows, or as set by tdsez_system_set
+        if (b->solo && nsys == 1 && force == 0 && sy->span_G != 1) {
+            const bool want = sy->span_G > 1 || (pl.P == kMaxChunks4 && pl.L > 48);
+            Plan sp;
+            if (want) {
+                const int G = span_plan(sy->N, sy->p, sy->span_G, sy->span_Pl, &sp);
+                if (G > 1) {
+                    pl = sp;
+                    b->span_G = G;
+                }
+            }
+        }
         b->plan[s] = pl;
         b->waves[s] = (char)plan_waves(pl);
         if (b->waves[s] > 1) ++b->nsplit;
@@ -214,6 +274,8 @@ tdsez_status pack_bands(BatchData* b) {
         SysDesc& d = b->desc[s];
         d = SysDesc{};
         d.N = pl.N; d.p = pl.p; d.P = pl.P; d.L = pl.L; d.m = pl.m; d.LS = pl.LS;
+        d.G = b->span_G;
+        d.Pl = pl.P / b->span_G;
         d.mi_is_s = sy->const_mass ? 1 : 0;
         d.cap = sy->d_W ? 1 : 0;
         d.aq = sy->d_Q ? 1 : 0;
@@ -296,6 +358,22 @@ tdsez_status upload_descriptors(BatchData* b, hipStream_t stream) {
     if (b->desc_on_device.size() == n &&
         std::memcmp(b->desc_on_device.data(), b->desc.data(), sizeof(SysDesc) * n) == 0)
         return TDSEZ_OK;
+    // an upload is a copy from pageable host memory, which a stream capture
+    // cannot hold: a captured call must repeat the previous call's arguments
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    TDSEZ_HIP_TRY(hipStreamIsCapturing(stream, &cap));
+    if (cap != hipStreamCaptureStatusNone) {
+        size_t at = 0;
+        if (b->desc_on_device.size() == n) {
+            const unsigned char* x = reinterpret_cast<const unsigned char*>(b->desc_on_device.data());
+            const unsigned char* y = reinterpret_cast<const unsigned char*>(b->desc.data());
+            while (at < sizeof(SysDesc) * n && x[at] == y[at]) ++at;
+        }
+        return fail(TDSEZ_EINVAL,
+                    "captured propagation call with arguments that differ from the previous call (descriptor byte "
+                    "%zu of %zu): run the call once eagerly with the same arguments first",
+                    at, sizeof(SysDesc) * n);
+    }
     // Workgroups are dispatched in index order, so when the batch holds more
     // systems than the device has wave slots the costliest ones (cost
     // N (p + 1) nsteps) start first and the short ones fill in behind them.
@@ -361,6 +439,36 @@ tdsez_status launch_propagate(BatchData* b, double* psi, const double* E, double
     const bool fp64 = prec == TDSEZ_FP64;
     ka.band = fp64 ? (const void*)b->d_band64 : (const void*)b->d_band32;
     ka.refine = fp64 ? 0 : b->refine;
+    if (b->span_G > 1) {
+        // one system on span_G cooperative workgroups
+        if (xt) return fail(TDSEZ_EUNSUPPORTED,
+                            "the extended kernels run on one workgroup: tdsez_system_set(sys, \"workgroups\", 1)");
+        const int G = b->span_G, p = b->plan[0].p, ns = b->desc[0].nsteps;
+        const size_t xch_b = 2 * sizeof(double) * (size_t)(2 * G * xch_entry(p));
+        const size_t gfac_b = 2 * sizeof(double) * (size_t)((long long)G * G * gfac_entry(p));
+        if (!b->d_xch) {
+            TDSEZ_HIP_TRY(hipMalloc(&b->d_xch, xch_b));
+            TDSEZ_HIP_TRY(hipMalloc(&b->d_gfac, gfac_b));
+        }
+        const long long need = 3LL * (ns + 1) * G;
+        if (need > b->obs_part_elems) {
+            (void)hipFree(b->d_obs_part);
+            b->d_obs_part = nullptr;
+            b->obs_part_elems = 0;
+            TDSEZ_HIP_TRY(hipMalloc(&b->d_obs_part, sizeof(double) * (size_t)need));
+            b->obs_part_elems = need;
+        }
+        ka.xch = b->d_xch;
+        ka.gfac = b->d_gfac;
+        ka.obs_part = b->d_obs_part;
+        TDSEZ_HIP_TRY(fp64 ? launch_prop_f64_span(ka, G, stream) : launch_prop_f32_span(ka, G, stream));
+        span_sum_kernel<<<1, 256, 0, stream>>>(b->d_obs_part, G, ns, obs, obs_mask, b->d_status);
+        TDSEZ_HIP_TRY(hipGetLastError());
+        dim3 grid((unsigned)std::min<long long>((maxN + 255) / 256, 1024), nsys);
+        unpack_state_kernel<<<grid, 256, 0, stream>>>(b->d_desc, b->d_state, psi);
+        TDSEZ_HIP_TRY(hipGetLastError());
+        return TDSEZ_OK;
+    }
     // Multi-wave systems (the costliest of the batch) are launched first,
     // the first group on the caller's stream; the other groups run
     // concurrently on side streams forked from and joined back into the

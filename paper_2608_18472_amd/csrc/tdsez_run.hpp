@@ -29,9 +29,10 @@ __device__ __forceinline__ void combine_waves(double (&v)[CAP], int cnt, int tid
     }
 }
 
-template <int PP, typename FT, int NW>
-__device__ __forceinline__ void reduced_solve(const SysDesc& sd, int tid, FT* red, bool factor, FT* zl) {
-    if constexpr (NW == 4) pass_reduced_cr<PP, FT, 4>(sd, tid, red, factor, zl);
+template <int PP, typename FT, int NW, bool SPAN>
+__device__ __forceinline__ void reduced_solve(const SysDesc& sd, int tid, FT* red, bool factor, FT* zl,
+                                              const SpanCtx<FT>& sc) {
+    if constexpr (NW == 4) pass_reduced_cr<PP, FT, 4, SPAN>(sd, tid, red, factor, zl, sc);
     else if constexpr (NW == 2) pass_reduced2<PP, FT>(sd, tid, red, factor, zl);
     else pass_reduced<PP, FT>(sd, tid, red, factor, zl);
 }
@@ -43,8 +44,14 @@ __device__ __forceinline__ void reduced_solve(const SysDesc& sd, int tid, FT* re
 // 129..256), the separator system by block cyclic reduction
 // (pass_reduced_cr).  XT: the extended kernels (an
 // absorbing potential in A_n and B_n, the extended series of section V.D,
-// the a_Q term of the acceleration).
-template <int PP, typename FT, int NW, bool XT>
+// the a_Q term of the acceleration).  SPAN: one system on sd.G workgroups of
+// four waves (a cooperative launch): workgroup g owns chunks g Pl ..
+// (g + 1) Pl - 1, the separator system is reduced per workgroup and the
+// super blocks solved in every workgroup after a grid barrier, a second grid
+// barrier follows every back substitution (the next pass reads the
+// neighbouring workgroups' state rows), and the observable sums are written
+// per workgroup (ka.obs_part) and added up after the launch.
+template <int PP, typename FT, int NW, bool XT, bool SPAN = false>
 __device__ __forceinline__ void run_system(const KernelArgs& ka, const SysDesc& sd, int sidx, FT* zl) {
     // optional phase profile: shader-clock cycles summed over the steps for
     // the passes H, A1 (FP32: one fused sweep counted under H), A2, R, B and,
@@ -57,8 +64,25 @@ __device__ __forceinline__ void run_system(const KernelArgs& ka, const SysDesc& 
     FT* red = (FT*)ka.red;
     FT* rhs = (FT*)ka.rhs;
     double* st = ka.st;
-    const int lane = threadIdx.x;  // chunk index
-    const bool active = lane < sd.P;
+    const int tid = threadIdx.x;
+    const int wg = SPAN ? (int)blockIdx.x : 0;
+    const int lane = SPAN ? wg * sd.Pl + tid : tid;  // chunk index
+    const bool active = SPAN ? (tid < sd.Pl && lane < sd.P) : lane < sd.P;
+    SpanCtx<FT> sc{0, sd.P, 0, 1, nullptr, nullptr};
+    int phase = 0;  // reduced solves so far (SPAN: exchange buffer parity)
+    if constexpr (SPAN) {
+        sc.k0 = wg * sd.Pl;
+        sc.Pl = sd.Pl;
+        sc.g = wg;
+        sc.G = sd.G;
+        sc.gfac = (FT*)ka.gfac + 2 * (long long)wg * sd.G * gfac_entry(PP);
+    }
+    auto span_ctx = [&]() {
+        SpanCtx<FT> c = sc;
+        if constexpr (SPAN) c.xch = (FT*)ka.xch + 2 * (long long)(phase & 1) * sd.G * xch_entry(PP);
+        ++phase;
+        return c;
+    };
     const double alpha = 0.5 * sd.dt;
     const double* Es = ka.E + sd.E_off;
     double* os = ka.obs ? ka.obs + sd.obs_off : nullptr;
@@ -113,17 +137,26 @@ __device__ __forceinline__ void run_system(const KernelArgs& ka, const SysDesc& 
             if (!kFused) pass_schur<PP, FT>(sd, lane, fac, red);
         }
         double sums[3] = {wave_sum(part[0]), wave_sum(part[1]), wave_sum(part[2])};
-        combine_waves<NW>(sums, 3, lane);
+        combine_waves<NW>(sums, 3, tid);
         double nu = sums[0], dip = sums[1], acc = sums[2];
         if constexpr (XT) {
             if (want_ext) {
                 const int cnt = 8 + 2 * sd.npop;
                 for (int i = 0; i < cnt; ++i) xs[i] = wave_sum(xs[i]);
-                combine_waves<NW>(xs, cnt, lane);
+                combine_waves<NW>(xs, cnt, tid);
                 if (want_acc && sd.aq) acc += xs[4];
             }
         }
-        if (lane == 0 && os) {
+        if constexpr (SPAN) {
+            // this workgroup's parts; the sums and the finiteness check follow
+            // the launch (no workgroup may leave before the others)
+            if (tid == 0 && ka.obs_part) {
+                double* op = ka.obs_part + 3 * ((long long)n * sd.G + wg);
+                op[0] = nu;
+                op[1] = dip;
+                op[2] = acc;
+            }
+        } else if (lane == 0 && os) {
             os[3 * n + 0] = (mask & TDSEZ_OBS_NORM) ? nu : 0.0;
             os[3 * n + 1] = (mask & TDSEZ_OBS_DIPOLE) ? dip : 0.0;
             os[3 * n + 2] = want_acc ? acc : 0.0;
@@ -146,21 +179,24 @@ __device__ __forceinline__ void run_system(const KernelArgs& ka, const SysDesc& 
             }
         }
         if (n == 0) nu0 = nu;
-        if (!isfinite(nu) || !isfinite(dip) || !isfinite(acc)) {
-            if (lane == 0) latch(ka.status, TDSEZ_ENONFINITE, sidx, n);
-            return;
-        }
-        if (ka.norm_tol > 0.0 && fabs(nu / nu0 - 1.0) > ka.norm_tol) {
-            if (lane == 0) latch(ka.status, TDSEZ_ENORMDRIFT, sidx, n);
-            return;
+        if constexpr (!SPAN) {
+            if (!isfinite(nu) || !isfinite(dip) || !isfinite(acc)) {
+                if (lane == 0) latch(ka.status, TDSEZ_ENONFINITE, sidx, n);
+                return;
+            }
+            if (ka.norm_tol > 0.0 && fabs(nu / nu0 - 1.0) > ka.norm_tol) {
+                if (lane == 0) latch(ka.status, TDSEZ_ENORMDRIFT, sidx, n);
+                return;
+            }
         }
         if (last) break;
         __syncthreads();
         mark(2);
-        reduced_solve<PP, FT, NW>(sd, lane, red, true, zl);
+        reduced_solve<PP, FT, NW, SPAN>(sd, tid, red, true, zl, span_ctx());
         __syncthreads();
         mark(3);
         if (active) pass_backsub<PP, FT, XT>(sd, lane, band, st, dtot, true, fac, red, alpha, Ebar);
+        if constexpr (SPAN) grid_barrier();
         __syncthreads();
         mark(4);
         // refinement sweeps exist for the FP32 factorisation only (FP64
@@ -175,23 +211,25 @@ __device__ __forceinline__ void run_system(const KernelArgs& ka, const SysDesc& 
                 // the last sweep's starting residual measures the FP32
                 // factorisation; beyond the batch tolerance the sweeps are
                 // not converging (latched, the propagation goes on)
+                // (SPAN: this workgroup's rows only)
                 double rs[2] = {wave_sum(nrm[0]), wave_sum(nrm[1])};
-                combine_waves<NW>(rs, 2, lane);
+                combine_waves<NW>(rs, 2, tid);
                 const double rel = rs[1] > 0.0 ? sqrt(rs[0] / rs[1]) : 0.0;
                 worst_rel = fmax(worst_rel, rel);
-                if (!(rel <= ka.refine_tol) && lane == 0) latch(ka.status, TDSEZ_ENOCONV, sidx, n);
+                if (!(rel <= ka.refine_tol) && tid == 0) latch(ka.status, TDSEZ_ENOCONV, sidx, n);
             }
-            reduced_solve<PP, FT, NW>(sd, lane, red, false, zl);
+            reduced_solve<PP, FT, NW, SPAN>(sd, tid, red, false, zl, span_ctx());
             __syncthreads();
             mark(6);
             if (active)
                 pass_backsub<PP, FT, XT>(sd, lane, band, st, sweep + 1 < refine ? dtot : nullptr, false, fac,
                                          red, alpha, Ebar);
+            if constexpr (SPAN) grid_barrier();
             __syncthreads();
             mark(7);
         }
     }
-    if (prof && lane == 0) {
+    if (prof && lane == 0 && tid == 0) {
         unsigned long long* pr = ka.prof + kProfSlots * sidx;
         for (int k = 0; k < kProfSlots - 2; ++k) pr[k] = tp[k];
         pr[kProfSlots - 2] = (unsigned long long)sd.nsteps;
@@ -201,20 +239,21 @@ __device__ __forceinline__ void run_system(const KernelArgs& ka, const SysDesc& 
 
 // zl: the separator recurrence's right-hand-side vector, P * p complex in
 // LDS, one array per kernel (shared by the p variants)
-template <typename FT, int NW, bool XT>
+template <typename FT, int NW, bool XT, bool SPAN = false>
 __device__ __forceinline__ void dispatch_system(const KernelArgs& ka) {
     // (four waves: the cyclic reduction's g vectors and block staging)
     __shared__ FT zl[NW == 4 ? CrLds<FT>::kTotal : 2 * kMaxP * kWave * NW];
-    const int sidx = ka.order[ka.order_off + blockIdx.x];
+    // a spanning launch holds one system (all its workgroups)
+    const int sidx = ka.order[ka.order_off + (SPAN ? 0 : (int)blockIdx.x)];
     const SysDesc sd = ka.descs[sidx];
     switch (sd.p) {
-        case 1: run_system<1, FT, NW, XT>(ka, sd, sidx, zl); break;
-        case 2: run_system<2, FT, NW, XT>(ka, sd, sidx, zl); break;
-        case 3: run_system<3, FT, NW, XT>(ka, sd, sidx, zl); break;
-        case 4: run_system<4, FT, NW, XT>(ka, sd, sidx, zl); break;
-        case 5: run_system<5, FT, NW, XT>(ka, sd, sidx, zl); break;
-        case 6: run_system<6, FT, NW, XT>(ka, sd, sidx, zl); break;
-        case 7: run_system<7, FT, NW, XT>(ka, sd, sidx, zl); break;
+        case 1: run_system<1, FT, NW, XT, SPAN>(ka, sd, sidx, zl); break;
+        case 2: run_system<2, FT, NW, XT, SPAN>(ka, sd, sidx, zl); break;
+        case 3: run_system<3, FT, NW, XT, SPAN>(ka, sd, sidx, zl); break;
+        case 4: run_system<4, FT, NW, XT, SPAN>(ka, sd, sidx, zl); break;
+        case 5: run_system<5, FT, NW, XT, SPAN>(ka, sd, sidx, zl); break;
+        case 6: run_system<6, FT, NW, XT, SPAN>(ka, sd, sidx, zl); break;
+        case 7: run_system<7, FT, NW, XT, SPAN>(ka, sd, sidx, zl); break;
         default: break;
     }
 }
@@ -261,6 +300,16 @@ __device__ __forceinline__ void dispatch_system(const KernelArgs& ka) {
     __global__ __launch_bounds__(4 * kWave) void tune_probe4_kernel(KernelArgs ka) {                       \
         dispatch_system<T, 4, false>(ka);                                                                  \
     }                                                                                                      \
+    template <typename T>                                                                                  \
+    __global__ __launch_bounds__(4 * kWave) void propagate_span_kernel(KernelArgs ka) {                    \
+        dispatch_system<T, 4, false, true>(ka);                                                            \
+    }                                                                                                      \
+    }                                                                                                      \
+    hipError_t NAME##_span(const KernelArgs& ka, int G, hipStream_t s) {                                   \
+        KernelArgs k = ka;                                                                                 \
+        void* args[] = {&k};                                                                               \
+        return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&propagate_span_kernel<FT>),       \
+                                          dim3(G), dim3(4 * kWave), args, 0, s);                          \
     }                                                                                                      \
     hipError_t NAME(const KernelArgs& ka, int n4, int n2, int n1, hipStream_t s4, hipStream_t s2,         \
                     hipStream_t s1, bool probe) {                                                          \

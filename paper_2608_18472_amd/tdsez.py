@@ -89,6 +89,8 @@ def lib():
         "tdsez_batch_two_wave": [vp, ip],
         "tdsez_batch_waves": [vp, ip],
         "tdsez_system_status": [vp, vp, ip],
+        "tdsez_system_set": [vp, ctypes.c_char_p, d],
+        "tdsez_system_workgroups": [vp, ip, ip],
     }
     for name, args in sigs.items():
         f = getattr(L, name)
@@ -485,6 +487,19 @@ def batch_waves(batch):
     out = np.zeros(len(batch.systems), dtype=np.int32)
     _check(lib().tdsez_batch_waves(batch.handle, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int))))
     return out
+
+
+def system_set(sys, key, value):
+    """Partition settings of the single-system plan ("workgroups",
+    "chunks_per_workgroup"; tdsez_system_set)."""
+    _check(lib().tdsez_system_set(sys.handle, key.encode(), float(value)))
+
+
+def system_workgroups(sys):
+    """(workgroups, chunk count) of the single-system plan."""
+    g, c = ctypes.c_int(), ctypes.c_int()
+    _check(lib().tdsez_system_workgroups(sys.handle, ctypes.byref(g), ctypes.byref(c)))
+    return g.value, c.value
 
 
 def system_status(sys, stream=None):

@@ -10,6 +10,7 @@ power of two and the largest (256), in batches that mix four-, two- and
 one-wave systems (three concurrent launches), in a captured graph, and
 through tdsez_propagate on a lone long system.
 """
+import gc
 import sys
 
 import numpy as np
@@ -153,8 +154,15 @@ def test_four_wave_graph_replays_match_eager(prec):
     graph = torch.cuda.CUDAGraph()
     psi.copy_(psi0)
     torch.cuda.synchronize()
-    with torch.cuda.graph(graph):
-        T.propagate_batched(b, psi, po, E, eo, dts, nss, prec, T.OBS_ALL, ob, oo, torch.cuda.current_stream())
+    # handles of earlier tests must not be destroyed (device frees) while
+    # the capture runs: collect them now and keep the collector off
+    gc.collect()
+    gc.disable()
+    try:
+        with torch.cuda.graph(graph):
+            T.propagate_batched(b, psi, po, E, eo, dts, nss, prec, T.OBS_ALL, ob, oo, torch.cuda.current_stream())
+    finally:
+        gc.enable()
     for rep in range(3):
         psi.copy_(psi0)
         ob.zero_()

@@ -3,6 +3,7 @@ and replayed: every replay, with eager work on the same stream in between,
 must reproduce the eager result bit for bit (same kernels, fixed summation
 order).  A warm-up call with the same arguments precedes the capture, so the
 captured call enqueues kernels only."""
+import gc
 import sys
 
 import numpy as np
@@ -56,8 +57,15 @@ def test_graph_replays_match_eager(prec):
     graph = torch.cuda.CUDAGraph()
     psi.copy_(psi0)
     torch.cuda.synchronize()
-    with torch.cuda.graph(graph):
-        T.propagate_batched(b, psi, po, E, eo, dts, nss, prec, T.OBS_ALL, ob, oo, torch.cuda.current_stream())
+    # handles of earlier tests must not be destroyed (device frees) while
+    # the capture runs: collect them now and keep the collector off
+    gc.collect()
+    gc.disable()
+    try:
+        with torch.cuda.graph(graph):
+            T.propagate_batched(b, psi, po, E, eo, dts, nss, prec, T.OBS_ALL, ob, oo, torch.cuda.current_stream())
+    finally:
+        gc.enable()
     for rep in range(3):
         psi.copy_(psi0)
         ob.zero_()

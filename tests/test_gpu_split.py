@@ -9,6 +9,7 @@ stream, so a graph captured from the call must replay to the eager result
 bit for bit, and mixed batches must keep the per-system bookkeeping
 (profile rows, chunk counts) in system order.
 """
+import gc
 import sys
 
 import numpy as np
@@ -162,8 +163,15 @@ def test_two_wave_graph_replays_match_eager(prec):
     graph = torch.cuda.CUDAGraph()
     psi.copy_(psi0)
     torch.cuda.synchronize()
-    with torch.cuda.graph(graph):
-        T.propagate_batched(b, psi, po, E, eo, dts, nss, prec, T.OBS_ALL, ob, oo, torch.cuda.current_stream())
+    # handles of earlier tests must not be destroyed (device frees) while
+    # the capture runs: collect them now and keep the collector off
+    gc.collect()
+    gc.disable()
+    try:
+        with torch.cuda.graph(graph):
+            T.propagate_batched(b, psi, po, E, eo, dts, nss, prec, T.OBS_ALL, ob, oo, torch.cuda.current_stream())
+    finally:
+        gc.enable()
     for rep in range(3):
         psi.copy_(psi0)
         ob.zero_()
