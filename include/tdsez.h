@@ -346,7 +346,9 @@ tdsez_status tdsez_propagate(tdsez_system sys, double* psi, const double* E, dou
  * rows, separator system, descriptor) lives in one file-scope device array
  * of 64 MiB per GPU, held until the process ends, and is filled from the
  * system's bands on every call; the kernels and the plan are those of
- * tdsez_propagate, so the results are the same.  A system that needs more
+ * tdsez_propagate on one workgroup (up to four waves), so the results are
+ * the same wherever tdsez_propagate keeps one workgroup (where it spreads a
+ * long chain over several, see tdsez_system_set, they agree to rounding).  A system that needs more
  * than 64 MiB (N above about 50 000 at order 8) is refused with EINVAL.
  * Every call on a GPU shares that GPU's array: calls that overlap on one
  * GPU (different streams, threads or processes' graphs replayed

@@ -557,7 +557,7 @@ extern "C" tdsez_status tdsez_propagate_noalloc(tdsez_system sys_h, double* psi,
     if (sy->d_W || sy->d_Q) return fail(TDSEZ_EUNSUPPORTED, "no-alloc propagation: no absorber or a_Q form");
     if ((obs & TDSEZ_OBS_ACCEL) && !sy->const_mass)
         return fail(TDSEZ_EUNSUPPORTED, "position-dependent mass: the acceleration needs the a_Q form");
-    // the plan of tdsez_propagate (up to four waves)
+    // the one-workgroup plan of tdsez_propagate (up to four waves; no spanning)
     const Plan pl = multi_wave_plan(sy->N, sy->p, 0, 4);
     const int nw = plan_waves(pl);
     // scratch layout
