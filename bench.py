@@ -35,8 +35,14 @@ CALIB_COPY_BYTES = 512 * 2 ** 20
 # (FETCH_SIZE, then WRITE_SIZE) scaled by the copy calibration; valid only for
 # the kernel sources they were taken on (sha256 of the listed files) and the
 # default --split.  See profiles/propagate_kernel_fp32_batch1024_pmc.md.
-TRAFFIC = {"sources_sha256": "d249a4f2d43b42c2ddec4a01d29231563de1efd9bf85b98bd53c75b92ae3f8d4",
-           "bytes_per_launch": 2.4251e+13, "split": 160}
+TRAFFIC = {"sources_sha256": "78b5763fe0ce3e7fd975ac5e8cb1b44be7d4b18a03dbf73020c61b492cea8744",
+           "bytes_per_launch": 2.4272e+13, "split": 160}
+# HBM bytes of one FP32 3D operator launch (apply3_kernel<3, float>, 97^3), from the
+# two counter runs of profiles/apply3_kernel_hydrogen97_3d.md, for the sources listed.
+TRAFFIC_3D = {"sources_sha256": "3194a86fe24927cd26bbfe8f0afbf868a4ba2b6297941c2ea94ebdd2dd920953",
+              "bytes_per_launch": 1.5976e+09}
+KERNEL_SOURCES_3D = ["paper_2608_18472_amd/csrc/tdsez_3d.hip", "paper_2608_18472_amd/csrc/tdsez_krylov.hpp",
+                     "paper_2608_18472_amd/csrc/tdsez_internal.hpp"]
 KERNEL_SOURCES = ["paper_2608_18472_amd/csrc/tdsez_passes.hpp", "paper_2608_18472_amd/csrc/tdsez_propagate.hip",
                   "paper_2608_18472_amd/csrc/tdsez_internal.hpp", "paper_2608_18472_amd/csrc/tdsez_run.hpp",
                   "paper_2608_18472_amd/csrc/tdsez_prop_f32.hip"]
@@ -56,10 +62,10 @@ def stencil3d_bytes(p, real_bytes):
 TABLE2_DOFSTEPS_256 = 912673 * 100 / 48.4
 
 
-def kernel_sources_sha():
+def kernel_sources_sha(files=None):
     import hashlib
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in (KERNEL_SOURCES if files is None else files):
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
@@ -507,7 +513,10 @@ def run_3d(args):
                                      "assembly 10.9 s, eigensolve 15.0 s); another machine, context",
         },
         "roofline": {"bound": "hbm", "achieved": b32 / (ms32 * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": b32 / (ms32 * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                     "frac": b32 / (ms32 * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "traffic": (TRAFFIC_3D["bytes_per_launch"]
+                                 if kernel_sources_sha(KERNEL_SOURCES_3D) == TRAFFIC_3D["sources_sha256"]
+                                 and n == 912673 else None),
                      "kernel": "apply3_kernel<3, float> (FP32 operator of the inner iterations), %d B/unknown"
                                % stencil3d_bytes(g.p, 4)},
     }
