@@ -113,7 +113,6 @@ struct Plan {
 // Device descriptor of one system of a batch (read by the propagation kernel).
 struct SysDesc {
     int N, p, P, L, m, LS;
-    int G, Pl;            // workgroups of a spanning system (else 1) and chunks per workgroup
     int nsteps;
     int mi_is_s;          // constant mass: Mi equals S bit for bit (m^-1 = 1 at every point)
     double dt;
@@ -131,6 +130,7 @@ struct SysDesc {
     int npop;             // projection states
     long long proj_off;   // doubles into the packed projection states
     long long ext_off;    // doubles into the caller's extended-series buffer
+    int G, Pl;            // workgroups of a spanning system (else 1) and chunks per workgroup
 };
 
 struct BatchData {
@@ -202,14 +202,14 @@ struct KernelArgs {
     int* status;
     unsigned long long* prof;
     double refine_tol;         // ENOCONV threshold of the last sweep's relative residual
-    // spanning launch only (one system on several workgroups)
-    void* xch;                 // exchanged super-block data, two buffers (FT)
-    void* gfac;                // per workgroup: factors of the super-block system (FT)
-    double* obs_part;          // per step and workgroup: norm, dipole, acceleration parts
     // extended kernels only
     const double* c0;          // initial states (state layout), or nullptr: no autocorrelation
     const double* proj;        // packed projection states S phi_k
     double* ext;               // extended series (caller's buffer), or nullptr
+    // spanning launch only (one system on several workgroups)
+    void* xch;                 // exchanged super-block data, two buffers (FT)
+    void* gfac;                // per workgroup: factors of the super-block system (FT)
+    double* obs_part;          // per step and workgroup: norm, dipole, acceleration parts
 };
 
 // ---------------------------------------------------------------- kernels

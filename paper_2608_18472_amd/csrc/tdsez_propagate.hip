@@ -413,7 +413,7 @@ tdsez_status launch_propagate(BatchData* b, double* psi, const double* E, double
         pack_state_kernel<<<grid, 256, 0, stream>>>(b->d_desc, psi, b->d_state, ext ? b->d_c0 : nullptr);
         TDSEZ_HIP_TRY(hipGetLastError());
     }
-    KernelArgs ka;
+    KernelArgs ka{};
     ka.descs = b->d_desc;
     ka.order = b->d_order;
     ka.order_off = 0;
