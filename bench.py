@@ -559,7 +559,7 @@ def run_h2p(args):
     """One long chain: the 1D H2+ model (N = 30 007, p = 7) over its whole
     6-cycle trapezoidal pulse (13 228 steps), FP32-refined then FP64, through
     the single-system call, whose plan spreads the chain over several
-    workgroups (64 chunks of about 20 rows each, one grid-wide exchange of
+    workgroups (64 chunks of about 16 rows each, one grid-wide exchange of
     the workgroups' last separator blocks per solve)."""
     import torch
     from paper_2608_18472_amd import tdsez as T

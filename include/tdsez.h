@@ -538,10 +538,11 @@ tdsez_status tdsez_system_status(tdsez_system sys, void* stream, int* step_out);
  * By default a system whose four-wave plan would hold chunks of more than 48
  * rows (N above about 12 000 at order 8) is spread over G workgroups of four
  * waves on different compute units, launched cooperatively (all resident
- * at once): workgroup g owns Pl consecutive chunks (chunks of about 2p + 6
+ * at once): workgroup g owns Pl consecutive chunks (chunks of about 2p + 1
  * rows), reduces its part of the separator system by block cyclic reduction
  * down to its last separator block, and after a grid barrier every
- * workgroup solves the G-block system of those blocks itself; a second
+ * workgroup solves the G-block system of those blocks itself (from both
+ * ends at once, as far as its own two blocks); a second
  * grid barrier follows each back substitution (the next pass reads the
  * neighbouring workgroups' rows).  Observable sums are formed per
  * workgroup and added in workgroup order after the launch; a non-finite

@@ -1161,7 +1161,8 @@ struct SpanCtx {
 // per workgroup: reduced S, C (coupling to the left super block), dS (pp
 // each), g and dg (p each), complex
 __host__ __device__ inline long long xch_entry(int p) { return 3LL * p * p + 2LL * p; }
-// per super block j: Dinv, M, C (pp each) and z (p), complex
+// per super block j: Dinv, M, C (pp each) and z (p), complex; G + 1 entries
+// per workgroup (the last one for the join of the two-sided elimination)
 __host__ __device__ inline long long gfac_entry(int p) { return 3LL * p * p + p; }
 
 __device__ __forceinline__ void grid_barrier() { cooperative_groups::this_grid().sync(); }
@@ -1420,72 +1421,173 @@ __device__ __forceinline__ void pass_reduced_cr(const SysDesc& sd, int tid, FT* 
             if (nlev == 0 && ext && j == 0 && i < p) st_c(xw, 3 * pp + (unsigned)(p + i), ld_c(blk(0), 3 * pp + (unsigned)(p + i)));
         }
         grid_barrier();
-        if (wv == 0) {
-            const BlkStage<FT, 1> S1{lds + CrLds<FT>::kG, i, j};
-            const int G = sc.G;
-            auto gf = [&](int jj) { return sc.gfac + 2 * (long long)jj * gfac_entry(p); };
-            // forward: Delta_j = diag_j - M_j C_j^T, M_j = C_j Delta_{j-1}^-1,
-            // z_j = rhs_j - M_j z_{j-1}
-            cplx<FT> dprev = zero, zprev = zero;  // Delta_{j-1}^-1 (entry), z_{j-1} (row)
-            for (int jj = 0; jj < G; ++jj) {
-                const FT* x0 = xe(jj);
-                const bool more = jj + 1 < G;
-                cplx<FT> rhs = csel(i < p, ld_c(x0, 3 * pp + ii), zero);
-                if (more) rhs = cadd(rhs, csel(i < p, ld_c(xe(jj + 1), 3 * pp + (unsigned)p + ii), zero));
-                cplx<FT> m = zero;
+        // The G super blocks: Sigma_j = S_j + dS_{j+1}, g_j = gs_j + dg_{j+1},
+        // T[j][j-1] = C_j.  Eliminated from both ends at once (h = G / 2):
+        // wave 0 forward over j = 0 .. h-1,
+        //   M_j = C_j Delta_{j-1}^-1,  Delta_j = Sigma_j - M_j C_j^T,  z_j = g_j - M_j z_{j-1},
+        // wave 1 backward over j = G-1 .. h,
+        //   N_j = C_{j+1}^T G_{j+1}^-1,  G_j = Sigma_j - N_j C_{j+1},  w_j = g_j - N_j w_{j+1},
+        // wave 1 joins at h (M_h = C_h Delta_{h-1}^-1, Delta'_h = G_h - M_h C_h^T,
+        // x_h = Delta'_h^-1 (w_h - M_h z_{h-1})), then each wave substitutes
+        // outwards only as far as this workgroup's two super blocks (g - 1,
+        // g).  Every workgroup repeats the same operations, so the values it
+        // writes for a super block are those of its neighbours, bit for bit.
+        // Per-workgroup storage (gf): Delta^-1 or G^-1, M or N, C_j, z or w;
+        // entry G holds the join's M_h and x_h.  Inputs are loaded one block
+        // ahead (they come from the other workgroups' fresh writes).
+        const int G = sc.G, h = G / 2;
+        auto gf = [&](int jj) { return sc.gfac + 2 * (long long)jj * gfac_entry(p); };
+        const int need_lo = sc.g > 0 ? sc.g - 1 : 0, need_hi = sc.g;
+        if (wv <= 1) {
+            const BlkStage<FT, 1> S1{lds + CrLds<FT>::kG + wv * CrLds<FT>::kWaveStage, i, j};
+            const int dir = wv == 0 ? 1 : -1;
+            const int j0 = wv == 0 ? 0 : G - 1;
+            const int cnt = wv == 0 ? h : G - h;
+            struct SupIn {
+                cplx<FT> rhs, a, cc, cct, cs, m;
+            };
+            // block jj's inputs; the coupling to the block eliminated before it
+            // is C_jj (forward) or C_{jj+1}^T (backward; C_{jj+1} kept as cct's
+            // transpose partner in cc)
+            auto sup_load = [&](int t) {
+                const int tt = t < cnt ? t : cnt - 1;
+                const int jc = j0 + dir * tt;
+                const bool more = jc + 1 < G;
+                const bool has_prev = dir > 0 ? jc > 0 : more;
+                const FT* x0 = xe(jc);
+                const FT* x1 = xe(more ? jc + 1 : jc);
+                const FT* xc = dir > 0 ? x0 : x1;  // the coupling's owner
+                SupIn r;
+                r.rhs = cadd(csel(i < p, ld_c(x0, 3 * pp + ii), zero),
+                             csel(i < p && more, ld_c(x1, 3 * pp + (unsigned)p + ii), zero));
                 if (factor) {
-                    cplx<FT> a[1] = {csel(valid, ld_c(x0, ee), ident)};
-                    if (more) a[0] = cadd(a[0], csel(valid, ld_c(xe(jj + 1), 2 * pp + ee), zero));
-                    const cplx<FT> cj = csel(valid && jj > 0, ld_c(x0, pp + ee), zero);
-                    if (jj > 0) {
-                        cplx<FT> cc[1] = {cj}, dd[1] = {dprev}, mm[1];
-                        S1.put(0, 0, cc[0]);
-                        S1.put(1, 0, dd[0]);
+                    r.a = cadd(csel(valid, ld_c(x0, ee), ident), csel(valid && more, ld_c(x1, 2 * pp + ee), zero));
+                    // forward: cc = C_jj, cct = C_jj^T; backward: cc = C_{jj+1}^T, cct = C_{jj+1}
+                    r.cc = csel(valid && has_prev, ld_c(xc, pp + (dir > 0 ? ee : et)), zero);
+                    r.cct = csel(valid && has_prev, ld_c(xc, pp + (dir > 0 ? et : ee)), zero);
+                    r.cs = csel(valid && jc > 0, ld_c(x0, pp + ee), zero);  // C_jj
+                    r.m = zero;
+                } else {
+                    r.a = r.cc = r.cct = r.cs = zero;
+                    r.m = csel(valid && has_prev, ld_c(gf(jc), pp + ee), zero);
+                }
+                return r;
+            };
+            cplx<FT> dprev = zero, zprev = zero;  // previous block's inverse (entry), z or w (row)
+            SupIn cur = sup_load(0);
+            for (int t = 0; t < cnt; ++t) {
+                const SupIn nxt = sup_load(t + 1);
+                const int jj = j0 + dir * t;
+                const bool raw = wv == 1 && jj == h;  // kept uninverted for the join
+                cplx<FT> m = cur.m;
+                if (factor) {
+                    cplx<FT> a[1] = {cur.a};
+                    if (t > 0) {
+                        cplx<FT> mm[1], mc[1];
+                        S1.put(0, 0, cur.cc);
+                        S1.put(1, 0, dprev);
                         wave_lds_sync();
                         stage_prod<p, FT, 1>(S1, 0, 1, mm);
                         wave_lds_sync();
                         m = mm[0];
-                        // a -= M C^T: stage M and C^T
                         S1.put(0, 0, m);
-                        S1.put(1, 0, csel(valid, ld_c(x0, pp + et), zero));
+                        S1.put(1, 0, cur.cct);
                         wave_lds_sync();
-                        cplx<FT> mc[1];
                         stage_prod<p, FT, 1>(S1, 0, 1, mc);
                         wave_lds_sync();
                         a[0] = csub(a[0], mc[0]);
                     }
-                    stage_inverse<p, FT, 1>(S1, 0, a);
+                    if (!raw) stage_inverse<p, FT, 1>(S1, 0, a);
                     FT* gj = gf(jj);
                     if (valid) {
                         st_c(gj, ee, a[0]);
                         st_c(gj, pp + ee, m);
-                        st_c(gj, 2 * pp + ee, cj);
+                        st_c(gj, 2 * pp + ee, cur.cs);  // C_jj, for the substitution
                     }
                     dprev = a[0];
-                } else {
-                    m = csel(valid && jj > 0, ld_c(gf(jj), pp + ee), zero);
                 }
-                const cplx<FT> z = csub(rhs, row_sum(cmul(m, colv(zprev))));
+                const cplx<FT> z = csub(cur.rhs, row_sum(cmul(m, colv(zprev))));
                 if (j == 0 && i < p) st_c(gf(jj), 3 * pp + (unsigned)i, z);
                 zprev = z;
+                cur = nxt;
             }
-            // backward: x_j = Delta_j^-1 (z_j - C_{j+1}^T x_{j+1}), down to
-            // this workgroup's left neighbour
-            cplx<FT> xnext = zero;  // x_{j+1}, row layout
-            const int jlo = sc.g > 0 ? sc.g - 1 : 0;
-            for (int jj = G - 1; jj >= jlo; --jj) {
-                const FT* gj = gf(jj);
-                cplx<FT> w = csel(i < p, ld_c(gj, 3 * pp + ii), zero);
-                if (jj + 1 < G) {
-                    const cplx<FT> ct = csel(valid, ld_c(gf(jj + 1), 2 * pp + et), zero);  // C_{j+1}^T
-                    w = csub(w, row_sum(cmul(ct, colv(xnext))));
+        }
+        __syncthreads();
+        FT* gj_join = gf(G);
+        if (wv == 1) {
+            const BlkStage<FT, 1> S1{lds + CrLds<FT>::kG + CrLds<FT>::kWaveStage, i, j};
+            const FT* gh = gf(h);
+            const cplx<FT> ch = csel(valid && h > 0, ld_c(xe(h), pp + ee), zero);
+            const cplx<FT> cht = csel(valid && h > 0, ld_c(xe(h), pp + et), zero);
+            const cplx<FT> dv = csel(valid && h > 0, ld_c(gf(h > 0 ? h - 1 : 0), ee), zero);
+            const cplx<FT> zp = csel(i < p && h > 0, ld_c(gf(h > 0 ? h - 1 : 0), 3 * pp + ii), zero);
+            const cplx<FT> wh = csel(i < p, ld_c(gh, 3 * pp + ii), zero);
+            cplx<FT> mh, dinv;
+            if (factor) {
+                cplx<FT> mm[1], mc[1];
+                S1.put(0, 0, ch);
+                S1.put(1, 0, dv);
+                wave_lds_sync();
+                stage_prod<p, FT, 1>(S1, 0, 1, mm);
+                wave_lds_sync();
+                mh = mm[0];
+                S1.put(0, 0, mh);
+                S1.put(1, 0, cht);
+                wave_lds_sync();
+                stage_prod<p, FT, 1>(S1, 0, 1, mc);
+                wave_lds_sync();
+                cplx<FT> a[1] = {csub(csel(valid, ld_c(gh, ee), ident), mc[0])};
+                stage_inverse<p, FT, 1>(S1, 0, a);
+                dinv = a[0];
+                if (valid) {
+                    st_c(gf(h), ee, dinv);
+                    st_c(gj_join, pp + ee, mh);
                 }
-                const cplx<FT> dv = csel(valid, ld_c(gj, ee), ident);
-                const cplx<FT> x = row_sum(cmul(dv, colv(w)));
-                if (jj == sc.g || jj == sc.g - 1) {
-                    if (j == 0 && i < p) st_c(x_base, (unsigned)(((jj + 1) * Pl - 1) * p + i), x);
-                }
-                xnext = x;
+            } else {
+                mh = csel(valid, ld_c(gj_join, pp + ee), zero);
+                dinv = csel(valid, ld_c(gh, ee), ident);
+            }
+            const cplx<FT> zr = csub(wh, row_sum(cmul(mh, colv(zp))));
+            const cplx<FT> xh = row_sum(cmul(dinv, colv(zr)));
+            if (j == 0 && i < p) st_c(gj_join, 3 * pp + (unsigned)i, xh);
+            if ((h == need_lo || h == need_hi) && j == 0 && i < p)
+                st_c(x_base, (unsigned)(((h + 1) * Pl - 1) * p + i), xh);
+        }
+        __syncthreads();
+        if (wv <= 1) {
+            // x_j = Delta_j^-1 (z_j - C_{j+1}^T x_{j+1}), j = h-1 .. need_lo   (wave 0)
+            // x_j = G_j^-1 (w_j - C_j x_{j-1}),       j = h+1 .. need_hi   (wave 1)
+            const int dir = wv == 0 ? -1 : 1;
+            const int j0 = h + dir;
+            const int cnt = wv == 0 ? (need_lo < h ? h - need_lo : 0) : (need_hi > h ? need_hi - h : 0);
+            struct BkIn {
+                cplx<FT> w, cp, dv;
+            };
+            auto bk_load = [&](int t) {
+                const int tt = t < cnt ? t : (cnt > 0 ? cnt - 1 : 0);
+                const int jc = j0 + dir * tt;
+                const int jq = jc >= 0 && jc < G ? jc : h;
+                const FT* gjq = gf(jq);
+                BkIn r;
+                r.w = csel(i < p, ld_c(gjq, 3 * pp + ii), zero);
+                // the coupling to the block solved before: C_{j+1}^T (stored
+                // as C of block j+1, read transposed) or C_j
+                r.cp = wv == 0 ? csel(valid, ld_c(gf(jq + 1 <= G - 1 ? jq + 1 : jq), 2 * pp + et), zero)
+                               : csel(valid, ld_c(gjq, 2 * pp + ee), zero);
+                r.dv = csel(valid, ld_c(gjq, ee), ident);
+                return r;
+            };
+            cplx<FT> xprev = csel(i < p, ld_c(gj_join, 3 * pp + ii), zero);  // x_h
+            BkIn bc = bk_load(0);
+            for (int t = 0; t < cnt; ++t) {
+                const BkIn bn = bk_load(t + 1);
+                const int jj = j0 + dir * t;
+                const cplx<FT> w = csub(bc.w, row_sum(cmul(bc.cp, colv(xprev))));
+                const cplx<FT> x = row_sum(cmul(bc.dv, colv(w)));
+                if ((jj == need_lo || jj == need_hi) && j == 0 && i < p)
+                    st_c(x_base, (unsigned)(((jj + 1) * Pl - 1) * p + i), x);
+                xprev = x;
+                bc = bn;
             }
         }
         __syncthreads();

@@ -219,10 +219,10 @@ int span_plan(int N, int p, int G, int Pl, Plan* out) {
     if (Pl <= 0) Pl = 64;
     if (Pl > kMaxChunks4) Pl = kMaxChunks4;
     if (G <= 0) {
-        // chunks of about 2p + 6 rows (measured on the 30 007-row H2+ chain:
-        // 64 chunks per workgroup and 20-row chunks beat 32, 128 or 256
-        // chunks per workgroup and 15- or 19-row chunks)
-        const double Lt = 2.0 * p + 6.0;
+        // chunks of about 2p + 1 rows (measured on the 30 007-row H2+ chain:
+        // 64 chunks per workgroup and 15- to 16-row chunks beat 32, 48, 96,
+        // 128 or 256 chunks per workgroup and 17- to 21-row chunks)
+        const double Lt = 2.0 * p + 1.0;
         G = (int)std::lround(N / (Lt * Pl));
         if (G > kMaxSpan) G = kMaxSpan;
     }
@@ -445,7 +445,7 @@ tdsez_status launch_propagate(BatchData* b, double* psi, const double* E, double
                             "the extended kernels run on one workgroup: tdsez_system_set(sys, \"workgroups\", 1)");
         const int G = b->span_G, p = b->plan[0].p, ns = b->desc[0].nsteps;
         const size_t xch_b = 2 * sizeof(double) * (size_t)(2 * G * xch_entry(p));
-        const size_t gfac_b = 2 * sizeof(double) * (size_t)((long long)G * G * gfac_entry(p));
+        const size_t gfac_b = 2 * sizeof(double) * (size_t)((long long)G * (G + 1) * gfac_entry(p));
         if (!b->d_xch) {
             TDSEZ_HIP_TRY(hipMalloc(&b->d_xch, xch_b));
             TDSEZ_HIP_TRY(hipMalloc(&b->d_gfac, gfac_b));

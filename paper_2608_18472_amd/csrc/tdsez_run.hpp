@@ -75,7 +75,7 @@ __device__ __forceinline__ void run_system(const KernelArgs& ka, const SysDesc& 
         sc.Pl = sd.Pl;
         sc.g = wg;
         sc.G = sd.G;
-        sc.gfac = (FT*)ka.gfac + 2 * (long long)wg * sd.G * gfac_entry(PP);
+        sc.gfac = (FT*)ka.gfac + 2 * (long long)wg * (sd.G + 1) * gfac_entry(PP);
     }
     auto span_ctx = [&]() {
         SpanCtx<FT> c = sc;
