@@ -35,8 +35,8 @@ CALIB_COPY_BYTES = 512 * 2 ** 20
 # (FETCH_SIZE, then WRITE_SIZE) scaled by the copy calibration; valid only for
 # the kernel sources they were taken on (sha256 of the listed files) and the
 # default --split.  See profiles/propagate_kernel_fp32_batch1024_pmc.md.
-TRAFFIC = {"sources_sha256": "638f37703f96266d1b8c74acee0693ec23df8ebe60a7687712691a65f8311534",
-           "bytes_per_launch": 2.4218e+13, "split": 160}
+TRAFFIC = {"sources_sha256": "a163664c17044e59169bae6512628882f5621b1f95ac76500fed0d7bb614687b",
+           "bytes_per_launch": 2.4252e+13, "split": 160}
 # HBM bytes of one FP32 3D operator launch (apply3_kernel<3, float>, 97^3), from the
 # two counter runs of profiles/apply3_kernel_hydrogen97_3d.md, for the sources listed.
 TRAFFIC_3D = {"sources_sha256": "3e452734ff4fe17aecf937eda575755b0443e1f9b93102b006896c8dac460f2a",
