@@ -277,21 +277,45 @@ def quad_grid_2d(breaks_x, breaks_y, nq):
     return np.meshgrid(xq, yq)
 
 
-def assemble_2d(breaks_x, breaks_y, order, nq, V):
+def assemble_2d(breaks_x, breaks_y, order, nq, V, dVx=None):
     """Matrices of the 2D problem: per-axis S, T, D half bands (1D assembly
     with V = 0) and the potential stencil V2 (orc_assemble_v2) for the
-    callable V(x, y)."""
+    callable V(x, y); with dVx(x, y) also the stencil G2 of dV/dx (the same
+    Galerkin integral with the derivative sampled), for the acceleration of
+    section IV.A (eq. pdm_acceleration with m = 1: a = -<dV/dx> - E <1>)."""
     bx, by = _f64(breaks_x), _f64(breaks_y)
     mx = assemble(bx, order, nq)
     my = assemble(by, order, nq)
     X, Y = quad_grid_2d(bx, by, nq)
-    Vq = _f64(V(X, Y))
     Nx, Ny, p = mx["N"], my["N"], mx["p"]
     w2 = 2 * p + 1
-    V2 = np.zeros((Ny * Nx, w2, w2))
-    _check(lib().orc_assemble_v2(_p(bx), len(bx), _p(by), len(by), order, nq, _p(Vq), _p(V2)), "assemble_v2")
-    return {"Nx": Nx, "Ny": Ny, "p": p, "Sx": mx["S"], "Tx": mx["T"], "Dx": mx["D"], "Sy": my["S"],
-            "Ty": my["T"], "V2": V2}
+
+    def stencil(f):
+        out = np.zeros((Ny * Nx, w2, w2))
+        _check(lib().orc_assemble_v2(_p(bx), len(bx), _p(by), len(by), order, nq, _p(_f64(f(X, Y))), _p(out)),
+               "assemble_v2")
+        return out
+
+    m2 = {"Nx": Nx, "Ny": Ny, "p": p, "Sx": mx["S"], "Tx": mx["T"], "Dx": mx["D"], "Sy": my["S"],
+          "Ty": my["T"], "V2": stencil(V)}
+    if dVx is not None:
+        m2["G2"] = stencil(dVx)
+    return m2
+
+
+def stencil_apply_2d(m2, st, c):
+    """(M c) for a matrix given as its (2p+1)^2 stencil per row, st[row, dy+p,
+    dx+p] = M[row][(iy+dy) Nx + ix+dx] (the V2 / G2 layout), c of shape
+    (Ny, Nx) or flat; a plain sum over the offsets of a zero-padded copy."""
+    Nx, Ny, p = m2["Nx"], m2["Ny"], m2["p"]
+    cc = np.zeros((Ny + 2 * p, Nx + 2 * p), dtype=np.complex128)
+    cc[p:p + Ny, p:p + Nx] = np.asarray(c).reshape(Ny, Nx)
+    s4 = st.reshape(Ny, Nx, 2 * p + 1, 2 * p + 1)
+    out = np.zeros((Ny, Nx), dtype=np.complex128)
+    for dy in range(-p, p + 1):
+        for dx in range(-p, p + 1):
+            out += s4[:, :, dy + p, dx + p] * cc[p + dy:p + dy + Ny, p + dx:p + dx + Nx]
+    return out.reshape(-1)
 
 
 def apply_2d(m2, c, a, b, Ebar, with_V=True):
@@ -359,17 +383,22 @@ def cn_solve_2d(m2, rhs, alpha, Ebar, x0=None, fdm=None, tol=1e-14, maxit=500):
 def propagate_2d(m2, psi0, E, dt, nsteps, tol=1e-14):
     """Crank-Nicolson propagation in 2D (section V.B with Ebar_n =
     (E_n + E_{n+1})/2): returns obs[n] = (nu_n, d_n) = (c^H S2 c, Re c^H D2 c)
-    for n = 0..nsteps and the final state (shape (Ny, Nx))."""
+    for n = 0..nsteps, and with G2 in m2 (assemble_2d with dVx) a third
+    column, the acceleration a_n = -Re c^H G2 c - E_n nu_n (section IV.A,
+    constant mass), and the final state (shape (Ny, Nx))."""
     alpha = 0.5 * dt
     c = _c128(np.asarray(psi0).reshape(-1)).copy()
     fdm = _fdm_factors(m2)
-    obs = np.zeros((nsteps + 1, 2))
+    acc = "G2" in m2
+    obs = np.zeros((nsteps + 1, 3 if acc else 2))
     for n in range(nsteps + 1):
         Sc = apply_2d(m2, c, 1.0, 0.0, 0.0, with_V=False)
         # D2 c = (T2 + V2 + 1 * D2) c - (T2 + V2) c
         Dc = apply_2d(m2, c, 0.0, 1.0, 1.0) - apply_2d(m2, c, 0.0, 1.0, 0.0)
         obs[n, 0] = np.real(np.vdot(c, Sc))
         obs[n, 1] = np.real(np.vdot(c, Dc))
+        if acc:
+            obs[n, 2] = -np.real(np.vdot(c, stencil_apply_2d(m2, m2["G2"], c))) - E[n] * obs[n, 0]
         if n == nsteps:
             break
         Eb = 0.5 * (E[n] + E[n + 1])

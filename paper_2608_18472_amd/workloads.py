@@ -296,6 +296,7 @@ class System2D:
     dt: float = 0.0
     nsteps: int = 0
     meta: dict = field(default_factory=dict)
+    dVx: Optional[Callable] = None  # dV/dx (x, y), vectorised: the acceleration observable
 
     @property
     def p(self):
@@ -318,7 +319,8 @@ def config4(n=512, nsteps=None, L=120.0, order=6):
     br = breaks_uniform(L, n - p + 2)
     E, ns, Tp = sin2_pulse(0.05, 0.057, 4, 0.05, nsteps)
     return System2D("soft-coulomb-2d", br, br.copy(), order, lambda x, y: -1.0 / np.sqrt(x * x + y * y + 1.0),
-                    10, E, 0.05, ns, {"E0": 0.05, "omega": 0.057, "Tp": Tp})
+                    10, E, 0.05, ns, {"E0": 0.05, "omega": 0.057, "Tp": Tp},
+                    lambda x, y: x / (x * x + y * y + 1.0) ** 1.5)
 
 
 @dataclass

@@ -128,3 +128,61 @@ def test_norm_is_conserved_under_the_field():
     E = 0.3 * np.sin(0.4 * np.arange(31))
     obs, _ = O.propagate_2d(m2, psi0, E, 0.1, 30)
     assert np.abs(obs[:, 0] / obs[0, 0] - 1.0).max() < 1e-12
+
+
+def test_stencil_apply_matches_dense_stencil_matrix():
+    """The oracle's offset-sum product with a stencil (used for the
+    acceleration) equals the dense matrix built entry by entry."""
+    bx = np.linspace(-3.0, 3.0, 9)
+    by = W.breaks_symexp(4.0, 8, 1.1)
+    m2 = O.assemble_2d(bx, by, 5, 6, lambda x, y: -1.0 / np.sqrt(x * x + y * y + 1.0),
+                       dVx=lambda x, y: x / (x * x + y * y + 1.0) ** 1.5)
+    rng = np.random.default_rng(7)
+    n = m2["Nx"] * m2["Ny"]
+    c = rng.normal(size=n) + 1j * rng.normal(size=n)
+    for key in ("V2", "G2"):
+        mk = dict(m2, V2=m2[key])
+        S2, H2 = dense_2d(mk)
+        _, H0 = dense_2d(mk, with_V=False)
+        ref = (H2 - H0) @ c
+        got = O.stencil_apply_2d(m2, m2[key], c)
+        assert np.abs(got - ref).max() < 1e-13 * np.abs(ref).max(), key
+
+
+def test_force_stencil_of_the_oscillator_is_the_dipole_matrix():
+    """V = (x^2 + y^2)/2 has dV/dx = x: the stencil of dV/dx (2D quadrature)
+    equals D2 = Dx (x) Sy from the 1D assemblies, so the acceleration of a
+    field-free oscillator is -d (and -d - E nu with a field)."""
+    bx = W.breaks_symexp(5.0, 10, 1.3)
+    by = np.linspace(-4.0, 4.5, 9)
+    m2 = O.assemble_2d(bx, by, 4, 7, lambda x, y: 0.5 * (x * x + y * y), dVx=lambda x, y: x + 0.0 * y)
+    Dx, Sy = dense(m2["Dx"]), dense(m2["Sy"])
+    D2 = np.kron(Sy, Dx)
+    _, H2a = dense_2d(dict(m2, V2=m2["G2"]))
+    _, H0 = dense_2d(m2, with_V=False)
+    G2 = H2a - H0
+    assert np.abs(G2 - D2).max() < 1e-12 * np.abs(D2).max()
+
+
+def test_acceleration_is_the_second_derivative_of_the_dipole():
+    """Ehrenfest for constant mass (section IV.A): d''(t) = a(t) =
+    -<dV/dx> - E <1> in the complete-basis limit.  For a driven ground state
+    the second difference of the propagated dipole meets the acceleration
+    column to 1e-4 of its size on a refined basis, 40x closer than on a
+    coarse one (the Galerkin relation converges with the basis; a wrong sign
+    or a missing field term would stay off at order one)."""
+    V = lambda x, y: -1.0 / np.sqrt(x * x + y * y + 1.0)
+    dV = lambda x, y: x / (x * x + y * y + 1.0) ** 1.5
+    errs = []
+    for nb in (12, 18):
+        bx, by = np.linspace(-7.0, 7.0, nb), np.linspace(-6.0, 6.0, nb - 2)
+        m2 = O.assemble_2d(bx, by, 4, 8, V, dVx=dV)
+        S2, H2 = dense_2d(m2)
+        ev, vec = sl.eigh(H2, S2, subset_by_index=[0, 0])
+        dt, ns = 0.01, 100
+        E = 0.2 * np.sin(2.0 * dt * np.arange(ns + 1) + 0.3)
+        obs, _ = O.propagate_2d(m2, vec[:, 0].astype(np.complex128), E, dt, ns)
+        d, a = obs[:, 1], obs[:, 2]
+        d2 = (d[2:] - 2.0 * d[1:-1] + d[:-2]) / (dt * dt)
+        errs.append(np.abs(d2 - a[1:-1]).max() / np.abs(a).max())
+    assert errs[1] < 3e-4 and errs[1] < errs[0] / 20.0, errs
