@@ -343,7 +343,7 @@ def run_2d(args):
 
     torch.cuda.set_device(0)
     sd = W.config4()
-    g = T.assemble_workload_2d(sd)
+    g = T.assemble_workload_2d(sd, with_force=False)  # norm and dipole only
     # initial state: product of the per-axis 1D ground states (library eigensolver)
     vecs = []
     for br in (sd.breaks_x, sd.breaks_y):

@@ -409,11 +409,16 @@ typedef struct tdsez_system2d_s* tdsez_system2d;
 /* Assemble a 2D problem on the device.  V_q: host FP64 samples of V at the
  * tensor grid of the per-axis quadrature points (tdsez_quad_points of each
  * axis), V_q[qy * nqx + qx], nqx = (nbx-1)*nq, nqy = (nby-1)*nq (copied).
+ * dVx_q: samples of dV/dx at the same points, or NULL; with them the force
+ * stencil G2[(iy,ix),(jy,jx)] = sum_q wx wy dV/dx N_ix N_jx N_iy N_jy is
+ * assembled too, for the acceleration of section IV.A (eq.
+ * pdm_acceleration with m = 1): a = -Re c^H G2 c - E c^H S2 c.
  * Also computes, once, the per-axis generalised eigendecompositions
  * T Q = S Q Lambda used by the preconditioner.  Needs at least 2p+1
- * unknowns per axis; order <= 8.  Synchronous. */
+ * unknowns per axis; order <= 8.  Synchronous.  EINVAL for a non-finite
+ * sample. */
 tdsez_status tdsez_assemble_2d(const double* breaks_x, int nbx, const double* breaks_y, int nby, int order, int nq,
-                               const double* V_q, tdsez_system2d* out);
+                               const double* V_q, const double* dVx_q, tdsez_system2d* out);
 tdsez_status tdsez_system2d_size(tdsez_system2d s, int* nx, int* ny, int* halfbw);
 /* Potential matrix as a (2p+1)^2 stencil per row (host FP64, caller-owned):
  * out[row*(2p+1)^2 + (dy+p)*(2p+1) + (dx+p)] = V2[row][(iy+dy)*Nx + ix+dx]. */
@@ -430,8 +435,10 @@ tdsez_status tdsez_get_v2(tdsez_system2d s, double* host_out);
  *     the operator and of P, made by the first such call) to a relative
  *     1e-5, and adds e to x in FP64; at most maxit sweeps per step.
  * Either way the result meets the same FP64 residual bound; ENOCONV when
- * the bound is not met.  obs: TDSEZ_OBS_NORM | TDSEZ_OBS_DIPOLE (x dipole);
- * obs_out[n*3 + 0..2] = (nu_n, d_n, 0) on the device, always FP64.
+ * the bound is not met.  obs: TDSEZ_OBS_NORM | TDSEZ_OBS_DIPOLE (x dipole)
+ * | TDSEZ_OBS_ACCEL (x acceleration, for a system assembled with dVx_q;
+ * EUNSUPPORTED otherwise); obs_out[n*3 + 0..2] = (nu_n, d_n, a_n) on the
+ * device (0 for an unrequested column), always FP64.
  * Enqueued on `stream`, but the host waits for the iteration scalars, so
  * the call returns when done. */
 tdsez_status tdsez_propagate_2d(tdsez_system2d s, double* psi, const double* E, double dt, int nsteps,

@@ -286,6 +286,78 @@ __global__ __launch_bounds__(kStencilThreads, 4) void apply_kernel(
     }
 }
 
+// Per-tile partial sums of Re c^H G2 c for a half stencil G2 (the force
+// stencil of dV/dx, section IV.A): the potential stage of apply_kernel with
+// G2 in place of V2, then Re(conj(c_i) (G2 c)_i) summed over the tile
+// (FP64, fixed order).
+template <int PP>
+__global__ __launch_bounds__(kStencilThreads) void form2_kernel(int Nx, int Ny, const double* __restrict__ G2h,
+                                                                const double* __restrict__ cre,
+                                                                const double* __restrict__ cim,
+                                                                double* __restrict__ part) {
+    constexpr int TX = TileShape<double>::TX, TY = TileShape<double>::TY;
+    constexpr int K = 2 * PP + 1;
+    constexpr int WX = TX + 2 * PP, WY = TY + 2 * PP;
+    __shared__ double tre[WY][WX], tim[WY][WX];
+    __shared__ double red[kStencilThreads];
+    const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+    const int ix = x0 + tx, iy = y0 + ty;
+    const long long plane = (long long)Nx * Ny;
+    for (int t = threadIdx.x; t < WX * WY; t += kStencilThreads) {
+        const int ly = t / WX, lx = t % WX;
+        const int gy = y0 + ly - PP, gx = x0 + lx - PP;
+        double vr = 0, vi = 0;
+        if (gy >= 0 && gy < Ny && gx >= 0 && gx < Nx) {
+            vr = cre[(long long)gy * Nx + gx];
+            vi = cim[(long long)gy * Nx + gx];
+        }
+        tre[ly][lx] = vr;
+        tim[ly][lx] = vi;
+    }
+    __syncthreads();
+    const int ixc = ix < Nx ? ix : Nx - 1, iyc = iy < Ny ? iy : Ny - 1;
+    const long long row = (long long)iyc * Nx + ixc;
+    const int cy = ty + PP, cx = tx + PP;
+    double gr = 0, gi = 0;
+    {
+        const double v0 = G2h[row];
+        gr += v0 * tre[cy][cx];
+        gi += v0 * tim[cy][cx];
+#pragma unroll
+        for (int e = 1; e <= PP; ++e) {
+            const double* __restrict__ pl = G2h + (long long)half_index(PP, 0, e) * plane;
+            const int jx = ixc - e < 0 ? 0 : ixc - e;
+            const double vd = pl[row];
+            const double vm = pl[(long long)iyc * Nx + jx];
+            gr += vd * tre[cy][cx + e] + vm * tre[cy][cx - e];
+            gi += vd * tim[cy][cx + e] + vm * tim[cy][cx - e];
+        }
+    }
+#pragma unroll 1
+    for (int dy = 1; dy <= PP; ++dy) {
+        const double* __restrict__ pl = G2h + (long long)half_index(PP, dy, -PP) * plane;
+        const long long mrow = (long long)(iyc - dy < 0 ? 0 : iyc - dy) * Nx;
+#pragma unroll
+        for (int kx = 0; kx < K; ++kx) {
+            const int e = kx - PP;
+            int jx = ixc - e;
+            jx = jx < 0 ? 0 : (jx >= Nx ? Nx - 1 : jx);
+            const double vd = pl[(long long)kx * plane + row];
+            const double vm = pl[(long long)kx * plane + mrow + jx];
+            gr += vd * tre[cy + dy][cx + e] + vm * tre[cy - dy][cx - e];
+            gi += vd * tim[cy + dy][cx + e] + vm * tim[cy - dy][cx - e];
+        }
+    }
+    red[threadIdx.x] = (ix < Nx && iy < Ny) ? tre[cy][cx] * gr + tim[cy][cx] * gi : 0.0;
+    __syncthreads();
+    for (int s = kStencilThreads / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[(long long)blockIdx.y * gridDim.x + blockIdx.x] = red[0];
+}
+
 }  // namespace
 }  // namespace tdsez
 
@@ -295,6 +367,8 @@ struct tdsez_system2d_s {
     SystemData ax, ay;         // per-axis 1D matrices (V = 0, m = 1)
     int Nx = 0, Ny = 0, p = 0, order = 0, nq = 0;
     double* d_V2h = nullptr;   // half stencil, [offset][row]
+    double* d_G2h = nullptr;   // force stencil of dV/dx (half, [offset][row]), or nullptr
+    double* d_acc_part = nullptr;  // per-tile partials of Re c^H G2 c
     double* d_Qx = nullptr;    // generalised eigenvectors (column-major), T Q = S Q Lambda
     double* d_Qy = nullptr;
     double* d_lx = nullptr;
@@ -325,6 +399,8 @@ void free2d(tdsez_system2d_s* s) {
     (void)hipFree(s->ax.d_H0);
     (void)hipFree(s->ay.d_H0);
     (void)hipFree(s->d_V2h);
+    (void)hipFree(s->d_G2h);
+    (void)hipFree(s->d_acc_part);
     (void)hipFree(s->d_Qx);
     (void)hipFree(s->d_Qy);
     (void)hipFree(s->d_lx);
@@ -394,6 +470,20 @@ struct Op2D {
     }
     int nblk_precond() const {
         return ((s->Nx + kGemmTile - 1) / kGemmTile) * ((s->Ny + kGemmTile - 1) / kGemmTile);
+    }
+    int accel(int in, double* part, hipStream_t stream) {
+        if (!s->d_G2h) return 0;
+        const dim3 g = stencil_grid<double>(s->Nx, s->Ny);
+        switch (s->p) {
+#define TD2_CASE(PV_)                                                                                        \
+    case PV_:                                                                                                \
+        form2_kernel<PV_><<<g, kStencilThreads, 0, stream>>>(s->Nx, s->Ny, s->d_G2h, cw.re(in), cw.im(in), part); \
+        break;
+            TD2_CASE(1) TD2_CASE(2) TD2_CASE(3) TD2_CASE(4) TD2_CASE(5) TD2_CASE(6) TD2_CASE(7)
+#undef TD2_CASE
+            default: return 0;
+        }
+        return (int)(g.x * g.y);
     }
     void apply(int in, int yv, double wr, double wi, double ar, double ai, double br, double bi, double Eb, int outv,
                double* obsp, const double* flag, hipStream_t stream, double* dotp = nullptr) {
@@ -471,7 +561,7 @@ struct Op2D {
 extern "C" {
 
 tdsez_status tdsez_assemble_2d(const double* breaks_x, int nbx, const double* breaks_y, int nby, int order, int nq,
-                               const double* V_q, tdsez_system2d* out) {
+                               const double* V_q, const double* dVx_q, tdsez_system2d* out) {
     if (!out) return fail(TDSEZ_EINVAL, "out is NULL");
     *out = nullptr;
     if (!breaks_x || !breaks_y || !V_q) return fail(TDSEZ_EINVAL, "NULL argument");
@@ -492,6 +582,8 @@ tdsez_status tdsez_assemble_2d(const double* breaks_x, int nbx, const double* br
     const long long nqx = (long long)(nbx - 1) * nq, nqy = (long long)(nby - 1) * nq;
     for (long long i = 0; i < nqx * nqy; ++i)
         if (!std::isfinite(V_q[i])) return fail(TDSEZ_EINVAL, "V_q[%lld] is not finite", i);
+    for (long long i = 0; dVx_q && i < nqx * nqy; ++i)
+        if (!std::isfinite(dVx_q[i])) return fail(TDSEZ_EINVAL, "dVx_q[%lld] is not finite", i);
     auto* s = new tdsez_system2d_s();
     s->Nx = Nx;
     s->Ny = Ny;
@@ -538,6 +630,11 @@ tdsez_status tdsez_assemble_2d(const double* breaks_x, int nbx, const double* br
         H(hipMalloc(&ddB, sizeof(double) * (nqx > nqy ? nqx : nqy) * (p + 1)));
         H(hipMalloc(&dVq, sizeof(double) * nqx * nqy));
         H(hipMalloc(&s->d_V2h, sizeof(double) * (size_t)half_count(p) * Nx * Ny));
+        if (dVx_q) {
+            H(hipMalloc(&s->d_G2h, sizeof(double) * (size_t)half_count(p) * Nx * Ny));
+            const dim3 g64 = stencil_grid<double>(Nx, Ny);
+            H(hipMalloc(&s->d_acc_part, sizeof(double) * (size_t)g64.x * g64.y));
+        }
         if (he == hipSuccess) {
             H(hipMemcpy(dbx, breaks_x, sizeof(double) * nbx, hipMemcpyHostToDevice));
             H(hipMemcpy(dby, breaks_y, sizeof(double) * nby, hipMemcpyHostToDevice));
@@ -551,6 +648,13 @@ tdsez_status tdsez_assemble_2d(const double* breaks_x, int nbx, const double* br
             basis_kernel<<<grid_for(nqy), 256>>>(dby, nby, p, nq, dyq, dBy, ddB);
             v2_kernel<<<4096, 256>>>(Nx, Ny, p, nq, nbx - 1, nby - 1, dbx, dby, dgw, dBx, dBy, dVq, s->d_V2h);
             H(hipGetLastError());
+            if (dVx_q) {
+                // the force stencil: the same integral with dV/dx sampled
+                H(hipDeviceSynchronize());
+                H(hipMemcpy(dVq, dVx_q, sizeof(double) * nqx * nqy, hipMemcpyHostToDevice));
+                v2_kernel<<<4096, 256>>>(Nx, Ny, p, nq, nbx - 1, nby - 1, dbx, dby, dgw, dBx, dBy, dVq, s->d_G2h);
+                H(hipGetLastError());
+            }
             H(hipDeviceSynchronize());
         }
         clean();
@@ -654,7 +758,9 @@ tdsez_status tdsez_propagate_2d(tdsez_system2d s, double* psi, const double* E, 
     if (!s || !psi || !E) return fail(TDSEZ_EINVAL, "NULL argument");
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(TDSEZ_EINVAL, "dt must be > 0");
     if (nsteps < 0) return fail(TDSEZ_EINVAL, "nsteps < 0");
-    if (obs & ~3u) return fail(TDSEZ_EINVAL, "2D observables: TDSEZ_OBS_NORM and TDSEZ_OBS_DIPOLE only");
+    if (obs & ~7u) return fail(TDSEZ_EINVAL, "unknown observable bits 0x%x", obs);
+    if ((obs & TDSEZ_OBS_ACCEL) && !s->d_G2h)
+        return fail(TDSEZ_EUNSUPPORTED, "the acceleration needs dV/dx (dVx_q at tdsez_assemble_2d)");
     if (obs && !obs_out) return fail(TDSEZ_EINVAL, "obs requested but obs_out is NULL");
     if (prec != TDSEZ_FP64 && prec != TDSEZ_FP32_REFINED) return fail(TDSEZ_EINVAL, "unknown precision %d", (int)prec);
     if (!(tol > 0.0) || maxit < 1) return fail(TDSEZ_EINVAL, "tol must be > 0 and maxit >= 1");
@@ -670,6 +776,7 @@ tdsez_status tdsez_propagate_2d(tdsez_system2d s, double* psi, const double* E, 
     cw.sc = s->d_sc;
     cw.status = s->d_status;
     cw.obs_part = s->d_obs_part;
+    cw.acc_part = s->d_acc_part;
     cw.dpart = s->d_dpart;
     const dim3 sgrid = stencil_grid<double>(s->Nx, s->Ny);
     cw.nblk_obs = (int)(sgrid.x * sgrid.y);

@@ -526,6 +526,8 @@ struct Op3D {
         // the last contraction: x, over the rows of all planes
         return ((s->Nx + kGemmTile - 1) / kGemmTile) * ((s->Nz * s->Ny + kGemmTile - 1) / kGemmTile);
     }
+    // no force stencil in 3D (the acceleration is not offered there)
+    int accel(int, double*, hipStream_t) { return 0; }
     template <typename FT>
     void apply_t(const FT* const* b, const FT* V3pad, const FT* cr, const FT* ci, const FT* yr, const FT* yi, double wr,
                  double wi, double ar, double ai, double br, double bi, double Eb, FT* outr, FT* outi, double* obsp,

@@ -15,6 +15,9 @@
 //   precond(in, out, flag, stream, rzp): out = P^-1 in, P the separable
 //       part, with per-block partial sums of in^T out when rzp is given;
 //   nblk_apply(fp32), nblk_precond(): the number of those partial sums;
+//   accel(in, part, stream): per-block partial sums of Re c^H G c for the
+//       acceleration (G the force stencil of dV/dx); returns their number,
+//       0 when the system has no force stencil;
 // apply and precond return at once when *flag is set (the solve has
 // converged).
 // Complex vectors are planar (real plane, then imaginary plane).
@@ -369,28 +372,36 @@ __global__ __launch_bounds__(kGemmThreads) void fdm_gemm_kernel(
 
 // observables: sum the per-block partials of apply_kernel (fixed order per
 // thread, then a tree over the block: deterministic)
+// The observables of c_n from the operator's per-block partials (norm and
+// dipole) and, where the system has the force stencil G (apart != null), the
+// acceleration a = -Re c^H G c - E_n nu (section IV.A, constant mass).
 __global__ __launch_bounds__(kRedThreads) void obs_finish_kernel(const double* __restrict__ part, int nblk,
-                                                                 double* __restrict__ out, unsigned mask) {
-    __shared__ double a[kRedThreads], b[kRedThreads];
-    double nu = 0.0, d = 0.0;
+                                                                 const double* __restrict__ apart, int nblk_a,
+                                                                 double En, double* __restrict__ out,
+                                                                 unsigned mask) {
+    __shared__ double a[kRedThreads], b[kRedThreads], g[kRedThreads];
+    double nu = 0.0, d = 0.0, f = 0.0;
     for (int k = threadIdx.x; k < nblk; k += kRedThreads) {
         nu += part[2 * k];
         d += part[2 * k + 1];
     }
+    for (int k = threadIdx.x; apart && k < nblk_a; k += kRedThreads) f += apart[k];
     a[threadIdx.x] = nu;
     b[threadIdx.x] = d;
+    g[threadIdx.x] = f;
     __syncthreads();
     for (int s = kRedThreads / 2; s > 0; s >>= 1) {
         if (threadIdx.x < s) {
             a[threadIdx.x] += a[threadIdx.x + s];
             b[threadIdx.x] += b[threadIdx.x + s];
+            g[threadIdx.x] += g[threadIdx.x + s];
         }
         __syncthreads();
     }
     if (threadIdx.x == 0) {
         out[0] = (mask & TDSEZ_OBS_NORM) ? a[0] : 0.0;
         out[1] = (mask & TDSEZ_OBS_DIPOLE) ? b[0] : 0.0;
-        out[2] = 0.0;
+        out[2] = (apart && (mask & TDSEZ_OBS_ACCEL)) ? -g[0] - En * a[0] : 0.0;
     }
 }
 
@@ -655,6 +666,7 @@ struct CnWork {
     int* status = nullptr;    // 4 ints: latched code, step
     double* obs_part = nullptr;
     int nblk_obs = 0;         // per-block observable partials written by apply
+    double* acc_part = nullptr;  // per-block partials of Re c^H G c (op.accel), or nullptr
     double* dpart = nullptr;  // partials of the dot products fused into apply and the preconditioner
     double* re(int k) const { return w + (size_t)(2 * k) * n; }
     double* im(int k) const { return w + (size_t)(2 * k + 1) * n; }
@@ -737,9 +749,11 @@ tdsez_status cn_cocg_propagate(const CnWork& cw, Op& op, double* psi, const doub
         const double Eb = step < nsteps ? 0.5 * (Eh[step] + Eh[step + 1]) : Eh[step];
         // b = -i dt H c (and the observables of c)
         op.apply(kC, -1, 0.0, 0.0, 0.0, 0.0, 0.0, -2.0 * alpha, Eb, kB, cw.obs_part, nullptr, stream);
-        if (obs)
-            obs_finish_kernel<<<1, kRedThreads, 0, stream>>>(cw.obs_part, cw.nblk_obs, obs_out + 3 * (size_t)step,
-                                                             obs);
+        if (obs) {
+            const int na = (obs & TDSEZ_OBS_ACCEL) && cw.acc_part ? op.accel(kC, cw.acc_part, stream) : 0;
+            obs_finish_kernel<<<1, kRedThreads, 0, stream>>>(cw.obs_part, cw.nblk_obs, na ? cw.acc_part : nullptr, na,
+                                                             Eh[step], obs_out + 3 * (size_t)step, obs);
+        }
         if (step == nsteps) break;
         // A x = b, A = S + i a H, warm start from the previous increment: r = b - A x.
         // The refined path forms this first residual with the FP32 operator: its

@@ -67,7 +67,7 @@ def lib():
         "tdsez_set_projectors": [vp, i, dp],
         "tdsez_ext_columns": [vp, ip],
         "tdsez_adjoint_batched": [vp, vp, lp, vp, lp, dp, ip, i, u, vp, lp, vp, vp, i, vp],
-        "tdsez_assemble_2d": [dp, i, dp, i, i, i, dp, ctypes.POINTER(vp)],
+        "tdsez_assemble_2d": [dp, i, dp, i, i, i, dp, dp, ctypes.POINTER(vp)],
         "tdsez_system2d_size": [vp, ip, ip, ip],
         "tdsez_get_v2": [vp, dp],
         "tdsez_propagate_2d": [vp, vp, vp, d, i, i, u, vp, d, i, vp],
@@ -536,21 +536,25 @@ class System2D:
             self.handle = None
 
 
-def assemble_2d(breaks_x, breaks_y, order, nq, V_q):
+def assemble_2d(breaks_x, breaks_y, order, nq, V_q, dVx_q=None):
     bx, by = _f64(breaks_x), _f64(breaks_y)
     vq = _f64(V_q)
+    gq = None if dVx_q is None else _f64(dVx_q)
     h = ctypes.c_void_p()
-    _check(lib().tdsez_assemble_2d(_dptr(bx), len(bx), _dptr(by), len(by), order, nq, _dptr(vq), ctypes.byref(h)))
+    _check(lib().tdsez_assemble_2d(_dptr(bx), len(bx), _dptr(by), len(by), order, nq, _dptr(vq),
+                                   _dptr(gq) if gq is not None else None, ctypes.byref(h)))
     return System2D(h)
 
 
-def assemble_workload_2d(sysdef):
-    """Assemble a workloads.System2D: sample V on the tensor grid of the
-    library's own per-axis quadrature points."""
+def assemble_workload_2d(sysdef, with_force=True):
+    """Assemble a workloads.System2D: sample V (and dV/dx, when the
+    definition has it and with_force) on the tensor grid of the library's
+    own per-axis quadrature points."""
     xq = quad_points(sysdef.breaks_x, sysdef.nq)
     yq = quad_points(sysdef.breaks_y, sysdef.nq)
     X, Y = np.meshgrid(xq, yq)
-    return assemble_2d(sysdef.breaks_x, sysdef.breaks_y, sysdef.order, sysdef.nq, sysdef.V(X, Y))
+    g = sysdef.dVx(X, Y) if (with_force and sysdef.dVx is not None) else None
+    return assemble_2d(sysdef.breaks_x, sysdef.breaks_y, sysdef.order, sysdef.nq, sysdef.V(X, Y), g)
 
 
 def get_v2(sys2d):

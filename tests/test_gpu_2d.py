@@ -45,12 +45,12 @@ def product_ground_state(sd):
     return np.outer(vecs[1], vecs[0]).astype(np.complex128)
 
 
-def run_gpu_2d(sd, psi0, nsteps, tol=1e-13, prec=T.FP64, g=None):
+def run_gpu_2d(sd, psi0, nsteps, tol=1e-13, prec=T.FP64, g=None, obs=T.OBS_NORM | T.OBS_DIPOLE):
     g = g if g is not None else T.assemble_workload_2d(sd)
     psi = torch.from_numpy(psi0.reshape(-1).copy()).cuda()
     E = torch.from_numpy(np.asarray(sd.E[: nsteps + 1], np.float64).copy()).cuda()
     o = torch.zeros(3 * (nsteps + 1), dtype=torch.float64, device="cuda")
-    T.propagate_2d(g, psi, E, sd.dt, nsteps, prec, T.OBS_NORM | T.OBS_DIPOLE, o, tol=tol, maxit=300)
+    T.propagate_2d(g, psi, E, sd.dt, nsteps, prec, obs, o, tol=tol, maxit=300)
     steps, its, mx, sweeps = T.system2d_stats(g)
     say("prec %d: %d steps, %.2f Krylov iterations per step (max %d), %.2f refinement sweeps per step" % (
         prec, steps, its / max(steps, 1), mx, sweeps / max(steps, 1)))
@@ -147,7 +147,7 @@ def test_2d_invalid_arguments():
     psi = torch.zeros(g.Nx * g.Ny, dtype=torch.complex128, device="cuda")
     E = torch.zeros(3, dtype=torch.float64, device="cuda")
     o = torch.zeros(9, dtype=torch.float64, device="cuda")
-    for kw in ({"obs": 7}, {"tol": 0.0}, {"maxit": 0}, {"prec": 5}):
+    for kw in ({"obs": 8}, {"tol": 0.0}, {"maxit": 0}, {"prec": 5}):
         args = dict(prec=T.FP64, obs=3, obs_out=o, tol=1e-12, maxit=10)
         args.update(kw)
         with pytest.raises(T.TdsezError) as e:
@@ -197,3 +197,30 @@ def test_exhausted_iteration_budget_latches_enoconv(prec):
     # the same system with a sufficient budget converges
     psi = torch.from_numpy(psi0.reshape(-1).copy()).cuda()
     T.propagate_2d(g, psi, E, sd.dt, 4, prec, 3, o, tol=1e-13, maxit=100)
+
+
+@pytest.mark.parametrize("prec", [T.FP64, T.FP32_REFINED])
+def test_acceleration_matches_oracle(prec):
+    """The x acceleration a = -Re c^H G2 c - E nu (section IV.A, m = 1) from
+    the force stencil of dV/dx, on the small graded grid under the strong
+    field: all three series against the oracle (FP64 1e-10, FP32-refined
+    1e-8, the bars of the other 2D series); a system assembled without
+    dV/dx refuses the acceleration."""
+    ns = 120
+    sd = small_case(ns)
+    sd.dVx = lambda x, y: x / (x * x + y * y + 1.0) ** 1.5
+    psi0 = product_ground_state(sd)
+    m2 = O.assemble_2d(sd.breaks_x, sd.breaks_y, sd.order, sd.nq, sd.V, dVx=sd.dVx)
+    ref, cref = O.propagate_2d(m2, psi0, sd.E, sd.dt, ns, tol=1e-14)
+    got, cgot = run_gpu_2d(sd, psi0, ns, prec=prec, obs=T.OBS_ALL)
+    errs = [rel(got[:, k], ref[:, k]) for k in range(3)]
+    say("2D acceleration errors", prec, errs, "max |a|", np.abs(ref[:, 2]).max())
+    tol = 1e-10 if prec == T.FP64 else 1e-8
+    assert max(errs) < tol, errs
+    g0 = T.assemble_workload_2d(sd, with_force=False)
+    psi = torch.from_numpy(psi0.reshape(-1).copy()).cuda()
+    E = torch.from_numpy(np.asarray(sd.E[: ns + 1], np.float64).copy()).cuda()
+    o = torch.zeros(3 * (ns + 1), dtype=torch.float64, device="cuda")
+    with pytest.raises(T.TdsezError) as e:
+        T.propagate_2d(g0, psi, E, sd.dt, 2, prec, T.OBS_ALL, o)
+    assert e.value.status == 7
