@@ -160,6 +160,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--tune-ms", type=float, default=3000.0,
                     help="partition autotuner budget per precision (setup, untimed); 0 keeps the default rule")
+    ap.add_argument("--adjoint-waves", type=int, choices=[1, 2], default=2,
+                    help="adjoint: waves per system (2: every system on two waves)")
     ap.add_argument("--max-waves", type=int, choices=[2, 4], default=2,
                     help="batch1d: the most waves a --split system may run on (4: cyclic reduction of the "
                          "separator system for systems whose four-wave plan has more than 128 chunks)")
@@ -647,6 +649,9 @@ def run_adjoint(args):
     # every system's ground state in one launch (two-vector subspace
     # iteration: the double well's lowest doublet is split by 6e-5 Ha)
     T.ground_state_batched(b, psi, po, tol=1e-12, maxit=2000)
+    if args.adjoint_waves == 2:
+        # every system on two waves (N = 1500: 71 chunks), forward and adjoint
+        T.batch_split(b, [s.nsteps for s in defs], len(defs))
     Bt = torch.from_numpy(basis).cuda()
     dt = [s.dt for s in defs]
     ns = [s.nsteps for s in defs]
@@ -723,6 +728,7 @@ def run_adjoint(args):
                         "Fourier pulses with 64 amplitudes (8-cycle 0.3 eV sin^2 fit + 10% seeded noise), "
                         "20000 steps, J = harmonic yield of orders 15-35, sqrt(Nt) checkpoints",
             "systems": len(defs),
+            "waves_per_system": args.adjoint_waves,
             "dof_steps": dofsteps,
             "forward_s": t_f,
             "backward_s": t_b,

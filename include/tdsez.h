@@ -278,8 +278,9 @@ tdsez_status tdsez_batch_chunks(tdsez_batch b, int* chunks_out);
  * unchanged and the calls stay capturable into a graph.  Results equal the
  * one-wave results up to rounding.  count = 0 restores one wave per system.
  * Re-packs the batch and clears the autotuner's plans (run tdsez_autotune
- * afterwards to tune the new plan; it keeps the marks).  The adjoint refuses
- * a batch with multi-wave systems (EUNSUPPORTED).  nsteps: host array of
+ * afterwards to tune the new plan; it keeps the marks).  The adjoint runs
+ * two-wave systems on two waves and refuses a batch with four-wave systems
+ * (EUNSUPPORTED).  nsteps: host array of
  * nsys step counts (may be NULL when count = 0).  Synchronous.  EINVAL for
  * count outside 0..nsys or a negative step count. */
 tdsez_status tdsez_batch_split(tdsez_batch b, const int* nsteps, int count);
@@ -387,9 +388,12 @@ tdsez_status tdsez_propagate_ext(tdsez_system sys, double* psi, const double* E,
  * (0: ceil(sqrt(nsteps))), so the cost is about three propagations and the
  * memory (nsteps/ckpt_stride + ckpt_stride + 1) states per system (device
  * workspace owned by the batch, grown on demand).  FP64 only
- * (TDSEZ_FP32_REFINED: EUNSUPPORTED).  Asynchronous on `stream`; device
- * failures are latched as for propagation.  Uses the batch's working state,
- * so it must not overlap a propagation of the same batch. */
+ * (TDSEZ_FP32_REFINED: EUNSUPPORTED).  One workgroup per system, of two
+ * waves for the systems that tdsez_batch_split put on two waves (their
+ * launch runs beside the one-wave launch, as for propagation); a batch with
+ * four-wave systems is refused (EUNSUPPORTED).  Asynchronous on `stream`;
+ * device failures are latched as for propagation.  Uses the batch's working
+ * state, so it must not overlap a propagation of the same batch. */
 tdsez_status tdsez_adjoint_batched(tdsez_batch b, const double* psi0_packed, const long* psi_off,
                                    const double* E_packed, const long* E_off, const double* dt,
                                    const int* nsteps, tdsez_precision prec, unsigned obs,

@@ -19,7 +19,9 @@
 // recomputed into a segment buffer before its adjoint steps run, so the
 // cost is about three forward propagations and the memory
 // (nsteps/ck + ck + 1) states per system.  Everything runs in FP64, one
-// wave per system, all systems of the batch in one launch.
+// wave per system, or two for the systems marked for two waves
+// (tdsez_batch_split; their separator system solved from both ends), all
+// systems of one workgroup size in one launch.
 #include <algorithm>
 #include <cmath>
 
@@ -49,6 +51,7 @@ struct AdjArgs {
     double* dJdpsi0;      // per system at psi_off, or nullptr
     int* status;
     long long state_total;  // complex elements of one whole-batch state
+    int order_off;          // first entry of order read by this launch
 };
 
 // copy the system's interleaved state (L x LS complex, at state_off of a
@@ -193,8 +196,29 @@ __device__ __forceinline__ void pass_adjoint_update(const SysDesc& sd, int k, co
     part[1] = mexp;
 }
 
+template <int PP, int NW>
+__device__ __forceinline__ void adj_reduced(const SysDesc& sd, int tid, double* red, double* zl) {
+    if constexpr (NW == 2) pass_reduced2<PP, double>(sd, tid, red, true, zl);
+    else pass_reduced<PP, double>(sd, tid, red, true, zl);
+}
+
+// sum over the workgroup of wave-uniform values (wave order, so every wave
+// gets the same bits)
+template <int NW>
+__device__ __forceinline__ double wg_sum(double v, int tid) {
+    v = wave_sum(v);
+    if constexpr (NW == 2) {
+        __shared__ double buf[2];
+        if ((tid & (kWave - 1)) == 0) buf[tid / kWave] = v;
+        __syncthreads();
+        v = buf[0] + buf[1];
+        __syncthreads();
+    }
+    return v;
+}
+
 // one forward step n -> n+1 in place on st (FP64, no refinement)
-template <int PP>
+template <int PP, int NW>
 __device__ __forceinline__ void forward_step(const AdjArgs& ka, const SysDesc& sd, int lane, double alpha, double Ebar,
                                              double* zl) {
     const bool active = lane < sd.P;
@@ -206,13 +230,13 @@ __device__ __forceinline__ void forward_step(const AdjArgs& ka, const SysDesc& s
         pass_schur<PP, double>(sd, lane, ka.fac, ka.red);
     }
     __syncthreads();
-    pass_reduced<PP, double>(sd, lane, ka.red, true, zl);
+    adj_reduced<PP, NW>(sd, lane, ka.red, zl);
     __syncthreads();
     if (active) pass_backsub<PP, double>(sd, lane, ka.band, ka.st, nullptr, true, ka.fac, ka.red, alpha, Ebar);
     __syncthreads();
 }
 
-template <int PP>
+template <int PP, int NW>
 __device__ __forceinline__ void run_adjoint(const AdjArgs& ka, const SysDesc& sd, int sidx, double* zl) {
     const int lane = threadIdx.x;
     const bool active = lane < sd.P;
@@ -256,13 +280,13 @@ __device__ __forceinline__ void run_adjoint(const AdjArgs& ka, const SysDesc& sd
             }
         }
     }
-    for (int n = lane; n <= ns; n += kWave) gE[n] = 0.0;
+    for (int n = lane; n <= ns; n += NW * kWave) gE[n] = 0.0;
     __syncthreads();
     // forward sweep keeping checkpoints 0, ck, 2 ck, ...
     copy_state(sd, lane, ka.st, state_at(ckpt, 0));
     __syncthreads();
     for (int n = 0; n < ns; ++n) {
-        forward_step<PP>(ka, sd, lane, alpha, ebar(n), zl);
+        forward_step<PP, NW>(ka, sd, lane, alpha, ebar(n), zl);
         if ((n + 1) % ck == 0 && n + 1 < ns) {
             copy_state(sd, lane, ka.st, state_at(ckpt, (n + 1) / ck));
             __syncthreads();
@@ -274,7 +298,7 @@ __device__ __forceinline__ void run_adjoint(const AdjArgs& ka, const SysDesc& sd
         if (active)
             pass_adjoint_update<PP>(sd, lane, ka.band, ka.wsol, ka.st, nullptr, ka.lam, false, alpha, Es[ns],
                                     Es[ns], jn(ns), jd(ns), ja(ns), part);
-        const double me = wave_sum(part[1]);
+        const double me = wg_sum<NW>(part[1], lane);
         if (lane == 0) gE[ns] -= ja(ns) * me;
         __syncthreads();
     }
@@ -286,7 +310,7 @@ __device__ __forceinline__ void run_adjoint(const AdjArgs& ka, const SysDesc& sd
         copy_state(sd, lane, state_at(ckpt, sgi), state_at(seg, 0));
         __syncthreads();
         for (int n = n0; n < n1; ++n) {
-            forward_step<PP>(ka, sd, lane, alpha, ebar(n), zl);
+            forward_step<PP, NW>(ka, sd, lane, alpha, ebar(n), zl);
             copy_state(sd, lane, ka.st, state_at(seg, n - n0 + 1));
             __syncthreads();
         }
@@ -299,7 +323,7 @@ __device__ __forceinline__ void run_adjoint(const AdjArgs& ka, const SysDesc& sd
                 pass_schur<PP, double>(sd, lane, ka.fac, ka.red);
             }
             __syncthreads();
-            pass_reduced<PP, double>(sd, lane, ka.red, true, zl);
+            adj_reduced<PP, NW>(sd, lane, ka.red, zl);
             __syncthreads();
             if (active)
                 pass_backsub<PP, double>(sd, lane, ka.band, ka.wsol, nullptr, true, ka.fac, ka.red, alpha, Eb,
@@ -311,8 +335,8 @@ __device__ __forceinline__ void run_adjoint(const AdjArgs& ka, const SysDesc& sd
                 pass_adjoint_update<PP>(sd, lane, ka.band, ka.wsol, state_at(seg, n - n0),
                                         state_at(seg, n - n0 + 1), ka.lam, true, alpha, Eb, Es[n], jn(n),
                                         jd(n), ja(n), part);
-            const double di = wave_sum(part[0]);
-            const double me = wave_sum(part[1]);
+            const double di = wg_sum<NW>(part[0], lane);
+            const double me = wg_sum<NW>(part[1], lane);
             if (!isfinite(di) || !isfinite(me)) {
                 if (lane == 0) latch(ka.status, TDSEZ_ENONFINITE, sidx, n);
                 return;
@@ -338,22 +362,26 @@ __device__ __forceinline__ void run_adjoint(const AdjArgs& ka, const SysDesc& sd
     }
 }
 
-__global__ __launch_bounds__(kWave) void adjoint_kernel(AdjArgs ka) {
+template <int NW>
+__device__ __forceinline__ void dispatch_adjoint(const AdjArgs& ka) {
     // the separator recurrence's right-hand-side vector (P * p complex)
-    __shared__ double zl[2 * kMaxP * kMaxChunks];
-    const int sidx = ka.order[blockIdx.x];
+    __shared__ double zl[2 * kMaxP * kWave * NW];
+    const int sidx = ka.order[ka.order_off + blockIdx.x];
     const SysDesc sd = ka.descs[sidx];
     switch (sd.p) {
-        case 1: run_adjoint<1>(ka, sd, sidx, zl); break;
-        case 2: run_adjoint<2>(ka, sd, sidx, zl); break;
-        case 3: run_adjoint<3>(ka, sd, sidx, zl); break;
-        case 4: run_adjoint<4>(ka, sd, sidx, zl); break;
-        case 5: run_adjoint<5>(ka, sd, sidx, zl); break;
-        case 6: run_adjoint<6>(ka, sd, sidx, zl); break;
-        case 7: run_adjoint<7>(ka, sd, sidx, zl); break;
+        case 1: run_adjoint<1, NW>(ka, sd, sidx, zl); break;
+        case 2: run_adjoint<2, NW>(ka, sd, sidx, zl); break;
+        case 3: run_adjoint<3, NW>(ka, sd, sidx, zl); break;
+        case 4: run_adjoint<4, NW>(ka, sd, sidx, zl); break;
+        case 5: run_adjoint<5, NW>(ka, sd, sidx, zl); break;
+        case 6: run_adjoint<6, NW>(ka, sd, sidx, zl); break;
+        case 7: run_adjoint<7, NW>(ka, sd, sidx, zl); break;
         default: break;
     }
 }
+
+__global__ __launch_bounds__(kWave) void adjoint_kernel(AdjArgs ka) { dispatch_adjoint<1>(ka); }
+__global__ __launch_bounds__(2 * kWave) void adjoint2_kernel(AdjArgs ka) { dispatch_adjoint<2>(ka); }
 
 }  // namespace
 
@@ -397,7 +425,7 @@ tdsez_status launch_adjoint(BatchData* b, const double* psi0, const double* E, c
         b->seg_elems = seg_total;
     }
     if (tdsez_status st = upload_descriptors(b, stream)) return st;
-    AdjArgs ka;
+    AdjArgs ka{};
     ka.descs = b->d_desc;
     ka.order = b->d_order;
     ka.band = b->d_band64;
@@ -417,8 +445,30 @@ tdsez_status launch_adjoint(BatchData* b, const double* psi0, const double* E, c
     ka.dJdpsi0 = dJdpsi0;
     ka.status = b->d_status;
     ka.state_total = state_total;
-    adjoint_kernel<<<nsys, kWave, 0, stream>>>(ka);
-    TDSEZ_HIP_TRY(hipGetLastError());
+    // two-wave systems first (entries 0..n2-1 of the order, caller's
+    // stream), the one-wave systems concurrently on the batch's side stream
+    // forked from and joined back into the caller's stream
+    const int n2 = b->nsplit, n1 = nsys - b->nsplit;
+    hipStream_t s1 = stream;
+    if (n2 > 0 && n1 > 0) {
+        TDSEZ_HIP_TRY(hipEventRecord(b->ev_fork, stream));
+        TDSEZ_HIP_TRY(hipStreamWaitEvent(b->side, b->ev_fork, 0));
+        s1 = b->side;
+    }
+    if (n2 > 0) {
+        ka.order_off = 0;
+        adjoint2_kernel<<<n2, 2 * kWave, 0, stream>>>(ka);
+        TDSEZ_HIP_TRY(hipGetLastError());
+    }
+    if (n1 > 0) {
+        ka.order_off = n2;
+        adjoint_kernel<<<n1, kWave, 0, s1>>>(ka);
+        TDSEZ_HIP_TRY(hipGetLastError());
+    }
+    if (n2 > 0 && n1 > 0) {
+        TDSEZ_HIP_TRY(hipEventRecord(b->ev_join, b->side));
+        TDSEZ_HIP_TRY(hipStreamWaitEvent(stream, b->ev_join, 0));
+    }
     return TDSEZ_OK;
 }
 

@@ -7,7 +7,9 @@ observable series, FP32-refined 1e-5 on the series.  The two-wave launch
 runs on the caller's stream beside a one-wave launch on an internal side
 stream, so a graph captured from the call must replay to the eager result
 bit for bit, and mixed batches must keep the per-system bookkeeping
-(profile rows, chunk counts) in system order.
+(profile rows, chunk counts) in system order.  The adjoint runs the
+two-wave systems on two waves and returns the one-wave batch's gradient to
+rounding.
 """
 import gc
 import sys
@@ -104,7 +106,7 @@ def test_two_wave_systems_match_oracle(prec):
     assert np.array_equal(T.batch_chunks(b), one)
 
 
-def test_two_wave_autotune_and_adjoint_refusal():
+def test_two_wave_autotune_and_adjoint():
     ns = 40
     defs = _mixed_batch(ns, seed=6)
     b = T.batch_create([T.assemble_workload(s) for s in defs])
@@ -126,11 +128,22 @@ def test_two_wave_autotune_and_adjoint_refusal():
     T.batch_status(b)
     _check(defs, refs, psi, po, obs, eo, ns, 1e-10, 1e-10)
     if flags.sum() > 0:
-        dJ = torch.ones_like(obs)
-        dE = torch.zeros_like(E)
-        with pytest.raises(T.TdsezError) as e:
-            T.adjoint_batched(b, psi, po, E, eo, dts, [ns] * len(defs), T.OBS_DIPOLE, dJ, oo, dE)
-        assert e.value.status == 7
+        # the adjoint runs the two-wave systems on two waves: the gradient
+        # equals the one-wave batch's to rounding
+        psi_in, _, _, _, _, _ = T.pack_batch_inputs(defs, psi0s)
+        dJ = torch.from_numpy(np.random.default_rng(9).normal(size=obs.numel())).cuda()
+        dE2 = torch.zeros_like(E)
+        T.adjoint_batched(b, psi_in, po, E, eo, dts, [ns] * len(defs), T.OBS_ALL, dJ, oo, dE2)
+        T.batch_status(b)
+        b1 = T.batch_create([T.assemble_workload(s) for s in defs])
+        dE1 = torch.zeros_like(E)
+        T.adjoint_batched(b1, psi_in, po, E, eo, dts, [ns] * len(defs), T.OBS_ALL, dJ, oo, dE1)
+        T.batch_status(b1)
+        g1, g2 = dE1.cpu().numpy(), dE2.cpu().numpy()
+        for i in range(len(defs)):
+            sl_ = slice(eo[i], eo[i] + ns + 1)
+            say("adjoint system", i, "two-wave" if flags[i] else "one-wave", rel(g2[sl_], g1[sl_]))
+            assert rel(g2[sl_], g1[sl_]) < 1e-9, i
     with pytest.raises(T.TdsezError) as e:
         T.batch_split(b, [ns] * len(defs), len(defs) + 1)
     assert e.value.status == 1
