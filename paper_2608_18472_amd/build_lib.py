@@ -41,8 +41,8 @@ def build(verbose=False, jobs=8):
         if p.wait() != 0:
             raise RuntimeError("hipcc failed on %s" % s)
     tmp = LIB + ".tmp%d" % os.getpid()
-    # rocBLAS (per-axis GEMMs of the 2D preconditioner) and rocSOLVER (its
-    # one-off generalised eigendecompositions)
+    # rocSOLVER (the one-off generalised eigendecompositions of the 2D/3D
+    # per-axis bands) and the rocBLAS handle it runs on
     cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs + [
         "-L/opt/rocm/lib", "-lrocblas", "-lrocsolver", "-Wl,-rpath,/opt/rocm/lib"]
     if verbose:

@@ -45,6 +45,7 @@ static tdsez_status check_breaks(const double* breaks, int nbreaks) {
 static void free_batch_device(BatchData* b) {
     (void)hipFree(b->d_band64);
     (void)hipFree(b->d_band32);
+    (void)hipFree(b->d_bandlo);
     (void)hipFree(b->d_state);
     (void)hipFree(b->d_dtot);
     (void)hipFree(b->d_rhs);
@@ -68,6 +69,7 @@ static void free_batch_device(BatchData* b) {
     b->d_c0 = nullptr;
     b->d_band64 = nullptr;
     b->d_band32 = nullptr;
+    b->d_bandlo = nullptr;
     b->d_state = nullptr;
     b->d_dtot = nullptr;
     b->d_rhs = nullptr;

@@ -32,6 +32,11 @@ constexpr double kRule1 = 0.6, kRule2 = 0.3, kRule4 = 0.15;
 // the complex absorbing potential), V, K (velocity), Q (a_Q form) for the
 // extended per-step series.
 constexpr int kNumMats = 9;
+// The refinement residual reads S, H0 and D as their FP32 roundings hi with
+// a signed 8-bit code q each: entry = hi (1 + q kLoScale), within
+// |hi| kLoScale / 2 of the FP64 value (|FP64 - hi| <= 2^-24 |hi|, so
+// |q| <= 128, clamped to 127).
+constexpr double kLoScale = 0x1p-31;
 enum { kMatS = 0, kMatH0 = 1, kMatD = 2, kMatG = 3, kMatMi = 4, kMatW = 5, kMatV = 6, kMatK = 7, kMatQ = 8 };
 // Largest number of projection states of the population series.
 constexpr int kMaxPop = 8;
@@ -145,6 +150,10 @@ struct BatchData {
     long long band_elems = 0, state_elems = 0, fac_elems64 = 0, red_elems64 = 0;
     double* d_band64 = nullptr;
     float* d_band32 = nullptr;
+    // 8-bit corrections of the FP32 S, H0, D bands (refinement residual):
+    // per system 3 * state_off words in, [row][S, H0, D][column], byte d =
+    // diagonal d
+    unsigned long long* d_bandlo = nullptr;
     double* d_state = nullptr;       // interleaved complex128 states
     double* d_dtot = nullptr;        // increment of the current step (refinement sweeps)
     void* d_rhs = nullptr;           // right-hand side of the current step (FP64 or FP32)
@@ -210,6 +219,8 @@ struct KernelArgs {
     void* xch;                 // exchanged super-block data, two buffers (FT)
     void* gfac;                // per workgroup: factors of the super-block system (FT)
     double* obs_part;          // per step and workgroup: norm, dipole, acceleration parts
+    // refinement residual: corrections of the FP32 S, H0, D bands
+    const unsigned long long* bandlo;
 };
 
 // ---------------------------------------------------------------- kernels

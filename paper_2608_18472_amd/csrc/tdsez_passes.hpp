@@ -1799,16 +1799,28 @@ __device__ __forceinline__ void pass_backsub(const SysDesc& sd, int k, const FT*
     for (int t = 0; t < PP; ++t) update(m + t, xr[t], sepc[t], sepd[t]);
 }
 
+// FP64 band entry of the refinement residual from its FP32 rounding and the
+// 8-bit code of diagonal d in `codes` (see kLoScale).
+__device__ __forceinline__ double band_entry(float hi, unsigned long long codes, int d) {
+    const int q = (int)(signed char)(unsigned char)(codes >> (8 * d));
+    return (double)hi * fma((double)q, kLoScale, 1.0);
+}
+
 // Pass C (refinement sweep): residual of the current iterate in FP64,
 //   r = B c_n - A c = -S dtot - i a H (2 c - dtot),   dtot = c - c_n,
-// from the FP64 bands S, H0, D (so the sweeps converge to the FP64
-// Crank-Nicolson step), then forward substitution with the stored factor
-// rows (yhat, and the chunk's separator right-hand sides yR, gT).
+// from S, H0, D to within 2^-32 of their FP64 entries (the FP32 bands and
+// an 8-bit correction per entry: 5 instead of 8 bytes), so the sweeps
+// converge to the Crank-Nicolson step of bands that differ from the FP64
+// ones by less than 2.4e-10 relative, then forward substitution with the
+// stored factor rows (yhat, and the chunk's separator right-hand sides
+// yR, gT).  The absorber W (extended kernels) is read in FP64.
 template <int PP, typename FT, bool XT = false>
 __device__ __forceinline__ void pass_residual(const SysDesc& sd, int k, const FT* __restrict__ band,
-                              const double* __restrict__ band64, const double* __restrict__ st,
+                              const double* __restrict__ band64, const unsigned long long* __restrict__ bandlo,
+                              const double* __restrict__ st,
                               const double* __restrict__ dtot, FT* __restrict__ fac,
                               FT* __restrict__ red, double alpha, double Ebar, double nrm[2]) {
+    static_assert(sizeof(FT) == 4, "the refinement residual belongs to the FP32 factorisation");
     const bool cap = XT && sd.cap != 0;
     constexpr int NM = kNumMats;
     constexpr int IT = 2 * PP + 2;
@@ -1818,6 +1830,7 @@ __device__ __forceinline__ void pass_residual(const SysDesc& sd, int k, const FT
     const int kk = col - 1;
     const FT* __restrict__ bnd = band + sd.band_off;
     const double* __restrict__ bnd64 = band64 + sd.band_off;
+    const unsigned long long* __restrict__ blo = bandlo + 3 * sd.state_off;
     const double* __restrict__ cst = st + 2 * sd.state_off;
     const double* __restrict__ dst = dtot + 2 * sd.state_off;
     FT* __restrict__ fc = fac + 2 * sd.fac_off;
@@ -1856,7 +1869,8 @@ __device__ __forceinline__ void pass_residual(const SysDesc& sd, int k, const FT
     // streamed row r (0 <= r < L + p; rows >= L are the next chunk's halo),
     // loaded one row ahead of its use
     struct RowIn {
-        double bS[PP + 1], bH[PP + 1], bD[PP + 1];
+        float bS[PP + 1], bH[PP + 1], bD[PP + 1];
+        unsigned long long qS, qH, qD;
         double bW[XT ? PP + 1 : 1];
         cplx<double> c, dd;
     };
@@ -1866,13 +1880,17 @@ __device__ __forceinline__ void pass_residual(const SysDesc& sd, int k, const FT
         const int lr = own ? r : r - L;
         const unsigned cc = (unsigned)(own ? col : col + 1);
         const unsigned rb = (unsigned)lr * rowstride + cc;
+        const unsigned lb = (unsigned)lr * (unsigned)(3 * LS) + cc;
         RowIn in;
 #pragma unroll
         for (int d = 0; d <= PP; ++d) {
-            in.bS[d] = bnd64[rb + (unsigned)((0 * (PP + 1) + d) * LS)];
-            in.bH[d] = bnd64[rb + (unsigned)((1 * (PP + 1) + d) * LS)];
-            in.bD[d] = bnd64[rb + (unsigned)((2 * (PP + 1) + d) * LS)];
+            in.bS[d] = bnd[rb + (unsigned)((0 * (PP + 1) + d) * LS)];
+            in.bH[d] = bnd[rb + (unsigned)((1 * (PP + 1) + d) * LS)];
+            in.bD[d] = bnd[rb + (unsigned)((2 * (PP + 1) + d) * LS)];
         }
+        in.qS = blo[lb];
+        in.qH = blo[lb + (unsigned)LS];
+        in.qD = blo[lb + 2u * (unsigned)LS];
         if constexpr (XT) {
 #pragma unroll
             for (int d = 0; d <= PP; ++d) in.bW[d] = cap ? bnd64[rb + (unsigned)((kMatW * (PP + 1) + d) * LS)] : 0.0;
@@ -1884,9 +1902,12 @@ __device__ __forceinline__ void pass_residual(const SysDesc& sd, int k, const FT
     };
     // count: the completed row r - p is a row of this chunk (r >= p)
     auto stream_row = [&](const RowIn& in, bool own, bool count) {
-        double h[PP + 1];
+        double h[PP + 1], sb[PP + 1];
 #pragma unroll
-        for (int d = 0; d <= PP; ++d) h[d] = in.bH[d] + Ebar * in.bD[d];
+        for (int d = 0; d <= PP; ++d) {
+            sb[d] = band_entry(in.bS[d], in.qS, d);
+            h[d] = band_entry(in.bH[d], in.qH, d) + Ebar * band_entry(in.bD[d], in.qD, d);
+        }
 #pragma unroll
         for (int d = 0; d < PP; ++d) {
             vw[d] = vw[d + 1];
@@ -1902,8 +1923,8 @@ __device__ __forceinline__ void pass_residual(const SysDesc& sd, int k, const FT
             for (int d = 0; d <= PP; ++d) {
                 hs.re += h[d] * vw[PP - d].re;
                 hs.im += h[d] * vw[PP - d].im;
-                ss.re += in.bS[d] * dw[PP - d].re;
-                ss.im += in.bS[d] * dw[PP - d].im;
+                ss.re += sb[d] * dw[PP - d].re;
+                ss.im += sb[d] * dw[PP - d].im;
             }
         }
         hacc[PP] = hs;
@@ -1912,8 +1933,8 @@ __device__ __forceinline__ void pass_residual(const SysDesc& sd, int k, const FT
         for (int d = 1; d <= PP; ++d) {
             hacc[PP - d].re += h[d] * vw[PP].re;
             hacc[PP - d].im += h[d] * vw[PP].im;
-            sacc[PP - d].re += in.bS[d] * dw[PP].re;
-            sacc[PP - d].im += in.bS[d] * dw[PP].im;
+            sacc[PP - d].re += sb[d] * dw[PP].re;
+            sacc[PP - d].im += sb[d] * dw[PP].im;
         }
         // completed residual of row r - p: -S dtot - a (W + i H) v
         double tr = -alpha * hacc[0].im, ti = alpha * hacc[0].re;  // i a H v

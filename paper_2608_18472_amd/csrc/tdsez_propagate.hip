@@ -140,6 +140,36 @@ __global__ void pack_band_kernel(BandSrc src, int N, int p, int P, int L, int LS
     }
 }
 
+// Signed 8-bit code of an FP64 band entry v against its FP32 rounding hi:
+// the q for which hi (1 + q kLoScale) is nearest to v.
+__device__ __forceinline__ int band_code(double v) {
+    const float hi = (float)v;
+    if (hi == 0.0f) return 0;
+    const double t = rint((v - (double)hi) / ((double)hi * kLoScale));
+    return (int)fmin(127.0, fmax(-127.0, t));
+}
+
+// Corrections of the FP32 S, H0, D bands for the refinement residual, from
+// the packed FP64 bands of one system: word (l, m, c) holds the codes of the
+// p + 1 diagonals of matrix m at row l, column c (byte d = diagonal d).
+__global__ void pack_lo_kernel(const double* __restrict__ b64, int p, int L, int LS,
+                               unsigned long long* __restrict__ lo) {
+    const long long total = (long long)L * 3 * LS;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+         e += (long long)gridDim.x * blockDim.x) {
+        const int col = (int)(e % LS);
+        const long long r = e / LS;
+        const int m = (int)(r % 3);  // kMatS, kMatH0, kMatD
+        const long long l = r / 3;
+        unsigned long long w = 0;
+        for (int d = 0; d <= p; ++d) {
+            const double v = b64[((l * kNumMats + m) * (p + 1) + d) * LS + col];
+            w |= (unsigned long long)(unsigned char)(signed char)band_code(v) << (8 * d);
+        }
+        lo[e] = w;
+    }
+}
+
 }  // namespace
 
 // Observables of a spanning system: the per-workgroup parts of every step
@@ -300,6 +330,7 @@ tdsez_status pack_bands(BatchData* b) {
     b->red_elems64 = roff;
     TDSEZ_HIP_TRY(hipMalloc(&b->d_band64, sizeof(double) * (size_t)boff));
     TDSEZ_HIP_TRY(hipMalloc(&b->d_band32, sizeof(float) * (size_t)boff));
+    TDSEZ_HIP_TRY(hipMalloc(&b->d_bandlo, sizeof(unsigned long long) * 3 * (size_t)soff));
     TDSEZ_HIP_TRY(hipMalloc(&b->d_state, 2 * sizeof(double) * (size_t)soff));
     // increments of the refinement sweeps; the halo columns stay zero
     TDSEZ_HIP_TRY(hipMalloc(&b->d_dtot, 2 * sizeof(double) * (size_t)soff));
@@ -342,6 +373,12 @@ tdsez_status pack_bands(BatchData* b) {
         pack_band_kernel<<<nb, th>>>(src, pl.N, pl.p, pl.P, pl.L, pl.LS, b->d_band64 + b->desc[s].band_off,
                                      b->d_band32 + b->desc[s].band_off);
         TDSEZ_HIP_TRY(hipGetLastError());
+        {
+            const long long nlo = 3LL * pl.L * pl.LS;
+            pack_lo_kernel<<<(int)std::min<long long>((nlo + th - 1) / th, 4096), th>>>(
+                b->d_band64 + b->desc[s].band_off, pl.p, pl.L, pl.LS, b->d_bandlo + 3 * b->desc[s].state_off);
+            TDSEZ_HIP_TRY(hipGetLastError());
+        }
         if (sy->npop > 0) {
             long long tp = (long long)sy->npop * pl.L * pl.LS;
             pack_proj_kernel<<<(int)std::min<long long>((tp + 255) / 256, 4096), 256>>>(
@@ -418,6 +455,7 @@ tdsez_status launch_propagate(BatchData* b, double* psi, const double* E, double
     ka.order = b->d_order;
     ka.order_off = 0;
     ka.band64 = b->d_band64;
+    ka.bandlo = b->d_bandlo;
     ka.st = b->d_state;
     ka.dtot = b->d_dtot;
     ka.rhs = b->d_rhs;
@@ -576,6 +614,7 @@ extern "C" tdsez_status tdsez_propagate_noalloc(tdsez_system sys_h, double* psi,
     const size_t o_st = take(2 * sizeof(double) * nstate), o_dtot = take(2 * sizeof(double) * nstate);
     const size_t o_rhs = take(2 * sizeof(double) * nstate), o_fac = take(2 * sizeof(double) * (nfac > 0 ? nfac : 1));
     const size_t o_red = take(2 * sizeof(double) * nred);
+    const size_t o_lo = take(sizeof(unsigned long long) * 3 * nstate);
     if (off > kNoallocBytes)
         return fail(TDSEZ_EINVAL, "no-alloc propagation: N = %d needs %zu bytes of scratch, the limit is %zu", sy->N,
                     off, kNoallocBytes);
@@ -603,6 +642,7 @@ extern "C" tdsez_status tdsez_propagate_noalloc(tdsez_system sys_h, double* psi,
     int* dstatus = dev_status ? dev_status : reinterpret_cast<int*>(base + o_status);
     double* b64 = reinterpret_cast<double*>(base + o_b64);
     float* b32 = reinterpret_cast<float*>(base + o_b32);
+    unsigned long long* lo = reinterpret_cast<unsigned long long*>(base + o_lo);
     double* st = reinterpret_cast<double*>(base + o_st);
     noalloc_setup_kernel<<<1, 64, 0, stream>>>(d, ddesc, dorder, dstatus);
     TDSEZ_HIP_TRY(hipGetLastError());
@@ -620,6 +660,9 @@ extern "C" tdsez_status tdsez_propagate_noalloc(tdsez_system sys_h, double* psi,
         const int nb = (int)std::min<long long>((nband + 255) / 256, 4096);
         pack_band_kernel<<<nb, 256, 0, stream>>>(src, pl.N, pl.p, pl.P, pl.L, pl.LS, b64, b32);
         TDSEZ_HIP_TRY(hipGetLastError());
+        pack_lo_kernel<<<(int)std::min<long long>((3 * nstate + 255) / 256, 4096), 256, 0, stream>>>(
+            b64, pl.p, pl.L, pl.LS, lo);
+        TDSEZ_HIP_TRY(hipGetLastError());
         dim3 grid((unsigned)std::min<long long>((nstate + 255) / 256, 1024), 1);
         pack_state_kernel<<<grid, 256, 0, stream>>>(ddesc, psi, st, nullptr);
         TDSEZ_HIP_TRY(hipGetLastError());
@@ -629,6 +672,7 @@ extern "C" tdsez_status tdsez_propagate_noalloc(tdsez_system sys_h, double* psi,
     ka.order = dorder;
     ka.order_off = 0;
     ka.band64 = b64;
+    ka.bandlo = lo;
     ka.st = st;
     ka.dtot = reinterpret_cast<double*>(base + o_dtot);
     ka.rhs = base + o_rhs;

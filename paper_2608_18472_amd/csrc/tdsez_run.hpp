@@ -201,10 +201,11 @@ __device__ __forceinline__ void run_system(const KernelArgs& ka, const SysDesc& 
         mark(4);
         // refinement sweeps exist for the FP32 factorisation only (FP64
         // launches pass refine = 0); FP64 code is built without them
-        for (int sweep = 0; sizeof(FT) == 4 && sweep < refine; ++sweep) {
+        if constexpr (sizeof(FT) == 4) for (int sweep = 0; sweep < refine; ++sweep) {
             double nrm[2] = {0.0, 0.0};
             if (active)
-                pass_residual<PP, FT, XT>(sd, lane, band, ka.band64, st, dtot, fac, red, alpha, Ebar, nrm);
+                pass_residual<PP, FT, XT>(sd, lane, band, ka.band64, ka.bandlo, st, dtot, fac, red, alpha, Ebar,
+                                          nrm);
             __syncthreads();
             mark(5);
             if (sweep + 1 == refine) {
