@@ -64,9 +64,14 @@ typedef enum tdsez_status {
  *     (right-hand side (B_n - A_n) c_n = -i dt H^{n+1/2} c_n formed in FP64,
  *     state accumulated in FP64), then runs `refine` iterative-refinement
  *     sweeps (default 1, see tdsez_batch_set): the residual
- *     B_n c_n - A_n c of the current iterate is formed in FP64 from the FP64
- *     bands and solved with the same FP32 factorisation, so the sweeps
- *     converge to the FP64 Crank-Nicolson step.  Without a sweep the FP32
+ *     B_n c_n - A_n c of the current iterate is formed in FP64 arithmetic
+ *     and solved with the same FP32 factorisation.  The residual reads S, H0
+ *     and D as their FP32 roundings hi with one signed 8-bit code q per
+ *     entry, entry = hi (1 + q 2^-31), q the nearest integer to
+ *     (v - hi) / (hi 2^-31) clamped to [-127, 127] for the FP64 entry v
+ *     (within 2^-32 |hi| of v; 5 bytes per entry read instead of 8), so
+ *     the sweeps converge to the Crank-Nicolson step of those bands; the
+ *     absorber W is read in FP64.  Without a sweep the FP32
  *     rounding of the factorisation acts like a perturbed mass matrix and
  *     the phase error grows linearly in time.  State, observables and time
  *     series stay FP64. */
@@ -225,7 +230,8 @@ tdsez_status tdsez_batch_create(const tdsez_system* sys, int nsys, tdsez_batch* 
 
 /* Tuning knobs of a batch.  key: "refine" (FP64-residual refinement sweeps
  * per step of TDSEZ_FP32_REFINED calls, integer 0..4, default 1; TDSEZ_FP64
- * calls run none), "refine_tol" (latch ENOCONV when the relative FP64
+ * calls run none; the residual's bands are described at
+ * TDSEZ_FP32_REFINED), "refine_tol" (latch ENOCONV when the relative FP64
  * residual ||r|| / sqrt(||S dx||^2 + ||a (W + i H) v||^2) entering the last
  * refinement sweep of a step exceeds the value, r = B_n c_n - A_n c,
  * dx = c - c_n, v = c + c_n, a = dt/2; default 1e-2; the propagation goes on,
