@@ -801,6 +801,14 @@ __device__ __forceinline__ void pass_schur(const SysDesc& sd, int k, const FT* _
     }
 }
 
+// orders one wave's LDS accesses (written entries become visible to the
+// wave's other lanes; later writes wait for earlier reads)
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Pass R: block tridiagonal solve over the P separators (block size p).
 //   Sigma_s = W_s + TL_{s+1},  coupling T[s][s-1] = F_s,  g_s = yR_s + gT_{s+1}
 //   Delta_0 = Sigma_0,  M_s = F_s Delta_{s-1}^-1,  Delta_s = Sigma_s - M_s F_s^T
@@ -813,6 +821,12 @@ __device__ __forceinline__ void pass_schur(const SysDesc& sd, int k, const FT* _
 // layout (lane (i, j) holds v[i]) or in column layout (lane (i, j) holds
 // v[j]).  With factor == false the block factors Delta_s^-1 and M_s stored by
 // an earlier call are reused (a further solve with the same matrix).
+
+// compile-time flag argument of the generic chain lambdas below
+template <bool B>
+struct BoolTag {
+    static constexpr bool value = B;
+};
 
 template <typename FT>
 __device__ inline cplx<FT> shfl_c(cplx<FT> v, int src) {
@@ -930,11 +944,20 @@ __device__ __forceinline__ void pass_reduced_w(const SysDesc& sd, int tid, FT* _
         }
         return a;
     };
+    // Block operands are prefetched kRing blocks ahead into a ring that is
+    // indexed by compile-time slots (the block loop is unrolled by kRing):
+    // each slot keeps its registers, so no copy waits for a load in flight,
+    // and the wait before a block's use covers only loads issued kRing
+    // blocks earlier (and the stores issued before them).
+    constexpr int kRing = sizeof(FT) == 4 ? 4 : 2;
     // elimination chain over blocks s = s0 + dir t, t = 0..count-1; the
     // coupling of block s to the block before it in the chain is F_s
     // (dir > 0) or F_{s+1}^T (dir < 0); with keep_last_raw the last block is
     // stored uninverted (for the join)
-    auto chain = [&](int s0, int count, int dir, bool keep_last_raw) {
+    auto chain = [&](auto fac_tag, int s0, int count, int dir, bool keep_last_raw) {
+        // a compile-time copy of `factor`: the solve-only loop then holds no
+        // global store, so its waits count loads only
+        constexpr bool factor = decltype(fac_tag)::value;
         struct In {
             cplx<FT> y, gt, w, tl, f;
         };
@@ -947,7 +970,7 @@ __device__ __forceinline__ void pass_reduced_w(const SysDesc& sd, int tid, FT* _
             In r;
             r.y = ld_c(bs, 3 * pp + ii);
             r.gt = ld_c(b1, 3 * pp + (unsigned)p + ii);
-            if (factor) {
+            if constexpr (factor) {
                 r.w = ld_c(bs, ee);
                 r.tl = ld_c(b1, 2 * pp + ee);
                 r.f = dir > 0 ? ld_c(bs, pp + ee) : ld_c(b1, pp + et);
@@ -959,15 +982,13 @@ __device__ __forceinline__ void pass_reduced_w(const SysDesc& sd, int tid, FT* _
         };
         cplx<FT> dprev = zero;  // inverse of the previous block of the chain
         cplx<FT> zc = zero;     // previous z (or w) in column layout
-        In cur = load(0);
-        for (int t = 0; t < count; ++t) {
-            In nxt = load(t + 1);
+        auto step = [&](const In& cur, int t) {
             const int s = s0 + dir * t;
             const bool more = s + 1 < P;
             const cplx<FT> g = csel(i < p, cadd(cur.y, csel(more, cur.gt, zero)), zero);
             const cplx<FT> fv = csel(valid, cur.f, zero);
             cplx<FT> mm = zero;
-            if (factor) {
+            if constexpr (factor) {
                 cplx<FT> a = csel(valid, cadd(cur.w, csel(more, cur.tl, zero)), ident);
                 if (t >= 1) {
                     mm = prod_cd(fv, dprev);
@@ -983,15 +1004,30 @@ __device__ __forceinline__ void pass_reduced_w(const SysDesc& sd, int tid, FT* _
             const cplx<FT> zr = csub(g, row_sum(cmul(mm, zc)));
             if (j == 0 && i < p) st_c(z_base, (unsigned)(s * p + i), zr);
             zc = shfl_c(zr, 8 * j);
-            cur = nxt;
+        };
+        In ring[kRing];
+#pragma unroll
+        for (int u = 0; u < kRing; ++u) ring[u] = load(u);
+        // whole groups of kRing blocks without control flow around the
+        // loads (load() clamps past the end), then the last < kRing blocks
+        int t0 = 0;
+        for (; t0 + kRing <= count; t0 += kRing) {
+#pragma unroll
+            for (int u = 0; u < kRing; ++u) {
+                step(ring[u], t0 + u);
+                ring[u] = load(t0 + u + kRing);
+            }
         }
+#pragma unroll
+        for (int u = 0; u + 1 < kRing; ++u)
+            if (t0 + u < count) step(ring[u], t0 + u);
     };
     // x_s = D_s^-1 (z_s - C x_prev) for s = s0 + dir t, where x_prev is the
     // solution of the block before s (xc, column layout) and C = F_{s+1}^T
     // (dir < 0) or F_s (dir > 0)
     auto backsub = [&](int s0, int count, int dir, cplx<FT> xc) {
         struct In {
-            cplx<FT> dv, cf, zs;
+            cplx<FT> dv, cf;
         };
         auto load = [&](int t) {
             const int tt = t < count ? t : count - 1;
@@ -1000,34 +1036,58 @@ __device__ __forceinline__ void pass_reduced_w(const SysDesc& sd, int tid, FT* _
             In r;
             r.dv = ld_c(dinv_base, (unsigned)sc * pp + ee);
             r.cf = dir < 0 ? ld_c(blk(s1), pp + et) : ld_c(blk(sc), pp + ee);
-            r.zs = ld_c(z_base, (unsigned)(sc * p) + ii);
             return r;
         };
-        In bc = load(0);
-        for (int t = 0; t < count; ++t) {
-            In bn = load(t + 1);
+        auto step = [&](const In& bc, int t) {
             const int s = s0 + dir * t;
             const bool has_prev = dir < 0 ? (s + 1 < P) : (s >= 1);
             const cplx<FT> dv = csel(valid, bc.dv, ident);
             const cplx<FT> cf = csel(valid && has_prev, bc.cf, zero);
-            const cplx<FT> zs = csel(i < p, bc.zs, zero);
+            const cplx<FT> zs = csel(i < p, ld_c(z_base, (unsigned)(s * p) + ii), zero);  // LDS
             const cplx<FT> wr = csub(zs, row_sum(cmul(cf, xc)));
             const cplx<FT> wc = shfl_c(wr, 8 * j);
             const cplx<FT> xr = row_sum(cmul(dv, wc));
-            if (j == 0 && i < p) st_c(x_base, (unsigned)(s * p + i), xr);
+            if (j == 0 && i < p) st_c(z_base, (unsigned)(s * p + i), xr);  // z_s is dead now
             xc = shfl_c(xr, 8 * j);
-            bc = bn;
+        };
+        In ring[kRing];
+#pragma unroll
+        for (int u = 0; u < kRing; ++u) ring[u] = load(u);
+        // whole groups of kRing blocks without control flow around the
+        // loads (load() clamps past the end), then the last < kRing blocks
+        int t0 = 0;
+        for (; t0 + kRing <= count; t0 += kRing) {
+#pragma unroll
+            for (int u = 0; u < kRing; ++u) {
+                step(ring[u], t0 + u);
+                ring[u] = load(t0 + u + kRing);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u + 1 < kRing; ++u)
+            if (t0 + u < count) step(ring[u], t0 + u);
+        // x of blocks s0 .. s0 + dir (count - 1) from LDS to the workspace
+        // in one coalesced sweep (no global store inside the block loop)
+        wave_lds_sync();
+        const int lo = dir > 0 ? s0 : s0 - (count - 1);
+        for (int e = lane; e < count * p; e += kWave) {
+            const unsigned at = (unsigned)(lo * p + e);
+            st_c(x_base, at, ld_c(z_base, at));
         }
     };
 
+    const auto run_chain = [&](int s0, int count, int dir, bool keep_last_raw) {
+        if (factor) chain(BoolTag<true>{}, s0, count, dir, keep_last_raw);
+        else chain(BoolTag<false>{}, s0, count, dir, keep_last_raw);
+    };
     if constexpr (NW == 1) {
-        chain(0, P, 1, false);
+        run_chain(0, P, 1, false);
         __syncthreads();  // z_s and the block factors written by other lanes
         backsub(P - 1, P, -1, zero);
         return;
     }
-    if (wv == 0) chain(0, h, 1, false);
-    else chain(P - 1, P - h, -1, true);
+    if (wv == 0) run_chain(0, h, 1, false);
+    else run_chain(P - 1, P - h, -1, true);
     __syncthreads();  // both halves eliminated
     if (wv == 1) {
         // join at block h
@@ -1086,13 +1146,6 @@ struct BlkStage {
         return ld_c(base, at(slot, c, r, col));
     }
 };
-// orders one wave's LDS accesses (written entries become visible to the
-// wave's other lanes; later writes wait for earlier reads)
-__device__ __forceinline__ void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 // out = C D for the staged slots sc (C) and sd (D)
 template <int p, typename FT, int K>
 __device__ __forceinline__ void stage_prod(const BlkStage<FT, K>& S, int sc, int sd, cplx<FT> (&out)[K]) {
