@@ -35,8 +35,8 @@ CALIB_COPY_BYTES = 512 * 2 ** 20
 # (FETCH_SIZE, then WRITE_SIZE) scaled by the copy calibration; valid only for
 # the kernel sources they were taken on (sha256 of the listed files) and the
 # default --split.  See profiles/propagate_kernel_fp32_batch1024_pmc.md.
-TRAFFIC = {"sources_sha256": "cc01434bb9a5a504148e5d2deca3bd602ef25202665c4ba8b18b3855f398f04e",
-           "bytes_per_launch": 2.2604e+13, "split": 160}
+TRAFFIC = {"sources_sha256": "8dee567ec1f0e5397a1739875182202a88db0c16b1e343f9204ede0bc215adf4",
+           "bytes_per_launch": 2.3230e+13, "split": 160}
 # HBM bytes of one FP32 3D operator launch (apply3_kernel<3, float>, 97^3), from the
 # two counter runs of profiles/apply3_kernel_hydrogen97_3d.md, for the sources listed.
 TRAFFIC_3D = {"sources_sha256": "756fca22b65f57f9e37586f21d326c3cde17514272baf647ce2ef519eb541425",
