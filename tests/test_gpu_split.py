@@ -242,6 +242,37 @@ def test_all_two_wave_batch_odd_chunks_and_zero_steps():
             assert rel(gi[:, k], r[:, k]) < 1e-10, (i, k)
 
 
+@pytest.mark.parametrize("P", [66, 67, 70, 71])
+def test_forced_two_wave_chunk_counts(P):
+    """Forced two-wave chunk counts whose halves (P/2 forward, the rest
+    backward) leave every remainder of the separator chain's four-block
+    prefetch groups (two in FP64); both precisions against the oracle."""
+    ns = 40
+    V, dV = W.soft_coulomb(2.0)
+    E = 0.06 * np.sin(0.05 * 0.05 * np.arange(ns + 1) + 0.4)
+    sd = W.System("two-forced", W.breaks_uniform(300.0, 3000 - 8 + 3), 8, lambda x: np.ones_like(x), V, dV, 10,
+                  E, 0.05, ns, True)
+    b = T.batch_create([T.assemble_workload(sd)])
+    T.batch_split(b, [ns], 1)
+    T.batch_set(b, "chunks", P)
+    assert T.batch_two_wave(b).tolist() == [1]
+    assert T.batch_chunks(b).tolist() == [P]
+    m, p0 = _oracle(sd)
+    r, cr = O.propagate(m, p0, sd.E, sd.dt, ns)
+    for prec in (T.FP64, T.FP32_REFINED):
+        psi, po, Eb, eo, obs, oo = T.pack_batch_inputs([sd], [p0])
+        T.propagate_batched(b, psi, po, Eb, eo, [sd.dt], [ns], prec, T.OBS_ALL, obs, oo)
+        T.batch_status(b)
+        got = obs.cpu().numpy().reshape(-1, 3)
+        errs = [rel(got[:, k], r[:, k]) for k in range(3)]
+        es = rel(psi.cpu().numpy(), cr)
+        say("P", P, "prec", prec, "state", es, "series", errs)
+        if prec == T.FP64:
+            assert es < 1e-10 and max(errs) < 1e-10
+        else:
+            assert max(errs) < 1e-5
+
+
 def test_marked_small_system_keeps_its_one_wave_plan():
     """A system marked for two waves whose two-wave plan has at most 64
     chunks (N = 1004: 58) keeps the one-wave plan (41 chunks)."""
