@@ -881,7 +881,8 @@ __device__ inline cplx<FT> row_sum(cplx<FT> v) {
 // in z (z'_h at h).  Both waves reach the same two barriers.  z lives in
 // LDS (zl: P * p complex, declared once per kernel): it is written and read
 // back within the pass, and LDS traffic does not queue behind the streaming
-// passes of the other waves of the CU.
+// passes of the other waves of the CU.  The back substitution writes x_s
+// over z_s in LDS and copies each wave's x to the workspace after its loop.
 template <int PP, typename FT, int NW>
 __device__ __forceinline__ void pass_reduced_w(const SysDesc& sd, int tid, FT* __restrict__ red, bool factor,
                                                FT* __restrict__ zl) {
