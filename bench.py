@@ -35,8 +35,8 @@ CALIB_COPY_BYTES = 512 * 2 ** 20
 # (FETCH_SIZE, then WRITE_SIZE) scaled by the copy calibration; valid only for
 # the kernel sources they were taken on (sha256 of the listed files) and the
 # default --split.  See profiles/propagate_kernel_fp32_batch1024_pmc.md.
-TRAFFIC = {"sources_sha256": "8dee567ec1f0e5397a1739875182202a88db0c16b1e343f9204ede0bc215adf4",
-           "bytes_per_launch": 2.3230e+13, "split": 160}
+TRAFFIC = {"sources_sha256": "4822775adf55b766be2badb7b2bb79ce46e46289a24d5e0e8b86c8194b897d90",
+           "bytes_per_launch": 2.3250e+13, "split": 160}
 # HBM bytes of one FP32 3D operator launch (apply3_kernel<3, float>, 97^3), from the
 # two counter runs of profiles/apply3_kernel_hydrogen97_3d.md, for the sources listed.
 TRAFFIC_3D = {"sources_sha256": "756fca22b65f57f9e37586f21d326c3cde17514272baf647ce2ef519eb541425",
