@@ -35,12 +35,12 @@ CALIB_COPY_BYTES = 512 * 2 ** 20
 # (FETCH_SIZE, then WRITE_SIZE) scaled by the copy calibration; valid only for
 # the kernel sources they were taken on (sha256 of the listed files) and the
 # default --split.  See profiles/propagate_kernel_fp32_batch1024_pmc.md.
-TRAFFIC = {"sources_sha256": "4822775adf55b766be2badb7b2bb79ce46e46289a24d5e0e8b86c8194b897d90",
-           "bytes_per_launch": 2.3250e+13, "split": 160}
+TRAFFIC = {"sources_sha256": "07b8a4d171ab343d1fa9bbf4716184a6a725e824f81f248094322eb689b394da",
+           "bytes_per_launch": 2.3239e+13, "split": 160}
 # HBM bytes of one FP32 3D operator launch (apply3_kernel<3, float>, 97^3), from the
 # two counter runs of profiles/apply3_kernel_hydrogen97_3d.md, for the sources listed.
-TRAFFIC_3D = {"sources_sha256": "756fca22b65f57f9e37586f21d326c3cde17514272baf647ce2ef519eb541425",
-              "bytes_per_launch": 1.5935e+09}
+TRAFFIC_3D = {"sources_sha256": "deb6768397d69cc4e21a03da513a5eaf98edeb3f80c55a2cb94f35dd38adeec0",
+              "bytes_per_launch": 1.5981e+09}
 KERNEL_SOURCES_3D = ["paper_2608_18472_amd/csrc/tdsez_3d.hip", "paper_2608_18472_amd/csrc/tdsez_krylov.hpp",
                      "paper_2608_18472_amd/csrc/tdsez_internal.hpp"]
 KERNEL_SOURCES = ["paper_2608_18472_amd/csrc/tdsez_passes.hpp", "paper_2608_18472_amd/csrc/tdsez_propagate.hip",

@@ -391,9 +391,13 @@ tdsez_status tdsez_propagate_ext(tdsez_system sys, double* psi, const double* E,
  * dJdE_packed: device FP64 [nsteps+1] per system at E_off (overwritten);
  * dJdpsi0_packed: device complex128 at psi_off, or NULL.  The forward
  * states are recomputed from psi0 with a checkpoint every ckpt_stride steps
- * (0: ceil(sqrt(nsteps))), so the cost is about three propagations and the
- * memory (nsteps/ckpt_stride + ckpt_stride + 1) states per system (device
- * workspace owned by the batch, grown on demand).  FP64 only
+ * (0: ceil(sqrt(nsteps))); the recomputation of a segment keeps each
+ * step's factorisation of A_n, which the adjoint step of that step reuses
+ * (it only substitutes).  The cost is about two and a half propagations,
+ * the memory (nsteps/ckpt_stride + ckpt_stride + 1) states and ckpt_stride
+ * factorisations (each 16 (2p + 2) bytes per row and 16 (6p^2 + 4p) bytes
+ * per chunk) per system
+ * (device workspace owned by the batch, grown on demand).  FP64 only
  * (TDSEZ_FP32_REFINED: EUNSUPPORTED).  One workgroup per system, of two
  * waves for the systems that tdsez_batch_split put on two waves (their
  * launch runs beside the one-wave launch, as for propagation); a batch with

@@ -16,9 +16,15 @@
 //
 // States are not stored for every step: a first forward sweep keeps every
 // ck-th state (ck ~ sqrt(nsteps)); each segment between two checkpoints is
-// recomputed into a segment buffer before its adjoint steps run, so the
-// cost is about three forward propagations and the memory
-// (nsteps/ck + ck + 1) states per system.  Everything runs in FP64, one
+// recomputed into a segment buffer before its adjoint steps run.  The
+// recomputation keeps every step's factorisation of A_n (factor rows and
+// separator factors, one slot per step of the segment), so an adjoint step
+// only substitutes: forward with the stored rows, the separator solve, back
+// substitution.  The cost is about two forward propagations and a half; the
+// memory (nsteps/ck + ck + 1) states and ck factorisations per system (each
+// 16 (2p + 2) bytes per row of factor rows and 16 (6p^2 + 4p) bytes per
+// chunk of separator data).  Everything
+// runs in FP64, one
 // wave per system, or two for the systems marked for two waves
 // (tdsez_batch_split; their separator system solved from both ends), all
 // systems of one workgroup size in one launch.
@@ -52,6 +58,8 @@ struct AdjArgs {
     int* status;
     long long state_total;  // complex elements of one whole-batch state
     int order_off;          // first entry of order read by this launch
+    long long fac_total;    // complex elements of one slot of fac (whole batch)
+    long long red_total;    // complex elements of one slot of red (whole batch)
 };
 
 // copy the system's interleaved state (L x LS complex, at state_off of a
@@ -196,10 +204,80 @@ __device__ __forceinline__ void pass_adjoint_update(const SysDesc& sd, int k, co
     part[1] = mexp;
 }
 
+// Forward substitution of conj(b) (b in state layout) with the factor rows
+// stored by the factorisation of A_n (passes A1/A2 of the segment's forward
+// step): yhat_j of every interior pivot, and the separator rows' right-hand
+// side yR and the left separator's Schur right-hand side gT of the chunk, as
+// passes A1 and A2 form them for a new right-hand side.
+template <int PP>
+__device__ __forceinline__ void pass_fwdsub_conj(const SysDesc& sd, int k, const double* __restrict__ rhs,
+                                                 double* __restrict__ fac, double* __restrict__ red) {
+    constexpr int IT = 2 * PP + 2;
+    const int L = sd.L, LS = sd.LS, P = sd.P, m = sd.m;
+    int col = k + 1;
+    asm volatile("" : "+v"(col));
+    const int kk = col - 1;
+    const double* __restrict__ rs = rhs + 2 * sd.state_off;
+    double* __restrict__ fc = fac + 2 * sd.fac_off;
+    const unsigned fstride = (unsigned)(IT * P);
+    auto fitem = [&](int j, int item) {
+        return ld_c(fc, (unsigned)j * fstride + (unsigned)(item * P) + (unsigned)kk);
+    };
+    auto b_of = [&](int r) {
+        const cplx<double> v = ld_c(rs, (unsigned)r * (unsigned)LS + (unsigned)col);
+        return cmk<double>(v.re, -v.im);
+    };
+    struct FRow {
+        cplx<double> l[PP], dinv, f[PP];
+    };
+    auto load_frow = [&](int j) {
+        if (j > m - 1) j = m - 1;
+        FRow fr;
+#pragma unroll
+        for (int i = 0; i < PP; ++i) fr.l[i] = fitem(j, i);
+        fr.dinv = fitem(j, PP);
+#pragma unroll
+        for (int t = 0; t < PP; ++t) fr.f[t] = fitem(j, PP + 2 + t);
+        return fr;
+    };
+    cplx<double> y[PP + 1], gT[PP];
+#pragma unroll
+    for (int i = 0; i <= PP; ++i) y[i] = cmk<double>(0, 0);
+#pragma unroll
+    for (int t = 0; t < PP; ++t) gT[t] = cmk<double>(0, 0);
+    FRow fcur = load_frow(0);
+    cplx<double> bcur = b_of(0);
+    for (int j = 0; j < m; ++j) {
+        const FRow fnxt = load_frow(j + 1);
+        const cplx<double> bnxt = b_of(j + 1 < L ? j + 1 : L - 1);
+        const cplx<double> yj = cadd(y[0], bcur);
+        st_c(fc, (unsigned)j * fstride + (unsigned)((PP + 1) * P) + (unsigned)kk, yj);
+#pragma unroll
+        for (int i = 1; i <= PP; ++i) y[i] = cfms(y[i], fcur.l[i - 1], yj);
+#pragma unroll
+        for (int t = 0; t < PP; ++t) gT[t] = cfms(gT[t], cmul(fcur.f[t], fcur.dinv), yj);
+#pragma unroll
+        for (int i = 1; i <= PP; ++i) y[i - 1] = y[i];
+        y[PP] = cmk<double>(0, 0);
+        fcur = fnxt;
+        bcur = bnxt;
+    }
+    // the separator rows m .. L-1 of the chunk
+#pragma unroll
+    for (int t = 0; t < PP; ++t) y[t] = cadd(y[t], b_of(m + t));
+    double* rb = red + 2 * (sd.red_off + (long long)k * RedLayout<double>::chunk_block(PP));
+    constexpr int pp = PP * PP;
+#pragma unroll
+    for (int i = 0; i < PP; ++i) {
+        st_c(rb, (unsigned)(3 * pp + i), y[i]);
+        st_c(rb, (unsigned)(3 * pp + PP + i), gT[i]);
+    }
+}
+
 template <int PP, int NW>
-__device__ __forceinline__ void adj_reduced(const SysDesc& sd, int tid, double* red, double* zl) {
-    if constexpr (NW == 2) pass_reduced2<PP, double>(sd, tid, red, true, zl);
-    else pass_reduced<PP, double>(sd, tid, red, true, zl);
+__device__ __forceinline__ void adj_reduced(const SysDesc& sd, int tid, double* red, double* zl, bool factor) {
+    if constexpr (NW == 2) pass_reduced2<PP, double>(sd, tid, red, factor, zl);
+    else pass_reduced<PP, double>(sd, tid, red, factor, zl);
 }
 
 // sum over the workgroup of wave-uniform values (wave order, so every wave
@@ -217,22 +295,23 @@ __device__ __forceinline__ double wg_sum(double v, int tid) {
     return v;
 }
 
-// one forward step n -> n+1 in place on st (FP64, no refinement)
+// one forward step n -> n+1 in place on st (FP64, no refinement); the
+// factorisation of A_n is left in the factor slot (fac, red)
 template <int PP, int NW>
 __device__ __forceinline__ void forward_step(const AdjArgs& ka, const SysDesc& sd, int lane, double alpha, double Ebar,
-                                             double* zl) {
+                                             double* zl, double* fac, double* red) {
     const bool active = lane < sd.P;
     double part[3];
     if (active) {
         pass_rhs<PP, double>(sd, lane, ka.band, ka.st, ka.rhs, alpha, Ebar, Ebar, false, true, part);
-        pass_elim<PP, double>(sd, lane, ka.band, ka.rhs, ka.fac, ka.red, alpha, Ebar);
-        pass_fill<PP, double, false>(sd, lane, ka.band, ka.fac, ka.red, alpha, Ebar);
-        pass_schur<PP, double>(sd, lane, ka.fac, ka.red);
+        pass_elim<PP, double>(sd, lane, ka.band, ka.rhs, fac, red, alpha, Ebar);
+        pass_fill<PP, double, false>(sd, lane, ka.band, fac, red, alpha, Ebar);
+        pass_schur<PP, double>(sd, lane, fac, red);
     }
     __syncthreads();
-    adj_reduced<PP, NW>(sd, lane, ka.red, zl);
+    adj_reduced<PP, NW>(sd, lane, red, zl, true);
     __syncthreads();
-    if (active) pass_backsub<PP, double>(sd, lane, ka.band, ka.st, nullptr, true, ka.fac, ka.red, alpha, Ebar);
+    if (active) pass_backsub<PP, double>(sd, lane, ka.band, ka.st, nullptr, true, fac, red, alpha, Ebar);
     __syncthreads();
 }
 
@@ -257,6 +336,10 @@ __device__ __forceinline__ void run_adjoint(const AdjArgs& ka, const SysDesc& sd
     // checkpoint and segment buffers hold whole-batch states (the system's
     // part at state_off, like the working state)
     auto state_at = [&](double* base, long long idx) { return base + 2 * (idx * ka.state_total); };
+    // factor slot of step n0 + t of the segment being reversed (whole-batch
+    // fac and red layouts, the system's part at fac_off / red_off)
+    auto fac_slot = [&](int t) { return ka.fac + 2 * ((long long)t * ka.fac_total); };
+    auto red_slot = [&](int t) { return ka.red + 2 * ((long long)t * ka.red_total); };
 
     // initial state: natural order -> interleaved, zero halos and padding
     if (active) {
@@ -286,7 +369,7 @@ __device__ __forceinline__ void run_adjoint(const AdjArgs& ka, const SysDesc& sd
     copy_state(sd, lane, ka.st, state_at(ckpt, 0));
     __syncthreads();
     for (int n = 0; n < ns; ++n) {
-        forward_step<PP, NW>(ka, sd, lane, alpha, ebar(n), zl);
+        forward_step<PP, NW>(ka, sd, lane, alpha, ebar(n), zl, fac_slot(0), red_slot(0));
         if ((n + 1) % ck == 0 && n + 1 < ns) {
             copy_state(sd, lane, ka.st, state_at(ckpt, (n + 1) / ck));
             __syncthreads();
@@ -310,24 +393,21 @@ __device__ __forceinline__ void run_adjoint(const AdjArgs& ka, const SysDesc& sd
         copy_state(sd, lane, state_at(ckpt, sgi), state_at(seg, 0));
         __syncthreads();
         for (int n = n0; n < n1; ++n) {
-            forward_step<PP, NW>(ka, sd, lane, alpha, ebar(n), zl);
+            forward_step<PP, NW>(ka, sd, lane, alpha, ebar(n), zl, fac_slot(n - n0), red_slot(n - n0));
             copy_state(sd, lane, ka.st, state_at(seg, n - n0 + 1));
             __syncthreads();
         }
         for (int n = n1 - 1; n >= n0; --n) {
             const double Eb = ebar(n);
-            // w = A_n^-1 conj(lambda_{n+1})
-            if (active) {
-                pass_elim<PP, double, true>(sd, lane, ka.band, ka.lam, ka.fac, ka.red, alpha, Eb);
-                pass_fill<PP, double, false>(sd, lane, ka.band, ka.fac, ka.red, alpha, Eb);
-                pass_schur<PP, double>(sd, lane, ka.fac, ka.red);
-            }
+            // w = A_n^-1 conj(lambda_{n+1}) with the factorisation of A_n kept
+            // by the recomputation of step n
+            double* fs = fac_slot(n - n0);
+            double* rs = red_slot(n - n0);
+            if (active) pass_fwdsub_conj<PP>(sd, lane, ka.lam, fs, rs);
             __syncthreads();
-            adj_reduced<PP, NW>(sd, lane, ka.red, zl);
+            adj_reduced<PP, NW>(sd, lane, rs, zl, false);
             __syncthreads();
-            if (active)
-                pass_backsub<PP, double>(sd, lane, ka.band, ka.wsol, nullptr, true, ka.fac, ka.red, alpha, Eb,
-                                         true);
+            if (active) pass_backsub<PP, double>(sd, lane, ka.band, ka.wsol, nullptr, true, fs, rs, alpha, Eb, true);
             __syncthreads();
             // lambda_n = g_n + A_n z, z = conj(w)
             double part[2] = {0.0, 0.0};
@@ -404,6 +484,9 @@ tdsez_status launch_adjoint(BatchData* b, const double* psi0, const double* E, c
     }
     const long long ck_total = (long long)max_nseg * state_total;
     const long long seg_total = (long long)(max_ck + 1) * state_total;
+    // one factor slot per step of a segment
+    const long long facs_total = (long long)max_ck * b->fac_elems64;
+    const long long reds_total = (long long)max_ck * b->red_elems64;
     if (!b->d_lam) {
         TDSEZ_HIP_TRY(hipMalloc(&b->d_lam, 2 * sizeof(double) * (size_t)state_total));
         TDSEZ_HIP_TRY(hipMalloc(&b->d_wsol, 2 * sizeof(double) * (size_t)state_total));
@@ -424,6 +507,20 @@ tdsez_status launch_adjoint(BatchData* b, const double* psi0, const double* E, c
         TDSEZ_HIP_TRY(hipMalloc(&b->d_seg, 2 * sizeof(double) * (size_t)seg_total));
         b->seg_elems = seg_total;
     }
+    if (facs_total > b->fac_seg_elems) {
+        (void)hipFree(b->d_fac_seg);
+        b->d_fac_seg = nullptr;
+        b->fac_seg_elems = 0;
+        TDSEZ_HIP_TRY(hipMalloc(&b->d_fac_seg, 2 * sizeof(double) * (size_t)facs_total));
+        b->fac_seg_elems = facs_total;
+    }
+    if (reds_total > b->red_seg_elems) {
+        (void)hipFree(b->d_red_seg);
+        b->d_red_seg = nullptr;
+        b->red_seg_elems = 0;
+        TDSEZ_HIP_TRY(hipMalloc(&b->d_red_seg, 2 * sizeof(double) * (size_t)reds_total));
+        b->red_seg_elems = reds_total;
+    }
     if (tdsez_status st = upload_descriptors(b, stream)) return st;
     AdjArgs ka{};
     ka.descs = b->d_desc;
@@ -431,8 +528,10 @@ tdsez_status launch_adjoint(BatchData* b, const double* psi0, const double* E, c
     ka.band = b->d_band64;
     ka.st = b->d_state;
     ka.rhs = (double*)b->d_rhs;
-    ka.fac = (double*)b->d_fac;
-    ka.red = (double*)b->d_red;
+    ka.fac = b->d_fac_seg;
+    ka.red = b->d_red_seg;
+    ka.fac_total = b->fac_elems64;
+    ka.red_total = b->red_elems64;
     ka.lam = b->d_lam;
     ka.wsol = b->d_wsol;
     ka.ckpt = b->d_ckpt;

@@ -53,8 +53,12 @@ static void free_batch_device(BatchData* b) {
     (void)hipFree(b->d_wsol);
     (void)hipFree(b->d_ckpt);
     (void)hipFree(b->d_seg);
+    (void)hipFree(b->d_fac_seg);
+    (void)hipFree(b->d_red_seg);
     b->d_lam = b->d_wsol = b->d_ckpt = b->d_seg = nullptr;
+    b->d_fac_seg = b->d_red_seg = nullptr;
     b->ckpt_elems = b->seg_elems = 0;
+    b->fac_seg_elems = b->red_seg_elems = 0;
     (void)hipFree(b->d_fac);
     (void)hipFree(b->d_red);
     (void)hipFree(b->d_desc);

@@ -163,6 +163,10 @@ struct BatchData {
     double* d_ckpt = nullptr;        // checkpoint states
     double* d_seg = nullptr;         // states of the segment being reversed
     long long ckpt_elems = 0, seg_elems = 0;
+    // the segment's factorisations (fac and red layouts, one slot per step)
+    double* d_fac_seg = nullptr;
+    double* d_red_seg = nullptr;
+    long long fac_seg_elems = 0, red_seg_elems = 0;
     void* d_fac = nullptr;           // factor workspace (sized for FP64)
     void* d_red = nullptr;           // reduced-system workspace (sized for FP64)
     SysDesc* d_desc = nullptr;
