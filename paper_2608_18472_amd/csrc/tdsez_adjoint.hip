@@ -132,25 +132,43 @@ __device__ __forceinline__ void pass_adjoint_update(const SysDesc& sd, int k, co
         load3(at, zw[d + 1], cw[d + 1], vw[d + 1]);
     }
     double dimag = 0.0, mexp = 0.0;
-    auto stream_row = [&](int r, bool own) {
+    // band and state rows, loaded one row ahead of their use
+    struct RowIn {
+        double s[PP + 1], h[PP + 1], d[PP + 1], g[PP + 1], m[PP + 1];
+        cplx<double> z, c, v;
+    };
+    auto load_row = [&](int r) {
+        if (r >= L + PP) r = L + PP - 1;  // past the end: reload the last row (unused)
+        const bool own = r < L;
         const int lr = own ? r : r - L;
         const unsigned cc = (unsigned)(own ? col : col + 1);
         const unsigned rb = (unsigned)lr * rowstride + cc;
+        RowIn in;
+#pragma unroll
+        for (int d = 0; d <= PP; ++d) {
+            in.s[d] = bnd[rb + (unsigned)((0 * (PP + 1) + d) * LS)];
+            in.h[d] = bnd[rb + (unsigned)((1 * (PP + 1) + d) * LS)];
+            in.d[d] = bnd[rb + (unsigned)((2 * (PP + 1) + d) * LS)];
+            in.g[d] = bnd[rb + (unsigned)((3 * (PP + 1) + d) * LS)];
+            in.m[d] = bnd[rb + (unsigned)((4 * (PP + 1) + d) * LS)];
+        }
+        load3((unsigned)lr * (unsigned)LS + cc, in.z, in.c, in.v);
+        return in;
+    };
+    auto stream_row = [&](const RowIn& in, int r, bool own) {
         cplx<double> a[PP + 1];
         double kk[PP + 1], dd[PP + 1], mi[PP + 1];
 #pragma unroll
         for (int d = 0; d <= PP; ++d) {
-            const double s = bnd[rb + (unsigned)((0 * (PP + 1) + d) * LS)];
-            const double h = bnd[rb + (unsigned)((1 * (PP + 1) + d) * LS)];
-            dd[d] = bnd[rb + (unsigned)((2 * (PP + 1) + d) * LS)];
-            const double g = bnd[rb + (unsigned)((3 * (PP + 1) + d) * LS)];
-            mi[d] = bnd[rb + (unsigned)((4 * (PP + 1) + d) * LS)];
+            const double s = in.s[d];
+            const double h = in.h[d];
+            dd[d] = in.d[d];
+            const double g = in.g[d];
+            mi[d] = in.m[d];
             a[d] = cmk<double>(s, alpha * (h + Ebar * dd[d]));
             kk[d] = 2.0 * jn * s + 2.0 * jd * dd[d] - 2.0 * ja * (g + En * mi[d]);
         }
-        const unsigned at = (unsigned)lr * (unsigned)LS + cc;
-        cplx<double> zr, cr, vr;
-        load3(at, zr, cr, vr);
+        const cplx<double> zr = in.z, cr = in.c, vr = in.v;
 #pragma unroll
         for (int d = 0; d < PP; ++d) {
             zw[d] = zw[d + 1];
@@ -197,9 +215,18 @@ __device__ __forceinline__ void pass_adjoint_update(const SysDesc& sd, int k, co
             lm[2 * o + 1] = az[0].im + kc[0].im;
         }
     };
-    for (int r = 0; r < L; ++r) stream_row(r, true);
+    RowIn cur = load_row(0);
+    for (int r = 0; r < L; ++r) {
+        const RowIn nxt = load_row(r + 1);
+        stream_row(cur, r, true);
+        cur = nxt;
+    }
 #pragma unroll
-    for (int t = 0; t < PP; ++t) stream_row(L + t, false);
+    for (int t = 0; t < PP; ++t) {
+        const RowIn nxt = load_row(L + t + 1);
+        stream_row(cur, L + t, false);
+        cur = nxt;
+    }
     part[0] = dimag;
     part[1] = mexp;
 }
