@@ -68,17 +68,34 @@ struct AdjArgs {
 __device__ __forceinline__ void copy_state(const SysDesc& sd, int lane, const double* src, double* dst) {
     if (lane >= sd.P) return;
     const int LS = sd.LS;
-    for (int l = 0; l < sd.L; ++l) {
-        const long long base = sd.state_off + (long long)l * LS;
-        long long at = base + lane + 1;
-        dst[2 * at] = src[2 * at];
-        dst[2 * at + 1] = src[2 * at + 1];
-        if (lane == 0) {
-            dst[2 * base] = src[2 * base];
-            dst[2 * base + 1] = src[2 * base + 1];
+    // the lane's own column, eight rows in flight at a time (the stores of a
+    // row would otherwise wait for its loads one row after the other)
+    constexpr int kRows = 8;
+    for (int l0 = 0; l0 < sd.L; l0 += kRows) {
+        double re[kRows], im[kRows];
+#pragma unroll
+        for (int u = 0; u < kRows; ++u) {
+            const int l = l0 + u < sd.L ? l0 + u : sd.L - 1;
+            const long long at = sd.state_off + (long long)l * LS + lane + 1;
+            re[u] = src[2 * at];
+            im[u] = src[2 * at + 1];
         }
-        if (lane == sd.P - 1) {
-            at = base + sd.P + 1;
+#pragma unroll
+        for (int u = 0; u < kRows; ++u) {
+            if (l0 + u < sd.L) {
+                const long long at = sd.state_off + (long long)(l0 + u) * LS + lane + 1;
+                dst[2 * at] = re[u];
+                dst[2 * at + 1] = im[u];
+            }
+        }
+    }
+    // the zero halo columns 0 (first lane) and P + 1 (last lane; one lane
+    // copies both when P = 1)
+    for (int h = 0; h < 2; ++h) {
+        if (!(h == 0 ? lane == 0 : lane == sd.P - 1)) continue;
+        const int hc = h == 0 ? 0 : sd.P + 1;
+        for (int l = 0; l < sd.L; ++l) {
+            const long long at = sd.state_off + (long long)l * LS + hc;
             dst[2 * at] = src[2 * at];
             dst[2 * at + 1] = src[2 * at + 1];
         }
