@@ -631,7 +631,9 @@ def run_adjoint(args):
     20 000 steps, config-2 geometry) driven by 64-amplitude Fourier pulses;
     one gradient = the differentiable forward series (one persistent
     propagation launch, FP64) and its backward (the discrete-adjoint launch
-    with sqrt(Nt) checkpoints).  Metric: gradient DOF-steps/s = sum N nsteps
+    with sqrt(Nt) checkpoints; each adjoint step substitutes with the
+    factorisation kept by its segment's recomputation).  Metric: gradient
+    DOF-steps/s = sum N nsteps
     / (forward + adjoint time); roofline of the adjoint launch with
     3 (3 (p+1) 8 + 2 16) = 672 algorithmic bytes per DOF-step (the
     checkpointing forward sweep, the segment recomputation and the adjoint
