@@ -397,7 +397,9 @@ tdsez_status tdsez_propagate_ext(tdsez_system sys, double* psi, const double* E,
  * the memory (nsteps/ckpt_stride + ckpt_stride + 1) states and ckpt_stride
  * factorisations (each 16 (2p + 2) bytes per row and 16 (6p^2 + 4p) bytes
  * per chunk) per system
- * (device workspace owned by the batch, grown on demand).  FP64 only
+ * (device workspace owned by the batch, grown on demand; a smaller
+ * ckpt_stride trades factorisation memory for checkpoint states, and a
+ * failed allocation returns TDSEZ_EHIP).  FP64 only
  * (TDSEZ_FP32_REFINED: EUNSUPPORTED).  One workgroup per system, of two
  * waves for the systems that tdsez_batch_split put on two waves (their
  * launch runs beside the one-wave launch, as for propagation); a batch with
