@@ -286,9 +286,15 @@ tdsez_status tdsez_batch_chunks(tdsez_batch b, int* chunks_out);
  * Re-packs the batch and clears the autotuner's plans (run tdsez_autotune
  * afterwards to tune the new plan; it keeps the marks).  The adjoint runs
  * two-wave systems on two waves and refuses a batch with four-wave systems
- * (EUNSUPPORTED).  nsteps: host array of
- * nsys step counts (may be NULL when count = 0).  Synchronous.  EINVAL for
- * count outside 0..nsys or a negative step count. */
+ * (EUNSUPPORTED).  count = TDSEZ_SPLIT_AUTO chooses the count from the
+ * current device: with S = 4 x its compute units (SIMDs) the batch's waves
+ * are to fill them with a margin of 16 %, count = clamp(floor(1.16 S) -
+ * nsys, 0, nsys) (a measured optimum: on a 1024-SIMD device the 1024-system
+ * batch runs fastest with 100 to 220 marked systems, 160 in the middle).
+ * nsteps: host array of nsys step counts (may be NULL when count = 0).
+ * Synchronous.  EINVAL for count outside 0..nsys (other than
+ * TDSEZ_SPLIT_AUTO) or a negative step count. */
+enum { TDSEZ_SPLIT_AUTO = -1 };
 tdsez_status tdsez_batch_split(tdsez_batch b, const int* nsteps, int count);
 
 /* 1 for every system that runs on more than one wave under the current

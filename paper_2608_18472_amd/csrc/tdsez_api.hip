@@ -1,5 +1,6 @@
 // C ABI of libtdsez (declared in include/tdsez.h): argument checking, handle
 // management and error reporting around the device code of tdsez_*.hip.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -668,6 +669,13 @@ tdsez_status tdsez_batch_split(tdsez_batch b, const int* nsteps, int count) {
     if (!b) return fail(TDSEZ_EINVAL, "b is NULL");
     BatchData* d = &b->d;
     const int nsys = (int)d->sys.size();
+    if (count == TDSEZ_SPLIT_AUTO) {
+        int dev = 0, cus = 0;
+        TDSEZ_HIP_TRY(hipGetDevice(&dev));
+        TDSEZ_HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        const int waves = (int)std::floor(1.16 * 4.0 * cus);
+        count = std::max(0, std::min(nsys, waves - nsys));
+    }
     if (count < 0 || count > nsys) return fail(TDSEZ_EINVAL, "count must be in 0..%d", nsys);
     if (count > 0 && !nsteps) return fail(TDSEZ_EINVAL, "nsteps is NULL");
     for (int s = 0; count > 0 && s < nsys; ++s)

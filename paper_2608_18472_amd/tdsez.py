@@ -462,10 +462,13 @@ def batch_chunks(batch):
     return out
 
 
+SPLIT_AUTO = -1
+
+
 def batch_split(batch, nsteps, count):
     """Run the `count` systems with the largest N (p + 1) nsteps on two waves,
     or four with the batch key max_waves = 4 (nsteps may be None with
-    count = 0)."""
+    count = 0; SPLIT_AUTO chooses the count from the device's SIMDs)."""
     if nsteps is None:
         _check(lib().tdsez_batch_split(batch.handle, None, int(count)))
         return

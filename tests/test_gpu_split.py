@@ -273,6 +273,31 @@ def test_forced_two_wave_chunk_counts(P):
             assert max(errs) < 1e-5
 
 
+def test_automatic_split_count_fills_the_simds():
+    """SPLIT_AUTO marks clamp(floor(1.16 S) - nsys, 0, nsys) systems, S = 4 x
+    the device's compute units; every marked system of N = 1600 (73 chunks
+    on two waves) runs on two waves, the costliest first."""
+    S = 4 * torch.cuda.get_device_properties(0).multi_processor_count
+    V, dV = W.soft_coulomb(2.0)
+    for nsys in (int(1.16 * S) - 150, 3):
+        defs = []
+        for i in range(nsys):
+            ns = 10 + (i % 7)
+            E = np.zeros(ns + 1)
+            defs.append(W.System("auto-%d" % i, W.breaks_uniform(200.0, 1600 - 8 + 3), 8, lambda x: np.ones_like(x),
+                                 V, dV, 10, E, 0.05, ns, True))
+        b = T.batch_create([T.assemble_workload(d) for d in defs])
+        T.batch_split(b, [d.nsteps for d in defs], T.SPLIT_AUTO)
+        flags = T.batch_two_wave(b)
+        want = max(0, min(nsys, int(1.16 * S) - nsys))
+        say("nsys", nsys, "S", S, "two-wave", int(flags.sum()), "expected", want)
+        assert int(flags.sum()) == want
+        if 0 < want < nsys:
+            # the marked systems are those with the most steps (same N and p)
+            ns = np.array([d.nsteps for d in defs])
+            assert ns[flags == 1].min() >= ns[flags == 0].max()
+
+
 def test_marked_small_system_keeps_its_one_wave_plan():
     """A system marked for two waves whose two-wave plan has at most 64
     chunks (N = 1004: 58) keeps the one-wave plan (41 chunks)."""
