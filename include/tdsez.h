@@ -285,8 +285,7 @@ tdsez_status tdsez_batch_chunks(tdsez_batch b, int* chunks_out);
  * one-wave results up to rounding.  count = 0 restores one wave per system.
  * Re-packs the batch and clears the autotuner's plans (run tdsez_autotune
  * afterwards to tune the new plan; it keeps the marks).  The adjoint runs
- * two-wave systems on two waves and refuses a batch with four-wave systems
- * (EUNSUPPORTED).  count = TDSEZ_SPLIT_AUTO chooses the count from the
+ * every system on the waves of its plan.  count = TDSEZ_SPLIT_AUTO chooses the count from the
  * current device: with S = 4 x its compute units (SIMDs) the batch's waves
  * are to fill them with a margin of 16 %, count = clamp(floor(1.16 S) -
  * nsys, 0, nsys) (a measured optimum: on a 1024-SIMD device the 1024-system
@@ -406,10 +405,10 @@ tdsez_status tdsez_propagate_ext(tdsez_system sys, double* psi, const double* E,
  * (device workspace owned by the batch, grown on demand; a smaller
  * ckpt_stride trades factorisation memory for checkpoint states, and a
  * failed allocation returns TDSEZ_EHIP).  FP64 only
- * (TDSEZ_FP32_REFINED: EUNSUPPORTED).  One workgroup per system, of two
- * waves for the systems that tdsez_batch_split put on two waves (their
- * launch runs beside the one-wave launch, as for propagation); a batch with
- * four-wave systems is refused (EUNSUPPORTED).  Asynchronous on `stream`;
+ * (TDSEZ_FP32_REFINED: EUNSUPPORTED).  One workgroup per system, of the
+ * waves its plan has (tdsez_batch_split: two, or four with cyclic reduction
+ * of the separator system; the launches of the three wave counts run
+ * concurrently, as for propagation).  Asynchronous on `stream`;
  * device failures are latched as for propagation.  Uses the batch's working
  * state, so it must not overlap a propagation of the same batch. */
 tdsez_status tdsez_adjoint_batched(tdsez_batch b, const double* psi0_packed, const long* psi_off,

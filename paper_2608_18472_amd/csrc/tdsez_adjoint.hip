@@ -25,9 +25,9 @@
 // 16 (2p + 2) bytes per row of factor rows and 16 (6p^2 + 4p) bytes per
 // chunk of separator data).  Everything
 // runs in FP64, one
-// wave per system, or two for the systems marked for two waves
-// (tdsez_batch_split; their separator system solved from both ends), all
-// systems of one workgroup size in one launch.
+// wave per system, or two or four for the systems marked by
+// tdsez_batch_split (their separator system solved from both ends, or by
+// block cyclic reduction), all systems of one workgroup size in one launch.
 #include <algorithm>
 #include <cmath>
 
@@ -320,8 +320,14 @@ __device__ __forceinline__ void pass_fwdsub_conj(const SysDesc& sd, int k, const
 
 template <int PP, int NW>
 __device__ __forceinline__ void adj_reduced(const SysDesc& sd, int tid, double* red, double* zl, bool factor) {
-    if constexpr (NW == 2) pass_reduced2<PP, double>(sd, tid, red, factor, zl);
-    else pass_reduced<PP, double>(sd, tid, red, factor, zl);
+    if constexpr (NW == 4) {
+        const SpanCtx<double> one{0, sd.P, 0, 1, nullptr, nullptr};  // one workgroup
+        pass_reduced_cr<PP, double, 4, false>(sd, tid, red, factor, zl, one);
+    } else if constexpr (NW == 2) {
+        pass_reduced2<PP, double>(sd, tid, red, factor, zl);
+    } else {
+        pass_reduced<PP, double>(sd, tid, red, factor, zl);
+    }
 }
 
 // sum over the workgroup of wave-uniform values (wave order, so every wave
@@ -329,11 +335,13 @@ __device__ __forceinline__ void adj_reduced(const SysDesc& sd, int tid, double* 
 template <int NW>
 __device__ __forceinline__ double wg_sum(double v, int tid) {
     v = wave_sum(v);
-    if constexpr (NW == 2) {
-        __shared__ double buf[2];
+    if constexpr (NW > 1) {
+        __shared__ double buf[NW];
         if ((tid & (kWave - 1)) == 0) buf[tid / kWave] = v;
         __syncthreads();
-        v = buf[0] + buf[1];
+        v = buf[0];
+#pragma unroll
+        for (int w = 1; w < NW; ++w) v += buf[w];
         __syncthreads();
     }
     return v;
@@ -489,7 +497,8 @@ __device__ __forceinline__ void run_adjoint(const AdjArgs& ka, const SysDesc& sd
 template <int NW>
 __device__ __forceinline__ void dispatch_adjoint(const AdjArgs& ka) {
     // the separator recurrence's right-hand-side vector (P * p complex)
-    __shared__ double zl[2 * kMaxP * kWave * NW];
+    // (four waves: the cyclic reduction's g vectors and block staging)
+    __shared__ double zl[NW == 4 ? CrLds<double>::kTotal : 2 * kMaxP * kWave * NW];
     const int sidx = ka.order[ka.order_off + blockIdx.x];
     const SysDesc sd = ka.descs[sidx];
     switch (sd.p) {
@@ -506,6 +515,7 @@ __device__ __forceinline__ void dispatch_adjoint(const AdjArgs& ka) {
 
 __global__ __launch_bounds__(kWave) void adjoint_kernel(AdjArgs ka) { dispatch_adjoint<1>(ka); }
 __global__ __launch_bounds__(2 * kWave) void adjoint2_kernel(AdjArgs ka) { dispatch_adjoint<2>(ka); }
+__global__ __launch_bounds__(4 * kWave) void adjoint4_kernel(AdjArgs ka) { dispatch_adjoint<4>(ka); }
 
 }  // namespace
 
@@ -588,29 +598,47 @@ tdsez_status launch_adjoint(BatchData* b, const double* psi0, const double* E, c
     ka.dJdpsi0 = dJdpsi0;
     ka.status = b->d_status;
     ka.state_total = state_total;
-    // two-wave systems first (entries 0..n2-1 of the order, caller's
-    // stream), the one-wave systems concurrently on the batch's side stream
-    // forked from and joined back into the caller's stream
-    const int n2 = b->nsplit, n1 = nsys - b->nsplit;
-    hipStream_t s1 = stream;
-    if (n2 > 0 && n1 > 0) {
-        TDSEZ_HIP_TRY(hipEventRecord(b->ev_fork, stream));
-        TDSEZ_HIP_TRY(hipStreamWaitEvent(b->side, b->ev_fork, 0));
-        s1 = b->side;
+    // four-wave systems first (entries 0..n4-1 of the order), then the
+    // two-wave and the one-wave systems; the first non-empty group runs on
+    // the caller's stream, the others concurrently on the batch's side
+    // streams forked from and joined back into it
+    const int n4 = b->n4, n2 = b->nsplit - b->n4, n1 = nsys - b->nsplit;
+    hipStream_t grp[3] = {stream, stream, stream};
+    hipStream_t sides[2] = {b->side, b->side2};
+    hipEvent_t joins[2] = {b->ev_join, b->ev_join2};
+    int nside = 0;
+    {
+        const int cnt[3] = {n4, n2, n1};
+        bool first = true;
+        for (int g = 0; g < 3; ++g) {
+            if (cnt[g] == 0) continue;
+            if (first) {
+                first = false;
+                continue;
+            }
+            if (nside == 0) TDSEZ_HIP_TRY(hipEventRecord(b->ev_fork, stream));
+            TDSEZ_HIP_TRY(hipStreamWaitEvent(sides[nside], b->ev_fork, 0));
+            grp[g] = sides[nside++];
+        }
+    }
+    if (n4 > 0) {
+        ka.order_off = 0;
+        adjoint4_kernel<<<n4, 4 * kWave, 0, grp[0]>>>(ka);
+        TDSEZ_HIP_TRY(hipGetLastError());
     }
     if (n2 > 0) {
-        ka.order_off = 0;
-        adjoint2_kernel<<<n2, 2 * kWave, 0, stream>>>(ka);
+        ka.order_off = n4;
+        adjoint2_kernel<<<n2, 2 * kWave, 0, grp[1]>>>(ka);
         TDSEZ_HIP_TRY(hipGetLastError());
     }
     if (n1 > 0) {
-        ka.order_off = n2;
-        adjoint_kernel<<<n1, kWave, 0, s1>>>(ka);
+        ka.order_off = n4 + n2;
+        adjoint_kernel<<<n1, kWave, 0, grp[2]>>>(ka);
         TDSEZ_HIP_TRY(hipGetLastError());
     }
-    if (n2 > 0 && n1 > 0) {
-        TDSEZ_HIP_TRY(hipEventRecord(b->ev_join, b->side));
-        TDSEZ_HIP_TRY(hipStreamWaitEvent(stream, b->ev_join, 0));
+    for (int k = 0; k < nside; ++k) {
+        TDSEZ_HIP_TRY(hipEventRecord(joins[k], sides[k]));
+        TDSEZ_HIP_TRY(hipStreamWaitEvent(stream, joins[k], 0));
     }
     return TDSEZ_OK;
 }

@@ -329,8 +329,6 @@ tdsez_status tdsez_adjoint_batched(tdsez_batch b, const double* psi0_packed, con
     if (!b || !psi0_packed || !psi_off || !E_packed || !E_off || !dt || !nsteps || !dJdobs_packed ||
         !obs_off || !dJdE_packed)
         return fail(TDSEZ_EINVAL, "NULL argument");
-    if (b->d.n4 > 0)
-        return fail(TDSEZ_EUNSUPPORTED, "the adjoint runs one or two waves per system; set max_waves to 2");
     if (b->d.any_cap)
         return fail(TDSEZ_EUNSUPPORTED, "the adjoint does not support an absorbing potential");
     for (size_t s = 0; s < b->d.sys.size(); ++s)
