@@ -35,8 +35,8 @@ CALIB_COPY_BYTES = 512 * 2 ** 20
 # (FETCH_SIZE, then WRITE_SIZE) scaled by the copy calibration; valid only for
 # the kernel sources they were taken on (sha256 of the listed files) and the
 # default --split.  See profiles/propagate_kernel_fp32_batch1024_pmc.md.
-TRAFFIC = {"sources_sha256": "07b8a4d171ab343d1fa9bbf4716184a6a725e824f81f248094322eb689b394da",
-           "bytes_per_launch": 2.3239e+13, "split": 160}
+TRAFFIC = {"sources_sha256": "9eb646a9691b338a6b3aba610fa68778d901ce4b2927dd343bdae9a04bad4ed0",
+           "bytes_per_launch": 2.3280e+13, "split": 160}
 # HBM bytes of one FP32 3D operator launch (apply3_kernel<3, float>, 97^3), from the
 # two counter runs of profiles/apply3_kernel_hydrogen97_3d.md, for the sources listed.
 TRAFFIC_3D = {"sources_sha256": "deb6768397d69cc4e21a03da513a5eaf98edeb3f80c55a2cb94f35dd38adeec0",

@@ -345,7 +345,9 @@ tdsez_status tdsez_propagate_batched_ext(tdsez_batch b, double* psi_packed, cons
  * keeps a one-system plan inside the system handle, created by the first
  * call).  The system runs on four waves when its four-wave plan has more
  * than 128 chunks (N above about 2460), else on two when its two-wave plan
- * has more than 64 (N above about 1230; see tdsez_batch_split).  psi: device
+ * has more than 64 (N above about 1230; see tdsez_batch_split) or when 65
+ * chunks of at least 2p rows fit (N above about 65 (2p - 1): a lone system is
+ * latency-bound, so it takes the shorter chunks), else on one.  psi: device
  * complex128 [N] in/out; E: device FP64 [nsteps+1]; obs_out: device FP64
  * [(nsteps+1)*3] or NULL.  Asynchronous on `stream`. */
 tdsez_status tdsez_propagate(tdsez_system sys, double* psi, const double* E, double dt, int nsteps,

@@ -263,6 +263,20 @@ int span_plan(int N, int p, int G, int Pl, Plan* out) {
     return out->P == G * Pl ? G : 1;
 }
 
+// The one-workgroup plan of a lone system (tdsez_propagate and the
+// allocation-free call): the multi-wave plan, but on two waves as soon as 65
+// chunks of at least 2p rows fit.  A lone system is latency-bound, so the
+// shorter chunks and the two-ended separator chain pay where the batch rule
+// (which weighs the waves against the other systems) keeps one wave.
+static Plan lone_plan(int N, int p) {
+    Plan pl = multi_wave_plan(N, p, 0, 4);
+    if (plan_waves(pl) == 1 && (N + kMaxChunks) / (kMaxChunks + 1) >= 2 * p) {
+        const Plan p2 = make_plan(N, p, kMaxChunks + 1, kMaxChunks2);
+        if (p2.P == kMaxChunks + 1) pl = p2;
+    }
+    return pl;
+}
+
 tdsez_status pack_bands(BatchData* b) {
     const int nsys = (int)b->sys.size();
     b->plan.resize(nsys);
@@ -283,6 +297,7 @@ tdsez_status pack_bands(BatchData* b) {
         // system whose two-wave rule gives at most 64 chunks stays on one
         // wave, with the one-wave rule); an unmarked one on one wave
         Plan pl = multi_wave_plan(sy->N, sy->p, force, req ? b->max_waves : 1);
+        if (b->solo && nsys == 1 && force == 0 && req && b->max_waves >= 4) pl = lone_plan(sy->N, sy->p);
         // the one-system plan of tdsez_propagate spreads a long chain over
         // several workgroups: automatically once the four-wave plan holds
         // chunks of more than 48 rows, or as set by tdsez_system_set
@@ -596,7 +611,7 @@ extern "C" tdsez_status tdsez_propagate_noalloc(tdsez_system sys_h, double* psi,
     if ((obs & TDSEZ_OBS_ACCEL) && !sy->const_mass)
         return fail(TDSEZ_EUNSUPPORTED, "position-dependent mass: the acceleration needs the a_Q form");
     // the one-workgroup plan of tdsez_propagate (up to four waves; no spanning)
-    const Plan pl = multi_wave_plan(sy->N, sy->p, 0, 4);
+    const Plan pl = lone_plan(sy->N, sy->p);
     const int nw = plan_waves(pl);
     // scratch layout
     const long long nband = (long long)pl.L * kNumMats * (pl.p + 1) * pl.LS;
